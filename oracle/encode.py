@@ -1,0 +1,196 @@
+"""Derived formats of the optimisation pool (test infrastructure).
+
+* ``delta16_ref``   column-index compression (Section 3.3, Table 2, class MB).
+  The paper stores 8- or 16-bit deltas between consecutive column indices of
+  a row, never mixing widths.  Reading used here: 16-bit offsets from the
+  row's first column (``base_i = c_0``, ``off_k = c_k - base_i``), which a
+  GPU decodes in O(1) per element without an in-row scan.  Feasible iff no
+  row spans more than 65535 columns.
+* ``merge_splits_ref``  start coordinates of the nonzero-balanced merge-path
+  tiles (Merrill and Garland, SC'16): the merge of the row-end list
+  ``rowptr[1..N]`` with the nonzero indices ``0..NNZ-1``, where nonzero j is
+  taken before row end i exactly when ``j < rowptr[i+1]``.
+* ``panel_windows_ref`` per-panel column windows for LDS-staged x blocks.
+* ``partition_ref``  the paper's default static partition: contiguous row
+  ranges with (as nearly as possible) equal nonzeros (Section 3.2.1).
+* ``to_bf16_bits_ref`` / ``to_f32_ref``  value rounding for the precision
+  path, round-to-nearest-even straight from FP64 (one rounding).
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+
+def delta16_ref(rowptr, colind):
+    """(feasible, base int32[N], off uint16[NNZ])."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colind = np.asarray(colind, dtype=np.int64)
+    n = len(rowptr) - 1
+    L = np.diff(rowptr)
+    base = np.zeros(n, dtype=np.int64)
+    ne = L > 0
+    base[ne] = colind[rowptr[:-1][ne]]
+    rows = np.repeat(np.arange(n, dtype=np.int64), L)
+    off = colind - base[rows]
+    feasible = bool(len(off) == 0 or off.max() <= 65535)
+    return feasible, base.astype(np.int32), (off & 0xFFFF).astype(np.uint16)
+
+
+def merge_walk_ref(rowptr, items_per_tile: int):
+    """Split coordinates by walking the whole merge sequentially.
+
+    Returns (split_row, split_nnz), each int32[ntiles + 1], where tile t starts
+    on diagonal min(t * items_per_tile, N + NNZ).
+    """
+    rowptr = [int(v) for v in rowptr]
+    n = len(rowptr) - 1
+    nnz = rowptr[-1]
+    total = n + nnz
+    ntiles = (total + items_per_tile - 1) // items_per_tile
+    out_i, out_j = [0], [0]
+    i = j = 0
+    for d in range(1, total + 1):
+        # consume one item: a nonzero if it belongs to the current row
+        if j < nnz and (i == n or j < rowptr[i + 1]):
+            j += 1
+        else:
+            i += 1
+        if d % items_per_tile == 0 and d < total:
+            out_i.append(i)
+            out_j.append(j)
+    while len(out_i) < ntiles + 1:
+        out_i.append(i)
+        out_j.append(j)
+    return np.array(out_i, dtype=np.int32), np.array(out_j, dtype=np.int32)
+
+
+def merge_search_ref(rowptr, items_per_tile: int):
+    """The same split coordinates by binary search on each tile diagonal.
+
+    On diagonal d the row coordinate is the smallest i in
+    [max(0, d - NNZ), min(d, N)] with rowptr[i+1] > d - i - 1 (min(d, N) if
+    there is none); the nonzero coordinate is d - i.
+    """
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    n = len(rowptr) - 1
+    nnz = int(rowptr[-1])
+    total = n + nnz
+    ntiles = (total + items_per_tile - 1) // items_per_tile
+    si = np.zeros(ntiles + 1, dtype=np.int64)
+    sj = np.zeros(ntiles + 1, dtype=np.int64)
+    for t in range(ntiles + 1):
+        d = min(t * items_per_tile, total)
+        lo, hi = max(0, d - nnz), min(d, n)
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if rowptr[mid + 1] <= d - mid - 1:
+                lo = mid + 1
+            else:
+                hi = mid
+        si[t], sj[t] = lo, d - lo
+    return si.astype(np.int32), sj.astype(np.int32)
+
+
+def panel_windows_ref(rowptr, colind, rows_per_panel: int):
+    """(cmin int32[P], cmax int32[P]): column window of each row panel.
+
+    A panel with no nonzeros gets the empty window (0, -1).
+    """
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colind = np.asarray(colind, dtype=np.int64)
+    n = len(rowptr) - 1
+    P = (n + rows_per_panel - 1) // rows_per_panel
+    cmin = np.zeros(P, dtype=np.int64)
+    cmax = np.full(P, -1, dtype=np.int64)
+    for p in range(P):
+        r0, r1 = p * rows_per_panel, min(n, (p + 1) * rows_per_panel)
+        lo, hi = None, None
+        for r in range(r0, r1):
+            a, b = rowptr[r], rowptr[r + 1]
+            if a < b:
+                lo = colind[a] if lo is None else min(lo, colind[a])
+                hi = colind[b - 1] if hi is None else max(hi, colind[b - 1])
+        if lo is not None:
+            cmin[p], cmax[p] = lo, hi
+    return cmin.astype(np.int32), cmax.astype(np.int32)
+
+
+def partition_ref(rowptr, parts: int):
+    """Row boundaries b[0..parts] of the equal-nonzero static partition.
+
+    b_0 = 0, b_parts = N and, in between, b_p is the first row whose start
+    offset reaches ceil(p * NNZ / parts).
+    """
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    n = len(rowptr) - 1
+    nnz = int(rowptr[-1])
+    b = np.zeros(parts + 1, dtype=np.int64)
+    for p in range(1, parts):
+        target = -((-p * nnz) // parts)
+        b[p] = int(np.searchsorted(rowptr, target, side="left"))
+    b[parts] = n
+    return b.astype(np.int32)
+
+
+def to_f32_ref(val) -> np.ndarray:
+    """FP64 -> FP32, round to nearest even (the C conversion)."""
+    return np.asarray(val, dtype=np.float64).astype(np.float32)
+
+
+def _bf16_bits_exact(x: float) -> int:
+    """bfloat16 bits of x by exact rational rounding (half to even)."""
+    if x != x:
+        return 0x7FC0
+    sign = 0x8000 if (x < 0 or (x == 0 and np.signbit(x))) else 0
+    a = abs(x)
+    if a == 0:
+        return sign
+    if a == float("inf"):
+        return sign | 0x7F80
+    fa = Fraction(a)
+    e = fa.numerator.bit_length() - fa.denominator.bit_length()
+    if Fraction(2) ** e > fa:
+        e -= 1                      # now 2**e <= a < 2**(e+1)
+    if e < -126:                    # subnormal: units of 2**-133
+        s = round(fa * 2 ** 133)
+        return sign | s             # s == 128 encodes the smallest normal
+    s = round(fa * Fraction(2) ** (7 - e))   # 128 <= s <= 256
+    if s == 256:
+        s, e = 128, e + 1
+    if e > 127:
+        return sign | 0x7F80
+    return sign | ((e + 127) << 7) | (s - 128)
+
+
+def to_bf16_bits_ref(val) -> np.ndarray:
+    """FP64 -> bfloat16 bit patterns (uint16), one round-to-nearest-even.
+
+    Normal-range values are rounded on the FP64 bit pattern (keep 7 fraction
+    bits, round on the next bit with the rest as sticky); zeros, subnormal
+    results, overflow and non-finite values go through exact rational
+    rounding.
+    """
+    v = np.ascontiguousarray(np.asarray(val, dtype=np.float64))
+    bits = v.view(np.uint64)
+    sign = ((bits >> np.uint64(63)) << np.uint64(15)).astype(np.uint64)
+    exp = ((bits >> np.uint64(52)) & np.uint64(0x7FF)).astype(np.int64) - 1023
+    mant = bits & np.uint64((1 << 52) - 1)
+    keep = mant >> np.uint64(45)                       # 7 fraction bits
+    rbit = (mant >> np.uint64(44)) & np.uint64(1)
+    sticky = (mant & np.uint64((1 << 44) - 1)) != 0
+    up = (rbit == 1) & (sticky | ((keep & np.uint64(1)) == 1))
+    body = ((exp + 127).astype(np.uint64) << np.uint64(7)) + keep + up.astype(np.uint64)
+    out = (sign | body).astype(np.uint64)
+    normal = (exp >= -126) & (exp <= 127)
+    normal &= body < np.uint64(0x7F80)                 # no overflow to inf
+    res = np.where(normal, out, np.uint64(0)).astype(np.uint16)
+    for i in np.nonzero(~normal)[0]:
+        res[i] = _bf16_bits_exact(float(v[i]))
+    return res
+
+
+def bf16_bits_to_f64(bits) -> np.ndarray:
+    b = np.asarray(bits, dtype=np.uint16).astype(np.uint32) << np.uint32(16)
+    return b.view(np.float32).astype(np.float64)

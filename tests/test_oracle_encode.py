@@ -1,0 +1,153 @@
+"""Pins of the oracle encoders against definitions written out independently."""
+import struct
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.encode import (bf16_bits_to_f64, delta16_ref, merge_search_ref,
+                           merge_walk_ref, panel_windows_ref, partition_ref,
+                           to_bf16_bits_ref, to_f32_ref)
+
+
+def cases(seed=3, count=40):
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        n = int(rng.integers(0, 60))
+        m = int(rng.integers(1, 70))
+        yield synth.tiny_random_csr(rng, n, m, float(rng.choice([0, .02, .2, .7, 1.0])))
+
+
+def test_delta16_roundtrip_and_feasibility():
+    for rp, ci, _ in cases():
+        ok, base, off = delta16_ref(rp, ci)
+        assert ok
+        rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+        assert np.array_equal(base[rows].astype(np.int64) + off, ci)
+        for i in range(len(rp) - 1):
+            if rp[i + 1] > rp[i]:
+                assert base[i] == ci[rp[i]] and off[rp[i]] == 0
+            else:
+                assert base[i] == 0
+    # a row spanning 65536 columns is infeasible, 65535 is feasible
+    assert delta16_ref([0, 2], [0, 65535])[0]
+    assert not delta16_ref([0, 2], [0, 65536])[0]
+
+
+def test_delta16_random_2m_infeasible_stencil_feasible():
+    rp, ci, _ = synth.uniform_random(20000, 2_000_000, 8, seed=2)
+    assert not delta16_ref(rp, ci)[0]
+    rp, ci, _ = synth.stencil3d_27(30)
+    assert delta16_ref(rp, ci)[0]
+
+
+@pytest.mark.parametrize("T", [1, 3, 7, 64, 2048])
+def test_merge_search_equals_walk(T):
+    for rp, ci, _ in cases(seed=T):
+        a = merge_walk_ref(rp, T)
+        b = merge_search_ref(rp, T)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_merge_split_properties():
+    rp, _, _ = synth.powerlaw(2000, 109, 500, seed=1)
+    T = 97
+    si, sj = merge_search_ref(rp, T)
+    n, nnz = len(rp) - 1, int(rp[-1])
+    assert si[0] == 0 and sj[0] == 0 and si[-1] == n and sj[-1] == nnz
+    for t in range(len(si)):
+        d = min(t * T, n + nnz)
+        i, j = int(si[t]), int(sj[t])
+        assert i + j == d
+        # every consumed nonzero belongs to a row < i or to row i itself
+        assert j <= (rp[i + 1] if i < n else nnz)
+        # every consumed row end lies at or before the nonzero cursor
+        assert i == 0 or rp[i] <= j
+
+
+def test_partition_equal_nnz():
+    rp, _, _ = synth.powerlaw(5000, 109, 2000, seed=2)
+    b = partition_ref(rp, 64)
+    nnz = int(rp[-1])
+    assert b[0] == 0 and b[-1] == 5000 and np.all(np.diff(b) >= 0)
+    for p in range(1, 64):
+        tgt = -((-p * nnz) // 64)
+        assert rp[b[p]] >= tgt and (b[p] == 0 or rp[b[p] - 1] < tgt)
+
+
+def test_panel_windows_bruteforce():
+    for rp, ci, _ in cases(seed=5):
+        H = 7
+        lo, hi = panel_windows_ref(rp, ci, H)
+        n = len(rp) - 1
+        for p in range(len(lo)):
+            seg = ci[rp[p * H]:rp[min(n, (p + 1) * H)]]
+            if len(seg):
+                assert lo[p] == seg.min() and hi[p] == seg.max()
+            else:
+                assert (lo[p], hi[p]) == (0, -1)
+
+
+def bf16_by_fraction(x):
+    """Round x to the nearest bfloat16 (ties to even) by scanning neighbours."""
+    f32 = np.float32(x)
+    # candidates: bf16 values around the float32 rounding of x
+    b = struct.unpack("<I", struct.pack("<f", float(f32)))[0] >> 16
+    best = None
+    for c in range(max(0, b - 2), min(0xFFFF, b + 3)):
+        v = struct.unpack("<f", struct.pack("<I", c << 16))[0]
+        if v != v or abs(v) == float("inf"):
+            continue
+        if (v < 0) != (x < 0) and v != 0:
+            continue
+        d = abs(Fraction(v) - Fraction(x))
+        key = (d, c & 1)
+        if best is None or key < best[0]:
+            best = (key, c)
+    return best[1]
+
+
+def test_bf16_round_to_nearest_even():
+    rng = np.random.default_rng(0)
+    vals = np.concatenate([rng.uniform(-1, 1, 3000),
+                           rng.uniform(-1, 1, 500) * 2.0 ** rng.integers(-120, 120, 500)])
+    # exact ties: bf16 value plus half an ulp, and a tie broken by a far bit
+    ties = []
+    for b in rng.integers(0x3C00, 0x4300, 200):
+        lo = struct.unpack("<f", struct.pack("<I", int(b) << 16))[0]
+        hi = struct.unpack("<f", struct.pack("<I", (int(b) + 1) << 16))[0]
+        mid = (lo + hi) / 2
+        ties += [mid, np.nextafter(mid, 10.0), np.nextafter(mid, -10.0)]
+    vals = np.concatenate([vals, ties, -np.array(ties)])
+    got = to_bf16_bits_ref(vals)
+    for v, g in zip(vals, got):
+        assert g == bf16_by_fraction(float(v)), v
+
+
+def test_bf16_special_values():
+    vals = np.array([0.0, -0.0, 1.0, -2.0, 3.0 * 2 ** 130, 2.0 ** -130, 2.0 ** -140, np.inf, -np.inf])
+    got = to_bf16_bits_ref(vals)
+    assert list(got[:4]) == [0x0000, 0x8000, 0x3F80, 0xC000]
+    assert got[4] == 0x7F80                   # overflow -> +inf
+    assert got[5] == 0x0008                   # 2^-130 = 8 units of 2^-133 (subnormal)
+    assert got[6] == 0x0000                   # 2^-140 rounds to zero
+    assert got[7] == 0x7F80 and got[8] == 0xFF80
+    back = bf16_bits_to_f64(got[:4])
+    assert list(back) == [0.0, -0.0, 1.0, -2.0]
+
+
+def test_integers_exact_in_bf16_and_f32():
+    v = np.arange(-256, 257, dtype=np.float64)
+    assert np.array_equal(bf16_bits_to_f64(to_bf16_bits_ref(v)), v)
+    assert np.array_equal(to_f32_ref(v).astype(np.float64), v)
+
+
+def test_f32_rounding_matches_fractions():
+    rng = np.random.default_rng(1)
+    for x in rng.uniform(-1, 1, 500):
+        f = float(to_f32_ref([x])[0])
+        up = float(np.nextafter(np.float32(f), np.float32(2)))
+        dn = float(np.nextafter(np.float32(f), np.float32(-2)))
+        d = abs(Fraction(f) - Fraction(x))
+        assert d <= abs(Fraction(up) - Fraction(x)) and d <= abs(Fraction(dn) - Fraction(x))
