@@ -1,0 +1,299 @@
+/*
+ * spmvsel — selected CSR SpMV on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libspmvsel.so.  Every entry point returns an spmv_status_t; no C++
+ * exception crosses the boundary.  After a non-zero status,
+ * spmv_last_error() returns a message for the calling thread.
+ *
+ * Method: Elafrou, Goumas, Koziris, "A lightweight optimization selection
+ * method for Sparse Matrix-Vector Multiplication" (arXiv 1511.02494).  The
+ * library computes y = A x for A in CSR (Section 2, Algorithm 1), extracts
+ * structural features of A (Table 1), classifies A with the profiling-based
+ * classifier (Section 3.2.1) or with a learned selector over the features
+ * (Section 3.2.2, here an MLP), and runs the optimisation chosen for it from
+ * a pool of six GPU variants (Table 2, remapped to the GPU).
+ *
+ * Conventions
+ *   - Pointers named d_* are device pointers (hipMalloc'd or from any
+ *     allocator of the current HIP device); others are host pointers.
+ *   - A stream argument is a hipStream_t passed as void* (NULL = the
+ *     default stream).
+ *   - CSR input: 0-based int32 indices (the paper's listing is 1-based);
+ *     rowptr[0] = 0, rowptr[N] = NNZ, rowptr non-decreasing; columns in
+ *     [0, M) and strictly increasing inside each row; NNZ < 2^31.  Empty
+ *     rows are allowed (y_i = 0); N = 0 and NNZ = 0 are valid.
+ *   - Value dtypes: SPMV_F64 values use double x and y; SPMV_F32 and
+ *     SPMV_BF16 values (bfloat16 bit patterns in uint16) use float x and y
+ *     with FP32 accumulation, Kahan-compensated on rows of more than 256
+ *     nonzeros.
+ */
+#ifndef SPMVSEL_H
+#define SPMVSEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spmv_plan *spmv_plan_t;
+
+typedef enum {
+    SPMV_OK = 0,
+    SPMV_ERR_ARG = 1,          /* bad argument (NULL, negative size, ...) */
+    SPMV_ERR_CSR_ROWPTR = 2,   /* rowptr[0] != 0, rowptr[N] != NNZ, decreasing, out of [0, NNZ] */
+    SPMV_ERR_CSR_COL_RANGE = 3,/* a column index outside [0, M) */
+    SPMV_ERR_CSR_UNSORTED = 4, /* columns not strictly increasing in a row (includes duplicates) */
+    SPMV_ERR_OOM = 5,          /* device allocation failed; nothing is leaked */
+    SPMV_ERR_HIP = 6,          /* any other HIP runtime error */
+    SPMV_ERR_INFEASIBLE = 7,   /* the variant cannot represent this matrix */
+    SPMV_ERR_NO_MODEL = 8      /* no MLP parameters loaded, or the file is corrupt */
+} spmv_status_t;
+
+typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
+
+/* The optimisation pool (Table 2, remapped to the GPU).
+ *  CSR_SCALAR  one lane per row: the unoptimised baseline of Section 4.3.
+ *  CSR_VECTOR  a sub-wavefront of 2..64 lanes per row, DPP/swizzle reduction
+ *              (vectorisation, class CMP; the architecture-centric default).
+ *  MERGE_PATH  nonzero-balanced merge-path tiles (class IMB; replaces the
+ *              OpenMP dynamic/auto schedules).
+ *  DELTA16     16-bit column offsets from each row's first column, streamed
+ *              through LDS (column-index compression, class MB).
+ *  XBLOCK_LDS  x staged in LDS per row panel and column window (class CML;
+ *              replaces software prefetching of x).
+ *  SHORT_ROW   rows streamed through LDS in unrolled 8-element runs with one
+ *              thread summing each row (short rows: inner-loop overhead). */
+typedef enum {
+    V_CSR_SCALAR = 0, V_CSR_VECTOR = 1, V_MERGE_PATH = 2,
+    V_DELTA16 = 3, V_XBLOCK_LDS = 4, V_SHORT_ROW = 5, SPMV_N_VARIANTS = 6
+} spmv_variant_t;
+
+/* Bottleneck classes of Section 3.1. */
+typedef enum { K_CML = 0, K_MB = 1, K_IMB = 2, K_CMP = 3 } spmv_class_t;
+
+typedef enum {
+    SEL_PROFILING = 0,  /* micro-benchmarks + threshold cascade (Section 3.2.1) */
+    SEL_MLP = 1,        /* features + MLP; falls back to SEL_PROFILING */
+    SEL_EXHAUSTIVE = 2  /* time every feasible variant, keep the fastest */
+} spmv_selector_t;
+
+/* plan_create flags */
+#define SPMV_COPY_INPUTS   1u  /* copy the CSR arrays instead of borrowing them */
+#define SPMV_SKIP_VALIDATE 2u  /* trust the caller's CSR (no validation pass) */
+
+#define SPMV_N_FEATURES 12
+#define SPMV_N_ACCUM 12
+
+/* Result of spmv_select. */
+typedef struct {
+    int32_t variant;        /* chosen spmv_variant_t */
+    int32_t klass;          /* spmv_class_t from the profiling cascade, or -1 */
+    int32_t selector;       /* selector actually used (after any fallback) */
+    int32_t fell_back;      /* 1 if SEL_MLP fell back to SEL_PROFILING */
+    uint32_t feasible;      /* bit v set if variant v can run this matrix */
+    float margin;           /* MLP top1 - top2 logit (0 if not run) */
+    float logits[6];        /* MLP logits (0 if not run) */
+    double meas[5];         /* profiling: t_base, t_nox, t_inf (s, median),
+                               d_max, d_mean (per-partition device-clock ticks) */
+    double scores[3];       /* s_nox, s_inf, s_bal */
+    double features[12];    /* spmv_features output */
+    double t_features_s;    /* host wall-clock of the feature extraction */
+    double t_decide_s;      /* MLP inference (or cascade) */
+    double t_profile_s;     /* micro-benchmarks (0 unless they ran) */
+    double t_total_s;       /* whole selection, excluding format preparation */
+    double t_prepare_s;     /* format preparation of the chosen variant */
+    double variant_times_s[6]; /* SEL_EXHAUSTIVE: median time per variant (0 = infeasible) */
+} spmv_select_info_t;
+
+/* ----------------------------------------------------------------------- */
+/* Plan life cycle                                                          */
+
+/* Create a plan for the CSR matrix A (N x M, NNZ nonzeros).  Validates the
+ * CSR invariants listed above on the device unless SPMV_SKIP_VALIDATE is set
+ * (CSR, Section 2) and returns the first violated one as a status.  The plan
+ * borrows d_rowptr[N+1], d_colind[NNZ] and d_val[NNZ] (dtype val_dtype)
+ * until spmv_plan_destroy, unless SPMV_COPY_INPUTS is set.  Derived formats
+ * are built lazily and owned by the plan.  Synchronises `stream`.
+ * Arrays must be 16-byte aligned.  *out is NULL on failure. */
+spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
+                               int64_t nnz, const int32_t *d_rowptr,
+                               const int32_t *d_colind, const void *d_val,
+                               int32_t val_dtype, void *stream, uint32_t flags);
+
+/* Release the plan and everything it owns.  NULL is a no-op (SPMV_OK). */
+spmv_status_t spmv_plan_destroy(spmv_plan_t plan);
+
+/* ----------------------------------------------------------------------- */
+/* The selected-SpMV path                                                   */
+
+/* The twelve structural features of Table 1 used by the selectors, in
+ * order: N, NNZ, nnz_avg, nnz_sd, nnz_max, nnz_min, bw_avg, bw_sd,
+ * dispersion_avg, dispersion_sd, miss_per_nnz, size.  bw_i is the column
+ * distance of a row's first and last nonzero; dispersion_i = nnz_i /
+ * (bw_i + 1) in Q31 fixed point; a miss is a gap of more than 128 bytes of
+ * x between consecutive nonzeros of a row; size is 1 if the CSR working set
+ * fits a 256 MiB last-level cache.  Standard deviations are population ones.
+ * Computed from exact integer sums (one pass over rowptr and colind on the
+ * device) and one fixed FP64 finalisation on the host, so the result is
+ * bit-reproducible.  out_acc (nullable) receives the exact sums:
+ * nnz_min, nnz_max, bw_max, S_L2, S_bw, S_bw2 (lo, hi), S_q, S_q2 (lo, hi),
+ * S_miss, NNZ.  Synchronous on the plan stream. */
+spmv_status_t spmv_features(spmv_plan_t plan, double out_features[12],
+                            uint64_t out_acc[12]);
+
+/* Choose a variant with `selector` (spmv_selector_t), set it on the plan and
+ * build its format.  info (nullable) receives the decision record.
+ * Synchronous. */
+spmv_status_t spmv_select(spmv_plan_t plan, int32_t selector,
+                          spmv_select_info_t *info);
+
+/* y = A x with the plan's current variant (CSR_SCALAR before any select or
+ * set_variant), on `stream`, asynchronously.  y is fully overwritten.
+ * d_x has M elements and d_y N elements, of type double for F64 plans and
+ * float otherwise.  Calls on one plan must not overlap in time (the merge
+ * path variant keeps per-tile carries in plan scratch). */
+spmv_status_t spmv_execute(spmv_plan_t plan, const void *d_x, void *d_y,
+                           void *stream);
+
+/* ----------------------------------------------------------------------- */
+/* Control and inspection                                                   */
+
+/* Force a variant; builds its format (synchronous).  SPMV_ERR_INFEASIBLE if
+ * the matrix cannot use it (DELTA16: a row spans more than 65535 columns;
+ * XBLOCK_LDS: the x windows staged for all panels exceed NNZ elements). */
+spmv_status_t spmv_set_variant(spmv_plan_t plan, int32_t variant);
+spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
+
+/* Bit v set if variant v can run this matrix (computes features if needed). */
+spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
+
+/* Algorithmic bytes of one SpMV with `variant`: 4(N+1) + ib NNZ + vb NNZ +
+ * xb M + yb N, plus 4N row bases for DELTA16 (ib = 2 there, else 4). */
+spmv_status_t spmv_bytes(spmv_plan_t plan, int32_t variant, int64_t *bytes);
+
+/* Median and minimum time of `reps` executions of `variant` (hipEvents on
+ * the plan stream, after 2 warm-ups).  cold != 0 evicts the 256 MiB
+ * Infinity Cache before each timed run by streaming a 512 MiB buffer.
+ * Uses internal x and y buffers.  SPMV_ERR_INFEASIBLE if not runnable. */
+spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
+                                int32_t cold, double *t_median_s, double *t_min_s);
+
+/* Plan parameters and derived arrays, for tests and tools.
+ * Keys: 0 variant, 1 csr_vector width, 2 short_row/delta16 rows per block,
+ * 3 merge-path items per tile, 4 merge-path tiles, 5 x-block rows per panel,
+ * 6 x-block panels, 7 x-block columns per LDS chunk, 8 profiling partitions,
+ * 9 delta16 feasible, 10 x-block feasible. */
+spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
+
+/* Copy a derived array to host memory (builds it if needed).  which:
+ * 0 delta16 base int32[N], 1 delta16 offsets uint16[NNZ], 2 merge-path split
+ * rows int32[tiles+1], 3 merge-path split nonzeros int32[tiles+1], 4 x-block
+ * window starts int32[panels], 5 x-block window ends int32[panels],
+ * 6 profiling partition bounds int32[parts+1].  `bytes` must equal the
+ * array size. */
+spmv_status_t spmv_plan_copy_format(spmv_plan_t plan, int32_t which,
+                                    void *host_dst, int64_t bytes);
+
+/* ----------------------------------------------------------------------- */
+/* Profiling-based classifier (Section 3.2.1)                               */
+
+/* Run the three micro-benchmarks against baseline CSR on the plan:
+ * baseline and `noxmiss` (all column indices 0) and `inflate` (int64 rowptr
+ * and colind), each the median of `reps` runs on a static partition of
+ * 256 x (CUs) row ranges with equal nonzeros, one per wavefront; `balance`
+ * from the per-partition device-clock durations of the baseline runs.
+ * meas = {t_base, t_nox, t_inf, d_max, d_mean}.  Temporary copies are
+ * freed before returning.  Synchronous. */
+spmv_status_t spmv_profile_measure(spmv_plan_t plan, int32_t reps, double meas[5]);
+
+/* The cascade as a pure host function: scores s_nox = t_base/t_nox,
+ * s_inf = t_inf/t_base, s_bal = d_max/d_mean (0 when a denominator is not
+ * positive); taken from the highest down (ties keep noxmiss, inflate,
+ * balance), the first exceeding its threshold theta[0..2] gives CML, MB or
+ * IMB; otherwise CMP.  Class -> variant: CML -> XBLOCK_LDS if feasible else
+ * CSR_VECTOR; MB -> DELTA16 if feasible else CSR_VECTOR; IMB -> MERGE_PATH;
+ * CMP -> SHORT_ROW if nnz_avg (features[2]) <= theta[3] else CSR_VECTOR. */
+spmv_status_t spmv_profile_decide(const double meas[5], const double features[12],
+                                  const double theta[4], uint32_t feasible_bits,
+                                  int32_t *variant, int32_t *klass);
+
+/* Process-wide thresholds used by spmv_select (default 2.0, 1.2, 1.5, 4.0). */
+spmv_status_t spmv_set_thresholds(const double theta[4]);
+spmv_status_t spmv_get_thresholds(double theta[4]);
+
+/* ----------------------------------------------------------------------- */
+/* Learned selector: MLP 12 -> 64 -> 64 -> 6, FP32                          */
+
+/* Load parameters for the current process (all devices) from a file:
+ * "SPMVMLP1", u32 version=1, u32 n_params=5382, f32 mu[12], f32 rho[12],
+ * f32 tau, f32 params[5382] (W1[64][12], b1, W2[64][64], b2, W3[6][64], b3),
+ * u32 CRC-32 (IEEE 802.3) of everything before it.  SPMV_ERR_NO_MODEL if the
+ * file is missing or corrupt (no model is then loaded). */
+spmv_status_t spmv_model_load(const char *path);
+spmv_status_t spmv_model_unload(void);
+
+/* Device inference for one feature vector: z_k = fl32(fl32(fl32(g_k) -
+ * mu_k) * rho_k) with g_k = plog2(1 + f_k) (k < 8) or f_k, where
+ * plog2(v) = (e - 1) + (2m - 1) for (m, e) = frexp(v); three dense layers
+ * with acc = 0; acc = fl32(acc + fl32(w * in)) in input order, then + bias,
+ * ReLU on the hidden layers; infeasible variants skipped; first maximal
+ * logit wins; margin = top1 - top2; fallback = margin < tau or some
+ * |z_k| > 8.  Outputs are nullable.  SPMV_ERR_NO_MODEL without a model. */
+spmv_status_t spmv_mlp_predict(const double features[12], uint32_t feasible_bits,
+                               int32_t *variant, float *margin, int32_t *fallback,
+                               float logits[6], float z[12]);
+
+/* One training minibatch on the device: mean softmax cross-entropy over
+ * the feasible logits (d_mask[B*6], 1 = feasible) of d_Z[B*12] against
+ * d_labels[B]; writes the loss to d_loss[0] and the gradient of every
+ * parameter to d_grads[5382].  B <= 1024. */
+spmv_status_t spmv_mlp_forward_backward(const float *d_params, const float *d_Z,
+                                        const int32_t *d_labels, const uint8_t *d_mask,
+                                        int32_t B, float *d_grads, float *d_loss,
+                                        void *stream);
+
+/* Adam (Kingma and Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */
+spmv_status_t spmv_mlp_adam_step(float *d_params, const float *d_grads, float *d_m,
+                                 float *d_v, int32_t n, int32_t step, float lr,
+                                 float b1, float b2, float eps, void *stream);
+
+/* ----------------------------------------------------------------------- */
+/* Utilities                                                                */
+
+/* FP64 -> FP32 (to_dtype SPMV_F32) or bfloat16 bits (SPMV_BF16), one
+ * round-to-nearest-even from FP64.  d_out has n elements of 4 or 2 bytes. */
+spmv_status_t spmv_quantize(const double *d_in, void *d_out, int64_t n,
+                            int32_t to_dtype, void *stream);
+
+/* Seeded synthetic CSR on the device.  family: 0 5-point 2D Laplacian,
+ * 1 9-point 2D box, 2 7-point 3D star, 3 27-point 3D box (p[0] = grid side;
+ * p[1] = 1 for random values else constant 2d/2d-1 stencil values),
+ * 4 uniform random (p = n_rows, n_cols, per_row), 5 banded (p = n, d16,
+ * half_width), 6 random rows (p = n, d16), 7 power law (p = n, p16, cap,
+ * force_long), 8 short rows (p = n).  Counter-based SplitMix64 draws.
+ * Call with d_rowptr only (others NULL) to get *nnz_out and rowptr; then
+ * again with d_colind and d_val of nnz_out elements. */
+spmv_status_t spmv_generate(int32_t family, const int64_t *params, int32_t n_params,
+                            uint64_t seed, int32_t *d_rowptr, int32_t *d_colind,
+                            double *d_val, int64_t *nnz_out, void *stream);
+
+/* x_j = 2 u_j - 1 with u_j = (h(seed, 1, j) >> 11) 2^-53 (double, n elements). */
+spmv_status_t spmv_generate_vector(int64_t n, uint64_t seed, double *d_x, void *stream);
+
+/* Evict the Infinity Cache: read and write a 512 MiB scratch buffer. */
+spmv_status_t spmv_cache_flush(void *stream);
+
+/* Attainable HBM bandwidth over a `bytes` buffer: streaming read and copy,
+ * median of 5 runs, in GB/s (1e9 B/s). */
+spmv_status_t spmv_hbm_probe(int64_t bytes, double *read_gbs, double *copy_gbs);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *spmv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPMVSEL_H */

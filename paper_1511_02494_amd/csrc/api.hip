@@ -1,0 +1,973 @@
+// Host side of libspmvsel: the C ABI declared in include/spmvsel.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace spmvsel {
+
+// ============================================================ errors
+static thread_local std::string g_err;
+
+void clear_error() { g_err.clear(); }
+
+spmv_status_t fail(spmv_status_t st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+spmv_status_t fail_hip(hipError_t e, const char *what, const char *file, int line) {
+    hipGetLastError();  // clear the sticky launch error, if any
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    g_err = buf;
+    return e == hipErrorOutOfMemory ? SPMV_ERR_OOM : SPMV_ERR_HIP;
+}
+
+spmv_status_t DevBuf::alloc(size_t n) {
+    if (p && bytes >= n) return SPMV_OK;
+    release();
+    const size_t want = n < 256 ? 256 : n;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return fail_hip(e, "hipMalloc", __FILE__, __LINE__);
+    }
+    bytes = want;
+    return SPMV_OK;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+// ============================================================ process state
+namespace {
+
+std::mutex g_mu;
+double g_theta[4] = {2.0, 1.2, 1.5, 4.0};
+
+struct Model {
+    bool loaded = false;
+    std::vector<float> params;  // 5382
+    float norm[24];             // mu[12], rho[12]
+    float tau = 0.f;
+    std::map<int, DevBuf *> dev;  // per-device copy: params then norm
+};
+Model g_model;
+
+std::map<int, DevBuf *> g_flush;  // 512 MiB eviction buffer per device
+constexpr size_t kFlushBytes = 512ull << 20;
+constexpr int kNParams = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 6 + 6;
+
+typedef unsigned __int128 u128;
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// Round an unsigned 128-bit integer to the nearest double (ties to even):
+// keep the top 64 bits with every dropped bit folded into a sticky bit, then
+// one 64-bit -> double conversion and an exact scaling.
+double u128_to_double(u128 v) {
+    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+    if (hi == 0) return (double)lo;
+    const int sh = 64 - __builtin_clzll(hi);
+    const uint64_t top = (uint64_t)(v >> sh);
+    const uint64_t sticky = (v & (((u128)1 << sh) - 1)) != 0 ? 1 : 0;
+    return ldexp((double)(top | sticky), sh);
+}
+
+uint32_t crc32(const unsigned char *p, size_t n) {
+    static uint32_t table[256];
+    static bool init = false;
+    if (!init) {
+        for (uint32_t i = 0; i < 256; ++i) {
+            uint32_t c = i;
+            for (int k = 0; k < 8; ++k) c = (c & 1) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+            table[i] = c;
+        }
+        init = true;
+    }
+    uint32_t c = 0xFFFFFFFFu;
+    for (size_t i = 0; i < n; ++i) c = table[(c ^ p[i]) & 0xFF] ^ (c >> 8);
+    return c ^ 0xFFFFFFFFu;
+}
+
+int pow2_ceil(double v, int lo, int hi) {
+    int w = lo;
+    while (w < hi && w < v) w <<= 1;
+    return w;
+}
+
+int pow2_floor(double v, int lo, int hi) {
+    int w = lo;
+    while (w * 2 <= hi && w * 2 <= v) w <<= 1;
+    return w;
+}
+
+hipStream_t S(const spmv_plan *P) { return P->stream; }
+
+spmv_status_t sync(const spmv_plan *P) {
+    SPMV_HIP(hipStreamSynchronize(P->stream));
+    return SPMV_OK;
+}
+
+// scratch layout (bytes)
+constexpr size_t kOffFlags = 0;                       // 3 u64
+constexpr size_t kOffRec = 256;                       // 16 u64
+constexpr size_t kOffSum = 512;                       // 1 u64
+constexpr size_t kOffMlp = 1024;                      // 64 floats
+constexpr size_t kOffPart = 4096;                     // kFeatBlocks * 16 u64
+constexpr size_t kScratchBytes = kOffPart + kFeatBlocks * 16 * 8;
+
+template <class T> T *scr(const spmv_plan *P, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(P->scratch.p) + off);
+}
+
+// ------------------------------------------------------------ features
+void finalize_features(const spmv_plan *P, const uint64_t *w, double *f) {
+    for (int i = 0; i < 12; ++i) f[i] = 0.0;
+    const int64_t n = P->n, nnz = P->nnz;
+    if (n == 0) return;
+    const double f0 = (double)n, f1 = (double)nnz, nn = f0 * f0;
+    const u128 sl2 = w[3], sbw = w[4], sbw2 = ((u128)w[6] << 64) | w[5];
+    const u128 sq = w[7], sq2 = ((u128)w[9] << 64) | w[8];
+    const int64_t smiss = (int64_t)(w[10] - w[11]);
+    f[0] = f0;
+    f[1] = f1;
+    f[2] = f1 / f0;
+    f[3] = sqrt(u128_to_double((u128)n * sl2 - (u128)nnz * (u128)nnz) / nn);
+    f[4] = (double)w[1];
+    f[5] = (double)w[0];
+    f[6] = (double)(uint64_t)sbw / f0;
+    f[7] = sqrt(u128_to_double((u128)n * sbw2 - sbw * sbw) / nn);
+    f[8] = ((double)(uint64_t)sq / 2147483648.0) / f0;
+    f[9] = sqrt(u128_to_double((u128)n * sq2 - sq * sq) / 4611686018427387904.0 / nn);
+    f[10] = nnz > 0 ? (double)smiss / f1 : 0.0;
+    const int64_t ws = 4 * (n + 1) + (4 + vbytes(P->dtype)) * nnz + xbytes(P->dtype) * P->m +
+                       xbytes(P->dtype) * n;
+    f[11] = ws <= kLlcBytes ? 1.0 : 0.0;
+}
+
+spmv_status_t ensure_features(spmv_plan *P) {
+    if (P->have_features) return SPMV_OK;
+    uint64_t *rec = scr<uint64_t>(P, kOffRec);
+    SPMV_HIP(launch_features(*P, scr<uint64_t>(P, kOffPart), rec, xbytes(P->dtype), S(P)));
+    uint64_t *h = static_cast<uint64_t *>(P->h_pinned);
+    SPMV_HIP(hipMemcpyAsync(h, rec, 16 * 8, hipMemcpyDeviceToHost, S(P)));
+    SPMV_TRY(sync(P));
+    uint64_t w[16];
+    memcpy(w, h, sizeof w);
+    if (P->n == 0) w[0] = 0;
+    finalize_features(P, w, P->feats);
+    const int64_t smiss = (int64_t)(w[10] - w[11]);
+    const uint64_t a[12] = {w[0], w[1], w[2], w[3], w[4], w[5],
+                            w[6], w[7], w[8], w[9], (uint64_t)smiss, (uint64_t)P->nnz};
+    memcpy(P->acc, a, sizeof a);
+    P->have_features = true;
+    return SPMV_OK;
+}
+
+bool d16_feasible(const spmv_plan *P) { return P->acc[2] <= 65535; }
+
+// ------------------------------------------------------------ formats
+spmv_status_t build_xblock(spmv_plan *P) {
+    if (P->xb_built) return SPMV_OK;
+    const int64_t panels = (P->n + P->xb_rows - 1) / P->xb_rows;
+    P->xb_panels = panels;
+    SPMV_TRY(P->xb_cmin.alloc((size_t)(panels > 0 ? panels : 1) * 4));
+    SPMV_TRY(P->xb_cmax.alloc((size_t)(panels > 0 ? panels : 1) * 4));
+    unsigned long long total = 0;
+    if (panels > 0) {
+        SPMV_HIP(launch_panel_windows(*P, P->xb_rows, P->xb_cmin.as<int32_t>(),
+                                      P->xb_cmax.as<int32_t>(), panels, S(P)));
+        auto *d_sum = scr<unsigned long long>(P, kOffSum);
+        SPMV_HIP(launch_window_sum(P->xb_cmin.as<int32_t>(), P->xb_cmax.as<int32_t>(), panels,
+                                   d_sum, S(P)));
+        SPMV_HIP(hipMemcpyAsync(P->h_pinned, d_sum, 8, hipMemcpyDeviceToHost, S(P)));
+        SPMV_TRY(sync(P));
+        memcpy(&total, P->h_pinned, 8);
+    }
+    P->xb_feasible = (int64_t)total <= P->nnz;
+    P->xb_built = true;
+    return SPMV_OK;
+}
+
+spmv_status_t build_format(spmv_plan *P, int v) {
+    switch (v) {
+    case V_CSR_SCALAR:
+    case V_CSR_VECTOR:
+    case V_SHORT_ROW:
+        return SPMV_OK;
+    case V_DELTA16: {
+        if (P->d16_built) return SPMV_OK;
+        SPMV_TRY(ensure_features(P));
+        if (!d16_feasible(P))
+            return fail(SPMV_ERR_INFEASIBLE, "delta16: a row spans %llu > 65535 columns",
+                        (unsigned long long)P->acc[2]);
+        SPMV_TRY(P->d16_base.alloc((size_t)(P->n > 0 ? P->n : 1) * 4));
+        SPMV_TRY(P->d16_off.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 2 + 16));
+        SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(), P->d16_off.as<uint16_t>(),
+                                       S(P)));
+        SPMV_TRY(sync(P));
+        P->d16_built = true;
+        return SPMV_OK;
+    }
+    case V_MERGE_PATH: {
+        if (P->mp_built) return SPMV_OK;
+        const int64_t tiles = (P->n + P->nnz + kMergeTile - 1) / kMergeTile;
+        P->mp_tiles = tiles;
+        SPMV_TRY(P->mp_split_row.alloc((size_t)(tiles + 1) * 4));
+        SPMV_TRY(P->mp_split_nnz.alloc((size_t)(tiles + 1) * 4));
+        SPMV_TRY(P->mp_carry_row.alloc((size_t)(tiles > 0 ? tiles : 1) * 4));
+        SPMV_TRY(P->mp_carry_val.alloc((size_t)(tiles > 0 ? tiles : 1) * 8));
+        SPMV_HIP(launch_merge_splits(*P, P->mp_split_row.as<int32_t>(),
+                                     P->mp_split_nnz.as<int32_t>(), tiles, S(P)));
+        SPMV_TRY(sync(P));
+        P->mp_built = true;
+        return SPMV_OK;
+    }
+    case V_XBLOCK_LDS:
+        SPMV_TRY(build_xblock(P));
+        if (!P->xb_feasible)
+            return fail(SPMV_ERR_INFEASIBLE,
+                        "xblock_lds: the column windows of the row panels exceed NNZ");
+        return SPMV_OK;
+    default:
+        return fail(SPMV_ERR_ARG, "unknown variant %d", v);
+    }
+}
+
+spmv_status_t feasible_mask(spmv_plan *P, uint32_t *bits) {
+    SPMV_TRY(ensure_features(P));
+    SPMV_TRY(build_xblock(P));
+    uint32_t b = (1u << V_CSR_SCALAR) | (1u << V_CSR_VECTOR) | (1u << V_MERGE_PATH) |
+                 (1u << V_SHORT_ROW);
+    if (d16_feasible(P)) b |= 1u << V_DELTA16;
+    if (P->xb_feasible) b |= 1u << V_XBLOCK_LDS;
+    *bits = b;
+    return SPMV_OK;
+}
+
+spmv_status_t run_variant(const spmv_plan *P, int v, const void *x, void *y, hipStream_t s) {
+    switch (v) {
+    case V_CSR_SCALAR: SPMV_HIP(launch_csr_scalar(*P, x, y, s)); break;
+    case V_CSR_VECTOR: SPMV_HIP(launch_csr_vector(*P, x, y, s)); break;
+    case V_MERGE_PATH: SPMV_HIP(launch_merge_path(*P, x, y, s)); break;
+    case V_DELTA16: SPMV_HIP(launch_rowstream(*P, true, x, y, s)); break;
+    case V_XBLOCK_LDS: SPMV_HIP(launch_xblock(*P, x, y, s)); break;
+    case V_SHORT_ROW: SPMV_HIP(launch_rowstream(*P, false, x, y, s)); break;
+    default: return fail(SPMV_ERR_ARG, "unknown variant %d", v);
+    }
+    return SPMV_OK;
+}
+
+spmv_status_t ensure_timing_vectors(spmv_plan *P) {
+    const size_t xb = xbytes(P->dtype);
+    SPMV_TRY(P->tx.alloc((size_t)(P->m > 0 ? P->m : 1) * xb));
+    SPMV_TRY(P->ty.alloc((size_t)(P->n > 0 ? P->n : 1) * xb));
+    SPMV_HIP(hipMemsetAsync(P->tx.p, 0, P->tx.bytes, S(P)));
+    return SPMV_OK;
+}
+
+spmv_status_t flush_cache(hipStream_t s) {
+    int dev = 0;
+    SPMV_HIP(hipGetDevice(&dev));
+    DevBuf *b;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_flush.find(dev);
+        if (it == g_flush.end()) it = g_flush.emplace(dev, new DevBuf()).first;
+        b = it->second;
+        if (!b->p) {
+            SPMV_TRY(b->alloc(kFlushBytes));
+            SPMV_HIP(hipMemset(b->p, 0, kFlushBytes));
+        }
+    }
+    SPMV_HIP(launch_flush(b->p, kFlushBytes, s));
+    return SPMV_OK;
+}
+
+double median(std::vector<double> v) {
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const size_t k = v.size();
+    return k % 2 ? v[k / 2] : 0.5 * (v[k / 2 - 1] + v[k / 2]);
+}
+
+spmv_status_t time_runs(spmv_plan *P, int reps, bool cold,
+                        const std::function<spmv_status_t()> &run, std::vector<double> *out) {
+    hipEvent_t a, b;
+    SPMV_HIP(hipEventCreate(&a));
+    SPMV_HIP(hipEventCreate(&b));
+    spmv_status_t st = SPMV_OK;
+    for (int r = 0; r < reps && st == SPMV_OK; ++r) {
+        if (cold) st = flush_cache(S(P));
+        if (st != SPMV_OK) break;
+        if (hipEventRecord(a, S(P)) != hipSuccess) { st = fail(SPMV_ERR_HIP, "event"); break; }
+        st = run();
+        if (st != SPMV_OK) break;
+        if (hipEventRecord(b, S(P)) != hipSuccess) { st = fail(SPMV_ERR_HIP, "event"); break; }
+        if (hipEventSynchronize(b) != hipSuccess) { st = fail(SPMV_ERR_HIP, "event sync"); break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, a, b);
+        out->push_back(ms * 1e-3);
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return st;
+}
+
+// ------------------------------------------------------------ profiling
+spmv_status_t profile_measure(spmv_plan *P, int reps, double meas[5]) {
+    for (int i = 0; i < 5; ++i) meas[i] = 0.0;
+    if (P->n == 0) return SPMV_OK;
+    if (!P->part_built) {
+        SPMV_TRY(P->part_bounds.alloc((size_t)(P->parts + 1) * 4));
+        SPMV_HIP(launch_partition(P->rowptr, P->n, P->parts, P->part_bounds.as<int32_t>(), S(P)));
+        P->part_built = true;
+    }
+    SPMV_TRY(ensure_timing_vectors(P));
+    DevBuf stamps, zeros, rp64, ci64;
+    SPMV_TRY(stamps.alloc((size_t)P->parts * 16));
+    SPMV_TRY(zeros.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 4));
+    SPMV_TRY(rp64.alloc((size_t)(P->n + 1) * 8));
+    SPMV_TRY(ci64.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 8));
+    SPMV_HIP(hipMemsetAsync(zeros.p, 0, zeros.bytes, S(P)));
+    SPMV_HIP(launch_widen(P->rowptr, rp64.as<int64_t>(), P->n + 1, S(P)));
+    SPMV_HIP(launch_widen(P->colind, ci64.as<int64_t>(), P->nnz, S(P)));
+    const int32_t *bounds = P->part_bounds.as<int32_t>();
+    auto *st = stamps.as<unsigned long long>();
+    auto base = [&]() -> spmv_status_t {
+        SPMV_HIP(launch_csr_part(*P, bounds, P->rowptr, P->colind, nullptr, nullptr, P->tx.p,
+                                 P->ty.p, st, S(P)));
+        return SPMV_OK;
+    };
+    auto nox = [&]() -> spmv_status_t {
+        SPMV_HIP(launch_csr_part(*P, bounds, P->rowptr, zeros.as<int32_t>(), nullptr, nullptr,
+                                 P->tx.p, P->ty.p, st, S(P)));
+        return SPMV_OK;
+    };
+    auto inf = [&]() -> spmv_status_t {
+        SPMV_HIP(launch_csr_part(*P, bounds, nullptr, nullptr, rp64.as<int64_t>(),
+                                 ci64.as<int64_t>(), P->tx.p, P->ty.p, st, S(P)));
+        return SPMV_OK;
+    };
+    // warm-up of each kind
+    SPMV_TRY(base());
+    SPMV_TRY(nox());
+    SPMV_TRY(inf());
+    std::vector<double> tb, tn, ti, dmax, dmean;
+    std::vector<unsigned long long> h((size_t)P->parts * 2);
+    for (int r = 0; r < reps; ++r) {
+        SPMV_TRY(time_runs(P, 1, false, base, &tb));
+        SPMV_HIP(hipMemcpyAsync(h.data(), st, h.size() * 8, hipMemcpyDeviceToHost, S(P)));
+        SPMV_TRY(sync(P));
+        double mx = 0.0, sum = 0.0;
+        for (int p = 0; p < P->parts; ++p) {
+            const double d = (double)(h[2 * p + 1] - h[2 * p]);
+            mx = d > mx ? d : mx;
+            sum += d;
+        }
+        dmax.push_back(mx);
+        dmean.push_back(sum / P->parts);
+    }
+    SPMV_TRY(time_runs(P, reps, false, nox, &tn));
+    SPMV_TRY(time_runs(P, reps, false, inf, &ti));
+    // balance score of the median baseline run
+    std::vector<std::pair<double, int>> order;
+    for (int r = 0; r < reps; ++r) order.push_back({dmax[r] / (dmean[r] > 0 ? dmean[r] : 1), r});
+    std::sort(order.begin(), order.end());
+    const int rm = order[order.size() / 2].second;
+    meas[0] = median(tb);
+    meas[1] = median(tn);
+    meas[2] = median(ti);
+    meas[3] = dmax[rm];
+    meas[4] = dmean[rm];
+    return SPMV_OK;
+}
+
+double ratio(double a, double b) { return b > 0 ? a / b : 0.0; }
+
+void cascade(const double meas[5], const double feats[12], const double th[4], uint32_t feas,
+             int32_t *variant, int32_t *klass, double scores[3]) {
+    const double s[3] = {ratio(meas[0], meas[1]), ratio(meas[2], meas[0]), ratio(meas[3], meas[4])};
+    int order[3] = {0, 1, 2};
+    std::stable_sort(order, order + 3, [&](int a, int b) { return s[a] > s[b]; });
+    int k = K_CMP;
+    for (int i = 0; i < 3; ++i) {
+        const int b = order[i];
+        if (s[b] > th[b]) {
+            k = b == 0 ? K_CML : b == 1 ? K_MB : K_IMB;
+            break;
+        }
+    }
+    int v;
+    if (k == K_CML) v = (feas >> V_XBLOCK_LDS) & 1 ? V_XBLOCK_LDS : V_CSR_VECTOR;
+    else if (k == K_MB) v = (feas >> V_DELTA16) & 1 ? V_DELTA16 : V_CSR_VECTOR;
+    else if (k == K_IMB) v = V_MERGE_PATH;
+    else v = feats[2] <= th[3] ? V_SHORT_ROW : V_CSR_VECTOR;
+    *variant = v;
+    *klass = k;
+    if (scores)
+        for (int i = 0; i < 3; ++i) scores[i] = s[i];
+}
+
+// ------------------------------------------------------------ MLP on device
+spmv_status_t model_device(const float **params, const float **norm) {
+    int dev = 0;
+    SPMV_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_model.loaded) return fail(SPMV_ERR_NO_MODEL, "no MLP model loaded");
+    auto it = g_model.dev.find(dev);
+    if (it == g_model.dev.end()) {
+        DevBuf *b = new DevBuf();
+        spmv_status_t st = b->alloc((kNParams + 24) * 4);
+        if (st != SPMV_OK) { delete b; return st; }
+        std::vector<float> host(g_model.params);
+        host.insert(host.end(), g_model.norm, g_model.norm + 24);
+        hipError_t e = hipMemcpy(b->p, host.data(), host.size() * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { delete b; return fail_hip(e, "hipMemcpy(model)", __FILE__, __LINE__); }
+        it = g_model.dev.emplace(dev, b).first;
+    }
+    *params = it->second->as<float>();
+    *norm = it->second->as<float>() + kNParams;
+    return SPMV_OK;
+}
+
+spmv_status_t mlp_predict(const double f[12], uint32_t feas, hipStream_t s, float *d_out,
+                          float *h_out, int32_t *variant, float *margin, int32_t *fallback,
+                          float *logits, float *z) {
+    const float *dp, *dn;
+    SPMV_TRY(model_device(&dp, &dn));
+    float tau;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        tau = g_model.tau;
+    }
+    SPMV_HIP(launch_mlp_infer(dp, dn, f, feas, tau, d_out, s));
+    SPMV_HIP(hipMemcpyAsync(h_out, d_out, 32 * 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    int32_t v;
+    memcpy(&v, &h_out[0], 4);
+    if (variant) *variant = v;
+    if (margin) *margin = h_out[1];
+    if (fallback) *fallback = h_out[2] != 0.f;
+    if (logits) memcpy(logits, h_out + 3, 6 * 4);
+    if (z) memcpy(z, h_out + 9, 12 * 4);
+    return SPMV_OK;
+}
+
+}  // namespace
+}  // namespace spmvsel
+
+using namespace spmvsel;
+
+// ============================================================ C ABI
+extern "C" {
+
+const char *spmv_last_error(void) { return g_err.c_str(); }
+
+spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols, int64_t nnz,
+                               const int32_t *d_rowptr, const int32_t *d_colind,
+                               const void *d_val, int32_t val_dtype, void *stream,
+                               uint32_t flags) {
+    clear_error();
+    if (!out) return fail(SPMV_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_rows < 0 || n_cols < 0 || nnz < 0)
+        return fail(SPMV_ERR_ARG, "negative size");
+    if (n_rows >= INT32_MAX || n_cols > INT32_MAX || nnz >= INT32_MAX)
+        return fail(SPMV_ERR_ARG, "sizes must be below 2^31");
+    if (val_dtype < SPMV_F64 || val_dtype > SPMV_BF16)
+        return fail(SPMV_ERR_ARG, "unknown value dtype %d", val_dtype);
+    if (!d_rowptr) return fail(SPMV_ERR_ARG, "rowptr is NULL");
+    if (nnz > 0 && (!d_colind || !d_val)) return fail(SPMV_ERR_ARG, "colind or val is NULL");
+    if (nnz > 0 && n_rows == 0) return fail(SPMV_ERR_CSR_ROWPTR, "nonzeros without rows");
+    if (((uintptr_t)d_rowptr & 3) || (nnz > 0 && (((uintptr_t)d_colind & 15) || ((uintptr_t)d_val & 15))))
+        return fail(SPMV_ERR_ARG, "arrays must be 16-byte aligned (rowptr 4-byte)");
+    spmv_plan *P = new (std::nothrow) spmv_plan();
+    if (!P) return fail(SPMV_ERR_OOM, "host allocation failed");
+    P->n = n_rows;
+    P->m = n_cols;
+    P->nnz = nnz;
+    P->dtype = val_dtype;
+    P->stream = (hipStream_t)stream;
+    P->flags = flags;
+    P->rowptr = d_rowptr;
+    P->colind = d_colind;
+    P->val = d_val;
+    auto bail = [&](spmv_status_t st) {
+        delete P;
+        return st;
+    };
+    spmv_status_t st;
+#define BAIL_HIP(expr)                                                      \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess) return bail(fail_hip(e_, #expr, __FILE__, __LINE__)); \
+    } while (0)
+#define BAIL(expr)                                                          \
+    do {                                                                    \
+        if ((st = (expr)) != SPMV_OK) return bail(st);                      \
+    } while (0)
+    BAIL_HIP(hipGetDevice(&P->device));
+    BAIL_HIP(hipDeviceGetAttribute(&P->num_cus, hipDeviceAttributeMultiprocessorCount, P->device));
+    BAIL_HIP(hipHostMalloc(&P->h_pinned, 4096, hipHostMallocDefault));
+    BAIL(P->scratch.alloc(kScratchBytes));
+    if (flags & SPMV_COPY_INPUTS) {
+        const size_t vb = vbytes(val_dtype);
+        BAIL(P->own_rowptr.alloc((size_t)(n_rows + 1) * 4));
+        BAIL(P->own_colind.alloc((size_t)(nnz > 0 ? nnz : 1) * 4 + 16));
+        BAIL(P->own_val.alloc((size_t)(nnz > 0 ? nnz : 1) * vb + 16));
+        BAIL_HIP(hipMemcpyAsync(P->own_rowptr.p, d_rowptr, (size_t)(n_rows + 1) * 4,
+                                hipMemcpyDeviceToDevice, P->stream));
+        if (nnz > 0) {
+            BAIL_HIP(hipMemcpyAsync(P->own_colind.p, d_colind, (size_t)nnz * 4,
+                                    hipMemcpyDeviceToDevice, P->stream));
+            BAIL_HIP(hipMemcpyAsync(P->own_val.p, d_val, (size_t)nnz * vb,
+                                    hipMemcpyDeviceToDevice, P->stream));
+        }
+        P->rowptr = P->own_rowptr.as<int32_t>();
+        P->colind = P->own_colind.as<int32_t>();
+        P->val = P->own_val.p;
+    }
+    // launch parameters from the mean row length
+    const double avg = n_rows > 0 ? (double)nnz / (double)n_rows : 0.0;
+    P->vec_width = pow2_ceil(avg, 2, 64);
+    P->rs_rows = pow2_floor((double)kChunk / (kBlock * (avg > 1e-9 ? avg : 1e-9)), 1, kRowStreamMaxR);
+    P->xb_rows = pow2_floor(32768.0 / (avg > 1.0 ? avg : 1.0), 256, kXbMaxRows);
+    P->xb_width = P->vec_width;
+    P->parts = P->num_cus * 8;
+    if (!(flags & SPMV_SKIP_VALIDATE)) {
+        uint64_t *f = scr<uint64_t>(P, kOffFlags);
+        BAIL_HIP(launch_validate(*P, f, P->stream));
+        BAIL_HIP(hipMemcpyAsync(P->h_pinned, f, 24, hipMemcpyDeviceToHost, P->stream));
+        BAIL_HIP(hipStreamSynchronize(P->stream));
+        uint64_t h[3];
+        memcpy(h, P->h_pinned, 24);
+        if (h[0] & 1) return bail(fail(SPMV_ERR_CSR_ROWPTR, "invalid rowptr"));
+        if (h[0] & 2) return bail(fail(SPMV_ERR_CSR_COL_RANGE, "column index outside [0, %lld)", (long long)n_cols));
+        if (h[1] != h[2])
+            return bail(fail(SPMV_ERR_CSR_UNSORTED, "columns not strictly increasing in %llu places",
+                             (unsigned long long)(h[1] - h[2])));
+    } else {
+        BAIL_HIP(hipStreamSynchronize(P->stream));
+    }
+#undef BAIL
+#undef BAIL_HIP
+    *out = P;
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_plan_destroy(spmv_plan_t P) {
+    if (!P) return SPMV_OK;
+    (void)hipStreamSynchronize(P->stream);
+    if (P->h_pinned) (void)hipHostFree(P->h_pinned);
+    delete P;
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_features(spmv_plan_t P, double out[12], uint64_t acc[12]) {
+    clear_error();
+    if (!P || !out) return fail(SPMV_ERR_ARG, "NULL argument");
+    SPMV_TRY(ensure_features(P));
+    memcpy(out, P->feats, sizeof P->feats);
+    if (acc) memcpy(acc, P->acc, sizeof P->acc);
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_execute(spmv_plan_t P, const void *d_x, void *d_y, void *stream) {
+    if (!P) return fail(SPMV_ERR_ARG, "plan is NULL");
+    if (P->n > 0 && !d_y) return fail(SPMV_ERR_ARG, "y is NULL");
+    if (P->nnz > 0 && !d_x) return fail(SPMV_ERR_ARG, "x is NULL");
+    return run_variant(P, P->variant, d_x, d_y, (hipStream_t)stream);
+}
+
+spmv_status_t spmv_set_variant(spmv_plan_t P, int32_t v) {
+    clear_error();
+    if (!P) return fail(SPMV_ERR_ARG, "plan is NULL");
+    if (v < 0 || v >= SPMV_N_VARIANTS) return fail(SPMV_ERR_ARG, "unknown variant %d", v);
+    SPMV_TRY(build_format(P, v));
+    P->variant = v;
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_get_variant(spmv_plan_t P, int32_t *v) {
+    if (!P || !v) return fail(SPMV_ERR_ARG, "NULL argument");
+    *v = P->variant;
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_variant_mask(spmv_plan_t P, uint32_t *bits) {
+    clear_error();
+    if (!P || !bits) return fail(SPMV_ERR_ARG, "NULL argument");
+    return feasible_mask(P, bits);
+}
+
+spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
+    if (!P || !bytes) return fail(SPMV_ERR_ARG, "NULL argument");
+    if (v < 0 || v >= SPMV_N_VARIANTS) return fail(SPMV_ERR_ARG, "unknown variant %d", v);
+    const int64_t vb = vbytes(P->dtype), xb = xbytes(P->dtype);
+    const int64_t ib = v == V_DELTA16 ? 2 : 4;
+    *bytes = 4 * (P->n + 1) + (ib + vb) * P->nnz + xb * P->m + xb * P->n +
+             (v == V_DELTA16 ? 4 * P->n : 0);
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_time_variant(spmv_plan_t P, int32_t v, int32_t reps, int32_t cold,
+                                double *t_med, double *t_min) {
+    clear_error();
+    if (!P || reps < 1) return fail(SPMV_ERR_ARG, "bad argument");
+    SPMV_TRY(build_format(P, v));
+    SPMV_TRY(ensure_timing_vectors(P));
+    auto run = [&]() { return run_variant(P, v, P->tx.p, P->ty.p, S(P)); };
+    SPMV_TRY(run());
+    SPMV_TRY(run());
+    std::vector<double> t;
+    SPMV_TRY(time_runs(P, reps, cold != 0, run, &t));
+    if (t_med) *t_med = median(t);
+    if (t_min) *t_min = *std::min_element(t.begin(), t.end());
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
+    clear_error();
+    if (!P || !value) return fail(SPMV_ERR_ARG, "NULL argument");
+    switch (key) {
+    case 0: *value = P->variant; break;
+    case 1: *value = P->vec_width; break;
+    case 2: *value = P->rs_rows * kBlock; break;
+    case 3: *value = kMergeTile; break;
+    case 4: *value = (P->n + P->nnz + kMergeTile - 1) / kMergeTile; break;
+    case 5: *value = P->xb_rows; break;
+    case 6: *value = (P->n + P->xb_rows - 1) / P->xb_rows; break;
+    case 7: *value = kXbChunkBytes / xbytes(P->dtype); break;
+    case 8: *value = P->parts; break;
+    case 9: SPMV_TRY(ensure_features(P)); *value = d16_feasible(P); break;
+    case 10: SPMV_TRY(build_xblock(P)); *value = P->xb_feasible; break;
+    default: return fail(SPMV_ERR_ARG, "unknown key %d", key);
+    }
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int64_t bytes) {
+    clear_error();
+    if (!P || (!dst && bytes > 0)) return fail(SPMV_ERR_ARG, "NULL argument");
+    const void *src = nullptr;
+    int64_t want = 0;
+    switch (which) {
+    case 0: case 1:
+        SPMV_TRY(build_format(P, V_DELTA16));
+        src = which == 0 ? P->d16_base.p : P->d16_off.p;
+        want = which == 0 ? 4 * P->n : 2 * P->nnz;
+        break;
+    case 2: case 3:
+        SPMV_TRY(build_format(P, V_MERGE_PATH));
+        src = which == 2 ? P->mp_split_row.p : P->mp_split_nnz.p;
+        want = 4 * (P->mp_tiles + 1);
+        break;
+    case 4: case 5:
+        SPMV_TRY(build_xblock(P));
+        src = which == 4 ? P->xb_cmin.p : P->xb_cmax.p;
+        want = 4 * P->xb_panels;
+        break;
+    case 6:
+        if (!P->part_built) {
+            SPMV_TRY(P->part_bounds.alloc((size_t)(P->parts + 1) * 4));
+            SPMV_HIP(launch_partition(P->rowptr, P->n, P->parts, P->part_bounds.as<int32_t>(), S(P)));
+            P->part_built = true;
+        }
+        src = P->part_bounds.p;
+        want = 4 * (P->parts + 1);
+        break;
+    default: return fail(SPMV_ERR_ARG, "unknown array %d", which);
+    }
+    if (bytes != want) return fail(SPMV_ERR_ARG, "array %d has %lld bytes, not %lld", which,
+                                   (long long)want, (long long)bytes);
+    if (want > 0) SPMV_HIP(hipMemcpyAsync(dst, src, (size_t)want, hipMemcpyDeviceToHost, S(P)));
+    return sync(P);
+}
+
+spmv_status_t spmv_profile_measure(spmv_plan_t P, int32_t reps, double meas[5]) {
+    clear_error();
+    if (!P || !meas || reps < 1) return fail(SPMV_ERR_ARG, "bad argument");
+    return profile_measure(P, reps, meas);
+}
+
+spmv_status_t spmv_profile_decide(const double meas[5], const double feats[12],
+                                  const double theta[4], uint32_t feas, int32_t *variant,
+                                  int32_t *klass) {
+    clear_error();
+    if (!meas || !feats || !theta || !variant || !klass) return fail(SPMV_ERR_ARG, "NULL argument");
+    cascade(meas, feats, theta, feas, variant, klass, nullptr);
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_set_thresholds(const double theta[4]) {
+    if (!theta) return fail(SPMV_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_mu);
+    memcpy(g_theta, theta, sizeof g_theta);
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_get_thresholds(double theta[4]) {
+    if (!theta) return fail(SPMV_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_mu);
+    memcpy(theta, g_theta, sizeof g_theta);
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_select(spmv_plan_t P, int32_t selector, spmv_select_info_t *info) {
+    clear_error();
+    if (!P) return fail(SPMV_ERR_ARG, "plan is NULL");
+    if (selector < SEL_PROFILING || selector > SEL_EXHAUSTIVE)
+        return fail(SPMV_ERR_ARG, "unknown selector %d", selector);
+    spmv_select_info_t I;
+    memset(&I, 0, sizeof I);
+    I.klass = -1;
+    double th[4];
+    spmv_get_thresholds(th);
+    const double t0 = now_s();
+    SPMV_TRY(ensure_features(P));
+    uint32_t feas = 0;
+    SPMV_TRY(feasible_mask(P, &feas));
+    const double t1 = now_s();
+    I.t_features_s = t1 - t0;
+    I.feasible = feas;
+    memcpy(I.features, P->feats, sizeof I.features);
+    int32_t v = V_CSR_VECTOR;
+    int used = selector;
+    if (selector == SEL_MLP) {
+        int32_t fb = 1;
+        spmv_status_t st = mlp_predict(P->feats, feas, S(P), scr<float>(P, kOffMlp),
+                                       static_cast<float *>(P->h_pinned) + 512, &v, &I.margin,
+                                       &fb, I.logits, nullptr);
+        if (st == SPMV_ERR_NO_MODEL) { fb = 1; clear_error(); }
+        else if (st != SPMV_OK) return st;
+        I.t_decide_s = now_s() - t1;
+        if (fb || v < 0) {
+            I.fell_back = 1;
+            used = SEL_PROFILING;
+        }
+    }
+    if (used == SEL_PROFILING) {
+        const double tp = now_s();
+        SPMV_TRY(profile_measure(P, 3, I.meas));
+        const double tq = now_s();
+        I.t_profile_s = tq - tp;
+        cascade(I.meas, P->feats, th, feas, &v, &I.klass, I.scores);
+        I.t_decide_s += now_s() - tq;
+    } else if (used == SEL_EXHAUSTIVE) {
+        double best = 0;
+        v = -1;
+        for (int k = 0; k < SPMV_N_VARIANTS; ++k) {
+            if (!((feas >> k) & 1)) continue;
+            double tm = 0;
+            SPMV_TRY(spmv_time_variant(P, k, 10, 0, &tm, nullptr));
+            I.variant_times_s[k] = tm;
+            if (v < 0 || tm < best) { best = tm; v = k; }
+        }
+        I.t_decide_s = now_s() - t1;
+    }
+    I.t_total_s = now_s() - t0;
+    I.selector = used;
+    const double tp0 = now_s();
+    SPMV_TRY(build_format(P, v));
+    I.t_prepare_s = now_s() - tp0;
+    P->variant = v;
+    I.variant = v;
+    if (info) *info = I;
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_model_load(const char *path) {
+    clear_error();
+    if (!path) return fail(SPMV_ERR_ARG, "NULL path");
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return fail(SPMV_ERR_NO_MODEL, "cannot open %s", path);
+    std::vector<unsigned char> buf;
+    unsigned char tmp[65536];
+    size_t got;
+    while ((got = fread(tmp, 1, sizeof tmp, fp)) > 0) buf.insert(buf.end(), tmp, tmp + got);
+    fclose(fp);
+    const size_t want = 8 + 4 + 4 + 24 * 4 + 4 + (size_t)kNParams * 4 + 4;
+    if (buf.size() != want) return fail(SPMV_ERR_NO_MODEL, "%s: %zu bytes, expected %zu", path, buf.size(), want);
+    if (memcmp(buf.data(), "SPMVMLP1", 8) != 0) return fail(SPMV_ERR_NO_MODEL, "%s: bad magic", path);
+    uint32_t ver, np, crc;
+    memcpy(&ver, &buf[8], 4);
+    memcpy(&np, &buf[12], 4);
+    memcpy(&crc, &buf[want - 4], 4);
+    if (ver != 1 || np != (uint32_t)kNParams) return fail(SPMV_ERR_NO_MODEL, "%s: bad header", path);
+    if (crc32(buf.data(), want - 4) != crc) return fail(SPMV_ERR_NO_MODEL, "%s: CRC mismatch", path);
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_model.dev) delete kv.second;
+    g_model.dev.clear();
+    memcpy(g_model.norm, &buf[16], 24 * 4);
+    memcpy(&g_model.tau, &buf[16 + 96], 4);
+    g_model.params.resize(kNParams);
+    memcpy(g_model.params.data(), &buf[16 + 96 + 4], (size_t)kNParams * 4);
+    g_model.loaded = true;
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_model_unload(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_model.dev) delete kv.second;
+    g_model.dev.clear();
+    g_model.loaded = false;
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_mlp_predict(const double features[12], uint32_t feas, int32_t *variant,
+                               float *margin, int32_t *fallback, float logits[6], float z[12]) {
+    clear_error();
+    if (!features) return fail(SPMV_ERR_ARG, "NULL features");
+    DevBuf out;
+    SPMV_TRY(out.alloc(256));
+    float h[32];
+    spmv_status_t st = mlp_predict(features, feas, nullptr, out.as<float>(), h, variant, margin,
+                                   fallback, logits, z);
+    return st;
+}
+
+spmv_status_t spmv_mlp_forward_backward(const float *params, const float *Z, const int32_t *labels,
+                                        const uint8_t *mask, int32_t B, float *grads, float *loss,
+                                        void *stream) {
+    clear_error();
+    if (!params || !Z || !labels || !mask || !grads || !loss || B < 1 || B > 1024)
+        return fail(SPMV_ERR_ARG, "bad argument");
+    SPMV_HIP(launch_mlp_fwd_bwd(params, Z, labels, mask, B, grads, loss, (hipStream_t)stream));
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_mlp_adam_step(float *p, const float *g, float *m, float *v, int32_t n,
+                                 int32_t step, float lr, float b1, float b2, float eps,
+                                 void *stream) {
+    clear_error();
+    if (!p || !g || !m || !v || n < 0 || step < 1) return fail(SPMV_ERR_ARG, "bad argument");
+    SPMV_HIP(launch_mlp_adam(p, g, m, v, n, step, lr, b1, b2, eps, (hipStream_t)stream));
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_quantize(const double *in, void *out, int64_t n, int32_t to, void *stream) {
+    clear_error();
+    if (n < 0 || (n > 0 && (!in || !out)) || (to != SPMV_F32 && to != SPMV_BF16))
+        return fail(SPMV_ERR_ARG, "bad argument");
+    SPMV_HIP(launch_quantize(in, out, n, to, (hipStream_t)stream));
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_cache_flush(void *stream) {
+    clear_error();
+    return flush_cache((hipStream_t)stream);
+}
+
+spmv_status_t spmv_hbm_probe(int64_t bytes, double *read_gbs, double *copy_gbs) {
+    clear_error();
+    if (bytes < (1 << 20)) return fail(SPMV_ERR_ARG, "buffer too small");
+    bytes &= ~(int64_t)4095;
+    DevBuf a, b, sink;
+    SPMV_TRY(a.alloc((size_t)bytes));
+    SPMV_TRY(b.alloc((size_t)bytes));
+    SPMV_TRY(sink.alloc(4096 * 8));
+    SPMV_HIP(hipMemset(a.p, 1, (size_t)bytes));
+    SPMV_HIP(hipMemset(b.p, 0, (size_t)bytes));
+    hipEvent_t e0, e1;
+    SPMV_HIP(hipEventCreate(&e0));
+    SPMV_HIP(hipEventCreate(&e1));
+    std::vector<double> tr, tc;
+    for (int r = 0; r < 6; ++r) {
+        float ms;
+        SPMV_HIP(hipEventRecord(e0, nullptr));
+        SPMV_HIP(launch_read_probe(a.p, (size_t)bytes, sink.as<double>(), nullptr));
+        SPMV_HIP(hipEventRecord(e1, nullptr));
+        SPMV_HIP(hipEventSynchronize(e1));
+        hipEventElapsedTime(&ms, e0, e1);
+        if (r) tr.push_back(ms * 1e-3);
+        SPMV_HIP(hipEventRecord(e0, nullptr));
+        SPMV_HIP(launch_copy_probe(a.p, b.p, (size_t)bytes, nullptr));
+        SPMV_HIP(hipEventRecord(e1, nullptr));
+        SPMV_HIP(hipEventSynchronize(e1));
+        hipEventElapsedTime(&ms, e0, e1);
+        if (r) tc.push_back(ms * 1e-3);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (read_gbs) *read_gbs = (double)bytes / median(tr) * 1e-9;
+    if (copy_gbs) *copy_gbs = 2.0 * (double)bytes / median(tc) * 1e-9;
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_generate(int32_t family, const int64_t *params, int32_t n_params, uint64_t seed,
+                            int32_t *d_rowptr, int32_t *d_colind, double *d_val, int64_t *nnz_out,
+                            void *stream) {
+    clear_error();
+    static const int need[9] = {2, 2, 2, 2, 3, 3, 2, 4, 1};
+    if (family < 0 || family > 8) return fail(SPMV_ERR_ARG, "unknown family %d", family);
+    if (!params || n_params < need[family] || n_params > 6 || !d_rowptr)
+        return fail(SPMV_ERR_ARG, "bad generator arguments");
+    int64_t p[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < n_params; ++i) p[i] = params[i];
+    for (int i = 0; i < need[family]; ++i)
+        if (p[i] < 0) return fail(SPMV_ERR_ARG, "negative generator parameter");
+    int64_t n;
+    if (family <= 1) n = p[0] * p[0];
+    else if (family <= 3) n = p[0] * p[0] * p[0];
+    else n = p[0];
+    if (p[0] > (1 << 24) * 128ll || n >= INT32_MAX) return fail(SPMV_ERR_ARG, "too many rows");
+    if (family == 4 && (p[1] < 1 || p[1] >= INT32_MAX)) return fail(SPMV_ERR_ARG, "bad column count");
+    if ((family == 5 || family == 6) && (p[1] < 1 || p[1] > (1 << 20)))
+        return fail(SPMV_ERR_ARG, "d16 out of range");
+    if (family == 7 && (p[1] < 1 || p[1] >= (1 << 16) || p[2] < 1 || p[2] >= (1 << 21)))
+        return fail(SPMV_ERR_ARG, "power-law parameters out of range");
+    hipStream_t s = (hipStream_t)stream;
+    if (!d_colind) {
+        DevBuf lens, tmp;
+        size_t need_tmp = 0;
+        SPMV_TRY(lens.alloc((size_t)(n > 0 ? n : 1) * 4));
+        SPMV_HIP(launch_gen_lengths(family, p, seed, n, lens.as<int32_t>(), s));
+        SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>(), d_rowptr, n, nullptr, 0, s, &need_tmp));
+        SPMV_TRY(tmp.alloc(need_tmp));
+        SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>(), d_rowptr, n, tmp.p, tmp.bytes, s, nullptr));
+        int64_t total = 0;
+        const int64_t nb = (int64_t)need_tmp / 8 - 1;
+        SPMV_HIP(hipMemcpyAsync(&total, tmp.as<int64_t>() + nb, 8, hipMemcpyDeviceToHost, s));
+        SPMV_HIP(hipStreamSynchronize(s));
+        if (total >= INT32_MAX) return fail(SPMV_ERR_ARG, "generated matrix has %lld >= 2^31 nonzeros", (long long)total);
+        if (nnz_out) *nnz_out = total;
+        return SPMV_OK;
+    }
+    if (!d_val) return fail(SPMV_ERR_ARG, "val is NULL");
+    SPMV_HIP(launch_gen_fill(family, p, seed, n, d_rowptr, d_colind, d_val, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_generate_vector(int64_t n, uint64_t seed, double *d_x, void *stream) {
+    clear_error();
+    if (n < 0 || (n > 0 && !d_x)) return fail(SPMV_ERR_ARG, "bad argument");
+    SPMV_HIP(launch_gen_vector(n, seed, d_x, (hipStream_t)stream));
+    return SPMV_OK;
+}
+
+}  // extern "C"

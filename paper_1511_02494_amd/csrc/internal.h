@@ -1,0 +1,172 @@
+// Internal declarations of libspmvsel (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "spmvsel.h"
+
+namespace spmvsel {
+
+// ---------------------------------------------------------------- constants
+constexpr int kBlock = 256;           // threads per workgroup for every SpMV kernel
+constexpr int kRunLen = 8;            // nonzeros per thread run in the streaming kernels
+constexpr int kChunk = kBlock * kRunLen;  // nonzeros staged per LDS chunk
+constexpr int kRowStreamMaxR = 8;     // rows per thread (max) in short_row / delta16
+constexpr int kMergeIpt = 8;          // merge-path items per thread
+constexpr int kMergeTile = kBlock * kMergeIpt;
+constexpr int kXbMaxRows = 1024;      // x-block panel height (max)
+constexpr int kXbChunkBytes = 32768;  // LDS bytes of staged x per chunk
+constexpr int kKahanMinLen = 257;     // FP32 rows longer than 256 use Kahan sums
+constexpr int kLineBytes = 128;       // cache line assumed by the miss feature
+constexpr int64_t kLlcBytes = 256ll << 20;
+constexpr int kFeatBlocks = 1024;     // feature kernel partial records
+
+// ---------------------------------------------------------------- errors
+spmv_status_t fail(spmv_status_t st, const char *fmt, ...);
+spmv_status_t fail_hip(hipError_t e, const char *what, const char *file, int line);
+void clear_error();
+
+#define SPMV_HIP(expr)                                                          \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess) return ::spmvsel::fail_hip(e_, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define SPMV_TRY(expr)                                                          \
+    do {                                                                        \
+        spmv_status_t s_ = (expr);                                              \
+        if (s_ != SPMV_OK) return s_;                                           \
+    } while (0)
+
+// ---------------------------------------------------------------- device buffer
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    spmv_status_t alloc(size_t n);        // no-op if already >= n bytes
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+inline int vbytes(int dtype) { return dtype == SPMV_F64 ? 8 : dtype == SPMV_F32 ? 4 : 2; }
+inline int xbytes(int dtype) { return dtype == SPMV_F64 ? 8 : 4; }
+
+// ---------------------------------------------------------------- plan
+struct FeatureRecord {  // exact integer accumulators reduced on the device
+    uint64_t w[16];
+};
+
+}  // namespace spmvsel
+
+struct spmv_plan {
+    int64_t n = 0, m = 0, nnz = 0;
+    const int32_t *rowptr = nullptr;
+    const int32_t *colind = nullptr;
+    const void *val = nullptr;
+    int dtype = SPMV_F64;
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0;
+    int device = 0;
+    int num_cus = 256;
+    int variant = V_CSR_SCALAR;
+
+    spmvsel::DevBuf own_rowptr, own_colind, own_val;  // SPMV_COPY_INPUTS
+    spmvsel::DevBuf scratch;     // small: flags, feature partials, records
+    void *h_pinned = nullptr;    // pinned host staging (4 KiB)
+
+    // features
+    bool have_features = false;
+    double feats[12] = {0};
+    uint64_t acc[12] = {0};
+
+    // launch parameters
+    int vec_width = 2;           // csr_vector sub-wave width
+    int rs_rows = 1;             // rows per thread in the streaming kernels
+    int xb_rows = 256;           // x-block panel height
+    int xb_width = 2;            // x-block sub-wave width
+    int parts = 2048;            // profiling partitions
+
+    // derived formats (lazy)
+    bool d16_built = false;
+    spmvsel::DevBuf d16_base, d16_off;
+    bool mp_built = false;
+    int64_t mp_tiles = 0;
+    spmvsel::DevBuf mp_split_row, mp_split_nnz, mp_carry_row, mp_carry_val;
+    bool xb_built = false, xb_feasible = false;
+    int64_t xb_panels = 0;
+    spmvsel::DevBuf xb_cmin, xb_cmax;
+    bool part_built = false;
+    spmvsel::DevBuf part_bounds;
+
+    // timing helpers (lazy)
+    spmvsel::DevBuf tx, ty;      // x and y used by spmv_time_variant / profiling
+};
+
+namespace spmvsel {
+
+// ---------------------------------------------------------------- launchers
+// validation (k_validate.hip): writes flags[0] (bit0 rowptr, bit1 col range),
+// counts[1] = descending pairs, counts[2] = descending pairs at row starts
+hipError_t launch_validate(const spmv_plan &P, uint64_t *d_flags, hipStream_t s);
+
+// features (k_features.hip): final record -> d_rec (16 words)
+hipError_t launch_features(const spmv_plan &P, uint64_t *d_partials, uint64_t *d_rec,
+                           int xb, hipStream_t s);
+
+// SpMV variants (k_spmv.hip)
+hipError_t launch_csr_scalar(const spmv_plan &P, const void *x, void *y, hipStream_t s);
+hipError_t launch_csr_vector(const spmv_plan &P, const void *x, void *y, hipStream_t s);
+hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y, hipStream_t s);
+hipError_t launch_merge_path(const spmv_plan &P, const void *x, void *y, hipStream_t s);
+hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t s);
+
+// format preparation (k_prep.hip)
+hipError_t launch_delta16_encode(const spmv_plan &P, int32_t *base, uint16_t *off, hipStream_t s);
+hipError_t launch_merge_splits(const spmv_plan &P, int32_t *srow, int32_t *snnz, int64_t tiles,
+                               hipStream_t s);
+hipError_t launch_panel_windows(const spmv_plan &P, int rows_per_panel, int32_t *cmin,
+                                int32_t *cmax, int64_t panels, hipStream_t s);
+hipError_t launch_partition(const int32_t *rowptr, int64_t n, int parts, int32_t *bounds,
+                            hipStream_t s);
+hipError_t launch_widen(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+hipError_t launch_window_sum(const int32_t *cmin, const int32_t *cmax, int64_t panels,
+                             unsigned long long *d_sum, hipStream_t s);
+hipError_t launch_quantize(const double *in, void *out, int64_t n, int to, hipStream_t s);
+
+// profiling micro-benchmarks (k_profile.hip)
+hipError_t launch_csr_part(const spmv_plan &P, const int32_t *bounds, const int32_t *rp32,
+                           const int32_t *ci32, const int64_t *rp64, const int64_t *ci64,
+                           const void *x, void *y, unsigned long long *stamps, hipStream_t s);
+
+// MLP (k_mlp.hip)
+hipError_t launch_mlp_infer(const float *d_params, const float *d_norm, const double *feats,
+                            uint32_t feasible, float tau, float *d_out, hipStream_t s);
+hipError_t launch_mlp_fwd_bwd(const float *params, const float *Z, const int32_t *labels,
+                              const uint8_t *mask, int B, float *grads, float *loss,
+                              hipStream_t s);
+hipError_t launch_mlp_adam(float *p, const float *g, float *m, float *v, int n, int step,
+                           float lr, float b1, float b2, float eps, hipStream_t s);
+
+// generator and utilities (k_gen.hip, k_util.hip)
+hipError_t launch_gen_lengths(int family, const int64_t *prm, uint64_t seed, int64_t n,
+                              int32_t *lens, hipStream_t s);
+hipError_t launch_gen_fill(int family, const int64_t *prm, uint64_t seed, int64_t n,
+                           const int32_t *rowptr, int32_t *colind, double *val, hipStream_t s);
+hipError_t launch_gen_vector(int64_t n, uint64_t seed, double *x, hipStream_t s);
+hipError_t launch_exclusive_scan_i32(const int32_t *lens, int32_t *rowptr, int64_t n,
+                                     void *tmp, size_t tmp_bytes, hipStream_t s,
+                                     size_t *tmp_needed);
+hipError_t launch_flush(void *buf, size_t bytes, hipStream_t s);
+hipError_t launch_read_probe(const void *buf, size_t bytes, double *sink, hipStream_t s);
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+}  // namespace spmvsel

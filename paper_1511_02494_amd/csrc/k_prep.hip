@@ -1,0 +1,202 @@
+// Format preparation for the variants (built once per plan, lazily).
+#include "dev.h"
+#include "internal.h"
+
+namespace spmvsel {
+
+// ---- delta16: base_i = first column of row i (0 if empty), off_k = c_k - base_i.
+// A sub-wavefront of W lanes per row (W from the mean row length).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_delta16_encode(int64_t n, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           int32_t *__restrict__ base,
+                                                           uint16_t *__restrict__ off) {
+    const int lane = threadIdx.x & (W - 1);
+    const int64_t nsub = (int64_t)gridDim.x * (kBlock / W);
+    for (int64_t i = blockIdx.x * (int64_t)(kBlock / W) + threadIdx.x / W; i < n; i += nsub) {
+        const int32_t a = rp[i], b = rp[i + 1];
+        const int32_t b0 = a < b ? ci[a] : 0;
+        if (lane == 0) base[i] = b0;
+        for (int32_t k = a + lane; k < b; k += W) off[k] = (uint16_t)(ci[k] - b0);
+    }
+}
+
+hipError_t launch_delta16_encode(const spmv_plan &P, int32_t *base, uint16_t *off, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    const int W = P.vec_width;
+    int64_t g = (P.n + (kBlock / W) - 1) / (kBlock / W);
+    if (g > (int64_t)P.num_cus * 32) g = (int64_t)P.num_cus * 32;
+    switch (W) {
+#define ENC(WW) case WW: hipLaunchKernelGGL((k_delta16_encode<WW>), dim3((unsigned)g), dim3(kBlock), 0, s, P.n, P.rowptr, P.colind, base, off); break;
+        ENC(2) ENC(4) ENC(8) ENC(16) ENC(32) ENC(64)
+#undef ENC
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---- merge path: start coordinate of every tile (t = 0..tiles).  On
+// diagonal d the row coordinate is the smallest i in [max(0, d-NNZ),
+// min(d, N)] with rowptr[i+1] > d - i - 1; the nonzero coordinate is d - i.
+__global__ __launch_bounds__(kBlock) void k_merge_splits(int64_t n, int64_t nnz, int64_t tiles,
+                                                         const int32_t *__restrict__ rp,
+                                                         int32_t *__restrict__ srow,
+                                                         int32_t *__restrict__ snnz) {
+    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (t > tiles) return;
+    const int64_t total = n + nnz;
+    const int64_t d = t * kMergeTile < total ? t * kMergeTile : total;
+    int64_t lo = d - nnz > 0 ? d - nnz : 0, hi = d < n ? d : n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)rp[mid + 1] <= d - mid - 1) lo = mid + 1; else hi = mid;
+    }
+    srow[t] = (int32_t)lo;
+    snnz[t] = (int32_t)(d - lo);
+}
+
+hipError_t launch_merge_splits(const spmv_plan &P, int32_t *srow, int32_t *snnz, int64_t tiles,
+                               hipStream_t s) {
+    const int64_t g = (tiles + 1 + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_merge_splits, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, P.nnz, tiles,
+                       P.rowptr, srow, snnz);
+    return hipGetLastError();
+}
+
+// ---- x-block panels: the column window [min first col, max last col] of
+// each panel of H rows ((0, -1) when the panel has no nonzeros).  One
+// wavefront per panel.
+__global__ __launch_bounds__(kBlock) void k_panel_windows(int64_t n, int H, int64_t panels,
+                                                          const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ ci,
+                                                          int32_t *__restrict__ cmin,
+                                                          int32_t *__restrict__ cmax) {
+    const int64_t p = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (p >= panels) return;
+    const int64_t r0 = p * H;
+    const int64_t r1 = (r0 + H) < n ? (r0 + H) : n;
+    int32_t lo = INT32_MAX, hi = -1;
+    for (int64_t r = r0 + lane; r < r1; r += 64) {
+        const int32_t a = rp[r], b = rp[r + 1];
+        if (a < b) {
+            lo = ci[a] < lo ? ci[a] : lo;
+            hi = ci[b - 1] > hi ? ci[b - 1] : hi;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+        lo = lo2 < lo ? lo2 : lo;
+        hi = hi2 > hi ? hi2 : hi;
+    }
+    if (lane == 0) {
+        cmin[p] = hi < 0 ? 0 : lo;
+        cmax[p] = hi;
+    }
+}
+
+hipError_t launch_panel_windows(const spmv_plan &P, int H, int32_t *cmin, int32_t *cmax,
+                                int64_t panels, hipStream_t s) {
+    const int64_t g = (panels * 64 + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_panel_windows, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, H, panels,
+                       P.rowptr, P.colind, cmin, cmax);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_window_sum(const int32_t *__restrict__ cmin,
+                                                       const int32_t *__restrict__ cmax,
+                                                       int64_t panels,
+                                                       unsigned long long *sum) {
+    unsigned long long t = 0;
+    for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < panels;
+         p += (int64_t)gridDim.x * kBlock)
+        t += (unsigned long long)(cmax[p] - cmin[p] + 1);
+    if (t) atomicAdd(sum, t);
+}
+
+hipError_t launch_window_sum(const int32_t *cmin, const int32_t *cmax, int64_t panels,
+                             unsigned long long *d_sum, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(d_sum, 0, sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    int64_t g = (panels + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_window_sum, dim3((unsigned)g), dim3(kBlock), 0, s, cmin, cmax, panels, d_sum);
+    return hipGetLastError();
+}
+
+// ---- static partition with equal nonzeros: b_0 = 0, b_P = N, and b_p the
+// first row whose start offset reaches ceil(p NNZ / P).
+__global__ __launch_bounds__(kBlock) void k_partition(int64_t n, int parts,
+                                                      const int32_t *__restrict__ rp,
+                                                      int32_t *__restrict__ b) {
+    const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (p > parts) return;
+    if (p == 0) { b[0] = 0; return; }
+    if (p == parts) { b[parts] = (int32_t)n; return; }
+    const int64_t nnz = rp[n];
+    const int64_t target = (p * nnz + parts - 1) / parts;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)rp[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    b[p] = (int32_t)lo;
+}
+
+hipError_t launch_partition(const int32_t *rowptr, int64_t n, int parts, int32_t *bounds,
+                            hipStream_t s) {
+    const int64_t g = (parts + 1 + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_partition, dim3((unsigned)g), dim3(kBlock), 0, s, n, parts, rowptr, bounds);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_widen(const int32_t *__restrict__ in,
+                                                  int64_t *__restrict__ out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        out[i] = in[i];
+}
+
+hipError_t launch_widen(const int32_t *in, int64_t *out, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)g), dim3(kBlock), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+// ---- value rounding from FP64, one round-to-nearest-even.
+// FP32: the conversion instruction.  BF16: round to odd into FP32 (truncate
+// toward zero, then set the last bit if anything was dropped), then round to
+// nearest even into 8 significant bits; rounding to odd first with at least
+// two extra bits makes the two-step rounding equal to a single rounding
+// (Boldo and Melquiond, IEEE TC 2008).
+__device__ __forceinline__ uint16_t f64_to_bf16(double d) {
+    if (d != d) return 0x7FC0;
+    float f = __double2float_rz(d);
+    uint32_t u = __float_as_uint(f);
+    if ((double)f != d) u |= 1u;
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(kBlock) void k_quantize(const double *__restrict__ in, void *out,
+                                                     int64_t n, int to) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double d = in[i];
+        if (to == SPMV_F32) static_cast<float *>(out)[i] = __double2float_rn(d);
+        else static_cast<uint16_t *>(out)[i] = f64_to_bf16(d);
+    }
+}
+
+hipError_t launch_quantize(const double *in, void *out, int64_t n, int to, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_quantize, dim3((unsigned)g), dim3(kBlock), 0, s, in, out, n, to);
+    return hipGetLastError();
+}
+
+}  // namespace spmvsel

@@ -1,0 +1,467 @@
+// The six SpMV variants of the optimisation pool (gfx950, wave64).
+//
+// All compute y_i = sum_j A_ij x_j for CSR A (Algorithm 1).  FP64 plans
+// accumulate in FP64; FP32/BF16 plans accumulate in FP32 with Kahan
+// compensation on rows of more than 256 nonzeros.  Reductions use fixed
+// pairings and fixed orders, so every variant is deterministic.
+#include "dev.h"
+#include "internal.h"
+
+namespace spmvsel {
+
+// ============================================================ csr_scalar
+// One lane per row, summing the row in increasing column order from +0:
+// exactly the order of Algorithm 1.  The unoptimised baseline.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_csr_scalar(int64_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       const V *__restrict__ val,
+                                                       const typename VT<V>::A *__restrict__ x,
+                                                       typename VT<V>::A *__restrict__ y) {
+    using A = typename VT<V>::A;
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t a = rp[i], b = rp[i + 1];
+    const bool comp = is_f32<A>() && (b - a) >= kKahanMinLen;
+    Sum<A> s;
+    for (int32_t k = a; k < b; ++k) s.add(VT<V>::cvt(val[k]) * x[ci[k]], comp);
+    y[i] = s.s;
+}
+
+// ============================================================ csr_vector
+// A sub-wavefront of W lanes per row (Bell and Garland's vector kernel with
+// the width adapted to the mean row length); lanes stride the row, then a
+// DPP/swizzle butterfly sums the lane partials.
+template <class V, int W>
+__global__ __launch_bounds__(kBlock) void k_csr_vector(int64_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       const V *__restrict__ val,
+                                                       const typename VT<V>::A *__restrict__ x,
+                                                       typename VT<V>::A *__restrict__ y) {
+    using A = typename VT<V>::A;
+    const int lane = threadIdx.x & (W - 1);
+    const int64_t nsub = (int64_t)gridDim.x * (kBlock / W);
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    for (int64_t i = blk * (kBlock / W) + threadIdx.x / W; i < n; i += nsub) {
+        const int32_t a = rp[i], b = rp[i + 1];
+        const bool comp = is_f32<A>() && (b - a) >= kKahanMinLen;
+        Sum<A> s;
+        int32_t k = a + lane;
+        // two independent loads in flight per lane
+        for (; k + W < b; k += 2 * W) {
+            const A v0 = VT<V>::cvt(ld_nt(val + k));
+            const A v1 = VT<V>::cvt(ld_nt(val + k + W));
+            const int32_t c0 = ld_nt(ci + k), c1 = ld_nt(ci + k + W);
+            const A p0 = v0 * x[c0];
+            const A p1 = v1 * x[c1];
+            s.add(p0, comp);
+            s.add(p1, comp);
+        }
+        if (k < b) s.add(VT<V>::cvt(ld_nt(val + k)) * x[ld_nt(ci + k)], comp);
+        const A t = group_sum<W>(s.s);
+        if (lane == 0) y[i] = t;
+    }
+}
+
+// ============================================================ row streaming
+// short_row and delta16.  A workgroup owns 256*R consecutive rows.  Their
+// nonzeros are streamed in LDS chunks of 2048: each thread loads an aligned
+// run of 8 with 16-byte vector loads, gathers x and stores the products;
+// then thread t sums its R rows from LDS in column order (the order of
+// Algorithm 1, so FP64 results equal the sequential sum bit for bit).
+// With D16 the column of nonzero k is base[row(k)] + off[k] (16-bit offsets
+// from the row's first column); the row of a run is found by binary search
+// over the block's row pointers in LDS.
+template <class V, bool D16>
+__global__ __launch_bounds__(kBlock) void k_rowstream(
+    int64_t n, int64_t nnz, int R, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ ci, const uint16_t *__restrict__ off,
+    const int32_t *__restrict__ rbase, const V *__restrict__ val,
+    const typename VT<V>::A *__restrict__ x, typename VT<V>::A *__restrict__ y) {
+    using A = typename VT<V>::A;
+    constexpr int RBMAX = kBlock * kRowStreamMaxR;
+    __shared__ int32_t s_rp[RBMAX + 1];
+    __shared__ int32_t s_base[D16 ? RBMAX : 1];
+    __shared__ A s_prod[kChunk];
+
+    const int RB = kBlock * R;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r0 = blk * RB;
+    const int nrows = (int)((n - r0) < RB ? (n - r0) : RB);
+    for (int r = threadIdx.x; r <= nrows; r += kBlock) s_rp[r] = rp[r0 + r];
+    if (D16)
+        for (int r = threadIdx.x; r < nrows; r += kBlock) s_base[r] = rbase[r0 + r];
+    __syncthreads();
+    const int32_t s = s_rp[0], e = s_rp[nrows];
+
+    int myr = threadIdx.x * R;
+    const int myr_end = (myr + R) < nrows ? (myr + R) : nrows;
+    int32_t k = myr < nrows ? s_rp[myr] : e;
+    bool comp = is_f32<A>() && myr < nrows && (s_rp[myr + 1] - s_rp[myr]) >= kKahanMinLen;
+    Sum<A> acc;
+
+    const int32_t a0 = s & ~(kRunLen - 1);
+    for (int32_t cs = a0; cs < e; cs += kChunk) {
+        // ---- phase 1: products of this thread's run
+        const int32_t e0 = cs + threadIdx.x * kRunLen;
+        if (e0 < e && e0 + kRunLen > s) {
+            V v[kRunLen];
+            int32_t col[kRunLen];
+            if (e0 + kRunLen <= nnz) {
+                load8_nt(val + e0, v);
+                if (D16) {
+                    uint16_t o[kRunLen];
+                    load8_nt(off + e0, o);
+#pragma unroll
+                    for (int j = 0; j < kRunLen; ++j) col[j] = o[j];
+                } else {
+                    load8_nt(ci + e0, col);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kRunLen; ++j) {
+                    const bool in = e0 + j < nnz;
+                    v[j] = in ? val[e0 + j] : V(0);
+                    col[j] = in ? (D16 ? (int32_t)off[e0 + j] : ci[e0 + j]) : 0;
+                }
+            }
+            int r = 0;
+            if (D16) {
+                // largest r with s_rp[r] <= max(e0, s): the row holding it
+                const int32_t t = e0 > s ? e0 : s;
+                int lo = 0, hi = nrows - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_rp[mid] <= t) lo = mid; else hi = mid - 1;
+                }
+                r = lo;
+            }
+            A p[kRunLen];
+#pragma unroll
+            for (int j = 0; j < kRunLen; ++j) {
+                const int32_t ee = e0 + j;
+                const bool valid = ee >= s && ee < e;
+                if (D16 && valid) {
+                    while (s_rp[r + 1] <= ee) ++r;
+                    col[j] += s_base[r];
+                }
+                p[j] = valid ? VT<V>::cvt(v[j]) * x[col[j]] : A(0);
+            }
+#pragma unroll
+            for (int j = 0; j < kRunLen; ++j) s_prod[threadIdx.x * kRunLen + j] = p[j];
+        }
+        __syncthreads();
+        // ---- phase 2: each thread sums its rows' products in this chunk
+        const int32_t ce = (cs + kChunk) < e ? (cs + kChunk) : e;
+        while (myr < myr_end) {
+            const int32_t rend = s_rp[myr + 1];
+            const int32_t lim = rend < ce ? rend : ce;
+            for (; k < lim; ++k) acc.add(s_prod[k - cs], comp);
+            if (k != rend) break;
+            y[r0 + myr] = acc.s;
+            acc.reset();
+            ++myr;
+            comp = is_f32<A>() && myr < myr_end && (s_rp[myr + 1] - s_rp[myr]) >= kKahanMinLen;
+        }
+        __syncthreads();
+    }
+    for (; myr < myr_end; ++myr) {  // rows with no nonzeros left (all empty)
+        y[r0 + myr] = acc.s;
+        acc.reset();
+    }
+}
+
+// ============================================================ merge path
+// Merrill and Garland's merge-based CSR SpMV.  Tile t covers the merge
+// diagonals [t*T, (t+1)*T) of row ends rowptr[1..N] and nonzero indices;
+// its start coordinates come precomputed.  Products and row ends are staged
+// in LDS; each thread finds its own start by a merge-path search in LDS and
+// consumes 8 items: a nonzero adds its product, a row end emits the row.
+// Rows finished inside one thread are summed in column order.  The first
+// row end of a thread adds the partial sums carried by the preceding
+// threads of the tile (in thread order); the partial row left at the tile's
+// end is stored as the tile's carry and added by k_merge_fixup in tile order.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_merge_path(
+    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
+    typename VT<V>::A *__restrict__ y, const int32_t *__restrict__ srow,
+    const int32_t *__restrict__ snnz, int32_t *__restrict__ carry_row,
+    typename VT<V>::A *__restrict__ carry_val) {
+    using A = typename VT<V>::A;
+    __shared__ int32_t s_end[kMergeTile + 1];
+    __shared__ A s_prod[kMergeTile];
+    __shared__ int32_t s_crow[kBlock];
+    __shared__ A s_cval[kBlock];
+    constexpr bool F32 = is_f32<A>();
+
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int32_t i0 = srow[tile], j0 = snnz[tile];
+    const int32_t i1 = srow[tile + 1], j1 = snnz[tile + 1];
+    const int nr = i1 - i0, nz = j1 - j0;
+
+    for (int r = threadIdx.x; r <= nr; r += kBlock) {
+        const int64_t row = (int64_t)i0 + r;
+        s_end[r] = row < n ? rp[row + 1] : INT32_MAX;
+    }
+    for (int q = threadIdx.x; q < nz; q += kBlock) {
+        const int32_t kk = j0 + q;
+        s_prod[q] = VT<V>::cvt(ld_nt(val + kk)) * x[ld_nt(ci + kk)];
+    }
+    __syncthreads();
+
+    // this thread's start on the merge path inside the tile
+    const int total = nr + nz;
+    const int d = threadIdx.x * kMergeIpt < total ? threadIdx.x * kMergeIpt : total;
+    int lo = d - nz > 0 ? d - nz : 0, hi = d < nr ? d : nr;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_end[mid] <= j0 + d - mid - 1) lo = mid + 1; else hi = mid;
+    }
+    int xi = lo, yj = d - lo;
+
+    Sum<A> run;
+    int head_row = -1;
+    A head_val = A(0);
+    const int dend = (d + kMergeIpt) < total ? (d + kMergeIpt) : total;
+    for (int it = d; it < dend; ++it) {
+        if (yj < nz && j0 + yj < s_end[xi]) {
+            run.add(s_prod[yj], F32);
+            ++yj;
+        } else {
+            if (head_row < 0) {
+                head_row = xi;
+                head_val = run.s;
+            } else {
+                y[i0 + xi] = run.s;
+            }
+            run.reset();
+            ++xi;
+        }
+    }
+    s_crow[threadIdx.x] = xi;  // row (local) still open at this thread's end
+    s_cval[threadIdx.x] = run.s;
+    __syncthreads();
+
+    if (head_row >= 0) {
+        int t0 = threadIdx.x;
+        while (t0 > 0 && s_crow[t0 - 1] == head_row) --t0;
+        Sum<A> c;
+        for (int t = t0; t < (int)threadIdx.x; ++t) c.add(s_cval[t], F32);
+        c.add(head_val, F32);
+        y[i0 + head_row] = c.s;
+    }
+    if (threadIdx.x == kBlock - 1) {
+        // partial sums of row i1 accumulated in this tile (continues later)
+        int t0 = kBlock - 1;
+        while (t0 > 0 && s_crow[t0 - 1] == nr) --t0;
+        Sum<A> c;
+        if (s_crow[kBlock - 1] == nr)
+            for (int t = t0; t < kBlock; ++t) c.add(s_cval[t], F32);
+        carry_row[tile] = i1;
+        carry_val[tile] = c.s;
+    }
+}
+
+// Adds the carries of consecutive tiles that end inside the same row, in
+// tile order, to that row (the tile finishing the row already wrote its
+// own part).  One thread per tile; only the first tile of a run works.
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_merge_fixup(int64_t n, int64_t tiles,
+                                                        const int32_t *__restrict__ carry_row,
+                                                        const A *__restrict__ carry_val,
+                                                        A *__restrict__ y) {
+    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (t >= tiles) return;
+    const int32_t row = carry_row[t];
+    if (row >= n) return;
+    if (t > 0 && carry_row[t - 1] == row) return;
+    Sum<A> c;
+    int64_t u = t;
+    for (; u < tiles && carry_row[u] == row; ++u) c.add(carry_val[u], is_f32<A>());
+    // the row ends in tile u (the tile that emitted it)
+    y[row] = y[row] + c.s;
+}
+
+// ============================================================ x-block LDS
+// Row panels of H rows; each panel's x window [cmin, cmax] is staged into
+// LDS in chunks of CB columns.  For each chunk, a sub-wavefront of W lanes
+// per row consumes the row's nonzeros whose columns fall in the chunk
+// (columns are sorted, so they are the next ones after the row's cursor),
+// gathering x from LDS; the chunk's partial is butterfly-summed and added
+// to the row's LDS accumulator by one lane, chunks in increasing order.
+template <class V, int W>
+__global__ __launch_bounds__(kBlock) void k_xblock(
+    int64_t n, int H, int CB, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
+    typename VT<V>::A *__restrict__ y, const int32_t *__restrict__ cmin_a,
+    const int32_t *__restrict__ cmax_a) {
+    using A = typename VT<V>::A;
+    extern __shared__ unsigned char smem[];
+    A *xs = reinterpret_cast<A *>(smem);                 // CB
+    A *yacc = xs + CB;                                   // H
+    int32_t *cur = reinterpret_cast<int32_t *>(yacc + H);  // H
+    int32_t *rend = cur + H;                             // H
+    constexpr int NS = kBlock / W;
+
+    const int64_t p = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r0 = p * H;
+    const int nrows = (int)((n - r0) < H ? (n - r0) : H);
+    const int32_t cmin = cmin_a[p], cmax = cmax_a[p];
+    for (int r = threadIdx.x; r < nrows; r += kBlock) {
+        cur[r] = rp[r0 + r];
+        rend[r] = rp[r0 + r + 1];
+        yacc[r] = A(0);
+    }
+    const int sub = threadIdx.x / W, lane = threadIdx.x & (W - 1);
+    const int wsub = (threadIdx.x & 63) / W;  // sub-wave index inside the wavefront
+    for (int64_t xc = cmin; xc <= cmax; xc += CB) {
+        const int64_t xe = (xc + CB) < ((int64_t)cmax + 1) ? (xc + CB) : ((int64_t)cmax + 1);
+        __syncthreads();
+        for (int64_t c = xc + threadIdx.x; c < xe; c += kBlock) xs[c - xc] = x[c];
+        __syncthreads();
+        for (int r = sub; r < nrows; r += NS) {
+            int32_t k = cur[r];
+            const int32_t ke = rend[r];
+            if (k >= ke) continue;
+            Sum<A> part;
+            while (true) {
+                const int32_t kk = k + lane;
+                bool in = kk < ke;
+                int32_t c = in ? ci[kk] : 0;
+                in = in && c < xe && c >= xc;
+                if (in) part.add(VT<V>::cvt(val[kk]) * xs[c - xc]);
+                const uint64_t bal = __ballot(in);
+                const uint64_t mine = W == 64 ? bal : ((bal >> (wsub * W)) & ((1ull << W) - 1));
+                const int cnt = __popcll(mine);
+                k += cnt;
+                if (cnt < W) break;
+            }
+            const A t = group_sum<W>(part.s);
+            if (lane == 0) {
+                yacc[r] = yacc[r] + t;
+                cur[r] = k;
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nrows; r += kBlock) y[r0 + r] = yacc[r];
+}
+
+// ============================================================ launchers
+namespace {
+
+template <class F>
+hipError_t by_dtype(int dtype, F &&f) {
+    switch (dtype) {
+    case SPMV_F64: return f((const double *)nullptr);
+    case SPMV_F32: return f((const float *)nullptr);
+    default: return f((const uint16_t *)nullptr);
+    }
+}
+
+inline unsigned grid_for(int64_t items, int per_block, int64_t cap) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_csr_scalar(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    return by_dtype(P.dtype, [&](auto tag) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
+        using A = typename VT<V>::A;
+        const unsigned g = grid_for(P.n, kBlock, INT32_MAX);
+        hipLaunchKernelGGL(k_csr_scalar<V>, dim3(g), dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
+                           (const V *)P.val, (const A *)x, (A *)y);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_csr_vector(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    return by_dtype(P.dtype, [&](auto tag) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
+        using A = typename VT<V>::A;
+        const int W = P.vec_width;
+        const unsigned g = grid_for(P.n, kBlock / W, (int64_t)P.num_cus * 32);
+#define SPMV_VEC(WW)                                                                       \
+    case WW:                                                                               \
+        hipLaunchKernelGGL((k_csr_vector<V, WW>), dim3(g), dim3(kBlock), 0, s, P.n, P.rowptr, \
+                           P.colind, (const V *)P.val, (const A *)x, (A *)y);             \
+        break;
+        switch (W) {
+            SPMV_VEC(2) SPMV_VEC(4) SPMV_VEC(8) SPMV_VEC(16) SPMV_VEC(32) SPMV_VEC(64)
+        default: return hipErrorInvalidValue;
+        }
+#undef SPMV_VEC
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    return by_dtype(P.dtype, [&](auto tag) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
+        using A = typename VT<V>::A;
+        const int R = P.rs_rows;
+        const unsigned g = grid_for(P.n, kBlock * R, INT32_MAX);
+        if (d16)
+            hipLaunchKernelGGL((k_rowstream<V, true>), dim3(g), dim3(kBlock), 0, s, P.n, P.nnz, R,
+                               P.rowptr, P.colind, P.d16_off.as<uint16_t>(),
+                               P.d16_base.as<int32_t>(), (const V *)P.val, (const A *)x, (A *)y);
+        else
+            hipLaunchKernelGGL((k_rowstream<V, false>), dim3(g), dim3(kBlock), 0, s, P.n, P.nnz, R,
+                               P.rowptr, P.colind, (const uint16_t *)nullptr,
+                               (const int32_t *)nullptr, (const V *)P.val, (const A *)x, (A *)y);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_merge_path(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    return by_dtype(P.dtype, [&](auto tag) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
+        using A = typename VT<V>::A;
+        if (P.mp_tiles <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k_merge_path<V>, dim3((unsigned)P.mp_tiles), dim3(kBlock), 0, s, P.n,
+                           P.rowptr, P.colind, (const V *)P.val, (const A *)x, (A *)y,
+                           P.mp_split_row.as<int32_t>(), P.mp_split_nnz.as<int32_t>(),
+                           P.mp_carry_row.as<int32_t>(), P.mp_carry_val.as<A>());
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const unsigned g = grid_for(P.mp_tiles, kBlock, INT32_MAX);
+        hipLaunchKernelGGL(k_merge_fixup<A>, dim3(g), dim3(kBlock), 0, s, P.n, P.mp_tiles,
+                           P.mp_carry_row.as<int32_t>(), P.mp_carry_val.as<A>(), (A *)y);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    return by_dtype(P.dtype, [&](auto tag) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
+        using A = typename VT<V>::A;
+        const int H = P.xb_rows;
+        const int CB = kXbChunkBytes / (int)sizeof(A);
+        const size_t shm = (size_t)CB * sizeof(A) + (size_t)H * (sizeof(A) + 8);
+        const unsigned g = (unsigned)P.xb_panels;
+#define SPMV_XB(WW)                                                                          \
+    case WW:                                                                                 \
+        hipLaunchKernelGGL((k_xblock<V, WW>), dim3(g), dim3(kBlock), shm, s, P.n, H, CB,     \
+                           P.rowptr, P.colind, (const V *)P.val, (const A *)x, (A *)y,       \
+                           P.xb_cmin.as<int32_t>(), P.xb_cmax.as<int32_t>());               \
+        break;
+        switch (P.xb_width) {
+            SPMV_XB(2) SPMV_XB(4) SPMV_XB(8) SPMV_XB(16) SPMV_XB(32) SPMV_XB(64)
+        default: return hipErrorInvalidValue;
+        }
+#undef SPMV_XB
+        return hipGetLastError();
+    });
+}
+
+}  // namespace spmvsel

@@ -1,0 +1,92 @@
+"""Derived formats and value rounding are byte-identical to the oracle (GPU)."""
+import struct
+
+import numpy as np
+import pytest
+
+import synth
+import paper_1511_02494_amd as S
+from oracle.encode import (delta16_ref, merge_search_ref, merge_walk_ref, panel_windows_ref,
+                           partition_ref, to_bf16_bits_ref, to_f32_ref)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from gpu_util import dev, make_plan  # noqa: E402
+
+MATS = [
+    ("laplace64", lambda: synth.laplace2d(64), 4096),
+    ("powerlaw", lambda: synth.powerlaw(30000, 109, 7000, seed=2), 30000),
+    ("shortrows", lambda: synth.short_rows(20000, seed=3), 20000),
+    ("banded", lambda: synth.banded(6000, 300, 200, seed=4), 6000),
+    ("stencil27", lambda: synth.stencil3d_27(16), 4096),
+]
+
+
+@pytest.mark.parametrize("name,build,m", MATS)
+def test_formats_match_oracle(name, build, m):
+    rp, ci, v = build()
+    n, nnz = len(rp) - 1, len(ci)
+    plan = make_plan(rp, ci, v, m)
+    h = plan.handle
+    ok, base, off = delta16_ref(rp, ci)
+    assert S.spmv_plan_query(h, 9) == int(ok)
+    if ok:
+        assert np.array_equal(S.spmv_plan_copy_format(h, 0, n), base)
+        assert np.array_equal(S.spmv_plan_copy_format(h, 1, nnz), off)
+    T = S.spmv_plan_query(h, 3)
+    tiles = S.spmv_plan_query(h, 4)
+    si, sj = merge_search_ref(rp, T)
+    assert len(si) == tiles + 1
+    assert np.array_equal(S.spmv_plan_copy_format(h, 2, tiles + 1), si)
+    assert np.array_equal(S.spmv_plan_copy_format(h, 3, tiles + 1), sj)
+    if n + nnz < 200000:
+        wi, wj = merge_walk_ref(rp, T)
+        assert np.array_equal(wi, si) and np.array_equal(wj, sj)
+    H = S.spmv_plan_query(h, 5)
+    P = S.spmv_plan_query(h, 6)
+    lo, hi = panel_windows_ref(rp, ci, H)
+    assert np.array_equal(S.spmv_plan_copy_format(h, 4, P), lo)
+    assert np.array_equal(S.spmv_plan_copy_format(h, 5, P), hi)
+    feas = int((hi.astype(np.int64) - lo + 1).sum() <= nnz)
+    assert S.spmv_plan_query(h, 10) == feas
+    parts = S.spmv_plan_query(h, 8)
+    assert np.array_equal(S.spmv_plan_copy_format(h, 6, parts + 1), partition_ref(rp, parts))
+    plan.close()
+
+
+def test_delta16_infeasible_on_wide_rows():
+    rp, ci, v = synth.uniform_random(3000, 2_000_000, 8, seed=2)
+    plan = make_plan(rp, ci, v, 2_000_000)
+    assert S.spmv_plan_query(plan.handle, 9) == 0
+    assert not (plan.mask() >> S.V_DELTA16) & 1
+    with pytest.raises(S.SpmvError) as e:
+        plan.set_variant(S.V_DELTA16)
+    assert e.value.status == S.SPMV_ERR_INFEASIBLE
+    plan.close()
+
+
+def rounding_cases():
+    rng = np.random.default_rng(0)
+    vals = [rng.uniform(-1, 1, 20000),
+            rng.uniform(-1, 1, 4000) * 2.0 ** rng.integers(-140, 130, 4000)]
+    ties = []
+    for b in rng.integers(0x0100, 0x7F00, 2000):
+        lo = struct.unpack("<f", struct.pack("<I", int(b) << 16))[0]
+        hi = struct.unpack("<f", struct.pack("<I", (int(b) + 1) << 16))[0]
+        mid = (lo + hi) / 2
+        ties += [mid, np.nextafter(mid, 1e300), np.nextafter(mid, -1e300)]
+    ties = np.array(ties)
+    specials = np.array([0.0, -0.0, np.inf, -np.inf, 1e300, -1e300, 3.4e38, 5e-324, 1e-45])
+    return np.concatenate(vals + [ties, -ties, specials])
+
+
+def test_quantize_bit_exact():
+    v = rounding_cases()
+    src = dev(v)
+    out32 = torch.empty(len(v), dtype=torch.float32, device="cuda:0")
+    out16 = torch.empty(len(v), dtype=torch.int16, device="cuda:0")
+    S.spmv_quantize(src, out32, len(v), S.SPMV_F32)
+    S.spmv_quantize(src, out16, len(v), S.SPMV_BF16)
+    torch.cuda.synchronize()
+    assert np.array_equal(out32.cpu().numpy().view(np.uint32), to_f32_ref(v).view(np.uint32))
+    assert np.array_equal(out16.cpu().numpy().view(np.uint16), to_bf16_bits_ref(v))

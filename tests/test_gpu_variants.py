@@ -1,0 +1,134 @@
+"""Parity of the six SpMV variants with the oracle (GPU, through the C ABI)."""
+import numpy as np
+import pytest
+
+import synth
+import paper_1511_02494_amd as S
+from oracle.spmv import spmv_exact, spmv_seq, within_tolerance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from gpu_util import make_plan, run  # noqa: E402
+
+TOL = {S.SPMV_F64: 1e-12, S.SPMV_F32: 1e-5, S.SPMV_BF16: 1e-2}
+SEQ_ORDER = {S.V_CSR_SCALAR, S.V_SHORT_ROW, S.V_DELTA16}  # sum in column order
+
+
+def one_long_row(n_cols=100_000, seed=0, values="random"):
+    rp = np.array([0, n_cols], np.int32)
+    ci = np.arange(n_cols, dtype=np.int32)
+    v = synth.random_values(n_cols, seed) if values == "random" else synth.int_values(n_cols, seed)
+    return rp, ci, v
+
+
+def empty_rows_mix(seed=1):
+    rng = np.random.default_rng(seed)
+    return synth.tiny_random_csr(rng, 300, 200, 0.02, int_valued=False)
+
+
+def ragged(seed=2, values="random"):
+    # row lengths 0..3000 cycling through chunk and tile boundaries
+    L = np.array([0, 1, 7, 8, 9, 255, 256, 257, 2047, 2048, 2049, 3000, 0, 0, 5] * 20)
+    rp = np.zeros(len(L) + 1, np.int64)
+    rp[1:] = np.cumsum(L)
+    ci = synth.strata_columns(rp, np.zeros(len(L), np.int64), np.full(len(L), 4000, np.int64), seed)
+    nnz = int(rp[-1])
+    v = synth.random_values(nnz, seed) if values == "random" else synth.int_values(nnz, seed)
+    return rp.astype(np.int32), ci, v
+
+
+CASES = {
+    "laplace64": (lambda v: synth.laplace2d(64, values="const" if v == "random" else "int"), 4096),
+    "stencil27_12": (lambda v: synth.stencil3d_27(12, seed=3, values=v), 1728),
+    "random_3000x8": (lambda v: synth.uniform_random(3000, 5000, 8, seed=4, values=v), 5000),
+    "powerlaw_20000": (lambda v: synth.powerlaw(20000, 109, 6000, seed=5, values=v), 20000),
+    "shortrows_5000": (lambda v: synth.short_rows(5000, seed=6, values=v), 5000),
+    "banded_4000": (lambda v: synth.banded(4000, 160, 40, seed=7, values=v), 4000),
+    "ragged": (lambda v: ragged(values=v), 4000),
+    "one_long_row": (lambda v: one_long_row(values=v), 100_000),
+    "empty_rows": (lambda v: empty_rows_mix(), 200),
+}
+
+
+def expected_mask(plan):
+    return S.spmv_variant_mask(plan.handle)
+
+
+@pytest.mark.parametrize("dtype", [S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16])
+@pytest.mark.parametrize("case", list(CASES))
+def test_variants_within_tolerance(case, dtype):
+    build, m = CASES[case]
+    rp, ci, v = build("random")
+    x = synth.vector(m, 11)
+    y_ref, scale = spmv_exact(rp, ci, v, x)
+    y_seq = spmv_seq(rp, ci, v, x)
+    plan = make_plan(rp, ci, v, m, dtype)
+    mask = expected_mask(plan)
+    print(f"case={case} dtype={dtype} n={len(rp) - 1} nnz={len(ci)} mask={mask:06b}", flush=True)
+    for var in range(6):
+        if not (mask >> var) & 1:
+            with pytest.raises(S.SpmvError) as e:
+                S.spmv_set_variant(plan.handle, var)
+            assert e.value.status == S.SPMV_ERR_INFEASIBLE
+            continue
+        y = run(plan, var, x, dtype)
+        ok, worst = within_tolerance(y, y_ref, scale, TOL[dtype])
+        assert ok, (S.VARIANTS[var], worst)
+        if dtype == S.SPMV_F64 and var in SEQ_ORDER:
+            assert np.array_equal(y, y_seq), S.VARIANTS[var]
+        y2 = run(plan, var, x, dtype)
+        assert np.array_equal(y, y2), f"{S.VARIANTS[var]} not deterministic"
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16])
+@pytest.mark.parametrize("case", ["laplace64", "stencil27_12", "random_3000x8", "powerlaw_20000",
+                                  "shortrows_5000", "ragged", "one_long_row"])
+def test_integer_valued_bit_exact(case, dtype):
+    """|a|, |x| <= 8 and partial sums below 2^24: every order is exact."""
+    build, m = CASES[case]
+    rp, ci, v = build("int")
+    x = synth.int_vector(m, 12)
+    y_seq = spmv_seq(rp, ci, v, x)
+    assert np.max(np.abs(y_seq), initial=0) < 2 ** 24
+    plan = make_plan(rp, ci, v, m, dtype)
+    mask = expected_mask(plan)
+    for var in range(6):
+        if (mask >> var) & 1:
+            y = run(plan, var, x, dtype)
+            assert np.array_equal(y, y_seq), (case, S.VARIANTS[var])
+    plan.close()
+
+
+@pytest.mark.parametrize("n,m", [(0, 0), (0, 5), (7, 0), (10, 10)])
+def test_degenerate_empty(n, m):
+    rp = np.zeros(n + 1, np.int32)
+    plan = make_plan(rp, np.zeros(0, np.int32), np.zeros(0), m)
+    assert plan.features()[0] == ([0.0] * 12 if n == 0 else plan.features()[0])
+    for var in range(6):
+        if (S.spmv_variant_mask(plan.handle) >> var) & 1:
+            y = run(plan, var, np.zeros(m), S.SPMV_F64)
+            assert np.all(y == 0) and len(y) == n
+    plan.close()
+
+
+def test_default_variant_is_csr_scalar():
+    rp, ci, v = synth.laplace2d(16)
+    plan = make_plan(rp, ci, v, 256)
+    assert plan.variant == S.V_CSR_SCALAR
+    plan.close()
+
+
+def test_copy_inputs_flag():
+    rp, ci, v = synth.banded(1000, 128, 20, seed=1)
+    x = synth.vector(1000, 2)
+    from gpu_util import upload_csr
+    r, c, vt = upload_csr(rp, ci, v)
+    plan = S.Plan(r, c, vt, 1000, flags=S.SPMV_COPY_INPUTS)
+    c.zero_()
+    vt.zero_()
+    y = run(plan, S.V_CSR_VECTOR, x)
+    y_ref, s = spmv_exact(rp, ci, v, x)
+    assert within_tolerance(y, y_ref, s, 1e-12)[0]
+    plan.close()
