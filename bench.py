@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Selected-SpMV benchmark on one MI355X.
+
+Workload: the four FP64 bottleneck-class matrices (27-point stencil on 100^3,
+uniform random 2M x 8/row, Pareto(1.5) row lengths 1M with a 200k row, short
+rows 8M), x ~ U[-1, 1), generated on the device from their seeds.
+
+One step = for every matrix: ``spmv_plan_create`` (validation),
+``spmv_select`` (device features + MLP inference, falling back to the
+profiling micro-benchmarks when the model is absent or unsure), format
+preparation of the chosen variant, then ``--iters`` SpMVs with it (the solver
+loop the selection is amortised over), and ``spmv_plan_destroy``.
+``value`` = algorithmic bytes of all those SpMVs / wall time of the step.
+
+Also reported (outside the timed steps): every variant's warm and cold
+(Infinity-Cache flushed) time per matrix, the best variant, the selection
+cost in SpMV-equivalents, attainable HBM bandwidth, the roofline of the
+dominant kernel (HIP events on the plan stream, inside the timed steps) and
+the oracle's single-thread CPU rate on the same matrices.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--iters", type=int, default=100, help="SpMVs per matrix per step")
+    ap.add_argument("--selector", default="mlp", choices=["mlp", "profiling", "exhaustive"])
+    ap.add_argument("--scale", type=int, default=1, help="divide matrix sizes (testing only)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant timing table")
+    ap.add_argument("--model", default=None)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1511_02494_amd as S
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    model = args.model or S.DEFAULT_MODEL
+    model_loaded = False
+    if os.path.exists(model):
+        S.spmv_model_load(model)
+        model_loaded = True
+    sel = {"mlp": S.SEL_MLP, "profiling": S.SEL_PROFILING, "exhaustive": S.SEL_EXHAUSTIVE}[args.selector]
+
+    # ---- inputs, generated on the device from their seeds
+    specs = synth.class_matrices(scale=args.scale)
+    mats = []
+    for sp in specs:
+        fam = S.FAMILY[sp.family]
+        p = sp.params
+        if sp.family == "stencil3d_27":
+            prm = [p["n"], 0]
+            n = p["n"] ** 3
+        elif sp.family == "uniform_random":
+            prm = [p["n_rows"], p["n_cols"], p["per_row"]]
+            n = p["n_rows"]
+        elif sp.family == "powerlaw":
+            prm = [p["n"], p["p16"], p["cap"], 1]
+            n = p["n"]
+        else:
+            prm = [p["n"]]
+            n = p["n"]
+        m = n
+        rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        nnz = S.spmv_generate(fam, prm, sp.seed, rp)
+        ci = torch.empty(nnz + 8, dtype=torch.int32, device=dev)
+        val = torch.empty(nnz + 8, dtype=torch.float64, device=dev)
+        S.spmv_generate(fam, prm, sp.seed, rp, ci, val)
+        x = torch.empty(m, dtype=torch.float64, device=dev)
+        S.spmv_generate_vector(m, sp.x_seed, x)
+        y = torch.empty(n, dtype=torch.float64, device=dev)
+        mats.append(dict(spec=sp, name=sp.name, n=n, m=m, nnz=nnz, rp=rp, ci=ci, val=val, x=x, y=y))
+        log(f"generated {sp.name}: n={n} nnz={nnz}")
+    torch.cuda.synchronize()
+
+    read_gbs, copy_gbs = S.spmv_hbm_probe(4 << 30)
+    log(f"HBM probe: read {read_gbs:.0f} GB/s, copy {copy_gbs:.0f} GB/s")
+
+    # ---- per-variant table (outside the timed steps)
+    for M in mats:
+        plan = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
+        mask = plan.mask()
+        M["mask"] = mask
+        M["variants"] = {}
+        if not args.no_sweep:
+            for v in range(6):
+                if not (mask >> v) & 1:
+                    continue
+                warm, _ = plan.time(v, reps=20, cold=False)
+                cold, _ = plan.time(v, reps=5, cold=True)
+                b = plan.bytes(v)
+                M["variants"][S.VARIANTS[v]] = dict(
+                    warm_us=warm * 1e6, cold_us=cold * 1e6, bytes=b,
+                    warm_gbs=b / warm * 1e-9, cold_gbs=b / cold * 1e-9)
+                log(f"  {M['name']:>22s} {S.VARIANTS[v]:>10s} warm {warm * 1e6:8.1f} us "
+                    f"({b / warm * 1e-9:6.0f} GB/s)  cold {cold * 1e6:8.1f} us "
+                    f"({b / cold * 1e-9:6.0f} GB/s)")
+        plan.close()
+
+    # ---- timed steps
+    def one_step(record):
+        out = []
+        for M in mats:
+            t0 = time.perf_counter()
+            plan = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
+            info = plan.select(sel)
+            t1 = time.perf_counter()
+            evs = []
+            for _ in range(args.iters):
+                if record:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    plan.execute(M["x"], M["y"], stream)
+                    e1.record(stream)
+                    evs.append((e0, e1))
+                else:
+                    plan.execute(M["x"], M["y"], stream)
+            plan.close()  # synchronises the stream
+            t2 = time.perf_counter()
+            out.append(dict(info=info, t_select=t1 - t0, t_loop=t2 - t1, ev=evs))
+        return out
+
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    steps = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        steps.append(one_step(True))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+
+    # ---- aggregate
+    per = []
+    total_bytes = 0
+    for i, M in enumerate(mats):
+        recs = [s[i] for s in steps]
+        v = recs[-1]["info"]["variant"]
+        bytes_v = None
+        kern = []
+        for r in recs:
+            kern += [a.elapsed_time(b) * 1e-3 for a, b in r["ev"]]
+        plan = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
+        bytes_v = plan.bytes(v)
+        total_bytes += sum(plan.bytes(r["info"]["variant"]) for r in recs) * args.iters
+        picks = sorted({S.VARIANTS[r["info"]["variant"]] for r in recs})
+        plan.close()
+        t_spmv = float(np.mean(kern))   # average launch duration (HIP events)
+        sel_cost = float(np.median([r["info"]["t_total_s"] for r in recs]))
+        var_tab = M["variants"]
+        best = min(var_tab, key=lambda k: var_tab[k]["warm_us"]) if var_tab else None
+        rec = dict(
+            matrix=M["name"], n=M["n"], nnz=M["nnz"], selected=S.VARIANTS[v], picks=picks,
+            selector_used=["profiling", "mlp", "exhaustive"][recs[-1]["info"]["selector"]],
+            fell_back=bool(recs[-1]["info"]["fell_back"]),
+            klass=(S.CLASSES[recs[-1]["info"]["klass"]] if recs[-1]["info"]["klass"] >= 0 else None),
+            bytes_alg=bytes_v, spmv_us=t_spmv * 1e6, spmv_gbs=bytes_v / t_spmv * 1e-9,
+            spmv_gflops=2 * M["nnz"] / t_spmv * 1e-9,
+            pct_hbm_peak_warm=100 * bytes_v / t_spmv * 1e-9 / HBM_PEAK_GBS,
+            selection_s=sel_cost, selection_spmv_equivs=sel_cost / t_spmv,
+            selection_csr_scalar_equivs=(sel_cost / (var_tab["csr_scalar"]["warm_us"] * 1e-6)
+                                         if "csr_scalar" in var_tab else None),
+            prepare_s=float(np.median([r["info"]["t_prepare_s"] for r in recs])),
+            step_matrix_s=float(np.median([r["t_select"] + r["t_loop"] for r in recs])),
+        )
+        if best:
+            rec["best_variant"] = best
+            rec["best_warm_gbs"] = var_tab[best]["warm_gbs"]
+            rec["selected_vs_best"] = var_tab[best]["warm_us"] / var_tab[S.VARIANTS[v]]["warm_us"]
+            rec["selected_cold_gbs"] = var_tab[S.VARIANTS[v]]["cold_gbs"]
+            rec["pct_hbm_peak_cold"] = 100 * var_tab[S.VARIANTS[v]]["cold_gbs"] / HBM_PEAK_GBS
+        per.append(rec)
+        log(f"{M['name']:>22s}: {rec['selected']:>10s} {rec['spmv_us']:8.1f} us "
+            f"{rec['spmv_gbs']:6.0f} GB/s; selection {sel_cost * 1e3:.2f} ms "
+            f"= {rec['selection_spmv_equivs']:.1f} SpMVs")
+
+    value = total_bytes / t_total * 1e-9
+    dom = max(range(len(per)), key=lambda i: per[i]["spmv_us"])
+    d = per[dom]
+    roof = {"bound": "hbm", "achieved": d["spmv_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": d["spmv_gbs"] / HBM_PEAK_GBS, "traffic": None,
+            "kernel": f"{d['selected']} on {d['matrix']}",
+            "bytes_per_launch": d["bytes_alg"], "launch_us": d["spmv_us"]}
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import cref
+        cref.build()
+        tb, tt = 0, 0.0
+        sample = []
+        for sp in specs:
+            rp, ci, val = sp.build()
+            x = sp.x(len(rp) - 1)
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                cref.spmv(rp, ci, val, x)
+                ts.append(time.perf_counter() - t0)
+            n = len(rp) - 1
+            b = 4 * (n + 1) + 12 * len(ci) + 16 * n
+            tb += b
+            tt += float(np.median(ts))
+            sample.append(sp.name)
+        cpu = {"value": tb / tt * 1e-9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": "one single-threaded SpMV (median of 3) of the plain C oracle loop on "
+                         "each of the four matrices; bytes counted as for the GPU "
+                         "(features and selection not included)",
+               "cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+
+    out = {
+        "metric": "selected-SpMV GB/s & % HBM peak vs best variant; selection cost in SpMV-equivs",
+        "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_total / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "four FP64 bottleneck classes: 27-point stencil 100^3, uniform "
+                               "random 2M x 8, Pareto(1.5) 1M with a 200k row, short rows 8M; "
+                               f"per matrix per step: validate, select ({args.selector}), "
+                               f"prepare, {args.iters} SpMVs",
+                   "scale": args.scale, "iters_per_matrix": args.iters,
+                   "selector": args.selector, "model_loaded": model_loaded},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "hbm_probe": {"read_gbs": read_gbs, "copy_gbs": copy_gbs},
+        "per_matrix": per,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

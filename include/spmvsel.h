@@ -59,11 +59,11 @@ typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
  *              (vectorisation, class CMP; the architecture-centric default).
  *  MERGE_PATH  nonzero-balanced merge-path tiles (class IMB; replaces the
  *              OpenMP dynamic/auto schedules).
- *  DELTA16     16-bit column offsets from each row's first column, streamed
- *              through LDS (column-index compression, class MB).
+ *  DELTA16     16-bit column offsets from one reference column per block of
+ *              rows, streamed through LDS (column-index compression, class MB).
  *  XBLOCK_LDS  x staged in LDS per row panel and column window (class CML;
  *              replaces software prefetching of x).
- *  SHORT_ROW   rows streamed through LDS in unrolled 8-element runs with one
+ *  SHORT_ROW   rows streamed through LDS in chunks of 2048 nonzeros with one
  *              thread summing each row (short rows: inner-loop overhead). */
 typedef enum {
     V_CSR_SCALAR = 0, V_CSR_VECTOR = 1, V_MERGE_PATH = 2,
@@ -161,7 +161,8 @@ spmv_status_t spmv_execute(spmv_plan_t plan, const void *d_x, void *d_y,
 /* Control and inspection                                                   */
 
 /* Force a variant; builds its format (synchronous).  SPMV_ERR_INFEASIBLE if
- * the matrix cannot use it (DELTA16: a row spans more than 65535 columns;
+ * the matrix cannot use it (DELTA16: a block of rows (256 x R, else 256)
+ * spans more than 65536 columns;
  * XBLOCK_LDS: the x windows staged for all panels exceed NNZ elements). */
 spmv_status_t spmv_set_variant(spmv_plan_t plan, int32_t variant);
 spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
@@ -170,7 +171,8 @@ spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
 spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
 
 /* Algorithmic bytes of one SpMV with `variant`: 4(N+1) + ib NNZ + vb NNZ +
- * xb M + yb N, plus 4N row bases for DELTA16 (ib = 2 there, else 4). */
+ * xb M + yb N, plus 4 bytes per block reference column for DELTA16 (ib = 2
+ * there, else 4). */
 spmv_status_t spmv_bytes(spmv_plan_t plan, int32_t variant, int64_t *bytes);
 
 /* Median and minimum time of `reps` executions of `variant` (hipEvents on
@@ -184,12 +186,13 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
  * Keys: 0 variant, 1 csr_vector width, 2 short_row/delta16 rows per block,
  * 3 merge-path items per tile, 4 merge-path tiles, 5 x-block rows per panel,
  * 6 x-block panels, 7 x-block columns per LDS chunk, 8 profiling partitions,
- * 9 delta16 feasible, 10 x-block feasible. */
+ * 9 delta16 feasible, 10 x-block feasible, 11 delta16 rows per block. */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:
- * 0 delta16 base int32[N], 1 delta16 offsets uint16[NNZ], 2 merge-path split
- * rows int32[tiles+1], 3 merge-path split nonzeros int32[tiles+1], 4 x-block
+ * 0 delta16 block reference columns int32[ceil(N / rows per block)],
+ * 1 delta16 offsets uint16[NNZ], 2 merge-path split rows int32[tiles+1],
+ * 3 merge-path split nonzeros int32[tiles+1], 4 x-block
  * window starts int32[panels], 5 x-block window ends int32[panels],
  * 6 profiling partition bounds int32[parts+1].  `bytes` must equal the
  * array size. */

@@ -2,10 +2,10 @@
 
 * ``delta16_ref``   column-index compression (Section 3.3, Table 2, class MB).
   The paper stores 8- or 16-bit deltas between consecutive column indices of
-  a row, never mixing widths.  Reading used here: 16-bit offsets from the
-  row's first column (``base_i = c_0``, ``off_k = c_k - base_i``), which a
-  GPU decodes in O(1) per element without an in-row scan.  Feasible iff no
-  row spans more than 65535 columns.
+  a row, never mixing widths.  Reading used here: 16-bit deltas from one
+  reference column per block of consecutive rows (the block's smallest
+  column), which a GPU decodes with a single add and no in-row scan or row
+  lookup.  Feasible iff no block spans more than 65536 columns.
 * ``merge_splits_ref``  start coordinates of the nonzero-balanced merge-path
   tiles (Merrill and Garland, SC'16): the merge of the row-end list
   ``rowptr[1..N]`` with the nonzero indices ``0..NNZ-1``, where nonzero j is
@@ -23,18 +23,28 @@ from fractions import Fraction
 import numpy as np
 
 
-def delta16_ref(rowptr, colind):
-    """(feasible, base int32[N], off uint16[NNZ])."""
+def delta16_ref(rowptr, colind, block_rows: int = 256):
+    """(feasible, base int32[B], off uint16[NNZ]) for blocks of ``block_rows`` rows.
+
+    Block b holds rows [b*block_rows, (b+1)*block_rows); its reference column
+    base_b is the smallest column of the block's nonzeros (0 if it has none)
+    and every nonzero of the block stores off_k = c_k - base_b.  Feasible iff
+    every offset fits 16 bits (each block spans at most 65536 columns).
+    """
     rowptr = np.asarray(rowptr, dtype=np.int64)
     colind = np.asarray(colind, dtype=np.int64)
     n = len(rowptr) - 1
-    L = np.diff(rowptr)
-    base = np.zeros(n, dtype=np.int64)
-    ne = L > 0
-    base[ne] = colind[rowptr[:-1][ne]]
-    rows = np.repeat(np.arange(n, dtype=np.int64), L)
-    off = colind - base[rows]
-    feasible = bool(len(off) == 0 or off.max() <= 65535)
+    nb = (n + block_rows - 1) // block_rows
+    base = np.zeros(nb, dtype=np.int64)
+    off = np.zeros(len(colind), dtype=np.int64)
+    feasible = True
+    for b in range(nb):
+        a, e = rowptr[b * block_rows], rowptr[min(n, (b + 1) * block_rows)]
+        if a < e:
+            base[b] = colind[a:e].min()
+            off[a:e] = colind[a:e] - base[b]
+            if off[a:e].max() > 65535:
+                feasible = False
     return feasible, base.astype(np.int32), (off & 0xFFFF).astype(np.uint16)
 
 

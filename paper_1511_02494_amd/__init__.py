@@ -94,6 +94,14 @@ class SpmvError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime with the same soname as /opt/rocm's.
+    # Loading torch first makes this library bind to that same runtime, so
+    # streams and device pointers from torch are valid here (two runtimes in
+    # one process cannot share them).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(the HIP library is required; there is no fallback)")
@@ -315,11 +323,12 @@ def spmv_hbm_probe(nbytes: int = 4 << 30):
 class Plan:
     """Owns a plan handle and keeps the borrowed CSR tensors alive."""
 
-    def __init__(self, rowptr, colind, val, n_cols, val_dtype=SPMV_F64, stream=None, flags=0):
+    def __init__(self, rowptr, colind, val, n_cols, val_dtype=SPMV_F64, stream=None, flags=0,
+                 nnz=None):
         self._keep = (rowptr, colind, val)
         self.n = int(rowptr.numel()) - 1
         self.m = int(n_cols)
-        self.nnz = int(colind.numel())
+        self.nnz = int(colind.numel()) if nnz is None else int(nnz)
         self.dtype = val_dtype
         self.handle = spmv_plan_create(self.n, self.m, self.nnz, rowptr, colind, val,
                                        val_dtype, stream, flags)

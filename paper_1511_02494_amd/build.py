@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libspmvsel.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
+FLAGS = ["-O3", f"--offload-arch={ARCH}", "-mcode-object-version=5", "-fPIC", "-std=c++17",
          "-ffp-contract=off", "-fno-fast-math",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC,

@@ -187,7 +187,39 @@ spmv_status_t ensure_features(spmv_plan *P) {
     return SPMV_OK;
 }
 
-bool d16_feasible(const spmv_plan *P) { return P->acc[2] <= 65535; }
+// delta16 feasibility: every block of d16_rows rows spans at most 65536
+// columns.  The block bases are the panel minima; tried first with the
+// short_row block height, then with 256-row blocks.
+spmv_status_t check_d16(spmv_plan *P) {
+    if (P->d16_checked) return SPMV_OK;
+    int heights[2] = {P->rs_rows * kBlock, kBlock};
+    for (int t = 0; t < 2; ++t) {
+        const int H = heights[t];
+        if (t == 1 && H == heights[0]) break;
+        const int64_t blocks = (P->n + H - 1) / H;
+        SPMV_TRY(P->d16_base.alloc((size_t)(blocks > 0 ? blocks : 1) * 4));
+        SPMV_TRY(P->d16_cmax.alloc((size_t)(blocks > 0 ? blocks : 1) * 4));
+        unsigned long long span = 0;
+        if (blocks > 0) {
+            SPMV_HIP(launch_panel_windows(*P, H, P->d16_base.as<int32_t>(), P->d16_cmax.as<int32_t>(),
+                                          blocks, S(P)));
+            auto *d = scr<unsigned long long>(P, kOffSum);
+            SPMV_HIP(launch_max_span(P->d16_base.as<int32_t>(), P->d16_cmax.as<int32_t>(), blocks,
+                                     d, S(P)));
+            SPMV_HIP(hipMemcpyAsync(P->h_pinned, d, 8, hipMemcpyDeviceToHost, S(P)));
+            SPMV_TRY(sync(P));
+            memcpy(&span, P->h_pinned, 8);
+        }
+        P->d16_rows = H;
+        P->d16_feasible = span <= 65535;
+        if (P->d16_feasible) break;
+    }
+    P->d16_cmax.release();
+    P->d16_checked = true;
+    return SPMV_OK;
+}
+
+bool d16_feasible(const spmv_plan *P) { return P->d16_feasible; }
 
 // ------------------------------------------------------------ formats
 spmv_status_t build_xblock(spmv_plan *P) {
@@ -220,11 +252,10 @@ spmv_status_t build_format(spmv_plan *P, int v) {
         return SPMV_OK;
     case V_DELTA16: {
         if (P->d16_built) return SPMV_OK;
-        SPMV_TRY(ensure_features(P));
+        SPMV_TRY(check_d16(P));
         if (!d16_feasible(P))
-            return fail(SPMV_ERR_INFEASIBLE, "delta16: a row spans %llu > 65535 columns",
-                        (unsigned long long)P->acc[2]);
-        SPMV_TRY(P->d16_base.alloc((size_t)(P->n > 0 ? P->n : 1) * 4));
+            return fail(SPMV_ERR_INFEASIBLE,
+                        "delta16: a block of %d rows spans more than 65536 columns", P->d16_rows);
         SPMV_TRY(P->d16_off.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 2 + 16));
         SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(), P->d16_off.as<uint16_t>(),
                                        S(P)));
@@ -258,7 +289,7 @@ spmv_status_t build_format(spmv_plan *P, int v) {
 }
 
 spmv_status_t feasible_mask(spmv_plan *P, uint32_t *bits) {
-    SPMV_TRY(ensure_features(P));
+    SPMV_TRY(check_d16(P));
     SPMV_TRY(build_xblock(P));
     uint32_t b = (1u << V_CSR_SCALAR) | (1u << V_CSR_VECTOR) | (1u << V_MERGE_PATH) |
                  (1u << V_SHORT_ROW);
@@ -629,8 +660,12 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
     if (v < 0 || v >= SPMV_N_VARIANTS) return fail(SPMV_ERR_ARG, "unknown variant %d", v);
     const int64_t vb = vbytes(P->dtype), xb = xbytes(P->dtype);
     const int64_t ib = v == V_DELTA16 ? 2 : 4;
-    *bytes = 4 * (P->n + 1) + (ib + vb) * P->nnz + xb * P->m + xb * P->n +
-             (v == V_DELTA16 ? 4 * P->n : 0);
+    int64_t extra = 0;
+    if (v == V_DELTA16) {
+        SPMV_TRY(check_d16(P));
+        extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
+    }
+    *bytes = 4 * (P->n + 1) + (ib + vb) * P->nnz + xb * P->m + xb * P->n + extra;
     return SPMV_OK;
 }
 
@@ -663,7 +698,8 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
     case 6: *value = (P->n + P->xb_rows - 1) / P->xb_rows; break;
     case 7: *value = kXbChunkBytes / xbytes(P->dtype); break;
     case 8: *value = P->parts; break;
-    case 9: SPMV_TRY(ensure_features(P)); *value = d16_feasible(P); break;
+    case 9: SPMV_TRY(check_d16(P)); *value = d16_feasible(P); break;
+    case 11: SPMV_TRY(check_d16(P)); *value = P->d16_rows; break;
     case 10: SPMV_TRY(build_xblock(P)); *value = P->xb_feasible; break;
     default: return fail(SPMV_ERR_ARG, "unknown key %d", key);
     }
@@ -679,7 +715,7 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
     case 0: case 1:
         SPMV_TRY(build_format(P, V_DELTA16));
         src = which == 0 ? P->d16_base.p : P->d16_off.p;
-        want = which == 0 ? 4 * P->n : 2 * P->nnz;
+        want = which == 0 ? 4 * ((P->n + P->d16_rows - 1) / P->d16_rows) : 2 * P->nnz;
         break;
     case 2: case 3:
         SPMV_TRY(build_format(P, V_MERGE_PATH));

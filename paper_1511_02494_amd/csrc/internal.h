@@ -96,8 +96,9 @@ struct spmv_plan {
     int parts = 2048;            // profiling partitions
 
     // derived formats (lazy)
-    bool d16_built = false;
-    spmvsel::DevBuf d16_base, d16_off;
+    bool d16_checked = false, d16_feasible = false, d16_built = false;
+    int d16_rows = 256;          // rows per block sharing one reference column
+    spmvsel::DevBuf d16_base, d16_off, d16_cmax;
     bool mp_built = false;
     int64_t mp_tiles = 0;
     spmvsel::DevBuf mp_split_row, mp_split_nnz, mp_carry_row, mp_carry_val;
@@ -130,7 +131,10 @@ hipError_t launch_merge_path(const spmv_plan &P, const void *x, void *y, hipStre
 hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 
 // format preparation (k_prep.hip)
-hipError_t launch_delta16_encode(const spmv_plan &P, int32_t *base, uint16_t *off, hipStream_t s);
+hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16_t *off,
+                                 hipStream_t s);
+hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t panels,
+                           unsigned long long *d_max, hipStream_t s);
 hipError_t launch_merge_splits(const spmv_plan &P, int32_t *srow, int32_t *snnz, int64_t tiles,
                                hipStream_t s);
 hipError_t launch_panel_windows(const spmv_plan &P, int rows_per_panel, int32_t *cmin,

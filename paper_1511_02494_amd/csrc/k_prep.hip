@@ -4,34 +4,59 @@
 
 namespace spmvsel {
 
-// ---- delta16: base_i = first column of row i (0 if empty), off_k = c_k - base_i.
-// A sub-wavefront of W lanes per row (W from the mean row length).
+// ---- delta16: off_k = c_k - base[row(k) / H], base = the block's smallest
+// column (from the panel windows with H rows per panel).  A sub-wavefront
+// of W lanes per row.
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_delta16_encode(int64_t n, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_delta16_encode(int64_t n, int H,
+                                                           const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
-                                                           int32_t *__restrict__ base,
+                                                           const int32_t *__restrict__ base,
                                                            uint16_t *__restrict__ off) {
     const int lane = threadIdx.x & (W - 1);
     const int64_t nsub = (int64_t)gridDim.x * (kBlock / W);
     for (int64_t i = blockIdx.x * (int64_t)(kBlock / W) + threadIdx.x / W; i < n; i += nsub) {
         const int32_t a = rp[i], b = rp[i + 1];
-        const int32_t b0 = a < b ? ci[a] : 0;
-        if (lane == 0) base[i] = b0;
+        const int32_t b0 = base[i / H];
         for (int32_t k = a + lane; k < b; k += W) off[k] = (uint16_t)(ci[k] - b0);
     }
 }
 
-hipError_t launch_delta16_encode(const spmv_plan &P, int32_t *base, uint16_t *off, hipStream_t s) {
+hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16_t *off, hipStream_t s) {
     if (P.n == 0) return hipSuccess;
     const int W = P.vec_width;
     int64_t g = (P.n + (kBlock / W) - 1) / (kBlock / W);
     if (g > (int64_t)P.num_cus * 32) g = (int64_t)P.num_cus * 32;
     switch (W) {
-#define ENC(WW) case WW: hipLaunchKernelGGL((k_delta16_encode<WW>), dim3((unsigned)g), dim3(kBlock), 0, s, P.n, P.rowptr, P.colind, base, off); break;
+#define ENC(WW) case WW: hipLaunchKernelGGL((k_delta16_encode<WW>), dim3((unsigned)g), dim3(kBlock), 0, s, P.n, P.d16_rows, P.rowptr, P.colind, base, off); break;
         ENC(2) ENC(4) ENC(8) ENC(16) ENC(32) ENC(64)
 #undef ENC
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// largest window span (cmax - cmin) over panels, for the 16-bit feasibility test
+__global__ __launch_bounds__(kBlock) void k_max_span(const int32_t *__restrict__ cmin,
+                                                     const int32_t *__restrict__ cmax,
+                                                     int64_t panels, unsigned long long *mx) {
+    unsigned long long t = 0;
+    for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < panels;
+         p += (int64_t)gridDim.x * kBlock) {
+        const int64_t d = (int64_t)cmax[p] - cmin[p];
+        if (d > (int64_t)t) t = (unsigned long long)d;
+    }
+    if (t) atomicMax(mx, t);
+}
+
+hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t panels,
+                           unsigned long long *d_max, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(d_max, 0, sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    int64_t g = (panels + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_max_span, dim3((unsigned)g), dim3(kBlock), 0, s, cmin, cmax, panels, d_max);
     return hipGetLastError();
 }
 

@@ -64,35 +64,44 @@ __global__ __launch_bounds__(kBlock) void k_csr_vector(int64_t n, const int32_t 
 }
 
 // ============================================================ row streaming
-// short_row and delta16.  A workgroup owns 256*R consecutive rows.  Their
-// nonzeros are streamed in LDS chunks of 2048: each thread loads an aligned
-// run of 8 with 16-byte vector loads, gathers x and stores the products;
-// then thread t sums its R rows from LDS in column order (the order of
-// Algorithm 1, so FP64 results equal the sequential sum bit for bit).
-// With D16 the column of nonzero k is base[row(k)] + off[k] (16-bit offsets
-// from the row's first column); the row of a run is found by binary search
-// over the block's row pointers in LDS.
-template <class V, bool D16>
+// short_row and delta16 (CSR-stream style).  A workgroup owns 256*R
+// consecutive rows.  Their nonzeros are streamed in LDS chunks of 2048 in a
+// striped layout: lane t of the workgroup takes the pairs starting at
+// chunk + 2t + 512j (j = 0..3) with 2-element vector loads, so that each
+// load and each x gather of a wavefront covers consecutive nonzeros.  The
+// products go to LDS; then thread t sums its R rows from LDS in column
+// order (the order of Algorithm 1, so FP64 results equal the sequential sum
+// bit for bit).
+// With D16 the column of nonzero k is base[block] + off[k]: 16-bit offsets
+// from the smallest column of the workgroup's block of rows.
+template <class T> struct Pair;
+template <> struct Pair<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Pair<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct Pair<uint16_t> { typedef unsigned short type __attribute__((ext_vector_type(2))); };
+template <> struct Pair<int32_t> { typedef int type __attribute__((ext_vector_type(2))); };
+
+template <class V, bool D16, int R>
 __global__ __launch_bounds__(kBlock) void k_rowstream(
-    int64_t n, int64_t nnz, int R, const int32_t *__restrict__ rp,
-    const int32_t *__restrict__ ci, const uint16_t *__restrict__ off,
-    const int32_t *__restrict__ rbase, const V *__restrict__ val,
-    const typename VT<V>::A *__restrict__ x, typename VT<V>::A *__restrict__ y) {
+    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const uint16_t *__restrict__ off, const int32_t *__restrict__ rbase,
+    const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
+    typename VT<V>::A *__restrict__ y) {
     using A = typename VT<V>::A;
-    constexpr int RBMAX = kBlock * kRowStreamMaxR;
-    __shared__ int32_t s_rp[RBMAX + 1];
-    __shared__ int32_t s_base[D16 ? RBMAX : 1];
+    using VP = typename Pair<V>::type;
+    using IP = typename Pair<int32_t>::type;
+    using OP = typename Pair<uint16_t>::type;
+    constexpr int RB = kBlock * R;
+    constexpr int NP = kRunLen / 2;  // pairs per thread per chunk
+    __shared__ int32_t s_rp[RB + 1];
     __shared__ A s_prod[kChunk];
 
-    const int RB = kBlock * R;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r0 = blk * RB;
     const int nrows = (int)((n - r0) < RB ? (n - r0) : RB);
     for (int r = threadIdx.x; r <= nrows; r += kBlock) s_rp[r] = rp[r0 + r];
-    if (D16)
-        for (int r = threadIdx.x; r < nrows; r += kBlock) s_base[r] = rbase[r0 + r];
     __syncthreads();
     const int32_t s = s_rp[0], e = s_rp[nrows];
+    const int32_t bbase = D16 ? rbase[blk] : 0;
 
     int myr = threadIdx.x * R;
     const int myr_end = (myr + R) < nrows ? (myr + R) : nrows;
@@ -100,55 +109,44 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
     bool comp = is_f32<A>() && myr < nrows && (s_rp[myr + 1] - s_rp[myr]) >= kKahanMinLen;
     Sum<A> acc;
 
-    const int32_t a0 = s & ~(kRunLen - 1);
+    const int32_t a0 = s & ~1;
     for (int32_t cs = a0; cs < e; cs += kChunk) {
-        // ---- phase 1: products of this thread's run
-        const int32_t e0 = cs + threadIdx.x * kRunLen;
-        if (e0 < e && e0 + kRunLen > s) {
-            V v[kRunLen];
-            int32_t col[kRunLen];
-            if (e0 + kRunLen <= nnz) {
-                load8_nt(val + e0, v);
+        // ---- phase 1: products of this thread's pairs
+        A p[kRunLen];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int32_t kk = cs + 2 * threadIdx.x + 2 * kBlock * j;
+            V v0 = V(0), v1 = V(0);
+            int32_t c0 = 0, c1 = 0;
+            if (kk + 1 < e) {
+                const VP vv = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + kk));
+                v0 = vv.x;
+                v1 = vv.y;
                 if (D16) {
-                    uint16_t o[kRunLen];
-                    load8_nt(off + e0, o);
-#pragma unroll
-                    for (int j = 0; j < kRunLen; ++j) col[j] = o[j];
+                    const OP oo = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + kk));
+                    c0 = oo.x;
+                    c1 = oo.y;
                 } else {
-                    load8_nt(ci + e0, col);
+                    const IP cc = __builtin_nontemporal_load(reinterpret_cast<const IP *>(ci + kk));
+                    c0 = cc.x;
+                    c1 = cc.y;
                 }
-            } else {
-#pragma unroll
-                for (int j = 0; j < kRunLen; ++j) {
-                    const bool in = e0 + j < nnz;
-                    v[j] = in ? val[e0 + j] : V(0);
-                    col[j] = in ? (D16 ? (int32_t)off[e0 + j] : ci[e0 + j]) : 0;
-                }
+            } else if (kk < e) {
+                v0 = val[kk];
+                c0 = D16 ? (int32_t)off[kk] : ci[kk];
             }
-            int r = 0;
+            const bool ok0 = kk >= s && kk < e, ok1 = kk + 1 >= s && kk + 1 < e;
             if (D16) {
-                // largest r with s_rp[r] <= max(e0, s): the row holding it
-                const int32_t t = e0 > s ? e0 : s;
-                int lo = 0, hi = nrows - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_rp[mid] <= t) lo = mid; else hi = mid - 1;
-                }
-                r = lo;
+                c0 += bbase;
+                c1 += bbase;
             }
-            A p[kRunLen];
+            p[2 * j] = ok0 ? VT<V>::cvt(v0) * x[c0] : A(0);
+            p[2 * j + 1] = ok1 ? VT<V>::cvt(v1) * x[c1] : A(0);
+        }
 #pragma unroll
-            for (int j = 0; j < kRunLen; ++j) {
-                const int32_t ee = e0 + j;
-                const bool valid = ee >= s && ee < e;
-                if (D16 && valid) {
-                    while (s_rp[r + 1] <= ee) ++r;
-                    col[j] += s_base[r];
-                }
-                p[j] = valid ? VT<V>::cvt(v[j]) * x[col[j]] : A(0);
-            }
-#pragma unroll
-            for (int j = 0; j < kRunLen; ++j) s_prod[threadIdx.x * kRunLen + j] = p[j];
+        for (int j = 0; j < NP; ++j) {
+            s_prod[2 * threadIdx.x + 2 * kBlock * j] = p[2 * j];
+            s_prod[2 * threadIdx.x + 2 * kBlock * j + 1] = p[2 * j + 1];
         }
         __syncthreads();
         // ---- phase 2: each thread sums its rows' products in this chunk
@@ -407,16 +405,26 @@ hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y
     return by_dtype(P.dtype, [&](auto tag) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
         using A = typename VT<V>::A;
-        const int R = P.rs_rows;
+        const int R = d16 ? P.d16_rows / kBlock : P.rs_rows;
         const unsigned g = grid_for(P.n, kBlock * R, INT32_MAX);
-        if (d16)
-            hipLaunchKernelGGL((k_rowstream<V, true>), dim3(g), dim3(kBlock), 0, s, P.n, P.nnz, R,
-                               P.rowptr, P.colind, P.d16_off.as<uint16_t>(),
-                               P.d16_base.as<int32_t>(), (const V *)P.val, (const A *)x, (A *)y);
-        else
-            hipLaunchKernelGGL((k_rowstream<V, false>), dim3(g), dim3(kBlock), 0, s, P.n, P.nnz, R,
-                               P.rowptr, P.colind, (const uint16_t *)nullptr,
-                               (const int32_t *)nullptr, (const V *)P.val, (const A *)x, (A *)y);
+        const uint16_t *off = P.d16_off.as<uint16_t>();
+        const int32_t *base = P.d16_base.as<int32_t>();
+#define SPMV_RS(RR)                                                                               \
+    case RR:                                                                                      \
+        if (d16)                                                                                  \
+            hipLaunchKernelGGL((k_rowstream<V, true, RR>), dim3(g), dim3(kBlock), 0, s, P.n,     \
+                               P.rowptr, P.colind, off, base, (const V *)P.val, (const A *)x,    \
+                               (A *)y);                                                           \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_rowstream<V, false, RR>), dim3(g), dim3(kBlock), 0, s, P.n,    \
+                               P.rowptr, P.colind, (const uint16_t *)nullptr,                     \
+                               (const int32_t *)nullptr, (const V *)P.val, (const A *)x, (A *)y); \
+        break;
+        switch (R) {
+            SPMV_RS(1) SPMV_RS(2) SPMV_RS(4) SPMV_RS(8)
+        default: return hipErrorInvalidValue;
+        }
+#undef SPMV_RS
         return hipGetLastError();
     });
 }

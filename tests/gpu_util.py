@@ -41,7 +41,7 @@ def x_tensor(x, dtype=S.SPMV_F64):
 
 def make_plan(rp, ci, val, n_cols, dtype=S.SPMV_F64, flags=0):
     r, c, v = upload_csr(rp, ci, val, dtype)
-    return S.Plan(r, c, v, n_cols, dtype, flags=flags)
+    return S.Plan(r, c, v, n_cols, dtype, flags=flags, nnz=len(ci))
 
 
 def run(plan, variant, x, dtype=S.SPMV_F64, fill=np.nan):

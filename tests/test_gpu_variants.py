@@ -105,7 +105,11 @@ def test_integer_valued_bit_exact(case, dtype):
 def test_degenerate_empty(n, m):
     rp = np.zeros(n + 1, np.int32)
     plan = make_plan(rp, np.zeros(0, np.int32), np.zeros(0), m)
-    assert plan.features()[0] == ([0.0] * 12 if n == 0 else plan.features()[0])
+    f, _ = plan.features()
+    if n == 0:
+        assert f == [0.0] * 12
+    else:
+        assert f[0] == n and f[1:11] == [0.0] * 10
     for var in range(6):
         if (S.spmv_variant_mask(plan.handle) >> var) & 1:
             y = run(plan, var, np.zeros(m), S.SPMV_F64)
@@ -125,7 +129,7 @@ def test_copy_inputs_flag():
     x = synth.vector(1000, 2)
     from gpu_util import upload_csr
     r, c, vt = upload_csr(rp, ci, v)
-    plan = S.Plan(r, c, vt, 1000, flags=S.SPMV_COPY_INPUTS)
+    plan = S.Plan(r, c, vt, 1000, flags=S.SPMV_COPY_INPUTS, nnz=len(ci))
     c.zero_()
     vt.zero_()
     y = run(plan, S.V_CSR_VECTOR, x)

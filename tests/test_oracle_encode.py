@@ -19,20 +19,23 @@ def cases(seed=3, count=40):
         yield synth.tiny_random_csr(rng, n, m, float(rng.choice([0, .02, .2, .7, 1.0])))
 
 
-def test_delta16_roundtrip_and_feasibility():
+@pytest.mark.parametrize("H", [1, 3, 256])
+def test_delta16_roundtrip_and_feasibility(H):
     for rp, ci, _ in cases():
-        ok, base, off = delta16_ref(rp, ci)
+        ok, base, off = delta16_ref(rp, ci, H)
         assert ok
-        rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
-        assert np.array_equal(base[rows].astype(np.int64) + off, ci)
-        for i in range(len(rp) - 1):
-            if rp[i + 1] > rp[i]:
-                assert base[i] == ci[rp[i]] and off[rp[i]] == 0
-            else:
-                assert base[i] == 0
-    # a row spanning 65536 columns is infeasible, 65535 is feasible
+        n = len(rp) - 1
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        blk = rows // H
+        assert np.array_equal(base[blk].astype(np.int64) + off, ci)
+        for b in range(len(base)):
+            seg = ci[rp[b * H]:rp[min(n, (b + 1) * H)]]
+            assert base[b] == (seg.min() if len(seg) else 0)
+    # a block spanning 65536 columns is infeasible, 65535 is feasible
     assert delta16_ref([0, 2], [0, 65535])[0]
     assert not delta16_ref([0, 2], [0, 65536])[0]
+    assert delta16_ref([0, 1, 2], [0, 65536], 1)[0]
+    assert not delta16_ref([0, 1, 2], [0, 65536], 2)[0]
 
 
 def test_delta16_random_2m_infeasible_stencil_feasible():
