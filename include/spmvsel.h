@@ -203,8 +203,10 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t plan, int32_t which,
 /* Profiling-based classifier (Section 3.2.1)                               */
 
 /* Run the three micro-benchmarks against baseline CSR on the plan:
- * baseline and `noxmiss` (all column indices 0) and `inflate` (int64 rowptr
- * and colind), each the median of `reps` runs on a static partition of
+ * baseline, `noxmiss` (irregular x accesses removed: every column index of
+ * row i replaced by i mod M; all-zero indices, as printed in the paper,
+ * would make every wavefront hit one cache line on a GPU) and `inflate`
+ * (int64 rowptr and colind), each the median of `reps` runs on a static partition of
  * 256 x (CUs) row ranges with equal nonzeros, one per wavefront; `balance`
  * from the per-partition device-clock durations of the baseline runs.
  * meas = {t_base, t_nox, t_inf, d_max, d_mean}.  Temporary copies are

@@ -1,8 +1,9 @@
 """Profiling-based classifier and class-to-optimisation map (test infrastructure).
 
 Section 3.2.1: three micro-benchmarks modify baseline CSR SpMV — ``noxmiss``
-(every column index set to zero), ``inflate`` (64-bit row pointers and
-column indices) and ``balance`` (per-thread execution times and their
+(irregular accesses to x removed; the paper zeroes every column index, which
+on a GPU makes every wavefront hit one cache line, so row i's indices are
+mapped to i instead), ``inflate`` (64-bit row pointers and column indices) and ``balance`` (per-thread execution times and their
 arithmetic mean, under the default static partition with equal nonzeros per
 thread).  Each yields a speedup over baseline CSR, except ``inflate`` whose
 slowdown (the inverse) is used.  The benchmarks are examined from the

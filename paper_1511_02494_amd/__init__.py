@@ -114,6 +114,7 @@ def _load():
 
 
 lib = _load()
+SELECTOR_CONFIG = os.path.join(_HERE, "selector_config.json")
 
 
 def spmv_last_error() -> str:
@@ -315,6 +316,19 @@ def spmv_hbm_probe(nbytes: int = 4 << 30):
     r, c = _F64(), _F64()
     _check("spmv_hbm_probe", lib.spmv_hbm_probe(nbytes, ctypes.byref(r), ctypes.byref(c)))
     return r.value, c.value
+
+
+def load_selector_config(path: str = SELECTOR_CONFIG) -> bool:
+    """Set the profiling thresholds calibrated for this GPU, if the file exists."""
+    if not os.path.exists(path):
+        return False
+    import json
+    with open(path) as f:
+        spmv_set_thresholds(json.load(f)["theta"])
+    return True
+
+
+load_selector_config()
 
 
 # ------------------------------------------------------------ convenience

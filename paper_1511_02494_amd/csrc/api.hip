@@ -383,7 +383,7 @@ spmv_status_t profile_measure(spmv_plan *P, int reps, double meas[5]) {
     SPMV_TRY(zeros.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 4));
     SPMV_TRY(rp64.alloc((size_t)(P->n + 1) * 8));
     SPMV_TRY(ci64.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 8));
-    SPMV_HIP(hipMemsetAsync(zeros.p, 0, zeros.bytes, S(P)));
+    SPMV_HIP(launch_row_columns(*P, zeros.as<int32_t>(), S(P)));
     SPMV_HIP(launch_widen(P->rowptr, rp64.as<int64_t>(), P->n + 1, S(P)));
     SPMV_HIP(launch_widen(P->colind, ci64.as<int64_t>(), P->nnz, S(P)));
     const int32_t *bounds = P->part_bounds.as<int32_t>();

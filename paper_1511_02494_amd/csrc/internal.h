@@ -142,6 +142,7 @@ hipError_t launch_panel_windows(const spmv_plan &P, int rows_per_panel, int32_t 
 hipError_t launch_partition(const int32_t *rowptr, int64_t n, int parts, int32_t *bounds,
                             hipStream_t s);
 hipError_t launch_widen(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+hipError_t launch_row_columns(const spmv_plan &P, int32_t *out, hipStream_t s);
 hipError_t launch_window_sum(const int32_t *cmin, const int32_t *cmax, int64_t panels,
                              unsigned long long *d_sum, hipStream_t s);
 hipError_t launch_quantize(const double *in, void *out, int64_t n, int to, hipStream_t s);

@@ -176,6 +176,36 @@ hipError_t launch_partition(const int32_t *rowptr, int64_t n, int parts, int32_t
     return hipGetLastError();
 }
 
+// noxmiss column array: every nonzero of row i gets column i mod M (x read
+// as a regular stream, one element per row).  A sub-wavefront of W lanes
+// per row.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_row_columns(int64_t n, int64_t m,
+                                                        const int32_t *__restrict__ rp,
+                                                        int32_t *__restrict__ out) {
+    const int lane = threadIdx.x & (W - 1);
+    const int64_t nsub = (int64_t)gridDim.x * (kBlock / W);
+    for (int64_t i = blockIdx.x * (int64_t)(kBlock / W) + threadIdx.x / W; i < n; i += nsub) {
+        const int32_t a = rp[i], b = rp[i + 1];
+        const int32_t c = (int32_t)(m > 0 ? i % m : 0);
+        for (int32_t k = a + lane; k < b; k += W) out[k] = c;
+    }
+}
+
+hipError_t launch_row_columns(const spmv_plan &P, int32_t *out, hipStream_t s) {
+    if (P.n == 0 || P.nnz == 0) return hipSuccess;
+    const int W = P.vec_width;
+    int64_t g = (P.n + (kBlock / W) - 1) / (kBlock / W);
+    if (g > (int64_t)P.num_cus * 32) g = (int64_t)P.num_cus * 32;
+    switch (W) {
+#define RC(WW) case WW: hipLaunchKernelGGL((k_row_columns<WW>), dim3((unsigned)g), dim3(kBlock), 0, s, P.n, P.m, P.rowptr, out); break;
+        RC(2) RC(4) RC(8) RC(16) RC(32) RC(64)
+#undef RC
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_widen(const int32_t *__restrict__ in,
                                                   int64_t *__restrict__ out, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;

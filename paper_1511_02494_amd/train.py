@@ -1,0 +1,416 @@
+"""Labelling, training and evaluation of the learned selector (MLP).
+
+The paper trains its feature-based classifiers offline on labelled matrices
+(Section 3.2.2 and 4.2); here the labels are the fastest variant measured on
+the device for each seeded synthetic matrix, and the network is trained on
+the device by the library's own forward/backward and Adam kernels.
+
+Subcommands (run on the GPU machine)::
+
+    python -m paper_1511_02494_amd.train label --seeds 10000:12000 --out train.jsonl
+    python -m paper_1511_02494_amd.train fit --train train.jsonl --out mlp_selector.bin
+    python -m paper_1511_02494_amd.train eval --model mlp_selector.bin --test test.jsonl
+
+``label`` appends one JSON record per matrix (resuming after the last seed
+already in the file): features, feasible mask, the time of every variant,
+the label, the profiling micro-benchmark measurements and the host cost of
+the feature extraction and of the profiling run.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+import synth
+import paper_1511_02494_amd as S
+from paper_1511_02494_amd.model_io import write_model
+
+N_FEAT = 12
+LOG_FEATURES = 8
+
+
+# --------------------------------------------------------------- matrices
+
+
+def device_params(spec):
+    """(family id, integer parameters, n_rows, n_cols) for the device generator."""
+    p = spec.params
+    f = spec.family
+    if f in ("laplace2d", "stencil2d_9"):
+        n = p["n"] ** 2
+        return S.FAMILY[f], [p["n"], 0 if p.get("values", "random") == "const" else 1], n, n
+    if f in ("stencil3d_7", "stencil3d_27"):
+        n = p["n"] ** 3
+        return S.FAMILY[f], [p["n"], 0 if p.get("values", "random") == "const" else 1], n, n
+    if f == "uniform_random":
+        return S.FAMILY[f], [p["n_rows"], p["n_cols"], p["per_row"]], p["n_rows"], p["n_cols"]
+    if f == "banded":
+        return S.FAMILY[f], [p["n"], p["d16"], p["half_width"]], p["n"], p["n"]
+    if f == "random_rows":
+        return S.FAMILY[f], [p["n"], p["d16"]], p["n"], p["n"]
+    if f == "powerlaw":
+        return S.FAMILY[f], [p["n"], p["p16"], p["cap"], int(p.get("force_long", True))], p["n"], p["n"]
+    if f == "short_rows":
+        return S.FAMILY[f], [p["n"]], p["n"], p["n"]
+    raise ValueError(f)
+
+
+def generate_on_device(spec, torch, dev):
+    """CSR arrays and x of ``spec`` generated on the device (same bytes as synth)."""
+    fam, prm, n, m = device_params(spec)
+    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    nnz = S.spmv_generate(fam, prm, spec.seed, rp)
+    ci = torch.empty(nnz + 8, dtype=torch.int32, device=dev)
+    val = torch.empty(nnz + 8, dtype=torch.float64, device=dev)
+    S.spmv_generate(fam, prm, spec.seed, rp, ci, val)
+    x = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
+    S.spmv_generate_vector(m, spec.x_seed, x)
+    return dict(rp=rp, ci=ci, val=val, x=x, n=n, m=m, nnz=nnz)
+
+
+# --------------------------------------------------------------- labelling
+
+
+def time_variants(plan, mask, reps=10):
+    """Median time of every feasible variant (0 for infeasible ones).
+
+    Every variant is timed once first; those within 3x of the fastest single
+    run get ``reps`` timed runs (a variant 3x slower cannot be within 5% of
+    the best)."""
+    t = [0.0] * 6
+    for v in range(6):
+        if (mask >> v) & 1:
+            t[v], _ = plan.time(v, reps=1)
+    best = min(x for x in t if x > 0)
+    for v in range(6):
+        if t[v] > 0 and t[v] <= 3 * best:
+            t[v], _ = plan.time(v, reps=reps)
+    return t
+
+
+def label_one(seed, torch, dev, reps=10):
+    spec = synth.sweep_spec(seed)
+    M = generate_on_device(spec, torch, dev)
+    plan = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
+    t0 = time.perf_counter()
+    feats, acc = plan.features()
+    t_feat = time.perf_counter() - t0
+    mask = plan.mask()
+    times = time_variants(plan, mask, reps)
+    label = min((v for v in range(6) if times[v] > 0), key=lambda v: (times[v], v))
+    t0 = time.perf_counter()
+    meas = S.spmv_profile_measure(plan.handle, 3)
+    t_prof = time.perf_counter() - t0
+    rec = dict(seed=seed, name=spec.name, family=spec.family, n=M["n"], nnz=M["nnz"],
+               features=feats, mask=mask, times=times, label=label, meas=meas,
+               bytes=[plan.bytes(v) for v in range(6)], t_features=t_feat, t_profile=t_prof)
+    plan.close()
+    return rec
+
+
+def cmd_label(args):
+    import torch
+    dev = torch.device("cuda:0")
+    lo, hi = (int(v) for v in args.seeds.split(":"))
+    done = set()
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            for line in f:
+                done.add(json.loads(line)["seed"])
+    t_start = time.time()
+    with open(args.out, "a") as f:
+        for seed in range(lo, hi):
+            if seed in done:
+                continue
+            if args.budget_s and time.time() - t_start > args.budget_s:
+                print(f"budget reached at seed {seed}", flush=True)
+                break
+            rec = label_one(seed, torch, dev, args.reps)
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            print(f"seed {seed} {rec['name']:>40s} nnz={rec['nnz']:>10d} "
+                  f"label={S.VARIANTS[rec['label']]:>10s} "
+                  f"best={min(t for t in rec['times'] if t > 0) * 1e6:9.1f}us", flush=True)
+            torch.cuda.empty_cache()
+
+
+# --------------------------------------------------------------- training
+
+
+def raw_inputs(features):
+    """g_k = plog2(1 + f_k) for k < 8, f_k otherwise (the model's input map)."""
+    out = []
+    for k, f in enumerate(features):
+        if k < LOG_FEATURES:
+            m, e = math.frexp(1.0 + f)
+            out.append(float(e - 1) + (2.0 * m - 1.0))
+        else:
+            out.append(float(f))
+    return out
+
+
+def normalise(G, mu, rho):
+    G32 = np.asarray(G, dtype=np.float64).astype(np.float32)
+    return ((G32 - mu).astype(np.float32) * rho).astype(np.float32)
+
+
+def load_records(path):
+    with open(path) as f:
+        return [json.loads(line) for line in f]
+
+
+def within(times, v, tol=0.05):
+    best = min(t for t in times if t > 0)
+    return times[v] > 0 and times[v] <= (1 + tol) * best
+
+
+def profiling_pick(rec, theta):
+    v, _ = S.spmv_profile_decide(rec["meas"], rec["features"], theta, rec["mask"])
+    return v
+
+
+def train_device(Z, labels, masks, Zv, lv, mv, epochs, lr, batch, seed, log):
+    """Adam on the device with the library's kernels; returns the best params."""
+    import torch
+    dev = torch.device("cuda:0")
+    P = torch.from_numpy(synth.he_uniform_params(seed)).to(dev)
+    Mm = torch.zeros_like(P)
+    Vv = torch.zeros_like(P)
+    G = torch.empty_like(P)
+    L = torch.empty(1, dtype=torch.float32, device=dev)
+    dZ = torch.from_numpy(Z).to(dev)
+    dl = torch.from_numpy(labels.astype(np.int32)).to(dev)
+    dm = torch.from_numpy(masks.astype(np.uint8)).to(dev)
+    dZv = torch.from_numpy(Zv).to(dev)
+    dlv = torch.from_numpy(lv.astype(np.int32)).to(dev)
+    dmv = torch.from_numpy(mv.astype(np.uint8)).to(dev)
+    Gv = torch.empty_like(P)
+    Lv = torch.empty(1, dtype=torch.float32, device=dev)
+    n = len(Z)
+    step = 0
+    best = (float("inf"), None, -1)
+    patience = 0
+    for ep in range(epochs):
+        order = synth.epoch_order(n, seed, ep)
+        for b0 in range(0, n, batch):
+            idx = torch.from_numpy(order[b0:b0 + batch].astype(np.int64)).to(dev)
+            B = len(idx)
+            zb, lb, mb = dZ[idx].contiguous(), dl[idx].contiguous(), dm[idx].contiguous()
+            S.spmv_mlp_forward_backward(P, zb, lb, mb, B, G, L)
+            step += 1
+            S.spmv_mlp_adam_step(P, G, Mm, Vv, P.numel(), step, lr)
+        # validation loss (one pass, batches of up to 1024)
+        tot = 0.0
+        for b0 in range(0, len(Zv), 1024):
+            sl = slice(b0, b0 + 1024)
+            B = len(Zv[sl])
+            S.spmv_mlp_forward_backward(P, dZv[sl].contiguous(), dlv[sl].contiguous(),
+                                        dmv[sl].contiguous(), B, Gv, Lv)
+            tot += Lv.item() * B
+        vloss = tot / max(1, len(Zv))
+        if vloss < best[0] - 1e-4:
+            best = (vloss, P.detach().cpu().numpy().copy(), ep)
+            patience = 0
+        else:
+            patience += 1
+        if ep % 10 == 0 or patience == 0:
+            log(f"epoch {ep:3d} train loss {L.item():.4f} val loss {vloss:.4f}")
+        if patience >= 30:
+            break
+    return best
+
+
+def cmd_fit(args):
+    recs = load_records(args.train)
+    theta = S.spmv_get_thresholds() if args.theta is None else [float(v) for v in args.theta.split(",")]
+    G = np.array([raw_inputs(r["features"]) for r in recs])
+    mu = G.mean(axis=0).astype(np.float32)
+    sd = G.std(axis=0)
+    rho = (1.0 / np.where(sd > 1e-12, sd, 1.0)).astype(np.float32)
+    Z = normalise(G, mu, rho)
+    labels = np.array([r["label"] for r in recs])
+    masks = np.array([[(r["mask"] >> v) & 1 for v in range(6)] for r in recs], dtype=bool)
+    # validation split: every tenth record by seed order
+    seeds = np.array([r["seed"] for r in recs])
+    val = (seeds % 10) == 7
+    tr = ~val
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    best_loss, params, ep = train_device(Z[tr], labels[tr], masks[tr], Z[val], labels[val],
+                                         masks[val], args.epochs, args.lr, args.batch,
+                                         args.seed, log)
+    log(f"best validation loss {best_loss:.4f} at epoch {ep}")
+    # margin threshold: the smallest tau that keeps the combined selector's
+    # validation hit rate (MLP when confident, profiling otherwise) highest
+    tmp = args.out + ".tmp"
+    write_model(tmp, params, mu, rho, 0.0)
+    S.spmv_model_load(tmp)
+    vrecs = [r for r, v in zip(recs, val) if v]
+    preds = [S.spmv_mlp_predict(r["features"], r["mask"]) for r in vrecs]
+    prof = [profiling_pick(r, theta) for r in vrecs]
+    cands = sorted({0.0} | {float(p["margin"]) for p in preds if np.isfinite(p["margin"])})
+    best_tau, best_score = 0.0, -1.0
+    for tau in cands:
+        hits, fb = 0, 0
+        for r, p, q in zip(vrecs, preds, prof):
+            use_mlp = p["margin"] >= tau and not np.any(np.abs(p["z"]) > 8)
+            v = p["variant"] if use_mlp else q
+            fb += not use_mlp
+            hits += within(r["times"], v)
+        score = hits / max(1, len(vrecs)) - 0.02 * fb / max(1, len(vrecs))
+        if score > best_score + 1e-12:
+            best_tau, best_score = tau, score
+    os.remove(tmp)
+    write_model(args.out, params, mu, rho, best_tau)
+    S.spmv_model_unload()
+    log(f"tau = {best_tau:.4f} (validation score {best_score:.3f}); wrote {args.out}")
+    info = dict(train=os.path.basename(args.train), records=len(recs), val_records=int(val.sum()),
+                best_val_loss=best_loss, best_epoch=ep, tau=best_tau, theta=theta,
+                epochs=args.epochs, lr=args.lr, batch=args.batch, seed=args.seed)
+    with open(args.out + ".json", "w") as f:
+        json.dump(info, f, indent=1)
+
+
+# --------------------------------------------------------------- calibration
+
+
+THETA_GRID = (
+    [1.05, 1.1, 1.15, 1.2, 1.3, 1.4, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0],   # noxmiss
+    [1.02, 1.05, 1.08, 1.1, 1.15, 1.2, 1.25, 1.3, 1.4, 1.5],           # inflate
+    [1.1, 1.2, 1.3, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0, 6.0],               # balance
+    [1.0, 2.0, 3.0, 4.0, 8.0, 16.0, 1e9],                              # CMP short-row split
+)
+
+
+def cmd_calibrate(args):
+    """Thresholds of the profiling cascade that maximise the fraction of
+    calibration matrices whose pick is within 5% of the fastest variant (the
+    paper sets them empirically and does not print them)."""
+    recs = [r for r in load_records(args.labels)
+            if args.lo <= r["seed"] < args.hi]
+    best, best_hit = None, -1.0
+    for a in THETA_GRID[0]:
+        for b in THETA_GRID[1]:
+            for c in THETA_GRID[2]:
+                for d in THETA_GRID[3]:
+                    th = [a, b, c, d]
+                    hit = sum(within(r["times"], profiling_pick(r, th)) for r in recs)
+                    if hit > best_hit:
+                        best, best_hit = th, hit
+    out = dict(theta=best, hit_rate=best_hit / max(1, len(recs)), seeds=[args.lo, args.hi],
+               labels=os.path.basename(args.labels))
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+# --------------------------------------------------------------- evaluation
+
+
+def evaluate(recs, model, theta, t_infer_s):
+    """Accuracy, regret and gain of the selectors over the records."""
+    S.spmv_model_load(model)
+    rows = []
+    for r in recs:
+        p = S.spmv_mlp_predict(r["features"], r["mask"])
+        q = profiling_pick(r, theta)
+        fb = bool(p["fallback"])
+        pick = q if fb else p["variant"]
+        t = r["times"]
+        best = min(x for x in t if x > 0)
+        rows.append(dict(seed=r["seed"], label=r["label"], mlp=p["variant"], fallback=fb,
+                         pick=pick, prof=q, best=best, t_pick=t[pick], t_mlp=t[p["variant"]],
+                         t_prof=t[q], t_vec=t[S.V_CSR_VECTOR], t_scalar=t[S.V_CSR_SCALAR],
+                         ov_mlp=r["t_features"] + t_infer_s + (r["t_profile"] if fb else 0.0),
+                         ov_prof=r["t_features"] + r["t_profile"]))
+    S.spmv_model_unload()
+
+    def stats(key):
+        reg = np.array([x[key] / x["best"] - 1 for x in rows])
+        return dict(mean_regret=float(reg.mean()), hit5=float(np.mean(reg <= 0.05)),
+                    mean_speedup_vs_scalar=float(np.mean([x["t_scalar"] / x[key] for x in rows])),
+                    mean_speedup_vs_vector=float(np.mean([x["t_vec"] / x[key] for x in rows])))
+
+    out = {
+        "matrices": len(rows),
+        "mlp_accuracy": float(np.mean([x["mlp"] == x["label"] for x in rows])),
+        "fallback_rate": float(np.mean([x["fallback"] for x in rows])),
+        "selector_mlp_with_fallback": stats("t_pick"),
+        "mlp_alone": stats("t_mlp"),
+        "profiling_only": stats("t_prof"),
+        "always_csr_vector": stats("t_vec"),
+        "always_csr_scalar": stats("t_scalar"),
+        "ideal": stats("best"),
+        "overhead_mlp_spmv_equivs_median": float(np.median([x["ov_mlp"] / x["t_pick"] for x in rows])),
+        "overhead_profiling_spmv_equivs_median": float(np.median([x["ov_prof"] / x["t_prof"] for x in rows])),
+        "overhead_mlp_le20_fraction": float(np.mean([x["ov_mlp"] / x["t_pick"] <= 20 for x in rows])),
+        "inference_us": t_infer_s * 1e6,
+    }
+    # break-even solver iterations against always-csr_vector and profiling-only
+    gain = [x["t_vec"] - x["t_pick"] for x in rows]
+    out["break_even_iters_vs_vector_median"] = float(np.median(
+        [x["ov_mlp"] / g if g > 0 else float("inf") for x, g in zip(rows, gain)]))
+    return out, rows
+
+
+def measure_inference(features, mask, reps=200):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        S.spmv_mlp_predict(features, mask)
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def cmd_eval(args):
+    recs = load_records(args.test)
+    theta = S.spmv_get_thresholds() if args.theta is None else [float(v) for v in args.theta.split(",")]
+    S.spmv_model_load(args.model)
+    t_inf = measure_inference(recs[0]["features"], recs[0]["mask"])
+    S.spmv_model_unload()
+    out, rows = evaluate(recs, args.model, theta, t_inf)
+    out["theta"] = theta
+    print(json.dumps(out, indent=1))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(dict(summary=out, rows=rows), f)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("label")
+    a.add_argument("--seeds", required=True)
+    a.add_argument("--out", required=True)
+    a.add_argument("--reps", type=int, default=10)
+    a.add_argument("--budget-s", type=float, default=0.0)
+    a = sub.add_parser("fit")
+    a.add_argument("--train", required=True)
+    a.add_argument("--out", required=True)
+    a.add_argument("--epochs", type=int, default=200)
+    a.add_argument("--lr", type=float, default=1e-3)
+    a.add_argument("--batch", type=int, default=128)
+    a.add_argument("--seed", type=int, default=7)
+    a.add_argument("--theta", default=None)
+    a = sub.add_parser("calibrate")
+    a.add_argument("--labels", required=True)
+    a.add_argument("--lo", type=int, default=1000)
+    a.add_argument("--hi", type=int, default=1100)
+    a.add_argument("--out", required=True)
+    a = sub.add_parser("eval")
+    a.add_argument("--model", required=True)
+    a.add_argument("--test", required=True)
+    a.add_argument("--theta", default=None)
+    a.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    {"label": cmd_label, "fit": cmd_fit, "eval": cmd_eval,
+     "calibrate": cmd_calibrate}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()
