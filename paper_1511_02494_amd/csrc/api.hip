@@ -74,6 +74,12 @@ struct Model {
 Model g_model;
 
 std::map<int, DevBuf *> g_flush;  // 512 MiB eviction buffer per device
+
+// Recycled per-plan buffers: pinned 4 KiB host staging and device scratch,
+// so that creating and destroying plans in a loop allocates nothing after
+// the first plan on each device.
+std::vector<void *> g_pinned_pool;
+std::map<int, std::vector<void *>> g_scratch_pool;
 constexpr size_t kFlushBytes = 512ull << 20;
 constexpr int kNParams = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 6 + 6;
 
@@ -508,6 +514,21 @@ spmv_status_t mlp_predict(const double f[12], uint32_t feas, hipStream_t s, floa
     return SPMV_OK;
 }
 
+// Return the plan's recycled buffers to the pools and free the rest.
+void release_plan(spmv_plan *P) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (P->h_pinned) g_pinned_pool.push_back(P->h_pinned);
+        if (P->scratch.p && P->scratch.bytes == kScratchBytes) {
+            g_scratch_pool[P->device].push_back(P->scratch.p);
+            P->scratch.p = nullptr;
+            P->scratch.bytes = 0;
+        }
+    }
+    P->h_pinned = nullptr;
+    delete P;
+}
+
 }  // namespace
 }  // namespace spmvsel
 
@@ -548,7 +569,7 @@ spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
     P->colind = d_colind;
     P->val = d_val;
     auto bail = [&](spmv_status_t st) {
-        delete P;
+        release_plan(P);
         return st;
     };
     spmv_status_t st;
@@ -563,7 +584,20 @@ spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
     } while (0)
     BAIL_HIP(hipGetDevice(&P->device));
     BAIL_HIP(hipDeviceGetAttribute(&P->num_cus, hipDeviceAttributeMultiprocessorCount, P->device));
-    BAIL_HIP(hipHostMalloc(&P->h_pinned, 4096, hipHostMallocDefault));
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_pinned_pool.empty()) {
+            P->h_pinned = g_pinned_pool.back();
+            g_pinned_pool.pop_back();
+        }
+        auto &sp = g_scratch_pool[P->device];
+        if (!sp.empty()) {
+            P->scratch.p = sp.back();
+            P->scratch.bytes = kScratchBytes;
+            sp.pop_back();
+        }
+    }
+    if (!P->h_pinned) BAIL_HIP(hipHostMalloc(&P->h_pinned, 4096, hipHostMallocDefault));
     BAIL(P->scratch.alloc(kScratchBytes));
     if (flags & SPMV_COPY_INPUTS) {
         const size_t vb = vbytes(val_dtype);
@@ -613,8 +647,7 @@ spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
 spmv_status_t spmv_plan_destroy(spmv_plan_t P) {
     if (!P) return SPMV_OK;
     (void)hipStreamSynchronize(P->stream);
-    if (P->h_pinned) (void)hipHostFree(P->h_pinned);
-    delete P;
+    release_plan(P);
     return SPMV_OK;
 }
 

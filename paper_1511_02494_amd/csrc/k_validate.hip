@@ -72,11 +72,18 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n, int64_t m, int64
             }
         }
     }
+    // one atomic per wavefront (counts per thread are at most 8)
     const unsigned long long b_rp = __ballot(bad_rp), b_col = __ballot(bad_col);
-    if ((threadIdx.x & 63) == 0 && (b_rp | b_col))
-        atomicOr(&flags[0], (b_rp ? 1ull : 0ull) | (b_col ? 2ull : 0ull));
-    if (desc) atomicAdd(&flags[1], desc);
-    if (excused) atomicAdd(&flags[2], excused);
+    int d = (int)desc, x = (int)excused;
+    for (int o = 32; o > 0; o >>= 1) {
+        d += __shfl_xor(d, o, 64);
+        x += __shfl_xor(x, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (b_rp | b_col) atomicOr(&flags[0], (b_rp ? 1ull : 0ull) | (b_col ? 2ull : 0ull));
+        if (d) atomicAdd(&flags[1], (unsigned long long)d);
+        if (x) atomicAdd(&flags[2], (unsigned long long)x);
+    }
 }
 
 hipError_t launch_validate(const spmv_plan &P, uint64_t *d_flags, hipStream_t s) {
