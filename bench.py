@@ -31,10 +31,58 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_bench_config1_traffic.json")
+
+
+def kernel_source_hash():
+    """SHA-256 of the HIP sources, to tell whether stored counters still apply."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1511_02494_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode() + f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel_names):
+    """HBM bytes per launch (fetch + write) of the given kernels, from the
+    rocprofv3 counters stored in profiles/, or None when they were taken on
+    another version of the kernels."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    total = 0.0
+    for name in kernel_names:
+        hits = [v for k, v in rec["kernels"].items() if k.startswith(name)]
+        if not hits:
+            return None
+        total += hits[0]["fetch_bytes"] + hits[0]["write_bytes"]
+    return total
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_names(v, plan):
+    """Demangled-name prefixes of the kernels one FP64 execute of variant v launches."""
+    import paper_1511_02494_amd as S
+    if v == S.V_CSR_SCALAR:
+        return ["void spmvsel::k_csr_scalar<double>"]
+    if v == S.V_CSR_VECTOR:
+        return [f"void spmvsel::k_csr_vector<double, {plan.query(1)}>"]
+    if v == S.V_MERGE_PATH:
+        return ["void spmvsel::k_merge_path<double>", "void spmvsel::k_merge_fixup<double>"]
+    if v == S.V_XBLOCK_LDS:
+        return ["void spmvsel::k_merge_slices<double>", "void spmvsel::k_merge_fixup_slices<double>",
+                "void spmvsel::k_slice_sum<double>"]
+    if v == S.V_DELTA16:
+        return [f"void spmvsel::k_rowstream<double, true, {plan.query(11) // 256}>"]
+    return [f"void spmvsel::k_rowstream<double, false, {plan.query(2) // 256}>"]
 
 
 def parse():
@@ -174,6 +222,7 @@ def main():
             kern += [a.elapsed_time(b) * 1e-3 for a, b in r["ev"]]
         plan = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
         bytes_v = plan.bytes(v)
+        kernels = kernel_names(v, plan)
         total_bytes += sum(plan.bytes(r["info"]["variant"]) for r in recs) * args.iters
         picks = sorted({S.VARIANTS[r["info"]["variant"]] for r in recs})
         plan.close()
@@ -183,6 +232,7 @@ def main():
         best = min(var_tab, key=lambda k: var_tab[k]["warm_us"]) if var_tab else None
         rec = dict(
             matrix=M["name"], n=M["n"], nnz=M["nnz"], selected=S.VARIANTS[v], picks=picks,
+            kernels=kernels,
             selector_used=["profiling", "mlp", "exhaustive"][recs[-1]["info"]["selector"]],
             fell_back=bool(recs[-1]["info"]["fell_back"]),
             klass=(S.CLASSES[recs[-1]["info"]["klass"]] if recs[-1]["info"]["klass"] >= 0 else None),
@@ -209,8 +259,9 @@ def main():
     value = total_bytes / t_total * 1e-9
     dom = max(range(len(per)), key=lambda i: per[i]["spmv_us"])
     d = per[dom]
+    traffic = stored_traffic(d["kernels"])
     roof = {"bound": "hbm", "achieved": d["spmv_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": d["spmv_gbs"] / HBM_PEAK_GBS, "traffic": None,
+            "frac": d["spmv_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": f"{d['selected']} on {d['matrix']}",
             "bytes_per_launch": d["bytes_alg"], "launch_us": d["spmv_us"]}
 

@@ -61,8 +61,11 @@ typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
  *              OpenMP dynamic/auto schedules).
  *  DELTA16     16-bit column offsets from one reference column per block of
  *              rows, streamed through LDS (column-index compression, class MB).
- *  XBLOCK_LDS  x staged in LDS per row panel and column window (class CML;
- *              replaces software prefetching of x).
+ *  XBLOCK_LDS  x blocking (class CML; replaces software prefetching of x):
+ *              the columns are cut into 8 slices, one per XCD, each stored as
+ *              its own CSR and run as merge-path tiles on that XCD, so the
+ *              slice of x it gathers stays in the XCD's L2; products are
+ *              staged in LDS; 8 partial y vectors are summed in slice order.
  *  SHORT_ROW   rows streamed through LDS in chunks of 2048 nonzeros with one
  *              thread summing each row (short rows: inner-loop overhead). */
 typedef enum {
@@ -162,8 +165,7 @@ spmv_status_t spmv_execute(spmv_plan_t plan, const void *d_x, void *d_y,
 
 /* Force a variant; builds its format (synchronous).  SPMV_ERR_INFEASIBLE if
  * the matrix cannot use it (DELTA16: a block of rows (256 x R, else 256)
- * spans more than 65536 columns;
- * XBLOCK_LDS: the x windows staged for all panels exceed NNZ elements). */
+ * spans more than 65536 columns). */
 spmv_status_t spmv_set_variant(spmv_plan_t plan, int32_t variant);
 spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
 
@@ -172,7 +174,8 @@ spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
 
 /* Algorithmic bytes of one SpMV with `variant`: 4(N+1) + ib NNZ + vb NNZ +
  * xb M + yb N, plus 4 bytes per block reference column for DELTA16 (ib = 2
- * there, else 4). */
+ * there, else 4), plus 7 more row-pointer arrays and 8 partial y vectors
+ * written and read back for XBLOCK_LDS. */
 spmv_status_t spmv_bytes(spmv_plan_t plan, int32_t variant, int64_t *bytes);
 
 /* Median and minimum time of `reps` executions of `variant` (hipEvents on
@@ -184,16 +187,17 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
 
 /* Plan parameters and derived arrays, for tests and tools.
  * Keys: 0 variant, 1 csr_vector width, 2 short_row/delta16 rows per block,
- * 3 merge-path items per tile, 4 merge-path tiles, 5 x-block rows per panel,
- * 6 x-block panels, 7 x-block columns per LDS chunk, 8 profiling partitions,
- * 9 delta16 feasible, 10 x-block feasible, 11 delta16 rows per block. */
+ * 3 merge-path items per tile, 4 merge-path tiles, 5 x-block columns per
+ * slice, 6 x-block tiles (all slices), 7 x-block slices, 8 profiling
+ * partitions, 9 delta16 feasible, 10 x-block feasible (always 1),
+ * 11 delta16 rows per block. */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:
  * 0 delta16 block reference columns int32[ceil(N / rows per block)],
  * 1 delta16 offsets uint16[NNZ], 2 merge-path split rows int32[tiles+1],
- * 3 merge-path split nonzeros int32[tiles+1], 4 x-block
- * window starts int32[panels], 5 x-block window ends int32[panels],
+ * 3 merge-path split nonzeros int32[tiles+1], 4 x-block slice row
+ * pointers int32[8 (N+1)], 5 x-block slice-major column indices int32[NNZ],
  * 6 profiling partition bounds int32[parts+1].  `bytes` must equal the
  * array size. */
 spmv_status_t spmv_plan_copy_format(spmv_plan_t plan, int32_t which,

@@ -10,7 +10,7 @@
   tiles (Merrill and Garland, SC'16): the merge of the row-end list
   ``rowptr[1..N]`` with the nonzero indices ``0..NNZ-1``, where nonzero j is
   taken before row end i exactly when ``j < rowptr[i+1]``.
-* ``panel_windows_ref`` per-panel column windows for LDS-staged x blocks.
+* ``slice_csr_ref``  the column-sliced CSR of x blocking (one slice per XCD).
 * ``partition_ref``  the paper's default static partition: contiguous row
   ranges with (as nearly as possible) equal nonzeros (Section 3.2.1).
 * ``to_bf16_bits_ref`` / ``to_f32_ref``  value rounding for the precision
@@ -103,28 +103,30 @@ def merge_search_ref(rowptr, items_per_tile: int):
     return si.astype(np.int32), sj.astype(np.int32)
 
 
-def panel_windows_ref(rowptr, colind, rows_per_panel: int):
-    """(cmin int32[P], cmax int32[P]): column window of each row panel.
+def slice_csr_ref(rowptr, colind, n_cols: int, slices: int = 8):
+    """Column-sliced CSR for x blocking.
 
-    A panel with no nonzeros gets the empty window (0, -1).
+    Columns are cut into ``slices`` slices of width ceil(M / slices) (column c
+    lies in slice c // width).  Returns (rowptrs int32[slices, N+1],
+    colind int32[NNZ]) where slice s keeps, row by row, the nonzeros of A whose
+    columns fall in it, and the column array holds slice 0's nonzeros, then
+    slice 1's, and so on.
     """
     rowptr = np.asarray(rowptr, dtype=np.int64)
     colind = np.asarray(colind, dtype=np.int64)
     n = len(rowptr) - 1
-    P = (n + rows_per_panel - 1) // rows_per_panel
-    cmin = np.zeros(P, dtype=np.int64)
-    cmax = np.full(P, -1, dtype=np.int64)
-    for p in range(P):
-        r0, r1 = p * rows_per_panel, min(n, (p + 1) * rows_per_panel)
-        lo, hi = None, None
-        for r in range(r0, r1):
-            a, b = rowptr[r], rowptr[r + 1]
-            if a < b:
-                lo = colind[a] if lo is None else min(lo, colind[a])
-                hi = colind[b - 1] if hi is None else max(hi, colind[b - 1])
-        if lo is not None:
-            cmin[p], cmax[p] = lo, hi
-    return cmin.astype(np.int32), cmax.astype(np.int32)
+    width = (n_cols + slices - 1) // slices if n_cols > 0 else 1
+    rps = np.zeros((slices, n + 1), dtype=np.int64)
+    parts = [[] for _ in range(slices)]
+    for i in range(n):
+        row = colind[rowptr[i]:rowptr[i + 1]]
+        sl = row // width
+        for s in range(slices):
+            seg = row[sl == s]
+            parts[s].append(seg)
+            rps[s, i + 1] = rps[s, i] + len(seg)
+    cols = [np.concatenate(p) if p else np.zeros(0, np.int64) for p in parts]
+    return rps.astype(np.int32), np.concatenate(cols).astype(np.int32)
 
 
 def partition_ref(rowptr, parts: int):

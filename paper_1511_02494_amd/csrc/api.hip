@@ -228,25 +228,65 @@ spmv_status_t check_d16(spmv_plan *P) {
 bool d16_feasible(const spmv_plan *P) { return P->d16_feasible; }
 
 // ------------------------------------------------------------ formats
-spmv_status_t build_xblock(spmv_plan *P) {
-    if (P->xb_built) return SPMV_OK;
-    const int64_t panels = (P->n + P->xb_rows - 1) / P->xb_rows;
-    P->xb_panels = panels;
-    SPMV_TRY(P->xb_cmin.alloc((size_t)(panels > 0 ? panels : 1) * 4));
-    SPMV_TRY(P->xb_cmax.alloc((size_t)(panels > 0 ? panels : 1) * 4));
-    unsigned long long total = 0;
-    if (panels > 0) {
-        SPMV_HIP(launch_panel_windows(*P, P->xb_rows, P->xb_cmin.as<int32_t>(),
-                                      P->xb_cmax.as<int32_t>(), panels, S(P)));
-        auto *d_sum = scr<unsigned long long>(P, kOffSum);
-        SPMV_HIP(launch_window_sum(P->xb_cmin.as<int32_t>(), P->xb_cmax.as<int32_t>(), panels,
-                                   d_sum, S(P)));
-        SPMV_HIP(hipMemcpyAsync(P->h_pinned, d_sum, 8, hipMemcpyDeviceToHost, S(P)));
+// x blocking: split the columns into kSlices slices (one per XCD) and store
+// each slice as its own CSR (rowptr per slice, slice-major colind/val), with
+// merge-path tiles per slice and one partial y per slice.
+spmv_status_t build_xslices(spmv_plan *P) {
+    if (P->xs_built) return SPMV_OK;
+    const int64_t n = P->n, nnz = P->nnz;
+    const int64_t cw = P->m > 0 ? (P->m + kSlices - 1) / kSlices : 1;
+    P->xs_width = cw;
+    SPMV_TRY(P->xs_rowptr.alloc((size_t)kSlices * (n + 1) * 4));
+    SPMV_TRY(P->xs_colind.alloc((size_t)(nnz > 0 ? nnz : 1) * 4 + 16));
+    SPMV_TRY(P->xs_val.alloc((size_t)(nnz > 0 ? nnz : 1) * vbytes(P->dtype) + 16));
+    SPMV_TRY(P->xs_y.alloc((size_t)kSlices * (n > 0 ? n : 1) * xbytes(P->dtype)));
+    int64_t snnz[kSlices] = {0};
+    if (n > 0) {
+        DevBuf lens, tmp;
+        SPMV_TRY(lens.alloc((size_t)kSlices * n * 4));
+        SPMV_HIP(launch_slice_count(*P, cw, lens.as<int32_t>(), S(P)));
+        size_t need = 0;
+        SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>(), P->xs_rowptr.as<int32_t>(), n,
+                                           nullptr, 0, S(P), &need));
+        SPMV_TRY(tmp.alloc(need));
+        for (int k = 0; k < kSlices; ++k)
+            SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>() + (size_t)k * n,
+                                               P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1),
+                                               n, tmp.p, tmp.bytes, S(P), nullptr));
+        int32_t *h = static_cast<int32_t *>(P->h_pinned);
+        for (int k = 0; k < kSlices; ++k)
+            SPMV_HIP(hipMemcpyAsync(h + k, P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1) + n, 4,
+                                    hipMemcpyDeviceToHost, S(P)));
         SPMV_TRY(sync(P));
-        memcpy(&total, P->h_pinned, 8);
+        for (int k = 0; k < kSlices; ++k) snnz[k] = h[k];
     }
-    P->xb_feasible = (int64_t)total <= P->nnz;
-    P->xb_built = true;
+    SliceOffsets so;
+    int64_t off = 0, toff = 0;
+    for (int k = 0; k < kSlices; ++k) {
+        so.off[k] = off;
+        P->xs_nnz_off[k] = off;
+        off += snnz[k];
+        P->xs_tiles[k] = n > 0 ? (n + snnz[k] + kMergeTile - 1) / kMergeTile : 0;
+        P->xs_tile_off[k] = toff;
+        toff += P->xs_tiles[k];
+    }
+    if (off != nnz) return fail(SPMV_ERR_HIP, "x-block slices hold %lld of %lld nonzeros",
+                                (long long)off, (long long)nnz);
+    SPMV_TRY(P->xs_srow.alloc((size_t)(toff + kSlices) * 4));
+    SPMV_TRY(P->xs_snnz.alloc((size_t)(toff + kSlices) * 4));
+    SPMV_TRY(P->xs_crow.alloc((size_t)(toff > 0 ? toff : 1) * 4));
+    SPMV_TRY(P->xs_cval.alloc((size_t)(toff > 0 ? toff : 1) * 8));
+    if (n > 0) {
+        SPMV_HIP(launch_slice_scatter(*P, P->xs_rowptr.as<int32_t>(), so, P->xs_colind.as<int32_t>(),
+                                      P->xs_val.p, S(P)));
+        for (int k = 0; k < kSlices; ++k)
+            SPMV_HIP(launch_merge_splits(P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1), n, snnz[k],
+                                         P->xs_srow.as<int32_t>() + P->xs_tile_off[k] + k,
+                                         P->xs_snnz.as<int32_t>() + P->xs_tile_off[k] + k,
+                                         P->xs_tiles[k], S(P)));
+        SPMV_TRY(sync(P));
+    }
+    P->xs_built = true;
     return SPMV_OK;
 }
 
@@ -277,18 +317,14 @@ spmv_status_t build_format(spmv_plan *P, int v) {
         SPMV_TRY(P->mp_split_nnz.alloc((size_t)(tiles + 1) * 4));
         SPMV_TRY(P->mp_carry_row.alloc((size_t)(tiles > 0 ? tiles : 1) * 4));
         SPMV_TRY(P->mp_carry_val.alloc((size_t)(tiles > 0 ? tiles : 1) * 8));
-        SPMV_HIP(launch_merge_splits(*P, P->mp_split_row.as<int32_t>(),
+        SPMV_HIP(launch_merge_splits(P->rowptr, P->n, P->nnz, P->mp_split_row.as<int32_t>(),
                                      P->mp_split_nnz.as<int32_t>(), tiles, S(P)));
         SPMV_TRY(sync(P));
         P->mp_built = true;
         return SPMV_OK;
     }
     case V_XBLOCK_LDS:
-        SPMV_TRY(build_xblock(P));
-        if (!P->xb_feasible)
-            return fail(SPMV_ERR_INFEASIBLE,
-                        "xblock_lds: the column windows of the row panels exceed NNZ");
-        return SPMV_OK;
+        return build_xslices(P);
     default:
         return fail(SPMV_ERR_ARG, "unknown variant %d", v);
     }
@@ -296,11 +332,9 @@ spmv_status_t build_format(spmv_plan *P, int v) {
 
 spmv_status_t feasible_mask(spmv_plan *P, uint32_t *bits) {
     SPMV_TRY(check_d16(P));
-    SPMV_TRY(build_xblock(P));
     uint32_t b = (1u << V_CSR_SCALAR) | (1u << V_CSR_VECTOR) | (1u << V_MERGE_PATH) |
-                 (1u << V_SHORT_ROW);
+                 (1u << V_SHORT_ROW) | (1u << V_XBLOCK_LDS);
     if (d16_feasible(P)) b |= 1u << V_DELTA16;
-    if (P->xb_feasible) b |= 1u << V_XBLOCK_LDS;
     *bits = b;
     return SPMV_OK;
 }
@@ -620,8 +654,6 @@ spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
     const double avg = n_rows > 0 ? (double)nnz / (double)n_rows : 0.0;
     P->vec_width = pow2_ceil(avg, 2, 64);
     P->rs_rows = pow2_floor((double)kChunk / (kBlock * (avg > 1e-9 ? avg : 1e-9)), 1, kRowStreamMaxR);
-    P->xb_rows = pow2_floor(32768.0 / (avg > 1.0 ? avg : 1.0), 256, kXbMaxRows);
-    P->xb_width = P->vec_width;
     P->parts = P->num_cus * 8;
     if (!(flags & SPMV_SKIP_VALIDATE)) {
         uint64_t *f = scr<uint64_t>(P, kOffFlags);
@@ -698,6 +730,8 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
         SPMV_TRY(check_d16(P));
         extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
     }
+    if (v == V_XBLOCK_LDS)  // slice row pointers, partial y written and read back
+        extra = 4 * (kSlices - 1) * (P->n + 1) + 2 * kSlices * xb * P->n;
     *bytes = 4 * (P->n + 1) + (ib + vb) * P->nnz + xb * P->m + xb * P->n + extra;
     return SPMV_OK;
 }
@@ -727,13 +761,13 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
     case 2: *value = P->rs_rows * kBlock; break;
     case 3: *value = kMergeTile; break;
     case 4: *value = (P->n + P->nnz + kMergeTile - 1) / kMergeTile; break;
-    case 5: *value = P->xb_rows; break;
-    case 6: *value = (P->n + P->xb_rows - 1) / P->xb_rows; break;
-    case 7: *value = kXbChunkBytes / xbytes(P->dtype); break;
+    case 5: *value = P->m > 0 ? (P->m + kSlices - 1) / kSlices : 1; break;
+    case 6: SPMV_TRY(build_xslices(P)); *value = P->xs_tile_off[kSlices - 1] + P->xs_tiles[kSlices - 1]; break;
+    case 7: *value = kSlices; break;
     case 8: *value = P->parts; break;
     case 9: SPMV_TRY(check_d16(P)); *value = d16_feasible(P); break;
     case 11: SPMV_TRY(check_d16(P)); *value = P->d16_rows; break;
-    case 10: SPMV_TRY(build_xblock(P)); *value = P->xb_feasible; break;
+    case 10: *value = 1; break;
     default: return fail(SPMV_ERR_ARG, "unknown key %d", key);
     }
     return SPMV_OK;
@@ -756,9 +790,9 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
         want = 4 * (P->mp_tiles + 1);
         break;
     case 4: case 5:
-        SPMV_TRY(build_xblock(P));
-        src = which == 4 ? P->xb_cmin.p : P->xb_cmax.p;
-        want = 4 * P->xb_panels;
+        SPMV_TRY(build_xslices(P));
+        src = which == 4 ? P->xs_rowptr.p : P->xs_colind.p;
+        want = which == 4 ? 4 * kSlices * (P->n + 1) : 4 * P->nnz;
         break;
     case 6:
         if (!P->part_built) {

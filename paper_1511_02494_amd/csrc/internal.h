@@ -20,8 +20,7 @@ constexpr int kChunk = kBlock * kRunLen;  // nonzeros staged per LDS chunk
 constexpr int kRowStreamMaxR = 8;     // rows per thread (max) in short_row / delta16
 constexpr int kMergeIpt = 8;          // merge-path items per thread
 constexpr int kMergeTile = kBlock * kMergeIpt;
-constexpr int kXbMaxRows = 1024;      // x-block panel height (max)
-constexpr int kXbChunkBytes = 32768;  // LDS bytes of staged x per chunk
+constexpr int kSlices = 8;            // x-block column slices (one per XCD)
 constexpr int kKahanMinLen = 257;     // FP32 rows longer than 256 use Kahan sums
 constexpr int kLineBytes = 128;       // cache line assumed by the miss feature
 constexpr int64_t kLlcBytes = 256ll << 20;
@@ -61,8 +60,8 @@ inline int vbytes(int dtype) { return dtype == SPMV_F64 ? 8 : dtype == SPMV_F32 
 inline int xbytes(int dtype) { return dtype == SPMV_F64 ? 8 : 4; }
 
 // ---------------------------------------------------------------- plan
-struct FeatureRecord {  // exact integer accumulators reduced on the device
-    uint64_t w[16];
+struct SliceOffsets {  // first nonzero of each column slice in the slice-major arrays
+    int64_t off[kSlices];
 };
 
 }  // namespace spmvsel
@@ -91,8 +90,6 @@ struct spmv_plan {
     // launch parameters
     int vec_width = 2;           // csr_vector sub-wave width
     int rs_rows = 1;             // rows per thread in the streaming kernels
-    int xb_rows = 256;           // x-block panel height
-    int xb_width = 2;            // x-block sub-wave width
     int parts = 2048;            // profiling partitions
 
     // derived formats (lazy)
@@ -102,9 +99,11 @@ struct spmv_plan {
     bool mp_built = false;
     int64_t mp_tiles = 0;
     spmvsel::DevBuf mp_split_row, mp_split_nnz, mp_carry_row, mp_carry_val;
-    bool xb_built = false, xb_feasible = false;
-    int64_t xb_panels = 0;
-    spmvsel::DevBuf xb_cmin, xb_cmax;
+    bool xs_built = false;       // x blocking: column slices, one per XCD
+    int64_t xs_width = 0;        // columns per slice
+    int64_t xs_nnz_off[spmvsel::kSlices] = {0}, xs_tiles[spmvsel::kSlices] = {0},
+            xs_tile_off[spmvsel::kSlices] = {0};
+    spmvsel::DevBuf xs_rowptr, xs_colind, xs_val, xs_srow, xs_snnz, xs_crow, xs_cval, xs_y;
     bool part_built = false;
     spmvsel::DevBuf part_bounds;
 
@@ -135,16 +134,17 @@ hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16
                                  hipStream_t s);
 hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t panels,
                            unsigned long long *d_max, hipStream_t s);
-hipError_t launch_merge_splits(const spmv_plan &P, int32_t *srow, int32_t *snnz, int64_t tiles,
-                               hipStream_t s);
+hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,
+                               int32_t *snnz, int64_t tiles, hipStream_t s);
+hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, int32_t *lens, hipStream_t s);
+hipError_t launch_slice_scatter(const spmv_plan &P, const int32_t *srp, const SliceOffsets &so,
+                                int32_t *xci, void *xval, hipStream_t s);
 hipError_t launch_panel_windows(const spmv_plan &P, int rows_per_panel, int32_t *cmin,
                                 int32_t *cmax, int64_t panels, hipStream_t s);
 hipError_t launch_partition(const int32_t *rowptr, int64_t n, int parts, int32_t *bounds,
                             hipStream_t s);
 hipError_t launch_widen(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
 hipError_t launch_row_columns(const spmv_plan &P, int32_t *out, hipStream_t s);
-hipError_t launch_window_sum(const int32_t *cmin, const int32_t *cmax, int64_t panels,
-                             unsigned long long *d_sum, hipStream_t s);
 hipError_t launch_quantize(const double *in, void *out, int64_t n, int to, hipStream_t s);
 
 // profiling micro-benchmarks (k_profile.hip)

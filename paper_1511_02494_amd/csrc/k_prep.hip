@@ -80,11 +80,92 @@ __global__ __launch_bounds__(kBlock) void k_merge_splits(int64_t n, int64_t nnz,
     snnz[t] = (int32_t)(d - lo);
 }
 
-hipError_t launch_merge_splits(const spmv_plan &P, int32_t *srow, int32_t *snnz, int64_t tiles,
-                               hipStream_t s) {
+hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,
+                               int32_t *snnz, int64_t tiles, hipStream_t s) {
     const int64_t g = (tiles + 1 + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_merge_splits, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, P.nnz, tiles,
-                       P.rowptr, srow, snnz);
+    hipLaunchKernelGGL(k_merge_splits, dim3((unsigned)g), dim3(kBlock), 0, s, n, nnz, tiles,
+                       rowptr, srow, snnz);
+    return hipGetLastError();
+}
+
+// ---- x blocking: column slices of width cw (slice of column c = c / cw).
+// Per row, the number of its nonzeros in each slice (columns are sorted, so
+// the slice boundaries are found by binary search inside the row).
+__global__ __launch_bounds__(kBlock) void k_slice_count(int64_t n, int64_t cw,
+                                                        const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        int32_t *__restrict__ lens) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int32_t b = rp[i + 1];
+        int32_t pos = rp[i];
+        for (int s = 0; s < kSlices - 1; ++s) {
+            const int64_t bound = (s + 1) * cw;
+            int32_t lo = pos, hi = b;  // first k in [pos, b) with ci[k] >= bound
+            while (lo < hi) {
+                const int32_t mid = lo + ((hi - lo) >> 1);
+                if ((int64_t)ci[mid] < bound) lo = mid + 1; else hi = mid;
+            }
+            lens[(int64_t)s * n + i] = lo - pos;
+            pos = lo;
+        }
+        lens[(int64_t)(kSlices - 1) * n + i] = b - pos;
+    }
+}
+
+// Copy every row's slice segments into the slice-major arrays.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_slice_scatter(int64_t n, const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ ci,
+                                                          const V *__restrict__ val,
+                                                          const int32_t *__restrict__ srp,
+                                                          SliceOffsets so,
+                                                          int32_t *__restrict__ xci,
+                                                          V *__restrict__ xval) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        int32_t pos = rp[i];
+        for (int s = 0; s < kSlices; ++s) {
+            const int32_t *r = srp + (int64_t)s * (n + 1);
+            const int32_t a = r[i], cnt = r[i + 1] - a;
+            const int64_t dst = so.off[s] + a;
+            for (int32_t j = 0; j < cnt; ++j) {
+                xci[dst + j] = ci[pos + j];
+                xval[dst + j] = val[pos + j];
+            }
+            pos += cnt;
+        }
+    }
+}
+
+hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, int32_t *lens, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    int64_t g = (P.n + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_slice_count, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, cw, P.rowptr,
+                       P.colind, lens);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_scatter(const spmv_plan &P, const int32_t *srp, const SliceOffsets &so,
+                                int32_t *xci, void *xval, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    int64_t g = (P.n + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    switch (P.dtype) {
+    case SPMV_F64:
+        hipLaunchKernelGGL(k_slice_scatter<double>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n,
+                           P.rowptr, P.colind, (const double *)P.val, srp, so, xci, (double *)xval);
+        break;
+    case SPMV_F32:
+        hipLaunchKernelGGL(k_slice_scatter<float>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n,
+                           P.rowptr, P.colind, (const float *)P.val, srp, so, xci, (float *)xval);
+        break;
+    default:
+        hipLaunchKernelGGL(k_slice_scatter<uint16_t>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n,
+                           P.rowptr, P.colind, (const uint16_t *)P.val, srp, so, xci,
+                           (uint16_t *)xval);
+    }
     return hipGetLastError();
 }
 
@@ -125,28 +206,6 @@ hipError_t launch_panel_windows(const spmv_plan &P, int H, int32_t *cmin, int32_
     const int64_t g = (panels * 64 + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_panel_windows, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, H, panels,
                        P.rowptr, P.colind, cmin, cmax);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(kBlock) void k_window_sum(const int32_t *__restrict__ cmin,
-                                                       const int32_t *__restrict__ cmax,
-                                                       int64_t panels,
-                                                       unsigned long long *sum) {
-    unsigned long long t = 0;
-    for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < panels;
-         p += (int64_t)gridDim.x * kBlock)
-        t += (unsigned long long)(cmax[p] - cmin[p] + 1);
-    if (t) atomicAdd(sum, t);
-}
-
-hipError_t launch_window_sum(const int32_t *cmin, const int32_t *cmax, int64_t panels,
-                             unsigned long long *d_sum, hipStream_t s) {
-    hipError_t e = hipMemsetAsync(d_sum, 0, sizeof(unsigned long long), s);
-    if (e != hipSuccess) return e;
-    int64_t g = (panels + kBlock - 1) / kBlock;
-    if (g < 1) g = 1;
-    if (g > 1024) g = 1024;
-    hipLaunchKernelGGL(k_window_sum, dim3((unsigned)g), dim3(kBlock), 0, s, cmin, cmax, panels, d_sum);
     return hipGetLastError();
 }
 

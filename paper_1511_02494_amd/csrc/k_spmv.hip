@@ -180,31 +180,38 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
 // threads of the tile (in thread order); the partial row left at the tile's
 // end is stored as the tile's carry and added by k_merge_fixup in tile order.
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_merge_path(
-    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
-    typename VT<V>::A *__restrict__ y, const int32_t *__restrict__ srow,
-    const int32_t *__restrict__ snnz, int32_t *__restrict__ carry_row,
-    typename VT<V>::A *__restrict__ carry_val) {
+struct MergeSmem {
     using A = typename VT<V>::A;
-    __shared__ int32_t s_end[kMergeTile + 1];
-    __shared__ A s_prod[kMergeTile];
-    __shared__ int32_t s_crow[kBlock];
-    __shared__ A s_cval[kBlock];
-    constexpr bool F32 = is_f32<A>();
+    int32_t end[kMergeTile + 1];
+    A prod[kMergeTile];
+    int32_t crow[kBlock];
+    A cval[kBlock];
+};
 
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+template <class V>
+__device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64_t n,
+                                           const int32_t *__restrict__ rp,
+                                           const int32_t *__restrict__ ci,
+                                           const V *__restrict__ val,
+                                           const typename VT<V>::A *__restrict__ x,
+                                           typename VT<V>::A *__restrict__ y,
+                                           const int32_t *__restrict__ srow,
+                                           const int32_t *__restrict__ snnz,
+                                           int32_t *__restrict__ carry_row,
+                                           typename VT<V>::A *__restrict__ carry_val) {
+    using A = typename VT<V>::A;
+    constexpr bool F32 = is_f32<A>();
     const int32_t i0 = srow[tile], j0 = snnz[tile];
     const int32_t i1 = srow[tile + 1], j1 = snnz[tile + 1];
     const int nr = i1 - i0, nz = j1 - j0;
 
     for (int r = threadIdx.x; r <= nr; r += kBlock) {
         const int64_t row = (int64_t)i0 + r;
-        s_end[r] = row < n ? rp[row + 1] : INT32_MAX;
+        sm.end[r] = row < n ? rp[row + 1] : INT32_MAX;
     }
     for (int q = threadIdx.x; q < nz; q += kBlock) {
         const int32_t kk = j0 + q;
-        s_prod[q] = VT<V>::cvt(ld_nt(val + kk)) * x[ld_nt(ci + kk)];
+        sm.prod[q] = VT<V>::cvt(ld_nt(val + kk)) * x[ld_nt(ci + kk)];
     }
     __syncthreads();
 
@@ -214,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_path(
     int lo = d - nz > 0 ? d - nz : 0, hi = d < nr ? d : nr;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (s_end[mid] <= j0 + d - mid - 1) lo = mid + 1; else hi = mid;
+        if (sm.end[mid] <= j0 + d - mid - 1) lo = mid + 1; else hi = mid;
     }
     int xi = lo, yj = d - lo;
 
@@ -223,8 +230,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_path(
     A head_val = A(0);
     const int dend = (d + kMergeIpt) < total ? (d + kMergeIpt) : total;
     for (int it = d; it < dend; ++it) {
-        if (yj < nz && j0 + yj < s_end[xi]) {
-            run.add(s_prod[yj], F32);
+        if (yj < nz && j0 + yj < sm.end[xi]) {
+            run.add(sm.prod[yj], F32);
             ++yj;
         } else {
             if (head_row < 0) {
@@ -237,113 +244,119 @@ __global__ __launch_bounds__(kBlock) void k_merge_path(
             ++xi;
         }
     }
-    s_crow[threadIdx.x] = xi;  // row (local) still open at this thread's end
-    s_cval[threadIdx.x] = run.s;
+    sm.crow[threadIdx.x] = xi;  // row (local) still open at this thread's end
+    sm.cval[threadIdx.x] = run.s;
     __syncthreads();
 
     if (head_row >= 0) {
         int t0 = threadIdx.x;
-        while (t0 > 0 && s_crow[t0 - 1] == head_row) --t0;
+        while (t0 > 0 && sm.crow[t0 - 1] == head_row) --t0;
         Sum<A> c;
-        for (int t = t0; t < (int)threadIdx.x; ++t) c.add(s_cval[t], F32);
+        for (int t = t0; t < (int)threadIdx.x; ++t) c.add(sm.cval[t], F32);
         c.add(head_val, F32);
         y[i0 + head_row] = c.s;
     }
     if (threadIdx.x == kBlock - 1) {
         // partial sums of row i1 accumulated in this tile (continues later)
         int t0 = kBlock - 1;
-        while (t0 > 0 && s_crow[t0 - 1] == nr) --t0;
+        while (t0 > 0 && sm.crow[t0 - 1] == nr) --t0;
         Sum<A> c;
-        if (s_crow[kBlock - 1] == nr)
-            for (int t = t0; t < kBlock; ++t) c.add(s_cval[t], F32);
+        if (sm.crow[kBlock - 1] == nr)
+            for (int t = t0; t < kBlock; ++t) c.add(sm.cval[t], F32);
         carry_row[tile] = i1;
         carry_val[tile] = c.s;
     }
+}
+
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_merge_path(
+    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
+    typename VT<V>::A *__restrict__ y, const int32_t *__restrict__ srow,
+    const int32_t *__restrict__ snnz, int32_t *__restrict__ carry_row,
+    typename VT<V>::A *__restrict__ carry_val) {
+    __shared__ MergeSmem<V> sm;
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    merge_tile<V>(sm, tile, n, rp, ci, val, x, y, srow, snnz, carry_row, carry_val);
 }
 
 // Adds the carries of consecutive tiles that end inside the same row, in
 // tile order, to that row (the tile finishing the row already wrote its
 // own part).  One thread per tile; only the first tile of a run works.
 template <class A>
-__global__ __launch_bounds__(kBlock) void k_merge_fixup(int64_t n, int64_t tiles,
-                                                        const int32_t *__restrict__ carry_row,
-                                                        const A *__restrict__ carry_val,
-                                                        A *__restrict__ y) {
-    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+__device__ __forceinline__ void merge_fixup_one(int64_t t, int64_t n, int64_t tiles,
+                                                const int32_t *__restrict__ carry_row,
+                                                const A *__restrict__ carry_val,
+                                                A *__restrict__ y) {
     if (t >= tiles) return;
     const int32_t row = carry_row[t];
     if (row >= n) return;
     if (t > 0 && carry_row[t - 1] == row) return;
     Sum<A> c;
-    int64_t u = t;
-    for (; u < tiles && carry_row[u] == row; ++u) c.add(carry_val[u], is_f32<A>());
-    // the row ends in tile u (the tile that emitted it)
+    for (int64_t u = t; u < tiles && carry_row[u] == row; ++u) c.add(carry_val[u], is_f32<A>());
     y[row] = y[row] + c.s;
 }
 
-// ============================================================ x-block LDS
-// Row panels of H rows; each panel's x window [cmin, cmax] is staged into
-// LDS in chunks of CB columns.  For each chunk, a sub-wavefront of W lanes
-// per row consumes the row's nonzeros whose columns fall in the chunk
-// (columns are sorted, so they are the next ones after the row's cursor),
-// gathering x from LDS; the chunk's partial is butterfly-summed and added
-// to the row's LDS accumulator by one lane, chunks in increasing order.
-template <class V, int W>
-__global__ __launch_bounds__(kBlock) void k_xblock(
-    int64_t n, int H, int CB, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
-    typename VT<V>::A *__restrict__ y, const int32_t *__restrict__ cmin_a,
-    const int32_t *__restrict__ cmax_a) {
-    using A = typename VT<V>::A;
-    extern __shared__ unsigned char smem[];
-    A *xs = reinterpret_cast<A *>(smem);                 // CB
-    A *yacc = xs + CB;                                   // H
-    int32_t *cur = reinterpret_cast<int32_t *>(yacc + H);  // H
-    int32_t *rend = cur + H;                             // H
-    constexpr int NS = kBlock / W;
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_merge_fixup(int64_t n, int64_t tiles,
+                                                        const int32_t *__restrict__ carry_row,
+                                                        const A *__restrict__ carry_val,
+                                                        A *__restrict__ y) {
+    merge_fixup_one<A>(blockIdx.x * (int64_t)kBlock + threadIdx.x, n, tiles, carry_row, carry_val, y);
+}
 
-    const int64_t p = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t r0 = p * H;
-    const int nrows = (int)((n - r0) < H ? (n - r0) : H);
-    const int32_t cmin = cmin_a[p], cmax = cmax_a[p];
-    for (int r = threadIdx.x; r < nrows; r += kBlock) {
-        cur[r] = rp[r0 + r];
-        rend[r] = rp[r0 + r + 1];
-        yacc[r] = A(0);
+// ============================================================ x blocking
+// The column range is cut into kSlices equal slices, one per XCD.  Slice s
+// is a CSR matrix of its own (all rows, the nonzeros whose columns fall in
+// the slice); workgroup b runs on XCD b mod 8 and processes a merge-path tile
+// of slice b mod 8, so the part of x a slice gathers (at most 2 MB for the
+// largest workloads here) stays in that XCD's 4 MB L2 instead of being
+// fetched line by line from the Infinity Cache.  Each slice writes a partial
+// y; k_slice_sum adds the partials in slice order.
+template <class A>
+struct SliceTable {
+    const int32_t *rp[kSlices];
+    const int32_t *srow[kSlices];
+    const int32_t *snnz[kSlices];
+    int32_t *crow[kSlices];
+    A *cval[kSlices];
+    A *y[kSlices];
+    int64_t off[kSlices];
+    int64_t tiles[kSlices];
+};
+
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_merge_slices(int64_t n, const int32_t *__restrict__ ci,
+                                                         const V *__restrict__ val,
+                                                         const typename VT<V>::A *__restrict__ x,
+                                                         SliceTable<typename VT<V>::A> T) {
+    __shared__ MergeSmem<V> sm;
+    const int s = blockIdx.x % kSlices;
+    const int64_t tile = blockIdx.x / kSlices;
+    if (tile >= T.tiles[s]) return;
+    merge_tile<V>(sm, tile, n, T.rp[s], ci + T.off[s], val + T.off[s], x, T.y[s], T.srow[s],
+                  T.snnz[s], T.crow[s], T.cval[s]);
+}
+
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_merge_fixup_slices(int64_t n, int64_t maxt,
+                                                               SliceTable<A> T) {
+    const int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const int s = (int)(g / (maxt > 0 ? maxt : 1));
+    if (s >= kSlices) return;
+    merge_fixup_one<A>(g % maxt, n, T.tiles[s], T.crow[s], T.cval[s], T.y[s]);
+}
+
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_slice_sum(int64_t n, SliceTable<A> T,
+                                                      A *__restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        A s = T.y[0][i];
+#pragma unroll
+        for (int k = 1; k < kSlices; ++k) s = s + T.y[k][i];
+        y[i] = s;
     }
-    const int sub = threadIdx.x / W, lane = threadIdx.x & (W - 1);
-    const int wsub = (threadIdx.x & 63) / W;  // sub-wave index inside the wavefront
-    for (int64_t xc = cmin; xc <= cmax; xc += CB) {
-        const int64_t xe = (xc + CB) < ((int64_t)cmax + 1) ? (xc + CB) : ((int64_t)cmax + 1);
-        __syncthreads();
-        for (int64_t c = xc + threadIdx.x; c < xe; c += kBlock) xs[c - xc] = x[c];
-        __syncthreads();
-        for (int r = sub; r < nrows; r += NS) {
-            int32_t k = cur[r];
-            const int32_t ke = rend[r];
-            if (k >= ke) continue;
-            Sum<A> part;
-            while (true) {
-                const int32_t kk = k + lane;
-                bool in = kk < ke;
-                int32_t c = in ? ci[kk] : 0;
-                in = in && c < xe && c >= xc;
-                if (in) part.add(VT<V>::cvt(val[kk]) * xs[c - xc]);
-                const uint64_t bal = __ballot(in);
-                const uint64_t mine = W == 64 ? bal : ((bal >> (wsub * W)) & ((1ull << W) - 1));
-                const int cnt = __popcll(mine);
-                k += cnt;
-                if (cnt < W) break;
-            }
-            const A t = group_sum<W>(part.s);
-            if (lane == 0) {
-                yacc[r] = yacc[r] + t;
-                cur[r] = k;
-            }
-        }
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < nrows; r += kBlock) y[r0 + r] = yacc[r];
 }
 
 // ============================================================ launchers
@@ -453,21 +466,31 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
     return by_dtype(P.dtype, [&](auto tag) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
         using A = typename VT<V>::A;
-        const int H = P.xb_rows;
-        const int CB = kXbChunkBytes / (int)sizeof(A);
-        const size_t shm = (size_t)CB * sizeof(A) + (size_t)H * (sizeof(A) + 8);
-        const unsigned g = (unsigned)P.xb_panels;
-#define SPMV_XB(WW)                                                                          \
-    case WW:                                                                                 \
-        hipLaunchKernelGGL((k_xblock<V, WW>), dim3(g), dim3(kBlock), shm, s, P.n, H, CB,     \
-                           P.rowptr, P.colind, (const V *)P.val, (const A *)x, (A *)y,       \
-                           P.xb_cmin.as<int32_t>(), P.xb_cmax.as<int32_t>());               \
-        break;
-        switch (P.xb_width) {
-            SPMV_XB(2) SPMV_XB(4) SPMV_XB(8) SPMV_XB(16) SPMV_XB(32) SPMV_XB(64)
-        default: return hipErrorInvalidValue;
+        SliceTable<A> T;
+        int64_t maxt = 0;
+        for (int k = 0; k < kSlices; ++k) {
+            T.rp[k] = P.xs_rowptr.as<int32_t>() + (size_t)k * (P.n + 1);
+            T.srow[k] = P.xs_srow.as<int32_t>() + P.xs_tile_off[k] + k;
+            T.snnz[k] = P.xs_snnz.as<int32_t>() + P.xs_tile_off[k] + k;
+            T.crow[k] = P.xs_crow.as<int32_t>() + P.xs_tile_off[k];
+            T.cval[k] = P.xs_cval.as<A>() + P.xs_tile_off[k];
+            T.y[k] = P.xs_y.as<A>() + (size_t)k * P.n;
+            T.off[k] = P.xs_nnz_off[k];
+            T.tiles[k] = P.xs_tiles[k];
+            if (T.tiles[k] > maxt) maxt = T.tiles[k];
         }
-#undef SPMV_XB
+        if (maxt > 0) {
+            hipLaunchKernelGGL(k_merge_slices<V>, dim3((unsigned)(maxt * kSlices)), dim3(kBlock), 0,
+                               s, P.n, P.xs_colind.as<int32_t>(), (const V *)P.xs_val.p,
+                               (const A *)x, T);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const unsigned g = grid_for(maxt * kSlices, kBlock, INT32_MAX);
+            hipLaunchKernelGGL(k_merge_fixup_slices<A>, dim3(g), dim3(kBlock), 0, s, P.n, maxt, T);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        const unsigned g = grid_for(P.n, kBlock, (int64_t)P.num_cus * 16);
+        hipLaunchKernelGGL(k_slice_sum<A>, dim3(g), dim3(kBlock), 0, s, P.n, T, (A *)y);
         return hipGetLastError();
     });
 }

@@ -367,6 +367,58 @@ def measure_inference(features, mask, reps=200):
     return float(np.median(ts))
 
 
+def cmd_sweep(args):
+    """Selector sweep report: the sweep matrices not used for calibration."""
+    recs = [r for r in load_records(args.labels) if args.lo <= r["seed"] < args.hi]
+    theta = S.spmv_get_thresholds()
+    have_model = os.path.exists(args.model)
+    t_inf = 0.0
+    if have_model:
+        S.spmv_model_load(args.model)
+        t_inf = measure_inference(recs[0]["features"], recs[0]["mask"])
+    rows = []
+    for r in recs:
+        t = r["times"]
+        best_v = min((v for v in range(6) if t[v] > 0), key=lambda v: (t[v], v))
+        q = profiling_pick(r, theta)
+        row = dict(seed=r["seed"], name=r["name"], n=r["n"], nnz=r["nnz"], best=S.VARIANTS[best_v],
+                   best_us=t[best_v] * 1e6, best_gbs=r["bytes"][best_v] / t[best_v] * 1e-9,
+                   prof=S.VARIANTS[q], prof_regret=t[q] / t[best_v] - 1,
+                   prof_overhead_spmv=(r["t_features"] + r["t_profile"]) / t[q])
+        if have_model:
+            p = S.spmv_mlp_predict(r["features"], r["mask"])
+            v = q if p["fallback"] else p["variant"]
+            row.update(mlp=S.VARIANTS[v], mlp_regret=t[v] / t[best_v] - 1, fell_back=bool(p["fallback"]),
+                       mlp_overhead_spmv=(r["t_features"] + t_inf
+                                          + (r["t_profile"] if p["fallback"] else 0)) / t[v])
+        f = r["features"]
+        ws = 4 * (r["n"] + 1) + 12 * r["nnz"] + 16 * r["n"]
+        row["bandwidth_bound"] = bool(ws > 2 * 256 * 2 ** 20 and f[10] < 0.05 and f[2] >= 8)
+        rows.append(row)
+    if have_model:
+        S.spmv_model_unload()
+    bw = [x for x in rows if x["bandwidth_bound"]]
+    out = {
+        "matrices": len(rows), "seeds": [args.lo, args.hi], "theta": theta,
+        "profiling_hit5": float(np.mean([x["prof_regret"] <= 0.05 for x in rows])),
+        "profiling_mean_regret": float(np.mean([x["prof_regret"] for x in rows])),
+        "profiling_overhead_spmv_equivs_median": float(np.median([x["prof_overhead_spmv"] for x in rows])),
+        "best_variant_counts": {v: sum(x["best"] == v for x in rows) for v in S.VARIANTS},
+        "best_gbs_median": float(np.median([x["best_gbs"] for x in rows])),
+        "bandwidth_bound_matrices": len(bw),
+        "bandwidth_bound_best_pct_hbm_warm": [round(100 * x["best_gbs"] / 8000, 1) for x in bw],
+    }
+    if have_model:
+        out.update(mlp_hit5=float(np.mean([x["mlp_regret"] <= 0.05 for x in rows])),
+                   mlp_mean_regret=float(np.mean([x["mlp_regret"] for x in rows])),
+                   mlp_overhead_spmv_equivs_median=float(np.median([x["mlp_overhead_spmv"] for x in rows])),
+                   mlp_fallback_rate=float(np.mean([x["fell_back"] for x in rows])))
+    print(json.dumps(out, indent=1))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(dict(summary=out, rows=rows), f, indent=1)
+
+
 def cmd_eval(args):
     recs = load_records(args.test)
     theta = S.spmv_get_thresholds() if args.theta is None else [float(v) for v in args.theta.split(",")]
@@ -402,6 +454,12 @@ def main(argv=None):
     a.add_argument("--lo", type=int, default=1000)
     a.add_argument("--hi", type=int, default=1100)
     a.add_argument("--out", required=True)
+    a = sub.add_parser("sweep")
+    a.add_argument("--labels", required=True)
+    a.add_argument("--model", default=S.DEFAULT_MODEL)
+    a.add_argument("--lo", type=int, default=1100)
+    a.add_argument("--hi", type=int, default=1200)
+    a.add_argument("--out", default=None)
     a = sub.add_parser("eval")
     a.add_argument("--model", required=True)
     a.add_argument("--test", required=True)
@@ -409,7 +467,7 @@ def main(argv=None):
     a.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     {"label": cmd_label, "fit": cmd_fit, "eval": cmd_eval,
-     "calibrate": cmd_calibrate}[args.cmd](args)
+     "calibrate": cmd_calibrate, "sweep": cmd_sweep}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -6,8 +6,8 @@ import pytest
 
 import synth
 import paper_1511_02494_amd as S
-from oracle.encode import (delta16_ref, merge_search_ref, merge_walk_ref, panel_windows_ref,
-                           partition_ref, to_bf16_bits_ref, to_f32_ref)
+from oracle.encode import (delta16_ref, merge_search_ref, merge_walk_ref, partition_ref,
+                           slice_csr_ref, to_bf16_bits_ref, to_f32_ref)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -45,13 +45,12 @@ def test_formats_match_oracle(name, build, m):
     if n + nnz < 200000:
         wi, wj = merge_walk_ref(rp, T)
         assert np.array_equal(wi, si) and np.array_equal(wj, sj)
-    H = S.spmv_plan_query(h, 5)
-    P = S.spmv_plan_query(h, 6)
-    lo, hi = panel_windows_ref(rp, ci, H)
-    assert np.array_equal(S.spmv_plan_copy_format(h, 4, P), lo)
-    assert np.array_equal(S.spmv_plan_copy_format(h, 5, P), hi)
-    feas = int((hi.astype(np.int64) - lo + 1).sum() <= nnz)
-    assert S.spmv_plan_query(h, 10) == feas
+    nsl = S.spmv_plan_query(h, 7)
+    rps, cx = slice_csr_ref(rp, ci, m, nsl)
+    assert np.array_equal(S.spmv_plan_copy_format(h, 4, nsl * (n + 1)), rps.reshape(-1))
+    assert np.array_equal(S.spmv_plan_copy_format(h, 5, nnz), cx)
+    tiles = sum((n + int(r[-1]) + T - 1) // T for r in rps)
+    assert S.spmv_plan_query(h, 6) == tiles
     parts = S.spmv_plan_query(h, 8)
     assert np.array_equal(S.spmv_plan_copy_format(h, 6, parts + 1), partition_ref(rp, parts))
     plan.close()

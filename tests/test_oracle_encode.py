@@ -7,7 +7,7 @@ import pytest
 
 import synth
 from oracle.encode import (bf16_bits_to_f64, delta16_ref, merge_search_ref,
-                           merge_walk_ref, panel_windows_ref, partition_ref,
+                           merge_walk_ref, partition_ref, slice_csr_ref,
                            to_bf16_bits_ref, to_f32_ref)
 
 
@@ -79,17 +79,20 @@ def test_partition_equal_nnz():
         assert rp[b[p]] >= tgt and (b[p] == 0 or rp[b[p] - 1] < tgt)
 
 
-def test_panel_windows_bruteforce():
+@pytest.mark.parametrize("S", [1, 3, 8])
+def test_slice_csr_reassembles_matrix(S):
     for rp, ci, _ in cases(seed=5):
-        H = 7
-        lo, hi = panel_windows_ref(rp, ci, H)
+        m = int(ci.max()) + 1 if len(ci) else 1
+        rps, cx = slice_csr_ref(rp, ci, m, S)
         n = len(rp) - 1
-        for p in range(len(lo)):
-            seg = ci[rp[p * H]:rp[min(n, (p + 1) * H)]]
-            if len(seg):
-                assert lo[p] == seg.min() and hi[p] == seg.max()
-            else:
-                assert (lo[p], hi[p]) == (0, -1)
+        width = (m + S - 1) // S
+        off = np.concatenate([[0], np.cumsum(rps[:, -1])])
+        assert off[-1] == len(ci)
+        for i in range(n):
+            parts = [cx[off[s] + rps[s, i]:off[s] + rps[s, i + 1]] for s in range(S)]
+            for s, p in enumerate(parts):
+                assert np.all(p // width == s)
+            assert np.array_equal(np.concatenate(parts), ci[rp[i]:rp[i + 1]])
 
 
 def bf16_by_fraction(x):
