@@ -190,7 +190,8 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
  * 3 merge-path items per tile, 4 merge-path tiles, 5 x-block columns per
  * slice, 6 x-block tiles (all slices), 7 x-block slices, 8 profiling
  * partitions, 9 delta16 feasible, 10 x-block feasible (always 1),
- * 11 delta16 rows per block. */
+ * 11 delta16 rows per block, 12 x-block per-slice kernel (rows per block of
+ * row streaming, or 0 for merge-path tiles). */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:

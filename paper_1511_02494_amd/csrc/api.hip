@@ -237,8 +237,10 @@ spmv_status_t build_xslices(spmv_plan *P) {
     const int64_t cw = P->m > 0 ? (P->m + kSlices - 1) / kSlices : 1;
     P->xs_width = cw;
     SPMV_TRY(P->xs_rowptr.alloc((size_t)kSlices * (n + 1) * 4));
-    SPMV_TRY(P->xs_colind.alloc((size_t)(nnz > 0 ? nnz : 1) * 4 + 16));
-    SPMV_TRY(P->xs_val.alloc((size_t)(nnz > 0 ? nnz : 1) * vbytes(P->dtype) + 16));
+    // slice starts are padded to 8 elements so every slice keeps the
+    // 16-byte alignment the vector loads rely on
+    SPMV_TRY(P->xs_colind.alloc((size_t)(nnz + 8 * kSlices) * 4 + 16));
+    SPMV_TRY(P->xs_val.alloc((size_t)(nnz + 8 * kSlices) * vbytes(P->dtype) + 16));
     SPMV_TRY(P->xs_y.alloc((size_t)kSlices * (n > 0 ? n : 1) * xbytes(P->dtype)));
     int64_t snnz[kSlices] = {0};
     if (n > 0) {
@@ -253,25 +255,40 @@ spmv_status_t build_xslices(spmv_plan *P) {
             SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>() + (size_t)k * n,
                                                P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1),
                                                n, tmp.p, tmp.bytes, S(P), nullptr));
+        auto *dmax = scr<unsigned long long>(P, kOffSum);
+        SPMV_HIP(launch_max_i32(lens.as<int32_t>(), (int64_t)kSlices * n, dmax, S(P)));
         int32_t *h = static_cast<int32_t *>(P->h_pinned);
         for (int k = 0; k < kSlices; ++k)
             SPMV_HIP(hipMemcpyAsync(h + k, P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1) + n, 4,
                                     hipMemcpyDeviceToHost, S(P)));
+        SPMV_HIP(hipMemcpyAsync(h + 2 * kSlices, dmax, 8, hipMemcpyDeviceToHost, S(P)));
         SPMV_TRY(sync(P));
         for (int k = 0; k < kSlices; ++k) snnz[k] = h[k];
+        unsigned long long maxlen = 0;
+        memcpy(&maxlen, h + 2 * kSlices, 8);
+        // slice rows no longer than a chunk: row-block streaming, else merge path
+        if (maxlen <= (unsigned long long)kChunk / 4) {
+            const double avg = (double)nnz / ((double)n * kSlices);
+            P->xs_rows = kBlock * pow2_floor((double)kChunk / (kBlock * (avg > 1e-9 ? avg : 1e-9)),
+                                             1, kRowStreamMaxR);
+        } else {
+            P->xs_rows = 0;
+        }
     }
     SliceOffsets so;
     int64_t off = 0, toff = 0;
+    int64_t total = 0;
     for (int k = 0; k < kSlices; ++k) {
         so.off[k] = off;
         P->xs_nnz_off[k] = off;
-        off += snnz[k];
+        off = (off + snnz[k] + 7) & ~(int64_t)7;
+        total += snnz[k];
         P->xs_tiles[k] = n > 0 ? (n + snnz[k] + kMergeTile - 1) / kMergeTile : 0;
         P->xs_tile_off[k] = toff;
         toff += P->xs_tiles[k];
     }
-    if (off != nnz) return fail(SPMV_ERR_HIP, "x-block slices hold %lld of %lld nonzeros",
-                                (long long)off, (long long)nnz);
+    if (total != nnz) return fail(SPMV_ERR_HIP, "x-block slices hold %lld of %lld nonzeros",
+                                  (long long)total, (long long)nnz);
     SPMV_TRY(P->xs_srow.alloc((size_t)(toff + kSlices) * 4));
     SPMV_TRY(P->xs_snnz.alloc((size_t)(toff + kSlices) * 4));
     SPMV_TRY(P->xs_crow.alloc((size_t)(toff > 0 ? toff : 1) * 4));
@@ -279,7 +296,7 @@ spmv_status_t build_xslices(spmv_plan *P) {
     if (n > 0) {
         SPMV_HIP(launch_slice_scatter(*P, P->xs_rowptr.as<int32_t>(), so, P->xs_colind.as<int32_t>(),
                                       P->xs_val.p, S(P)));
-        for (int k = 0; k < kSlices; ++k)
+        for (int k = 0; k < kSlices && P->xs_rows == 0; ++k)
             SPMV_HIP(launch_merge_splits(P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1), n, snnz[k],
                                          P->xs_srow.as<int32_t>() + P->xs_tile_off[k] + k,
                                          P->xs_snnz.as<int32_t>() + P->xs_tile_off[k] + k,
@@ -764,6 +781,7 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
     case 5: *value = P->m > 0 ? (P->m + kSlices - 1) / kSlices : 1; break;
     case 6: SPMV_TRY(build_xslices(P)); *value = P->xs_tile_off[kSlices - 1] + P->xs_tiles[kSlices - 1]; break;
     case 7: *value = kSlices; break;
+    case 12: SPMV_TRY(build_xslices(P)); *value = P->xs_rows; break;
     case 8: *value = P->parts; break;
     case 9: SPMV_TRY(check_d16(P)); *value = d16_feasible(P); break;
     case 11: SPMV_TRY(check_d16(P)); *value = P->d16_rows; break;
@@ -791,8 +809,23 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
         break;
     case 4: case 5:
         SPMV_TRY(build_xslices(P));
-        src = which == 4 ? P->xs_rowptr.p : P->xs_colind.p;
-        want = which == 4 ? 4 * kSlices * (P->n + 1) : 4 * P->nnz;
+        if (which == 5) {  // the slices without their alignment padding
+            if (bytes != 4 * P->nnz) return fail(SPMV_ERR_ARG, "array 5 has %lld bytes", (long long)(4 * P->nnz));
+            int64_t done = 0;
+            for (int k = 0; k < kSlices; ++k) {
+                int32_t last = 0;
+                SPMV_HIP(hipMemcpy(&last, P->xs_rowptr.as<int32_t>() + (size_t)k * (P->n + 1) + P->n, 4,
+                                   hipMemcpyDeviceToHost));
+                if (last > 0)
+                    SPMV_HIP(hipMemcpy(static_cast<int32_t *>(dst) + done,
+                                       P->xs_colind.as<int32_t>() + P->xs_nnz_off[k], (size_t)last * 4,
+                                       hipMemcpyDeviceToHost));
+                done += last;
+            }
+            return SPMV_OK;
+        }
+        src = P->xs_rowptr.p;
+        want = 4 * kSlices * (P->n + 1);
         break;
     case 6:
         if (!P->part_built) {

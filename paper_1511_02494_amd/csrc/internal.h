@@ -101,6 +101,7 @@ struct spmv_plan {
     spmvsel::DevBuf mp_split_row, mp_split_nnz, mp_carry_row, mp_carry_val;
     bool xs_built = false;       // x blocking: column slices, one per XCD
     int64_t xs_width = 0;        // columns per slice
+    int xs_rows = 0;             // >0: row-streaming per slice with this block height; 0: merge path
     int64_t xs_nnz_off[spmvsel::kSlices] = {0}, xs_tiles[spmvsel::kSlices] = {0},
             xs_tile_off[spmvsel::kSlices] = {0};
     spmvsel::DevBuf xs_rowptr, xs_colind, xs_val, xs_srow, xs_snnz, xs_crow, xs_cval, xs_y;
@@ -137,6 +138,7 @@ hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t pan
 hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,
                                int32_t *snnz, int64_t tiles, hipStream_t s);
 hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, int32_t *lens, hipStream_t s);
+hipError_t launch_max_i32(const int32_t *a, int64_t n, unsigned long long *d_max, hipStream_t s);
 hipError_t launch_slice_scatter(const spmv_plan &P, const int32_t *srp, const SliceOffsets &so,
                                 int32_t *xci, void *xval, hipStream_t s);
 hipError_t launch_panel_windows(const spmv_plan &P, int rows_per_panel, int32_t *cmin,

@@ -113,6 +113,28 @@ __global__ __launch_bounds__(kBlock) void k_slice_count(int64_t n, int64_t cw,
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_max_i32(const int32_t *__restrict__ a, int64_t n,
+                                                    unsigned long long *mx) {
+    int32_t t = 0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        t = a[i] > t ? a[i] : t;
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t u = __shfl_xor(t, o, 64);
+        t = u > t ? u : t;
+    }
+    if ((threadIdx.x & 63) == 0 && t > 0) atomicMax(mx, (unsigned long long)t);
+}
+
+hipError_t launch_max_i32(const int32_t *a, int64_t n, unsigned long long *d_max, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(d_max, 0, sizeof(unsigned long long), s);
+    if (e != hipSuccess || n == 0) return e;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(k_max_i32, dim3((unsigned)g), dim3(kBlock), 0, s, a, n, d_max);
+    return hipGetLastError();
+}
+
 // Copy every row's slice segments into the slice-major arrays.
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_slice_scatter(int64_t n, const int32_t *__restrict__ rp,

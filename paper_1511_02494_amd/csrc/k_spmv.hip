@@ -81,8 +81,8 @@ template <> struct Pair<uint16_t> { typedef unsigned short type __attribute__((e
 template <> struct Pair<int32_t> { typedef int type __attribute__((ext_vector_type(2))); };
 
 template <class V, bool D16, int R>
-__global__ __launch_bounds__(kBlock) void k_rowstream(
-    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+__device__ __forceinline__ void rowstream_block(
+    int64_t blk, int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const uint16_t *__restrict__ off, const int32_t *__restrict__ rbase,
     const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
     typename VT<V>::A *__restrict__ y) {
@@ -95,7 +95,6 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
     __shared__ int32_t s_rp[RB + 1];
     __shared__ A s_prod[kChunk];
 
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r0 = blk * RB;
     const int nrows = (int)((n - r0) < RB ? (n - r0) : RB);
     for (int r = threadIdx.x; r <= nrows; r += kBlock) s_rp[r] = rp[r0 + r];
@@ -167,6 +166,15 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
         y[r0 + myr] = acc.s;
         acc.reset();
     }
+}
+
+template <class V, bool D16, int R>
+__global__ __launch_bounds__(kBlock) void k_rowstream(
+    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const uint16_t *__restrict__ off, const int32_t *__restrict__ rbase,
+    const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
+    typename VT<V>::A *__restrict__ y) {
+    rowstream_block<V, D16, R>(xcd_remap(blockIdx.x, gridDim.x), n, rp, ci, off, rbase, val, x, y);
 }
 
 // ============================================================ merge path
@@ -338,6 +346,20 @@ __global__ __launch_bounds__(kBlock) void k_merge_slices(int64_t n, const int32_
                   T.snnz[s], T.crow[s], T.cval[s]);
 }
 
+// Short slice rows: row-block streaming on each slice (block b on XCD b mod 8).
+template <class V, int R>
+__global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t nblocks,
+                                                             const int32_t *__restrict__ ci,
+                                                             const V *__restrict__ val,
+                                                             const typename VT<V>::A *__restrict__ x,
+                                                             SliceTable<typename VT<V>::A> T) {
+    const int s = blockIdx.x % kSlices;
+    const int64_t b = blockIdx.x / kSlices;
+    if (b >= nblocks) return;
+    rowstream_block<V, false, R>(b, n, T.rp[s], ci + T.off[s], nullptr, nullptr, val + T.off[s], x,
+                                 T.y[s]);
+}
+
 template <class A>
 __global__ __launch_bounds__(kBlock) void k_merge_fixup_slices(int64_t n, int64_t maxt,
                                                                SliceTable<A> T) {
@@ -479,7 +501,22 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             T.tiles[k] = P.xs_tiles[k];
             if (T.tiles[k] > maxt) maxt = T.tiles[k];
         }
-        if (maxt > 0) {
+        if (P.xs_rows > 0) {  // short slice rows: row-block streaming per slice
+            const int R = P.xs_rows / kBlock;
+            const int64_t nb = (P.n + P.xs_rows - 1) / P.xs_rows;
+            const unsigned g = (unsigned)(nb * kSlices);
+            const int32_t *xci = P.xs_colind.as<int32_t>();
+            const V *xv = (const V *)P.xs_val.p;
+            switch (R) {
+            case 1: hipLaunchKernelGGL((k_rowstream_slices<V, 1>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T); break;
+            case 2: hipLaunchKernelGGL((k_rowstream_slices<V, 2>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T); break;
+            case 4: hipLaunchKernelGGL((k_rowstream_slices<V, 4>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T); break;
+            case 8: hipLaunchKernelGGL((k_rowstream_slices<V, 8>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T); break;
+            default: return hipErrorInvalidValue;
+            }
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        } else if (maxt > 0) {
             hipLaunchKernelGGL(k_merge_slices<V>, dim3((unsigned)(maxt * kSlices)), dim3(kBlock), 0,
                                s, P.n, P.xs_colind.as<int32_t>(), (const V *)P.xs_val.p,
                                (const A *)x, T);
