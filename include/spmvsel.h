@@ -172,10 +172,11 @@ spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
 /* Bit v set if variant v can run this matrix (computes features if needed). */
 spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
 
-/* Algorithmic bytes of one SpMV with `variant`: 4(N+1) + ib NNZ + vb NNZ +
- * xb M + yb N, plus 4 bytes per block reference column for DELTA16 (ib = 2
- * there, else 4), plus 7 more row-pointer arrays and 8 partial y vectors
- * written and read back for XBLOCK_LDS. */
+/* Algorithmic (compulsory) bytes of one SpMV with `variant`: 4(N+1) +
+ * ib NNZ + vb NNZ + xb M + yb N, plus 4 bytes per block reference column for
+ * DELTA16 (ib = 2 there, else 4).  Traffic a variant adds on top (the
+ * XBLOCK_LDS slice row pointers and partial y vectors) is overhead and is
+ * not counted. */
 spmv_status_t spmv_bytes(spmv_plan_t plan, int32_t variant, int64_t *bytes);
 
 /* Median and minimum time of `reps` executions of `variant` (hipEvents on

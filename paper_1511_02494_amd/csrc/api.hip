@@ -747,8 +747,6 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
         SPMV_TRY(check_d16(P));
         extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
     }
-    if (v == V_XBLOCK_LDS)  // slice row pointers, partial y written and read back
-        extra = 4 * (kSlices - 1) * (P->n + 1) + 2 * kSlices * xb * P->n;
     *bytes = 4 * (P->n + 1) + (ib + vb) * P->nnz + xb * P->m + xb * P->n + extra;
     return SPMV_OK;
 }

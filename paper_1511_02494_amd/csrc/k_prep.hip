@@ -91,26 +91,43 @@ hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, in
 // ---- x blocking: column slices of width cw (slice of column c = c / cw).
 // Per row, the number of its nonzeros in each slice (columns are sorted, so
 // the slice boundaries are found by binary search inside the row).
+// Slice preparation takes rows in blocks of kBlock and streams the block's
+// nonzeros with coalesced loads; each nonzero finds its row by a search of
+// the block's row pointers held in LDS, so a long row is shared by the whole
+// block instead of falling to one thread.
+__device__ inline int block_row_of(const int32_t *s_rp, int nr, int32_t k) {
+    int lo = 0, hi = nr - 1;  // largest r with s_rp[r] <= k
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rp[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int slice_of(int32_t c, int64_t cw) {
+    const int64_t s = (int64_t)c / cw;
+    return s < kSlices - 1 ? (int)s : kSlices - 1;
+}
+
+// lens[s * n + i] = nonzeros of row i in column slice s (columns [s*cw, (s+1)*cw),
+// the last slice also takes the remainder).
 __global__ __launch_bounds__(kBlock) void k_slice_count(int64_t n, int64_t cw,
                                                         const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ ci,
                                                         int32_t *__restrict__ lens) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        const int32_t b = rp[i + 1];
-        int32_t pos = rp[i];
-        for (int s = 0; s < kSlices - 1; ++s) {
-            const int64_t bound = (s + 1) * cw;
-            int32_t lo = pos, hi = b;  // first k in [pos, b) with ci[k] >= bound
-            while (lo < hi) {
-                const int32_t mid = lo + ((hi - lo) >> 1);
-                if ((int64_t)ci[mid] < bound) lo = mid + 1; else hi = mid;
-            }
-            lens[(int64_t)s * n + i] = lo - pos;
-            pos = lo;
-        }
-        lens[(int64_t)(kSlices - 1) * n + i] = b - pos;
-    }
+    __shared__ int32_t s_rp[kBlock + 1];
+    __shared__ int32_t s_cnt[kSlices * kBlock];
+    const int64_t r0 = (int64_t)blockIdx.x * kBlock;
+    const int nr = (int)((n - r0) < kBlock ? (n - r0) : kBlock);
+    for (int i = threadIdx.x; i <= nr; i += kBlock) s_rp[i] = rp[r0 + i];
+    for (int i = threadIdx.x; i < kSlices * kBlock; i += kBlock) s_cnt[i] = 0;
+    __syncthreads();
+    const int64_t k1 = s_rp[nr];
+    for (int64_t k = s_rp[0] + (int64_t)threadIdx.x; k < k1; k += kBlock)
+        atomicAdd(&s_cnt[slice_of(ci[k], cw) * kBlock + block_row_of(s_rp, nr, (int32_t)k)], 1);
+    __syncthreads();
+    for (int s = 0; s < kSlices; ++s)
+        if ((int)threadIdx.x < nr) lens[(int64_t)s * n + r0 + threadIdx.x] = s_cnt[s * kBlock + threadIdx.x];
 }
 
 __global__ __launch_bounds__(kBlock) void k_max_i32(const int32_t *__restrict__ a, int64_t n,
@@ -135,35 +152,47 @@ hipError_t launch_max_i32(const int32_t *a, int64_t n, unsigned long long *d_max
     return hipGetLastError();
 }
 
-// Copy every row's slice segments into the slice-major arrays.
+// Copy every row's slice segments into the slice-major arrays.  Within a
+// row the segments follow in slice order, so nonzero k of row r in slice s
+// moves by the fixed amount off[s] + srp_s[r] - (rp[r] + earlier segments).
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_slice_scatter(int64_t n, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_slice_scatter(int64_t n, int64_t cw,
+                                                          const int32_t *__restrict__ rp,
                                                           const int32_t *__restrict__ ci,
                                                           const V *__restrict__ val,
                                                           const int32_t *__restrict__ srp,
                                                           SliceOffsets so,
                                                           int32_t *__restrict__ xci,
                                                           V *__restrict__ xval) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        int32_t pos = rp[i];
+    __shared__ int32_t s_rp[kBlock + 1];
+    __shared__ int64_t s_shift[kSlices * kBlock];
+    const int64_t r0 = (int64_t)blockIdx.x * kBlock;
+    const int nr = (int)((n - r0) < kBlock ? (n - r0) : kBlock);
+    for (int i = threadIdx.x; i <= nr; i += kBlock) s_rp[i] = rp[r0 + i];
+    __syncthreads();
+    if ((int)threadIdx.x < nr) {
+        const int64_t i = r0 + threadIdx.x;
+        int64_t pos = s_rp[threadIdx.x];
         for (int s = 0; s < kSlices; ++s) {
             const int32_t *r = srp + (int64_t)s * (n + 1);
-            const int32_t a = r[i], cnt = r[i + 1] - a;
-            const int64_t dst = so.off[s] + a;
-            for (int32_t j = 0; j < cnt; ++j) {
-                xci[dst + j] = ci[pos + j];
-                xval[dst + j] = val[pos + j];
-            }
-            pos += cnt;
+            const int32_t a = r[i];
+            s_shift[s * kBlock + threadIdx.x] = so.off[s] + a - pos;
+            pos += r[i + 1] - a;
         }
+    }
+    __syncthreads();
+    const int64_t k1 = s_rp[nr];
+    for (int64_t k = s_rp[0] + (int64_t)threadIdx.x; k < k1; k += kBlock) {
+        const int32_t c = ci[k];
+        const int64_t d = k + s_shift[slice_of(c, cw) * kBlock + block_row_of(s_rp, nr, (int32_t)k)];
+        xci[d] = c;
+        xval[d] = val[k];
     }
 }
 
 hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, int32_t *lens, hipStream_t s) {
     if (P.n == 0) return hipSuccess;
-    int64_t g = (P.n + kBlock - 1) / kBlock;
-    if (g > 65536) g = 65536;
+    const int64_t g = (P.n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_slice_count, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, cw, P.rowptr,
                        P.colind, lens);
     return hipGetLastError();
@@ -172,19 +201,19 @@ hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, int32_t *lens, hip
 hipError_t launch_slice_scatter(const spmv_plan &P, const int32_t *srp, const SliceOffsets &so,
                                 int32_t *xci, void *xval, hipStream_t s) {
     if (P.n == 0) return hipSuccess;
-    int64_t g = (P.n + kBlock - 1) / kBlock;
-    if (g > 65536) g = 65536;
+    const int64_t g = (P.n + kBlock - 1) / kBlock;
+    const int64_t cw = P.xs_width;
     switch (P.dtype) {
     case SPMV_F64:
-        hipLaunchKernelGGL(k_slice_scatter<double>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n,
+        hipLaunchKernelGGL(k_slice_scatter<double>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, cw,
                            P.rowptr, P.colind, (const double *)P.val, srp, so, xci, (double *)xval);
         break;
     case SPMV_F32:
-        hipLaunchKernelGGL(k_slice_scatter<float>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n,
+        hipLaunchKernelGGL(k_slice_scatter<float>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, cw,
                            P.rowptr, P.colind, (const float *)P.val, srp, so, xci, (float *)xval);
         break;
     default:
-        hipLaunchKernelGGL(k_slice_scatter<uint16_t>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n,
+        hipLaunchKernelGGL(k_slice_scatter<uint16_t>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, cw,
                            P.rowptr, P.colind, (const uint16_t *)P.val, srp, so, xci,
                            (uint16_t *)xval);
     }
