@@ -34,34 +34,12 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_bench_config1_traffic.json")
 
 
-def kernel_source_hash():
-    """SHA-256 of the HIP sources, to tell whether stored counters still apply."""
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1511_02494_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(os.path.basename(p).encode() + f.read())
-    return h.hexdigest()
-
-
 def stored_traffic(kernel_names):
-    """HBM bytes per launch (fetch + write) of the given kernels, from the
+    """HBM bytes per launch (fetch + write) of the given kernels from the
     rocprofv3 counters stored in profiles/, or None when they were taken on
     another version of the kernels."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    with open(TRAFFIC_FILE) as f:
-        rec = json.load(f)
-    if rec.get("source_sha256") != kernel_source_hash():
-        return None
-    total = 0.0
-    for name in kernel_names:
-        hits = [v for k, v in rec["kernels"].items() if k.startswith(name)]
-        if not hits:
-            return None
-        total += hits[0]["fetch_bytes"] + hits[0]["write_bytes"]
-    return total
+    from paper_1511_02494_amd.profiling import stored_traffic as st
+    return st(TRAFFIC_FILE, kernel_names)
 
 
 def log(*a):
@@ -78,6 +56,10 @@ def kernel_names(v, plan):
     if v == S.V_MERGE_PATH:
         return ["void spmvsel::k_merge_path<double>", "void spmvsel::k_merge_fixup<double>"]
     if v == S.V_XBLOCK_LDS:
+        rows = plan.query(12)  # rows per block of the per-slice row-streaming kernel, 0 = merge path
+        if rows > 0:
+            return [f"void spmvsel::k_rowstream_slices<double, {rows // 256}>",
+                    "void spmvsel::k_slice_sum<double>"]
         return ["void spmvsel::k_merge_slices<double>", "void spmvsel::k_merge_fixup_slices<double>",
                 "void spmvsel::k_slice_sum<double>"]
     if v == S.V_DELTA16:
@@ -94,6 +76,8 @@ def parse():
     ap.add_argument("--selector", default="mlp", choices=["mlp", "profiling", "exhaustive"])
     ap.add_argument("--scale", type=int, default=1, help="divide matrix sizes (testing only)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
+                    help="CPU time budget of the oracle baseline (all four matrices)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant timing table")
     ap.add_argument("--model", default=None)
     return ap.parse_args()
@@ -270,24 +254,26 @@ def main():
         from oracle import cref
         cref.build()
         tb, tt = 0, 0.0
-        sample = []
+        reps = []
         for sp in specs:
             rp, ci, val = sp.build()
             x = sp.x(len(rp) - 1)
-            ts = []
-            for _ in range(3):
-                t0 = time.perf_counter()
-                cref.spmv(rp, ci, val, x)
-                ts.append(time.perf_counter() - t0)
             n = len(rp) - 1
             b = 4 * (n + 1) + 12 * len(ci) + 16 * n
-            tb += b
-            tt += float(np.median(ts))
-            sample.append(sp.name)
+            k, t_m = 0, 0.0
+            while t_m < args.cpu_seconds / len(specs) or k < 2:  # about the budget per matrix
+                t0 = time.perf_counter()
+                cref.spmv(rp, ci, val, x)
+                t_m += time.perf_counter() - t0
+                k += 1
+            tb += b * k
+            tt += t_m
+            reps.append(f"{sp.name} x{k}")
+            log(f"cpu oracle {sp.name}: {k} SpMVs in {t_m:.1f} s")
         cpu = {"value": tb / tt * 1e-9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": "one single-threaded SpMV (median of 3) of the plain C oracle loop on "
-                         "each of the four matrices; bytes counted as for the GPU "
-                         "(features and selection not included)",
+               "sample": "repeated single-threaded SpMVs of the plain C oracle loop on the four "
+                         f"bench matrices ({', '.join(reps)}; {tt:.1f} s of CPU time); bytes "
+                         "counted as for the GPU, selection not included",
                "cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
 
     out = {

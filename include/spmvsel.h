@@ -169,6 +169,14 @@ spmv_status_t spmv_execute(spmv_plan_t plan, const void *d_x, void *d_y,
 spmv_status_t spmv_set_variant(spmv_plan_t plan, int32_t variant);
 spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
 
+/* Column slices of the XBLOCK_LDS format: 0 (default) picks the smallest of
+ * 1, 2, 4, 8 that cuts x into slices of at most 4 MiB (measured best on the
+ * random and power-law workloads), so that each XCD's 4 MB L2 mostly holds the
+ * slice it gathers from; 1, 2, 4 or 8 force that count (tests,
+ * tuning).  If the format is built with another count it is rebuilt
+ * (synchronous).  SPMV_ERR_ARG for any other value. */
+spmv_status_t spmv_set_xblock_slices(spmv_plan_t plan, int32_t slices);
+
 /* Bit v set if variant v can run this matrix (computes features if needed). */
 spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
 
@@ -199,7 +207,8 @@ spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
  * 0 delta16 block reference columns int32[ceil(N / rows per block)],
  * 1 delta16 offsets uint16[NNZ], 2 merge-path split rows int32[tiles+1],
  * 3 merge-path split nonzeros int32[tiles+1], 4 x-block slice row
- * pointers int32[8 (N+1)], 5 x-block slice-major column indices int32[NNZ],
+ * pointers int32[S (N+1)] (S = key 7), 5 x-block slice-major column
+ * indices int32[NNZ],
  * 6 profiling partition bounds int32[parts+1].  `bytes` must equal the
  * array size. */
 spmv_status_t spmv_plan_copy_format(spmv_plan_t plan, int32_t which,
@@ -293,6 +302,13 @@ spmv_status_t spmv_generate(int32_t family, const int64_t *params, int32_t n_par
 
 /* x_j = 2 u_j - 1 with u_j = (h(seed, 1, j) >> 11) 2^-53 (double, n elements). */
 spmv_status_t spmv_generate_vector(int64_t n, uint64_t seed, double *d_x, void *stream);
+
+/* Device memory the library releases (derived formats, temporaries) is kept
+ * per device for reuse, up to 8 GiB in all and 1 GiB per block, because plans
+ * are typically created and destroyed around every solve.  This call frees
+ * every kept block on every device.  A failed allocation also frees the kept
+ * blocks of its device and retries once. */
+spmv_status_t spmv_release_cached_blocks(void);
 
 /* Evict the Infinity Cache: read and write a 512 MiB scratch buffer. */
 spmv_status_t spmv_cache_flush(void *stream);

@@ -65,6 +65,7 @@ _PROTOS = {
     "spmv_set_variant": (_I32, [_P, _I32]),
     "spmv_get_variant": (_I32, [_P, _PI32]),
     "spmv_variant_mask": (_I32, [_P, _PU32]),
+    "spmv_set_xblock_slices": (_I32, [_P, _I32]),
     "spmv_bytes": (_I32, [_P, _I32, _PI64]),
     "spmv_time_variant": (_I32, [_P, _I32, _I32, _I32, _PF64, _PF64]),
     "spmv_plan_query": (_I32, [_P, _I32, _PI64]),
@@ -81,6 +82,7 @@ _PROTOS = {
     "spmv_quantize": (_I32, [_P, _P, _I64, _I32, _P]),
     "spmv_generate": (_I32, [_I32, _PI64, _I32, _U64, _P, _P, _P, _PI64, _P]),
     "spmv_generate_vector": (_I32, [_I64, _U64, _P, _P]),
+    "spmv_release_cached_blocks": (_I32, []),
     "spmv_cache_flush": (_I32, [_P]),
     "spmv_hbm_probe": (_I32, [_I64, _PF64, _PF64]),
     "spmv_last_error": (ctypes.c_char_p, []),
@@ -188,6 +190,10 @@ def spmv_get_variant(plan) -> int:
     v = _I32()
     _check("spmv_get_variant", lib.spmv_get_variant(plan, ctypes.byref(v)))
     return v.value
+
+
+def spmv_set_xblock_slices(plan, slices: int):
+    _check("spmv_set_xblock_slices", lib.spmv_set_xblock_slices(plan, slices))
 
 
 def spmv_variant_mask(plan) -> int:
@@ -306,6 +312,10 @@ def spmv_generate(family: int, params, seed: int, rowptr, colind=None, val=None,
 
 def spmv_generate_vector(n: int, seed: int, x, stream=None):
     _check("spmv_generate_vector", lib.spmv_generate_vector(n, seed, _addr(x), _stream(stream)))
+
+
+def spmv_release_cached_blocks():
+    _check("spmv_release_cached_blocks", lib.spmv_release_cached_blocks())
 
 
 def spmv_cache_flush(stream=None):

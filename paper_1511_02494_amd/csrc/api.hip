@@ -39,21 +39,93 @@ spmv_status_t fail_hip(hipError_t e, const char *what, const char *file, int lin
     return e == hipErrorOutOfMemory ? SPMV_ERR_OOM : SPMV_ERR_HIP;
 }
 
+// ---- device block cache.  Plans are built and destroyed around solver
+// loops, and hipMalloc / hipFree of their derived formats (hundreds of MB)
+// cost more than the kernels that fill them.  Released blocks are kept per
+// device, up to kCacheBytes in all, and handed out again for requests of at
+// least half their size.  A release waits for the device as hipFree does, so
+// a cached block is never handed out while a kernel may still use it.
+namespace {
+constexpr size_t kCacheBytes = size_t(8) << 30;
+constexpr size_t kCacheMaxBlock = size_t(1) << 30;  // larger blocks go straight back
+std::mutex g_cache_mu;
+std::multimap<std::pair<int, size_t>, void *> g_cache;  // (device, bytes) -> block
+size_t g_cache_total = 0;
+
+size_t round_request(size_t n) {
+    if (n < 256) return 256;
+    const size_t g = n >= (size_t(1) << 20) ? (size_t(1) << 20) : 256;
+    return (n + g - 1) / g * g;
+}
+
+void cache_trim(int dev, bool all_devices) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto it = g_cache.begin(); it != g_cache.end();) {
+        if (all_devices || it->first.first == dev) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            if (cur != it->first.first) (void)hipSetDevice(it->first.first);
+            (void)hipFree(it->second);
+            if (cur != it->first.first) (void)hipSetDevice(cur);
+            g_cache_total -= it->first.second;
+            it = g_cache.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+}  // namespace
+
 spmv_status_t DevBuf::alloc(size_t n) {
     if (p && bytes >= n) return SPMV_OK;
     release();
-    const size_t want = n < 256 ? 256 : n;
-    hipError_t e = hipMalloc(&p, want);
+    const size_t want = round_request(n);
+    int d = 0;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice", __FILE__, __LINE__);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.lower_bound({d, want});
+        if (it != g_cache.end() && it->first.first == d && it->first.second / 2 <= want) {
+            p = it->second;
+            bytes = it->first.second;
+            dev = d;
+            g_cache_total -= bytes;
+            g_cache.erase(it);
+            return SPMV_OK;
+        }
+    }
+    e = hipMalloc(&p, want);
+    if (e == hipErrorOutOfMemory) {  // give the cached blocks back and try once more
+        (void)hipGetLastError();
+        cache_trim(d, false);
+        e = hipMalloc(&p, want);
+    }
     if (e != hipSuccess) {
         p = nullptr;
         return fail_hip(e, "hipMalloc", __FILE__, __LINE__);
     }
     bytes = want;
+    dev = d;
     return SPMV_OK;
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != dev) (void)hipSetDevice(dev);
+    bool kept = false;
+    if (hipDeviceSynchronize() == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        if (bytes <= kCacheMaxBlock && g_cache_total + bytes <= kCacheBytes) {
+            g_cache.emplace(std::make_pair(dev, bytes), p);
+            g_cache_total += bytes;
+            kept = true;
+        }
+    }
+    if (!kept) (void)hipFree(p);
+    if (cur != dev) (void)hipSetDevice(cur);
     p = nullptr;
     bytes = 0;
 }
@@ -228,47 +300,70 @@ spmv_status_t check_d16(spmv_plan *P) {
 bool d16_feasible(const spmv_plan *P) { return P->d16_feasible; }
 
 // ------------------------------------------------------------ formats
-// x blocking: split the columns into kSlices slices (one per XCD) and store
-// each slice as its own CSR (rowptr per slice, slice-major colind/val), with
-// merge-path tiles per slice and one partial y per slice.
+// x blocking: split the columns into S slices (S <= 8, one XCD group each)
+// and store each slice as its own CSR (rowptr per slice, slice-major
+// colind/val), with merge-path tiles per slice when a slice row is long, and
+// one partial y per slice.
+// Slice count: the requested one, else the smallest power of two that cuts
+// x into slices of at most kSliceXBytes (at most one slice per XCD).
+int xs_slice_count(const spmv_plan *P) {
+    if (P->xs_req > 0) return P->xs_req;
+    const int64_t xb = (int64_t)xbytes(P->dtype) * P->m;
+    int ns = 1;
+    while (ns < kSlices && xb > kSliceXBytes * ns) ns *= 2;
+    return ns;
+}
+
+int64_t xs_slice_width(const spmv_plan *P, int ns) {
+    return P->m > 0 ? (P->m + ns - 1) / ns : 1;
+}
+
 spmv_status_t build_xslices(spmv_plan *P) {
     if (P->xs_built) return SPMV_OK;
     const int64_t n = P->n, nnz = P->nnz;
-    const int64_t cw = P->m > 0 ? (P->m + kSlices - 1) / kSlices : 1;
+    const int ns = xs_slice_count(P);
+    const int64_t cw = xs_slice_width(P, ns);
+    P->xs_slices = ns;
     P->xs_width = cw;
-    SPMV_TRY(P->xs_rowptr.alloc((size_t)kSlices * (n + 1) * 4));
+    for (int k = 0; k < kSlices; ++k) P->xs_nnz_off[k] = P->xs_tiles[k] = P->xs_tile_off[k] = 0;
+    SPMV_TRY(P->xs_rowptr.alloc((size_t)ns * (n + 1) * 4));
     // slice starts are padded to 8 elements so every slice keeps the
     // 16-byte alignment the vector loads rely on
-    SPMV_TRY(P->xs_colind.alloc((size_t)(nnz + 8 * kSlices) * 4 + 16));
-    SPMV_TRY(P->xs_val.alloc((size_t)(nnz + 8 * kSlices) * vbytes(P->dtype) + 16));
-    SPMV_TRY(P->xs_y.alloc((size_t)kSlices * (n > 0 ? n : 1) * xbytes(P->dtype)));
+    SPMV_TRY(P->xs_colind.alloc((size_t)(nnz + 8 * ns) * 4 + 16));
+    SPMV_TRY(P->xs_val.alloc((size_t)(nnz + 8 * ns) * vbytes(P->dtype) + 16));
+    SPMV_TRY(P->xs_y.alloc((size_t)ns * (n > 0 ? n : 1) * xbytes(P->dtype)));
     int64_t snnz[kSlices] = {0};
+    // merge-path tiles of the original CSR, walked by the count and scatter kernels
+    const int64_t mtiles = (n + nnz + kMergeTile - 1) / kMergeTile;
+    DevBuf msr, msn;
+    SPMV_TRY(msr.alloc((size_t)(mtiles + 1) * 4));
+    SPMV_TRY(msn.alloc((size_t)(mtiles + 1) * 4));
     if (n > 0) {
+        SPMV_HIP(launch_merge_splits(P->rowptr, n, nnz, msr.as<int32_t>(), msn.as<int32_t>(), mtiles,
+                                     S(P)));
         DevBuf lens, tmp;
-        SPMV_TRY(lens.alloc((size_t)kSlices * n * 4));
-        SPMV_HIP(launch_slice_count(*P, cw, lens.as<int32_t>(), S(P)));
+        SPMV_TRY(lens.alloc((size_t)ns * n * 4));
+        SPMV_HIP(launch_slice_count(*P, cw, msr.as<int32_t>(), msn.as<int32_t>(), mtiles,
+                                    lens.as<int32_t>(), S(P)));
         size_t need = 0;
+        auto *dmax = scr<unsigned long long>(P, kOffSum);  // then the slice totals
+        int64_t *dtot = reinterpret_cast<int64_t *>(dmax + 1);
         SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>(), P->xs_rowptr.as<int32_t>(), n,
-                                           nullptr, 0, S(P), &need));
+                                           ns, dtot, nullptr, 0, S(P), &need));
         SPMV_TRY(tmp.alloc(need));
-        for (int k = 0; k < kSlices; ++k)
-            SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>() + (size_t)k * n,
-                                               P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1),
-                                               n, tmp.p, tmp.bytes, S(P), nullptr));
-        auto *dmax = scr<unsigned long long>(P, kOffSum);
-        SPMV_HIP(launch_max_i32(lens.as<int32_t>(), (int64_t)kSlices * n, dmax, S(P)));
-        int32_t *h = static_cast<int32_t *>(P->h_pinned);
-        for (int k = 0; k < kSlices; ++k)
-            SPMV_HIP(hipMemcpyAsync(h + k, P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1) + n, 4,
-                                    hipMemcpyDeviceToHost, S(P)));
-        SPMV_HIP(hipMemcpyAsync(h + 2 * kSlices, dmax, 8, hipMemcpyDeviceToHost, S(P)));
+        SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>(), P->xs_rowptr.as<int32_t>(), n,
+                                           ns, dtot, tmp.p, tmp.bytes, S(P), nullptr));
+        SPMV_HIP(launch_max_i32(lens.as<int32_t>(), (int64_t)ns * n, scr<int32_t>(P, kOffPart),
+                                dmax, S(P)));
+        int64_t *h = static_cast<int64_t *>(P->h_pinned);
+        SPMV_HIP(hipMemcpyAsync(h, dmax, 8 * (1 + ns), hipMemcpyDeviceToHost, S(P)));
         SPMV_TRY(sync(P));
-        for (int k = 0; k < kSlices; ++k) snnz[k] = h[k];
         unsigned long long maxlen = 0;
-        memcpy(&maxlen, h + 2 * kSlices, 8);
+        memcpy(&maxlen, h, 8);
+        for (int k = 0; k < ns; ++k) snnz[k] = h[1 + k];
         // slice rows no longer than a chunk: row-block streaming, else merge path
         if (maxlen <= (unsigned long long)kChunk / 4) {
-            const double avg = (double)nnz / ((double)n * kSlices);
+            const double avg = (double)nnz / ((double)n * ns);
             P->xs_rows = kBlock * pow2_floor((double)kChunk / (kBlock * (avg > 1e-9 ? avg : 1e-9)),
                                              1, kRowStreamMaxR);
         } else {
@@ -278,7 +373,8 @@ spmv_status_t build_xslices(spmv_plan *P) {
     SliceOffsets so;
     int64_t off = 0, toff = 0;
     int64_t total = 0;
-    for (int k = 0; k < kSlices; ++k) {
+    for (int k = 0; k < kSlices; ++k) so.off[k] = 0;
+    for (int k = 0; k < ns; ++k) {
         so.off[k] = off;
         P->xs_nnz_off[k] = off;
         off = (off + snnz[k] + 7) & ~(int64_t)7;
@@ -289,14 +385,15 @@ spmv_status_t build_xslices(spmv_plan *P) {
     }
     if (total != nnz) return fail(SPMV_ERR_HIP, "x-block slices hold %lld of %lld nonzeros",
                                   (long long)total, (long long)nnz);
-    SPMV_TRY(P->xs_srow.alloc((size_t)(toff + kSlices) * 4));
-    SPMV_TRY(P->xs_snnz.alloc((size_t)(toff + kSlices) * 4));
+    SPMV_TRY(P->xs_srow.alloc((size_t)(toff + ns) * 4));
+    SPMV_TRY(P->xs_snnz.alloc((size_t)(toff + ns) * 4));
     SPMV_TRY(P->xs_crow.alloc((size_t)(toff > 0 ? toff : 1) * 4));
     SPMV_TRY(P->xs_cval.alloc((size_t)(toff > 0 ? toff : 1) * 8));
     if (n > 0) {
-        SPMV_HIP(launch_slice_scatter(*P, P->xs_rowptr.as<int32_t>(), so, P->xs_colind.as<int32_t>(),
+        SPMV_HIP(launch_slice_scatter(*P, msr.as<int32_t>(), msn.as<int32_t>(), mtiles,
+                                      P->xs_rowptr.as<int32_t>(), so, P->xs_colind.as<int32_t>(),
                                       P->xs_val.p, S(P)));
-        for (int k = 0; k < kSlices && P->xs_rows == 0; ++k)
+        for (int k = 0; k < ns && P->xs_rows == 0; ++k)
             SPMV_HIP(launch_merge_splits(P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1), n, snnz[k],
                                          P->xs_srow.as<int32_t>() + P->xs_tile_off[k] + k,
                                          P->xs_snnz.as<int32_t>() + P->xs_tile_off[k] + k,
@@ -357,6 +454,9 @@ spmv_status_t feasible_mask(spmv_plan *P, uint32_t *bits) {
 }
 
 spmv_status_t run_variant(const spmv_plan *P, int v, const void *x, void *y, hipStream_t s) {
+    if ((v == V_DELTA16 && !P->d16_built) || (v == V_MERGE_PATH && !P->mp_built) ||
+        (v == V_XBLOCK_LDS && !P->xs_built))
+        return fail(SPMV_ERR_ARG, "variant %d has no prepared format", v);
     switch (v) {
     case V_CSR_SCALAR: SPMV_HIP(launch_csr_scalar(*P, x, y, s)); break;
     case V_CSR_VECTOR: SPMV_HIP(launch_csr_vector(*P, x, y, s)); break;
@@ -674,7 +774,8 @@ spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
     P->parts = P->num_cus * 8;
     if (!(flags & SPMV_SKIP_VALIDATE)) {
         uint64_t *f = scr<uint64_t>(P, kOffFlags);
-        BAIL_HIP(launch_validate(*P, f, P->stream));
+        static_assert(kFeatBlocks * 16 >= kValGrid * 3, "validation partials fit the scratch");
+        BAIL_HIP(launch_validate(*P, f, scr<uint64_t>(P, kOffPart), P->stream));
         BAIL_HIP(hipMemcpyAsync(P->h_pinned, f, 24, hipMemcpyDeviceToHost, P->stream));
         BAIL_HIP(hipStreamSynchronize(P->stream));
         uint64_t h[3];
@@ -776,9 +877,9 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
     case 2: *value = P->rs_rows * kBlock; break;
     case 3: *value = kMergeTile; break;
     case 4: *value = (P->n + P->nnz + kMergeTile - 1) / kMergeTile; break;
-    case 5: *value = P->m > 0 ? (P->m + kSlices - 1) / kSlices : 1; break;
-    case 6: SPMV_TRY(build_xslices(P)); *value = P->xs_tile_off[kSlices - 1] + P->xs_tiles[kSlices - 1]; break;
-    case 7: *value = kSlices; break;
+    case 5: *value = xs_slice_width(P, xs_slice_count(P)); break;
+    case 6: SPMV_TRY(build_xslices(P)); *value = P->xs_tile_off[P->xs_slices - 1] + P->xs_tiles[P->xs_slices - 1]; break;
+    case 7: *value = xs_slice_count(P); break;
     case 12: SPMV_TRY(build_xslices(P)); *value = P->xs_rows; break;
     case 8: *value = P->parts; break;
     case 9: SPMV_TRY(check_d16(P)); *value = d16_feasible(P); break;
@@ -810,7 +911,7 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
         if (which == 5) {  // the slices without their alignment padding
             if (bytes != 4 * P->nnz) return fail(SPMV_ERR_ARG, "array 5 has %lld bytes", (long long)(4 * P->nnz));
             int64_t done = 0;
-            for (int k = 0; k < kSlices; ++k) {
+            for (int k = 0; k < P->xs_slices; ++k) {
                 int32_t last = 0;
                 SPMV_HIP(hipMemcpy(&last, P->xs_rowptr.as<int32_t>() + (size_t)k * (P->n + 1) + P->n, 4,
                                    hipMemcpyDeviceToHost));
@@ -823,7 +924,7 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
             return SPMV_OK;
         }
         src = P->xs_rowptr.p;
-        want = 4 * kSlices * (P->n + 1);
+        want = 4 * P->xs_slices * (P->n + 1);
         break;
     case 6:
         if (!P->part_built) {
@@ -1011,6 +1112,27 @@ spmv_status_t spmv_quantize(const double *in, void *out, int64_t n, int32_t to, 
     return SPMV_OK;
 }
 
+spmv_status_t spmv_set_xblock_slices(spmv_plan_t P, int32_t slices) {
+    clear_error();
+    if (!P) return fail(SPMV_ERR_ARG, "NULL plan");
+    if (slices != 0 && slices != 1 && slices != 2 && slices != 4 && slices != 8)
+        return fail(SPMV_ERR_ARG, "x-block slices must be 0 (automatic), 1, 2, 4 or 8, not %d", slices);
+    if (slices == P->xs_req) return SPMV_OK;
+    P->xs_req = slices;
+    if (P->xs_built && xs_slice_count(P) != P->xs_slices) {
+        SPMV_TRY(sync(P));
+        P->xs_built = false;
+        if (P->variant == V_XBLOCK_LDS) SPMV_TRY(build_xslices(P));  // else on next use
+    }
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_release_cached_blocks(void) {
+    clear_error();
+    cache_trim(0, true);
+    return SPMV_OK;
+}
+
 spmv_status_t spmv_cache_flush(void *stream) {
     clear_error();
     return flush_cache((hipStream_t)stream);
@@ -1080,9 +1202,9 @@ spmv_status_t spmv_generate(int32_t family, const int64_t *params, int32_t n_par
         size_t need_tmp = 0;
         SPMV_TRY(lens.alloc((size_t)(n > 0 ? n : 1) * 4));
         SPMV_HIP(launch_gen_lengths(family, p, seed, n, lens.as<int32_t>(), s));
-        SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>(), d_rowptr, n, nullptr, 0, s, &need_tmp));
+        SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>(), d_rowptr, n, 1, nullptr, nullptr, 0, s, &need_tmp));
         SPMV_TRY(tmp.alloc(need_tmp));
-        SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>(), d_rowptr, n, tmp.p, tmp.bytes, s, nullptr));
+        SPMV_HIP(launch_exclusive_scan_i32(lens.as<int32_t>(), d_rowptr, n, 1, nullptr, tmp.p, tmp.bytes, s, nullptr));
         int64_t total = 0;
         const int64_t nb = (int64_t)need_tmp / 8 - 1;
         SPMV_HIP(hipMemcpyAsync(&total, tmp.as<int64_t>() + nb, 8, hipMemcpyDeviceToHost, s));

@@ -20,11 +20,13 @@ constexpr int kChunk = kBlock * kRunLen;  // nonzeros staged per LDS chunk
 constexpr int kRowStreamMaxR = 8;     // rows per thread (max) in short_row / delta16
 constexpr int kMergeIpt = 8;          // merge-path items per thread
 constexpr int kMergeTile = kBlock * kMergeIpt;
-constexpr int kSlices = 8;            // x-block column slices (one per XCD)
+constexpr int kSlices = 8;            // x-block column slices at most (one per XCD)
+constexpr int64_t kSliceXBytes = 4ll << 20;  // x bytes per slice the automatic count aims at
 constexpr int kKahanMinLen = 257;     // FP32 rows longer than 256 use Kahan sums
 constexpr int kLineBytes = 128;       // cache line assumed by the miss feature
 constexpr int64_t kLlcBytes = 256ll << 20;
 constexpr int kFeatBlocks = 1024;     // feature kernel partial records
+constexpr int kValGrid = 2048;        // validation blocks (one partial each)
 
 // ---------------------------------------------------------------- errors
 spmv_status_t fail(spmv_status_t st, const char *fmt, ...);
@@ -47,6 +49,7 @@ void clear_error();
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    int dev = 0;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -99,7 +102,9 @@ struct spmv_plan {
     bool mp_built = false;
     int64_t mp_tiles = 0;
     spmvsel::DevBuf mp_split_row, mp_split_nnz, mp_carry_row, mp_carry_val;
-    bool xs_built = false;       // x blocking: column slices, one per XCD
+    bool xs_built = false;       // x blocking: column slices (slice s on XCDs s, s+S, ...)
+    int xs_req = 0;              // requested slice count (0: from the size of x)
+    int xs_slices = 0;           // slice count S of the built format (1, 2, 4 or 8)
     int64_t xs_width = 0;        // columns per slice
     int xs_rows = 0;             // >0: row-streaming per slice with this block height; 0: merge path
     int64_t xs_nnz_off[spmvsel::kSlices] = {0}, xs_tiles[spmvsel::kSlices] = {0},
@@ -117,7 +122,9 @@ namespace spmvsel {
 // ---------------------------------------------------------------- launchers
 // validation (k_validate.hip): writes flags[0] (bit0 rowptr, bit1 col range),
 // counts[1] = descending pairs, counts[2] = descending pairs at row starts
-hipError_t launch_validate(const spmv_plan &P, uint64_t *d_flags, hipStream_t s);
+// d_part: kValGrid * 3 u64 of device scratch for per-block partials
+hipError_t launch_validate(const spmv_plan &P, uint64_t *d_flags, uint64_t *d_part,
+                           hipStream_t s);
 
 // features (k_features.hip): final record -> d_rec (16 words)
 hipError_t launch_features(const spmv_plan &P, uint64_t *d_partials, uint64_t *d_rec,
@@ -137,9 +144,13 @@ hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t pan
                            unsigned long long *d_max, hipStream_t s);
 hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,
                                int32_t *snnz, int64_t tiles, hipStream_t s);
-hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, int32_t *lens, hipStream_t s);
-hipError_t launch_max_i32(const int32_t *a, int64_t n, unsigned long long *d_max, hipStream_t s);
-hipError_t launch_slice_scatter(const spmv_plan &P, const int32_t *srp, const SliceOffsets &so,
+hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, const int32_t *srow,
+                              const int32_t *snnz, int64_t tiles, int32_t *lens, hipStream_t s);
+// d_part: 2048 int32 of device scratch for per-block maxima
+hipError_t launch_max_i32(const int32_t *a, int64_t n, int32_t *d_part,
+                          unsigned long long *d_max, hipStream_t s);
+hipError_t launch_slice_scatter(const spmv_plan &P, const int32_t *srow, const int32_t *snnz,
+                                int64_t tiles, const int32_t *srp, const SliceOffsets &so,
                                 int32_t *xci, void *xval, hipStream_t s);
 hipError_t launch_panel_windows(const spmv_plan &P, int rows_per_panel, int32_t *cmin,
                                 int32_t *cmax, int64_t panels, hipStream_t s);
@@ -169,8 +180,8 @@ hipError_t launch_gen_lengths(int family, const int64_t *prm, uint64_t seed, int
 hipError_t launch_gen_fill(int family, const int64_t *prm, uint64_t seed, int64_t n,
                            const int32_t *rowptr, int32_t *colind, double *val, hipStream_t s);
 hipError_t launch_gen_vector(int64_t n, uint64_t seed, double *x, hipStream_t s);
-hipError_t launch_exclusive_scan_i32(const int32_t *lens, int32_t *rowptr, int64_t n,
-                                     void *tmp, size_t tmp_bytes, hipStream_t s,
+hipError_t launch_exclusive_scan_i32(const int32_t *lens, int32_t *rowptr, int64_t n, int segs,
+                                     int64_t *totals, void *tmp, size_t tmp_bytes, hipStream_t s,
                                      size_t *tmp_needed);
 hipError_t launch_flush(void *buf, size_t bytes, hipStream_t s);
 hipError_t launch_read_probe(const void *buf, size_t bytes, double *sink, hipStream_t s);

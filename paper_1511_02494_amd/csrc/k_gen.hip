@@ -243,18 +243,40 @@ hipError_t launch_gen_vector(int64_t n, uint64_t seed, double *x, hipStream_t s)
     return hipGetLastError();
 }
 
-// ---- exclusive scan of row lengths into rowptr (int64 block sums; the
-// caller checks that the total fits below 2^31).
+// ---- exclusive scans of row lengths into row pointers, for `segs`
+// independent arrays at once (input s at lens + s*n, output s at
+// rowptr + s*(n+1)); int64 block sums, the caller checks that totals fit
+// below 2^31.  Per segment: tile sums, a scan of the tile sums by one block,
+// then each tile's scan.
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 
+// Exclusive scan of v over the block (all threads take part); returns this
+// thread's exclusive prefix and sets *total to the block's sum.
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t *total) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const int64_t t = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const int64_t incl = sh[threadIdx.x];
+    *total = sh[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_scan_sums(const int32_t *__restrict__ in, int64_t n,
-                                                      int64_t *__restrict__ sums) {
+                                                      int64_t nb, int64_t *__restrict__ sums) {
     __shared__ int64_t red[kBlock];
-    const int64_t base = blockIdx.x * (int64_t)kScanTile;
+    const int64_t seg = blockIdx.x / nb, b = blockIdx.x % nb;
+    in += seg * n;
+    const int64_t base = b * kScanTile;
     int64_t s = 0;
     for (int j = 0; j < kScanItems; ++j) {
-        const int64_t i = base + threadIdx.x * kScanItems + j;
+        const int64_t i = base + j * kBlock + threadIdx.x;
         if (i < n) s += in[i];
     }
     red[threadIdx.x] = s;
@@ -263,69 +285,68 @@ __global__ __launch_bounds__(kBlock) void k_scan_sums(const int32_t *__restrict_
         if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) sums[seg * (nb + 1) + b] = red[0];
 }
 
-__global__ __launch_bounds__(1) void k_scan_top(int64_t *sums, int64_t nb) {
-    int64_t run = 0;
-    for (int64_t b = 0; b < nb; ++b) {
-        const int64_t v = sums[b];
-        sums[b] = run;
-        run += v;
+__global__ __launch_bounds__(kBlock) void k_scan_top(int64_t *sums, int64_t nb, int64_t *totals) {
+    __shared__ int64_t sh[kBlock];
+    int64_t *sg = sums + blockIdx.x * (nb + 1);
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kBlock) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < nb ? sg[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan(v, sh, &tot);
+        if (i < nb) sg[i] = carry + ex;
+        carry += tot;
     }
-    sums[nb] = run;
+    if (threadIdx.x == 0) {
+        sg[nb] = carry;
+        if (totals) totals[blockIdx.x] = carry;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *__restrict__ in, int64_t n,
+                                                       int64_t nb,
                                                        const int64_t *__restrict__ sums,
                                                        int32_t *__restrict__ out) {
-    __shared__ int64_t part[kBlock];
-    const int64_t base = blockIdx.x * (int64_t)kScanTile;
-    int64_t s = 0;
+    __shared__ int64_t sh[kBlock];
+    const int64_t seg = blockIdx.x / nb, b = blockIdx.x % nb;
+    in += seg * n;
+    out += seg * (n + 1);
+    const int64_t base = b * kScanTile;
+    int64_t carry = sums[seg * (nb + 1) + b];
     for (int j = 0; j < kScanItems; ++j) {
-        const int64_t i = base + threadIdx.x * kScanItems + j;
-        if (i < n) s += in[i];
+        const int64_t i = base + j * kBlock + threadIdx.x;
+        const int64_t v = i < n ? in[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan(v, sh, &tot);
+        if (i < n) out[i + 1] = (int32_t)(carry + ex + v);
+        carry += tot;
     }
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t run = sums[blockIdx.x];
-        for (int t = 0; t < kBlock; ++t) {
-            const int64_t v = part[t];
-            part[t] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-    int64_t run = part[threadIdx.x];
-    for (int j = 0; j < kScanItems; ++j) {
-        const int64_t i = base + threadIdx.x * kScanItems + j;
-        if (i < n) {
-            run += in[i];
-            out[i + 1] = (int32_t)run;
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+    if (b == 0 && threadIdx.x == 0) out[0] = 0;
 }
 
-hipError_t launch_exclusive_scan_i32(const int32_t *lens, int32_t *rowptr, int64_t n, void *tmp,
-                                     size_t tmp_bytes, hipStream_t s, size_t *tmp_needed) {
+hipError_t launch_exclusive_scan_i32(const int32_t *lens, int32_t *rowptr, int64_t n, int segs,
+                                     int64_t *totals, void *tmp, size_t tmp_bytes, hipStream_t s,
+                                     size_t *tmp_needed) {
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    const size_t need = (size_t)(nb + 1) * 8;
+    const size_t need = (size_t)(nb + 1) * 8 * (size_t)segs;
     if (tmp_needed) *tmp_needed = need;
     if (!tmp) return hipSuccess;
-    if (tmp_bytes < need) return hipErrorInvalidValue;
+    if (tmp_bytes < need || segs < 1) return hipErrorInvalidValue;
+    if (nb == 0) {  // n == 0: every output is the single entry 0
+        hipError_t e = hipMemsetAsync(rowptr, 0, 4 * (size_t)segs, s);
+        if (e == hipSuccess) e = hipMemsetAsync(tmp, 0, need, s);  // segment totals
+        if (e == hipSuccess && totals) e = hipMemsetAsync(totals, 0, 8 * (size_t)segs, s);
+        return e;
+    }
     int64_t *sums = static_cast<int64_t *>(tmp);
-    if (nb > 0) {
-        hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(kBlock), 0, s, lens, n, sums);
-    }
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1), 0, s, sums, nb);
-    if (nb > 0) {
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, lens, n, sums, rowptr);
-    } else {
-        hipError_t e = hipMemsetAsync(rowptr, 0, 4, s);
-        if (e != hipSuccess) return e;
-    }
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)(nb * segs)), dim3(kBlock), 0, s, lens, n, nb,
+                       sums);
+    hipLaunchKernelGGL(k_scan_top, dim3((unsigned)segs), dim3(kBlock), 0, s, sums, nb, totals);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)(nb * segs)), dim3(kBlock), 0, s, lens, n, nb,
+                       sums, rowptr);
     return hipGetLastError();
 }
 

@@ -88,50 +88,107 @@ hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, in
     return hipGetLastError();
 }
 
-// ---- x blocking: column slices of width cw (slice of column c = c / cw).
-// Per row, the number of its nonzeros in each slice (columns are sorted, so
-// the slice boundaries are found by binary search inside the row).
-// Slice preparation takes rows in blocks of kBlock and streams the block's
-// nonzeros with coalesced loads; each nonzero finds its row by a search of
-// the block's row pointers held in LDS, so a long row is shared by the whole
-// block instead of falling to one thread.
-__device__ inline int block_row_of(const int32_t *s_rp, int nr, int32_t k) {
-    int lo = 0, hi = nr - 1;  // largest r with s_rp[r] <= k
+// ---- x blocking: column slices of width cw (slice of column c = c / cw,
+// the last slice also takes the remainder).  Slice preparation walks the
+// merge path of the CSR (row ends and nonzeros) in tiles of kMergeTile items
+// whose start coordinates come from k_merge_splits: a long row is shared by
+// many workgroups and a run of empty rows costs one item per row.  Each
+// thread consumes kMergeIpt consecutive items and so knows the row of every
+// nonzero it takes.  Within a row the columns are sorted, so the nonzeros of
+// one slice form one run.
+__device__ inline int slice_of(int32_t c, int64_t cw, int ns) {
+    const int64_t s = (int64_t)c / cw;
+    return s < ns - 1 ? (int)s : ns - 1;
+}
+
+// First position in [lo, hi] whose column is in slice s or later (ci[hi] is);
+// slice s > 0 starts at column s*cw whatever the slice count.
+__device__ inline int32_t run_start(const int32_t *__restrict__ ci, int32_t lo, int32_t hi, int s,
+                                    int64_t cw) {
+    if (s == 0) return lo;
+    const int64_t bound = (int64_t)s * cw;
     while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_rp[mid] <= k) lo = mid; else hi = mid - 1;
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)ci[mid] < bound) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
 
-__device__ inline int slice_of(int32_t c, int64_t cw) {
-    const int64_t s = (int64_t)c / cw;
-    return s < kSlices - 1 ? (int)s : kSlices - 1;
+struct SliceTile {
+    int32_t i0, j0, nr, nz, rs0;  // first row, first nonzero, sizes, start of row i0
+    int xi, yj, dend, it;          // this thread's walk
+};
+
+// Loads the tile's row ends into s_end[0..nr] and its columns (and the one
+// after) into s_ci[0..nz]; positions this thread on the merge path.
+__device__ inline SliceTile slice_tile_begin(int64_t tile, int64_t n, int64_t nnz,
+                                             const int32_t *__restrict__ rp,
+                                             const int32_t *__restrict__ ci,
+                                             const int32_t *__restrict__ srow,
+                                             const int32_t *__restrict__ snnz, int32_t *s_end,
+                                             int32_t *s_ci) {
+    SliceTile T;
+    T.i0 = srow[tile];
+    T.j0 = snnz[tile];
+    T.nr = srow[tile + 1] - T.i0;
+    T.nz = snnz[tile + 1] - T.j0;
+    T.rs0 = rp[T.i0];
+    for (int r = threadIdx.x; r <= T.nr; r += kBlock) {
+        const int64_t row = (int64_t)T.i0 + r;
+        s_end[r] = row < n ? rp[row + 1] : INT32_MAX;
+    }
+    for (int q = threadIdx.x; q <= T.nz; q += kBlock)
+        s_ci[q] = (int64_t)T.j0 + q < nnz ? ci[T.j0 + q] : INT32_MAX;
+    __syncthreads();
+    const int total = T.nr + T.nz;
+    const int d = (int)threadIdx.x * kMergeIpt < total ? (int)threadIdx.x * kMergeIpt : total;
+    int lo = d - T.nz > 0 ? d - T.nz : 0, hi = d < T.nr ? d : T.nr;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_end[mid] <= T.j0 + d - mid - 1) lo = mid + 1; else hi = mid;
+    }
+    T.xi = lo;
+    T.yj = d - lo;
+    T.it = d;
+    T.dend = (d + kMergeIpt) < total ? (d + kMergeIpt) : total;
+    return T;
 }
 
-// lens[s * n + i] = nonzeros of row i in column slice s (columns [s*cw, (s+1)*cw),
-// the last slice also takes the remainder).
-__global__ __launch_bounds__(kBlock) void k_slice_count(int64_t n, int64_t cw,
+// lens[s * n + i] = nonzeros of row i in slice s; lens must be zero on entry
+// (only non-empty runs are written, each by the thread holding its last
+// nonzero).
+__global__ __launch_bounds__(kBlock) void k_slice_count(int64_t n, int64_t nnz, int64_t cw, int ns,
                                                         const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ ci,
+                                                        const int32_t *__restrict__ srow,
+                                                        const int32_t *__restrict__ snnz,
                                                         int32_t *__restrict__ lens) {
-    __shared__ int32_t s_rp[kBlock + 1];
-    __shared__ int32_t s_cnt[kSlices * kBlock];
-    const int64_t r0 = (int64_t)blockIdx.x * kBlock;
-    const int nr = (int)((n - r0) < kBlock ? (n - r0) : kBlock);
-    for (int i = threadIdx.x; i <= nr; i += kBlock) s_rp[i] = rp[r0 + i];
-    for (int i = threadIdx.x; i < kSlices * kBlock; i += kBlock) s_cnt[i] = 0;
-    __syncthreads();
-    const int64_t k1 = s_rp[nr];
-    for (int64_t k = s_rp[0] + (int64_t)threadIdx.x; k < k1; k += kBlock)
-        atomicAdd(&s_cnt[slice_of(ci[k], cw) * kBlock + block_row_of(s_rp, nr, (int32_t)k)], 1);
-    __syncthreads();
-    for (int s = 0; s < kSlices; ++s)
-        if ((int)threadIdx.x < nr) lens[(int64_t)s * n + r0 + threadIdx.x] = s_cnt[s * kBlock + threadIdx.x];
+    __shared__ int32_t s_end[kMergeTile + 1];
+    __shared__ int32_t s_ci[kMergeTile + 1];
+    SliceTile T = slice_tile_begin(blockIdx.x, n, nnz, rp, ci, srow, snnz, s_end, s_ci);
+    for (; T.it < T.dend; ++T.it) {
+        if (T.yj < T.nz && T.j0 + T.yj < s_end[T.xi]) {
+            const int32_t k = T.j0 + T.yj;
+            const int s = slice_of(s_ci[T.yj], cw, ns);
+            const bool last = k + 1 == s_end[T.xi] || slice_of(s_ci[T.yj + 1], cw, ns) != s;
+            if (last) {
+                const int32_t rs = T.xi == 0 ? T.rs0 : s_end[T.xi - 1];
+                lens[(int64_t)s * n + T.i0 + T.xi] = k + 1 - run_start(ci, rs, k, s, cw);
+            }
+            ++T.yj;
+        } else {
+            ++T.xi;
+        }
+    }
 }
 
+// Maximum of a non-negative int32 array: per-block maxima into part[], then
+// one block folds them (no same-address atomics).
+constexpr int kMaxGrid = 2048;
+
 __global__ __launch_bounds__(kBlock) void k_max_i32(const int32_t *__restrict__ a, int64_t n,
-                                                    unsigned long long *mx) {
+                                                    int32_t *__restrict__ part) {
+    __shared__ int32_t sh[kBlock / 64];
     int32_t t = 0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock)
@@ -140,81 +197,117 @@ __global__ __launch_bounds__(kBlock) void k_max_i32(const int32_t *__restrict__ 
         const int32_t u = __shfl_xor(t, o, 64);
         t = u > t ? u : t;
     }
-    if ((threadIdx.x & 63) == 0 && t > 0) atomicMax(mx, (unsigned long long)t);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBlock / 64; ++q) t = sh[q] > t ? sh[q] : t;
+        part[blockIdx.x] = t;
+    }
 }
 
-hipError_t launch_max_i32(const int32_t *a, int64_t n, unsigned long long *d_max, hipStream_t s) {
-    hipError_t e = hipMemsetAsync(d_max, 0, sizeof(unsigned long long), s);
-    if (e != hipSuccess || n == 0) return e;
+__global__ __launch_bounds__(kBlock) void k_max_final(const int32_t *__restrict__ part, int np,
+                                                      unsigned long long *__restrict__ mx) {
+    __shared__ int32_t sh[kBlock / 64];
+    int32_t t = 0;
+    for (int i = threadIdx.x; i < np; i += kBlock) t = part[i] > t ? part[i] : t;
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t u = __shfl_xor(t, o, 64);
+        t = u > t ? u : t;
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBlock / 64; ++q) t = sh[q] > t ? sh[q] : t;
+        *mx = (unsigned long long)t;
+    }
+}
+
+hipError_t launch_max_i32(const int32_t *a, int64_t n, int32_t *d_part,
+                          unsigned long long *d_max, hipStream_t s) {
     int64_t g = (n + kBlock - 1) / kBlock;
-    if (g > 2048) g = 2048;
-    hipLaunchKernelGGL(k_max_i32, dim3((unsigned)g), dim3(kBlock), 0, s, a, n, d_max);
+    if (g > kMaxGrid) g = kMaxGrid;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_max_i32, dim3((unsigned)g), dim3(kBlock), 0, s, a, n, d_part);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, d_part, (int)g, d_max);
     return hipGetLastError();
 }
 
-// Copy every row's slice segments into the slice-major arrays.  Within a
-// row the segments follow in slice order, so nonzero k of row r in slice s
-// moves by the fixed amount off[s] + srp_s[r] - (rp[r] + earlier segments).
+// Copy every row's slice runs into the slice-major arrays: nonzero k of row
+// i in slice s moves to off[s] + srp_s[i] + (k - start of its run).  A thread
+// finds the start of its first run by a search inside the row; later runs it
+// meets start at the nonzero where the row or the slice changes.
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_slice_scatter(int64_t n, int64_t cw,
-                                                          const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_slice_scatter(int64_t n, int64_t nnz, int64_t cw,
+                                                          int ns, const int32_t *__restrict__ rp,
                                                           const int32_t *__restrict__ ci,
                                                           const V *__restrict__ val,
+                                                          const int32_t *__restrict__ srow,
+                                                          const int32_t *__restrict__ snnz,
                                                           const int32_t *__restrict__ srp,
                                                           SliceOffsets so,
                                                           int32_t *__restrict__ xci,
                                                           V *__restrict__ xval) {
-    __shared__ int32_t s_rp[kBlock + 1];
-    __shared__ int64_t s_shift[kSlices * kBlock];
-    const int64_t r0 = (int64_t)blockIdx.x * kBlock;
-    const int nr = (int)((n - r0) < kBlock ? (n - r0) : kBlock);
-    for (int i = threadIdx.x; i <= nr; i += kBlock) s_rp[i] = rp[r0 + i];
-    __syncthreads();
-    if ((int)threadIdx.x < nr) {
-        const int64_t i = r0 + threadIdx.x;
-        int64_t pos = s_rp[threadIdx.x];
-        for (int s = 0; s < kSlices; ++s) {
-            const int32_t *r = srp + (int64_t)s * (n + 1);
-            const int32_t a = r[i];
-            s_shift[s * kBlock + threadIdx.x] = so.off[s] + a - pos;
-            pos += r[i + 1] - a;
+    __shared__ int32_t s_end[kMergeTile + 1];
+    __shared__ int32_t s_ci[kMergeTile + 1];
+    SliceTile T = slice_tile_begin(blockIdx.x, n, nnz, rp, ci, srow, snnz, s_end, s_ci);
+    int cur_row = -1, cur_s = -1;
+    int64_t shift = 0;
+    int32_t run_end = 0;  // first position past the run's slot (writes stay inside it)
+    for (; T.it < T.dend; ++T.it) {
+        if (T.yj < T.nz && T.j0 + T.yj < s_end[T.xi]) {
+            const int32_t k = T.j0 + T.yj;
+            const int32_t c = s_ci[T.yj];
+            const int s = slice_of(c, cw, ns);
+            if (T.xi != cur_row || s != cur_s) {
+                const int32_t rs = T.xi == 0 ? T.rs0 : s_end[T.xi - 1];
+                const int32_t st = (T.xi == cur_row || k == rs) ? k : run_start(ci, rs, k, s, cw);
+                const int32_t *r = srp + (int64_t)s * (n + 1) + T.i0 + T.xi;
+                shift = so.off[s] + r[0] - st;
+                run_end = st + (r[1] - r[0]);
+                cur_row = T.xi;
+                cur_s = s;
+            }
+            if (k < run_end) {
+                xci[k + shift] = c;
+                xval[k + shift] = val[k];
+            }
+            ++T.yj;
+        } else {
+            ++T.xi;
         }
-    }
-    __syncthreads();
-    const int64_t k1 = s_rp[nr];
-    for (int64_t k = s_rp[0] + (int64_t)threadIdx.x; k < k1; k += kBlock) {
-        const int32_t c = ci[k];
-        const int64_t d = k + s_shift[slice_of(c, cw) * kBlock + block_row_of(s_rp, nr, (int32_t)k)];
-        xci[d] = c;
-        xval[d] = val[k];
     }
 }
 
-hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, int32_t *lens, hipStream_t s) {
+hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, const int32_t *srow,
+                              const int32_t *snnz, int64_t tiles, int32_t *lens, hipStream_t s) {
     if (P.n == 0) return hipSuccess;
-    const int64_t g = (P.n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_slice_count, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, cw, P.rowptr,
-                       P.colind, lens);
+    hipError_t e = hipMemsetAsync(lens, 0, (size_t)P.xs_slices * P.n * 4, s);
+    if (e != hipSuccess || tiles == 0) return e;
+    hipLaunchKernelGGL(k_slice_count, dim3((unsigned)tiles), dim3(kBlock), 0, s, P.n, P.nnz, cw,
+                       P.xs_slices, P.rowptr, P.colind, srow, snnz, lens);
     return hipGetLastError();
 }
 
-hipError_t launch_slice_scatter(const spmv_plan &P, const int32_t *srp, const SliceOffsets &so,
+hipError_t launch_slice_scatter(const spmv_plan &P, const int32_t *srow, const int32_t *snnz,
+                                int64_t tiles, const int32_t *srp, const SliceOffsets &so,
                                 int32_t *xci, void *xval, hipStream_t s) {
-    if (P.n == 0) return hipSuccess;
-    const int64_t g = (P.n + kBlock - 1) / kBlock;
+    if (P.n == 0 || tiles == 0) return hipSuccess;
     const int64_t cw = P.xs_width;
+    const dim3 g((unsigned)tiles);
     switch (P.dtype) {
     case SPMV_F64:
-        hipLaunchKernelGGL(k_slice_scatter<double>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, cw,
-                           P.rowptr, P.colind, (const double *)P.val, srp, so, xci, (double *)xval);
+        hipLaunchKernelGGL(k_slice_scatter<double>, g, dim3(kBlock), 0, s, P.n, P.nnz, cw,
+                           P.xs_slices, P.rowptr, P.colind, (const double *)P.val, srow, snnz, srp, so, xci,
+                           (double *)xval);
         break;
     case SPMV_F32:
-        hipLaunchKernelGGL(k_slice_scatter<float>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, cw,
-                           P.rowptr, P.colind, (const float *)P.val, srp, so, xci, (float *)xval);
+        hipLaunchKernelGGL(k_slice_scatter<float>, g, dim3(kBlock), 0, s, P.n, P.nnz, cw,
+                           P.xs_slices, P.rowptr, P.colind, (const float *)P.val, srow, snnz, srp, so, xci,
+                           (float *)xval);
         break;
     default:
-        hipLaunchKernelGGL(k_slice_scatter<uint16_t>, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, cw,
-                           P.rowptr, P.colind, (const uint16_t *)P.val, srp, so, xci,
+        hipLaunchKernelGGL(k_slice_scatter<uint16_t>, g, dim3(kBlock), 0, s, P.n, P.nnz, cw,
+                           P.xs_slices, P.rowptr, P.colind, (const uint16_t *)P.val, srow, snnz, srp, so, xci,
                            (uint16_t *)xval);
     }
     return hipGetLastError();

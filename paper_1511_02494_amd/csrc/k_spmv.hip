@@ -80,7 +80,7 @@ template <> struct Pair<float> { typedef float type __attribute__((ext_vector_ty
 template <> struct Pair<uint16_t> { typedef unsigned short type __attribute__((ext_vector_type(2))); };
 template <> struct Pair<int32_t> { typedef int type __attribute__((ext_vector_type(2))); };
 
-template <class V, bool D16, int R>
+template <class V, bool D16, int R, bool STAGE>
 __device__ __forceinline__ void rowstream_block(
     int64_t blk, int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const uint16_t *__restrict__ off, const int32_t *__restrict__ rbase,
@@ -94,6 +94,11 @@ __device__ __forceinline__ void rowstream_block(
     constexpr int NP = kRunLen / 2;  // pairs per thread per chunk
     __shared__ int32_t s_rp[RB + 1];
     __shared__ A s_prod[kChunk];
+    // STAGE: with several rows per thread, results are staged here and
+    // written coalesced at the end (direct stores stride lanes by R rows);
+    // pays off where y is a large share of the traffic (x-block partials)
+    constexpr bool SY = STAGE && R > 1;
+    __shared__ A s_y[SY ? RB : 1];
 
     const int64_t r0 = blk * RB;
     const int nrows = (int)((n - r0) < RB ? (n - r0) : RB);
@@ -155,7 +160,7 @@ __device__ __forceinline__ void rowstream_block(
             const int32_t lim = rend < ce ? rend : ce;
             for (; k < lim; ++k) acc.add(s_prod[k - cs], comp);
             if (k != rend) break;
-            y[r0 + myr] = acc.s;
+            if (SY) s_y[myr] = acc.s; else y[r0 + myr] = acc.s;
             acc.reset();
             ++myr;
             comp = is_f32<A>() && myr < myr_end && (s_rp[myr + 1] - s_rp[myr]) >= kKahanMinLen;
@@ -163,8 +168,12 @@ __device__ __forceinline__ void rowstream_block(
         __syncthreads();
     }
     for (; myr < myr_end; ++myr) {  // rows with no nonzeros left (all empty)
-        y[r0 + myr] = acc.s;
+        if (SY) s_y[myr] = acc.s; else y[r0 + myr] = acc.s;
         acc.reset();
+    }
+    if (SY) {
+        __syncthreads();
+        for (int r = threadIdx.x; r < nrows; r += kBlock) y[r0 + r] = s_y[r];
     }
 }
 
@@ -174,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
     const uint16_t *__restrict__ off, const int32_t *__restrict__ rbase,
     const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
     typename VT<V>::A *__restrict__ y) {
-    rowstream_block<V, D16, R>(xcd_remap(blockIdx.x, gridDim.x), n, rp, ci, off, rbase, val, x, y);
+    rowstream_block<V, D16, R, false>(xcd_remap(blockIdx.x, gridDim.x), n, rp, ci, off, rbase, val, x, y);
 }
 
 // ============================================================ merge path
@@ -217,9 +226,23 @@ __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64
         const int64_t row = (int64_t)i0 + r;
         sm.end[r] = row < n ? rp[row + 1] : INT32_MAX;
     }
-    for (int q = threadIdx.x; q < nz; q += kBlock) {
-        const int32_t kk = j0 + q;
-        sm.prod[q] = VT<V>::cvt(ld_nt(val + kk)) * x[ld_nt(ci + kk)];
+    {
+        // all of this thread's index and value loads first, then the gathers,
+        // so every load of the tile is in flight at once
+        constexpr int PPT = kMergeTile / kBlock;
+        int32_t c[PPT];
+        V v[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int q = threadIdx.x + j * kBlock;
+            c[j] = q < nz ? ld_nt(ci + j0 + q) : 0;
+            v[j] = q < nz ? ld_nt(val + j0 + q) : V(0);
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int q = threadIdx.x + j * kBlock;
+            if (q < nz) sm.prod[q] = VT<V>::cvt(v[j]) * x[c[j]];
+        }
     }
     __syncthreads();
 
@@ -314,15 +337,24 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(int64_t n, int64_t tiles
 }
 
 // ============================================================ x blocking
-// The column range is cut into kSlices equal slices, one per XCD.  Slice s
-// is a CSR matrix of its own (all rows, the nonzeros whose columns fall in
-// the slice); workgroup b runs on XCD b mod 8 and processes a merge-path tile
-// of slice b mod 8, so the part of x a slice gathers (at most 2 MB for the
-// largest workloads here) stays in that XCD's 4 MB L2 instead of being
-// fetched line by line from the Infinity Cache.  Each slice writes a partial
-// y; k_slice_sum adds the partials in slice order.
+// The column range is cut into S equal slices (S = 1, 2, 4 or 8, sized so a
+// slice of x is at most 4 MB).  Slice s is a CSR matrix of its own (all rows,
+// the nonzeros whose columns fall in the slice).  Workgroup b runs on XCD
+// x = b mod 8 and works on slice x mod S, so each XCD gathers from one slice
+// of x only, which stays in its 4 MB L2 instead of being fetched line by
+// line from the Infinity Cache; the 8/S XCDs of a slice take its row blocks
+// (or tiles) in turn.  Each slice writes a partial y; k_slice_sum adds the
+// partials in slice order.
+// Work unit (row block or tile) and slice of workgroup b.
+__device__ inline int64_t slice_unit(int ns, int *slice) {
+    const int x = blockIdx.x % 8;
+    *slice = x % ns;
+    return (int64_t)(blockIdx.x / 8) * (8 / ns) + x / ns;
+}
+
 template <class A>
 struct SliceTable {
+    int ns;  // slice count S
     const int32_t *rp[kSlices];
     const int32_t *srow[kSlices];
     const int32_t *snnz[kSlices];
@@ -339,24 +371,24 @@ __global__ __launch_bounds__(kBlock) void k_merge_slices(int64_t n, const int32_
                                                          const typename VT<V>::A *__restrict__ x,
                                                          SliceTable<typename VT<V>::A> T) {
     __shared__ MergeSmem<V> sm;
-    const int s = blockIdx.x % kSlices;
-    const int64_t tile = blockIdx.x / kSlices;
+    int s;
+    const int64_t tile = slice_unit(T.ns, &s);
     if (tile >= T.tiles[s]) return;
     merge_tile<V>(sm, tile, n, T.rp[s], ci + T.off[s], val + T.off[s], x, T.y[s], T.srow[s],
                   T.snnz[s], T.crow[s], T.cval[s]);
 }
 
-// Short slice rows: row-block streaming on each slice (block b on XCD b mod 8).
+// Short slice rows: row-block streaming on each slice.
 template <class V, int R>
 __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t nblocks,
                                                              const int32_t *__restrict__ ci,
                                                              const V *__restrict__ val,
                                                              const typename VT<V>::A *__restrict__ x,
                                                              SliceTable<typename VT<V>::A> T) {
-    const int s = blockIdx.x % kSlices;
-    const int64_t b = blockIdx.x / kSlices;
+    int s;
+    const int64_t b = slice_unit(T.ns, &s);
     if (b >= nblocks) return;
-    rowstream_block<V, false, R>(b, n, T.rp[s], ci + T.off[s], nullptr, nullptr, val + T.off[s], x,
+    rowstream_block<V, false, R, true>(b, n, T.rp[s], ci + T.off[s], nullptr, nullptr, val + T.off[s], x,
                                  T.y[s]);
 }
 
@@ -365,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup_slices(int64_t n, int64_
                                                                SliceTable<A> T) {
     const int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     const int s = (int)(g / (maxt > 0 ? maxt : 1));
-    if (s >= kSlices) return;
+    if (s >= T.ns) return;
     merge_fixup_one<A>(g % maxt, n, T.tiles[s], T.crow[s], T.cval[s], T.y[s]);
 }
 
@@ -375,8 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_slice_sum(int64_t n, SliceTable<A> T
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
         A s = T.y[0][i];
-#pragma unroll
-        for (int k = 1; k < kSlices; ++k) s = s + T.y[k][i];
+        for (int k = 1; k < T.ns; ++k) s = s + T.y[k][i];
         y[i] = s;
     }
 }
@@ -489,8 +520,10 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
         using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
         using A = typename VT<V>::A;
         SliceTable<A> T;
+        T.ns = P.xs_slices;
+        const int G = 8 / T.ns;  // XCDs per slice
         int64_t maxt = 0;
-        for (int k = 0; k < kSlices; ++k) {
+        for (int k = 0; k < T.ns; ++k) {
             T.rp[k] = P.xs_rowptr.as<int32_t>() + (size_t)k * (P.n + 1);
             T.srow[k] = P.xs_srow.as<int32_t>() + P.xs_tile_off[k] + k;
             T.snnz[k] = P.xs_snnz.as<int32_t>() + P.xs_tile_off[k] + k;
@@ -504,7 +537,7 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
         if (P.xs_rows > 0) {  // short slice rows: row-block streaming per slice
             const int R = P.xs_rows / kBlock;
             const int64_t nb = (P.n + P.xs_rows - 1) / P.xs_rows;
-            const unsigned g = (unsigned)(nb * kSlices);
+            const unsigned g = (unsigned)((nb + G - 1) / G * 8);
             const int32_t *xci = P.xs_colind.as<int32_t>();
             const V *xv = (const V *)P.xs_val.p;
             switch (R) {
@@ -517,12 +550,12 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         } else if (maxt > 0) {
-            hipLaunchKernelGGL(k_merge_slices<V>, dim3((unsigned)(maxt * kSlices)), dim3(kBlock), 0,
+            hipLaunchKernelGGL(k_merge_slices<V>, dim3((unsigned)((maxt + G - 1) / G * 8)), dim3(kBlock), 0,
                                s, P.n, P.xs_colind.as<int32_t>(), (const V *)P.xs_val.p,
                                (const A *)x, T);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
-            const unsigned g = grid_for(maxt * kSlices, kBlock, INT32_MAX);
+            const unsigned g = grid_for(maxt * T.ns, kBlock, INT32_MAX);
             hipLaunchKernelGGL(k_merge_fixup_slices<A>, dim3(g), dim3(kBlock), 0, s, P.n, maxt, T);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }

@@ -1,0 +1,151 @@
+"""rocprofv3 summaries for the selected-SpMV bench.
+
+Turns the CSV output of three rocprofv3 runs of ``bench.py`` (one
+``--kernel-trace --stats`` run, one ``--pmc FETCH_SIZE`` run, one
+``--pmc WRITE_SIZE`` run) into the short text summaries kept in ``profiles/``
+and the per-kernel traffic record ``bench.py`` reads for its roofline.
+
+HBM bytes are calibrated in the same runs: the bench's bandwidth probe reads
+a buffer of known size with ``k_read`` and copies it with ``k_copy``, so
+bytes = counter * (known bytes / counter of the probe kernel).
+
+    python -m paper_1511_02494_amd.profiling --stats DIR --fetch DIR --write DIR \\
+        --cmd-stats "..." --cmd-fetch "..." --cmd-write "..." --workload "..." \\
+        --stats-md profiles/A.md --traffic-md profiles/B.md --traffic-json profiles/C.json
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROBE_BYTES = 4 << 30  # buffer size bench.py hands to spmv_hbm_probe
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 of the HIP sources, to tell whether stored counters still apply."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1511_02494_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode() + f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(path: str, kernel_prefixes) -> float | None:
+    """HBM bytes per launch (fetch + write, summed over the given kernels)
+    from a traffic record, or None when it is missing, was taken on other
+    kernel sources, or lacks one of the kernels."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    total = 0.0
+    for name in kernel_prefixes:
+        hits = [v for k, v in rec["kernels"].items() if k.startswith(name)]
+        if not hits:
+            return None
+        total += hits[0]["fetch_bytes"] + hits[0]["write_bytes"]
+    return total
+
+
+def _one(d: str, suffix: str) -> str:
+    hits = glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def read_stats(d: str):
+    rows = []
+    with open(_one(d, "kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append(dict(name=r["Name"], calls=int(r["Calls"]),
+                             total_ms=float(r["TotalDurationNs"]) / 1e6,
+                             avg_us=float(r["AverageNs"]) / 1e3, min_us=float(r["MinNs"]) / 1e3,
+                             max_us=float(r["MaxNs"]) / 1e3, pct=float(r["Percentage"])))
+    return sorted(rows, key=lambda r: -r["total_ms"])
+
+
+def read_counter(d: str, counter: str):
+    """kernel name -> list of per-dispatch values (KiB) of one counter."""
+    out = defaultdict(list)
+    with open(_one(d, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def _short(name: str, n: int = 100) -> str:
+    return name if len(name) <= n else name[:n] + "..."
+
+
+def _find(d, prefix):
+    for k, v in d.items():
+        if k.startswith(prefix):
+            return v
+    raise SystemExit(f"calibration kernel {prefix} not in the counter run")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    for k in ("stats", "fetch", "write", "cmd-stats", "cmd-fetch", "cmd-write", "workload",
+              "stats-md", "traffic-md", "traffic-json"):
+        ap.add_argument("--" + k, required=True)
+    a = ap.parse_args(argv)
+
+    stats = read_stats(a.stats)
+    with open(a.stats_md, "w") as f:
+        f.write("# Kernel time summary: selected-SpMV bench\n\n")
+        f.write(f"Workload: {a.workload}\n\nCommand (repository root, one MI355X):\n\n"
+                f"    {a.cmd_stats}\n\n")
+        f.write("| kernel | calls | total ms | average us | min us | max us | % |\n"
+                "|---|---:|---:|---:|---:|---:|---:|\n")
+        for r in stats:
+            f.write(f"| `{_short(r['name'])}` | {r['calls']} | {r['total_ms']:.2f} | "
+                    f"{r['avg_us']:.1f} | {r['min_us']:.1f} | {r['max_us']:.1f} | "
+                    f"{r['pct']:.2f} |\n")
+
+    fetch = read_counter(a.fetch, "FETCH_SIZE")
+    write = read_counter(a.write, "WRITE_SIZE")
+    rd = _find(fetch, "spmvsel::k_read")
+    cp = _find(write, "spmvsel::k_copy")
+    kib = PROBE_BYTES / 1024
+    fscale = kib / (sum(rd) / len(rd))
+    wscale = kib / (sum(cp) / len(cp))
+    kernels = {}
+    for name in sorted(set(fetch) | set(write)):
+        fv, wv = fetch.get(name, []), write.get(name, [])
+        fk = sum(fv) / len(fv) if fv else 0.0
+        wk = sum(wv) / len(wv) if wv else 0.0
+        kernels[name] = dict(dispatches=max(len(fv), len(wv)), fetch_kib=fk, write_kib=wk,
+                             fetch_bytes=fk * 1024 * fscale, write_bytes=wk * 1024 * wscale)
+    rec = dict(source_sha256=kernel_source_hash(), fetch_scale=fscale, write_scale=wscale,
+               probe_bytes=PROBE_BYTES, commands=[a.cmd_fetch, a.cmd_write], kernels=kernels)
+    with open(a.traffic_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    with open(a.traffic_md, "w") as f:
+        f.write("# HBM traffic per dispatch (rocprofv3 PMC): selected-SpMV bench\n\n")
+        f.write(f"Workload: {a.workload}\n\nCommands (repository root, one MI355X), one counter "
+                f"per run:\n\n    {a.cmd_fetch}\n    {a.cmd_write}\n\n")
+        f.write(f"Calibration in the same runs (bandwidth probe, {PROBE_BYTES >> 30} GiB buffer): "
+                f"`k_read` FETCH_SIZE scale {fscale:.3f}, `k_copy` WRITE_SIZE scale "
+                f"{wscale:.3f} (true bytes per counter byte). Mean per dispatch.\n\n")
+        f.write("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled fetch MB | "
+                "scaled write MB |\n|---|---:|---:|---:|---:|---:|\n")
+        for name, v in kernels.items():
+            f.write(f"| `{_short(name)}` | {v['dispatches']} | {v['fetch_kib']:.0f} | "
+                    f"{v['write_kib']:.0f} | {v['fetch_bytes'] / 1e6:.1f} | "
+                    f"{v['write_bytes'] / 1e6:.1f} |\n")
+    print(f"wrote {a.stats_md}, {a.traffic_md}, {a.traffic_json}")
+
+
+if __name__ == "__main__":
+    main()

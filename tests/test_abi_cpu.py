@@ -76,3 +76,10 @@ def test_plan_create_argument_errors():
     with pytest.raises(S.SpmvError):
         S.spmv_plan_create(4, 4, 4, 16, 8, 16, S.SPMV_F64, 0)   # misaligned colind
     S.spmv_plan_destroy(None)
+
+
+def test_null_plan_arguments():
+    for fn, args in [(S.spmv_set_xblock_slices, (None, 4)), (S.spmv_set_variant, (None, 1))]:
+        with pytest.raises(S.SpmvError) as e:
+            fn(*args)
+        assert e.value.status == S.SPMV_ERR_ARG

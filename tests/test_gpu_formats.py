@@ -45,12 +45,15 @@ def test_formats_match_oracle(name, build, m):
     if n + nnz < 200000:
         wi, wj = merge_walk_ref(rp, T)
         assert np.array_equal(wi, si) and np.array_equal(wj, sj)
-    nsl = S.spmv_plan_query(h, 7)
-    rps, cx = slice_csr_ref(rp, ci, m, nsl)
-    assert np.array_equal(S.spmv_plan_copy_format(h, 4, nsl * (n + 1)), rps.reshape(-1))
-    assert np.array_equal(S.spmv_plan_copy_format(h, 5, nnz), cx)
-    tiles = sum((n + int(r[-1]) + T - 1) // T for r in rps)
-    assert S.spmv_plan_query(h, 6) == tiles
+    for forced in (0, 8, 2):
+        S.spmv_set_xblock_slices(h, forced)
+        nsl = S.spmv_plan_query(h, 7)
+        assert forced == 0 or nsl == forced
+        rps, cx = slice_csr_ref(rp, ci, m, nsl)
+        assert np.array_equal(S.spmv_plan_copy_format(h, 4, nsl * (n + 1)), rps.reshape(-1))
+        assert np.array_equal(S.spmv_plan_copy_format(h, 5, nnz), cx)
+        tiles = sum((n + int(r[-1]) + T - 1) // T for r in rps)
+        assert S.spmv_plan_query(h, 6) == tiles
     parts = S.spmv_plan_query(h, 8)
     assert np.array_equal(S.spmv_plan_copy_format(h, 6, parts + 1), partition_ref(rp, parts))
     plan.close()

@@ -136,3 +136,44 @@ def test_copy_inputs_flag():
     y_ref, s = spmv_exact(rp, ci, v, x)
     assert within_tolerance(y, y_ref, s, 1e-12)[0]
     plan.close()
+
+
+@pytest.mark.parametrize("slices", [1, 2, 4, 8])
+@pytest.mark.parametrize("case", ["stencil27_12", "random_3000x8", "powerlaw_20000", "ragged",
+                                  "one_long_row", "empty_rows", "shortrows_5000"])
+def test_xblock_every_slice_count(case, slices):
+    """x blocking with each forced slice count (small matrices pick 1 slice by
+    themselves): row-streaming and merge-path slice kernels, both dtypes paths."""
+    build, m = CASES[case]
+    rp, ci, v = build("random")
+    x = synth.vector(m, 13)
+    y_ref, scale = spmv_exact(rp, ci, v, x)
+    for dtype in (S.SPMV_F64, S.SPMV_F32):
+        plan = make_plan(rp, ci, v, m, dtype)
+        S.spmv_set_xblock_slices(plan.handle, slices)
+        y = run(plan, S.V_XBLOCK_LDS, x, dtype)
+        assert S.spmv_plan_query(plan.handle, 7) == slices
+        ok, worst = within_tolerance(y, y_ref, scale, TOL[dtype])
+        assert ok, (slices, dtype, worst)
+        assert np.array_equal(y, run(plan, S.V_XBLOCK_LDS, x, dtype))
+        plan.close()
+
+
+def test_xblock_slice_count_change_rebuilds():
+    rp, ci, v = CASES["powerlaw_20000"][0]("int")
+    x = synth.int_vector(20000, 14)
+    y_seq = spmv_seq(rp, ci, v, x)
+    plan = make_plan(rp, ci, v, 20000)
+    y1 = run(plan, S.V_XBLOCK_LDS, x)
+    for k in (8, 2, 0, 4):
+        S.spmv_set_xblock_slices(plan.handle, k)  # active variant: rebuilt at once
+        xt = torch.from_numpy(np.asarray(x, np.float64)).to("cuda:0")
+        y = torch.full((plan.n,), float("nan"), dtype=torch.float64, device="cuda:0")
+        plan.execute(xt, y)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), y_seq), k
+    assert np.array_equal(y1, y_seq)
+    with pytest.raises(S.SpmvError) as e:
+        S.spmv_set_xblock_slices(plan.handle, 3)
+    assert e.value.status == S.SPMV_ERR_ARG
+    plan.close()
