@@ -253,27 +253,41 @@ def main():
     if not args.no_cpu:
         from oracle import cref
         cref.build()
-        tb, tt = 0, 0.0
-        reps = []
+
+        def time_oracle(threads, budget):
+            tb, tt, reps, used = 0, 0.0, [], 1
+            for sp, (rp, ci, val, x) in zip(specs, host_mats):
+                n = len(rp) - 1
+                b = 4 * (n + 1) + 12 * len(ci) + 16 * n
+                k, t_m = 0, 0.0
+                while t_m < budget / len(specs) or k < 3:
+                    t0 = time.perf_counter()
+                    _, used = cref.spmv(rp, ci, val, x, threads=threads)
+                    t_m += time.perf_counter() - t0
+                    k += 1
+                tb += b * k
+                tt += t_m
+                reps.append(f"{sp.name} x{k}")
+                log(f"cpu oracle ({used} threads) {sp.name}: {k} SpMVs in {t_m:.1f} s")
+            return tb / tt * 1e-9, used, reps, tt
+
+        host_mats = []
         for sp in specs:
             rp, ci, val = sp.build()
-            x = sp.x(len(rp) - 1)
-            n = len(rp) - 1
-            b = 4 * (n + 1) + 12 * len(ci) + 16 * n
-            k, t_m = 0, 0.0
-            while t_m < args.cpu_seconds / len(specs) or k < 2:  # about the budget per matrix
-                t0 = time.perf_counter()
-                cref.spmv(rp, ci, val, x)
-                t_m += time.perf_counter() - t0
-                k += 1
-            tb += b * k
-            tt += t_m
-            reps.append(f"{sp.name} x{k}")
-            log(f"cpu oracle {sp.name}: {k} SpMVs in {t_m:.1f} s")
-        cpu = {"value": tb / tt * 1e-9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": "repeated single-threaded SpMVs of the plain C oracle loop on the four "
-                         f"bench matrices ({', '.join(reps)}; {tt:.1f} s of CPU time); bytes "
-                         "counted as for the GPU, selection not included",
+            host_mats.append((np.ascontiguousarray(rp, np.int32), np.ascontiguousarray(ci, np.int32),
+                              np.ascontiguousarray(val, np.float64),
+                              np.ascontiguousarray(sp.x(len(rp) - 1), np.float64)))
+        v1, _, reps1, t1 = time_oracle(False, 0.6 * args.cpu_seconds)
+        vm, used, repsm, tm = time_oracle(True, 0.4 * args.cpu_seconds)
+        note = ("bytes counted as for the GPU (4(N+1) + 12 NNZ + 16 N), selection not "
+                "included; matrices built by the seeded host generator")
+        cpu = {"value": vm, "unit": "GB/s", "cores": used, "kind": "oracle",
+               "sample": "repeated SpMVs of the plain C oracle loop, OpenMP static partition "
+                         f"with equal nonzeros per thread, on the four bench matrices "
+                         f"({', '.join(repsm)}; {tm:.1f} s); " + note,
+               "single_thread": {"value": v1, "unit": "GB/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"same loop, one thread ({', '.join(reps1)}; "
+                                           f"{t1:.1f} s)"},
                "cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
 
     out = {
