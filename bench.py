@@ -67,6 +67,58 @@ def kernel_names(v, plan):
     return [f"void spmvsel::k_rowstream<double, false, {plan.query(2) // 256}>"]
 
 
+def precision_report(S, torch, dev, mats, per, log):
+    """FP32 and BF16 stored values (FP32 x, FP32 accumulation, Kahan on rows
+    longer than 256) on each class matrix, with int32 indices (the FP64
+    selection, or short_row where that is delta16) and with delta16 where it
+    is feasible: time and GB/s against the FP64 path on the same variant, and
+    max_i |y_i - y64_i| / sum_j |a_ij| |x_j| against the library's FP64 result
+    (the tests pin that to the CPU oracle)."""
+    out = []
+    for M, rec in zip(mats, per):
+        n, nnz = M["n"], M["nnz"]
+        sel_v = S.VARIANTS.index(rec["selected"])
+        variants = [S.V_SHORT_ROW if sel_v == S.V_DELTA16 else sel_v]
+        if (M["mask"] >> S.V_DELTA16) & 1:
+            variants.append(S.V_DELTA16)
+        p64 = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=nnz)
+        p64.set_variant(S.V_CSR_SCALAR)
+        y64 = torch.empty(n, dtype=torch.float64, device=dev)
+        p64.execute(M["x"], y64)
+        pa = S.Plan(M["rp"], M["ci"], M["val"].abs(), M["m"], nnz=nnz)
+        pa.set_variant(S.V_CSR_SCALAR)
+        scale = torch.empty(n, dtype=torch.float64, device=dev)
+        pa.execute(M["x"].abs(), scale)
+        torch.cuda.synchronize()
+        pa.close()
+        x32 = M["x"].float()
+        t64 = {v: p64.time(v, reps=20)[0] for v in variants}
+        for dt, dname, tdt in ((S.SPMV_F32, "f32", torch.float32), (S.SPMV_BF16, "bf16", torch.int16)):
+            vq = torch.empty(nnz + 8, dtype=tdt, device=dev)
+            S.spmv_quantize(M["val"], vq, nnz, dt)
+            pq = S.Plan(M["rp"], M["ci"], vq, M["m"], dt, nnz=nnz)
+            for v in variants:
+                tq, _ = pq.time(v, reps=20)
+                pq.set_variant(v)
+                yq = torch.empty(n, dtype=torch.float32, device=dev)
+                pq.execute(x32, yq)
+                err = (yq.double() - y64).abs()
+                rel = torch.where(scale > 0, err / scale.clamp_min(1e-300), err)
+                r = dict(matrix=M["name"], values=dname, variant=S.VARIANTS[v],
+                         index="delta16" if v == S.V_DELTA16 else "int32",
+                         us=tq * 1e6, gbs=pq.bytes(v) / tq * 1e-9,
+                         f64_us=t64[v] * 1e6, f64_gbs=p64.bytes(v) / t64[v] * 1e-9,
+                         speedup_vs_f64=t64[v] / tq, max_rel_err=float(rel.max()))
+                out.append(r)
+                log(f"  precision {M['name']:>22s} {dname:>4s} {r['variant']:>10s} "
+                    f"{r['us']:7.1f} us ({r['gbs']:5.0f} GB/s; FP64 {r['f64_us']:7.1f} us) "
+                    f"max err / sum|a||x| = {r['max_rel_err']:.2e}")
+            pq.close()
+            del vq
+        p64.close()
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +128,7 @@ def parse():
     ap.add_argument("--selector", default="mlp", choices=["mlp", "profiling", "exhaustive"])
     ap.add_argument("--scale", type=int, default=1, help="divide matrix sizes (testing only)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32/BF16 report")
     ap.add_argument("--cpu-seconds", type=float, default=16.0,
                     help="CPU time budget of the oracle baseline (all four matrices)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant timing table")
@@ -240,6 +293,8 @@ def main():
             f"{rec['spmv_gbs']:6.0f} GB/s; selection {sel_cost * 1e3:.2f} ms "
             f"= {rec['selection_spmv_equivs']:.1f} SpMVs")
 
+    precision = [] if args.no_precision else precision_report(S, torch, dev, mats, per, log)
+
     value = total_bytes / t_total * 1e-9
     dom = max(range(len(per)), key=lambda i: per[i]["spmv_us"])
     d = per[dom]
@@ -304,6 +359,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "hbm_probe": {"read_gbs": read_gbs, "copy_gbs": copy_gbs},
+        "precision": precision,
         "per_matrix": per,
     }
     print(json.dumps(out), flush=True)

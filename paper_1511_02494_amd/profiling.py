@@ -12,6 +12,8 @@ bytes = counter * (known bytes / counter of the probe kernel).
     python -m paper_1511_02494_amd.profiling --stats DIR --fetch DIR --write DIR \\
         --cmd-stats "..." --cmd-fetch "..." --cmd-write "..." --workload "..." \\
         --stats-md profiles/A.md --traffic-md profiles/B.md --traffic-json profiles/C.json
+    python -m paper_1511_02494_amd.profiling counters --dirs D1 D2 --cmds "..." "..." \\
+        --kernels PREFIX... --title "..." --out profiles/D.md
 """
 from __future__ import annotations
 
@@ -94,7 +96,46 @@ def _find(d, prefix):
     raise SystemExit(f"calibration kernel {prefix} not in the counter run")
 
 
+def counters_main(argv):
+    """Per-kernel means of arbitrary counters from several --pmc runs."""
+    ap = argparse.ArgumentParser(prog="profiling counters")
+    ap.add_argument("--dirs", nargs="+", required=True)
+    ap.add_argument("--cmds", nargs="+", required=True)
+    ap.add_argument("--kernels", nargs="+", required=True, help="kernel name prefixes to report")
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--notes", default="")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    vals = defaultdict(lambda: defaultdict(list))
+    order = []
+    for d in a.dirs:
+        with open(_one(d, "counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                c = r["Counter_Name"]
+                if c not in order:
+                    order.append(c)
+                vals[r["Kernel_Name"]][c].append(float(r["Counter_Value"]))
+    with open(a.out, "w") as f:
+        f.write(f"# {a.title}\n\nCommands (repository root, one MI355X), one counter group per "
+                "run:\n\n" + "".join(f"    {c}\n" for c in a.cmds) + "\n")
+        if a.notes:
+            f.write(a.notes + "\n\n")
+        f.write("Mean per dispatch (rocprofv3 sums each counter over the device).\n\n")
+        f.write("| kernel | " + " | ".join(order) + " |\n|---|" + "---:|" * len(order) + "\n")
+        for name in sorted(vals):
+            if not any(name.startswith(k) for k in a.kernels):
+                continue
+            row = [sum(vals[name][c]) / len(vals[name][c]) if vals[name][c] else float("nan")
+                   for c in order]
+            f.write(f"| `{_short(name, 60)}` | " + " | ".join(f"{v:.4g}" for v in row) + " |\n")
+    print(f"wrote {a.out}")
+
+
 def main(argv=None):
+    import sys
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "counters":
+        return counters_main(argv[1:])
     ap = argparse.ArgumentParser()
     for k in ("stats", "fetch", "write", "cmd-stats", "cmd-fetch", "cmd-write", "workload",
               "stats-md", "traffic-md", "traffic-json"):
