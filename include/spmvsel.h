@@ -79,7 +79,9 @@ typedef enum { K_CML = 0, K_MB = 1, K_IMB = 2, K_CMP = 3 } spmv_class_t;
 typedef enum {
     SEL_PROFILING = 0,  /* micro-benchmarks + threshold cascade (Section 3.2.1) */
     SEL_MLP = 1,        /* features + MLP; falls back to SEL_PROFILING */
-    SEL_EXHAUSTIVE = 2  /* time every feasible variant, keep the fastest */
+    SEL_EXHAUSTIVE = 2, /* time every feasible variant, keep the fastest */
+    SEL_DTREE = 3,      /* features + CART decision tree; falls back to SEL_PROFILING */
+    SEL_GNB = 4         /* features + Gaussian naive Bayes; falls back to SEL_PROFILING */
 } spmv_selector_t;
 
 /* plan_create flags */
@@ -92,9 +94,10 @@ typedef enum {
 /* Result of spmv_select. */
 typedef struct {
     int32_t variant;        /* chosen spmv_variant_t */
-    int32_t klass;          /* spmv_class_t from the profiling cascade, or -1 */
+    int32_t klass;          /* spmv_class_t from the profiling cascade or from a
+                               class-labelled feature classifier, or -1 */
     int32_t selector;       /* selector actually used (after any fallback) */
-    int32_t fell_back;      /* 1 if SEL_MLP fell back to SEL_PROFILING */
+    int32_t fell_back;      /* 1 if SEL_MLP / SEL_DTREE / SEL_GNB fell back to SEL_PROFILING */
     uint32_t feasible;      /* bit v set if variant v can run this matrix */
     float margin;           /* MLP top1 - top2 logit (0 if not run) */
     float logits[6];        /* MLP logits (0 if not run) */
@@ -279,6 +282,69 @@ spmv_status_t spmv_mlp_forward_backward(const float *d_params, const float *d_Z,
 spmv_status_t spmv_mlp_adam_step(float *d_params, const float *d_grads, float *d_m,
                                  float *d_v, int32_t n, int32_t step, float lr,
                                  float b1, float b2, float eps, void *stream);
+
+/* ----------------------------------------------------------------------- */
+/* The paper's feature classifiers (Section 3.2.2, Tables 4 and 5)          */
+/*
+ * A CART decision tree (Gini criterion) and Gaussian naive Bayes over the
+ * twelve features of spmv_features.  Labels are either variants
+ * (SPMV_LABEL_VARIANT, 6 classes, the label kind of the MLP) or bottleneck
+ * classes (SPMV_LABEL_CLASS, 4 classes CML/MB/IMB/CMP as the profiling
+ * cascade assigns them, mapped to a variant through Table 2 with the current
+ * thresholds).  Fitting is host code; prediction for selection runs on the
+ * device.  Arrays are host memory, row-major, owned by the caller.
+ *
+ * CART: a node splits on feature j at t (left x_j <= t); thresholds lie
+ * between consecutive distinct values a < b (t = a/2 + b/2, or a if that
+ * rounds out of [a, b)); children keep >= min_leaf samples; the split with
+ * the lowest weighted Gini impurity wins (compared exactly; first in
+ * (feature, threshold) order on ties) and must lower the impurity strictly.
+ * Leaves: depth max_depth (root 0), pure, < 2 min_leaf samples, no split.
+ * Nodes are in pre-order; feature[i] = -1 marks a leaf; counts[i][k] are
+ * the training samples of class k under node i.  A prediction is the
+ * feasible class with the largest leaf count (lowest on ties).
+ *
+ * Naive Bayes on g_k = plog2(1 + f_k) (k < 8; plog2 as for the MLP) or f_k:
+ * mu, var per class (population, sums in sample order) + 1e-9 times the
+ * largest feature variance; stored w = 0.5 / var, c = log(n_k / n) -
+ * 0.5 sum_j log(2 pi var).  Score c_k - sum_j w_kj (g_j - mu_kj)^2. */
+typedef enum { SPMV_CLF_DTREE = 0, SPMV_CLF_GNB = 1 } spmv_classifier_t;
+typedef enum { SPMV_LABEL_VARIANT = 0, SPMV_LABEL_CLASS = 1 } spmv_label_kind_t;
+
+/* Fit a tree on X[n][12] with labels y[n] in [0, n_classes) (n_classes <= 8,
+ * max_depth <= 64, min_leaf >= 1).  Outputs have room for max_nodes nodes
+ * (counts: max_nodes x n_classes); *n_nodes receives the node count.
+ * SPMV_ERR_ARG if the tree would need more nodes, or on bad input. */
+spmv_status_t spmv_dtree_fit(const double *X, const int32_t *y, int64_t n, int32_t n_classes,
+                             int32_t max_depth, int32_t min_leaf, int32_t max_nodes,
+                             int32_t *feature, double *threshold, int32_t *left, int32_t *right,
+                             int32_t *counts, int32_t *n_nodes);
+
+/* Fit naive Bayes on raw features F[n][12]: mu[n_classes][12],
+ * w[n_classes][12], c[n_classes], count[n_classes] (classes without
+ * samples have count 0 and are never predicted). */
+spmv_status_t spmv_gnb_fit(const double *F, const int32_t *y, int64_t n, int32_t n_classes,
+                           double *mu, double *w, double *c, int32_t *count);
+
+/* Install the process-wide models used by SEL_DTREE / SEL_GNB (copied; the
+ * tree's structure is checked: pre-order children, features in range).
+ * n_classes must be 6 for SPMV_LABEL_VARIANT and 4 for SPMV_LABEL_CLASS. */
+spmv_status_t spmv_dtree_load(int32_t n_nodes, int32_t n_classes, int32_t label_kind,
+                              const int32_t *feature, const double *threshold, const int32_t *left,
+                              const int32_t *right, const int32_t *counts);
+spmv_status_t spmv_gnb_load(int32_t n_classes, int32_t label_kind, const double *mu,
+                            const double *w, const double *c, const int32_t *count);
+spmv_status_t spmv_classifier_unload(int32_t which);
+
+/* Device inference of a loaded classifier (synchronous).  variant: the
+ * selected variant; label: the predicted class index (variant or bottleneck
+ * class); fallback: 1 if no feasible class has support (the selector then
+ * falls back to profiling); leaf: the tree leaf (-1 for naive Bayes);
+ * scores: the naive Bayes scores s_k (8 slots; zeros for the tree).  Output
+ * pointers may be NULL.  SPMV_ERR_NO_MODEL if the classifier is not loaded. */
+spmv_status_t spmv_classifier_predict(int32_t which, const double features[12], uint32_t feasible,
+                                      int32_t *variant, int32_t *label, int32_t *fallback,
+                                      int32_t *leaf, double scores[8]);
 
 /* ----------------------------------------------------------------------- */
 /* Utilities                                                                */

@@ -26,7 +26,9 @@ SPMV_F64, SPMV_F32, SPMV_BF16 = range(3)
 V_CSR_SCALAR, V_CSR_VECTOR, V_MERGE_PATH, V_DELTA16, V_XBLOCK_LDS, V_SHORT_ROW = range(6)
 VARIANTS = ["csr_scalar", "csr_vector", "merge_path", "delta16", "xblock_lds", "short_row"]
 CLASSES = ["CML", "MB", "IMB", "CMP"]
-SEL_PROFILING, SEL_MLP, SEL_EXHAUSTIVE = range(3)
+SEL_PROFILING, SEL_MLP, SEL_EXHAUSTIVE, SEL_DTREE, SEL_GNB = range(5)
+SPMV_CLF_DTREE, SPMV_CLF_GNB = range(2)
+SPMV_LABEL_VARIANT, SPMV_LABEL_CLASS = range(2)
 SPMV_COPY_INPUTS, SPMV_SKIP_VALIDATE = 1, 2
 FEATURE_NAMES = ["N", "NNZ", "nnz_avg", "nnz_sd", "nnz_max", "nnz_min", "bw_avg", "bw_sd",
                  "dispersion_avg", "dispersion_sd", "miss_per_nnz", "size"]
@@ -82,6 +84,12 @@ _PROTOS = {
     "spmv_quantize": (_I32, [_P, _P, _I64, _I32, _P]),
     "spmv_generate": (_I32, [_I32, _PI64, _I32, _U64, _P, _P, _P, _PI64, _P]),
     "spmv_generate_vector": (_I32, [_I64, _U64, _P, _P]),
+    "spmv_dtree_fit": (_I32, [_P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _PI32]),
+    "spmv_gnb_fit": (_I32, [_P, _P, _I64, _I32, _P, _P, _P, _P]),
+    "spmv_dtree_load": (_I32, [_I32, _I32, _I32, _P, _P, _P, _P, _P]),
+    "spmv_gnb_load": (_I32, [_I32, _I32, _P, _P, _P, _P]),
+    "spmv_classifier_unload": (_I32, [_I32]),
+    "spmv_classifier_predict": (_I32, [_I32, _PF64, _U32, _PI32, _PI32, _PI32, _PI32, _PF64]),
     "spmv_release_cached_blocks": (_I32, []),
     "spmv_cache_flush": (_I32, [_P]),
     "spmv_hbm_probe": (_I32, [_I64, _PF64, _PF64]),
@@ -312,6 +320,89 @@ def spmv_generate(family: int, params, seed: int, rowptr, colind=None, val=None,
 
 def spmv_generate_vector(n: int, seed: int, x, stream=None):
     _check("spmv_generate_vector", lib.spmv_generate_vector(n, seed, _addr(x), _stream(stream)))
+
+
+# ------------------------------------------------- the paper's feature classifiers
+
+
+def _np(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(_P)
+
+
+def spmv_dtree_fit(X, y, n_classes: int, max_depth: int, min_leaf: int, max_nodes: int | None = None):
+    """CART fit on X[n, 12]; returns dict(feature, threshold, left, right, counts) (numpy)."""
+    X, px = _np(X, np.float64)
+    y, py = _np(y, np.int32)
+    n = len(y)
+    cap = max_nodes or 2 * n + 1
+    out = dict(feature=np.empty(cap, np.int32), threshold=np.empty(cap, np.float64),
+               left=np.empty(cap, np.int32), right=np.empty(cap, np.int32),
+               counts=np.empty((cap, n_classes), np.int32))
+    nn = _I32()
+    _check("spmv_dtree_fit", lib.spmv_dtree_fit(
+        px, py, n, n_classes, max_depth, min_leaf, cap,
+        *(out[k].ctypes.data_as(_P) for k in ("feature", "threshold", "left", "right", "counts")),
+        ctypes.byref(nn)))
+    return {k: v[:nn.value].copy() for k, v in out.items()}
+
+
+def spmv_gnb_fit(F, y, n_classes: int):
+    """Gaussian naive Bayes fit on raw features F[n, 12]; dict(mu, w, c, count)."""
+    F, pf = _np(F, np.float64)
+    y, py = _np(y, np.int32)
+    out = dict(mu=np.empty((n_classes, 12)), w=np.empty((n_classes, 12)), c=np.empty(n_classes),
+               count=np.empty(n_classes, np.int32))
+    _check("spmv_gnb_fit", lib.spmv_gnb_fit(pf, py, len(y), n_classes,
+                                            *(out[k].ctypes.data_as(_P) for k in ("mu", "w", "c", "count"))))
+    return out
+
+
+def spmv_dtree_load(tree, label_kind: int = SPMV_LABEL_VARIANT):
+    arrs = [_np(tree["feature"], np.int32), _np(tree["threshold"], np.float64),
+            _np(tree["left"], np.int32), _np(tree["right"], np.int32), _np(tree["counts"], np.int32)]
+    counts = np.asarray(tree["counts"])
+    _check("spmv_dtree_load", lib.spmv_dtree_load(len(tree["feature"]), counts.shape[1], label_kind,
+                                                  *(p for _, p in arrs)))
+
+
+def spmv_gnb_load(model, label_kind: int = SPMV_LABEL_VARIANT):
+    arrs = [_np(model["mu"], np.float64), _np(model["w"], np.float64), _np(model["c"], np.float64),
+            _np(model["count"], np.int32)]
+    _check("spmv_gnb_load", lib.spmv_gnb_load(len(model["c"]), label_kind, *(p for _, p in arrs)))
+
+
+def spmv_classifier_unload(which: int):
+    _check("spmv_classifier_unload", lib.spmv_classifier_unload(which))
+
+
+def spmv_classifier_predict(which: int, features, feasible: int = 63) -> dict:
+    f = _darr([float(v) for v in features], _F64)
+    v, lab, fb, leaf = _I32(), _I32(), _I32(), _I32()
+    sc = (_F64 * 8)()
+    _check("spmv_classifier_predict", lib.spmv_classifier_predict(
+        which, f, feasible, ctypes.byref(v), ctypes.byref(lab), ctypes.byref(fb), ctypes.byref(leaf), sc))
+    return dict(variant=v.value, label=lab.value, fallback=bool(fb.value), leaf=leaf.value,
+                scores=list(sc))
+
+
+DTREE_MODEL = os.path.join(_HERE, "dtree_selector.json")
+GNB_MODEL = os.path.join(_HERE, "gnb_selector.json")
+
+
+def load_classifiers(dtree: str = DTREE_MODEL, gnb: str = GNB_MODEL) -> list:
+    """Install the stored CART and naive Bayes selectors (for SEL_DTREE / SEL_GNB);
+    returns the names of those found."""
+    import json
+    got = []
+    for path, loader, name in ((dtree, spmv_dtree_load, "dtree"), (gnb, spmv_gnb_load, "gnb")):
+        if os.path.exists(path):
+            with open(path) as f:
+                m = json.load(f)
+            kind = SPMV_LABEL_VARIANT if m.pop("label_kind") == "variant" else SPMV_LABEL_CLASS
+            loader({k: np.asarray(v) for k, v in m.items()}, kind)
+            got.append(name)
+    return got
 
 
 def spmv_release_cached_blocks():

@@ -212,7 +212,8 @@ spmv_status_t sync(const spmv_plan *P) {
 // scratch layout (bytes)
 constexpr size_t kOffFlags = 0;                       // 3 u64
 constexpr size_t kOffRec = 256;                       // 16 u64
-constexpr size_t kOffSum = 512;                       // 1 u64
+constexpr size_t kOffSum = 512;                       // 9 u64: a maximum, slice totals
+constexpr size_t kOffClf = 768;                       // 80 bytes: classifier output
 constexpr size_t kOffMlp = 1024;                      // 64 floats
 constexpr size_t kOffPart = 4096;                     // kFeatBlocks * 16 u64
 constexpr size_t kScratchBytes = kOffPart + kFeatBlocks * 16 * 8;
@@ -596,6 +597,18 @@ spmv_status_t profile_measure(spmv_plan *P, int reps, double meas[5]) {
 
 double ratio(double a, double b) { return b > 0 ? a / b : 0.0; }
 
+}  // namespace
+
+// Table 2 on the GPU: the optimisation for a bottleneck class.
+int class_variant(int k, const double feats[12], const double th[4], uint32_t feas) {
+    if (k == K_CML) return (feas >> V_XBLOCK_LDS) & 1 ? V_XBLOCK_LDS : V_CSR_VECTOR;
+    if (k == K_MB) return (feas >> V_DELTA16) & 1 ? V_DELTA16 : V_CSR_VECTOR;
+    if (k == K_IMB) return V_MERGE_PATH;
+    return feats[2] <= th[3] ? V_SHORT_ROW : V_CSR_VECTOR;
+}
+
+namespace {
+
 void cascade(const double meas[5], const double feats[12], const double th[4], uint32_t feas,
              int32_t *variant, int32_t *klass, double scores[3]) {
     const double s[3] = {ratio(meas[0], meas[1]), ratio(meas[2], meas[0]), ratio(meas[3], meas[4])};
@@ -609,12 +622,7 @@ void cascade(const double meas[5], const double feats[12], const double th[4], u
             break;
         }
     }
-    int v;
-    if (k == K_CML) v = (feas >> V_XBLOCK_LDS) & 1 ? V_XBLOCK_LDS : V_CSR_VECTOR;
-    else if (k == K_MB) v = (feas >> V_DELTA16) & 1 ? V_DELTA16 : V_CSR_VECTOR;
-    else if (k == K_IMB) v = V_MERGE_PATH;
-    else v = feats[2] <= th[3] ? V_SHORT_ROW : V_CSR_VECTOR;
-    *variant = v;
+    *variant = class_variant(k, feats, th, feas);
     *klass = k;
     if (scores)
         for (int i = 0; i < 3; ++i) scores[i] = s[i];
@@ -975,7 +983,7 @@ spmv_status_t spmv_get_thresholds(double theta[4]) {
 spmv_status_t spmv_select(spmv_plan_t P, int32_t selector, spmv_select_info_t *info) {
     clear_error();
     if (!P) return fail(SPMV_ERR_ARG, "plan is NULL");
-    if (selector < SEL_PROFILING || selector > SEL_EXHAUSTIVE)
+    if (selector < SEL_PROFILING || selector > SEL_GNB)
         return fail(SPMV_ERR_ARG, "unknown selector %d", selector);
     spmv_select_info_t I;
     memset(&I, 0, sizeof I);
@@ -1001,6 +1009,17 @@ spmv_status_t spmv_select(spmv_plan_t P, int32_t selector, spmv_select_info_t *i
         else if (st != SPMV_OK) return st;
         I.t_decide_s = now_s() - t1;
         if (fb || v < 0) {
+            I.fell_back = 1;
+            used = SEL_PROFILING;
+        }
+    } else if (selector == SEL_DTREE || selector == SEL_GNB) {
+        int32_t fb = 1, lab = -1;
+        spmv_status_t st = classic_predict(selector == SEL_DTREE ? 0 : 1, P->feats, feas, th, S(P),
+                                           scr<char>(P, kOffClf), &v, &lab, &fb);
+        if (st == SPMV_ERR_NO_MODEL) { fb = 1; clear_error(); }
+        else if (st != SPMV_OK) return st;
+        I.t_decide_s = now_s() - t1;
+        if (fb || v < 0 || !((feas >> v) & 1)) {
             I.fell_back = 1;
             used = SEL_PROFILING;
         }

@@ -123,6 +123,13 @@ namespace spmvsel {
 // validation (k_validate.hip): writes flags[0] (bit0 rowptr, bit1 col range),
 // counts[1] = descending pairs, counts[2] = descending pairs at row starts
 // d_part: kValGrid * 3 u64 of device scratch for per-block partials
+// Table 2 on the GPU: the variant for bottleneck class k (K_CML ... K_CMP).
+int class_variant(int k, const double feats[12], const double th[4], uint32_t feas);
+// Device inference of the CART (which 0) or naive Bayes (1) selector; d_out
+// needs 80 bytes of device memory.  SPMV_ERR_NO_MODEL if none is loaded.
+spmv_status_t classic_predict(int which, const double f[12], uint32_t feas, const double th[4],
+                              hipStream_t s, void *d_out, int32_t *variant, int32_t *label,
+                              int32_t *fallback);
 hipError_t launch_validate(const spmv_plan &P, uint64_t *d_flags, uint64_t *d_part,
                            hipStream_t s);
 

@@ -433,6 +433,117 @@ def cmd_eval(args):
             json.dump(dict(summary=out, rows=rows), f)
 
 
+# ------------------------------------------------ the paper's feature classifiers
+
+
+def class_labels(recs, theta):
+    """Bottleneck class of every record from the profiling cascade (Section 3.2.1)."""
+    return np.array([S.spmv_profile_decide(r["meas"], r["features"], theta, r["mask"])[1]
+                     for r in recs], dtype=np.int32)
+
+
+def clf_fit(kind, X, y, C, depth=None, leaf=None):
+    if kind == "dtree":
+        return S.spmv_dtree_fit(X, y, C, depth, leaf)
+    return S.spmv_gnb_fit(X, y, C)
+
+
+def clf_load(kind, model, label_kind):
+    (S.spmv_dtree_load if kind == "dtree" else S.spmv_gnb_load)(model, label_kind)
+
+
+def clf_predict(kind, r):
+    return S.spmv_classifier_predict(S.SPMV_CLF_DTREE if kind == "dtree" else S.SPMV_CLF_GNB,
+                                     r["features"], r["mask"])
+
+
+def clf_scores(kind, recs, labels, label_kind, theta):
+    """Accuracy against the labels and time-based scores of the picks (device inference);
+    a fallback takes the profiling cascade's pick."""
+    acc, hit, reg, fb, ov = [], [], [], [], []
+    for r, lab in zip(recs, labels):
+        p = clf_predict(kind, r)
+        q = profiling_pick(r, theta)
+        v = q if p["fallback"] else p["variant"]
+        t = r["times"]
+        best = min(x for x in t if x > 0)
+        acc.append(p["label"] == lab)
+        hit.append(t[v] <= 1.05 * best)
+        reg.append(t[v] / best - 1)
+        fb.append(p["fallback"])
+        ov.append(r["t_features"] + (r["t_profile"] if p["fallback"] else 0.0))
+    return dict(accuracy=float(np.mean(acc)), hit5=float(np.mean(hit)), mean_regret=float(np.mean(reg)),
+                fallback_rate=float(np.mean(fb)), overhead_s=ov)
+
+
+def cmd_classic(args):
+    """CART and Gaussian NB selectors: hyper-parameters on the validation split,
+    LOOCV accuracy on the training labels (the paper's protocol), held-out
+    regret against the MLP and the profiling cascade."""
+    train, test = load_records(args.train), load_records(args.test)
+    theta = S.spmv_get_thresholds()
+    Xtr = np.array([r["features"] for r in train])
+    lab = {"variant": (np.array([r["label"] for r in train], dtype=np.int32), 6, S.SPMV_LABEL_VARIANT),
+           "class": (class_labels(train, theta), 4, S.SPMV_LABEL_CLASS)}
+    test_lab = {"variant": [r["label"] for r in test], "class": list(class_labels(test, theta))}
+    is_val = np.array([r["seed"] % 10 == 7 for r in train])
+    val = [r for r, v in zip(train, is_val) if v]
+    out = {"theta": theta, "train": len(train), "test": len(test), "models": {}}
+    models = {}
+    for lk, (y, C, lkind) in lab.items():
+        # tree hyper-parameters: best validation hit rate (then accuracy, then smaller tree)
+        grid = []
+        for depth in (3, 4, 6, 8, 10, 12, 16, 24):
+            for leaf in (1, 2, 5, 10, 20):
+                t = clf_fit("dtree", Xtr[~is_val], y[~is_val], C, depth, leaf)
+                clf_load("dtree", t, lkind)
+                sc = clf_scores("dtree", val, y[is_val], lkind, theta)
+                grid.append((sc["hit5"], sc["accuracy"], -len(t["feature"]), depth, leaf))
+        grid.sort(reverse=True)
+        depth, leaf = grid[0][3], grid[0][4]
+        for kind in ("dtree", "gnb"):
+            kw = dict(depth=depth, leaf=leaf) if kind == "dtree" else {}
+            # leave-one-out on the training labels
+            hits = 0
+            for i in range(len(train)):
+                keep = np.arange(len(train)) != i
+                m = clf_fit(kind, Xtr[keep], y[keep], C, **kw)
+                clf_load(kind, m, lkind)
+                hits += clf_predict(kind, train[i])["label"] == y[i]
+            model = clf_fit(kind, Xtr, y, C, **kw)
+            clf_load(kind, model, lkind)
+            sc = clf_scores(kind, test, test_lab[lk], lkind, theta)
+            ts = []
+            for _ in range(200):
+                t0 = time.perf_counter()
+                clf_predict(kind, test[0])
+                ts.append(time.perf_counter() - t0)
+            t_inf = float(np.median(ts))
+            ov = [o + t_inf for o in sc.pop("overhead_s")]
+            picks_t = []
+            for r in test:
+                p = clf_predict(kind, r)
+                v = profiling_pick(r, theta) if p["fallback"] else p["variant"]
+                picks_t.append(r["times"][v])
+            name = f"{kind}_{lk}_labels"
+            out["models"][name] = dict(
+                loocv_accuracy=hits / len(train), **sc, inference_us=t_inf * 1e6,
+                overhead_spmv_equivs_median=float(np.median([o / t for o, t in zip(ov, picks_t)])),
+                **({"max_depth": depth, "min_leaf": leaf, "nodes": len(model["feature"])}
+                   if kind == "dtree" else {}))
+            models[name] = model
+            print(name, json.dumps(out["models"][name]), flush=True)
+        S.spmv_classifier_unload(S.SPMV_CLF_DTREE)
+        S.spmv_classifier_unload(S.SPMV_CLF_GNB)
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1)
+    if args.model_dir:
+        for kind in ("dtree", "gnb"):
+            m = models[f"{kind}_variant_labels"]
+            with open(os.path.join(args.model_dir, f"{kind}_selector.json"), "w") as f:
+                json.dump({"label_kind": "variant", **{k: np.asarray(v).tolist() for k, v in m.items()}}, f)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -460,13 +571,18 @@ def main(argv=None):
     a.add_argument("--lo", type=int, default=1100)
     a.add_argument("--hi", type=int, default=1200)
     a.add_argument("--out", default=None)
+    a = sub.add_parser("classic")
+    a.add_argument("--train", required=True)
+    a.add_argument("--test", required=True)
+    a.add_argument("--out", required=True)
+    a.add_argument("--model-dir", default=None)
     a = sub.add_parser("eval")
     a.add_argument("--model", required=True)
     a.add_argument("--test", required=True)
     a.add_argument("--theta", default=None)
     a.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    {"label": cmd_label, "fit": cmd_fit, "eval": cmd_eval,
+    {"label": cmd_label, "fit": cmd_fit, "eval": cmd_eval, "classic": cmd_classic,
      "calibrate": cmd_calibrate, "sweep": cmd_sweep}[args.cmd](args)
 
 
