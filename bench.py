@@ -74,6 +74,7 @@ def precision_report(S, torch, dev, mats, per, log):
     is feasible: time and GB/s against the FP64 path on the same variant, and
     max_i |y_i - y64_i| / sum_j |a_ij| |x_j| against the library's FP64 result
     (the tests pin that to the CPU oracle)."""
+    import numpy as np  # noqa: F401
     out = []
     for M, rec in zip(mats, per):
         n, nnz = M["n"], M["nnz"]
@@ -119,6 +120,66 @@ def precision_report(S, torch, dev, mats, per, log):
     return out
 
 
+def amortization_report(S, torch, dev, mats, log, rtol=1e-8, max_iters=5000):
+    """Conjugate gradients on the SPD systems of the workload (the 5-point
+    Laplacian on 64^2 and the 27-point stencil on 100^3, b ~ U[-1, 1) from a
+    seed): time to a solution with the learned selection against fixed
+    csr_scalar (unoptimised) and csr_vector (architecture-centric), and the
+    iteration count after which the selection has paid for itself."""
+    import numpy as np
+    systems = []
+    n = 64 * 64
+    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    nnz = S.spmv_generate(0, [64, 0], 0, rp)
+    ci = torch.empty(nnz + 8, dtype=torch.int32, device=dev)
+    val = torch.empty(nnz + 8, dtype=torch.float64, device=dev)
+    S.spmv_generate(0, [64, 0], 0, rp, ci, val)
+    systems.append(dict(name="laplace2d_64^2", n=n, nnz=nnz, rp=rp, ci=ci, val=val))
+    st = next(M for M in mats if M["name"].startswith("stencil27"))
+    systems.append(dict(name=st["name"], n=st["n"], nnz=st["nnz"], rp=st["rp"], ci=st["ci"], val=st["val"]))
+    out = []
+    for sy in systems:
+        b = torch.empty(sy["n"], dtype=torch.float64, device=dev)
+        S.spmv_generate_vector(sy["n"], 7, b)
+        rec = dict(system=sy["name"], n=sy["n"], nnz=sy["nnz"], rtol=rtol)
+        for how in ("selected", "csr_scalar", "csr_vector"):
+            runs = []
+            for rep in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan = S.Plan(sy["rp"], sy["ci"], sy["val"], sy["n"], nnz=sy["nnz"])
+                if how == "selected":
+                    plan.select(S.SEL_MLP)
+                else:
+                    plan.set_variant(S.VARIANTS.index(how))
+                t1 = time.perf_counter()
+                x = torch.zeros(sy["n"], dtype=torch.float64, device=dev)
+                it, rel = S.spmv_cg(plan.handle, b, x, max_iters, rtol)
+                t2 = time.perf_counter()
+                v = S.VARIANTS[plan.variant]
+                plan.close()
+                runs.append((t1 - t0, t2 - t1, it, rel, v))
+            setup = float(np.median([r[0] for r in runs]))
+            solve = float(np.median([r[1] for r in runs]))
+            it, rel, v = runs[-1][2], runs[-1][3], runs[-1][4]
+            rec[how] = dict(variant=v, setup_ms=setup * 1e3, solve_ms=solve * 1e3, iterations=it,
+                            rel_resid=rel, ms_per_iteration=solve / max(it, 1) * 1e3,
+                            total_ms=(setup + solve) * 1e3)
+        sel = rec["selected"]
+        for base in ("csr_scalar", "csr_vector"):
+            bs = rec[base]
+            gain = bs["ms_per_iteration"] - sel["ms_per_iteration"]
+            extra = sel["setup_ms"] - bs["setup_ms"]
+            rec[f"break_even_iterations_vs_{base}"] = (extra / gain if gain > 0 else None)
+            rec[f"speedup_to_solution_vs_{base}"] = bs["total_ms"] / sel["total_ms"]
+        log(f"  CG {sy['name']:>16s}: selected {sel['variant']} {sel['iterations']} it "
+            f"{sel['total_ms']:.2f} ms (setup {sel['setup_ms']:.2f}); csr_scalar "
+            f"{rec['csr_scalar']['total_ms']:.2f} ms; csr_vector {rec['csr_vector']['total_ms']:.2f} ms; "
+            f"break-even vs csr_vector {rec['break_even_iterations_vs_csr_vector']}")
+        out.append(rec)
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +190,7 @@ def parse():
     ap.add_argument("--scale", type=int, default=1, help="divide matrix sizes (testing only)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32/BF16 report")
+    ap.add_argument("--no-amortization", action="store_true", help="skip the CG report")
     ap.add_argument("--cpu-seconds", type=float, default=16.0,
                     help="CPU time budget of the oracle baseline (all four matrices)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant timing table")
@@ -294,6 +356,7 @@ def main():
             f"= {rec['selection_spmv_equivs']:.1f} SpMVs")
 
     precision = [] if args.no_precision else precision_report(S, torch, dev, mats, per, log)
+    amort = [] if args.no_amortization else amortization_report(S, torch, dev, mats, log)
 
     value = total_bytes / t_total * 1e-9
     dom = max(range(len(per)), key=lambda i: per[i]["spmv_us"])
@@ -360,6 +423,7 @@ def main():
         "cpu_baseline": cpu,
         "hbm_probe": {"read_gbs": read_gbs, "copy_gbs": copy_gbs},
         "precision": precision,
+        "amortization": amort,
         "per_matrix": per,
     }
     print(json.dumps(out), flush=True)

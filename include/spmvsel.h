@@ -347,6 +347,20 @@ spmv_status_t spmv_classifier_predict(int32_t which, const double features[12], 
                                       int32_t *leaf, double scores[8]);
 
 /* ----------------------------------------------------------------------- */
+/* Solver loop                                                              */
+
+/* Conjugate gradients (Hestenes and Stiefel 1952) with the plan's current
+ * variant: the iterative method whose SpMVs repay the selection.  The plan
+ * must be FP64 and square, its matrix symmetric positive definite.  d_b
+ * (N doubles) is read; d_x (N doubles) holds the start and receives the
+ * result.  Stops when ||r|| <= rtol ||b|| (r the updated residual) or after
+ * max_iters iterations; *iters and *rel_resid (||r|| / ||b||) may be NULL.
+ * Synchronous on `stream`; deterministic (fixed-order dot products);
+ * allocates 3 N doubles of workspace per call (kept blocks are reused). */
+spmv_status_t spmv_cg(spmv_plan_t plan, const double *d_b, double *d_x, int32_t max_iters,
+                      double rtol, void *stream, int32_t *iters, double *rel_resid);
+
+/* ----------------------------------------------------------------------- */
 /* Utilities                                                                */
 
 /* FP64 -> FP32 (to_dtype SPMV_F32) or bfloat16 bits (SPMV_BF16), one

@@ -90,6 +90,7 @@ _PROTOS = {
     "spmv_gnb_load": (_I32, [_I32, _I32, _P, _P, _P, _P]),
     "spmv_classifier_unload": (_I32, [_I32]),
     "spmv_classifier_predict": (_I32, [_I32, _PF64, _U32, _PI32, _PI32, _PI32, _PI32, _PF64]),
+    "spmv_cg": (_I32, [_P, _P, _P, _I32, _F64, _P, _PI32, _PF64]),
     "spmv_release_cached_blocks": (_I32, []),
     "spmv_cache_flush": (_I32, [_P]),
     "spmv_hbm_probe": (_I32, [_I64, _PF64, _PF64]),
@@ -384,6 +385,14 @@ def spmv_classifier_predict(which: int, features, feasible: int = 63) -> dict:
         which, f, feasible, ctypes.byref(v), ctypes.byref(lab), ctypes.byref(fb), ctypes.byref(leaf), sc))
     return dict(variant=v.value, label=lab.value, fallback=bool(fb.value), leaf=leaf.value,
                 scores=list(sc))
+
+
+def spmv_cg(plan, b, x, max_iters: int = 1000, rtol: float = 1e-8, stream=None):
+    """Conjugate gradients in place on x; returns (iterations, ||r|| / ||b||)."""
+    it, rel = _I32(), _F64()
+    _check("spmv_cg", lib.spmv_cg(plan, _addr(b), _addr(x), max_iters, rtol, _stream(stream),
+                                  ctypes.byref(it), ctypes.byref(rel)))
+    return it.value, rel.value
 
 
 DTREE_MODEL = os.path.join(_HERE, "dtree_selector.json")

@@ -454,21 +454,6 @@ spmv_status_t feasible_mask(spmv_plan *P, uint32_t *bits) {
     return SPMV_OK;
 }
 
-spmv_status_t run_variant(const spmv_plan *P, int v, const void *x, void *y, hipStream_t s) {
-    if ((v == V_DELTA16 && !P->d16_built) || (v == V_MERGE_PATH && !P->mp_built) ||
-        (v == V_XBLOCK_LDS && !P->xs_built))
-        return fail(SPMV_ERR_ARG, "variant %d has no prepared format", v);
-    switch (v) {
-    case V_CSR_SCALAR: SPMV_HIP(launch_csr_scalar(*P, x, y, s)); break;
-    case V_CSR_VECTOR: SPMV_HIP(launch_csr_vector(*P, x, y, s)); break;
-    case V_MERGE_PATH: SPMV_HIP(launch_merge_path(*P, x, y, s)); break;
-    case V_DELTA16: SPMV_HIP(launch_rowstream(*P, true, x, y, s)); break;
-    case V_XBLOCK_LDS: SPMV_HIP(launch_xblock(*P, x, y, s)); break;
-    case V_SHORT_ROW: SPMV_HIP(launch_rowstream(*P, false, x, y, s)); break;
-    default: return fail(SPMV_ERR_ARG, "unknown variant %d", v);
-    }
-    return SPMV_OK;
-}
 
 spmv_status_t ensure_timing_vectors(spmv_plan *P) {
     const size_t xb = xbytes(P->dtype);
@@ -605,6 +590,23 @@ int class_variant(int k, const double feats[12], const double th[4], uint32_t fe
     if (k == K_MB) return (feas >> V_DELTA16) & 1 ? V_DELTA16 : V_CSR_VECTOR;
     if (k == K_IMB) return V_MERGE_PATH;
     return feats[2] <= th[3] ? V_SHORT_ROW : V_CSR_VECTOR;
+}
+
+// One SpMV with variant v (its format must be built).
+spmv_status_t run_variant(const spmv_plan *P, int v, const void *x, void *y, hipStream_t s) {
+    if ((v == V_DELTA16 && !P->d16_built) || (v == V_MERGE_PATH && !P->mp_built) ||
+        (v == V_XBLOCK_LDS && !P->xs_built))
+        return fail(SPMV_ERR_ARG, "variant %d has no prepared format", v);
+    switch (v) {
+    case V_CSR_SCALAR: SPMV_HIP(launch_csr_scalar(*P, x, y, s)); break;
+    case V_CSR_VECTOR: SPMV_HIP(launch_csr_vector(*P, x, y, s)); break;
+    case V_MERGE_PATH: SPMV_HIP(launch_merge_path(*P, x, y, s)); break;
+    case V_DELTA16: SPMV_HIP(launch_rowstream(*P, true, x, y, s)); break;
+    case V_XBLOCK_LDS: SPMV_HIP(launch_xblock(*P, x, y, s)); break;
+    case V_SHORT_ROW: SPMV_HIP(launch_rowstream(*P, false, x, y, s)); break;
+    default: return fail(SPMV_ERR_ARG, "unknown variant %d", v);
+    }
+    return SPMV_OK;
 }
 
 namespace {

@@ -123,6 +123,9 @@ namespace spmvsel {
 // validation (k_validate.hip): writes flags[0] (bit0 rowptr, bit1 col range),
 // counts[1] = descending pairs, counts[2] = descending pairs at row starts
 // d_part: kValGrid * 3 u64 of device scratch for per-block partials
+// One SpMV y = A x with variant v on stream s (SPMV_ERR_ARG if v's format is
+// not built).
+spmv_status_t run_variant(const spmv_plan *P, int v, const void *x, void *y, hipStream_t s);
 // Table 2 on the GPU: the variant for bottleneck class k (K_CML ... K_CMP).
 int class_variant(int k, const double feats[12], const double th[4], uint32_t feas);
 // Device inference of the CART (which 0) or naive Bayes (1) selector; d_out
