@@ -10,7 +10,8 @@
   tiles (Merrill and Garland, SC'16): the merge of the row-end list
   ``rowptr[1..N]`` with the nonzero indices ``0..NNZ-1``, where nonzero j is
   taken before row end i exactly when ``j < rowptr[i+1]``.
-* ``slice_csr_ref``  the column-sliced CSR of x blocking (one slice per XCD).
+* ``slice_csr_ref``  the column-sliced CSR of x blocking (one slice per XCD);
+  ``xblock_split_ref`` takes rows with a long slice segment out of it.
 * ``partition_ref``  the paper's default static partition: contiguous row
   ranges with (as nearly as possible) equal nonzeros (Section 3.2.1).
 * ``to_bf16_bits_ref`` / ``to_f32_ref``  value rounding for the precision
@@ -127,6 +128,38 @@ def slice_csr_ref(rowptr, colind, n_cols: int, slices: int = 8):
             rps[s, i + 1] = rps[s, i] + len(seg)
     cols = [np.concatenate(p) if p else np.zeros(0, np.int64) for p in parts]
     return rps.astype(np.int32), np.concatenate(cols).astype(np.int32)
+
+
+def xblock_split_ref(rowptr, colind, n_cols: int, slices: int, max_seg: int = 512,
+                     max_share: float = 0.25):
+    """The x-block split into short and long rows.
+
+    A row is long when one of its slice segments (slice_csr_ref) has more
+    than ``max_seg`` nonzeros.  When the long rows hold at most ``max_share``
+    of the nonzeros they leave the slices (their segments become empty) and
+    are summed from the original CSR instead; otherwise nothing is split.
+    Returns (long row indices int32[L] in ascending order, slice row
+    pointers int32[slices, N+1], slice-major columns int32) of the slices.
+    """
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colind = np.asarray(colind, dtype=np.int64)
+    n = len(rowptr) - 1
+    rps, _ = slice_csr_ref(rowptr, colind, n_cols, slices)
+    seg = np.diff(rps.astype(np.int64), axis=1)          # [slices, N]
+    long_rows = np.nonzero(seg.max(axis=0, initial=0) > max_seg)[0] if n else np.zeros(0, np.int64)
+    long_nnz = int(np.sum(rowptr[long_rows + 1] - rowptr[long_rows]))
+    if len(long_rows) == 0 or long_nnz > max_share * len(colind):
+        rps, cols = slice_csr_ref(rowptr, colind, n_cols, slices)
+        return np.zeros(0, np.int32), rps, cols
+    keep = np.ones(n, dtype=bool)
+    keep[long_rows] = False
+    L = np.diff(rowptr)
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    rp2[1:] = np.cumsum(np.where(keep, L, 0))
+    ci2 = np.concatenate([colind[rowptr[i]:rowptr[i + 1]] for i in range(n) if keep[i]] or
+                         [np.zeros(0, np.int64)])
+    rps, cols = slice_csr_ref(rp2, ci2, n_cols, slices)
+    return long_rows.astype(np.int32), rps, cols
 
 
 def partition_ref(rowptr, parts: int):

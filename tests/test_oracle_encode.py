@@ -157,3 +157,35 @@ def test_f32_rounding_matches_fractions():
         dn = float(np.nextafter(np.float32(f), np.float32(-2)))
         d = abs(Fraction(f) - Fraction(x))
         assert d <= abs(Fraction(up) - Fraction(x)) and d <= abs(Fraction(dn) - Fraction(x))
+
+
+def test_xblock_split_takes_long_rows_out():
+    from oracle.encode import slice_csr_ref, xblock_split_ref
+    rng = np.random.default_rng(11)
+    n, m = 400, 8000
+    rows = []
+    for i in range(n):
+        if i in (17, 230):   # long: 700 columns inside slice 0 (width 2000)
+            rows.append(np.sort(rng.choice(2000, 700, replace=False)))
+        else:
+            rows.append(np.sort(rng.choice(m, rng.integers(0, 30), replace=False)))
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows)
+    lr, rps, cols = xblock_split_ref(rp, ci, m, 4)
+    assert lr.tolist() == [17, 230]
+    for s in range(4):
+        seg = np.diff(rps[s])
+        assert seg[17] == 0 and seg[230] == 0 and seg.max() <= 512
+    # short rows keep their slice segments unchanged
+    full, _ = slice_csr_ref(rp, ci, m, 4)
+    keep = np.setdiff1d(np.arange(n), lr)
+    assert np.array_equal(np.diff(rps, axis=1)[:, keep], np.diff(full, axis=1)[:, keep])
+    assert len(cols) + 1400 == len(ci)
+    # brute force of the long-row rule
+    width = 2000
+    brute = [i for i in range(n) if max(np.bincount(rows[i] // width, minlength=4), default=0) > 512]
+    assert brute == lr.tolist()
+    # long rows above a quarter of the nonzeros: nothing is split
+    lr2, rps2, _ = xblock_split_ref(rp, ci, m, 4, max_share=0.1)
+    assert len(lr2) == 0 and np.array_equal(rps2, full)
