@@ -173,9 +173,10 @@ spmv_status_t spmv_set_variant(spmv_plan_t plan, int32_t variant);
 spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
 
 /* Column slices of the XBLOCK_LDS format: 0 (default) picks the smallest of
- * 1, 2, 4, 8 that cuts x into slices of at most 4 MiB (measured best on the
- * random and power-law workloads), so that each XCD's 4 MB L2 mostly holds the
- * slice it gathers from; 1, 2, 4 or 8 force that count (tests,
+ * 1, 2, 4, 8 that cuts x into slices of at most 2 MiB while keeping at
+ * least 2 nonzeros per slice row on average (the partial y vectors grow with
+ * the count), so that each XCD's 4 MB L2 mostly holds the slice it gathers
+ * from; 1, 2, 4 or 8 force that count (tests,
  * tuning).  If the format is built with another count it is rebuilt
  * (synchronous).  SPMV_ERR_ARG for any other value. */
 spmv_status_t spmv_set_xblock_slices(spmv_plan_t plan, int32_t slices);
@@ -203,7 +204,11 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
  * slice, 6 x-block tiles (all slices), 7 x-block slices, 8 profiling
  * partitions, 9 delta16 feasible, 10 x-block feasible (always 1),
  * 11 delta16 rows per block, 12 x-block per-slice kernel (rows per block of
- * row streaming, or 0 for merge-path tiles). */
+ * row streaming, or 0 for merge-path tiles), 13 x-block long rows (rows
+ * with a slice segment longer than 512 nonzeros, summed from the original
+ * CSR in chunks of 2048 instead of in the slices; 0 when they would hold
+ * more than a quarter of the nonzeros, in which case nothing is split and
+ * the slices use merge-path tiles). */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:
@@ -211,9 +216,10 @@ spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
  * 1 delta16 offsets uint16[NNZ], 2 merge-path split rows int32[tiles+1],
  * 3 merge-path split nonzeros int32[tiles+1], 4 x-block slice row
  * pointers int32[S (N+1)] (S = key 7), 5 x-block slice-major column
- * indices int32[NNZ],
- * 6 profiling partition bounds int32[parts+1].  `bytes` must equal the
- * array size. */
+ * indices int32[NNZ minus the long rows' nonzeros],
+ * 6 profiling partition bounds int32[parts+1], 7 x-block long rows
+ * int32[key 13] (ascending; their slice segments are empty in 4 and 5).
+ * `bytes` must equal the array size. */
 spmv_status_t spmv_plan_copy_format(spmv_plan_t plan, int32_t which,
                                     void *host_dst, int64_t bytes);
 

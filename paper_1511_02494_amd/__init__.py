@@ -231,7 +231,7 @@ def spmv_plan_query(plan, key: int) -> int:
 
 
 _FORMAT_DTYPES = {0: np.int32, 1: np.uint16, 2: np.int32, 3: np.int32, 4: np.int32,
-                  5: np.int32, 6: np.int32}
+                  5: np.int32, 6: np.int32, 7: np.int32}
 
 
 def spmv_plan_copy_format(plan, which: int, count: int) -> np.ndarray:

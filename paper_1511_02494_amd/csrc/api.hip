@@ -213,6 +213,7 @@ spmv_status_t sync(const spmv_plan *P) {
 constexpr size_t kOffFlags = 0;                       // 3 u64
 constexpr size_t kOffRec = 256;                       // 16 u64
 constexpr size_t kOffSum = 512;                       // 9 u64: a maximum, slice totals
+constexpr size_t kOffLong = 640;                      // 1 i64: long-row count
 constexpr size_t kOffClf = 768;                       // 80 bytes: classifier output
 constexpr size_t kOffMlp = 1024;                      // 64 floats
 constexpr size_t kOffPart = 4096;                     // kFeatBlocks * 16 u64
@@ -306,17 +307,83 @@ bool d16_feasible(const spmv_plan *P) { return P->d16_feasible; }
 // colind/val), with merge-path tiles per slice when a slice row is long, and
 // one partial y per slice.
 // Slice count: the requested one, else the smallest power of two that cuts
-// x into slices of at most kSliceXBytes (at most one slice per XCD).
+// x into slices of at most kSliceXBytes (at most one slice per XCD), as long
+// as a slice row keeps kSliceMinAvg nonzeros on average (fewer, and the
+// partial y vectors cost more than the L2 hits gain).
 int xs_slice_count(const spmv_plan *P) {
     if (P->xs_req > 0) return P->xs_req;
     const int64_t xb = (int64_t)xbytes(P->dtype) * P->m;
+    const double avg = P->n > 0 ? (double)P->nnz / (double)P->n : 0.0;
     int ns = 1;
-    while (ns < kSlices && xb > kSliceXBytes * ns) ns *= 2;
+    while (ns < kSlices && xb > kSliceXBytes * ns && avg >= (double)kSliceMinAvg * 2 * ns) ns *= 2;
     return ns;
 }
 
 int64_t xs_slice_width(const spmv_plan *P, int ns) {
     return P->m > 0 ? (P->m + ns - 1) / ns : 1;
+}
+
+// Rows whose longest slice segment exceeds kSliceStreamMaxLen leave the
+// slices (their segments are zeroed in lens) when they hold at most
+// kLongMaxShare of the nonzeros; they are then summed from the original CSR
+// in chunks of kLongChunk.  Otherwise nothing changes and the slices use
+// merge-path tiles.
+spmv_status_t split_long_rows(spmv_plan *P, int ns, int32_t *lens) {
+    const int64_t n = P->n;
+    P->xs_nlong = P->xs_nchunks = P->xs_long_nnz = 0;
+    DevBuf flags, pos, tmp, rows, beg, end;
+    SPMV_TRY(flags.alloc((size_t)n * 4));
+    SPMV_TRY(pos.alloc((size_t)(n + 1) * 4));
+    SPMV_HIP(launch_long_flags(n, ns, lens, flags.as<int32_t>(), S(P)));
+    size_t need = 0;
+    int64_t *dtot = scr<int64_t>(P, kOffLong);
+    SPMV_HIP(launch_exclusive_scan_i32(flags.as<int32_t>(), pos.as<int32_t>(), n, 1, dtot, nullptr, 0,
+                                       S(P), &need));
+    SPMV_TRY(tmp.alloc(need));
+    SPMV_HIP(launch_exclusive_scan_i32(flags.as<int32_t>(), pos.as<int32_t>(), n, 1, dtot, tmp.p,
+                                       tmp.bytes, S(P), nullptr));
+    int64_t *h = static_cast<int64_t *>(P->h_pinned);
+    SPMV_HIP(hipMemcpyAsync(h, dtot, 8, hipMemcpyDeviceToHost, S(P)));
+    SPMV_TRY(sync(P));
+    const int64_t L = h[0];
+    if (L == 0) return SPMV_OK;
+    SPMV_TRY(rows.alloc((size_t)L * 4));
+    SPMV_TRY(beg.alloc((size_t)L * 4));
+    SPMV_TRY(end.alloc((size_t)L * 4));
+    SPMV_HIP(launch_long_compact(n, flags.as<int32_t>(), pos.as<int32_t>(), P->rowptr,
+                                 rows.as<int32_t>(), beg.as<int32_t>(), end.as<int32_t>(), S(P)));
+    std::vector<int32_t> hb(L), he(L);
+    SPMV_HIP(hipMemcpyAsync(hb.data(), beg.p, (size_t)L * 4, hipMemcpyDeviceToHost, S(P)));
+    SPMV_HIP(hipMemcpyAsync(he.data(), end.p, (size_t)L * 4, hipMemcpyDeviceToHost, S(P)));
+    SPMV_TRY(sync(P));
+    int64_t long_nnz = 0;
+    for (int64_t t = 0; t < L; ++t) long_nnz += he[t] - hb[t];
+    if ((double)long_nnz > kLongMaxShare * (double)P->nnz) return SPMV_OK;
+    std::vector<int32_t> first(L + 1), ck0, ck1;
+    for (int64_t t = 0; t < L; ++t) {
+        first[t] = (int32_t)ck0.size();
+        for (int64_t k = hb[t]; k < he[t]; k += kLongChunk) {
+            ck0.push_back((int32_t)k);
+            ck1.push_back((int32_t)std::min<int64_t>(he[t], k + kLongChunk));
+        }
+    }
+    first[L] = (int32_t)ck0.size();
+    const int64_t nc = (int64_t)ck0.size();
+    SPMV_TRY(P->xs_lrows.alloc((size_t)L * 4));
+    SPMV_TRY(P->xs_lfirst.alloc((size_t)(L + 1) * 4));
+    SPMV_TRY(P->xs_lck0.alloc((size_t)nc * 4));
+    SPMV_TRY(P->xs_lck1.alloc((size_t)nc * 4));
+    SPMV_TRY(P->xs_lsum.alloc((size_t)nc * 8));
+    SPMV_HIP(hipMemcpyAsync(P->xs_lrows.p, rows.p, (size_t)L * 4, hipMemcpyDeviceToDevice, S(P)));
+    SPMV_HIP(hipMemcpyAsync(P->xs_lfirst.p, first.data(), (size_t)(L + 1) * 4, hipMemcpyHostToDevice, S(P)));
+    SPMV_HIP(hipMemcpyAsync(P->xs_lck0.p, ck0.data(), (size_t)nc * 4, hipMemcpyHostToDevice, S(P)));
+    SPMV_HIP(hipMemcpyAsync(P->xs_lck1.p, ck1.data(), (size_t)nc * 4, hipMemcpyHostToDevice, S(P)));
+    SPMV_HIP(launch_long_zero(L, ns, n, rows.as<int32_t>(), lens, S(P)));
+    SPMV_TRY(sync(P));  // the host vectors above must outlive the copies
+    P->xs_nlong = L;
+    P->xs_nchunks = nc;
+    P->xs_long_nnz = long_nnz;
+    return SPMV_OK;
 }
 
 spmv_status_t build_xslices(spmv_plan *P) {
@@ -326,6 +393,7 @@ spmv_status_t build_xslices(spmv_plan *P) {
     const int64_t cw = xs_slice_width(P, ns);
     P->xs_slices = ns;
     P->xs_width = cw;
+    P->xs_nlong = P->xs_nchunks = P->xs_long_nnz = 0;
     for (int k = 0; k < kSlices; ++k) P->xs_nnz_off[k] = P->xs_tiles[k] = P->xs_tile_off[k] = 0;
     SPMV_TRY(P->xs_rowptr.alloc((size_t)ns * (n + 1) * 4));
     // slice starts are padded to 8 elements so every slice keeps the
@@ -346,6 +414,7 @@ spmv_status_t build_xslices(spmv_plan *P) {
         SPMV_TRY(lens.alloc((size_t)ns * n * 4));
         SPMV_HIP(launch_slice_count(*P, cw, msr.as<int32_t>(), msn.as<int32_t>(), mtiles,
                                     lens.as<int32_t>(), S(P)));
+        SPMV_TRY(split_long_rows(P, ns, lens.as<int32_t>()));
         size_t need = 0;
         auto *dmax = scr<unsigned long long>(P, kOffSum);  // then the slice totals
         int64_t *dtot = reinterpret_cast<int64_t *>(dmax + 1);
@@ -364,7 +433,7 @@ spmv_status_t build_xslices(spmv_plan *P) {
         for (int k = 0; k < ns; ++k) snnz[k] = h[1 + k];
         // slice rows no longer than a chunk: row-block streaming, else merge path
         if (maxlen <= (unsigned long long)kChunk / 4) {
-            const double avg = (double)nnz / ((double)n * ns);
+            const double avg = (double)(nnz - P->xs_long_nnz) / ((double)n * ns);
             P->xs_rows = kBlock * pow2_floor((double)kChunk / (kBlock * (avg > 1e-9 ? avg : 1e-9)),
                                              1, kRowStreamMaxR);
         } else {
@@ -384,8 +453,9 @@ spmv_status_t build_xslices(spmv_plan *P) {
         P->xs_tile_off[k] = toff;
         toff += P->xs_tiles[k];
     }
-    if (total != nnz) return fail(SPMV_ERR_HIP, "x-block slices hold %lld of %lld nonzeros",
-                                  (long long)total, (long long)nnz);
+    if (total + P->xs_long_nnz != nnz)
+        return fail(SPMV_ERR_HIP, "x-block slices hold %lld of %lld nonzeros (%lld in long rows)",
+                    (long long)total, (long long)nnz, (long long)P->xs_long_nnz);
     SPMV_TRY(P->xs_srow.alloc((size_t)(toff + ns) * 4));
     SPMV_TRY(P->xs_snnz.alloc((size_t)(toff + ns) * 4));
     SPMV_TRY(P->xs_crow.alloc((size_t)(toff > 0 ? toff : 1) * 4));
@@ -891,6 +961,7 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
     case 6: SPMV_TRY(build_xslices(P)); *value = P->xs_tile_off[P->xs_slices - 1] + P->xs_tiles[P->xs_slices - 1]; break;
     case 7: *value = xs_slice_count(P); break;
     case 12: SPMV_TRY(build_xslices(P)); *value = P->xs_rows; break;
+    case 13: SPMV_TRY(build_xslices(P)); *value = P->xs_nlong; break;
     case 8: *value = P->parts; break;
     case 9: SPMV_TRY(check_d16(P)); *value = d16_feasible(P); break;
     case 11: SPMV_TRY(check_d16(P)); *value = P->d16_rows; break;
@@ -919,7 +990,8 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
     case 4: case 5:
         SPMV_TRY(build_xslices(P));
         if (which == 5) {  // the slices without their alignment padding
-            if (bytes != 4 * P->nnz) return fail(SPMV_ERR_ARG, "array 5 has %lld bytes", (long long)(4 * P->nnz));
+            const int64_t want5 = 4 * (P->nnz - P->xs_long_nnz);
+            if (bytes != want5) return fail(SPMV_ERR_ARG, "array 5 has %lld bytes", (long long)want5);
             int64_t done = 0;
             for (int k = 0; k < P->xs_slices; ++k) {
                 int32_t last = 0;
@@ -944,6 +1016,11 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
         }
         src = P->part_bounds.p;
         want = 4 * (P->parts + 1);
+        break;
+    case 7:
+        SPMV_TRY(build_xslices(P));
+        src = P->xs_lrows.p;
+        want = 4 * P->xs_nlong;
         break;
     default: return fail(SPMV_ERR_ARG, "unknown array %d", which);
     }

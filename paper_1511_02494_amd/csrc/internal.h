@@ -21,7 +21,11 @@ constexpr int kRowStreamMaxR = 8;     // rows per thread (max) in short_row / de
 constexpr int kMergeIpt = 8;          // merge-path items per thread
 constexpr int kMergeTile = kBlock * kMergeIpt;
 constexpr int kSlices = 8;            // x-block column slices at most (one per XCD)
-constexpr int64_t kSliceXBytes = 4ll << 20;  // x bytes per slice the automatic count aims at
+constexpr int64_t kSliceXBytes = 2ll << 20;  // x bytes per slice the automatic count aims at
+constexpr int kSliceMinAvg = 2;       // ... keeping at least this many nonzeros per slice row
+constexpr int kSliceStreamMaxLen = kChunk / 4;  // longest slice segment for row streaming
+constexpr int kLongChunk = 2048;      // nonzeros per block of the long-row sums
+constexpr double kLongMaxShare = 0.25;  // long rows leave the slices up to this share of NNZ
 constexpr int kKahanMinLen = 257;     // FP32 rows longer than 256 use Kahan sums
 constexpr int kLineBytes = 128;       // cache line assumed by the miss feature
 constexpr int64_t kLlcBytes = 256ll << 20;
@@ -110,6 +114,10 @@ struct spmv_plan {
     int64_t xs_nnz_off[spmvsel::kSlices] = {0}, xs_tiles[spmvsel::kSlices] = {0},
             xs_tile_off[spmvsel::kSlices] = {0};
     spmvsel::DevBuf xs_rowptr, xs_colind, xs_val, xs_srow, xs_snnz, xs_crow, xs_cval, xs_y;
+    // rows with a slice segment longer than kSliceStreamMaxLen, taken out of
+    // the slices and summed from the original CSR in chunks of kLongChunk
+    int64_t xs_nlong = 0, xs_nchunks = 0, xs_long_nnz = 0;
+    spmvsel::DevBuf xs_lrows, xs_lfirst, xs_lck0, xs_lck1, xs_lsum;
     bool part_built = false;
     spmvsel::DevBuf part_bounds;
 
@@ -154,6 +162,15 @@ hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t pan
                            unsigned long long *d_max, hipStream_t s);
 hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,
                                int32_t *snnz, int64_t tiles, hipStream_t s);
+// Long rows of the x-block split: flags[i] = 1 if a slice segment of row i
+// exceeds kSliceStreamMaxLen; then, from the scanned flags, the row list with
+// its [start, end) nonzero range.
+hipError_t launch_long_flags(int64_t n, int ns, const int32_t *lens, int32_t *flags, hipStream_t s);
+hipError_t launch_long_compact(int64_t n, const int32_t *flags, const int32_t *pos,
+                               const int32_t *rp, int32_t *rows, int32_t *beg, int32_t *end,
+                               hipStream_t s);
+hipError_t launch_long_zero(int64_t L, int ns, int64_t n, const int32_t *rows, int32_t *lens,
+                            hipStream_t s);
 hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, const int32_t *srow,
                               const int32_t *snnz, int64_t tiles, int32_t *lens, hipStream_t s);
 // d_part: 2048 int32 of device scratch for per-block maxima

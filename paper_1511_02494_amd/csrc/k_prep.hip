@@ -182,6 +182,70 @@ __global__ __launch_bounds__(kBlock) void k_slice_count(int64_t n, int64_t nnz, 
     }
 }
 
+// ---- long rows of the x-block split
+__global__ __launch_bounds__(kBlock) void k_long_flags(int64_t n, int ns,
+                                                       const int32_t *__restrict__ lens,
+                                                       int32_t *__restrict__ flags) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        int32_t mx = 0;
+        for (int s = 0; s < ns; ++s) mx = lens[(int64_t)s * n + i] > mx ? lens[(int64_t)s * n + i] : mx;
+        flags[i] = mx > kSliceStreamMaxLen;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_long_compact(int64_t n, const int32_t *__restrict__ flags,
+                                                         const int32_t *__restrict__ pos,
+                                                         const int32_t *__restrict__ rp,
+                                                         int32_t *__restrict__ rows,
+                                                         int32_t *__restrict__ beg,
+                                                         int32_t *__restrict__ end) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        if (flags[i]) {
+            const int32_t t = pos[i];
+            rows[t] = (int32_t)i;
+            beg[t] = rp[i];
+            end[t] = rp[i + 1];
+        }
+}
+
+__global__ __launch_bounds__(kBlock) void k_long_zero(int64_t L, int ns, int64_t n,
+                                                      const int32_t *__restrict__ rows,
+                                                      int32_t *__restrict__ lens) {
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < L;
+         t += (int64_t)gridDim.x * kBlock)
+        for (int s = 0; s < ns; ++s) lens[(int64_t)s * n + rows[t]] = 0;
+}
+
+hipError_t launch_long_flags(int64_t n, int ns, const int32_t *lens, int32_t *flags, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_long_flags, dim3((unsigned)g), dim3(kBlock), 0, s, n, ns, lens, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_long_compact(int64_t n, const int32_t *flags, const int32_t *pos,
+                               const int32_t *rp, int32_t *rows, int32_t *beg, int32_t *end,
+                               hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_long_compact, dim3((unsigned)g), dim3(kBlock), 0, s, n, flags, pos, rp,
+                       rows, beg, end);
+    return hipGetLastError();
+}
+
+hipError_t launch_long_zero(int64_t L, int ns, int64_t n, const int32_t *rows, int32_t *lens,
+                            hipStream_t s) {
+    if (L == 0) return hipSuccess;
+    int64_t g = (L + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_long_zero, dim3((unsigned)g), dim3(kBlock), 0, s, L, ns, n, rows, lens);
+    return hipGetLastError();
+}
+
 // Maximum of a non-negative int32 array: per-block maxima into part[], then
 // one block folds them (no same-address atomics).
 constexpr int kMaxGrid = 2048;

@@ -401,6 +401,57 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup_slices(int64_t n, int64_
     merge_fixup_one<A>(g % maxt, n, T.tiles[s], T.crow[s], T.cval[s], T.y[s]);
 }
 
+// Long rows of the split, summed from the original CSR: one block per chunk
+// of at most kLongChunk nonzeros of one row (all loads first, then the
+// gathers; per-thread sums folded by a fixed tree), then one thread per row
+// adds its chunk sums in order (Kahan for FP32) and stores the row in the
+// first partial y, where the slice kernel left a zero.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_long_chunks(const int32_t *__restrict__ ck0,
+                                                        const int32_t *__restrict__ ck1,
+                                                        const int32_t *__restrict__ ci,
+                                                        const V *__restrict__ val,
+                                                        const typename VT<V>::A *__restrict__ x,
+                                                        typename VT<V>::A *__restrict__ lsum) {
+    using A = typename VT<V>::A;
+    constexpr int PPT = kLongChunk / kBlock;
+    __shared__ A sh[kBlock];
+    const int32_t k0 = ck0[blockIdx.x], k1 = ck1[blockIdx.x];
+    int32_t c[PPT];
+    V v[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int32_t k = k0 + (int32_t)threadIdx.x + j * kBlock;
+        c[j] = k < k1 ? ld_nt(ci + k) : 0;
+        v[j] = k < k1 ? ld_nt(val + k) : V(0);
+    }
+    A t = A(0);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int32_t k = k0 + (int32_t)threadIdx.x + j * kBlock;
+        if (k < k1) t = t + VT<V>::cvt(v[j]) * x[c[j]];
+    }
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lsum[blockIdx.x] = sh[0];
+}
+
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_long_rows(int64_t L, const int32_t *__restrict__ rows,
+                                                      const int32_t *__restrict__ first,
+                                                      const A *__restrict__ lsum,
+                                                      A *__restrict__ y0) {
+    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (t >= L) return;
+    Sum<A> acc;
+    for (int32_t c = first[t]; c < first[t + 1]; ++c) acc.add(lsum[c], is_f32<A>());
+    y0[rows[t]] = acc.s;
+}
+
 template <class A>
 __global__ __launch_bounds__(kBlock) void k_slice_sum(int64_t n, SliceTable<A> T,
                                                       A *__restrict__ y) {
@@ -557,6 +608,17 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             if (e != hipSuccess) return e;
             const unsigned g = grid_for(maxt * T.ns, kBlock, INT32_MAX);
             hipLaunchKernelGGL(k_merge_fixup_slices<A>, dim3(g), dim3(kBlock), 0, s, P.n, maxt, T);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if (P.xs_nlong > 0) {  // rows taken out of the slices
+            hipLaunchKernelGGL(k_long_chunks<V>, dim3((unsigned)P.xs_nchunks), dim3(kBlock), 0, s,
+                               P.xs_lck0.as<int32_t>(), P.xs_lck1.as<int32_t>(), P.colind,
+                               (const V *)P.val, (const A *)x, P.xs_lsum.as<A>());
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_long_rows<A>, dim3(grid_for(P.xs_nlong, kBlock, INT32_MAX)),
+                               dim3(kBlock), 0, s, P.xs_nlong, P.xs_lrows.as<int32_t>(),
+                               P.xs_lfirst.as<int32_t>(), P.xs_lsum.as<A>(), T.y[0]);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         const unsigned g = grid_for(P.n, kBlock, (int64_t)P.num_cus * 16);

@@ -7,7 +7,7 @@ import pytest
 import synth
 import paper_1511_02494_amd as S
 from oracle.encode import (delta16_ref, merge_search_ref, merge_walk_ref, partition_ref,
-                           slice_csr_ref, to_bf16_bits_ref, to_f32_ref)
+                           xblock_split_ref, to_bf16_bits_ref, to_f32_ref)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -49,9 +49,11 @@ def test_formats_match_oracle(name, build, m):
         S.spmv_set_xblock_slices(h, forced)
         nsl = S.spmv_plan_query(h, 7)
         assert forced == 0 or nsl == forced
-        rps, cx = slice_csr_ref(rp, ci, m, nsl)
+        lr, rps, cx = xblock_split_ref(rp, ci, m, nsl)
+        assert S.spmv_plan_query(h, 13) == len(lr)
+        assert np.array_equal(S.spmv_plan_copy_format(h, 7, len(lr)), lr)
         assert np.array_equal(S.spmv_plan_copy_format(h, 4, nsl * (n + 1)), rps.reshape(-1))
-        assert np.array_equal(S.spmv_plan_copy_format(h, 5, nnz), cx)
+        assert np.array_equal(S.spmv_plan_copy_format(h, 5, len(cx)), cx)
         tiles = sum((n + int(r[-1]) + T - 1) // T for r in rps)
         assert S.spmv_plan_query(h, 6) == tiles
     parts = S.spmv_plan_query(h, 8)
