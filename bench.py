@@ -57,8 +57,9 @@ def kernel_names(v, plan):
         return ["void spmvsel::k_merge_path<double>", "void spmvsel::k_merge_fixup<double>"]
     if v == S.V_XBLOCK_LDS:
         rows = plan.query(12)  # rows per block of the per-slice row-streaming kernel, 0 = merge path
+        long_rows = ["void spmvsel::k_long_rows<double>"] if plan.query(13) > 0 else []
         if rows > 0:
-            return [f"void spmvsel::k_rowstream_slices<double, {rows // 256}>",
+            return [f"void spmvsel::k_rowstream_slices<double, {rows // 256}>", *long_rows,
                     "void spmvsel::k_slice_sum<double>"]
         return ["void spmvsel::k_merge_slices<double>", "void spmvsel::k_merge_fixup_slices<double>",
                 "void spmvsel::k_slice_sum<double>"]

@@ -307,15 +307,14 @@ bool d16_feasible(const spmv_plan *P) { return P->d16_feasible; }
 // colind/val), with merge-path tiles per slice when a slice row is long, and
 // one partial y per slice.
 // Slice count: the requested one, else the smallest power of two that cuts
-// x into slices of at most kSliceXBytes (at most one slice per XCD), as long
+// x into slices of at most kSliceXEntries (at most one slice per XCD), as long
 // as a slice row keeps kSliceMinAvg nonzeros on average (fewer, and the
 // partial y vectors cost more than the L2 hits gain).
 int xs_slice_count(const spmv_plan *P) {
     if (P->xs_req > 0) return P->xs_req;
-    const int64_t xb = (int64_t)xbytes(P->dtype) * P->m;
     const double avg = P->n > 0 ? (double)P->nnz / (double)P->n : 0.0;
     int ns = 1;
-    while (ns < kSlices && xb > kSliceXBytes * ns && avg >= (double)kSliceMinAvg * 2 * ns) ns *= 2;
+    while (ns < kSlices && P->m > kSliceXEntries * ns && avg >= (double)kSliceMinAvg * 2 * ns) ns *= 2;
     return ns;
 }
 

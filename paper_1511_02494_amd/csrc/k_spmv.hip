@@ -378,13 +378,85 @@ __global__ __launch_bounds__(kBlock) void k_merge_slices(int64_t n, const int32_
                   T.snnz[s], T.crow[s], T.cval[s]);
 }
 
-// Short slice rows: row-block streaming on each slice.
+// Long rows of the split, summed from the original CSR: one block per chunk
+// of at most kLongChunk nonzeros of one row (all loads first, then the
+// gathers; per-thread sums folded by a fixed tree; these blocks ride at the
+// end of the slice kernel's grid, filling CUs as slice blocks finish), then
+// one wavefront per
+// row adds its chunk sums (per lane in order, Kahan for FP32, then a fixed
+// butterfly) and stores the row in the first partial y, where the slice
+// kernel left a zero.
+template <class V>
+__device__ __forceinline__ void long_chunk_block(int64_t c, const int32_t *__restrict__ ck0,
+                                                 const int32_t *__restrict__ ck1,
+                                                 const int32_t *__restrict__ ci,
+                                                 const V *__restrict__ val,
+                                                 const typename VT<V>::A *__restrict__ x,
+                                                 typename VT<V>::A *__restrict__ lsum) {
+    using A = typename VT<V>::A;
+    constexpr int PPT = kLongChunk / kBlock;
+    __shared__ A sh[kBlock];
+    const int32_t k0 = ck0[c], k1 = ck1[c];
+    int32_t cc[PPT];
+    V v[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int32_t k = k0 + (int32_t)threadIdx.x + j * kBlock;
+        cc[j] = k < k1 ? ld_nt(ci + k) : 0;
+        v[j] = k < k1 ? ld_nt(val + k) : V(0);
+    }
+    A t = A(0);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int32_t k = k0 + (int32_t)threadIdx.x + j * kBlock;
+        if (k < k1) t = t + VT<V>::cvt(v[j]) * x[cc[j]];
+    }
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lsum[c] = sh[0];
+}
+
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_long_rows(int64_t L, const int32_t *__restrict__ rows,
+                                                      const int32_t *__restrict__ first,
+                                                      const A *__restrict__ lsum,
+                                                      A *__restrict__ y0) {
+    // one wavefront per row: lane l adds chunks l, l+64, ... in order, then a
+    // fixed butterfly over the lanes
+    const int64_t t = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (t >= L) return;  // whole wavefronts leave together
+    Sum<A> acc;
+    for (int32_t c = first[t] + lane; c < first[t + 1]; c += 64) acc.add(lsum[c], is_f32<A>());
+    const A v = group_sum<64>(acc.s);
+    if (lane == 0) y0[rows[t]] = v;
+}
+
+// Short slice rows: row-block streaming on each slice; workgroups from
+// `sgrid` on sum the long-row chunks instead.
+struct LongChunks {
+    const int32_t *ck0, *ck1, *ci;
+    const void *val;
+    void *lsum;
+};
+
 template <class V, int R>
 __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t nblocks,
                                                              const int32_t *__restrict__ ci,
                                                              const V *__restrict__ val,
                                                              const typename VT<V>::A *__restrict__ x,
-                                                             SliceTable<typename VT<V>::A> T) {
+                                                             SliceTable<typename VT<V>::A> T,
+                                                             int64_t sgrid, LongChunks LC) {
+    using A = typename VT<V>::A;
+    if ((int64_t)blockIdx.x >= sgrid) {
+        long_chunk_block<V>((int64_t)blockIdx.x - sgrid, LC.ck0, LC.ck1, LC.ci,
+                            static_cast<const V *>(LC.val), x, static_cast<A *>(LC.lsum));
+        return;
+    }
     int s;
     const int64_t b = slice_unit(T.ns, &s);
     if (b >= nblocks) return;
@@ -399,57 +471,6 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup_slices(int64_t n, int64_
     const int s = (int)(g / (maxt > 0 ? maxt : 1));
     if (s >= T.ns) return;
     merge_fixup_one<A>(g % maxt, n, T.tiles[s], T.crow[s], T.cval[s], T.y[s]);
-}
-
-// Long rows of the split, summed from the original CSR: one block per chunk
-// of at most kLongChunk nonzeros of one row (all loads first, then the
-// gathers; per-thread sums folded by a fixed tree), then one thread per row
-// adds its chunk sums in order (Kahan for FP32) and stores the row in the
-// first partial y, where the slice kernel left a zero.
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_long_chunks(const int32_t *__restrict__ ck0,
-                                                        const int32_t *__restrict__ ck1,
-                                                        const int32_t *__restrict__ ci,
-                                                        const V *__restrict__ val,
-                                                        const typename VT<V>::A *__restrict__ x,
-                                                        typename VT<V>::A *__restrict__ lsum) {
-    using A = typename VT<V>::A;
-    constexpr int PPT = kLongChunk / kBlock;
-    __shared__ A sh[kBlock];
-    const int32_t k0 = ck0[blockIdx.x], k1 = ck1[blockIdx.x];
-    int32_t c[PPT];
-    V v[PPT];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const int32_t k = k0 + (int32_t)threadIdx.x + j * kBlock;
-        c[j] = k < k1 ? ld_nt(ci + k) : 0;
-        v[j] = k < k1 ? ld_nt(val + k) : V(0);
-    }
-    A t = A(0);
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const int32_t k = k0 + (int32_t)threadIdx.x + j * kBlock;
-        if (k < k1) t = t + VT<V>::cvt(v[j]) * x[c[j]];
-    }
-    sh[threadIdx.x] = t;
-    __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) lsum[blockIdx.x] = sh[0];
-}
-
-template <class A>
-__global__ __launch_bounds__(kBlock) void k_long_rows(int64_t L, const int32_t *__restrict__ rows,
-                                                      const int32_t *__restrict__ first,
-                                                      const A *__restrict__ lsum,
-                                                      A *__restrict__ y0) {
-    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (t >= L) return;
-    Sum<A> acc;
-    for (int32_t c = first[t]; c < first[t + 1]; ++c) acc.add(lsum[c], is_f32<A>());
-    y0[rows[t]] = acc.s;
 }
 
 template <class A>
@@ -585,17 +606,21 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             T.tiles[k] = P.xs_tiles[k];
             if (T.tiles[k] > maxt) maxt = T.tiles[k];
         }
+        if (P.xs_nlong > 0 && P.xs_rows == 0) return hipErrorInvalidValue;  // split implies streaming
         if (P.xs_rows > 0) {  // short slice rows: row-block streaming per slice
             const int R = P.xs_rows / kBlock;
             const int64_t nb = (P.n + P.xs_rows - 1) / P.xs_rows;
-            const unsigned g = (unsigned)((nb + G - 1) / G * 8);
+            const int64_t sg = (nb + G - 1) / G * 8;
+            const unsigned g = (unsigned)(sg + P.xs_nchunks);
             const int32_t *xci = P.xs_colind.as<int32_t>();
             const V *xv = (const V *)P.xs_val.p;
+            const LongChunks LC{P.xs_lck0.as<int32_t>(), P.xs_lck1.as<int32_t>(), P.colind, P.val,
+                                P.xs_lsum.p};
             switch (R) {
-            case 1: hipLaunchKernelGGL((k_rowstream_slices<V, 1>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T); break;
-            case 2: hipLaunchKernelGGL((k_rowstream_slices<V, 2>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T); break;
-            case 4: hipLaunchKernelGGL((k_rowstream_slices<V, 4>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T); break;
-            case 8: hipLaunchKernelGGL((k_rowstream_slices<V, 8>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T); break;
+            case 1: hipLaunchKernelGGL((k_rowstream_slices<V, 1>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;
+            case 2: hipLaunchKernelGGL((k_rowstream_slices<V, 2>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;
+            case 4: hipLaunchKernelGGL((k_rowstream_slices<V, 4>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;
+            case 8: hipLaunchKernelGGL((k_rowstream_slices<V, 8>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;
             default: return hipErrorInvalidValue;
             }
             hipError_t e = hipGetLastError();
@@ -610,16 +635,12 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             hipLaunchKernelGGL(k_merge_fixup_slices<A>, dim3(g), dim3(kBlock), 0, s, P.n, maxt, T);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-        if (P.xs_nlong > 0) {  // rows taken out of the slices
-            hipLaunchKernelGGL(k_long_chunks<V>, dim3((unsigned)P.xs_nchunks), dim3(kBlock), 0, s,
-                               P.xs_lck0.as<int32_t>(), P.xs_lck1.as<int32_t>(), P.colind,
-                               (const V *)P.val, (const A *)x, P.xs_lsum.as<A>());
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_long_rows<A>, dim3(grid_for(P.xs_nlong, kBlock, INT32_MAX)),
+        if (P.xs_nlong > 0) {  // rows taken out of the slices (chunks summed above)
+            hipLaunchKernelGGL(k_long_rows<A>, dim3(grid_for(P.xs_nlong * 64, kBlock, INT32_MAX)),
                                dim3(kBlock), 0, s, P.xs_nlong, P.xs_lrows.as<int32_t>(),
                                P.xs_lfirst.as<int32_t>(), P.xs_lsum.as<A>(), T.y[0]);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
         }
         const unsigned g = grid_for(P.n, kBlock, (int64_t)P.num_cus * 16);
         hipLaunchKernelGGL(k_slice_sum<A>, dim3(g), dim3(kBlock), 0, s, P.n, T, (A *)y);
