@@ -62,10 +62,15 @@ typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
  *  DELTA16     16-bit column offsets from one reference column per block of
  *              rows, streamed through LDS (column-index compression, class MB).
  *  XBLOCK_LDS  x blocking (class CML; replaces software prefetching of x):
- *              the columns are cut into 8 slices, one per XCD, each stored as
- *              its own CSR and run as merge-path tiles on that XCD, so the
- *              slice of x it gathers stays in the XCD's L2; products are
- *              staged in LDS; 8 partial y vectors are summed in slice order.
+ *              the columns are cut into S <= 8 slices (spmv_set_xblock_slices),
+ *              each stored as its own CSR and run on the XCDs that take that
+ *              slice, so the slice of x it gathers stays in their L2; rows
+ *              are streamed through LDS per slice, rows with a slice segment
+ *              over 512 nonzeros are summed from the CSR in chunks instead
+ *              (merge-path tiles per slice when such rows hold over a
+ *              quarter of the nonzeros); S partial y vectors are summed in
+ *              slice order.  (The name is kept from an earlier design that
+ *              staged x windows in LDS.)
  *  SHORT_ROW   rows streamed through LDS in chunks of 2048 nonzeros with one
  *              thread summing each row (short rows: inner-loop overhead). */
 typedef enum {

@@ -17,10 +17,13 @@ Modules
 ``select``    the profiling classifier's cascade (Section 3.2.1) and the
               class-to-optimisation map (Table 2).
 ``encode``    the derived formats: 16-bit column offsets (Section 3.3),
-              merge-path split coordinates, x-window panels, partitions, and
-              FP32/BF16 value rounding.
+              merge-path split coordinates, x-block column slices and their
+              long-row split, partitions, and FP32/BF16 value rounding.
 ``mlp``       the learned selector: input transform, FP32 forward pass with a
               fixed operation order, FP64 forward/backward and Adam.
+``classic``   the paper's feature classifiers (Section 3.2.2): CART with the
+              Gini criterion and Gaussian naive Bayes.
+``cg``        conjugate gradients, the solver loop that amortises selection.
 ``cref``      ctypes wrapper of the plain C SpMV in ``csrc/spmv_ref.c``
               (the same loop, for host timing).
 

@@ -20,7 +20,7 @@ order (noxmiss, inflate, balance).  A score whose denominator is not
 positive is 0.
 
 Table 2 maps classes to optimisations; the GPU pool remaps them:
-CML -> xblock_lds (x staged in LDS) if feasible, else csr_vector;
+CML -> xblock_lds (x blocking by column slices) if feasible, else csr_vector;
 MB  -> delta16 (16-bit column offsets) if feasible, else csr_vector;
 IMB -> merge_path (nonzero-balanced merge-based CSR);
 CMP -> short_row if nnz_avg <= theta[3], else csr_vector.

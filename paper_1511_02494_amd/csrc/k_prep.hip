@@ -377,9 +377,10 @@ hipError_t launch_slice_scatter(const spmv_plan &P, const int32_t *srow, const i
     return hipGetLastError();
 }
 
-// ---- x-block panels: the column window [min first col, max last col] of
-// each panel of H rows ((0, -1) when the panel has no nonzeros).  One
-// wavefront per panel.
+// ---- row panels: the column window [min first col, max last col] of each
+// panel of H rows ((0, -1) when the panel has no nonzeros), which gives the
+// delta16 reference columns and its 16-bit span test.  One wavefront per
+// panel.
 __global__ __launch_bounds__(kBlock) void k_panel_windows(int64_t n, int H, int64_t panels,
                                                           const int32_t *__restrict__ rp,
                                                           const int32_t *__restrict__ ci,
