@@ -45,7 +45,10 @@ def test_mlp_gain_over_profiling_cascade():
     def mlp(r):
         p = S.spmv_mlp_predict(r["features"], r["mask"])
         return profiling(r, theta) if p["fallback"] else p["variant"]
-    hit_m, reg_m = score(recs, mlp)
+    try:
+        hit_m, reg_m = score(recs, mlp)
+    finally:
+        S.spmv_model_unload()
     hit_p, reg_p = score(recs, lambda r: profiling(r, theta))
     hit_v, _ = score(recs, lambda r: S.V_CSR_VECTOR)
     over = [r["t_features"] / min(x for x in r["times"] if x > 0) for r in recs]
@@ -55,7 +58,6 @@ def test_mlp_gain_over_profiling_cascade():
     assert hit_m >= 0.90                      # the learned selector's target
     assert hit_m > hit_p + 0.2 and reg_m < reg_p
     assert np.median(over) <= 20
-    S.spmv_model_unload()
 
 
 def test_cart_gain_over_profiling_cascade():
@@ -68,9 +70,11 @@ def test_cart_gain_over_profiling_cascade():
     def tree(r):
         p = S.spmv_classifier_predict(S.SPMV_CLF_DTREE, r["features"], r["mask"])
         return profiling(r, theta) if p["fallback"] else p["variant"]
-    hit_t, reg_t = score(recs, tree)
+    try:
+        hit_t, reg_t = score(recs, tree)
+    finally:
+        S.spmv_classifier_unload(S.SPMV_CLF_DTREE)
+        S.spmv_classifier_unload(S.SPMV_CLF_GNB)
     hit_p, reg_p = score(recs, lambda r: profiling(r, theta))
     print(f"\nheld-out: CART {hit_t:.3f} within 5% (regret {reg_t:.3f}); profiling {hit_p:.3f}", flush=True)
     assert hit_t >= 0.85 and hit_t > hit_p and reg_t < reg_p
-    S.spmv_classifier_unload(S.SPMV_CLF_DTREE)
-    S.spmv_classifier_unload(S.SPMV_CLF_GNB)
