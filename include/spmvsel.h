@@ -66,7 +66,7 @@ typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
  *              each stored as its own CSR and run on the XCDs that take that
  *              slice, so the slice of x it gathers stays in their L2; rows
  *              are streamed through LDS per slice, rows with a slice segment
- *              over 512 nonzeros are summed from the CSR in chunks instead
+ *              over 128 nonzeros are summed from the CSR in chunks instead
  *              (merge-path tiles per slice when such rows hold over a
  *              quarter of the nonzeros); S partial y vectors are summed in
  *              slice order.  (The name is kept from an earlier design that
@@ -210,8 +210,8 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
  * partitions, 9 delta16 feasible, 10 x-block feasible (always 1),
  * 11 delta16 rows per block, 12 x-block per-slice kernel (rows per block of
  * row streaming, or 0 for merge-path tiles), 13 x-block long rows (rows
- * with a slice segment longer than 512 nonzeros, summed from the original
- * CSR in chunks of 2048 instead of in the slices; 0 when they would hold
+ * with a slice segment longer than 128 nonzeros, summed from the original
+ * CSR in chunks of 256 instead of in the slices; 0 when they would hold
  * more than a quarter of the nonzeros, in which case nothing is split and
  * the slices use merge-path tiles). */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);

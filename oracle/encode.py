@@ -130,7 +130,7 @@ def slice_csr_ref(rowptr, colind, n_cols: int, slices: int = 8):
     return rps.astype(np.int32), np.concatenate(cols).astype(np.int32)
 
 
-def xblock_split_ref(rowptr, colind, n_cols: int, slices: int, max_seg: int = 512,
+def xblock_split_ref(rowptr, colind, n_cols: int, slices: int, max_seg: int = 128,
                      max_share: float = 0.25):
     """The x-block split into short and long rows.
 

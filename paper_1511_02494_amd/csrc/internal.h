@@ -23,8 +23,8 @@ constexpr int kMergeTile = kBlock * kMergeIpt;
 constexpr int kSlices = 8;            // x-block column slices at most (one per XCD)
 constexpr int64_t kSliceXEntries = 256ll << 10;  // x entries per slice the automatic count aims at
 constexpr int kSliceMinAvg = 2;       // ... keeping at least this many nonzeros per slice row
-constexpr int kSliceStreamMaxLen = kChunk / 4;  // longest slice segment for row streaming
-constexpr int kLongChunk = 1024;      // nonzeros per block of the long-row sums
+constexpr int kSliceStreamMaxLen = 128;  // longest slice segment for row streaming
+constexpr int kLongChunk = 256;       // nonzeros per block of the long-row sums
 constexpr double kLongMaxShare = 0.25;  // long rows leave the slices up to this share of NNZ
 constexpr int kKahanMinLen = 257;     // FP32 rows longer than 256 use Kahan sums
 constexpr int kLineBytes = 128;       // cache line assumed by the miss feature

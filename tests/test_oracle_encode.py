@@ -176,7 +176,7 @@ def test_xblock_split_takes_long_rows_out():
     assert lr.tolist() == [17, 230]
     for s in range(4):
         seg = np.diff(rps[s])
-        assert seg[17] == 0 and seg[230] == 0 and seg.max() <= 512
+        assert seg[17] == 0 and seg[230] == 0 and seg.max() <= 128
     # short rows keep their slice segments unchanged
     full, _ = slice_csr_ref(rp, ci, m, 4)
     keep = np.setdiff1d(np.arange(n), lr)
@@ -184,7 +184,7 @@ def test_xblock_split_takes_long_rows_out():
     assert len(cols) + 1400 == len(ci)
     # brute force of the long-row rule
     width = 2000
-    brute = [i for i in range(n) if max(np.bincount(rows[i] // width, minlength=4), default=0) > 512]
+    brute = [i for i in range(n) if max(np.bincount(rows[i] // width, minlength=4), default=0) > 128]
     assert brute == lr.tolist()
     # long rows above a quarter of the nonzeros: nothing is split
     lr2, rps2, _ = xblock_split_ref(rp, ci, m, 4, max_share=0.1)
