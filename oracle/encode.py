@@ -6,6 +6,12 @@
   reference column per block of consecutive rows (the block's smallest
   column), which a GPU decodes with a single add and no in-row scan or row
   lookup.  Feasible iff no block spans more than 65536 columns.
+* ``delta16_sliced_ref``  the second layout of the same 16-bit offsets, for
+  matrices whose rows in a group of 64 have nearly equal lengths (stencils):
+  64-row slices stored column-major in pairs, one row per lane of a
+  wavefront, each slice with its own reference column.  A combination of the
+  MB optimisation with a GPU storage order, in the spirit of the paper's
+  closing remarks on wider pools and multi-level optimisation.
 * ``merge_splits_ref``  start coordinates of the nonzero-balanced merge-path
   tiles (Merrill and Garland, SC'16): the merge of the row-end list
   ``rowptr[1..N]`` with the nonzero indices ``0..NNZ-1``, where nonzero j is
@@ -47,6 +53,73 @@ def delta16_ref(rowptr, colind, block_rows: int = 256):
             if off[a:e].max() > 65535:
                 feasible = False
     return feasible, base.astype(np.int32), (off & 0xFFFF).astype(np.uint16)
+
+
+SLICE_ROWS = 64     # rows per slice: one per lane of a wavefront
+SLICE_MAX_PAD = 1.3  # sliced layout only if its slots are at most this many per nonzero
+
+
+def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
+    """The sliced delta16 layout of a CSR matrix.
+
+    Slice s holds rows [64 s, 64 s + 64) (lanes past the last row are empty
+    rows).  Its width w_s is its longest row rounded up to an even count, its
+    reference column base_s the smallest column among its nonzeros (0 if
+    none), and its storage starts at unit u_s = sum_{t<s} w_t / 2, where one
+    unit is 128 slots (a pair of nonzeros for each of the 64 lanes).  The
+    k-th nonzero (k from 0, in column order) of the row in lane l lives at
+
+        slot = 128 u_s + 128 (k // 2) + 2 l + (k % 2)
+
+    with off[slot] = c - base_s and vals[slot] = a; every other slot holds 0.
+    Returns a dict with width (int32[S]), base (int32[S]), units (int32[S],
+    the exclusive prefix sums u_s), slots (64 sum w_s), off (int64[slots];
+    the caller checks they fit 16 bits) and vals (float64[slots]).
+    """
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colind = np.asarray(colind, dtype=np.int64)
+    val = np.asarray(val, dtype=np.float64)
+    n = len(rowptr) - 1
+    ns = (n + slice_rows - 1) // slice_rows
+    width = np.zeros(ns, dtype=np.int64)
+    base = np.zeros(ns, dtype=np.int64)
+    for s in range(ns):
+        r0, r1 = s * slice_rows, min(n, (s + 1) * slice_rows)
+        lens = rowptr[r0 + 1:r1 + 1] - rowptr[r0:r1]
+        longest = int(lens.max()) if len(lens) else 0
+        width[s] = longest + (longest % 2)
+        a, e = rowptr[r0], rowptr[r1]
+        base[s] = colind[a:e].min() if a < e else 0
+    units = np.zeros(ns, dtype=np.int64)
+    for s in range(1, ns):
+        units[s] = units[s - 1] + width[s - 1] // 2
+    slots = int(slice_rows * width.sum())
+    off = np.zeros(slots, dtype=np.int64)
+    vals = np.zeros(slots, dtype=np.float64)
+    pair_stride = 2 * slice_rows
+    for i in range(n):
+        s, lane = divmod(i, slice_rows)
+        for k in range(rowptr[i + 1] - rowptr[i]):
+            j = rowptr[i] + k
+            slot = pair_stride * units[s] + pair_stride * (k // 2) + 2 * lane + (k % 2)
+            off[slot] = colind[j] - base[s]
+            vals[slot] = val[j]
+    return dict(width=width.astype(np.int32), base=base.astype(np.int32),
+                units=units.astype(np.int32), slots=slots, off=off, vals=vals)
+
+
+def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int,
+                       max_pad: float = SLICE_MAX_PAD) -> int:
+    """Layout of the delta16 variant: -1 infeasible, 0 rows streamed, 1 sliced.
+
+    A 64-row slice lies inside one block of the streamed layout, so it spans
+    no more columns than that block: the sliced layout is feasible whenever
+    the streamed one is, and it is taken when padding keeps its slot count at
+    most ``max_pad`` times the nonzero count.
+    """
+    if not block_feasible:
+        return -1
+    return 1 if slots <= max_pad * nnz else 0
 
 
 def merge_walk_ref(rowptr, items_per_tile: int):

@@ -6,9 +6,10 @@ import numpy as np
 import pytest
 
 import synth
-from oracle.encode import (bf16_bits_to_f64, delta16_ref, merge_search_ref,
-                           merge_walk_ref, partition_ref, slice_csr_ref,
-                           to_bf16_bits_ref, to_f32_ref)
+from oracle.encode import (bf16_bits_to_f64, delta16_layout_ref, delta16_ref,
+                           delta16_sliced_ref, merge_search_ref, merge_walk_ref,
+                           partition_ref, slice_csr_ref, to_bf16_bits_ref, to_f32_ref)
+from oracle.spmv import spmv_seq
 
 
 def cases(seed=3, count=40):
@@ -43,6 +44,95 @@ def test_delta16_random_2m_infeasible_stencil_feasible():
     assert not delta16_ref(rp, ci)[0]
     rp, ci, _ = synth.stencil3d_27(30)
     assert delta16_ref(rp, ci)[0]
+
+
+def test_delta16_sliced_laplacian_closed_form():
+    """5-point Laplacian on a 64 x 64 grid: slice s is grid line s.
+
+    Lines 0 and 63 have rows of 3 or 4 nonzeros (width 4), the other lines
+    rows of 4 or 5 (width 6); line s >= 1 starts with column 64 (s - 1).
+    Row 64 s + j of an inner line and inner column (1 <= s, j <= 62) holds
+    columns 64(s-1)+j, 64s+j-1, 64s+j, 64s+j+1, 64(s+1)+j.
+    """
+    rp, ci, v = synth.laplace2d(64)
+    L = delta16_sliced_ref(rp, ci, v)
+    assert L["width"].tolist() == [4] + [6] * 62 + [4]
+    assert L["base"].tolist() == [0] + [64 * (s - 1) for s in range(1, 64)]
+    assert L["units"].tolist() == [0] + [2 + 3 * (s - 1) for s in range(1, 64)]
+    assert L["slots"] == 64 * (4 + 6 * 62 + 4) == 24320
+    assert len(ci) == 20224
+    assert delta16_layout_ref(True, L["slots"], len(ci)) == 1  # 1.2025 slots per nonzero
+    for s_, j in ((1, 1), (17, 40), (62, 62)):
+        for k, want in enumerate([j, 63 + j, 64 + j, 65 + j, 128 + j]):
+            slot = 128 * (2 + 3 * (s_ - 1)) + 128 * (k // 2) + 2 * j + k % 2
+            assert L["off"][slot] == want
+            assert L["vals"][slot] == (4.0 if k == 2 else -1.0)
+        # the padding slot after the fifth nonzero
+        assert L["vals"][128 * (2 + 3 * (s_ - 1)) + 128 * 2 + 2 * j + 1] == 0.0
+
+
+def test_delta16_sliced_layout_rule():
+    # rows of 1 and 2 nonzeros: width 2, 128 slots per 96 nonzeros -> streamed
+    n = 128
+    lens = np.array([1 + (i % 2) for i in range(n)])
+    rp = np.concatenate([[0], np.cumsum(lens)])
+    ci = np.concatenate([np.arange(i, i + lens[i]) for i in range(n)])
+    L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
+    assert L["slots"] == 256 and len(ci) == 192
+    assert delta16_layout_ref(True, L["slots"], len(ci)) == 0
+    assert delta16_layout_ref(False, 0, 0) == -1
+    # equal odd rows of 27: 28 slots per 27 nonzeros -> sliced
+    rp = np.arange(0, 27 * 128 + 1, 27)
+    ci = np.concatenate([np.arange(27) + i for i in range(128)])
+    L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
+    assert L["width"].tolist() == [28, 28] and L["slots"] == 64 * 56
+    assert delta16_layout_ref(True, L["slots"], len(ci)) == 1
+    # 70 such rows: the second slice pads 58 empty lanes -> streamed
+    L = delta16_sliced_ref(rp[:71], ci[:27 * 70], np.ones(27 * 70))
+    assert L["slots"] == 64 * 56
+    assert delta16_layout_ref(True, L["slots"], 27 * 70) == 0
+
+
+def test_delta16_sliced_places_every_nonzero_once():
+    for rp, ci, v in cases(seed=11):
+        n = len(rp) - 1
+        L = delta16_sliced_ref(rp, ci, v)
+        seen = np.zeros(L["slots"], dtype=bool)
+        for i in range(n):
+            s_, lane = divmod(i, 64)
+            assert L["width"][s_] % 2 == 0 and L["width"][s_] >= rp[i + 1] - rp[i]
+            for k in range(rp[i + 1] - rp[i]):
+                slot = 128 * L["units"][s_] + 128 * (k // 2) + 2 * lane + k % 2
+                assert not seen[slot]
+                seen[slot] = True
+                assert L["base"][s_] + L["off"][slot] == ci[rp[i] + k]
+                assert L["vals"][slot] == v[rp[i] + k]
+        assert not np.any(L["vals"][~seen]) and not np.any(L["off"][~seen])
+        for s_ in range(len(L["base"])):
+            seg = ci[rp[64 * s_]:rp[min(n, 64 * s_ + 64)]]
+            assert L["base"][s_] == (seg.min() if len(seg) else 0)
+
+
+def test_delta16_sliced_spmv_in_lane_order_is_sequential():
+    """Summing each lane's slots in k order from +0 is Algorithm 1's sum."""
+    rng = np.random.default_rng(5)
+    for n in (1, 63, 64, 65, 200):
+        lens = rng.integers(0, 40, n)
+        lens[rng.integers(0, n)] = 0
+        rp = np.concatenate([[0], np.cumsum(lens)])
+        ci = np.concatenate([np.sort(rng.choice(300, l, replace=False)) for l in lens]).astype(np.int64)
+        v = rng.uniform(-1, 1, len(ci))
+        x = rng.uniform(-1, 1, 300)
+        L = delta16_sliced_ref(rp, ci, v)
+        y = np.zeros(n)
+        for i in range(n):
+            s_, lane = divmod(i, 64)
+            acc = 0.0
+            for k in range(rp[i + 1] - rp[i]):
+                slot = 128 * L["units"][s_] + 128 * (k // 2) + 2 * lane + k % 2
+                acc = acc + L["vals"][slot] * x[L["base"][s_] + L["off"][slot]]
+            y[i] = acc
+        assert np.array_equal(y, spmv_seq(rp, ci, v, x))
 
 
 @pytest.mark.parametrize("T", [1, 3, 7, 64, 2048])
