@@ -64,6 +64,8 @@ def kernel_names(v, plan):
         return ["void spmvsel::k_merge_slices<double>", "void spmvsel::k_merge_fixup_slices<double>",
                 "void spmvsel::k_slice_sum<double>"]
     if v == S.V_DELTA16:
+        if plan.query(14) == 1:  # sliced layout
+            return ["void spmvsel::k_sliced_d16<double>"]
         return [f"void spmvsel::k_rowstream<double, true, {plan.query(11) // 256}>"]
     return [f"void spmvsel::k_rowstream<double, false, {plan.query(2) // 256}>"]
 

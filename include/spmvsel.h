@@ -59,8 +59,16 @@ typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
  *              (vectorisation, class CMP; the architecture-centric default).
  *  MERGE_PATH  nonzero-balanced merge-path tiles (class IMB; replaces the
  *              OpenMP dynamic/auto schedules).
- *  DELTA16     16-bit column offsets from one reference column per block of
- *              rows, streamed through LDS (column-index compression, class MB).
+ *  DELTA16     16-bit column offsets from one reference column per group of
+ *              rows (column-index compression, class MB; Section 3.3), in one
+ *              of two layouts (spmv_set_delta16_layout): rows streamed
+ *              through LDS with one reference per block of 256 x R rows, or
+ *              sliced: slices of 64 rows, one row per lane of a wavefront,
+ *              the nonzeros stored column-major in pairs with one reference
+ *              per slice, taken when padding to the slice's longest row
+ *              costs at most 1.35 slots per nonzero, or 1.5 when rows
+ *              average 16 nonzeros or more (stencils, rows of nearly equal
+ *              length).
  *  XBLOCK_LDS  x blocking (class CML; replaces software prefetching of x):
  *              the columns are cut into S <= 8 slices (spmv_set_xblock_slices),
  *              each stored as its own CSR and run on the XCDs that take that
@@ -186,6 +194,15 @@ spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
  * (synchronous).  SPMV_ERR_ARG for any other value. */
 spmv_status_t spmv_set_xblock_slices(spmv_plan_t plan, int32_t slices);
 
+/* Layout of the DELTA16 format: -1 (default) picks the sliced layout when
+ * its slots (each slice padded to its longest row, rounded up to even) are
+ * at most 1.35 per nonzero, or 1.5 when NNZ >= 16 N, else rows streamed
+ * (sliced layouts also need NNZ < 2^30); 0 forces rows streamed, 1
+ * forces sliced (tests, tuning).  A built format is dropped and, if DELTA16
+ * is the plan's variant, rebuilt (synchronous).  SPMV_ERR_ARG for any other
+ * value; building reports SPMV_ERR_INFEASIBLE as for the variant. */
+spmv_status_t spmv_set_delta16_layout(spmv_plan_t plan, int32_t layout);
+
 /* Bit v set if variant v can run this matrix (computes features if needed). */
 spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
 
@@ -213,7 +230,9 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
  * with a slice segment longer than 128 nonzeros, summed from the original
  * CSR in chunks of 256 instead of in the slices; 0 when they would hold
  * more than a quarter of the nonzeros, in which case nothing is split and
- * the slices use merge-path tiles). */
+ * the slices use merge-path tiles), 14 delta16 layout (-1 infeasible,
+ * 0 rows streamed, 1 sliced), 15 delta16 sliced slots (64 x the sum of the
+ * slice widths, padding included). */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:
@@ -224,6 +243,14 @@ spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
  * indices int32[NNZ minus the long rows' nonzeros],
  * 6 profiling partition bounds int32[parts+1], 7 x-block long rows
  * int32[key 13] (ascending; their slice segments are empty in 4 and 5).
+ * Sliced delta16 layout (SPMV_ERR_ARG in the streamed layout, as 0 and 1
+ * are in the sliced one), S = ceil(N / 64) slices: 8 widths int32[S] (the
+ * slice's longest row rounded up to even), 9 units int32[S] (exclusive
+ * prefix sums of width / 2), 10 reference columns int32[S] (the slice's
+ * smallest column, 0 if it has none), 11 offsets uint16[key 15],
+ * 12 values [key 15] of the plan's value type.  The k-th nonzero of row
+ * 64 s + l is at slot 128 units[s] + 128 (k / 2) + 2 l + (k % 2); every
+ * other slot holds zero.
  * `bytes` must equal the array size. */
 spmv_status_t spmv_plan_copy_format(spmv_plan_t plan, int32_t which,
                                     void *host_dst, int64_t bytes);

@@ -55,8 +55,10 @@ def delta16_ref(rowptr, colind, block_rows: int = 256):
     return feasible, base.astype(np.int32), (off & 0xFFFF).astype(np.uint16)
 
 
-SLICE_ROWS = 64     # rows per slice: one per lane of a wavefront
-SLICE_MAX_PAD = 1.3  # sliced layout only if its slots are at most this many per nonzero
+SLICE_ROWS = 64          # rows per slice: one per lane of a wavefront
+SLICE_MAX_PAD = 1.35     # sliced layout only if its slots are at most this many per nonzero,
+SLICE_MAX_PAD_LONG = 1.5  # or this many when the rows average at least
+SLICE_LONG_MEAN = 16      # this many nonzeros
 
 
 def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
@@ -108,18 +110,21 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
                 units=units.astype(np.int32), slots=slots, off=off, vals=vals)
 
 
-def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int,
-                       max_pad: float = SLICE_MAX_PAD) -> int:
+def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int, n: int) -> int:
     """Layout of the delta16 variant: -1 infeasible, 0 rows streamed, 1 sliced.
 
     A 64-row slice lies inside one block of the streamed layout, so it spans
     no more columns than that block: the sliced layout is feasible whenever
-    the streamed one is, and it is taken when padding keeps its slot count at
-    most ``max_pad`` times the nonzero count.
+    the streamed one is.  It is taken when padding keeps its slot count at
+    most 1.35 times the nonzero count, or 1.5 times when the rows of the n-row
+    matrix average at least 16 nonzeros, and NNZ < 2^30.
     """
     if not block_feasible:
         return -1
-    return 1 if slots <= max_pad * nnz else 0
+    if nnz >= 1 << 30:
+        return 0
+    ok = slots <= SLICE_MAX_PAD * nnz or (nnz >= SLICE_LONG_MEAN * n and slots <= SLICE_MAX_PAD_LONG * nnz)
+    return 1 if ok else 0
 
 
 def merge_walk_ref(rowptr, items_per_tile: int):

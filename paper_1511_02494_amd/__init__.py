@@ -68,6 +68,7 @@ _PROTOS = {
     "spmv_get_variant": (_I32, [_P, _PI32]),
     "spmv_variant_mask": (_I32, [_P, _PU32]),
     "spmv_set_xblock_slices": (_I32, [_P, _I32]),
+    "spmv_set_delta16_layout": (_I32, [_P, _I32]),
     "spmv_bytes": (_I32, [_P, _I32, _PI64]),
     "spmv_time_variant": (_I32, [_P, _I32, _I32, _I32, _PF64, _PF64]),
     "spmv_plan_query": (_I32, [_P, _I32, _PI64]),
@@ -205,6 +206,10 @@ def spmv_set_xblock_slices(plan, slices: int):
     _check("spmv_set_xblock_slices", lib.spmv_set_xblock_slices(plan, slices))
 
 
+def spmv_set_delta16_layout(plan, layout: int):
+    _check("spmv_set_delta16_layout", lib.spmv_set_delta16_layout(plan, layout))
+
+
 def spmv_variant_mask(plan) -> int:
     b = _U32()
     _check("spmv_variant_mask", lib.spmv_variant_mask(plan, ctypes.byref(b)))
@@ -231,11 +236,14 @@ def spmv_plan_query(plan, key: int) -> int:
 
 
 _FORMAT_DTYPES = {0: np.int32, 1: np.uint16, 2: np.int32, 3: np.int32, 4: np.int32,
-                  5: np.int32, 6: np.int32, 7: np.int32}
+                  5: np.int32, 6: np.int32, 7: np.int32, 8: np.int32, 9: np.int32, 10: np.int32,
+                  11: np.uint16}
 
 
-def spmv_plan_copy_format(plan, which: int, count: int) -> np.ndarray:
-    out = np.empty(count, dtype=_FORMAT_DTYPES[which])
+def spmv_plan_copy_format(plan, which: int, count: int, dtype=None) -> np.ndarray:
+    """Array ``which`` of the plan's formats; ``dtype`` is required for the
+    sliced delta16 values (12), which have the plan's value type."""
+    out = np.empty(count, dtype=dtype or _FORMAT_DTYPES[which])
     _check("spmv_plan_copy_format",
            lib.spmv_plan_copy_format(plan, which, out.ctypes.data_as(_P), out.nbytes))
     return out
@@ -482,6 +490,9 @@ class Plan:
 
     def set_variant(self, v):
         spmv_set_variant(self.handle, v)
+
+    def set_delta16_layout(self, layout):
+        spmv_set_delta16_layout(self.handle, layout)
 
     @property
     def variant(self):

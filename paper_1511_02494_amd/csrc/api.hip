@@ -301,6 +301,65 @@ spmv_status_t check_d16(spmv_plan *P) {
 
 bool d16_feasible(const spmv_plan *P) { return P->d16_feasible; }
 
+// delta16 layout: the shape of the sliced layout (widths, reference columns,
+// slot offsets) decides it; sliced when its slots, padding included, are at
+// most kSellMaxPad per nonzero, or kSellMaxPadLong when rows average at least
+// kSellLongMean nonzeros (longer rows hide more padding), or when forced.  A
+// 64-row slice lies inside one block of the streamed layout, so it is
+// feasible whenever that is.
+spmv_status_t d16_decide_layout(spmv_plan *P) {
+    if (P->d16_layout >= 0) return SPMV_OK;
+    SPMV_TRY(check_d16(P));
+    if (!d16_feasible(P))
+        return fail(SPMV_ERR_INFEASIBLE,
+                    "delta16: a block of %d rows spans more than 65536 columns", P->d16_rows);
+    if (P->nnz >= (1ll << 30)) {  // beyond the sliced layout's int32 slot arithmetic
+        if (P->d16_layout_req == 1)
+            return fail(SPMV_ERR_INFEASIBLE, "delta16: the sliced layout needs NNZ < 2^30");
+        P->d16_layout = 0;
+        return SPMV_OK;
+    }
+    const int64_t nsl = (P->n + kSellRows - 1) / kSellRows;
+    const size_t nb = (size_t)(nsl > 0 ? nsl : 1) * 4;
+    SPMV_TRY(P->d16s_width.alloc(nb));
+    SPMV_TRY(P->d16s_units.alloc(nb + 4));  // the scan also writes the total after the last slice
+    SPMV_TRY(P->d16s_base.alloc(nb));
+    DevBuf halfw, tmp;
+    SPMV_TRY(halfw.alloc(nb));
+    int64_t units = 0;
+    if (nsl > 0) {
+        SPMV_HIP(launch_sliced_shape(*P, P->d16s_width.as<int32_t>(), halfw.as<int32_t>(),
+                                     P->d16s_base.as<int32_t>(), S(P)));
+        size_t need = 0;
+        int64_t *dtot = scr<int64_t>(P, kOffSum);
+        SPMV_HIP(launch_exclusive_scan_i32(halfw.as<int32_t>(), P->d16s_units.as<int32_t>(), nsl, 1,
+                                           dtot, nullptr, 0, S(P), &need));
+        SPMV_TRY(tmp.alloc(need));
+        SPMV_HIP(launch_exclusive_scan_i32(halfw.as<int32_t>(), P->d16s_units.as<int32_t>(), nsl, 1,
+                                           dtot, tmp.p, tmp.bytes, S(P), nullptr));
+        SPMV_HIP(hipMemcpyAsync(P->h_pinned, dtot, 8, hipMemcpyDeviceToHost, S(P)));
+        SPMV_TRY(sync(P));
+        memcpy(&units, P->h_pinned, 8);
+    }
+    P->d16_nsl = nsl;
+    P->d16_slots = units * 2 * kSellRows;
+    // the unit offsets are int32 (with NNZ < 2^30 every width is too)
+    const bool representable = units <= INT32_MAX;
+    const double slots = (double)P->d16_slots, nnz = (double)P->nnz;
+    const bool padded_ok = slots <= kSellMaxPad * nnz ||
+                           (P->nnz >= (int64_t)kSellLongMean * P->n && slots <= kSellMaxPadLong * nnz);
+    const int automatic = representable && padded_ok ? 1 : 0;
+    if (P->d16_layout_req == 1 && !representable)
+        return fail(SPMV_ERR_INFEASIBLE, "delta16: the sliced layout needs under 2^31 slot pairs");
+    P->d16_layout = P->d16_layout_req >= 0 ? P->d16_layout_req : automatic;
+    if (P->d16_layout == 0) {
+        P->d16s_width.release();
+        P->d16s_units.release();
+        P->d16s_base.release();
+    }
+    return SPMV_OK;
+}
+
 // ------------------------------------------------------------ formats
 // x blocking: split the columns into S slices (S <= 8, one XCD group each)
 // and store each slice as its own CSR (rowptr per slice, slice-major
@@ -482,10 +541,19 @@ spmv_status_t build_format(spmv_plan *P, int v) {
         return SPMV_OK;
     case V_DELTA16: {
         if (P->d16_built) return SPMV_OK;
-        SPMV_TRY(check_d16(P));
-        if (!d16_feasible(P))
-            return fail(SPMV_ERR_INFEASIBLE,
-                        "delta16: a block of %d rows spans more than 65536 columns", P->d16_rows);
+        SPMV_TRY(d16_decide_layout(P));
+        if (P->d16_layout == 1) {
+            const size_t slots = (size_t)P->d16_slots;
+            SPMV_TRY(P->d16s_off.alloc(slots * 2 + 16));
+            SPMV_TRY(P->d16s_val.alloc(slots * vbytes(P->dtype) + 16));
+            SPMV_HIP(hipMemsetAsync(P->d16s_off.p, 0, slots * 2 + 16, S(P)));
+            SPMV_HIP(hipMemsetAsync(P->d16s_val.p, 0, slots * vbytes(P->dtype) + 16, S(P)));
+            SPMV_HIP(launch_sliced_scatter(*P, P->d16s_units.as<int32_t>(), P->d16s_base.as<int32_t>(),
+                                           P->d16s_off.as<uint16_t>(), P->d16s_val.p, S(P)));
+            SPMV_TRY(sync(P));
+            P->d16_built = true;
+            return SPMV_OK;
+        }
         SPMV_TRY(P->d16_off.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 2 + 16));
         SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(), P->d16_off.as<uint16_t>(),
                                        S(P)));
@@ -670,7 +738,10 @@ spmv_status_t run_variant(const spmv_plan *P, int v, const void *x, void *y, hip
     case V_CSR_SCALAR: SPMV_HIP(launch_csr_scalar(*P, x, y, s)); break;
     case V_CSR_VECTOR: SPMV_HIP(launch_csr_vector(*P, x, y, s)); break;
     case V_MERGE_PATH: SPMV_HIP(launch_merge_path(*P, x, y, s)); break;
-    case V_DELTA16: SPMV_HIP(launch_rowstream(*P, true, x, y, s)); break;
+    case V_DELTA16:
+        if (P->d16_layout == 1) SPMV_HIP(launch_sliced_d16(*P, x, y, s));
+        else SPMV_HIP(launch_rowstream(*P, true, x, y, s));
+        break;
     case V_XBLOCK_LDS: SPMV_HIP(launch_xblock(*P, x, y, s)); break;
     case V_SHORT_ROW: SPMV_HIP(launch_rowstream(*P, false, x, y, s)); break;
     default: return fail(SPMV_ERR_ARG, "unknown variant %d", v);
@@ -924,8 +995,9 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
     const int64_t ib = v == V_DELTA16 ? 2 : 4;
     int64_t extra = 0;
     if (v == V_DELTA16) {
-        SPMV_TRY(check_d16(P));
-        extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
+        SPMV_TRY(d16_decide_layout(P));
+        extra = P->d16_layout == 1 ? 12 * P->d16_nsl  // width, units and base per slice
+                                   : 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
     }
     *bytes = 4 * (P->n + 1) + (ib + vb) * P->nnz + xb * P->m + xb * P->n + extra;
     return SPMV_OK;
@@ -964,6 +1036,13 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
     case 8: *value = P->parts; break;
     case 9: SPMV_TRY(check_d16(P)); *value = d16_feasible(P); break;
     case 11: SPMV_TRY(check_d16(P)); *value = P->d16_rows; break;
+    case 14:
+        SPMV_TRY(check_d16(P));
+        if (!d16_feasible(P)) { *value = -1; break; }
+        SPMV_TRY(d16_decide_layout(P));
+        *value = P->d16_layout;
+        break;
+    case 15: SPMV_TRY(d16_decide_layout(P)); *value = P->d16_slots; break;
     case 10: *value = 1; break;
     default: return fail(SPMV_ERR_ARG, "unknown key %d", key);
     }
@@ -976,8 +1055,17 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
     const void *src = nullptr;
     int64_t want = 0;
     switch (which) {
+    case 8: case 9: case 10: case 11: case 12:
+        SPMV_TRY(build_format(P, V_DELTA16));
+        if (P->d16_layout != 1) return fail(SPMV_ERR_ARG, "delta16 is not in the sliced layout");
+        src = which == 8 ? P->d16s_width.p : which == 9 ? P->d16s_units.p : which == 10 ? P->d16s_base.p
+            : which == 11 ? P->d16s_off.p : P->d16s_val.p;
+        want = which <= 10 ? 4 * P->d16_nsl : which == 11 ? 2 * P->d16_slots
+                                                           : vbytes(P->dtype) * P->d16_slots;
+        break;
     case 0: case 1:
         SPMV_TRY(build_format(P, V_DELTA16));
+        if (P->d16_layout != 0) return fail(SPMV_ERR_ARG, "delta16 is not in the streamed layout");
         src = which == 0 ? P->d16_base.p : P->d16_off.p;
         want = which == 0 ? 4 * ((P->n + P->d16_rows - 1) / P->d16_rows) : 2 * P->nnz;
         break;
@@ -1221,6 +1309,26 @@ spmv_status_t spmv_set_xblock_slices(spmv_plan_t P, int32_t slices) {
         P->xs_built = false;
         if (P->variant == V_XBLOCK_LDS) SPMV_TRY(build_xslices(P));  // else on next use
     }
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_set_delta16_layout(spmv_plan_t P, int32_t layout) {
+    clear_error();
+    if (!P) return fail(SPMV_ERR_ARG, "NULL plan");
+    if (layout < -1 || layout > 1)
+        return fail(SPMV_ERR_ARG, "delta16 layout must be -1 (automatic), 0 or 1, not %d", layout);
+    if (layout == P->d16_layout_req) return SPMV_OK;
+    SPMV_TRY(sync(P));
+    P->d16_layout_req = layout;
+    P->d16_layout = -1;
+    P->d16_built = false;
+    P->d16_off.release();
+    P->d16s_width.release();
+    P->d16s_units.release();
+    P->d16s_base.release();
+    P->d16s_off.release();
+    P->d16s_val.release();
+    if (P->variant == V_DELTA16) SPMV_TRY(build_format(P, V_DELTA16));  // else on next use
     return SPMV_OK;
 }
 

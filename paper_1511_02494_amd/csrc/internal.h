@@ -27,6 +27,10 @@ constexpr int kSliceStreamMaxLen = 128;  // longest slice segment for row stream
 constexpr int kLongChunk = 256;       // nonzeros per block of the long-row sums
 constexpr double kLongMaxShare = 0.25;  // long rows leave the slices up to this share of NNZ
 constexpr int kKahanMinLen = 257;     // FP32 rows longer than 256 use Kahan sums
+constexpr int kSellRows = 64;         // rows per slice of the sliced delta16 layout (one per lane)
+constexpr double kSellMaxPad = 1.35;  // ... taken when its slots are at most this many per nonzero,
+constexpr double kSellMaxPadLong = 1.5;  // or this many when the mean row has
+constexpr int kSellLongMean = 16;        // at least this many nonzeros
 constexpr int kLineBytes = 128;       // cache line assumed by the miss feature
 constexpr int64_t kLlcBytes = 256ll << 20;
 constexpr int kFeatBlocks = 1024;     // feature kernel partial records
@@ -103,6 +107,12 @@ struct spmv_plan {
     bool d16_checked = false, d16_feasible = false, d16_built = false;
     int d16_rows = 256;          // rows per block sharing one reference column
     spmvsel::DevBuf d16_base, d16_off, d16_cmax;
+    // delta16 layout: 0 rows streamed (d16_base/d16_off), 1 sliced (64-row
+    // slices stored column-major in pairs, one reference column per slice)
+    int d16_layout = -1;         // -1: not decided yet
+    int d16_layout_req = -1;     // forced layout, -1 automatic
+    int64_t d16_nsl = 0, d16_slots = 0;
+    spmvsel::DevBuf d16s_width, d16s_units, d16s_base, d16s_off, d16s_val;
     bool mp_built = false;
     int64_t mp_tiles = 0;
     spmvsel::DevBuf mp_split_row, mp_split_nnz, mp_carry_row, mp_carry_val;
@@ -152,12 +162,21 @@ hipError_t launch_features(const spmv_plan &P, uint64_t *d_partials, uint64_t *d
 hipError_t launch_csr_scalar(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 hipError_t launch_csr_vector(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y, hipStream_t s);
+hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 hipError_t launch_merge_path(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 
 // format preparation (k_prep.hip)
 hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16_t *off,
                                  hipStream_t s);
+// Sliced delta16 layout: per slice of kSellRows rows its width (longest row
+// rounded up to even), half width and reference column (smallest column);
+// then, with the scanned half widths (units of 128 slots), the scatter of
+// offsets and values into the zero-filled slot arrays.
+hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
+                               hipStream_t s);
+hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
+                                 uint16_t *off, void *vals, hipStream_t s);
 hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t panels,
                            unsigned long long *d_max, hipStream_t s);
 hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,

@@ -36,6 +36,106 @@ hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16
     return hipGetLastError();
 }
 
+// ---- delta16, sliced layout.  Slice s = rows [64 s, 64 s + 64), one per
+// lane of a wavefront; its width is the longest row rounded up to an even
+// count and its reference column the smallest column of its nonzeros.  The
+// k-th nonzero of the row in lane l is stored at slot
+//   128 units[s] + 128 (k / 2) + 2 l + (k % 2)
+// (units = exclusive prefix sums of the half widths), so that lane l reads
+// its nonzeros in pairs and a wavefront's pair load is 64 consecutive pairs.
+__global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
+                                                         const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         int32_t *__restrict__ width,
+                                                         int32_t *__restrict__ halfw,
+                                                         int32_t *__restrict__ base) {
+    const int64_t sl = blockIdx.x * (int64_t)(kBlock / kSellRows) + threadIdx.x / kSellRows;
+    if (sl >= nsl) return;  // whole wavefronts leave together
+    const int64_t r = sl * kSellRows + (threadIdx.x & (kSellRows - 1));
+    int len = 0, first = INT32_MAX;
+    if (r < n) {
+        const int32_t a = rp[r], e = rp[r + 1];
+        len = e - a;
+        if (len > 0) first = ci[a];
+    }
+#pragma unroll
+    for (int d = kSellRows / 2; d > 0; d >>= 1) {
+        const int ol = __shfl_xor(len, d, kSellRows);
+        const int of = __shfl_xor(first, d, kSellRows);
+        len = ol > len ? ol : len;
+        first = of < first ? of : first;
+    }
+    if ((threadIdx.x & (kSellRows - 1)) == 0) {
+        const int w = len + (len & 1);
+        width[sl] = w;
+        halfw[sl] = w / 2;
+        base[sl] = first == INT32_MAX ? 0 : first;
+    }
+}
+
+hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
+                               hipStream_t s) {
+    const int64_t nsl = (P.n + kSellRows - 1) / kSellRows;
+    if (nsl == 0) return hipSuccess;
+    const int64_t per = kBlock / kSellRows;
+    hipLaunchKernelGGL(k_sliced_shape, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0, s,
+                       P.n, nsl, P.rowptr, P.colind, width, halfw, base);
+    return hipGetLastError();
+}
+
+// One workgroup per kBlock rows (kBlock / 64 slices): thread t takes the
+// block's nonzeros t, t + kBlock, ... (coalesced reads), finds its row by a
+// binary search of the block's row pointers in LDS and writes its slot.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const V *__restrict__ val,
+                                                           const int32_t *__restrict__ units,
+                                                           const int32_t *__restrict__ base,
+                                                           uint16_t *__restrict__ off,
+                                                           V *__restrict__ vals) {
+    __shared__ int32_t s_rp[kBlock + 1];
+    const int64_t r0 = (int64_t)blockIdx.x * kBlock;
+    const int nrows = (int)((n - r0) < kBlock ? (n - r0) : kBlock);
+    for (int r = threadIdx.x; r <= nrows; r += kBlock) s_rp[r] = rp[r0 + r];
+    __syncthreads();
+    const int32_t e = s_rp[nrows];
+    for (int32_t j = s_rp[0] + (int32_t)threadIdx.x; j < e; j += kBlock) {
+        int lo = 0, hi = nrows - 1;  // last row i with s_rp[i] <= j
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_rp[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        const int64_t r = r0 + lo;
+        const int k = j - s_rp[lo];
+        const int64_t sl = r / kSellRows;
+        const int lane = (int)(r % kSellRows);
+        const int64_t slot = 2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1);
+        off[slot] = (uint16_t)(ci[j] - base[sl]);
+        vals[slot] = val[j];
+    }
+}
+
+hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
+                                 uint16_t *off, void *vals, hipStream_t s) {
+    if (P.n == 0 || P.nnz == 0) return hipSuccess;
+    const dim3 g((unsigned)((P.n + kBlock - 1) / kBlock));
+    switch (P.dtype) {
+    case SPMV_F64:
+        hipLaunchKernelGGL(k_sliced_scatter<double>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
+                           (const double *)P.val, units, base, off, (double *)vals);
+        break;
+    case SPMV_F32:
+        hipLaunchKernelGGL(k_sliced_scatter<float>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
+                           (const float *)P.val, units, base, off, (float *)vals);
+        break;
+    default:
+        hipLaunchKernelGGL(k_sliced_scatter<uint16_t>, g, dim3(kBlock), 0, s, P.n, P.rowptr,
+                           P.colind, (const uint16_t *)P.val, units, base, off, (uint16_t *)vals);
+    }
+    return hipGetLastError();
+}
+
 // largest window span (cmax - cmin) over panels, for the 16-bit feasibility test
 __global__ __launch_bounds__(kBlock) void k_max_span(const int32_t *__restrict__ cmin,
                                                      const int32_t *__restrict__ cmax,

@@ -186,6 +186,61 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
     rowstream_block<V, D16, R, false>(xcd_remap(blockIdx.x, gridDim.x), n, rp, ci, off, rbase, val, x, y);
 }
 
+// ============================================================ delta16, sliced
+// The sliced layout of the 16-bit offsets (slices of 64 rows, one row per
+// lane, nonzeros stored column-major in pairs; see k_sliced_scatter).  Lane l
+// of the wavefront of slice s sums its row in column order from +0, so FP64
+// results equal the sequential sum bit for bit.  Each step loads two pairs per
+// lane (a wavefront load is 64 consecutive pairs, coalesced), then gathers
+// their four x entries: on stencils the lanes' columns are consecutive too.
+// Every lane loads every pair up to the slice width (padding slots hold zero
+// offsets, so their gathers stay in range); products past the row's end are
+// dropped, which keeps the loads free of branches.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_sliced_d16(
+    int64_t n, int64_t nsl, const int32_t *__restrict__ rp, const int32_t *__restrict__ width,
+    const int32_t *__restrict__ units, const int32_t *__restrict__ base,
+    const uint16_t *__restrict__ off, const V *__restrict__ val,
+    const typename VT<V>::A *__restrict__ x, typename VT<V>::A *__restrict__ y) {
+    using A = typename VT<V>::A;
+    using VP = typename Pair<V>::type;
+    using OP = typename Pair<uint16_t>::type;
+    const int64_t sl = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kSellRows) +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x / kSellRows);
+    if (sl >= nsl) return;  // whole wavefronts leave together
+    const int lane = threadIdx.x & (kSellRows - 1);
+    const int64_t r = sl * kSellRows + lane;
+    const int w = width[sl];
+    const int64_t o = 2 * kSellRows * (int64_t)units[sl] + 2 * lane;
+    const int32_t b = base[sl];
+    const int len = r < n ? rp[r + 1] - rp[r] : 0;
+    const bool comp = is_f32<A>() && len >= kKahanMinLen;
+    Sum<A> acc;
+    for (int k0 = 0; k0 < w; k0 += 4) {
+        const int k1 = (k0 + 2) < w ? k0 + 2 : w - 2;  // past the width: reload the last pair
+        const int64_t q0 = o + (int64_t)(k0 / 2) * (2 * kSellRows);
+        const int64_t q1 = o + (int64_t)(k1 / 2) * (2 * kSellRows);
+        const VP v0 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q0));
+        const OP c0 = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + q0));
+        const VP v1 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q1));
+        const OP c1 = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + q1));
+        const A x0 = x[b + (int32_t)c0.x], x1 = x[b + (int32_t)c0.y];
+        const A x2 = x[b + (int32_t)c1.x], x3 = x[b + (int32_t)c1.y];
+        const A p[4] = {VT<V>::cvt(v0.x) * x0, VT<V>::cvt(v0.y) * x1, VT<V>::cvt(v1.x) * x2,
+                        VT<V>::cvt(v1.y) * x3};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (comp) {
+                if (k0 + i < len) acc.add_comp(p[i]);
+            } else {
+                // a +0 addend leaves a sum that started at +0 unchanged
+                acc.add(k0 + i < len ? p[i] : A(0));
+            }
+        }
+    }
+    if (r < n) y[r] = acc.s;
+}
+
 // ============================================================ merge path
 // Merrill and Garland's merge-based CSR SpMV.  Tile t covers the merge
 // diagonals [t*T, (t+1)*T) of row ends rowptr[1..N] and nonzero indices;
@@ -563,6 +618,21 @@ hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y
         default: return hipErrorInvalidValue;
         }
 #undef SPMV_RS
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    return by_dtype(P.dtype, [&](auto tag) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
+        using A = typename VT<V>::A;
+        const int64_t per = kBlock / kSellRows;
+        const unsigned g = (unsigned)((P.d16_nsl + per - 1) / per);
+        hipLaunchKernelGGL((k_sliced_d16<V>), dim3(g), dim3(kBlock), 0, s, P.n, P.d16_nsl, P.rowptr,
+                           P.d16s_width.as<int32_t>(), P.d16s_units.as<int32_t>(),
+                           P.d16s_base.as<int32_t>(), P.d16s_off.as<uint16_t>(),
+                           P.d16s_val.as<V>(), (const A *)x, (A *)y);
         return hipGetLastError();
     });
 }

@@ -6,8 +6,9 @@ import pytest
 
 import synth
 import paper_1511_02494_amd as S
-from oracle.encode import (delta16_ref, merge_search_ref, merge_walk_ref, partition_ref,
-                           xblock_split_ref, to_bf16_bits_ref, to_f32_ref)
+from oracle.encode import (delta16_layout_ref, delta16_ref, delta16_sliced_ref, merge_search_ref,
+                           merge_walk_ref, partition_ref, xblock_split_ref, to_bf16_bits_ref,
+                           to_f32_ref)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -34,8 +35,17 @@ def test_formats_match_oracle(name, build, m):
         pytest.fail("delta16 should have retried with 256-row blocks")
     assert S.spmv_plan_query(h, 9) == int(ok)
     if ok:
+        L = delta16_sliced_ref(rp, ci, v)
+        assert S.spmv_plan_query(h, 14) == delta16_layout_ref(True, L["slots"], nnz, n)
+        assert S.spmv_plan_query(h, 15) == L["slots"]
+        S.spmv_set_delta16_layout(h, 0)
+        assert S.spmv_plan_query(h, 14) == 0
         assert np.array_equal(S.spmv_plan_copy_format(h, 0, len(base)), base)
         assert np.array_equal(S.spmv_plan_copy_format(h, 1, nnz), off)
+        S.spmv_set_delta16_layout(h, 1)
+        check_sliced(h, L, np.float64)
+    else:
+        assert S.spmv_plan_query(h, 14) == -1
     T = S.spmv_plan_query(h, 3)
     tiles = S.spmv_plan_query(h, 4)
     si, sj = merge_search_ref(rp, T)
@@ -58,6 +68,51 @@ def test_formats_match_oracle(name, build, m):
         assert S.spmv_plan_query(h, 6) == tiles
     parts = S.spmv_plan_query(h, 8)
     assert np.array_equal(S.spmv_plan_copy_format(h, 6, parts + 1), partition_ref(rp, parts))
+    plan.close()
+
+
+def check_sliced(h, L, vdtype):
+    ns = len(L["width"])
+    assert np.array_equal(S.spmv_plan_copy_format(h, 8, ns), L["width"])
+    assert np.array_equal(S.spmv_plan_copy_format(h, 9, ns), L["units"])
+    assert np.array_equal(S.spmv_plan_copy_format(h, 10, ns), L["base"])
+    assert np.all(L["off"] < 65536)
+    assert np.array_equal(S.spmv_plan_copy_format(h, 11, L["slots"]), L["off"].astype(np.uint16))
+    got = S.spmv_plan_copy_format(h, 12, L["slots"], vdtype)
+    assert np.array_equal(got, L["vals"].astype(vdtype))
+
+
+@pytest.mark.parametrize("dtype", [S.SPMV_F32, S.SPMV_BF16])
+def test_delta16_sliced_low_precision_values(dtype):
+    """The sliced slots hold the plan's own FP32 / BF16 values."""
+    rp, ci, v = synth.stencil3d_27(9, seed=2, values="random")
+    plan = make_plan(rp, ci, v, 729, dtype)
+    S.spmv_set_delta16_layout(plan.handle, 1)
+    if dtype == S.SPMV_F32:
+        q = to_f32_ref(v).astype(np.float64)
+        L = delta16_sliced_ref(rp, ci, q)
+        check_sliced(plan.handle, L, np.float32)
+    else:
+        bits = to_bf16_bits_ref(v)
+        L = delta16_sliced_ref(rp, ci, bits.astype(np.float64))  # bit patterns as numbers
+        L["vals"] = L["vals"].astype(np.uint16)
+        check_sliced(plan.handle, L, np.uint16)
+    plan.close()
+
+
+def test_delta16_sliced_on_stencil_streamed_on_uneven_rows():
+    rp, ci, v = synth.stencil3d_27(16)
+    plan = make_plan(rp, ci, v, 4096)
+    assert S.spmv_plan_query(plan.handle, 14) == 1
+    plan.close()
+    rp, ci, v = synth.banded(6000, 300, 200, seed=4)  # lengths 0.5 d .. 1.5 d
+    plan = make_plan(rp, ci, v, 6000)
+    assert S.spmv_plan_query(plan.handle, 14) == 0
+    with pytest.raises(S.SpmvError) as e:
+        S.spmv_plan_copy_format(plan.handle, 8, 1)
+    assert e.value.status == S.SPMV_ERR_ARG
+    with pytest.raises(S.SpmvError):
+        S.spmv_set_delta16_layout(plan.handle, 2)
     plan.close()
 
 

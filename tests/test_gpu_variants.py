@@ -83,6 +83,59 @@ def test_variants_within_tolerance(case, dtype):
 
 
 @pytest.mark.parametrize("dtype", [S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16])
+@pytest.mark.parametrize("case", ["laplace64", "stencil27_12", "random_3000x8", "shortrows_5000",
+                                  "banded_4000", "ragged", "empty_rows"])
+def test_delta16_both_layouts(case, dtype):
+    """delta16 rows streamed and sliced: FP64 in Algorithm 1's order bit for
+    bit, FP32/BF16 (Kahan on the ragged case's rows above 256) within
+    tolerance, integer-valued inputs exact in every dtype."""
+    build, m = CASES[case]
+    rp, ci, v = build("random")
+    x = synth.vector(m, 15)
+    y_ref, scale = spmv_exact(rp, ci, v, x)
+    y_seq = spmv_seq(rp, ci, v, x)
+    ri, cii, vi = build("int")
+    xi = synth.int_vector(m, 16)
+    yi_seq = spmv_seq(ri, cii, vi, xi)
+    for layout in (0, 1):
+        plan = make_plan(rp, ci, v, m, dtype)
+        if not (plan.mask() >> S.V_DELTA16) & 1:
+            plan.close()
+            pytest.skip("delta16 infeasible")
+        S.spmv_set_delta16_layout(plan.handle, layout)
+        y = run(plan, S.V_DELTA16, x, dtype)
+        assert S.spmv_plan_query(plan.handle, 14) == layout
+        ok, worst = within_tolerance(y, y_ref, scale, TOL[dtype])
+        assert ok, (layout, worst)
+        if dtype == S.SPMV_F64:
+            assert np.array_equal(y, y_seq), layout
+        assert np.array_equal(y, run(plan, S.V_DELTA16, x, dtype))
+        plan.close()
+        if case == "empty_rows":  # its generator has no integer-valued form
+            continue
+        plan = make_plan(ri, cii, vi, m, dtype)
+        S.spmv_set_delta16_layout(plan.handle, layout)
+        assert np.array_equal(run(plan, S.V_DELTA16, xi, dtype), yi_seq), layout
+        plan.close()
+
+
+def test_delta16_layout_change_rebuilds():
+    rp, ci, v = CASES["stencil27_12"][0]("random")
+    x = synth.vector(1728, 17)
+    y_seq = spmv_seq(rp, ci, v, x)
+    plan = make_plan(rp, ci, v, 1728)
+    run(plan, S.V_DELTA16, x)
+    for layout in (0, 1, -1, 0):
+        S.spmv_set_delta16_layout(plan.handle, layout)  # active variant: rebuilt at once
+        xt = torch.from_numpy(np.asarray(x, np.float64)).to("cuda:0")
+        y = torch.full((plan.n,), float("nan"), dtype=torch.float64, device="cuda:0")
+        plan.execute(xt, y)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), y_seq), layout
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16])
 @pytest.mark.parametrize("case", ["laplace64", "stencil27_12", "random_3000x8", "powerlaw_20000",
                                   "shortrows_5000", "ragged", "one_long_row"])
 def test_integer_valued_bit_exact(case, dtype):

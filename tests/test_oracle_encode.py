@@ -61,7 +61,7 @@ def test_delta16_sliced_laplacian_closed_form():
     assert L["units"].tolist() == [0] + [2 + 3 * (s - 1) for s in range(1, 64)]
     assert L["slots"] == 64 * (4 + 6 * 62 + 4) == 24320
     assert len(ci) == 20224
-    assert delta16_layout_ref(True, L["slots"], len(ci)) == 1  # 1.2025 slots per nonzero
+    assert delta16_layout_ref(True, L["slots"], len(ci), 4096) == 1  # 1.2025 slots per nonzero
     for s_, j in ((1, 1), (17, 40), (62, 62)):
         for k, want in enumerate([j, 63 + j, 64 + j, 65 + j, 128 + j]):
             slot = 128 * (2 + 3 * (s_ - 1)) + 128 * (k // 2) + 2 * j + k % 2
@@ -72,25 +72,40 @@ def test_delta16_sliced_laplacian_closed_form():
 
 
 def test_delta16_sliced_layout_rule():
-    # rows of 1 and 2 nonzeros: width 2, 128 slots per 96 nonzeros -> streamed
-    n = 128
-    lens = np.array([1 + (i % 2) for i in range(n)])
-    rp = np.concatenate([[0], np.cumsum(lens)])
-    ci = np.concatenate([np.arange(i, i + lens[i]) for i in range(n)])
-    L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
+    def csr(lens):
+        lens = np.asarray(lens)
+        rp = np.concatenate([[0], np.cumsum(lens)])
+        ci = np.concatenate([np.arange(i, i + lens[i]) for i in range(len(lens))])
+        return rp, ci, delta16_sliced_ref(rp, ci, np.ones(len(ci)))
+    # rows of 1 and 2 nonzeros: width 2, 128 slots per 96 nonzeros -> sliced
+    rp, ci, L = csr([1 + (i % 2) for i in range(128)])
     assert L["slots"] == 256 and len(ci) == 192
-    assert delta16_layout_ref(True, L["slots"], len(ci)) == 0
-    assert delta16_layout_ref(False, 0, 0) == -1
+    assert delta16_layout_ref(True, L["slots"], len(ci), 128) == 1
+    # rows of 1 and 3: width 4, 256 slots per 128 nonzeros -> streamed
+    rp, ci, L = csr([1 + 2 * (i % 2) for i in range(64)])
+    assert L["slots"] == 256 and len(ci) == 128
+    assert delta16_layout_ref(True, L["slots"], len(ci), 64) == 0
+    assert delta16_layout_ref(False, 0, 0, 0) == -1
+    # one row of 30 among rows of 20: 1920 slots per 1290 nonzeros (1.49),
+    # sliced because rows average 20 nonzeros; one row of 14 among rows of
+    # 10: 896 per 644 (1.39), streamed because they average 10
+    rp, ci, L = csr([30] + [20] * 63)
+    assert L["slots"] == 1920 and len(ci) == 1290
+    assert delta16_layout_ref(True, L["slots"], len(ci), 64) == 1
+    rp, ci, L = csr([14] + [10] * 63)
+    assert L["slots"] == 896 and len(ci) == 644
+    assert delta16_layout_ref(True, L["slots"], len(ci), 64) == 0
     # equal odd rows of 27: 28 slots per 27 nonzeros -> sliced
     rp = np.arange(0, 27 * 128 + 1, 27)
     ci = np.concatenate([np.arange(27) + i for i in range(128)])
     L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
     assert L["width"].tolist() == [28, 28] and L["slots"] == 64 * 56
-    assert delta16_layout_ref(True, L["slots"], len(ci)) == 1
-    # 70 such rows: the second slice pads 58 empty lanes -> streamed
+    assert delta16_layout_ref(True, L["slots"], len(ci), 128) == 1
+    # 70 such rows: the second slice pads 58 empty lanes -> 1.9 slots per
+    # nonzero, streamed
     L = delta16_sliced_ref(rp[:71], ci[:27 * 70], np.ones(27 * 70))
     assert L["slots"] == 64 * 56
-    assert delta16_layout_ref(True, L["slots"], 27 * 70) == 0
+    assert delta16_layout_ref(True, L["slots"], 27 * 70, 70) == 0
 
 
 def test_delta16_sliced_places_every_nonzero_once():
