@@ -207,10 +207,13 @@ spmv_status_t spmv_set_delta16_layout(spmv_plan_t plan, int32_t layout);
 spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
 
 /* Algorithmic (compulsory) bytes of one SpMV with `variant`: 4(N+1) +
- * ib NNZ + vb NNZ + xb M + yb N, plus 4 bytes per block reference column for
- * DELTA16 (ib = 2 there, else 4).  Traffic a variant adds on top (the
- * XBLOCK_LDS slice row pointers and partial y vectors) is overhead and is
- * not counted. */
+ * ib NNZ + vb NNZ + xb M + yb N, plus for DELTA16 (ib = 2 there, else 4)
+ * 4 bytes per block reference column in the streamed layout, or 12 bytes
+ * per 64-row slice (width, unit offset, reference column) in the sliced one
+ * (the layout is decided here if needed; the streamed form where DELTA16 is
+ * infeasible).  Traffic a variant adds on top (the XBLOCK_LDS slice row
+ * pointers and partial y vectors, the sliced layout's padding slots) is
+ * overhead and is not counted. */
 spmv_status_t spmv_bytes(spmv_plan_t plan, int32_t variant, int64_t *bytes);
 
 /* Median and minimum time of `reps` executions of `variant` (hipEvents on

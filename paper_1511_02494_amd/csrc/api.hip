@@ -994,10 +994,12 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
     const int64_t vb = vbytes(P->dtype), xb = xbytes(P->dtype);
     const int64_t ib = v == V_DELTA16 ? 2 : 4;
     int64_t extra = 0;
-    if (v == V_DELTA16) {
-        SPMV_TRY(d16_decide_layout(P));
-        extra = P->d16_layout == 1 ? 12 * P->d16_nsl  // width, units and base per slice
-                                   : 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
+    if (v == V_DELTA16) {  // also defined where the variant is infeasible
+        SPMV_TRY(check_d16(P));
+        if (d16_feasible(P)) SPMV_TRY(d16_decide_layout(P));
+        extra = d16_feasible(P) && P->d16_layout == 1
+                    ? 12 * P->d16_nsl  // width, units and base per slice
+                    : 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
     }
     *bytes = 4 * (P->n + 1) + (ib + vb) * P->nnz + xb * P->m + xb * P->n + extra;
     return SPMV_OK;

@@ -105,7 +105,7 @@ def test_delta16_sliced_on_stencil_streamed_on_uneven_rows():
     plan = make_plan(rp, ci, v, 4096)
     assert S.spmv_plan_query(plan.handle, 14) == 1
     plan.close()
-    rp, ci, v = synth.banded(6000, 300, 200, seed=4)  # lengths 0.5 d .. 1.5 d
+    rp, ci, v = synth.banded(6000, 128, 30, seed=4)  # 8 per row on average, 0.5 d .. 1.5 d
     plan = make_plan(rp, ci, v, 6000)
     assert S.spmv_plan_query(plan.handle, 14) == 0
     with pytest.raises(S.SpmvError) as e:
