@@ -58,6 +58,8 @@ def kernel_names(v, plan):
     if v == S.V_XBLOCK_LDS:
         rows = plan.query(12)  # rows per block of the per-slice row-streaming kernel, 0 = merge path
         long_rows = ["void spmvsel::k_long_rows<double>"] if plan.query(13) > 0 else []
+        if plan.query(16) > 0:  # phased slices: no partial y, no slice sum
+            return [f"void spmvsel::k_phased_slices<double, {plan.query(16)}>", *long_rows]
         if rows > 0:
             return [f"void spmvsel::k_rowstream_slices<double, {rows // 256}>", *long_rows,
                     "void spmvsel::k_slice_sum<double>"]

@@ -77,8 +77,12 @@ typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
  *              over 128 nonzeros are summed from the CSR in chunks instead
  *              (merge-path tiles per slice when such rows hold over a
  *              quarter of the nonzeros); S partial y vectors are summed in
- *              slice order.  (The name is kept from an earlier design that
- *              staged x windows in LDS.)
+ *              slice order.  When no row leaves the slices, a workgroup
+ *              instead owns a few row blocks and walks the slices in order
+ *              (all workgroups resident, so all gather from about one slice
+ *              at a time), each row's sum kept by its thread: no partial y,
+ *              and FP64 rows summed in column order.  (The name is kept from
+ *              an earlier design that staged x windows in LDS.)
  *  SHORT_ROW   rows streamed through LDS in chunks of 2048 nonzeros with one
  *              thread summing each row (short rows: inner-loop overhead). */
 typedef enum {
@@ -235,7 +239,8 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
  * more than a quarter of the nonzeros, in which case nothing is split and
  * the slices use merge-path tiles), 14 delta16 layout (-1 infeasible,
  * 0 rows streamed, 1 sliced), 15 delta16 sliced slots (64 x the sum of the
- * slice widths, padding included). */
+ * slice widths, padding included), 16 x-block row blocks per workgroup of
+ * the phased slice kernel (0 when the slices use merge-path tiles). */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:

@@ -452,13 +452,14 @@ spmv_status_t build_xslices(spmv_plan *P) {
     P->xs_slices = ns;
     P->xs_width = cw;
     P->xs_nlong = P->xs_nchunks = P->xs_long_nnz = 0;
+    P->xs_pj = 0;
+    P->xs_pg = 0;
     for (int k = 0; k < kSlices; ++k) P->xs_nnz_off[k] = P->xs_tiles[k] = P->xs_tile_off[k] = 0;
     SPMV_TRY(P->xs_rowptr.alloc((size_t)ns * (n + 1) * 4));
     // slice starts are padded to 8 elements so every slice keeps the
     // 16-byte alignment the vector loads rely on
     SPMV_TRY(P->xs_colind.alloc((size_t)(nnz + 8 * ns) * 4 + 16));
     SPMV_TRY(P->xs_val.alloc((size_t)(nnz + 8 * ns) * vbytes(P->dtype) + 16));
-    SPMV_TRY(P->xs_y.alloc((size_t)ns * (n > 0 ? n : 1) * xbytes(P->dtype)));
     int64_t snnz[kSlices] = {0};
     // merge-path tiles of the original CSR, walked by the count and scatter kernels
     const int64_t mtiles = (n + nnz + kMergeTile - 1) / kMergeTile;
@@ -494,10 +495,14 @@ spmv_status_t build_xslices(spmv_plan *P) {
             const double avg = (double)(nnz - P->xs_long_nnz) / ((double)n * ns);
             P->xs_rows = kBlock * pow2_floor((double)kChunk / (kBlock * (avg > 1e-9 ? avg : 1e-9)),
                                              1, kRowStreamMaxR);
+            if (P->xs_nlong == 0) SPMV_HIP(phased_geometry(*P, &P->xs_pj, &P->xs_pg));
         } else {
             P->xs_rows = 0;
         }
     }
+    // partial y vectors only for the slice kernels that write them
+    if (P->xs_pj == 0) SPMV_TRY(P->xs_y.alloc((size_t)ns * (n > 0 ? n : 1) * xbytes(P->dtype)));
+    else P->xs_y.release();
     SliceOffsets so;
     int64_t off = 0, toff = 0;
     int64_t total = 0;
@@ -1035,6 +1040,7 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
     case 7: *value = xs_slice_count(P); break;
     case 12: SPMV_TRY(build_xslices(P)); *value = P->xs_rows; break;
     case 13: SPMV_TRY(build_xslices(P)); *value = P->xs_nlong; break;
+    case 16: SPMV_TRY(build_xslices(P)); *value = P->xs_pj; break;
     case 8: *value = P->parts; break;
     case 9: SPMV_TRY(check_d16(P)); *value = d16_feasible(P); break;
     case 11: SPMV_TRY(check_d16(P)); *value = P->d16_rows; break;

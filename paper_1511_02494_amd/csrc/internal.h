@@ -128,6 +128,10 @@ struct spmv_plan {
     // the slices and summed from the original CSR in chunks of kLongChunk
     int64_t xs_nlong = 0, xs_nchunks = 0, xs_long_nnz = 0;
     spmvsel::DevBuf xs_lrows, xs_lfirst, xs_lck0, xs_lck1, xs_lsum;
+    // phased row streaming (no partial y): row blocks per workgroup and
+    // workgroups; 0 when the slices use the partial-y kernels
+    int xs_pj = 0;
+    int64_t xs_pg = 0;
     bool part_built = false;
     spmvsel::DevBuf part_bounds;
 
@@ -163,6 +167,7 @@ hipError_t launch_csr_scalar(const spmv_plan &P, const void *x, void *y, hipStre
 hipError_t launch_csr_vector(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y, hipStream_t s);
 hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStream_t s);
+hipError_t phased_geometry(const spmv_plan &P, int *blocks_per_group, int64_t *groups);
 hipError_t launch_merge_path(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 

@@ -399,7 +399,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(int64_t n, int64_t tiles
 // of x only, which stays in its 4 MB L2 instead of being fetched line by
 // line from the Infinity Cache; the 8/S XCDs of a slice take its row blocks
 // (or tiles) in turn.  Each slice writes a partial y; k_slice_sum adds the
-// partials in slice order.
+// partials in slice order.  Where no row leaves the slices, k_phased_slices
+// (below) walks the slices in time instead and needs no partial y.
 // Work unit (row block or tile) and slice of workgroup b.
 __device__ inline int64_t slice_unit(int ns, int *slice) {
     const int x = blockIdx.x % 8;
@@ -441,16 +442,18 @@ __global__ __launch_bounds__(kBlock) void k_merge_slices(int64_t n, const int32_
 // row adds its chunk sums (per lane in order, Kahan for FP32, then a fixed
 // butterfly) and stores the row in the first partial y, where the slice
 // kernel left a zero.
+// `sh` is kBlock elements of the calling kernel's LDS (its own arrays, so
+// the chunk blocks add nothing to the kernel's LDS size and occupancy).
 template <class V>
 __device__ __forceinline__ void long_chunk_block(int64_t c, const int32_t *__restrict__ ck0,
                                                  const int32_t *__restrict__ ck1,
                                                  const int32_t *__restrict__ ci,
                                                  const V *__restrict__ val,
                                                  const typename VT<V>::A *__restrict__ x,
-                                                 typename VT<V>::A *__restrict__ lsum) {
+                                                 typename VT<V>::A *__restrict__ lsum,
+                                                 typename VT<V>::A *sh) {
     using A = typename VT<V>::A;
     constexpr int PPT = kLongChunk / kBlock;
-    __shared__ A sh[kBlock];
     const int32_t k0 = ck0[c], k1 = ck1[c];
     int32_t cc[PPT];
     V v[PPT];
@@ -508,8 +511,9 @@ __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t 
                                                              int64_t sgrid, LongChunks LC) {
     using A = typename VT<V>::A;
     if ((int64_t)blockIdx.x >= sgrid) {
+        __shared__ A sh[kBlock];
         long_chunk_block<V>((int64_t)blockIdx.x - sgrid, LC.ck0, LC.ck1, LC.ci,
-                            static_cast<const V *>(LC.val), x, static_cast<A *>(LC.lsum));
+                            static_cast<const V *>(LC.val), x, static_cast<A *>(LC.lsum), sh);
         return;
     }
     int s;
@@ -517,6 +521,97 @@ __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t 
     if (b >= nblocks) return;
     rowstream_block<V, false, R, true>(b, n, T.rp[s], ci + T.off[s], nullptr, nullptr, val + T.off[s], x,
                                  T.y[s]);
+}
+
+// Phased row streaming on the slices, without partial y vectors.  Workgroup
+// w owns the 256-row blocks w, w + G, ..., w + (J - 1) G and walks the slices
+// in order, each owned row's sum kept in a register of the thread that owns
+// the row.  The slices are column ranges in increasing order, so every row
+// (long rows aside) is summed in column order: Algorithm 1's order, bit for
+// bit in FP64.  The grid holds at most as many of these workgroups as the
+// CUs run at once, so they walk the slices together and the part of x being
+// gathered at any time is about one slice, which the L2s hold.  Used when no
+// row leaves the slices: the long rows' chunk sums, run as extra workgroups
+// of this grid, as a kernel of their own or after the slices, all cost more
+// than the per-slice kernel with partial y vectors below saves.
+template <class V, int J>
+__global__ __launch_bounds__(kBlock) void k_phased_slices(
+    int64_t n, int64_t nblk, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
+    SliceTable<typename VT<V>::A> T, typename VT<V>::A *__restrict__ y) {
+    using A = typename VT<V>::A;
+    using VP = typename Pair<V>::type;
+    using IP = typename Pair<int32_t>::type;
+    constexpr int NP = kRunLen / 2;  // pairs per thread per chunk
+    __shared__ int32_t s_rp[kBlock + 1];
+    __shared__ A s_prod[kChunk];
+    const int64_t G = gridDim.x, w = blockIdx.x;
+    const int t = threadIdx.x;
+    Sum<A> acc[J];
+    bool comp[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int64_t r = (w + j * G) * kBlock + t;
+        comp[j] = is_f32<A>() && r < n && (rp[r + 1] - rp[r]) >= kKahanMinLen;
+    }
+    for (int sl = 0; sl < T.ns; ++sl) {
+        const int32_t *__restrict__ srp = T.rp[sl];
+        const int32_t *__restrict__ sci = ci + T.off[sl];
+        const V *__restrict__ sv = val + T.off[sl];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int64_t blk = w + j * G;
+            if (blk >= nblk) break;  // the same for the whole workgroup
+            const int64_t r0 = blk * kBlock;
+            const int nrows = (int)((n - r0) < kBlock ? (n - r0) : kBlock);
+            __syncthreads();  // the previous pass is done with s_rp and s_prod
+            for (int r = t; r <= nrows; r += kBlock) s_rp[r] = srp[r0 + r];
+            __syncthreads();
+            const int32_t a = s_rp[0], e = s_rp[nrows];
+            int32_t k = t < nrows ? s_rp[t] : e;
+            const int32_t kend = t < nrows ? s_rp[t + 1] : e;
+            for (int32_t cs = a & ~1; cs < e; cs += kChunk) {
+                A p[kRunLen];
+                // each pair's gathers follow its own loads: with more
+                // gathers in flight per thread (all loads first) the kernel
+                // ran slower, its L1 miss slots being the limit
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    const int32_t kk = cs + 2 * t + 2 * kBlock * q;
+                    V v0 = V(0), v1 = V(0);
+                    int32_t c0 = 0, c1 = 0;
+                    if (kk + 1 < e) {
+                        const VP vv = __builtin_nontemporal_load(reinterpret_cast<const VP *>(sv + kk));
+                        const IP cc = __builtin_nontemporal_load(reinterpret_cast<const IP *>(sci + kk));
+                        v0 = vv.x;
+                        v1 = vv.y;
+                        c0 = cc.x;
+                        c1 = cc.y;
+                    } else if (kk < e) {
+                        v0 = sv[kk];
+                        c0 = sci[kk];
+                    }
+                    const bool ok0 = kk >= a && kk < e, ok1 = kk + 1 >= a && kk + 1 < e;
+                    p[2 * q] = ok0 ? VT<V>::cvt(v0) * x[c0] : A(0);
+                    p[2 * q + 1] = ok1 ? VT<V>::cvt(v1) * x[c1] : A(0);
+                }
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    s_prod[2 * t + 2 * kBlock * q] = p[2 * q];
+                    s_prod[2 * t + 2 * kBlock * q + 1] = p[2 * q + 1];
+                }
+                __syncthreads();
+                const int32_t ce = (cs + kChunk) < e ? (cs + kChunk) : e;
+                for (; k < kend && k < ce; ++k) acc[j].add(s_prod[k - cs], comp[j]);
+                __syncthreads();
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int64_t r = (w + j * G) * kBlock + t;
+        if (w + j * G < nblk && r < n) y[r] = acc[j].s;
+    }
 }
 
 template <class A>
@@ -622,6 +717,35 @@ hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y
     });
 }
 
+// Geometry of the phased x-block kernel: the fewest row blocks per workgroup
+// J (1, 2, 4 or 8) for which the G = ceil(blocks / J) workgroups fit on the
+// CUs at once (by the occupancy the runtime reports for that instance), else
+// J = 8 with more workgroups than fit.
+hipError_t phased_geometry(const spmv_plan &P, int *J, int64_t *G) {
+    const int64_t nblk = (P.n + kBlock - 1) / kBlock;
+    return by_dtype(P.dtype, [&](auto tag) -> hipError_t {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
+        const void *fns[4] = {reinterpret_cast<const void *>(&k_phased_slices<V, 1>),
+                              reinterpret_cast<const void *>(&k_phased_slices<V, 2>),
+                              reinterpret_cast<const void *>(&k_phased_slices<V, 4>),
+                              reinterpret_cast<const void *>(&k_phased_slices<V, 8>)};
+        for (int i = 0; i < 4; ++i) {
+            const int j = 1 << i;
+            int per_cu = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fns[i], kBlock, 0);
+            if (e != hipSuccess) return e;
+            const int64_t need = (nblk + j - 1) / j, cap = (int64_t)P.num_cus * per_cu;
+            if (need <= cap || j == 8) {  // all slots that fit, for the smallest J
+                *J = j;
+                *G = need <= cap ? (cap < nblk ? cap : nblk) : need;
+                if (*G < 1) *G = 1;
+                return hipSuccess;
+            }
+        }
+        return hipErrorInvalidValue;
+    });
+}
+
 hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
     if (P.n == 0) return hipSuccess;
     return by_dtype(P.dtype, [&](auto tag) {
@@ -671,12 +795,32 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             T.snnz[k] = P.xs_snnz.as<int32_t>() + P.xs_tile_off[k] + k;
             T.crow[k] = P.xs_crow.as<int32_t>() + P.xs_tile_off[k];
             T.cval[k] = P.xs_cval.as<A>() + P.xs_tile_off[k];
-            T.y[k] = P.xs_y.as<A>() + (size_t)k * P.n;
+            T.y[k] = P.xs_y.p ? P.xs_y.as<A>() + (size_t)k * P.n : nullptr;  // none when phased
             T.off[k] = P.xs_nnz_off[k];
             T.tiles[k] = P.xs_tiles[k];
             if (T.tiles[k] > maxt) maxt = T.tiles[k];
         }
         if (P.xs_nlong > 0 && P.xs_rows == 0) return hipErrorInvalidValue;  // split implies streaming
+        const LongChunks LC{P.xs_lck0.as<int32_t>(), P.xs_lck1.as<int32_t>(), P.colind, P.val,
+                            P.xs_lsum.p};
+        if (P.xs_rows > 0 && P.xs_pj > 0) {  // phased row streaming: no partial y
+            const int64_t nblk = (P.n + kBlock - 1) / kBlock;
+            const unsigned g = (unsigned)P.xs_pg;
+            const int32_t *xci = P.xs_colind.as<int32_t>();
+            const V *xv = (const V *)P.xs_val.p;
+#define SPMV_PH(JJ)                                                                                    \
+    case JJ:                                                                                           \
+        hipLaunchKernelGGL((k_phased_slices<V, JJ>), dim3(g), dim3(kBlock), 0, s, P.n, nblk,          \
+                           P.rowptr, xci, xv, (const A *)x, T, (A *)y);                             \
+        break;
+            if (P.xs_nlong > 0) return hipErrorInvalidValue;  // phased only without long rows
+            switch (P.xs_pj) {
+                SPMV_PH(1) SPMV_PH(2) SPMV_PH(4) SPMV_PH(8)
+            default: return hipErrorInvalidValue;
+            }
+#undef SPMV_PH
+            return hipGetLastError();
+        }
         if (P.xs_rows > 0) {  // short slice rows: row-block streaming per slice
             const int R = P.xs_rows / kBlock;
             const int64_t nb = (P.n + P.xs_rows - 1) / P.xs_rows;
@@ -684,8 +828,6 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             const unsigned g = (unsigned)(sg + P.xs_nchunks);
             const int32_t *xci = P.xs_colind.as<int32_t>();
             const V *xv = (const V *)P.xs_val.p;
-            const LongChunks LC{P.xs_lck0.as<int32_t>(), P.xs_lck1.as<int32_t>(), P.colind, P.val,
-                                P.xs_lsum.p};
             switch (R) {
             case 1: hipLaunchKernelGGL((k_rowstream_slices<V, 1>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;
             case 2: hipLaunchKernelGGL((k_rowstream_slices<V, 2>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;

@@ -14,13 +14,14 @@ import pytest
 import synth
 import paper_1511_02494_amd as S
 from oracle.encode import to_bf16_bits_ref, to_f32_ref
-from oracle.spmv import spmv_exact
+from oracle.spmv import spmv_exact, spmv_seq_rows
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 from gpu_util import DEV, dev  # noqa: E402
 
 TOL = {S.SPMV_F64: 1e-12, S.SPMV_F32: 1e-5, S.SPMV_BF16: 1e-2}
+SEQ_ORDER = {S.V_CSR_SCALAR, S.V_SHORT_ROW, S.V_DELTA16}  # sum in column order
 SPECS = synth.class_matrices(scale=1)
 
 
@@ -48,6 +49,7 @@ def test_fullsize_variants(spec):
     rng = np.random.default_rng(0)
     rows = sample_rows(rp, rng)
     y_ref, scale = spmv_exact(rp, ci, v, x, rows)
+    y_seq = spmv_seq_rows(rp, ci, v, x, rows)
     r_t, c_t = dev(rp), dev(ci)
     print(f"\n{spec.name}: n={n} nnz={len(ci)} sampled rows={len(rows)}", flush=True)
     for dtype in (S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16):
@@ -56,9 +58,12 @@ def test_fullsize_variants(spec):
         tdt = torch.float64 if dtype == S.SPMV_F64 else torch.float32
         plan = S.Plan(r_t, c_t, v_t, n, dtype, nnz=len(ci))
         mask = plan.mask()
-        for var in range(6):
-            if not (mask >> var) & 1:
-                continue
+        runs = [(var, None) for var in range(6) if (mask >> var) & 1]
+        if (mask >> S.V_DELTA16) & 1:  # the layout the rule did not pick, forced
+            runs.append((S.V_DELTA16, 1 - plan.query(14)))
+        for var, layout in runs:
+            if layout is not None:
+                S.spmv_set_delta16_layout(plan.handle, layout)
             plan.set_variant(var)
             y = torch.full((n,), float("nan"), dtype=tdt, device=DEV)
             plan.execute(x_t, y)
@@ -70,10 +75,13 @@ def test_fullsize_variants(spec):
             ys = y.cpu().numpy()[rows].astype(np.float64)
             err = np.abs(ys - y_ref)
             rel = float(np.max(np.where(scale > 0, err / np.where(scale > 0, scale, 1), 0)))
-            print(f"  dtype={['f64', 'f32', 'bf16'][dtype]:>4s} {S.VARIANTS[var]:>10s} "
+            name = S.VARIANTS[var] + ("" if layout is None else f"/layout{layout}")
+            print(f"  dtype={['f64', 'f32', 'bf16'][dtype]:>4s} {name:>18s} "
                   f"max |y - y_ref| / sum|a||x| = {rel:.3e}", flush=True)
-            assert np.all(err <= TOL[dtype] * scale), (S.VARIANTS[var], dtype, rel)
+            assert np.all(err <= TOL[dtype] * scale), (name, dtype, rel)
             assert np.all(ys[scale == 0] == 0)
+            if dtype == S.SPMV_F64 and var in SEQ_ORDER:
+                assert np.array_equal(ys, y_seq), name
             del y, y2
         plan.close()
         del v_t, x_t

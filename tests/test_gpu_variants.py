@@ -212,6 +212,27 @@ def test_xblock_every_slice_count(case, slices):
         plan.close()
 
 
+@pytest.mark.parametrize("case", ["laplace64", "stencil27_12", "random_3000x8", "shortrows_5000",
+                                  "banded_4000", "empty_rows", "powerlaw_20000", "ragged"])
+def test_xblock_phased_walk_is_sequential(case):
+    """Without long rows the slices are walked in order by one thread per
+    row (no partial y): FP64 results are Algorithm 1's sums bit for bit."""
+    build, m = CASES[case]
+    rp, ci, v = build("random")
+    x = synth.vector(m, 18)
+    y_seq = spmv_seq(rp, ci, v, x)
+    for slices in (1, 2, 4, 8):
+        plan = make_plan(rp, ci, v, m)
+        S.spmv_set_xblock_slices(plan.handle, slices)
+        y = run(plan, S.V_XBLOCK_LDS, x)
+        phased, nlong, rows = (S.spmv_plan_query(plan.handle, k) for k in (16, 13, 12))
+        print(f"case={case} slices={slices} phased J={phased} long rows={nlong} rows/block={rows}", flush=True)
+        assert (phased > 0) == (nlong == 0 and rows > 0)
+        if phased:
+            assert np.array_equal(y, y_seq), slices
+        plan.close()
+
+
 def test_xblock_slice_count_change_rebuilds():
     rp, ci, v = CASES["powerlaw_20000"][0]("int")
     x = synth.int_vector(20000, 14)
