@@ -57,12 +57,12 @@ def kernel_names(v, plan):
         return ["void spmvsel::k_merge_path<double>", "void spmvsel::k_merge_fixup<double>"]
     if v == S.V_XBLOCK_LDS:
         rows = plan.query(12)  # rows per block of the per-slice row-streaming kernel, 0 = merge path
-        long_rows = ["void spmvsel::k_long_rows<double>"] if plan.query(13) > 0 else []
         if plan.query(16) > 0:  # phased slices: no partial y, no slice sum
-            return [f"void spmvsel::k_phased_slices<double, {plan.query(16)}>", *long_rows]
-        if rows > 0:
-            return [f"void spmvsel::k_rowstream_slices<double, {rows // 256}>", *long_rows,
-                    "void spmvsel::k_slice_sum<double>"]
+            return [f"void spmvsel::k_phased_slices<double, {plan.query(16)}>"]
+        if rows > 0:  # per-slice partials; with long rows their sums join the slice sum
+            finish = "k_slice_finish" if plan.query(13) > 0 else "k_slice_sum"
+            return [f"void spmvsel::k_rowstream_slices<double, {rows // 256}>",
+                    f"void spmvsel::{finish}<double>"]
         return ["void spmvsel::k_merge_slices<double>", "void spmvsel::k_merge_fixup_slices<double>",
                 "void spmvsel::k_slice_sum<double>"]
     if v == S.V_DELTA16:
@@ -191,6 +191,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=100, help="SpMVs per matrix per step")
+    ap.add_argument("--event-every", type=int, default=10,
+                    help="bracket every k-th SpMV of the timed steps with HIP events (the "
+                         "launch-duration sample of the roofline); each pair adds a few "
+                         "microseconds of stream gaps, so not every launch carries one")
     ap.add_argument("--selector", default="mlp", choices=["mlp", "profiling", "exhaustive"])
     ap.add_argument("--scale", type=int, default=1, help="divide matrix sizes (testing only)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -289,8 +293,8 @@ def main():
             info = plan.select(sel)
             t1 = time.perf_counter()
             evs = []
-            for _ in range(args.iters):
-                if record:
+            for it in range(args.iters):
+                if record and it % args.event_every == 0:
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
                     e0.record(stream)
@@ -423,6 +427,7 @@ def main():
                                f"per matrix per step: validate, select ({args.selector}), "
                                f"prepare, {args.iters} SpMVs",
                    "scale": args.scale, "iters_per_matrix": args.iters,
+                   "launch_events_every": args.event_every,
                    "selector": args.selector, "model_loaded": model_loaded},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -432,6 +432,8 @@ spmv_status_t split_long_rows(spmv_plan *P, int ns, int32_t *lens) {
     SPMV_TRY(P->xs_lck0.alloc((size_t)nc * 4));
     SPMV_TRY(P->xs_lck1.alloc((size_t)nc * 4));
     SPMV_TRY(P->xs_lsum.alloc((size_t)nc * 8));
+    SPMV_TRY(P->xs_lmask.alloc((size_t)((n + 31) / 32) * 4));
+    SPMV_HIP(launch_long_mask(n, flags.as<int32_t>(), P->xs_lmask.as<uint32_t>(), S(P)));
     SPMV_HIP(hipMemcpyAsync(P->xs_lrows.p, rows.p, (size_t)L * 4, hipMemcpyDeviceToDevice, S(P)));
     SPMV_HIP(hipMemcpyAsync(P->xs_lfirst.p, first.data(), (size_t)(L + 1) * 4, hipMemcpyHostToDevice, S(P)));
     SPMV_HIP(hipMemcpyAsync(P->xs_lck0.p, ck0.data(), (size_t)nc * 4, hipMemcpyHostToDevice, S(P)));

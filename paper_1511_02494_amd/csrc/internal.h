@@ -128,6 +128,7 @@ struct spmv_plan {
     // the slices and summed from the original CSR in chunks of kLongChunk
     int64_t xs_nlong = 0, xs_nchunks = 0, xs_long_nnz = 0;
     spmvsel::DevBuf xs_lrows, xs_lfirst, xs_lck0, xs_lck1, xs_lsum;
+    spmvsel::DevBuf xs_lmask;    // one bit per row: set for the long rows
     // phased row streaming (no partial y): row blocks per workgroup and
     // workgroups; 0 when the slices use the partial-y kernels
     int xs_pj = 0;
@@ -195,6 +196,8 @@ hipError_t launch_long_compact(int64_t n, const int32_t *flags, const int32_t *p
                                hipStream_t s);
 hipError_t launch_long_zero(int64_t L, int ns, int64_t n, const int32_t *rows, int32_t *lens,
                             hipStream_t s);
+// mask[w] bit b = flags[32 w + b] != 0
+hipError_t launch_long_mask(int64_t n, const int32_t *flags, uint32_t *mask, hipStream_t s);
 hipError_t launch_slice_count(const spmv_plan &P, int64_t cw, const int32_t *srow,
                               const int32_t *snnz, int64_t tiles, int32_t *lens, hipStream_t s);
 // d_part: 2048 int32 of device scratch for per-block maxima

@@ -136,6 +136,27 @@ hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const
     return hipGetLastError();
 }
 
+// one bit per row from the long-row flags (a thread per 32-row word)
+__global__ __launch_bounds__(kBlock) void k_long_mask(int64_t n, const int32_t *__restrict__ flags,
+                                                      uint32_t *__restrict__ mask) {
+    const int64_t w = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (w * 32 >= n) return;
+    uint32_t m = 0;
+    for (int b = 0; b < 32; ++b) {
+        const int64_t i = w * 32 + b;
+        if (i < n && flags[i] != 0) m |= 1u << b;
+    }
+    mask[w] = m;
+}
+
+hipError_t launch_long_mask(int64_t n, const int32_t *flags, uint32_t *mask, hipStream_t s) {
+    const int64_t words = (n + 31) / 32;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_long_mask, dim3((unsigned)((words + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, n, flags, mask);
+    return hipGetLastError();
+}
+
 // largest window span (cmax - cmin) over panels, for the 16-bit feasibility test
 __global__ __launch_bounds__(kBlock) void k_max_span(const int32_t *__restrict__ cmin,
                                                      const int32_t *__restrict__ cmax,

@@ -437,11 +437,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_slices(int64_t n, const int32_
 // Long rows of the split, summed from the original CSR: one block per chunk
 // of at most kLongChunk nonzeros of one row (all loads first, then the
 // gathers; per-thread sums folded by a fixed tree; these blocks ride at the
-// end of the slice kernel's grid, filling CUs as slice blocks finish), then
-// one wavefront per
-// row adds its chunk sums (per lane in order, Kahan for FP32, then a fixed
-// butterfly) and stores the row in the first partial y, where the slice
-// kernel left a zero.
+// end of the slice kernel's grid, filling CUs as slice blocks finish); then
+// k_slice_finish gives each long row a wavefront that adds its chunk sums.
 // `sh` is kBlock elements of the calling kernel's LDS (its own arrays, so
 // the chunk blocks add nothing to the kernel's LDS size and occupancy).
 template <class V>
@@ -476,22 +473,6 @@ __device__ __forceinline__ void long_chunk_block(int64_t c, const int32_t *__res
         __syncthreads();
     }
     if (threadIdx.x == 0) lsum[c] = sh[0];
-}
-
-template <class A>
-__global__ __launch_bounds__(kBlock) void k_long_rows(int64_t L, const int32_t *__restrict__ rows,
-                                                      const int32_t *__restrict__ first,
-                                                      const A *__restrict__ lsum,
-                                                      A *__restrict__ y0) {
-    // one wavefront per row: lane l adds chunks l, l+64, ... in order, then a
-    // fixed butterfly over the lanes
-    const int64_t t = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (t >= L) return;  // whole wavefronts leave together
-    Sum<A> acc;
-    for (int32_t c = first[t] + lane; c < first[t + 1]; c += 64) acc.add(lsum[c], is_f32<A>());
-    const A v = group_sum<64>(acc.s);
-    if (lane == 0) y0[rows[t]] = v;
 }
 
 // Short slice rows: row-block streaming on each slice; workgroups from
@@ -621,6 +602,36 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup_slices(int64_t n, int64_
     const int s = (int)(g / (maxt > 0 ? maxt : 1));
     if (s >= T.ns) return;
     merge_fixup_one<A>(g % maxt, n, T.tiles[s], T.crow[s], T.cval[s], T.y[s]);
+}
+
+// Slice sums and long rows in one launch: blocks below gsum add the partial
+// y vectors in slice order for every row whose bit in `longmask` is clear;
+// the blocks after them give each long row a wavefront that adds its chunk
+// sums (per lane in order, Kahan for FP32, then a fixed butterfly) and
+// stores the row.  The two sets of rows are disjoint.
+template <class A>
+__global__ __launch_bounds__(kBlock) void k_slice_finish(int64_t n, SliceTable<A> T,
+                                                         A *__restrict__ y, int64_t gsum,
+                                                         const uint32_t *__restrict__ longmask,
+                                                         int64_t L, const int32_t *__restrict__ rows,
+                                                         const int32_t *__restrict__ first,
+                                                         const A *__restrict__ lsum) {
+    if ((int64_t)blockIdx.x < gsum) {
+        for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += gsum * kBlock) {
+            if ((longmask[i >> 5] >> (i & 31)) & 1u) continue;
+            A s = T.y[0][i];
+            for (int k = 1; k < T.ns; ++k) s = s + T.y[k][i];
+            y[i] = s;
+        }
+        return;
+    }
+    const int64_t t = (((int64_t)blockIdx.x - gsum) * kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (t >= L) return;  // whole wavefronts leave together
+    Sum<A> acc;
+    for (int32_t c = first[t] + lane; c < first[t + 1]; c += 64) acc.add(lsum[c], is_f32<A>());
+    const A v = group_sum<64>(acc.s);
+    if (lane == 0) y[rows[t]] = v;
 }
 
 template <class A>
@@ -848,11 +859,13 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         if (P.xs_nlong > 0) {  // rows taken out of the slices (chunks summed above)
-            hipLaunchKernelGGL(k_long_rows<A>, dim3(grid_for(P.xs_nlong * 64, kBlock, INT32_MAX)),
-                               dim3(kBlock), 0, s, P.xs_nlong, P.xs_lrows.as<int32_t>(),
-                               P.xs_lfirst.as<int32_t>(), P.xs_lsum.as<A>(), T.y[0]);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
+            const int64_t gsum = grid_for(P.n, kBlock, (int64_t)P.num_cus * 16);
+            const int64_t glong = (P.xs_nlong * 64 + kBlock - 1) / kBlock;
+            hipLaunchKernelGGL(k_slice_finish<A>, dim3((unsigned)(gsum + glong)), dim3(kBlock), 0, s,
+                               P.n, T, (A *)y, gsum, P.xs_lmask.as<uint32_t>(), P.xs_nlong,
+                               P.xs_lrows.as<int32_t>(), P.xs_lfirst.as<int32_t>(),
+                               P.xs_lsum.as<A>());
+            return hipGetLastError();
         }
         const unsigned g = grid_for(P.n, kBlock, (int64_t)P.num_cus * 16);
         hipLaunchKernelGGL(k_slice_sum<A>, dim3(g), dim3(kBlock), 0, s, P.n, T, (A *)y);
