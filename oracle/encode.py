@@ -9,9 +9,11 @@
 * ``delta16_sliced_ref``  the second layout of the same 16-bit offsets, for
   matrices whose rows in a group of 64 have nearly equal lengths (stencils):
   64-row slices stored column-major in pairs, one row per lane of a
-  wavefront, each slice with its own reference column.  A combination of the
-  MB optimisation with a GPU storage order, in the spirit of the paper's
-  closing remarks on wider pools and multi-level optimisation.
+  wavefront, each slice with its own reference column; a slice whose rows
+  share at most 32 diagonals stores those diagonals once and a bit mask per
+  row instead of any column data.  A combination of the MB optimisation with
+  a GPU storage order, in the spirit of the paper's closing remarks on wider
+  pools and multi-level optimisation.
 * ``merge_splits_ref``  start coordinates of the nonzero-balanced merge-path
   tiles (Merrill and Garland, SC'16): the merge of the row-end list
   ``rowptr[1..N]`` with the nonzero indices ``0..NNZ-1``, where nonzero j is
@@ -65,49 +67,85 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
     """The sliced delta16 layout of a CSR matrix.
 
     Slice s holds rows [64 s, 64 s + 64) (lanes past the last row are empty
-    rows).  Its width w_s is its longest row rounded up to an even count, its
-    reference column base_s the smallest column among its nonzeros (0 if
-    none), and its storage starts at unit u_s = sum_{t<s} w_t / 2, where one
-    unit is 128 slots (a pair of nonzeros for each of the 64 lanes).  The
-    k-th nonzero (k from 0, in column order) of the row in lane l lives at
+    rows).  Each slice is of one of two kinds:
+
+    * diagonal (kind 1): U_s, the sorted distinct values of c - r over the
+      slice's nonzeros, has at most 32 entries and, rounded up to an even
+      count, is no wider than the slice's longest row rounded up to even.
+      Position k of a row holds its nonzero on diagonal U_s[k], if any; the
+      row's mask has bit k set for each diagonal it has.  Columns are not
+      stored: the column at position k of row r is r + U_s[k].
+    * offset (kind 0): position k of a row holds its k-th nonzero (from 0,
+      in column order) and off[slot] = c - base_s, base_s being the smallest
+      column among the slice's nonzeros (0 if none).
+
+    The slice's width w_s is |U_s| or its longest row, rounded up to even,
+    and its storage starts at unit u_s = sum_{t<s} w_t / 2, where one unit is
+    128 slots (a pair of positions for each of the 64 lanes).  Position k of
+    the row in lane l lives at
 
         slot = 128 u_s + 128 (k // 2) + 2 l + (k % 2)
 
-    with off[slot] = c - base_s and vals[slot] = a; every other slot holds 0.
-    Returns a dict with width (int32[S]), base (int32[S]), units (int32[S],
-    the exclusive prefix sums u_s), slots (64 sum w_s), off (int64[slots];
-    the caller checks they fit 16 bits) and vals (float64[slots]).
+    with vals[slot] = a; every other slot (and off[] of diagonal slices)
+    holds 0.  Returns a dict with kind, width, base, units (int32[S]), diag
+    (int32[32 S]: U_s zero-padded, zeros for offset slices), mask (uint32[N]:
+    0 in offset slices), slots (64 sum w_s), off (int64[slots]; the caller
+    checks they fit 16 bits), vals (float64[slots]) and nnz_offset (the
+    nonzeros of the offset slices).
     """
     rowptr = np.asarray(rowptr, dtype=np.int64)
     colind = np.asarray(colind, dtype=np.int64)
     val = np.asarray(val, dtype=np.float64)
     n = len(rowptr) - 1
     ns = (n + slice_rows - 1) // slice_rows
+    kind = np.zeros(ns, dtype=np.int64)
     width = np.zeros(ns, dtype=np.int64)
     base = np.zeros(ns, dtype=np.int64)
+    diag = np.zeros(32 * ns, dtype=np.int64)
+    diag_sets = []
     for s in range(ns):
         r0, r1 = s * slice_rows, min(n, (s + 1) * slice_rows)
         lens = rowptr[r0 + 1:r1 + 1] - rowptr[r0:r1]
         longest = int(lens.max()) if len(lens) else 0
-        width[s] = longest + (longest % 2)
+        w_off = longest + (longest % 2)
         a, e = rowptr[r0], rowptr[r1]
         base[s] = colind[a:e].min() if a < e else 0
+        rel = sorted({int(colind[j]) - i for i in range(r0, r1)
+                      for j in range(rowptr[i], rowptr[i + 1])})
+        d_even = len(rel) + (len(rel) % 2)
+        if len(rel) <= 32 and d_even <= w_off:
+            kind[s], width[s] = 1, d_even
+            diag[32 * s:32 * s + len(rel)] = rel
+        else:
+            width[s] = w_off
+        diag_sets.append(rel)
     units = np.zeros(ns, dtype=np.int64)
     for s in range(1, ns):
         units[s] = units[s - 1] + width[s - 1] // 2
     slots = int(slice_rows * width.sum())
     off = np.zeros(slots, dtype=np.int64)
     vals = np.zeros(slots, dtype=np.float64)
+    mask = np.zeros(n, dtype=np.int64)
+    nnz_offset = 0
     pair_stride = 2 * slice_rows
     for i in range(n):
         s, lane = divmod(i, slice_rows)
-        for k in range(rowptr[i + 1] - rowptr[i]):
-            j = rowptr[i] + k
+        for k_row in range(rowptr[i + 1] - rowptr[i]):
+            j = rowptr[i] + k_row
+            if kind[s]:
+                k = diag_sets[s].index(int(colind[j]) - i)
+                mask[i] |= 1 << k
+            else:
+                k = k_row
+                nnz_offset += 1
             slot = pair_stride * units[s] + pair_stride * (k // 2) + 2 * lane + (k % 2)
-            off[slot] = colind[j] - base[s]
+            if not kind[s]:
+                off[slot] = colind[j] - base[s]
             vals[slot] = val[j]
-    return dict(width=width.astype(np.int32), base=base.astype(np.int32),
-                units=units.astype(np.int32), slots=slots, off=off, vals=vals)
+    return dict(kind=kind.astype(np.int32), width=width.astype(np.int32),
+                base=base.astype(np.int32), units=units.astype(np.int32),
+                diag=diag.astype(np.int32), mask=mask.astype(np.uint32), slots=slots,
+                off=off, vals=vals, nnz_offset=nnz_offset)
 
 
 def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int, n: int) -> int:

@@ -49,26 +49,33 @@ def test_delta16_random_2m_infeasible_stencil_feasible():
 def test_delta16_sliced_laplacian_closed_form():
     """5-point Laplacian on a 64 x 64 grid: slice s is grid line s.
 
-    Lines 0 and 63 have rows of 3 or 4 nonzeros (width 4), the other lines
-    rows of 4 or 5 (width 6); line s >= 1 starts with column 64 (s - 1).
-    Row 64 s + j of an inner line and inner column (1 <= s, j <= 62) holds
-    columns 64(s-1)+j, 64s+j-1, 64s+j, 64s+j+1, 64(s+1)+j.
+    Every slice is diagonal: lines 1..62 use the diagonals -64, -1, 0, 1, 64
+    (width 6), line 0 lacks -64 and line 63 lacks 64 (width 4).  Rows at the
+    ends of a line lack -1 or 1, so their masks miss that bit and its slot
+    stays empty.
     """
     rp, ci, v = synth.laplace2d(64)
     L = delta16_sliced_ref(rp, ci, v)
+    assert L["kind"].tolist() == [1] * 64
     assert L["width"].tolist() == [4] + [6] * 62 + [4]
-    assert L["base"].tolist() == [0] + [64 * (s - 1) for s in range(1, 64)]
     assert L["units"].tolist() == [0] + [2 + 3 * (s - 1) for s in range(1, 64)]
     assert L["slots"] == 64 * (4 + 6 * 62 + 4) == 24320
-    assert len(ci) == 20224
+    assert len(ci) == 20224 and L["nnz_offset"] == 0
     assert delta16_layout_ref(True, L["slots"], len(ci), 4096) == 1  # 1.2025 slots per nonzero
-    for s_, j in ((1, 1), (17, 40), (62, 62)):
-        for k, want in enumerate([j, 63 + j, 64 + j, 65 + j, 128 + j]):
+    d = L["diag"].reshape(64, 32)
+    assert d[0, :4].tolist() == [-1, 0, 1, 64] and d[63, :4].tolist() == [-64, -1, 0, 1]
+    assert all(d[s_, :5].tolist() == [-64, -1, 0, 1, 64] for s_ in range(1, 63))
+    assert not d[:, 5:].any() and not L["off"].any()
+    m = L["mask"].reshape(64, 64)
+    assert m[0].tolist() == [14] + [15] * 62 + [11]
+    assert m[63].tolist() == [13] + [15] * 62 + [7]
+    assert all(m[s_].tolist() == [29] + [31] * 62 + [23] for s_ in range(1, 63))
+    for s_, j in ((1, 1), (17, 40), (62, 62), (5, 0), (9, 63)):
+        present = [k for k in range(5) if (m[s_, j] >> k) & 1]
+        for k in range(6):
             slot = 128 * (2 + 3 * (s_ - 1)) + 128 * (k // 2) + 2 * j + k % 2
-            assert L["off"][slot] == want
-            assert L["vals"][slot] == (4.0 if k == 2 else -1.0)
-        # the padding slot after the fifth nonzero
-        assert L["vals"][128 * (2 + 3 * (s_ - 1)) + 128 * 2 + 2 * j + 1] == 0.0
+            want = (4.0 if k == 2 else -1.0) if k in present else 0.0
+            assert L["vals"][slot] == want, (s_, j, k)
 
 
 def test_delta16_sliced_layout_rule():
@@ -109,43 +116,70 @@ def test_delta16_sliced_layout_rule():
 
 
 def test_delta16_sliced_places_every_nonzero_once():
-    for rp, ci, v in cases(seed=11):
+    kinds = set()
+    for rp, ci, v in list(cases(seed=11)) + [synth.stencil3d_27(5, seed=2, values="random"),
+                                             synth.banded(300, 48, 3, seed=3)]:
+        rp, ci, v = np.asarray(rp), np.asarray(ci), np.asarray(v)
         n = len(rp) - 1
         L = delta16_sliced_ref(rp, ci, v)
         seen = np.zeros(L["slots"], dtype=bool)
-        for i in range(n):
-            s_, lane = divmod(i, 64)
-            assert L["width"][s_] % 2 == 0 and L["width"][s_] >= rp[i + 1] - rp[i]
-            for k in range(rp[i + 1] - rp[i]):
-                slot = 128 * L["units"][s_] + 128 * (k // 2) + 2 * lane + k % 2
-                assert not seen[slot]
-                seen[slot] = True
-                assert L["base"][s_] + L["off"][slot] == ci[rp[i] + k]
-                assert L["vals"][slot] == v[rp[i] + k]
+        for s_ in range(len(L["width"])):
+            r0, r1 = 64 * s_, min(n, 64 * s_ + 64)
+            rel = sorted({int(ci[j]) - i for i in range(r0, r1) for j in range(rp[i], rp[i + 1])})
+            longest = max([rp[i + 1] - rp[i] for i in range(r0, r1)], default=0)
+            diag = len(rel) <= 32 and len(rel) + len(rel) % 2 <= longest + longest % 2
+            assert L["kind"][s_] == int(diag)
+            kinds.add(int(diag))
+            for i in range(r0, r1):
+                lane = i - r0
+                for k_row in range(rp[i + 1] - rp[i]):
+                    j = rp[i] + k_row
+                    k = rel.index(int(ci[j]) - i) if diag else k_row
+                    assert k < L["width"][s_]
+                    slot = 128 * L["units"][s_] + 128 * (k // 2) + 2 * lane + k % 2
+                    assert not seen[slot]
+                    seen[slot] = True
+                    assert L["vals"][slot] == v[j]
+                    if diag:
+                        assert L["diag"][32 * s_ + k] == ci[j] - i and (L["mask"][i] >> k) & 1
+                    else:
+                        assert L["base"][s_] + L["off"][slot] == ci[j]
+                if diag:
+                    assert bin(int(L["mask"][i])).count("1") == rp[i + 1] - rp[i]
+                else:
+                    assert L["mask"][i] == 0
         assert not np.any(L["vals"][~seen]) and not np.any(L["off"][~seen])
-        for s_ in range(len(L["base"])):
-            seg = ci[rp[64 * s_]:rp[min(n, 64 * s_ + 64)]]
-            assert L["base"][s_] == (seg.min() if len(seg) else 0)
+    assert kinds == {0, 1}
 
 
 def test_delta16_sliced_spmv_in_lane_order_is_sequential():
-    """Summing each lane's slots in k order from +0 is Algorithm 1's sum."""
+    """Summing each lane's positions in order from +0 (adding nothing for an
+    empty position) is Algorithm 1's sum, in both kinds of slice."""
     rng = np.random.default_rng(5)
+    mats = []
     for n in (1, 63, 64, 65, 200):
         lens = rng.integers(0, 40, n)
         lens[rng.integers(0, n)] = 0
         rp = np.concatenate([[0], np.cumsum(lens)])
         ci = np.concatenate([np.sort(rng.choice(300, l, replace=False)) for l in lens]).astype(np.int64)
-        v = rng.uniform(-1, 1, len(ci))
-        x = rng.uniform(-1, 1, 300)
+        mats.append((rp, ci, rng.uniform(-1, 1, len(ci)), 300))
+    rp, ci, v = synth.stencil3d_27(6, seed=4, values="random")
+    mats.append((np.asarray(rp), np.asarray(ci), np.asarray(v), 216))
+    for rp, ci, v, m in mats:
+        n = len(rp) - 1
+        x = rng.uniform(-1, 1, m)
         L = delta16_sliced_ref(rp, ci, v)
         y = np.zeros(n)
         for i in range(n):
             s_, lane = divmod(i, 64)
             acc = 0.0
-            for k in range(rp[i + 1] - rp[i]):
+            for k in range(L["width"][s_]):
                 slot = 128 * L["units"][s_] + 128 * (k // 2) + 2 * lane + k % 2
-                acc = acc + L["vals"][slot] * x[L["base"][s_] + L["off"][slot]]
+                if L["kind"][s_]:
+                    if (L["mask"][i] >> k) & 1:
+                        acc = acc + L["vals"][slot] * x[i + L["diag"][32 * s_ + k]]
+                elif k < rp[i + 1] - rp[i]:
+                    acc = acc + L["vals"][slot] * x[L["base"][s_] + L["off"][slot]]
             y[i] = acc
         assert np.array_equal(y, spmv_seq(rp, ci, v, x))
 
