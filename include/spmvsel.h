@@ -68,7 +68,9 @@ typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
  *              per slice, taken when padding to the slice's longest row
  *              costs at most 1.35 slots per nonzero, or 1.5 when rows
  *              average 16 nonzeros or more (stencils, rows of nearly equal
- *              length).
+ *              length); a slice whose rows use at most 32 diagonals c - r
+ *              stores those diagonals once and a bit mask per row, and no
+ *              column data at all.
  *  XBLOCK_LDS  x blocking (class CML; replaces software prefetching of x):
  *              the columns are cut into S <= 8 slices (spmv_set_xblock_slices),
  *              each stored as its own CSR and run on the XCDs that take that
@@ -212,10 +214,12 @@ spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
 
 /* Algorithmic (compulsory) bytes of one SpMV with `variant`: 4(N+1) +
  * ib NNZ + vb NNZ + xb M + yb N, plus for DELTA16 (ib = 2 there, else 4)
- * 4 bytes per block reference column in the streamed layout, or 12 bytes
- * per 64-row slice (width, unit offset, reference column) in the sliced one
- * (the layout is decided here if needed; the streamed form where DELTA16 is
- * infeasible).  Traffic a variant adds on top (the XBLOCK_LDS slice row
+ * 4 bytes per block reference column in the streamed layout; in the sliced
+ * one, 16 bytes per 64-row slice (width, unit offset, reference column,
+ * kind) and 128 per diagonal slice (its diagonals), with 2 index bytes only
+ * for the nonzeros of offset slices (a row's mask in a diagonal slice takes
+ * the place of its row pointer).  The layout is decided here if needed; the
+ * streamed form is counted where DELTA16 is infeasible.  Traffic a variant adds on top (the XBLOCK_LDS slice row
  * pointers and partial y vectors, the sliced layout's padding slots) is
  * overhead and is not counted. */
 spmv_status_t spmv_bytes(spmv_plan_t plan, int32_t variant, int64_t *bytes);
@@ -256,9 +260,15 @@ spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
  * slice's longest row rounded up to even), 9 units int32[S] (exclusive
  * prefix sums of width / 2), 10 reference columns int32[S] (the slice's
  * smallest column, 0 if it has none), 11 offsets uint16[key 15],
- * 12 values [key 15] of the plan's value type.  The k-th nonzero of row
- * 64 s + l is at slot 128 units[s] + 128 (k / 2) + 2 l + (k % 2); every
- * other slot holds zero.
+ * 12 values [key 15] of the plan's value type, 13 kinds int32[S] (0 for an
+ * offset slice, 1 + D for a diagonal slice of D diagonals), 14 diagonals
+ * int32[32 S] (slice s's sorted diagonals c - r from 32 s, zero-padded;
+ * zeros for offset slices), 15 masks uint32[N] (bit k: the row has a
+ * nonzero on diagonal k of its slice; 0 in offset slices).  Position k of
+ * row 64 s + l is at slot 128 units[s] + 128 (k / 2) + 2 l + (k % 2), where
+ * k counts the row's nonzeros in an offset slice and is the diagonal's index
+ * in a diagonal slice; offsets are 0 in diagonal slices and every other slot
+ * holds zero.
  * `bytes` must equal the array size. */
 spmv_status_t spmv_plan_copy_format(spmv_plan_t plan, int32_t which,
                                     void *host_dst, int64_t bytes);

@@ -87,7 +87,8 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
         slot = 128 u_s + 128 (k // 2) + 2 l + (k % 2)
 
     with vals[slot] = a; every other slot (and off[] of diagonal slices)
-    holds 0.  Returns a dict with kind, width, base, units (int32[S]), diag
+    holds 0.  Returns a dict with kind, ndiag (|U_s| of diagonal slices, else
+    0), width, base, units (int32[S]), diag
     (int32[32 S]: U_s zero-padded, zeros for offset slices), mask (uint32[N]:
     0 in offset slices), slots (64 sum w_s), off (int64[slots]; the caller
     checks they fit 16 bits), vals (float64[slots]) and nnz_offset (the
@@ -99,6 +100,7 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
     n = len(rowptr) - 1
     ns = (n + slice_rows - 1) // slice_rows
     kind = np.zeros(ns, dtype=np.int64)
+    ndiag = np.zeros(ns, dtype=np.int64)
     width = np.zeros(ns, dtype=np.int64)
     base = np.zeros(ns, dtype=np.int64)
     diag = np.zeros(32 * ns, dtype=np.int64)
@@ -114,7 +116,7 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
                       for j in range(rowptr[i], rowptr[i + 1])})
         d_even = len(rel) + (len(rel) % 2)
         if len(rel) <= 32 and d_even <= w_off:
-            kind[s], width[s] = 1, d_even
+            kind[s], ndiag[s], width[s] = 1, len(rel), d_even
             diag[32 * s:32 * s + len(rel)] = rel
         else:
             width[s] = w_off
@@ -142,7 +144,8 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
             if not kind[s]:
                 off[slot] = colind[j] - base[s]
             vals[slot] = val[j]
-    return dict(kind=kind.astype(np.int32), width=width.astype(np.int32),
+    return dict(kind=kind.astype(np.int32), ndiag=ndiag.astype(np.int32),
+                width=width.astype(np.int32),
                 base=base.astype(np.int32), units=units.astype(np.int32),
                 diag=diag.astype(np.int32), mask=mask.astype(np.uint32), slots=slots,
                 off=off, vals=vals, nnz_offset=nnz_offset)

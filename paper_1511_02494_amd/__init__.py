@@ -237,7 +237,7 @@ def spmv_plan_query(plan, key: int) -> int:
 
 _FORMAT_DTYPES = {0: np.int32, 1: np.uint16, 2: np.int32, 3: np.int32, 4: np.int32,
                   5: np.int32, 6: np.int32, 7: np.int32, 8: np.int32, 9: np.int32, 10: np.int32,
-                  11: np.uint16}
+                  11: np.uint16, 13: np.int32, 14: np.int32, 15: np.uint32}
 
 
 def spmv_plan_copy_format(plan, which: int, count: int, dtype=None) -> np.ndarray:

@@ -324,12 +324,16 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     SPMV_TRY(P->d16s_width.alloc(nb));
     SPMV_TRY(P->d16s_units.alloc(nb + 4));  // the scan also writes the total after the last slice
     SPMV_TRY(P->d16s_base.alloc(nb));
+    SPMV_TRY(P->d16s_kind.alloc(nb));
+    SPMV_TRY(P->d16s_diag.alloc(nb * kSellMaxDiag));
+    SPMV_TRY(P->d16s_nnz.alloc(nb));
     DevBuf halfw, tmp;
     SPMV_TRY(halfw.alloc(nb));
-    int64_t units = 0;
+    int64_t units = 0, nnz_off = 0, ndiag = 0;
     if (nsl > 0) {
         SPMV_HIP(launch_sliced_shape(*P, P->d16s_width.as<int32_t>(), halfw.as<int32_t>(),
-                                     P->d16s_base.as<int32_t>(), S(P)));
+                                     P->d16s_base.as<int32_t>(), P->d16s_kind.as<int32_t>(),
+                                     P->d16s_diag.as<int32_t>(), P->d16s_nnz.as<int32_t>(), S(P)));
         size_t need = 0;
         int64_t *dtot = scr<int64_t>(P, kOffSum);
         SPMV_HIP(launch_exclusive_scan_i32(halfw.as<int32_t>(), P->d16s_units.as<int32_t>(), nsl, 1,
@@ -338,9 +342,18 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
         SPMV_HIP(launch_exclusive_scan_i32(halfw.as<int32_t>(), P->d16s_units.as<int32_t>(), nsl, 1,
                                            dtot, tmp.p, tmp.bytes, S(P), nullptr));
         SPMV_HIP(hipMemcpyAsync(P->h_pinned, dtot, 8, hipMemcpyDeviceToHost, S(P)));
+        std::vector<int32_t> kinds((size_t)nsl), counts((size_t)nsl);
+        SPMV_HIP(hipMemcpyAsync(kinds.data(), P->d16s_kind.p, nb, hipMemcpyDeviceToHost, S(P)));
+        SPMV_HIP(hipMemcpyAsync(counts.data(), P->d16s_nnz.p, nb, hipMemcpyDeviceToHost, S(P)));
         SPMV_TRY(sync(P));
         memcpy(&units, P->h_pinned, 8);
+        for (int64_t k = 0; k < nsl; ++k) {
+            if (kinds[k] > 0) ++ndiag;
+            else nnz_off += counts[k];
+        }
     }
+    P->d16_nnz_off = nnz_off;
+    P->d16_ndiag = ndiag;
     P->d16_nsl = nsl;
     P->d16_slots = units * 2 * kSellRows;
     // the unit offsets are int32 (with NNZ < 2^30 every width is too)
@@ -352,10 +365,13 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     if (P->d16_layout_req == 1 && !representable)
         return fail(SPMV_ERR_INFEASIBLE, "delta16: the sliced layout needs under 2^31 slot pairs");
     P->d16_layout = P->d16_layout_req >= 0 ? P->d16_layout_req : automatic;
+    P->d16s_nnz.release();
     if (P->d16_layout == 0) {
         P->d16s_width.release();
         P->d16s_units.release();
         P->d16s_base.release();
+        P->d16s_kind.release();
+        P->d16s_diag.release();
     }
     return SPMV_OK;
 }
@@ -553,10 +569,15 @@ spmv_status_t build_format(spmv_plan *P, int v) {
             const size_t slots = (size_t)P->d16_slots;
             SPMV_TRY(P->d16s_off.alloc(slots * 2 + 16));
             SPMV_TRY(P->d16s_val.alloc(slots * vbytes(P->dtype) + 16));
+            const size_t mbytes = (size_t)(P->n > 0 ? P->n : 1) * 4;
+            SPMV_TRY(P->d16s_mask.alloc(mbytes));
             SPMV_HIP(hipMemsetAsync(P->d16s_off.p, 0, slots * 2 + 16, S(P)));
             SPMV_HIP(hipMemsetAsync(P->d16s_val.p, 0, slots * vbytes(P->dtype) + 16, S(P)));
+            SPMV_HIP(hipMemsetAsync(P->d16s_mask.p, 0, mbytes, S(P)));
             SPMV_HIP(launch_sliced_scatter(*P, P->d16s_units.as<int32_t>(), P->d16s_base.as<int32_t>(),
-                                           P->d16s_off.as<uint16_t>(), P->d16s_val.p, S(P)));
+                                           P->d16s_kind.as<int32_t>(), P->d16s_diag.as<int32_t>(),
+                                           P->d16s_off.as<uint16_t>(), P->d16s_val.p,
+                                           P->d16s_mask.as<uint32_t>(), S(P)));
             SPMV_TRY(sync(P));
             P->d16_built = true;
             return SPMV_OK;
@@ -1004,9 +1025,15 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
     if (v == V_DELTA16) {  // also defined where the variant is infeasible
         SPMV_TRY(check_d16(P));
         if (d16_feasible(P)) SPMV_TRY(d16_decide_layout(P));
-        extra = d16_feasible(P) && P->d16_layout == 1
-                    ? 12 * P->d16_nsl  // width, units and base per slice
-                    : 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
+        if (d16_feasible(P) && P->d16_layout == 1) {
+            // offsets only in offset slices; width, units, base and kind per
+            // slice, 32 diagonals per diagonal slice; a row's mask replaces
+            // its row pointer in diagonal slices
+            *bytes = 4 * (P->n + 1) + vb * P->nnz + 2 * P->d16_nnz_off + xb * P->m + xb * P->n +
+                     16 * P->d16_nsl + 4 * kSellMaxDiag * P->d16_ndiag;
+            return SPMV_OK;
+        }
+        extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
     }
     *bytes = 4 * (P->n + 1) + (ib + vb) * P->nnz + xb * P->m + xb * P->n + extra;
     return SPMV_OK;
@@ -1065,13 +1092,19 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
     const void *src = nullptr;
     int64_t want = 0;
     switch (which) {
-    case 8: case 9: case 10: case 11: case 12:
+    case 8: case 9: case 10: case 11: case 12: case 13: case 14: case 15:
         SPMV_TRY(build_format(P, V_DELTA16));
         if (P->d16_layout != 1) return fail(SPMV_ERR_ARG, "delta16 is not in the sliced layout");
-        src = which == 8 ? P->d16s_width.p : which == 9 ? P->d16s_units.p : which == 10 ? P->d16s_base.p
-            : which == 11 ? P->d16s_off.p : P->d16s_val.p;
-        want = which <= 10 ? 4 * P->d16_nsl : which == 11 ? 2 * P->d16_slots
-                                                           : vbytes(P->dtype) * P->d16_slots;
+        switch (which) {
+        case 8: src = P->d16s_width.p; want = 4 * P->d16_nsl; break;
+        case 9: src = P->d16s_units.p; want = 4 * P->d16_nsl; break;
+        case 10: src = P->d16s_base.p; want = 4 * P->d16_nsl; break;
+        case 11: src = P->d16s_off.p; want = 2 * P->d16_slots; break;
+        case 12: src = P->d16s_val.p; want = vbytes(P->dtype) * P->d16_slots; break;
+        case 13: src = P->d16s_kind.p; want = 4 * P->d16_nsl; break;
+        case 14: src = P->d16s_diag.p; want = 4 * kSellMaxDiag * P->d16_nsl; break;
+        default: src = P->d16s_mask.p; want = 4 * P->n; break;
+        }
         break;
     case 0: case 1:
         SPMV_TRY(build_format(P, V_DELTA16));
@@ -1338,6 +1371,9 @@ spmv_status_t spmv_set_delta16_layout(spmv_plan_t P, int32_t layout) {
     P->d16s_base.release();
     P->d16s_off.release();
     P->d16s_val.release();
+    P->d16s_kind.release();
+    P->d16s_diag.release();
+    P->d16s_mask.release();
     if (P->variant == V_DELTA16) SPMV_TRY(build_format(P, V_DELTA16));  // else on next use
     return SPMV_OK;
 }

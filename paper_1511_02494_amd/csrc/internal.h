@@ -31,6 +31,7 @@ constexpr int kSellRows = 64;         // rows per slice of the sliced delta16 la
 constexpr double kSellMaxPad = 1.35;  // ... taken when its slots are at most this many per nonzero,
 constexpr double kSellMaxPadLong = 1.5;  // or this many when the mean row has
 constexpr int kSellLongMean = 16;        // at least this many nonzeros
+constexpr int kSellMaxDiag = 32;         // diagonals a diagonal slice can hold (mask bits)
 constexpr int kLineBytes = 128;       // cache line assumed by the miss feature
 constexpr int64_t kLlcBytes = 256ll << 20;
 constexpr int kFeatBlocks = 1024;     // feature kernel partial records
@@ -112,7 +113,11 @@ struct spmv_plan {
     int d16_layout = -1;         // -1: not decided yet
     int d16_layout_req = -1;     // forced layout, -1 automatic
     int64_t d16_nsl = 0, d16_slots = 0;
+    int64_t d16_nnz_off = 0, d16_ndiag = 0;  // nonzeros of offset slices; diagonal slices
     spmvsel::DevBuf d16s_width, d16s_units, d16s_base, d16s_off, d16s_val;
+    // per slice: 0 for an offset slice, 1 + D for a diagonal slice of D
+    // diagonals (listed in d16s_diag[32 s .. 32 s + D)); one mask per row
+    spmvsel::DevBuf d16s_kind, d16s_diag, d16s_mask, d16s_nnz;
     bool mp_built = false;
     int64_t mp_tiles = 0;
     spmvsel::DevBuf mp_split_row, mp_split_nnz, mp_carry_row, mp_carry_val;
@@ -179,10 +184,15 @@ hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16
 // rounded up to even), half width and reference column (smallest column);
 // then, with the scanned half widths (units of 128 slots), the scatter of
 // offsets and values into the zero-filled slot arrays.
+// Diagonal slices: a slice whose rows' values of c - r, D distinct ones, fit
+// kSellMaxDiag and, rounded up to even, its offset width, lists them in
+// diag[32 s ..] (kind = 1 + D) and sets bit k of a row's mask for each
+// diagonal k the row has; its positions follow the diagonals, not the row.
 hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
-                               hipStream_t s);
+                               int32_t *kind, int32_t *diag, int32_t *snnz, hipStream_t s);
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
-                                 uint16_t *off, void *vals, hipStream_t s);
+                                 const int32_t *kind, const int32_t *diag, uint16_t *off,
+                                 void *vals, uint32_t *mask, hipStream_t s);
 hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t panels,
                            unsigned long long *d_max, hipStream_t s);
 hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,

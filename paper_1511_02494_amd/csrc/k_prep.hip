@@ -37,63 +37,103 @@ hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16
 }
 
 // ---- delta16, sliced layout.  Slice s = rows [64 s, 64 s + 64), one per
-// lane of a wavefront; its width is the longest row rounded up to an even
-// count and its reference column the smallest column of its nonzeros.  The
+// lane of a wavefront.  Offset slices: width = the longest row rounded up to
+// an even count, reference column = the smallest column of the slice; the
 // k-th nonzero of the row in lane l is stored at slot
 //   128 units[s] + 128 (k / 2) + 2 l + (k % 2)
-// (units = exclusive prefix sums of the half widths), so that lane l reads
-// its nonzeros in pairs and a wavefront's pair load is 64 consecutive pairs.
+// (units = exclusive prefix sums of the half widths), so lane l reads its
+// nonzeros in pairs and a wavefront's pair load is 64 consecutive pairs.
+// Diagonal slices (see internal.h) use the same slots with k = the index of
+// the nonzero's diagonal c - r among the slice's sorted diagonals.
 __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
                                                          const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci,
                                                          int32_t *__restrict__ width,
                                                          int32_t *__restrict__ halfw,
-                                                         int32_t *__restrict__ base) {
+                                                         int32_t *__restrict__ base,
+                                                         int32_t *__restrict__ kind,
+                                                         int32_t *__restrict__ diag,
+                                                         int32_t *__restrict__ snnz) {
     const int64_t sl = blockIdx.x * (int64_t)(kBlock / kSellRows) + threadIdx.x / kSellRows;
     if (sl >= nsl) return;  // whole wavefronts leave together
-    const int64_t r = sl * kSellRows + (threadIdx.x & (kSellRows - 1));
-    int len = 0, first = INT32_MAX;
+    const int lane = threadIdx.x & (kSellRows - 1);
+    const int64_t r = sl * kSellRows + lane;
+    int32_t a = 0, e = 0;
     if (r < n) {
-        const int32_t a = rp[r], e = rp[r + 1];
-        len = e - a;
-        if (len > 0) first = ci[a];
+        a = rp[r];
+        e = rp[r + 1];
     }
+    int len = e - a, first = len > 0 ? ci[a] : INT32_MAX, cnt = len;
 #pragma unroll
     for (int d = kSellRows / 2; d > 0; d >>= 1) {
         const int ol = __shfl_xor(len, d, kSellRows);
         const int of = __shfl_xor(first, d, kSellRows);
+        cnt += __shfl_xor(cnt, d, kSellRows);
         len = ol > len ? ol : len;
         first = of < first ? of : first;
     }
-    if ((threadIdx.x & (kSellRows - 1)) == 0) {
-        const int w = len + (len & 1);
+    const int w_off = len + (len & 1);
+    // the slice's distinct diagonals in increasing order: each round takes
+    // the smallest head c - r over the lanes, and the lanes holding it move on
+    constexpr int64_t kNone = INT64_MAX;
+    int32_t p = a, mine = 0, D = 0;
+    bool fits = true;
+    while (true) {
+        const int64_t head = p < e ? (int64_t)ci[p] - r : kNone;
+        int64_t m = head;
+#pragma unroll
+        for (int d = kSellRows / 2; d > 0; d >>= 1) {
+            const int64_t o = __shfl_xor(m, d, kSellRows);
+            m = o < m ? o : m;
+        }
+        if (m == kNone) break;
+        if (D >= kSellMaxDiag) {
+            fits = false;
+            break;
+        }
+        if (lane == D) mine = (int32_t)m;
+        ++D;
+        if (head == m) ++p;
+    }
+    const int d_even = D + (D & 1);
+    const bool is_diag = fits && d_even <= w_off;
+    if (lane < kSellMaxDiag) diag[sl * kSellMaxDiag + lane] = is_diag && lane < D ? mine : 0;
+    if (lane == 0) {
+        const int w = is_diag ? d_even : w_off;
         width[sl] = w;
         halfw[sl] = w / 2;
         base[sl] = first == INT32_MAX ? 0 : first;
+        kind[sl] = is_diag ? 1 + D : 0;
+        snnz[sl] = cnt;
     }
 }
 
 hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
-                               hipStream_t s) {
+                               int32_t *kind, int32_t *diag, int32_t *snnz, hipStream_t s) {
     const int64_t nsl = (P.n + kSellRows - 1) / kSellRows;
     if (nsl == 0) return hipSuccess;
     const int64_t per = kBlock / kSellRows;
     hipLaunchKernelGGL(k_sliced_shape, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0, s,
-                       P.n, nsl, P.rowptr, P.colind, width, halfw, base);
+                       P.n, nsl, P.rowptr, P.colind, width, halfw, base, kind, diag, snnz);
     return hipGetLastError();
 }
 
 // One workgroup per kBlock rows (kBlock / 64 slices): thread t takes the
 // block's nonzeros t, t + kBlock, ... (coalesced reads), finds its row by a
-// binary search of the block's row pointers in LDS and writes its slot.
+// binary search of the block's row pointers in LDS and writes its slot (in a
+// diagonal slice: the slot of its diagonal, found by a binary search of the
+// slice's diagonals, and the diagonal's bit in the row's mask).
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
                                                            const V *__restrict__ val,
                                                            const int32_t *__restrict__ units,
                                                            const int32_t *__restrict__ base,
+                                                           const int32_t *__restrict__ kind,
+                                                           const int32_t *__restrict__ diag,
                                                            uint16_t *__restrict__ off,
-                                                           V *__restrict__ vals) {
+                                                           V *__restrict__ vals,
+                                                           uint32_t *__restrict__ mask) {
     __shared__ int32_t s_rp[kBlock + 1];
     const int64_t r0 = (int64_t)blockIdx.x * kBlock;
     const int nrows = (int)((n - r0) < kBlock ? (n - r0) : kBlock);
@@ -107,31 +147,45 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
             if (s_rp[mid] <= j) lo = mid; else hi = mid - 1;
         }
         const int64_t r = r0 + lo;
-        const int k = j - s_rp[lo];
         const int64_t sl = r / kSellRows;
         const int lane = (int)(r % kSellRows);
+        const int kd = kind[sl];
+        int k = j - s_rp[lo];
+        if (kd > 0) {  // position of the diagonal c - r among the slice's D
+            const int64_t rel = (int64_t)ci[j] - r;
+            const int32_t *dg = diag + sl * kSellMaxDiag;
+            int a = 0, b = kd - 2;  // the diagonal is present: search [0, D - 1]
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if ((int64_t)dg[mid] < rel) a = mid + 1; else b = mid;
+            }
+            k = a;
+            atomicOr(mask + r, 1u << k);
+        }
         const int64_t slot = 2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1);
-        off[slot] = (uint16_t)(ci[j] - base[sl]);
+        if (kd == 0) off[slot] = (uint16_t)(ci[j] - base[sl]);
         vals[slot] = val[j];
     }
 }
 
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
-                                 uint16_t *off, void *vals, hipStream_t s) {
+                                 const int32_t *kind, const int32_t *diag, uint16_t *off,
+                                 void *vals, uint32_t *mask, hipStream_t s) {
     if (P.n == 0 || P.nnz == 0) return hipSuccess;
     const dim3 g((unsigned)((P.n + kBlock - 1) / kBlock));
     switch (P.dtype) {
     case SPMV_F64:
         hipLaunchKernelGGL(k_sliced_scatter<double>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
-                           (const double *)P.val, units, base, off, (double *)vals);
+                           (const double *)P.val, units, base, kind, diag, off, (double *)vals, mask);
         break;
     case SPMV_F32:
         hipLaunchKernelGGL(k_sliced_scatter<float>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
-                           (const float *)P.val, units, base, off, (float *)vals);
+                           (const float *)P.val, units, base, kind, diag, off, (float *)vals, mask);
         break;
     default:
         hipLaunchKernelGGL(k_sliced_scatter<uint16_t>, g, dim3(kBlock), 0, s, P.n, P.rowptr,
-                           P.colind, (const uint16_t *)P.val, units, base, off, (uint16_t *)vals);
+                           P.colind, (const uint16_t *)P.val, units, base, kind, diag, off,
+                           (uint16_t *)vals, mask);
     }
     return hipGetLastError();
 }

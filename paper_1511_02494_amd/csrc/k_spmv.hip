@@ -198,8 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
 // dropped, which keeps the loads free of branches.
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_sliced_d16(
-    int64_t n, int64_t nsl, const int32_t *__restrict__ rp, const int32_t *__restrict__ width,
-    const int32_t *__restrict__ units, const int32_t *__restrict__ base,
+    int64_t n, int64_t m, int64_t nsl, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ width, const int32_t *__restrict__ units,
+    const int32_t *__restrict__ base, const int32_t *__restrict__ kind,
+    const int32_t *__restrict__ diag, const uint32_t *__restrict__ mask,
     const uint16_t *__restrict__ off, const V *__restrict__ val,
     const typename VT<V>::A *__restrict__ x, typename VT<V>::A *__restrict__ y) {
     using A = typename VT<V>::A;
@@ -212,6 +214,40 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     const int64_t r = sl * kSellRows + lane;
     const int w = width[sl];
     const int64_t o = 2 * kSellRows * (int64_t)units[sl] + 2 * lane;
+    if (kind[sl] > 0) {
+        // diagonal slice: the column of position k is r + dg[k] (the same
+        // diagonals for every lane, so those are scalar loads); only values
+        // are streamed, and the row's mask says which positions it has.
+        // Rows here hold at most 32 nonzeros, so FP32 needs no Kahan sum.
+        const int32_t *dg = diag + sl * kSellMaxDiag;
+        const uint32_t mk = r < n ? mask[r] : 0u;
+        A acc = A(0);
+        for (int k0 = 0; k0 < w; k0 += 4) {
+            const int k1 = (k0 + 2) < w ? k0 + 2 : w - 2;
+            const VP v0 = __builtin_nontemporal_load(
+                reinterpret_cast<const VP *>(val + o + (int64_t)(k0 / 2) * (2 * kSellRows)));
+            const VP v1 = __builtin_nontemporal_load(
+                reinterpret_cast<const VP *>(val + o + (int64_t)(k1 / 2) * (2 * kSellRows)));
+            const int32_t d[4] = {dg[k0], dg[k0 + 1], dg[k1], dg[k1 + 1]};
+            A xv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {  // a position the row lacks may point outside x
+                int64_t c = r + d[i];
+                c = c < 0 ? 0 : (c >= m ? m - 1 : c);
+                xv[i] = x[c];
+            }
+            const A p[4] = {VT<V>::cvt(v0.x) * xv[0], VT<V>::cvt(v0.y) * xv[1],
+                            VT<V>::cvt(v1.x) * xv[2], VT<V>::cvt(v1.y) * xv[3]};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = k0 + i;
+                // a +0 addend leaves a sum that started at +0 unchanged
+                acc = acc + ((k < w && ((mk >> k) & 1u)) ? p[i] : A(0));
+            }
+        }
+        if (r < n) y[r] = acc;
+        return;
+    }
     const int32_t b = base[sl];
     const int len = r < n ? rp[r + 1] - rp[r] : 0;
     const bool comp = is_f32<A>() && len >= kKahanMinLen;
@@ -764,10 +800,11 @@ hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStre
         using A = typename VT<V>::A;
         const int64_t per = kBlock / kSellRows;
         const unsigned g = (unsigned)((P.d16_nsl + per - 1) / per);
-        hipLaunchKernelGGL((k_sliced_d16<V>), dim3(g), dim3(kBlock), 0, s, P.n, P.d16_nsl, P.rowptr,
-                           P.d16s_width.as<int32_t>(), P.d16s_units.as<int32_t>(),
-                           P.d16s_base.as<int32_t>(), P.d16s_off.as<uint16_t>(),
-                           P.d16s_val.as<V>(), (const A *)x, (A *)y);
+        hipLaunchKernelGGL((k_sliced_d16<V>), dim3(g), dim3(kBlock), 0, s, P.n, P.m, P.d16_nsl,
+                           P.rowptr, P.d16s_width.as<int32_t>(), P.d16s_units.as<int32_t>(),
+                           P.d16s_base.as<int32_t>(), P.d16s_kind.as<int32_t>(),
+                           P.d16s_diag.as<int32_t>(), P.d16s_mask.as<uint32_t>(),
+                           P.d16s_off.as<uint16_t>(), P.d16s_val.as<V>(), (const A *)x, (A *)y);
         return hipGetLastError();
     });
 }

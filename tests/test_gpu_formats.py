@@ -44,6 +44,10 @@ def test_formats_match_oracle(name, build, m):
         assert np.array_equal(S.spmv_plan_copy_format(h, 1, nnz), off)
         S.spmv_set_delta16_layout(h, 1)
         check_sliced(h, L, np.float64)
+        # compulsory bytes: no offsets in diagonal slices, their diagonals once
+        want = (4 * (n + 1) + 8 * nnz + 2 * L["nnz_offset"] + 8 * m + 8 * n + 16 * len(L["width"])
+                + 128 * int(np.count_nonzero(L["kind"])))
+        assert S.spmv_bytes(h, S.V_DELTA16) == want
     else:
         assert S.spmv_plan_query(h, 14) == -1
     T = S.spmv_plan_query(h, 3)
@@ -73,6 +77,10 @@ def test_formats_match_oracle(name, build, m):
 
 def check_sliced(h, L, vdtype):
     ns = len(L["width"])
+    kinds = S.spmv_plan_copy_format(h, 13, ns)
+    assert np.array_equal(kinds, np.where(L["kind"] > 0, 1 + L["ndiag"], 0))
+    assert np.array_equal(S.spmv_plan_copy_format(h, 14, 32 * ns), L["diag"])
+    assert np.array_equal(S.spmv_plan_copy_format(h, 15, len(L["mask"])), L["mask"])
     assert np.array_equal(S.spmv_plan_copy_format(h, 8, ns), L["width"])
     assert np.array_equal(S.spmv_plan_copy_format(h, 9, ns), L["units"])
     assert np.array_equal(S.spmv_plan_copy_format(h, 10, ns), L["base"])
