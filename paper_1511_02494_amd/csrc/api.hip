@@ -573,7 +573,6 @@ spmv_status_t build_format(spmv_plan *P, int v) {
             SPMV_TRY(P->d16s_mask.alloc(mbytes));
             SPMV_HIP(hipMemsetAsync(P->d16s_off.p, 0, slots * 2 + 16, S(P)));
             SPMV_HIP(hipMemsetAsync(P->d16s_val.p, 0, slots * vbytes(P->dtype) + 16, S(P)));
-            SPMV_HIP(hipMemsetAsync(P->d16s_mask.p, 0, mbytes, S(P)));
             SPMV_HIP(launch_sliced_scatter(*P, P->d16s_units.as<int32_t>(), P->d16s_base.as<int32_t>(),
                                            P->d16s_kind.as<int32_t>(), P->d16s_diag.as<int32_t>(),
                                            P->d16s_off.as<uint16_t>(), P->d16s_val.p,

@@ -108,6 +108,21 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
+// Minimum over the 64 lanes of a wavefront (every lane gets it).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int wave_min(int v) {
+    v = min(v, dpp_i<kQuadSwap1>(v));
+    v = min(v, dpp_i<kQuadSwap2>(v));
+    v = min(v, dpp_i<kRowHalfMirror>(v));
+    v = min(v, dpp_i<kRowMirror>(v));
+    v = min(v, __builtin_amdgcn_ds_swizzle(v, 0x401F));
+    v = min(v, __shfl_xor(v, 32, 64));
+    return v;
+}
+
 // ------------------------------------------------------------ accumulation
 // Plain sum from +0, or Kahan's compensated sum (Kahan 1965) for FP32 rows
 // longer than 256 nonzeros.  Compiled without contraction, so every

@@ -54,12 +54,15 @@ __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
                                                          int32_t *__restrict__ kind,
                                                          int32_t *__restrict__ diag,
                                                          int32_t *__restrict__ snnz) {
-    const int64_t sl = blockIdx.x * (int64_t)(kBlock / kSellRows) + threadIdx.x / kSellRows;
-    if (sl >= nsl) return;  // whole wavefronts leave together
+    constexpr int kWaves = kBlock / kSellRows;
+    __shared__ int32_t s_ci[kWaves][kSellRows * kSellMaxDiag];  // a slice's nonzeros
+    const int wv = threadIdx.x / kSellRows;
+    const int64_t sl = blockIdx.x * (int64_t)kWaves + wv;
+    const bool live = sl < nsl;  // (no early exit: every thread reaches the barrier)
     const int lane = threadIdx.x & (kSellRows - 1);
     const int64_t r = sl * kSellRows + lane;
     int32_t a = 0, e = 0;
-    if (r < n) {
+    if (live && r < n) {
         a = rp[r];
         e = rp[r + 1];
     }
@@ -73,28 +76,36 @@ __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
         first = of < first ? of : first;
     }
     const int w_off = len + (len & 1);
+    // A slice with a row longer than 32 has more than 32 diagonals.  Else its
+    // nonzeros (at most 64 x 32) are staged in LDS with coalesced loads.
+    const bool maybe = live && len <= kSellMaxDiag;
+    const int32_t A = live ? rp[sl * kSellRows] : 0;
+    const int32_t E = live ? rp[(sl + 1) * kSellRows < n ? (sl + 1) * kSellRows : n] : 0;
+    if (maybe)
+        for (int32_t i = lane; i < E - A; i += kSellRows) s_ci[wv][i] = ci[A + i];
+    __syncthreads();
     // the slice's distinct diagonals in increasing order: each round takes
-    // the smallest head c - r over the lanes, and the lanes holding it move on
-    constexpr int64_t kNone = INT64_MAX;
+    // the smallest head c - r over the lanes (c - r fits int32; INT32_MAX
+    // marks an exhausted lane, so a row reaching that diagonal, possible only
+    // for column 2^31 - 1 of row 0, makes the slice an offset slice), and the
+    // lanes holding it move on
     int32_t p = a, mine = 0, D = 0;
-    bool fits = true;
-    while (true) {
-        const int64_t head = p < e ? (int64_t)ci[p] - r : kNone;
-        int64_t m = head;
-#pragma unroll
-        for (int d = kSellRows / 2; d > 0; d >>= 1) {
-            const int64_t o = __shfl_xor(m, d, kSellRows);
-            m = o < m ? o : m;
-        }
-        if (m == kNone) break;
+    bool fits = maybe;
+    if (maybe)
+        fits = wave_min(e > a && s_ci[wv][e - 1 - A] - (int32_t)r == INT32_MAX ? 0 : 1) == 1;
+    while (fits) {
+        const int32_t head = p < e ? s_ci[wv][p - A] - (int32_t)r : INT32_MAX;
+        const int32_t m = wave_min(head);
+        if (m == INT32_MAX) break;
         if (D >= kSellMaxDiag) {
             fits = false;
             break;
         }
-        if (lane == D) mine = (int32_t)m;
+        if (lane == D) mine = m;
         ++D;
         if (head == m) ++p;
     }
+    if (!live) return;
     const int d_even = D + (D & 1);
     const bool is_diag = fits && d_even <= w_off;
     if (lane < kSellMaxDiag) diag[sl * kSellMaxDiag + lane] = is_diag && lane < D ? mine : 0;
@@ -119,10 +130,12 @@ hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *half
 }
 
 // One workgroup per kBlock rows (kBlock / 64 slices): thread t takes the
-// block's nonzeros t, t + kBlock, ... (coalesced reads), finds its row by a
-// binary search of the block's row pointers in LDS and writes its slot (in a
-// diagonal slice: the slot of its diagonal, found by a binary search of the
-// slice's diagonals, and the diagonal's bit in the row's mask).
+// block's nonzeros t, t + kBlock, ... (coalesced reads) and finds its row by
+// a binary search of the block's row pointers in LDS.  In an offset slice
+// it writes its offset and value; in a diagonal slice it finds its diagonal
+// among the slice's (in LDS) by a binary search, writes its value to that
+// position and sets the diagonal's bit in the row's mask (LDS atomics; the
+// masks are stored once at the end, zero for rows of offset slices).
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
@@ -134,10 +147,21 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
                                                            uint16_t *__restrict__ off,
                                                            V *__restrict__ vals,
                                                            uint32_t *__restrict__ mask) {
+    constexpr int kWaves = kBlock / kSellRows;
     __shared__ int32_t s_rp[kBlock + 1];
+    __shared__ int32_t s_dg[kWaves][kSellMaxDiag];
+    __shared__ int32_t s_kind[kWaves];
+    __shared__ uint32_t s_mask[kBlock];
     const int64_t r0 = (int64_t)blockIdx.x * kBlock;
     const int nrows = (int)((n - r0) < kBlock ? (n - r0) : kBlock);
+    const int64_t sl0 = r0 / kSellRows;
+    const int nsl = (nrows + kSellRows - 1) / kSellRows;
     for (int r = threadIdx.x; r <= nrows; r += kBlock) s_rp[r] = rp[r0 + r];
+    if ((int)threadIdx.x < kWaves) s_kind[threadIdx.x] = threadIdx.x < nsl ? kind[sl0 + threadIdx.x] : 0;
+    for (int i = threadIdx.x; i < kWaves * kSellMaxDiag; i += kBlock)
+        s_dg[i / kSellMaxDiag][i % kSellMaxDiag] =
+            i / kSellMaxDiag < nsl ? diag[sl0 * kSellMaxDiag + i] : 0;
+    s_mask[threadIdx.x] = 0;
     __syncthreads();
     const int32_t e = s_rp[nrows];
     for (int32_t j = s_rp[0] + (int32_t)threadIdx.x; j < e; j += kBlock) {
@@ -146,32 +170,34 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
             const int mid = (lo + hi + 1) >> 1;
             if (s_rp[mid] <= j) lo = mid; else hi = mid - 1;
         }
-        const int64_t r = r0 + lo;
-        const int64_t sl = r / kSellRows;
-        const int lane = (int)(r % kSellRows);
-        const int kd = kind[sl];
+        const int ls = lo / kSellRows;  // the slice within the block
+        const int lane = lo % kSellRows;
+        const int64_t sl = sl0 + ls;
+        const int kd = s_kind[ls];
         int k = j - s_rp[lo];
         if (kd > 0) {  // position of the diagonal c - r among the slice's D
-            const int64_t rel = (int64_t)ci[j] - r;
-            const int32_t *dg = diag + sl * kSellMaxDiag;
-            int a = 0, b = kd - 2;  // the diagonal is present: search [0, D - 1]
+            const int32_t rel = ci[j] - (int32_t)(r0 + lo);
+            int a = 0, b = kd - 2;  // it is present: search [0, D - 1]
             while (a < b) {
                 const int mid = (a + b) >> 1;
-                if ((int64_t)dg[mid] < rel) a = mid + 1; else b = mid;
+                if (s_dg[ls][mid] < rel) a = mid + 1; else b = mid;
             }
             k = a;
-            atomicOr(mask + r, 1u << k);
+            atomicOr(&s_mask[lo], 1u << k);
+        } else {
+            off[2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1)] =
+                (uint16_t)(ci[j] - base[sl]);
         }
-        const int64_t slot = 2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1);
-        if (kd == 0) off[slot] = (uint16_t)(ci[j] - base[sl]);
-        vals[slot] = val[j];
+        vals[2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1)] = val[j];
     }
+    __syncthreads();
+    if ((int)threadIdx.x < nrows) mask[r0 + threadIdx.x] = s_mask[threadIdx.x];
 }
 
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
                                  const int32_t *kind, const int32_t *diag, uint16_t *off,
                                  void *vals, uint32_t *mask, hipStream_t s) {
-    if (P.n == 0 || P.nnz == 0) return hipSuccess;
+    if (P.n == 0) return hipSuccess;  // (with no nonzeros it still writes the zero masks)
     const dim3 g((unsigned)((P.n + kBlock - 1) / kBlock));
     switch (P.dtype) {
     case SPMV_F64:
