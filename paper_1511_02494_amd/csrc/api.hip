@@ -32,7 +32,7 @@ spmv_status_t fail(spmv_status_t st, const char *fmt, ...) {
 }
 
 spmv_status_t fail_hip(hipError_t e, const char *what, const char *file, int line) {
-    hipGetLastError();  // clear the sticky launch error, if any
+    (void)hipGetLastError();  // clear the sticky launch error, if any
     char buf[512];
     snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
     g_err = buf;
@@ -667,11 +667,11 @@ spmv_status_t time_runs(spmv_plan *P, int reps, bool cold,
         if (hipEventRecord(b, S(P)) != hipSuccess) { st = fail(SPMV_ERR_HIP, "event"); break; }
         if (hipEventSynchronize(b) != hipSuccess) { st = fail(SPMV_ERR_HIP, "event sync"); break; }
         float ms = 0.f;
-        hipEventElapsedTime(&ms, a, b);
+        if (hipEventElapsedTime(&ms, a, b) != hipSuccess) { st = fail(SPMV_ERR_HIP, "event time"); break; }
         out->push_back(ms * 1e-3);
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     return st;
 }
 
@@ -1408,17 +1408,17 @@ spmv_status_t spmv_hbm_probe(int64_t bytes, double *read_gbs, double *copy_gbs) 
         SPMV_HIP(launch_read_probe(a.p, (size_t)bytes, sink.as<double>(), nullptr));
         SPMV_HIP(hipEventRecord(e1, nullptr));
         SPMV_HIP(hipEventSynchronize(e1));
-        hipEventElapsedTime(&ms, e0, e1);
+        SPMV_HIP(hipEventElapsedTime(&ms, e0, e1));
         if (r) tr.push_back(ms * 1e-3);
         SPMV_HIP(hipEventRecord(e0, nullptr));
         SPMV_HIP(launch_copy_probe(a.p, b.p, (size_t)bytes, nullptr));
         SPMV_HIP(hipEventRecord(e1, nullptr));
         SPMV_HIP(hipEventSynchronize(e1));
-        hipEventElapsedTime(&ms, e0, e1);
+        SPMV_HIP(hipEventElapsedTime(&ms, e0, e1));
         if (r) tc.push_back(ms * 1e-3);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (read_gbs) *read_gbs = (double)bytes / median(tr) * 1e-9;
     if (copy_gbs) *copy_gbs = 2.0 * (double)bytes / median(tc) * 1e-9;
     return SPMV_OK;

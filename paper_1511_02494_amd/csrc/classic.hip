@@ -330,7 +330,7 @@ spmv_status_t spmv_dtree_fit(const double *X, const int32_t *y, int64_t n, int32
         if (y[i] < 0 || y[i] >= n_classes) return fail(SPMV_ERR_ARG, "label %d out of range", y[i]);
     for (int64_t i = 0; i < n * kNF; ++i)
         if (!(X[i] == X[i])) return fail(SPMV_ERR_ARG, "NaN feature");
-    TreeFit T{X, y, n_classes, max_depth, min_leaf, max_nodes};
+    TreeFit T{X, y, n_classes, max_depth, min_leaf, max_nodes, {}, {}, {}, {}, {}, false};
     std::vector<int32_t> idx(n);
     for (int64_t i = 0; i < n; ++i) idx[i] = (int32_t)i;
     T.grow(idx, 0);

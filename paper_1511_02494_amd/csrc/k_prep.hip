@@ -157,7 +157,8 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
     const int64_t sl0 = r0 / kSellRows;
     const int nsl = (nrows + kSellRows - 1) / kSellRows;
     for (int r = threadIdx.x; r <= nrows; r += kBlock) s_rp[r] = rp[r0 + r];
-    if ((int)threadIdx.x < kWaves) s_kind[threadIdx.x] = threadIdx.x < nsl ? kind[sl0 + threadIdx.x] : 0;
+    if ((int)threadIdx.x < kWaves)
+        s_kind[threadIdx.x] = (int)threadIdx.x < nsl ? kind[sl0 + threadIdx.x] : 0;
     for (int i = threadIdx.x; i < kWaves * kSellMaxDiag; i += kBlock)
         s_dg[i / kSellMaxDiag][i % kSellMaxDiag] =
             i / kSellMaxDiag < nsl ? diag[sl0 * kSellMaxDiag + i] : 0;

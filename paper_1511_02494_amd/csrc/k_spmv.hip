@@ -339,7 +339,7 @@ __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64
 
     // this thread's start on the merge path inside the tile
     const int total = nr + nz;
-    const int d = threadIdx.x * kMergeIpt < total ? threadIdx.x * kMergeIpt : total;
+    const int d = (int)threadIdx.x * kMergeIpt < total ? (int)threadIdx.x * kMergeIpt : total;
     int lo = d - nz > 0 ? d - nz : 0, hi = d < nr ? d : nr;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
