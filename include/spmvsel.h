@@ -20,8 +20,10 @@
  *     default stream).
  *   - CSR input: 0-based int32 indices (the paper's listing is 1-based);
  *     rowptr[0] = 0, rowptr[N] = NNZ, rowptr non-decreasing; columns in
- *     [0, M) and strictly increasing inside each row; NNZ < 2^31.  Empty
- *     rows are allowed (y_i = 0); N = 0 and NNZ = 0 are valid.
+ *     [0, M) and strictly increasing inside each row; N < 2^31 - 1,
+ *     M < 2^31 and NNZ < 2^31 - 2^16 (the kernels step int32 nonzero
+ *     indices up to 2048 past a row's end).  Empty rows are allowed
+ *     (y_i = 0); N = 0 and NNZ = 0 are valid.
  *   - Value dtypes: SPMV_F64 values use double x and y; SPMV_F32 and
  *     SPMV_BF16 values (bfloat16 bit patterns in uint16) use float x and y
  *     with FP32 accumulation, Kahan-compensated on rows of more than 256
@@ -141,7 +143,9 @@ typedef struct {
  * borrows d_rowptr[N+1], d_colind[NNZ] and d_val[NNZ] (dtype val_dtype)
  * until spmv_plan_destroy, unless SPMV_COPY_INPUTS is set.  Derived formats
  * are built lazily and owned by the plan.  Synchronises `stream`.
- * Arrays must be 16-byte aligned.  *out is NULL on failure. */
+ * Arrays must be 16-byte aligned.  Sizes outside the limits above, an
+ * unknown dtype, a NULL or misaligned array return SPMV_ERR_ARG before any
+ * device work.  *out is NULL on failure. */
 spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
                                int64_t nnz, const int32_t *d_rowptr,
                                const int32_t *d_colind, const void *d_val,

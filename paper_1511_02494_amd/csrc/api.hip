@@ -876,8 +876,11 @@ spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
     *out = nullptr;
     if (n_rows < 0 || n_cols < 0 || nnz < 0)
         return fail(SPMV_ERR_ARG, "negative size");
-    if (n_rows >= INT32_MAX || n_cols > INT32_MAX || nnz >= INT32_MAX)
+    if (n_rows >= INT32_MAX || n_cols > INT32_MAX)
         return fail(SPMV_ERR_ARG, "sizes must be below 2^31");
+    // the kernels step int32 nonzero indices up to a chunk (2048) past a
+    // row's or a tile's end, so NNZ keeps that much headroom below 2^31
+    if (nnz >= kMaxNnz) return fail(SPMV_ERR_ARG, "NNZ must be below 2^31 - 2^16");
     if (val_dtype < SPMV_F64 || val_dtype > SPMV_BF16)
         return fail(SPMV_ERR_ARG, "unknown value dtype %d", val_dtype);
     if (!d_rowptr) return fail(SPMV_ERR_ARG, "rowptr is NULL");

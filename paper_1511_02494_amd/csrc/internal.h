@@ -19,6 +19,7 @@ constexpr int kRunLen = 8;            // nonzeros per thread run in the streamin
 constexpr int kChunk = kBlock * kRunLen;  // nonzeros staged per LDS chunk
 constexpr int kRowStreamMaxR = 8;     // rows per thread (max) in short_row / delta16
 constexpr int kMergeIpt = 8;          // merge-path items per thread
+constexpr int64_t kMaxNnz = (1ll << 31) - (1ll << 16);  // NNZ below this: int32 index headroom
 constexpr int kMergeTile = kBlock * kMergeIpt;
 constexpr int kSlices = 8;            // x-block column slices at most (one per XCD)
 constexpr int64_t kSliceXEntries = 256ll << 10;  // x entries per slice the automatic count aims at

@@ -65,7 +65,8 @@ def test_model_file_roundtrip_and_corruption(tmp_path):
 
 
 def test_plan_create_argument_errors():
-    for args in [(-1, 1, 0), (1, -1, 0), (1, 1, -1), (2 ** 31, 1, 0)]:
+    for args in [(-1, 1, 0), (1, -1, 0), (1, 1, -1), (2 ** 31, 1, 0), (2 ** 31 - 1, 1, 0),
+                 (1, 2 ** 31, 0), (1, 1, 2 ** 31 - 2 ** 16), (1, 1, 2 ** 31 - 1)]:
         with pytest.raises(S.SpmvError) as e:
             S.spmv_plan_create(*args, 16, 16, 16, S.SPMV_F64, 0)
         assert e.value.status == S.SPMV_ERR_ARG
