@@ -13,7 +13,8 @@
   share at most 32 diagonals stores those diagonals once and a bit mask per
   row instead of any column data.  A combination of the MB optimisation with
   a GPU storage order, in the spirit of the paper's closing remarks on wider
-  pools and multi-level optimisation.
+  pools and multi-level optimisation.  ``delta16_offset_bits_ref`` takes the
+  paper's other width: 8-bit offsets when every offset slice fits them.
 * ``merge_splits_ref``  start coordinates of the nonzero-balanced merge-path
   tiles (Merrill and Garland, SC'16): the merge of the row-end list
   ``rowptr[1..N]`` with the nonzero indices ``0..NNZ-1``, where nonzero j is
@@ -88,7 +89,8 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
 
     with vals[slot] = a; every other slot (and off[] of diagonal slices)
     holds 0.  Returns a dict with kind, ndiag (|U_s| of diagonal slices, else
-    0), width, base, units (int32[S]), diag
+    0), width, base, units, span (int32[S]; span_s is the largest column of
+    the slice minus base_s, 0 if it has no nonzeros), diag
     (int32[32 S]: U_s zero-padded, zeros for offset slices), mask (uint32[N]:
     0 in offset slices), slots (64 sum w_s), off (int64[slots]; the caller
     checks they fit 16 bits), vals (float64[slots]) and nnz_offset (the
@@ -103,6 +105,7 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
     ndiag = np.zeros(ns, dtype=np.int64)
     width = np.zeros(ns, dtype=np.int64)
     base = np.zeros(ns, dtype=np.int64)
+    span = np.zeros(ns, dtype=np.int64)
     diag = np.zeros(32 * ns, dtype=np.int64)
     diag_sets = []
     for s in range(ns):
@@ -112,6 +115,7 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
         w_off = longest + (longest % 2)
         a, e = rowptr[r0], rowptr[r1]
         base[s] = colind[a:e].min() if a < e else 0
+        span[s] = colind[a:e].max() - base[s] if a < e else 0
         rel = sorted({int(colind[j]) - i for i in range(r0, r1)
                       for j in range(rowptr[i], rowptr[i + 1])})
         d_even = len(rel) + (len(rel) % 2)
@@ -147,8 +151,23 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
     return dict(kind=kind.astype(np.int32), ndiag=ndiag.astype(np.int32),
                 width=width.astype(np.int32),
                 base=base.astype(np.int32), units=units.astype(np.int32),
+                span=span.astype(np.int32),
                 diag=diag.astype(np.int32), mask=mask.astype(np.uint32), slots=slots,
                 off=off, vals=vals, nnz_offset=nnz_offset)
+
+
+def delta16_offset_bits_ref(kind, span, nnz_offset: int) -> int:
+    """Bits per stored offset of the sliced layout (Section 3.3: deltas of 8
+    or 16 bits wherever possible, one width per matrix, never both).
+
+    An offset is c - base_s, from 0 to span_s, so 8 bits hold every offset of
+    the matrix when each offset slice (kind 0) has span_s <= 255.  Then, if
+    the matrix has any offsets to store, the width is 8; otherwise 16.
+    """
+    kind = np.asarray(kind)
+    span = np.asarray(span)
+    fits8 = bool(np.all(span[kind == 0] <= 255))
+    return 8 if fits8 and nnz_offset > 0 else 16
 
 
 def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int, n: int) -> int:

@@ -69,6 +69,7 @@ _PROTOS = {
     "spmv_variant_mask": (_I32, [_P, _PU32]),
     "spmv_set_xblock_slices": (_I32, [_P, _I32]),
     "spmv_set_delta16_layout": (_I32, [_P, _I32]),
+    "spmv_set_delta16_offset_bits": (_I32, [_P, _I32]),
     "spmv_bytes": (_I32, [_P, _I32, _PI64]),
     "spmv_time_variant": (_I32, [_P, _I32, _I32, _I32, _PF64, _PF64]),
     "spmv_plan_query": (_I32, [_P, _I32, _PI64]),
@@ -210,6 +211,10 @@ def spmv_set_delta16_layout(plan, layout: int):
     _check("spmv_set_delta16_layout", lib.spmv_set_delta16_layout(plan, layout))
 
 
+def spmv_set_delta16_offset_bits(plan, bits: int):
+    _check("spmv_set_delta16_offset_bits", lib.spmv_set_delta16_offset_bits(plan, bits))
+
+
 def spmv_variant_mask(plan) -> int:
     b = _U32()
     _check("spmv_variant_mask", lib.spmv_variant_mask(plan, ctypes.byref(b)))
@@ -242,7 +247,10 @@ _FORMAT_DTYPES = {0: np.int32, 1: np.uint16, 2: np.int32, 3: np.int32, 4: np.int
 
 def spmv_plan_copy_format(plan, which: int, count: int, dtype=None) -> np.ndarray:
     """Array ``which`` of the plan's formats; ``dtype`` is required for the
-    sliced delta16 values (12), which have the plan's value type."""
+    sliced delta16 values (12), which have the plan's value type.  The sliced
+    offsets (11) take the plan's offset width (query key 17)."""
+    if dtype is None and which == 11:
+        dtype = np.uint8 if spmv_plan_query(plan, 17) == 8 else np.uint16
     out = np.empty(count, dtype=dtype or _FORMAT_DTYPES[which])
     _check("spmv_plan_copy_format",
            lib.spmv_plan_copy_format(plan, which, out.ctypes.data_as(_P), out.nbytes))
@@ -493,6 +501,9 @@ class Plan:
 
     def set_delta16_layout(self, layout):
         spmv_set_delta16_layout(self.handle, layout)
+
+    def set_delta16_offset_bits(self, bits):
+        spmv_set_delta16_offset_bits(self.handle, bits)
 
     @property
     def variant(self):

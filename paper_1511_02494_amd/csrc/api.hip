@@ -327,13 +327,15 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     SPMV_TRY(P->d16s_kind.alloc(nb));
     SPMV_TRY(P->d16s_diag.alloc(nb * kSellMaxDiag));
     SPMV_TRY(P->d16s_nnz.alloc(nb));
-    DevBuf halfw, tmp;
+    DevBuf halfw, tmp, span;
     SPMV_TRY(halfw.alloc(nb));
-    int64_t units = 0, nnz_off = 0, ndiag = 0;
+    SPMV_TRY(span.alloc(nb));
+    int64_t units = 0, nnz_off = 0, ndiag = 0, max_span = 0;
     if (nsl > 0) {
         SPMV_HIP(launch_sliced_shape(*P, P->d16s_width.as<int32_t>(), halfw.as<int32_t>(),
                                      P->d16s_base.as<int32_t>(), P->d16s_kind.as<int32_t>(),
-                                     P->d16s_diag.as<int32_t>(), P->d16s_nnz.as<int32_t>(), S(P)));
+                                     P->d16s_diag.as<int32_t>(), P->d16s_nnz.as<int32_t>(),
+                                     span.as<int32_t>(), S(P)));
         size_t need = 0;
         int64_t *dtot = scr<int64_t>(P, kOffSum);
         SPMV_HIP(launch_exclusive_scan_i32(halfw.as<int32_t>(), P->d16s_units.as<int32_t>(), nsl, 1,
@@ -342,18 +344,24 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
         SPMV_HIP(launch_exclusive_scan_i32(halfw.as<int32_t>(), P->d16s_units.as<int32_t>(), nsl, 1,
                                            dtot, tmp.p, tmp.bytes, S(P), nullptr));
         SPMV_HIP(hipMemcpyAsync(P->h_pinned, dtot, 8, hipMemcpyDeviceToHost, S(P)));
-        std::vector<int32_t> kinds((size_t)nsl), counts((size_t)nsl);
+        std::vector<int32_t> kinds((size_t)nsl), counts((size_t)nsl), spans((size_t)nsl);
         SPMV_HIP(hipMemcpyAsync(kinds.data(), P->d16s_kind.p, nb, hipMemcpyDeviceToHost, S(P)));
         SPMV_HIP(hipMemcpyAsync(counts.data(), P->d16s_nnz.p, nb, hipMemcpyDeviceToHost, S(P)));
+        SPMV_HIP(hipMemcpyAsync(spans.data(), span.p, nb, hipMemcpyDeviceToHost, S(P)));
         SPMV_TRY(sync(P));
         memcpy(&units, P->h_pinned, 8);
         for (int64_t k = 0; k < nsl; ++k) {
-            if (kinds[k] > 0) ++ndiag;
-            else nnz_off += counts[k];
+            if (kinds[k] > 0) {
+                ++ndiag;
+            } else {
+                nnz_off += counts[k];
+                if (spans[k] > max_span) max_span = spans[k];
+            }
         }
     }
     P->d16_nnz_off = nnz_off;
     P->d16_ndiag = ndiag;
+    P->d16_span = max_span;
     P->d16_nsl = nsl;
     P->d16_slots = units * 2 * kSellRows;
     // the unit offsets are int32 (with NNZ < 2^30 every width is too)
@@ -364,7 +372,17 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     const int automatic = representable && padded_ok ? 1 : 0;
     if (P->d16_layout_req == 1 && !representable)
         return fail(SPMV_ERR_INFEASIBLE, "delta16: the sliced layout needs under 2^31 slot pairs");
-    P->d16_layout = P->d16_layout_req >= 0 ? P->d16_layout_req : automatic;
+    // one offset width for the whole matrix: 8 bits when every offset slice
+    // fits them (and there are offsets at all), else 16
+    const bool fits8 = max_span <= 255;
+    const int layout = P->d16_layout_req >= 0 ? P->d16_layout_req : automatic;
+    if (layout == 1 && P->d16_offw_req == 8 && !fits8)
+        return fail(SPMV_ERR_INFEASIBLE,
+                    "delta16: 8-bit offsets need every offset slice to span at most 256 columns "
+                    "(the widest spans %lld)", (long long)max_span + 1);
+    P->d16_layout = layout;
+    if (layout == 0) P->d16_offw = 16;  // the streamed layout stores 16 bits
+    else P->d16_offw = P->d16_offw_req > 0 ? P->d16_offw_req : (fits8 && nnz_off > 0 ? 8 : 16);
     P->d16s_nnz.release();
     if (P->d16_layout == 0) {
         P->d16s_width.release();
@@ -567,15 +585,16 @@ spmv_status_t build_format(spmv_plan *P, int v) {
         SPMV_TRY(d16_decide_layout(P));
         if (P->d16_layout == 1) {
             const size_t slots = (size_t)P->d16_slots;
-            SPMV_TRY(P->d16s_off.alloc(slots * 2 + 16));
+            const int ob = P->d16_offw / 8;
+            SPMV_TRY(P->d16s_off.alloc(slots * ob + 16));
             SPMV_TRY(P->d16s_val.alloc(slots * vbytes(P->dtype) + 16));
             const size_t mbytes = (size_t)(P->n > 0 ? P->n : 1) * 4;
             SPMV_TRY(P->d16s_mask.alloc(mbytes));
-            SPMV_HIP(hipMemsetAsync(P->d16s_off.p, 0, slots * 2 + 16, S(P)));
+            SPMV_HIP(hipMemsetAsync(P->d16s_off.p, 0, slots * ob + 16, S(P)));
             SPMV_HIP(hipMemsetAsync(P->d16s_val.p, 0, slots * vbytes(P->dtype) + 16, S(P)));
             SPMV_HIP(launch_sliced_scatter(*P, P->d16s_units.as<int32_t>(), P->d16s_base.as<int32_t>(),
                                            P->d16s_kind.as<int32_t>(), P->d16s_diag.as<int32_t>(),
-                                           P->d16s_off.as<uint16_t>(), P->d16s_val.p,
+                                           P->d16s_off.p, ob, P->d16s_val.p,
                                            P->d16s_mask.as<uint32_t>(), S(P)));
             SPMV_TRY(sync(P));
             P->d16_built = true;
@@ -1031,8 +1050,8 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
             // offsets only in offset slices; width, units, base and kind per
             // slice, 32 diagonals per diagonal slice; a row's mask replaces
             // its row pointer in diagonal slices
-            *bytes = 4 * (P->n + 1) + vb * P->nnz + 2 * P->d16_nnz_off + xb * P->m + xb * P->n +
-                     16 * P->d16_nsl + 4 * kSellMaxDiag * P->d16_ndiag;
+            *bytes = 4 * (P->n + 1) + vb * P->nnz + (P->d16_offw / 8) * P->d16_nnz_off +
+                     xb * P->m + xb * P->n + 16 * P->d16_nsl + 4 * kSellMaxDiag * P->d16_ndiag;
             return SPMV_OK;
         }
         extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
@@ -1082,6 +1101,13 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
         *value = P->d16_layout;
         break;
     case 15: SPMV_TRY(d16_decide_layout(P)); *value = P->d16_slots; break;
+    case 17:
+    case 18:
+        SPMV_TRY(check_d16(P));
+        if (!d16_feasible(P)) { *value = -1; break; }
+        SPMV_TRY(d16_decide_layout(P));
+        *value = key == 17 ? P->d16_offw : P->d16_span;
+        break;
     case 10: *value = 1; break;
     default: return fail(SPMV_ERR_ARG, "unknown key %d", key);
     }
@@ -1101,7 +1127,7 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
         case 8: src = P->d16s_width.p; want = 4 * P->d16_nsl; break;
         case 9: src = P->d16s_units.p; want = 4 * P->d16_nsl; break;
         case 10: src = P->d16s_base.p; want = 4 * P->d16_nsl; break;
-        case 11: src = P->d16s_off.p; want = 2 * P->d16_slots; break;
+        case 11: src = P->d16s_off.p; want = (P->d16_offw / 8) * P->d16_slots; break;
         case 12: src = P->d16s_val.p; want = vbytes(P->dtype) * P->d16_slots; break;
         case 13: src = P->d16s_kind.p; want = 4 * P->d16_nsl; break;
         case 14: src = P->d16s_diag.p; want = 4 * kSellMaxDiag * P->d16_nsl; break;
@@ -1375,6 +1401,23 @@ spmv_status_t spmv_set_delta16_layout(spmv_plan_t P, int32_t layout) {
     P->d16s_val.release();
     P->d16s_kind.release();
     P->d16s_diag.release();
+    P->d16s_mask.release();
+    if (P->variant == V_DELTA16) SPMV_TRY(build_format(P, V_DELTA16));  // else on next use
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_set_delta16_offset_bits(spmv_plan_t P, int32_t bits) {
+    clear_error();
+    if (!P) return fail(SPMV_ERR_ARG, "NULL plan");
+    if (bits != 0 && bits != 8 && bits != 16)
+        return fail(SPMV_ERR_ARG, "delta16 offset bits must be 0 (automatic), 8 or 16, not %d", bits);
+    if (bits == P->d16_offw_req) return SPMV_OK;
+    SPMV_TRY(sync(P));
+    P->d16_offw_req = bits;
+    P->d16_layout = -1;  // decided again, with the new width
+    P->d16_built = false;
+    P->d16s_off.release();
+    P->d16s_val.release();
     P->d16s_mask.release();
     if (P->variant == V_DELTA16) SPMV_TRY(build_format(P, V_DELTA16));  // else on next use
     return SPMV_OK;

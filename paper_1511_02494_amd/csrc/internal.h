@@ -113,6 +113,11 @@ struct spmv_plan {
     // slices stored column-major in pairs, one reference column per slice)
     int d16_layout = -1;         // -1: not decided yet
     int d16_layout_req = -1;     // forced layout, -1 automatic
+    // bits per stored offset in the sliced layout: 8 when every offset
+    // slice spans at most 256 columns, else 16 (one width per matrix)
+    int d16_offw = 16;
+    int d16_offw_req = 0;        // forced width, 0 automatic
+    int64_t d16_span = 0;        // largest column span of an offset slice
     int64_t d16_nsl = 0, d16_slots = 0;
     int64_t d16_nnz_off = 0, d16_ndiag = 0;  // nonzeros of offset slices; diagonal slices
     spmvsel::DevBuf d16s_width, d16s_units, d16s_base, d16s_off, d16s_val;
@@ -190,9 +195,11 @@ hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16
 // diag[32 s ..] (kind = 1 + D) and sets bit k of a row's mask for each
 // diagonal k the row has; its positions follow the diagonals, not the row.
 hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
-                               int32_t *kind, int32_t *diag, int32_t *snnz, hipStream_t s);
+                               int32_t *kind, int32_t *diag, int32_t *snnz, int32_t *span,
+                               hipStream_t s);
+// off holds uint8 offsets when off_bytes is 1, uint16 when it is 2
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
-                                 const int32_t *kind, const int32_t *diag, uint16_t *off,
+                                 const int32_t *kind, const int32_t *diag, void *off, int off_bytes,
                                  void *vals, uint32_t *mask, hipStream_t s);
 hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t panels,
                            unsigned long long *d_max, hipStream_t s);

@@ -53,7 +53,8 @@ __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
                                                          int32_t *__restrict__ base,
                                                          int32_t *__restrict__ kind,
                                                          int32_t *__restrict__ diag,
-                                                         int32_t *__restrict__ snnz) {
+                                                         int32_t *__restrict__ snnz,
+                                                         int32_t *__restrict__ span) {
     constexpr int kWaves = kBlock / kSellRows;
     __shared__ int32_t s_ci[kWaves][kSellRows * kSellMaxDiag];  // a slice's nonzeros
     const int wv = threadIdx.x / kSellRows;
@@ -67,13 +68,16 @@ __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
         e = rp[r + 1];
     }
     int len = e - a, first = len > 0 ? ci[a] : INT32_MAX, cnt = len;
+    int last = len > 0 ? ci[e - 1] : -1;  // columns increase along a row
 #pragma unroll
     for (int d = kSellRows / 2; d > 0; d >>= 1) {
         const int ol = __shfl_xor(len, d, kSellRows);
         const int of = __shfl_xor(first, d, kSellRows);
+        const int oz = __shfl_xor(last, d, kSellRows);
         cnt += __shfl_xor(cnt, d, kSellRows);
         len = ol > len ? ol : len;
         first = of < first ? of : first;
+        last = oz > last ? oz : last;
     }
     const int w_off = len + (len & 1);
     // A slice with a row longer than 32 has more than 32 diagonals.  Else its
@@ -116,16 +120,18 @@ __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
         base[sl] = first == INT32_MAX ? 0 : first;
         kind[sl] = is_diag ? 1 + D : 0;
         snnz[sl] = cnt;
+        span[sl] = cnt > 0 ? last - first : 0;  // largest offset c - base
     }
 }
 
 hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
-                               int32_t *kind, int32_t *diag, int32_t *snnz, hipStream_t s) {
+                               int32_t *kind, int32_t *diag, int32_t *snnz, int32_t *span,
+                               hipStream_t s) {
     const int64_t nsl = (P.n + kSellRows - 1) / kSellRows;
     if (nsl == 0) return hipSuccess;
     const int64_t per = kBlock / kSellRows;
     hipLaunchKernelGGL(k_sliced_shape, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0, s,
-                       P.n, nsl, P.rowptr, P.colind, width, halfw, base, kind, diag, snnz);
+                       P.n, nsl, P.rowptr, P.colind, width, halfw, base, kind, diag, snnz, span);
     return hipGetLastError();
 }
 
@@ -136,7 +142,7 @@ hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *half
 // among the slice's (in LDS) by a binary search, writes its value to that
 // position and sets the diagonal's bit in the row's mask (LDS atomics; the
 // masks are stored once at the end, zero for rows of offset slices).
-template <class V>
+template <class V, class O>
 __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
                                                            const V *__restrict__ val,
@@ -144,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
                                                            const int32_t *__restrict__ base,
                                                            const int32_t *__restrict__ kind,
                                                            const int32_t *__restrict__ diag,
-                                                           uint16_t *__restrict__ off,
+                                                           O *__restrict__ off,
                                                            V *__restrict__ vals,
                                                            uint32_t *__restrict__ mask) {
     constexpr int kWaves = kBlock / kSellRows;
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
             atomicOr(&s_mask[lo], 1u << k);
         } else {
             off[2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1)] =
-                (uint16_t)(ci[j] - base[sl]);
+                (O)(ci[j] - base[sl]);
         }
         vals[2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1)] = val[j];
     }
@@ -196,23 +202,25 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
 }
 
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
-                                 const int32_t *kind, const int32_t *diag, uint16_t *off,
+                                 const int32_t *kind, const int32_t *diag, void *off, int off_bytes,
                                  void *vals, uint32_t *mask, hipStream_t s) {
     if (P.n == 0) return hipSuccess;  // (with no nonzeros it still writes the zero masks)
+    if (off_bytes != 1 && off_bytes != 2) return hipErrorInvalidValue;
     const dim3 g((unsigned)((P.n + kBlock - 1) / kBlock));
+    auto go = [&](auto vtag, auto otag) {
+        using V = std::remove_pointer_t<decltype(vtag)>;
+        using O = std::remove_pointer_t<decltype(otag)>;
+        hipLaunchKernelGGL((k_sliced_scatter<V, O>), g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
+                           (const V *)P.val, units, base, kind, diag, (O *)off, (V *)vals, mask);
+    };
+    auto by_off = [&](auto vtag) {
+        if (off_bytes == 1) go(vtag, (uint8_t *)nullptr);
+        else go(vtag, (uint16_t *)nullptr);
+    };
     switch (P.dtype) {
-    case SPMV_F64:
-        hipLaunchKernelGGL(k_sliced_scatter<double>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
-                           (const double *)P.val, units, base, kind, diag, off, (double *)vals, mask);
-        break;
-    case SPMV_F32:
-        hipLaunchKernelGGL(k_sliced_scatter<float>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
-                           (const float *)P.val, units, base, kind, diag, off, (float *)vals, mask);
-        break;
-    default:
-        hipLaunchKernelGGL(k_sliced_scatter<uint16_t>, g, dim3(kBlock), 0, s, P.n, P.rowptr,
-                           P.colind, (const uint16_t *)P.val, units, base, kind, diag, off,
-                           (uint16_t *)vals, mask);
+    case SPMV_F64: by_off((double *)nullptr); break;
+    case SPMV_F32: by_off((float *)nullptr); break;
+    default: by_off((uint16_t *)nullptr);
     }
     return hipGetLastError();
 }

@@ -78,6 +78,7 @@ template <class T> struct Pair;
 template <> struct Pair<double> { typedef double type __attribute__((ext_vector_type(2))); };
 template <> struct Pair<float> { typedef float type __attribute__((ext_vector_type(2))); };
 template <> struct Pair<uint16_t> { typedef unsigned short type __attribute__((ext_vector_type(2))); };
+template <> struct Pair<uint8_t> { typedef unsigned char type __attribute__((ext_vector_type(2))); };
 template <> struct Pair<int32_t> { typedef int type __attribute__((ext_vector_type(2))); };
 
 template <class V, bool D16, int R, bool STAGE>
@@ -187,8 +188,10 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
 }
 
 // ============================================================ delta16, sliced
-// The sliced layout of the 16-bit offsets (slices of 64 rows, one row per
-// lane, nonzeros stored column-major in pairs; see k_sliced_scatter).  Lane l
+// The sliced layout of the offsets (slices of 64 rows, one row per lane,
+// nonzeros stored column-major in pairs; see k_sliced_scatter), O = uint16_t,
+// or uint8_t where every offset slice of the matrix spans at most 256
+// columns (one width per matrix, as the paper's deltas).  Lane l
 // of the wavefront of slice s sums its row in column order from +0, so FP64
 // results equal the sequential sum bit for bit.  Each step loads two pairs per
 // lane (a wavefront load is 64 consecutive pairs, coalesced), then gathers
@@ -196,17 +199,17 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
 // Every lane loads every pair up to the slice width (padding slots hold zero
 // offsets, so their gathers stay in range); products past the row's end are
 // dropped, which keeps the loads free of branches.
-template <class V>
+template <class V, class O>
 __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     int64_t n, int64_t m, int64_t nsl, const int32_t *__restrict__ rp,
     const int32_t *__restrict__ width, const int32_t *__restrict__ units,
     const int32_t *__restrict__ base, const int32_t *__restrict__ kind,
     const int32_t *__restrict__ diag, const uint32_t *__restrict__ mask,
-    const uint16_t *__restrict__ off, const V *__restrict__ val,
+    const O *__restrict__ off, const V *__restrict__ val,
     const typename VT<V>::A *__restrict__ x, typename VT<V>::A *__restrict__ y) {
     using A = typename VT<V>::A;
     using VP = typename Pair<V>::type;
-    using OP = typename Pair<uint16_t>::type;
+    using OP = typename Pair<O>::type;
     const int64_t sl = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kSellRows) +
                        __builtin_amdgcn_readfirstlane(threadIdx.x / kSellRows);
     if (sl >= nsl) return;  // whole wavefronts leave together
@@ -795,16 +798,26 @@ hipError_t phased_geometry(const spmv_plan &P, int *J, int64_t *G) {
 
 hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
     if (P.n == 0) return hipSuccess;
+    if (P.d16_offw != 8 && P.d16_offw != 16) return hipErrorInvalidValue;
     return by_dtype(P.dtype, [&](auto tag) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
         using A = typename VT<V>::A;
         const int64_t per = kBlock / kSellRows;
         const unsigned g = (unsigned)((P.d16_nsl + per - 1) / per);
-        hipLaunchKernelGGL((k_sliced_d16<V>), dim3(g), dim3(kBlock), 0, s, P.n, P.m, P.d16_nsl,
-                           P.rowptr, P.d16s_width.as<int32_t>(), P.d16s_units.as<int32_t>(),
-                           P.d16s_base.as<int32_t>(), P.d16s_kind.as<int32_t>(),
-                           P.d16s_diag.as<int32_t>(), P.d16s_mask.as<uint32_t>(),
-                           P.d16s_off.as<uint16_t>(), P.d16s_val.as<V>(), (const A *)x, (A *)y);
+        if (P.d16_offw == 8)
+            hipLaunchKernelGGL((k_sliced_d16<V, uint8_t>), dim3(g), dim3(kBlock), 0, s, P.n, P.m,
+                               P.d16_nsl, P.rowptr, P.d16s_width.as<int32_t>(),
+                               P.d16s_units.as<int32_t>(), P.d16s_base.as<int32_t>(),
+                               P.d16s_kind.as<int32_t>(), P.d16s_diag.as<int32_t>(),
+                               P.d16s_mask.as<uint32_t>(), P.d16s_off.as<uint8_t>(),
+                               P.d16s_val.as<V>(), (const A *)x, (A *)y);
+        else
+            hipLaunchKernelGGL((k_sliced_d16<V, uint16_t>), dim3(g), dim3(kBlock), 0, s, P.n, P.m,
+                               P.d16_nsl, P.rowptr, P.d16s_width.as<int32_t>(),
+                               P.d16s_units.as<int32_t>(), P.d16s_base.as<int32_t>(),
+                               P.d16s_kind.as<int32_t>(), P.d16s_diag.as<int32_t>(),
+                               P.d16s_mask.as<uint32_t>(), P.d16s_off.as<uint16_t>(),
+                               P.d16s_val.as<V>(), (const A *)x, (A *)y);
         return hipGetLastError();
     });
 }

@@ -6,9 +6,9 @@ import pytest
 
 import synth
 import paper_1511_02494_amd as S
-from oracle.encode import (delta16_layout_ref, delta16_ref, delta16_sliced_ref, merge_search_ref,
-                           merge_walk_ref, partition_ref, xblock_split_ref, to_bf16_bits_ref,
-                           to_f32_ref)
+from oracle.encode import (delta16_layout_ref, delta16_offset_bits_ref, delta16_ref,
+                           delta16_sliced_ref, merge_search_ref, merge_walk_ref, partition_ref,
+                           xblock_split_ref, to_bf16_bits_ref, to_f32_ref)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -20,6 +20,8 @@ MATS = [
     ("shortrows", lambda: synth.short_rows(20000, seed=3), 20000),
     ("banded", lambda: synth.banded(6000, 300, 200, seed=4), 6000),
     ("stencil27", lambda: synth.stencil3d_27(16), 4096),
+    # rows of 30..65 nonzeros inside a 65-column band: 8-bit offsets
+    ("narrowband", lambda: synth.banded(6000, 960, 32, seed=5), 6000),
 ]
 
 
@@ -45,8 +47,9 @@ def test_formats_match_oracle(name, build, m):
         S.spmv_set_delta16_layout(h, 1)
         check_sliced(h, L, np.float64)
         # compulsory bytes: no offsets in diagonal slices, their diagonals once
-        want = (4 * (n + 1) + 8 * nnz + 2 * L["nnz_offset"] + 8 * m + 8 * n + 16 * len(L["width"])
-                + 128 * int(np.count_nonzero(L["kind"])))
+        bits = delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"])
+        want = (4 * (n + 1) + 8 * nnz + bits // 8 * L["nnz_offset"] + 8 * m + 8 * n
+                + 16 * len(L["width"]) + 128 * int(np.count_nonzero(L["kind"])))
         assert S.spmv_bytes(h, S.V_DELTA16) == want
     else:
         assert S.spmv_plan_query(h, 14) == -1
@@ -75,8 +78,13 @@ def test_formats_match_oracle(name, build, m):
     plan.close()
 
 
-def check_sliced(h, L, vdtype):
+def check_sliced(h, L, vdtype, bits=None):
     ns = len(L["width"])
+    if bits is None:
+        bits = delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"])
+    assert S.spmv_plan_query(h, 17) == bits
+    spans = L["span"][L["kind"] == 0]
+    assert S.spmv_plan_query(h, 18) == (int(spans.max()) if len(spans) else 0)
     kinds = S.spmv_plan_copy_format(h, 13, ns)
     assert np.array_equal(kinds, np.where(L["kind"] > 0, 1 + L["ndiag"], 0))
     assert np.array_equal(S.spmv_plan_copy_format(h, 14, 32 * ns), L["diag"])
@@ -84,8 +92,10 @@ def check_sliced(h, L, vdtype):
     assert np.array_equal(S.spmv_plan_copy_format(h, 8, ns), L["width"])
     assert np.array_equal(S.spmv_plan_copy_format(h, 9, ns), L["units"])
     assert np.array_equal(S.spmv_plan_copy_format(h, 10, ns), L["base"])
-    assert np.all(L["off"] < 65536)
-    assert np.array_equal(S.spmv_plan_copy_format(h, 11, L["slots"]), L["off"].astype(np.uint16))
+    assert np.all(L["off"] < (1 << bits))
+    odt = np.uint8 if bits == 8 else np.uint16
+    got = S.spmv_plan_copy_format(h, 11, L["slots"])
+    assert got.dtype == odt and np.array_equal(got, L["off"].astype(odt))
     got = S.spmv_plan_copy_format(h, 12, L["slots"], vdtype)
     assert np.array_equal(got, L["vals"].astype(vdtype))
 
@@ -105,6 +115,44 @@ def test_delta16_sliced_low_precision_values(dtype):
         L = delta16_sliced_ref(rp, ci, bits.astype(np.float64))  # bit patterns as numbers
         L["vals"] = L["vals"].astype(np.uint16)
         check_sliced(plan.handle, L, np.uint16)
+    plan.close()
+
+
+def test_delta16_offset_bits_forced():
+    """8 bits where every offset slice fits them, 16 when forced (the same
+    offsets, wider), and 8 refused where a slice spans more."""
+    rp, ci, v = synth.banded(6000, 960, 32, seed=5)
+    L = delta16_sliced_ref(rp, ci, v)
+    assert delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"]) == 8
+    plan = make_plan(rp, ci, v, 6000)
+    h = plan.handle
+    assert S.spmv_plan_query(h, 14) == 1
+    b8 = S.spmv_bytes(h, S.V_DELTA16)
+    check_sliced(h, L, np.float64)
+    S.spmv_set_delta16_offset_bits(h, 16)
+    check_sliced(h, L, np.float64, bits=16)
+    assert S.spmv_bytes(h, S.V_DELTA16) == b8 + L["nnz_offset"]
+    S.spmv_set_delta16_offset_bits(h, 8)
+    check_sliced(h, L, np.float64, bits=8)
+    with pytest.raises(S.SpmvError) as e:
+        S.spmv_set_delta16_offset_bits(h, 4)
+    assert e.value.status == S.SPMV_ERR_ARG
+    plan.close()
+    rp, ci, v = synth.banded(6000, 300, 200, seed=4)  # offset slices span about 460 columns
+    L = delta16_sliced_ref(rp, ci, v)
+    plan = make_plan(rp, ci, v, 6000)
+    h = plan.handle
+    S.spmv_set_delta16_layout(h, 1)
+    assert S.spmv_plan_query(h, 17) == 16
+    S.spmv_set_delta16_offset_bits(h, 8)
+    with pytest.raises(S.SpmvError) as e:
+        S.spmv_plan_query(h, 17)
+    assert e.value.status == S.SPMV_ERR_INFEASIBLE
+    with pytest.raises(S.SpmvError) as e:
+        S.spmv_set_variant(h, S.V_DELTA16)
+    assert e.value.status == S.SPMV_ERR_INFEASIBLE
+    S.spmv_set_delta16_offset_bits(h, 0)
+    check_sliced(h, L, np.float64)
     plan.close()
 
 

@@ -4,6 +4,7 @@ import pytest
 
 import synth
 import paper_1511_02494_amd as S
+from oracle.encode import delta16_offset_bits_ref, delta16_sliced_ref
 from oracle.spmv import spmv_exact, spmv_seq, within_tolerance
 
 pytestmark = pytest.mark.gpu
@@ -45,6 +46,7 @@ CASES = {
     "powerlaw_20000": (lambda v: synth.powerlaw(20000, 109, 6000, seed=5, values=v), 20000),
     "shortrows_5000": (lambda v: synth.short_rows(5000, seed=6, values=v), 5000),
     "banded_4000": (lambda v: synth.banded(4000, 160, 40, seed=7, values=v), 4000),
+    "narrowband_3000": (lambda v: synth.banded(3000, 960, 32, seed=8, values=v), 3000),
     "ragged": (lambda v: ragged(values=v), 4000),
     "one_long_row": (lambda v: one_long_row(values=v), 100_000),
     "empty_rows": (lambda v: empty_rows_mix(), 200),
@@ -84,7 +86,7 @@ def test_variants_within_tolerance(case, dtype):
 
 @pytest.mark.parametrize("dtype", [S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16])
 @pytest.mark.parametrize("case", ["laplace64", "stencil27_12", "random_3000x8", "shortrows_5000",
-                                  "banded_4000", "ragged", "empty_rows"])
+                                  "banded_4000", "narrowband_3000", "ragged", "empty_rows"])
 def test_delta16_both_layouts(case, dtype):
     """delta16 rows streamed and sliced: FP64 in Algorithm 1's order bit for
     bit, FP32/BF16 (Kahan on the ragged case's rows above 256) within
@@ -117,6 +119,32 @@ def test_delta16_both_layouts(case, dtype):
         S.spmv_set_delta16_layout(plan.handle, layout)
         assert np.array_equal(run(plan, S.V_DELTA16, xi, dtype), yi_seq), layout
         plan.close()
+
+
+@pytest.mark.parametrize("dtype", [S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16])
+@pytest.mark.parametrize("case", ["narrowband_3000", "empty_rows", "banded_4000", "random_3000x8"])
+def test_delta16_offset_widths_agree(case, dtype):
+    """8- and 16-bit offsets store the same offsets, so the kernels gather the
+    same x entries and sum in the same order: identical results."""
+    build, m = CASES[case]
+    rp, ci, v = build("random")
+    x = synth.vector(m, 19)
+    y_ref, scale = spmv_exact(rp, ci, v, x)
+    plan = make_plan(rp, ci, v, m, dtype)
+    S.spmv_set_delta16_layout(plan.handle, 1)
+    y_auto = run(plan, S.V_DELTA16, x, dtype)
+    bits = S.spmv_plan_query(plan.handle, 17)
+    print(f"case={case} dtype={dtype} automatic offset bits={bits}", flush=True)
+    L = delta16_sliced_ref(rp, ci, v)
+    assert bits == delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"])
+    assert bits == (16 if case == "random_3000x8" else 8)
+    assert within_tolerance(y_auto, y_ref, scale, TOL[dtype])[0]
+    S.spmv_set_delta16_offset_bits(plan.handle, 16)
+    assert np.array_equal(run(plan, S.V_DELTA16, x, dtype), y_auto)
+    if bits == 8:
+        S.spmv_set_delta16_offset_bits(plan.handle, 8)
+        assert np.array_equal(run(plan, S.V_DELTA16, x, dtype), y_auto)
+    plan.close()
 
 
 def test_delta16_layout_change_rebuilds():

@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 
 import synth
-from oracle.encode import (bf16_bits_to_f64, delta16_layout_ref, delta16_ref,
-                           delta16_sliced_ref, merge_search_ref, merge_walk_ref,
+from oracle.encode import (bf16_bits_to_f64, delta16_layout_ref, delta16_offset_bits_ref,
+                           delta16_ref, delta16_sliced_ref, merge_search_ref, merge_walk_ref,
                            partition_ref, slice_csr_ref, to_bf16_bits_ref, to_f32_ref)
 from oracle.spmv import spmv_seq
 
@@ -113,6 +113,51 @@ def test_delta16_sliced_layout_rule():
     L = delta16_sliced_ref(rp[:71], ci[:27 * 70], np.ones(27 * 70))
     assert L["slots"] == 64 * 56
     assert delta16_layout_ref(True, L["slots"], 27 * 70, 70) == 0
+
+
+def dense_band(n, w):
+    """Row i holds every column of [i - w, i + w] inside [0, n)."""
+    cols = [np.arange(max(0, i - w), min(n, i + w + 1)) for i in range(n)]
+    rp = np.concatenate([[0], np.cumsum([len(c) for c in cols])])
+    return rp, np.concatenate(cols)
+
+
+@pytest.mark.parametrize("w, bits", [(96, 8), (97, 16), (20, 8)])
+def test_delta16_offset_bits_dense_band(w, bits):
+    """A dense band of half-width w has 2w + 1 > 32 diagonals, so every slice
+    stores offsets.  Slice s spans from max(0, 64 s - w) to
+    min(n - 1, 64 s + 63 + w); inside the matrix that is 2 w + 63 columns
+    apart, which fits 8-bit offsets up to w = 96.  There the offset of the
+    k-th nonzero of lane l is l + k (column 64 s + l - w + k)."""
+    n = 640
+    rp, ci = dense_band(n, w)
+    L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
+    ns = n // 64
+    assert L["kind"].tolist() == [0] * ns
+    span = [min(n - 1, 64 * s + 63 + w) - max(0, 64 * s - w) for s in range(ns)]
+    assert L["span"].tolist() == span
+    assert delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"]) == bits
+    for s in range(ns):
+        if 64 * s - w < 0 or 64 * s + 63 + w > n - 1:
+            continue  # clipped at the matrix edge
+        for lane in range(64):
+            for k in range(2 * w + 1):
+                slot = 128 * L["units"][s] + 128 * (k // 2) + 2 * lane + k % 2
+                assert L["off"][slot] == lane + k
+
+
+def test_delta16_offset_bits_rule():
+    # no offset slices at all (a tridiagonal matrix: 3 diagonals): 16 bits
+    rp, ci = dense_band(200, 1)
+    L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
+    assert L["nnz_offset"] == 0 and delta16_offset_bits_ref(L["kind"], L["span"], 0) == 16
+    # diagonal slices do not count: a slice may span far more than 256 columns
+    # if it stores diagonals
+    kind = np.array([1, 0, 3])
+    assert delta16_offset_bits_ref(kind, np.array([100000, 255, 70000]), 5) == 8
+    assert delta16_offset_bits_ref(kind, np.array([0, 256, 0]), 5) == 16
+    # an empty offset slice spans 0
+    assert delta16_offset_bits_ref(np.array([0, 0]), np.array([0, 17]), 3) == 8
 
 
 def test_delta16_sliced_places_every_nonzero_once():
