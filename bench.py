@@ -127,74 +127,80 @@ def precision_report(S, torch, dev, mats, per, log):
 
 
 def offset_width_report(S, torch, dev, log, scale=1):
-    """delta16 (sliced) with 8-bit against 16-bit column offsets (the paper's
-    two delta widths, one per matrix) on a narrow band: 2M rows of 30..65
-    nonzeros inside a 65-column band (generator family banded, d = 60,
-    W = 32), so every slice stores offsets and each spans 127 columns.  FP64,
+    """delta16 (sliced) with 8-bit delta codes against 16-bit offsets (the
+    paper's two delta widths, one per matrix) on two bands of 2M rows with
+    30..90 nonzeros per row (generator family banded, d = 60): half width 32
+    (rows capped at 65; slices span 127 columns, so 16-bit offsets would also
+    fit 8 bits) and half width 200 (slices span about 460 columns; only the
+    delta codes fit 8 bits), the sliced layout forced on the second.  FP64,
     FP32 and BF16 values; warm and cold time, algorithmic bytes and GB/s of
     each width, whether both give the same y, and max_i |y_i - y64_i| /
     sum_j |a_ij| |x_j| against the library's FP64 sequential CSR result."""
     n = 2_000_000 // scale
-    prm = [n, 960, 32]
-    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
-    nnz = S.spmv_generate(S.FAMILY["banded"], prm, 9, rp)
-    ci = torch.empty(nnz + 8, dtype=torch.int32, device=dev)
-    val = torch.empty(nnz + 8, dtype=torch.float64, device=dev)
-    S.spmv_generate(S.FAMILY["banded"], prm, 9, rp, ci, val)
-    x = torch.empty(n, dtype=torch.float64, device=dev)
-    S.spmv_generate_vector(n, 10, x)
-    p64 = S.Plan(rp, ci, val, n, nnz=nnz)
-    p64.set_variant(S.V_CSR_SCALAR)
-    y64 = torch.empty(n, dtype=torch.float64, device=dev)
-    p64.execute(x, y64)
-    p64.close()
-    pa = S.Plan(rp, ci, val.abs(), n, nnz=nnz)
-    pa.set_variant(S.V_CSR_SCALAR)
-    scale_v = torch.empty(n, dtype=torch.float64, device=dev)
-    pa.execute(x.abs(), scale_v)
-    torch.cuda.synchronize()
-    pa.close()
-    name = f"band_{n}_d60_w32"
     out = []
-    for dt, dname, tdt in ((S.SPMV_F64, "f64", torch.float64), (S.SPMV_F32, "f32", torch.float32),
-                           (S.SPMV_BF16, "bf16", torch.int16)):
-        if dt == S.SPMV_F64:
-            v = val
-        else:
-            v = torch.empty(nnz + 16, dtype=tdt, device=dev)
-            S.spmv_quantize(val, v, nnz, dt)
-        plan = S.Plan(rp, ci, v, n, dt, nnz=nnz)
-        h = plan.handle
-        xin = x if dt == S.SPMV_F64 else x.float()
-        r = dict(matrix=name, n=n, nnz=nnz, values=dname, layout=S.spmv_plan_query(h, 14),
-                 span=S.spmv_plan_query(h, 18))
-        ys = []
-        for req in (0, 16):
-            S.spmv_set_delta16_offset_bits(h, req)
-            bits = S.spmv_plan_query(h, 17)
-            t, _ = plan.time(S.V_DELTA16, reps=20)
-            tc, _ = plan.time(S.V_DELTA16, reps=10, cold=True)
-            by = plan.bytes(S.V_DELTA16)
-            plan.set_variant(S.V_DELTA16)
-            y = torch.empty(n, dtype=torch.float64 if dt == S.SPMV_F64 else torch.float32, device=dev)
-            plan.execute(xin, y)
-            torch.cuda.synchronize()
-            ys.append(y)
-            r[f"bits{bits}"] = dict(us=t * 1e6, cold_us=tc * 1e6, bytes=by, gbs=by / t * 1e-9,
-                                    cold_gbs=by / tc * 1e-9)
-        err = (ys[0].double() - y64).abs()
-        rel = torch.where(scale_v > 0, err / scale_v.clamp_min(1e-300), err)
-        r["same_y"] = bool(torch.equal(ys[0], ys[1]))
-        r["max_rel_err"] = float(rel.max())
-        out.append(r)
-        b8, b16 = r.get("bits8"), r.get("bits16")
-        if b8 and b16:
-            log(f"  offsets {name} {dname:>4s}: 8-bit {b8['us']:7.1f} us (cold {b8['cold_us']:6.1f}, "
-                f"{b8['bytes'] / 1e6:.0f} MB)  16-bit {b16['us']:7.1f} us (cold {b16['cold_us']:6.1f}, "
-                f"{b16['bytes'] / 1e6:.0f} MB)  same y {r['same_y']}  max err {r['max_rel_err']:.2e}")
-        plan.close()
-        if dt != S.SPMV_F64:
-            del v
+    for w in (32, 200):
+        prm = [n, 960, w]
+        rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        nnz = S.spmv_generate(S.FAMILY["banded"], prm, 9, rp)
+        ci = torch.empty(nnz + 8, dtype=torch.int32, device=dev)
+        val = torch.empty(nnz + 8, dtype=torch.float64, device=dev)
+        S.spmv_generate(S.FAMILY["banded"], prm, 9, rp, ci, val)
+        x = torch.empty(n, dtype=torch.float64, device=dev)
+        S.spmv_generate_vector(n, 10, x)
+        p64 = S.Plan(rp, ci, val, n, nnz=nnz)
+        p64.set_variant(S.V_CSR_SCALAR)
+        y64 = torch.empty(n, dtype=torch.float64, device=dev)
+        p64.execute(x, y64)
+        p64.close()
+        pa = S.Plan(rp, ci, val.abs(), n, nnz=nnz)
+        pa.set_variant(S.V_CSR_SCALAR)
+        scale_v = torch.empty(n, dtype=torch.float64, device=dev)
+        pa.execute(x.abs(), scale_v)
+        torch.cuda.synchronize()
+        pa.close()
+        name = f"band_{n}_d60_w{w}"
+        for dt, dname, tdt in ((S.SPMV_F64, "f64", torch.float64), (S.SPMV_F32, "f32", torch.float32),
+                               (S.SPMV_BF16, "bf16", torch.int16)):
+            if dt == S.SPMV_F64:
+                v = val
+            else:
+                v = torch.empty(nnz + 16, dtype=tdt, device=dev)
+                S.spmv_quantize(val, v, nnz, dt)
+            plan = S.Plan(rp, ci, v, n, dt, nnz=nnz)
+            h = plan.handle
+            auto_layout = S.spmv_plan_query(h, 14)
+            S.spmv_set_delta16_layout(h, 1)
+            xin = x if dt == S.SPMV_F64 else x.float()
+            r = dict(matrix=name, n=n, nnz=nnz, values=dname, automatic_layout=auto_layout,
+                     span=S.spmv_plan_query(h, 18), automatic_bits=S.spmv_plan_query(h, 17))
+            ys = []
+            for req in (8, 16):
+                S.spmv_set_delta16_offset_bits(h, req)
+                t, _ = plan.time(S.V_DELTA16, reps=20)
+                tc, _ = plan.time(S.V_DELTA16, reps=10, cold=True)
+                by = plan.bytes(S.V_DELTA16)
+                plan.set_variant(S.V_DELTA16)
+                y = torch.empty(n, dtype=torch.float64 if dt == S.SPMV_F64 else torch.float32,
+                                device=dev)
+                plan.execute(xin, y)
+                torch.cuda.synchronize()
+                ys.append(y)
+                r[f"bits{req}"] = dict(us=t * 1e6, cold_us=tc * 1e6, bytes=by, gbs=by / t * 1e-9,
+                                       cold_gbs=by / tc * 1e-9, escapes=S.spmv_plan_query(h, 20))
+            err = (ys[0].double() - y64).abs()
+            rel = torch.where(scale_v > 0, err / scale_v.clamp_min(1e-300), err)
+            r["same_y"] = bool(torch.equal(ys[0], ys[1]))
+            r["max_rel_err"] = float(rel.max())
+            out.append(r)
+            b8, b16 = r["bits8"], r["bits16"]
+            log(f"  codes {name} {dname:>4s} (auto {r['automatic_bits']} bits): 8-bit {b8['us']:7.1f} us "
+                f"(cold {b8['cold_us']:6.1f}, {b8['bytes'] / 1e6:.0f} MB, {b8['escapes']} escapes)  "
+                f"16-bit {b16['us']:7.1f} us (cold {b16['cold_us']:6.1f}, {b16['bytes'] / 1e6:.0f} MB)  "
+                f"same y {r['same_y']}  max err {r['max_rel_err']:.2e}")
+            plan.close()
+            if dt != S.SPMV_F64:
+                del v
+        del rp, ci, val, x, y64, scale_v
     return out
 
 

@@ -72,10 +72,11 @@ typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
  *              average 16 nonzeros or more (stencils, rows of nearly equal
  *              length); a slice whose rows use at most 32 diagonals c - r
  *              stores those diagonals once and a bit mask per row, and no
- *              column data at all.  The sliced layout's offsets take 8 bits
- *              when every offset slice spans at most 256 columns, else 16:
- *              one width per matrix, never both (Section 3.3;
- *              spmv_set_delta16_offset_bits).
+ *              column data at all.  The sliced layout's other slices store
+ *              16-bit offsets from the slice's reference column or 8-bit
+ *              deltas from the row's previous column, code 255 escaping to
+ *              the full column: one width per matrix, never both
+ *              (Section 3.3; spmv_set_delta16_offset_bits).
  *  XBLOCK_LDS  x blocking (class CML; replaces software prefetching of x):
  *              the columns are cut into S <= 8 slices (spmv_set_xblock_slices),
  *              each stored as its own CSR and run on the XCDs that take that
@@ -216,15 +217,21 @@ spmv_status_t spmv_set_xblock_slices(spmv_plan_t plan, int32_t slices);
  * value; building reports SPMV_ERR_INFEASIBLE as for the variant. */
 spmv_status_t spmv_set_delta16_layout(spmv_plan_t plan, int32_t layout);
 
-/* Offset width of the sliced DELTA16 layout, the same for every offset
- * slice of the matrix (Section 3.3 uses 8- or 16-bit deltas, never both):
- * 0 (default) takes 8 bits when every offset slice's columns lie within 256
- * of its reference column (offsets 0..255) and the matrix has offset slices,
- * else 16; 8 or 16 force the width (tests, tuning), and building then
- * reports SPMV_ERR_INFEASIBLE for 8 if an offset slice spans more.  The
- * rows-streamed layout always stores 16 bits.  A built format is dropped
- * and, if DELTA16 is the plan's variant, rebuilt (synchronous).
- * SPMV_ERR_ARG for any other value. */
+/* Column-code width of the sliced DELTA16 layout's offset slices, the same
+ * for the whole matrix (Section 3.3 uses 8- or 16-bit deltas, never both).
+ * 16: offsets c - ref from the slice's reference column (its smallest).
+ * 8: the code of a row's k-th nonzero is c_k - c_(k-1), with c_(-1) = ref,
+ * when that is at most 254, else 255 (escape) and c_k itself is stored: the
+ * e-th escape of lane l of slice s is escape entry 64 (eunits[s] + e) + l,
+ * eunits being the exclusive prefix sums over slices of the largest number
+ * of escapes of one of the slice's rows (E).  A slice spanning at most 255
+ * columns has no escapes.  0 (default) takes 8 bits when the matrix has
+ * offset slices and 256 sum E <= (nonzeros of offset slices) / 2 (the escape
+ * entries cost at most half of the byte per nonzero the codes save), else
+ * 16; 8 or 16 force the width (tests, tuning).  The rows-streamed layout
+ * always stores 16 bits.  A built format is dropped and, if DELTA16 is the
+ * plan's variant, rebuilt (synchronous).  SPMV_ERR_ARG for any other
+ * value. */
 spmv_status_t spmv_set_delta16_offset_bits(spmv_plan_t plan, int32_t bits);
 
 /* Bit v set if variant v can run this matrix (computes features if needed). */
@@ -235,8 +242,9 @@ spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
  * 4 bytes per block reference column in the streamed layout; in the sliced
  * one, 16 bytes per 64-row slice (width, unit offset, reference column,
  * kind) and 128 per diagonal slice (its diagonals), with 1 or 2 index bytes
- * (the offset width) only for the nonzeros of offset slices (a row's mask in
- * a diagonal slice takes
+ * (the code width) only for the nonzeros of offset slices, plus with 8-bit
+ * codes 4 bytes per escaped column and 4 per slice (its eunits entry) (a
+ * row's mask in a diagonal slice takes
  * the place of its row pointer).  The layout is decided here if needed; the
  * streamed form is counted where DELTA16 is infeasible.  Traffic a variant adds on top (the XBLOCK_LDS slice row
  * pointers and partial y vectors, the sliced layout's padding slots) is
@@ -264,9 +272,10 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
  * 0 rows streamed, 1 sliced), 15 delta16 sliced slots (64 x the sum of the
  * slice widths, padding included), 16 x-block row blocks per workgroup of
  * the phased slice kernel (0 when the slices use merge-path tiles),
- * 17 delta16 offset bits (8 or 16; -1 infeasible), 18 delta16 largest
+ * 17 delta16 code bits (8 or 16; -1 infeasible), 18 delta16 largest
  * offset of an offset slice (its columns minus its reference column; 0 with
- * no offset slices; -1 infeasible). */
+ * no offset slices; -1 infeasible), 19 delta16 escape units (sum E; 0 with
+ * 16-bit codes), 20 delta16 escaped nonzeros (0 with 16-bit codes). */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:
@@ -281,8 +290,12 @@ spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
  * are in the sliced one), S = ceil(N / 64) slices: 8 widths int32[S] (the
  * slice's longest row rounded up to even), 9 units int32[S] (exclusive
  * prefix sums of width / 2), 10 reference columns int32[S] (the slice's
- * smallest column, 0 if it has none), 11 offsets [key 15] of key 17 bits
- * (uint8 or uint16),
+ * smallest column, 0 if it has none), 11 column codes: uint16 offsets
+ * [key 15] at the slots below, or uint8 delta codes [key 15 + 128 S] with
+ * code k of lane l of slice s at byte 128 (units[s] + s) + 256 (k / 4) +
+ * 4 l + k % 4 (0 in diagonal slices and padding),
+ * 16 escaped columns int32[64 x key 19] (0 where unused), 17 eunits
+ * int32[S] (8-bit codes only, else empty),
  * 12 values [key 15] of the plan's value type, 13 kinds int32[S] (0 for an
  * offset slice, 1 + D for a diagonal slice of D diagonals), 14 diagonals
  * int32[32 S] (slice s's sorted diagonals c - r from 32 s, zero-padded;

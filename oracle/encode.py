@@ -13,8 +13,10 @@
   share at most 32 diagonals stores those diagonals once and a bit mask per
   row instead of any column data.  A combination of the MB optimisation with
   a GPU storage order, in the spirit of the paper's closing remarks on wider
-  pools and multi-level optimisation.  ``delta16_offset_bits_ref`` takes the
-  paper's other width: 8-bit offsets when every offset slice fits them.
+  pools and multi-level optimisation.  ``delta8_codes_ref`` is the paper's
+  other width: 8-bit deltas between consecutive columns of a row, with an
+  escape code for a gap that does not fit; ``delta16_offset_bits_ref``
+  chooses the width.
 * ``merge_splits_ref``  start coordinates of the nonzero-balanced merge-path
   tiles (Merrill and Garland, SC'16): the merge of the row-end list
   ``rowptr[1..N]`` with the nonzero indices ``0..NNZ-1``, where nonzero j is
@@ -156,18 +158,112 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
                 off=off, vals=vals, nnz_offset=nnz_offset)
 
 
-def delta16_offset_bits_ref(kind, span, nnz_offset: int) -> int:
-    """Bits per stored offset of the sliced layout (Section 3.3: deltas of 8
-    or 16 bits wherever possible, one width per matrix, never both).
+ESCAPE = 255  # 8-bit code of a column stored in full
 
-    An offset is c - base_s, from 0 to span_s, so 8 bits hold every offset of
-    the matrix when each offset slice (kind 0) has span_s <= 255.  Then, if
-    the matrix has any offsets to store, the width is 8; otherwise 16.
+
+def delta8_codes_ref(rowptr, colind, L, slice_rows: int = SLICE_ROWS):
+    """8-bit delta coding of the offset slices of a sliced layout ``L``
+    (Section 3.3: delta indexing of the column indices, Pooch and Nieder).
+
+    In an offset slice s the k-th nonzero of the row in lane l, column c_k,
+    gets the code d = c_k - c_{k-1}, with c_{-1} = base_s, when d <= 254;
+    otherwise the escape code 255, and c_k itself goes to the slice's escape
+    area: the e-th escape of lane l is esc[64 (eunits_s + e) + l], where E_s
+    is the largest number of escapes of a row of the slice and eunits the
+    exclusive prefix sums of E.  Codes go in groups of four positions per
+    lane: code k of lane l of slice s is at
+
+        128 (u_s + s) + 256 (k // 4) + 4 l + (k % 4)
+
+    (u_s the slice's unit offset; one spare unit per slice covers a width
+    that is not a multiple of 4), 128 (sum of widths / 2 + S) bytes in all.
+    Every other code is 0 (so a padding position repeats the row's last
+    column) and unused escape entries hold 0.  Diagonal slices have no codes
+    and E_s = 0.  Returns a dict with codes (uint8), E and eunits
+    (int32[S]), esc (int32[64 sum E]) and escapes (the escaped nonzeros).
     """
-    kind = np.asarray(kind)
-    span = np.asarray(span)
-    fits8 = bool(np.all(span[kind == 0] <= 255))
-    return 8 if fits8 and nnz_offset > 0 else 16
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colind = np.asarray(colind, dtype=np.int64)
+    n = len(rowptr) - 1
+    ns = len(L["width"])
+    E = np.zeros(ns, dtype=np.int64)
+    row_escapes = []
+    for i in range(n):
+        s, lane = divmod(i, slice_rows)
+        if L["kind"][s]:
+            row_escapes.append([])
+            continue
+        prev, esc_cols = int(L["base"][s]), []
+        for j in range(rowptr[i], rowptr[i + 1]):
+            if colind[j] - prev >= ESCAPE:
+                esc_cols.append(int(colind[j]))
+            prev = int(colind[j])
+        row_escapes.append(esc_cols)
+        E[s] = max(E[s], len(esc_cols))
+    eunits = np.zeros(ns, dtype=np.int64)
+    for s in range(1, ns):
+        eunits[s] = eunits[s - 1] + E[s - 1]
+    codes = np.zeros(L["slots"] + 2 * slice_rows * ns, dtype=np.uint8)
+    esc = np.zeros(slice_rows * int(E.sum()), dtype=np.int64)
+    escapes = 0
+    for i in range(n):
+        s, lane = divmod(i, slice_rows)
+        if L["kind"][s]:
+            continue
+        prev, e = int(L["base"][s]), 0
+        for k in range(rowptr[i + 1] - rowptr[i]):
+            c = int(colind[rowptr[i] + k])
+            slot = code_slot_ref(L["units"][s], s, lane, k, slice_rows)
+            if c - prev >= ESCAPE:
+                codes[slot] = ESCAPE
+                esc[slice_rows * (eunits[s] + e) + lane] = c
+                e += 1
+                escapes += 1
+            else:
+                codes[slot] = c - prev
+            prev = c
+    return dict(codes=codes, E=E.astype(np.int32), eunits=eunits.astype(np.int32),
+                esc=esc.astype(np.int32), escapes=escapes)
+
+
+def code_slot_ref(unit: int, s: int, lane: int, k: int, slice_rows: int = SLICE_ROWS) -> int:
+    """Byte of 8-bit code k of lane ``lane`` of slice s (unit offset ``unit``)."""
+    return 2 * slice_rows * (int(unit) + s) + 4 * slice_rows * (k // 4) + 4 * lane + k % 4
+
+
+def delta8_decode_ref(codes, esc, L, row_lengths, slice_rows: int = SLICE_ROWS):
+    """The columns of every offset-slice row back from its codes (the
+    inverse of ``delta8_codes_ref``), as a list of lists (empty for rows of
+    diagonal slices)."""
+    out = []
+    for i, length in enumerate(row_lengths):
+        s, lane = divmod(i, slice_rows)
+        cols = []
+        if not L["kind"][s]:
+            c, e = int(L["base"][s]), 0
+            for k in range(length):
+                d = int(codes[code_slot_ref(L["units"][s], s, lane, k, slice_rows)])
+                if d == ESCAPE:
+                    c = int(esc[slice_rows * (int(L["eunits"][s]) + e) + lane])
+                    e += 1
+                else:
+                    c += d
+                cols.append(c)
+        out.append(cols)
+    return out
+
+
+def delta16_offset_bits_ref(nnz_offset: int, escape_units: int) -> int:
+    """Bits per stored column code of the sliced layout (Section 3.3: deltas
+    of 8 or 16 bits, one width per matrix, never both).
+
+    16 bits are offsets c - base_s, which always fit (a slice spans at most
+    65536 columns).  8 bits are the delta codes of ``delta8_codes_ref``; their
+    escape area holds 64 int32 entries per unit of E.  The matrix takes 8
+    bits when it has offsets to store and that area costs at most half of the
+    byte the codes save per nonzero: 256 sum E <= nnz_offset / 2.
+    """
+    return 8 if nnz_offset > 0 and 512 * escape_units <= nnz_offset else 16
 
 
 def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int, n: int) -> int:

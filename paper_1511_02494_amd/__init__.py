@@ -242,13 +242,14 @@ def spmv_plan_query(plan, key: int) -> int:
 
 _FORMAT_DTYPES = {0: np.int32, 1: np.uint16, 2: np.int32, 3: np.int32, 4: np.int32,
                   5: np.int32, 6: np.int32, 7: np.int32, 8: np.int32, 9: np.int32, 10: np.int32,
-                  11: np.uint16, 13: np.int32, 14: np.int32, 15: np.uint32}
+                  11: np.uint16, 13: np.int32, 14: np.int32, 15: np.uint32, 16: np.int32,
+                  17: np.int32}
 
 
 def spmv_plan_copy_format(plan, which: int, count: int, dtype=None) -> np.ndarray:
     """Array ``which`` of the plan's formats; ``dtype`` is required for the
     sliced delta16 values (12), which have the plan's value type.  The sliced
-    offsets (11) take the plan's offset width (query key 17)."""
+    column codes (11) take the plan's code width (query key 17)."""
     if dtype is None and which == 11:
         dtype = np.uint8 if spmv_plan_query(plan, 17) == 8 else np.uint16
     out = np.empty(count, dtype=dtype or _FORMAT_DTYPES[which])

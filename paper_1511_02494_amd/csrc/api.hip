@@ -372,17 +372,48 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     const int automatic = representable && padded_ok ? 1 : 0;
     if (P->d16_layout_req == 1 && !representable)
         return fail(SPMV_ERR_INFEASIBLE, "delta16: the sliced layout needs under 2^31 slot pairs");
-    // one offset width for the whole matrix: 8 bits when every offset slice
-    // fits them (and there are offsets at all), else 16
-    const bool fits8 = max_span <= 255;
     const int layout = P->d16_layout_req >= 0 ? P->d16_layout_req : automatic;
-    if (layout == 1 && P->d16_offw_req == 8 && !fits8)
-        return fail(SPMV_ERR_INFEASIBLE,
-                    "delta16: 8-bit offsets need every offset slice to span at most 256 columns "
-                    "(the widest spans %lld)", (long long)max_span + 1);
+    // one code width for the whole matrix.  8-bit delta codes escape a gap of
+    // 255 or more; a slice spanning fewer columns has none.  Otherwise the
+    // escapes are counted, and 8 bits are taken when their area (64 int32
+    // entries per unit of the per-slice maximum) costs at most half of the
+    // byte per nonzero that the codes save
+    int64_t esc_units = 0, nesc = 0;
+    std::vector<int32_t> eunits;
+    int offw = 16;
+    if (layout == 1 && P->d16_offw_req != 16 && (nnz_off > 0 || P->d16_offw_req == 8)) {
+        eunits.assign((size_t)nsl, 0);
+        if (max_span >= 255) {
+            DevBuf dE, dN;
+            SPMV_TRY(dE.alloc(nb));
+            SPMV_TRY(dN.alloc(nb));
+            SPMV_HIP(launch_sliced_escapes(*P, P->d16s_base.as<int32_t>(), P->d16s_kind.as<int32_t>(),
+                                           dE.as<int32_t>(), dN.as<int32_t>(), S(P)));
+            std::vector<int32_t> hE((size_t)nsl), hN((size_t)nsl);
+            SPMV_HIP(hipMemcpyAsync(hE.data(), dE.p, nb, hipMemcpyDeviceToHost, S(P)));
+            SPMV_HIP(hipMemcpyAsync(hN.data(), dN.p, nb, hipMemcpyDeviceToHost, S(P)));
+            SPMV_TRY(sync(P));
+            for (int64_t k = 0; k < nsl; ++k) {
+                eunits[(size_t)k] = (int32_t)esc_units;  // at most one unit per slot pair
+                esc_units += hE[(size_t)k];
+                nesc += hN[(size_t)k];
+            }
+        }
+        const bool want8 = P->d16_offw_req == 8 || 512 * esc_units <= nnz_off;
+        if (want8) offw = 8;
+    }
+    if (offw == 8) {
+        SPMV_TRY(P->d16s_eunits.alloc(nb));
+        SPMV_HIP(hipMemcpyAsync(P->d16s_eunits.p, eunits.data(), nb, hipMemcpyHostToDevice, S(P)));
+        SPMV_TRY(sync(P));  // the host vector goes out of scope
+    } else {
+        P->d16s_eunits.release();
+        esc_units = nesc = 0;
+    }
     P->d16_layout = layout;
-    if (layout == 0) P->d16_offw = 16;  // the streamed layout stores 16 bits
-    else P->d16_offw = P->d16_offw_req > 0 ? P->d16_offw_req : (fits8 && nnz_off > 0 ? 8 : 16);
+    P->d16_offw = offw;
+    P->d16_esc_units = esc_units;
+    P->d16_nesc = nesc;
     P->d16s_nnz.release();
     if (P->d16_layout == 0) {
         P->d16s_width.release();
@@ -585,17 +616,29 @@ spmv_status_t build_format(spmv_plan *P, int v) {
         SPMV_TRY(d16_decide_layout(P));
         if (P->d16_layout == 1) {
             const size_t slots = (size_t)P->d16_slots;
-            const int ob = P->d16_offw / 8;
-            SPMV_TRY(P->d16s_off.alloc(slots * ob + 16));
+            const bool d8 = P->d16_offw == 8;
+            // 8-bit codes: one byte per slot plus a spare unit per slice
+            const size_t cbytes = d8 ? slots + (size_t)(2 * kSellRows) * P->d16_nsl : slots * 2;
+            SPMV_TRY(P->d16s_off.alloc(cbytes + 16));
             SPMV_TRY(P->d16s_val.alloc(slots * vbytes(P->dtype) + 16));
             const size_t mbytes = (size_t)(P->n > 0 ? P->n : 1) * 4;
             SPMV_TRY(P->d16s_mask.alloc(mbytes));
-            SPMV_HIP(hipMemsetAsync(P->d16s_off.p, 0, slots * ob + 16, S(P)));
+            SPMV_HIP(hipMemsetAsync(P->d16s_off.p, 0, cbytes + 16, S(P)));
             SPMV_HIP(hipMemsetAsync(P->d16s_val.p, 0, slots * vbytes(P->dtype) + 16, S(P)));
             SPMV_HIP(launch_sliced_scatter(*P, P->d16s_units.as<int32_t>(), P->d16s_base.as<int32_t>(),
                                            P->d16s_kind.as<int32_t>(), P->d16s_diag.as<int32_t>(),
-                                           P->d16s_off.p, ob, P->d16s_val.p,
+                                           d8 ? nullptr : P->d16s_off.as<uint16_t>(), P->d16s_val.p,
                                            P->d16s_mask.as<uint32_t>(), S(P)));
+            if (d8) {
+                const size_t eb = (size_t)P->d16_esc_units * kSellRows * 4 + 16;
+                SPMV_TRY(P->d16s_esc.alloc(eb));
+                SPMV_HIP(hipMemsetAsync(P->d16s_esc.p, 0, eb, S(P)));
+                SPMV_HIP(launch_sliced_codes(*P, P->d16s_units.as<int32_t>(), P->d16s_base.as<int32_t>(),
+                                             P->d16s_kind.as<int32_t>(), P->d16s_eunits.as<int32_t>(),
+                                             P->d16s_off.as<uint8_t>(), P->d16s_esc.as<int32_t>(), S(P)));
+            } else {
+                P->d16s_esc.release();
+            }
             SPMV_TRY(sync(P));
             P->d16_built = true;
             return SPMV_OK;
@@ -1050,8 +1093,12 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
             // offsets only in offset slices; width, units, base and kind per
             // slice, 32 diagonals per diagonal slice; a row's mask replaces
             // its row pointer in diagonal slices
-            *bytes = 4 * (P->n + 1) + vb * P->nnz + (P->d16_offw / 8) * P->d16_nnz_off +
-                     xb * P->m + xb * P->n + 16 * P->d16_nsl + 4 * kSellMaxDiag * P->d16_ndiag;
+            // 8-bit codes: 4 bytes per escaped column and 4 per slice (its
+            // first escape unit)
+            const bool d8 = P->d16_offw == 8;
+            *bytes = 4 * (P->n + 1) + vb * P->nnz + (d8 ? 1 : 2) * P->d16_nnz_off +
+                     (d8 ? 4 * P->d16_nesc + 4 * P->d16_nsl : 0) + xb * P->m + xb * P->n +
+                     16 * P->d16_nsl + 4 * kSellMaxDiag * P->d16_ndiag;
             return SPMV_OK;
         }
         extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
@@ -1103,10 +1150,13 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
     case 15: SPMV_TRY(d16_decide_layout(P)); *value = P->d16_slots; break;
     case 17:
     case 18:
+    case 19:
+    case 20:
         SPMV_TRY(check_d16(P));
         if (!d16_feasible(P)) { *value = -1; break; }
         SPMV_TRY(d16_decide_layout(P));
-        *value = key == 17 ? P->d16_offw : P->d16_span;
+        *value = key == 17 ? P->d16_offw : key == 18 ? P->d16_span
+                 : key == 19 ? P->d16_esc_units : P->d16_nesc;
         break;
     case 10: *value = 1; break;
     default: return fail(SPMV_ERR_ARG, "unknown key %d", key);
@@ -1120,14 +1170,19 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
     const void *src = nullptr;
     int64_t want = 0;
     switch (which) {
-    case 8: case 9: case 10: case 11: case 12: case 13: case 14: case 15:
+    case 8: case 9: case 10: case 11: case 12: case 13: case 14: case 15: case 16: case 17:
         SPMV_TRY(build_format(P, V_DELTA16));
         if (P->d16_layout != 1) return fail(SPMV_ERR_ARG, "delta16 is not in the sliced layout");
         switch (which) {
         case 8: src = P->d16s_width.p; want = 4 * P->d16_nsl; break;
         case 9: src = P->d16s_units.p; want = 4 * P->d16_nsl; break;
         case 10: src = P->d16s_base.p; want = 4 * P->d16_nsl; break;
-        case 11: src = P->d16s_off.p; want = (P->d16_offw / 8) * P->d16_slots; break;
+        case 11:
+            src = P->d16s_off.p;
+            want = P->d16_offw == 8 ? P->d16_slots + 2 * kSellRows * P->d16_nsl : 2 * P->d16_slots;
+            break;
+        case 16: src = P->d16s_esc.p; want = 4 * kSellRows * P->d16_esc_units; break;
+        case 17: src = P->d16s_eunits.p; want = P->d16_offw == 8 ? 4 * P->d16_nsl : 0; break;
         case 12: src = P->d16s_val.p; want = vbytes(P->dtype) * P->d16_slots; break;
         case 13: src = P->d16s_kind.p; want = 4 * P->d16_nsl; break;
         case 14: src = P->d16s_diag.p; want = 4 * kSellMaxDiag * P->d16_nsl; break;
@@ -1402,6 +1457,8 @@ spmv_status_t spmv_set_delta16_layout(spmv_plan_t P, int32_t layout) {
     P->d16s_kind.release();
     P->d16s_diag.release();
     P->d16s_mask.release();
+    P->d16s_esc.release();
+    P->d16s_eunits.release();
     if (P->variant == V_DELTA16) SPMV_TRY(build_format(P, V_DELTA16));  // else on next use
     return SPMV_OK;
 }
@@ -1419,6 +1476,8 @@ spmv_status_t spmv_set_delta16_offset_bits(spmv_plan_t P, int32_t bits) {
     P->d16s_off.release();
     P->d16s_val.release();
     P->d16s_mask.release();
+    P->d16s_esc.release();
+    P->d16s_eunits.release();
     if (P->variant == V_DELTA16) SPMV_TRY(build_format(P, V_DELTA16));  // else on next use
     return SPMV_OK;
 }

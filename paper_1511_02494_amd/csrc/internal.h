@@ -113,11 +113,15 @@ struct spmv_plan {
     // slices stored column-major in pairs, one reference column per slice)
     int d16_layout = -1;         // -1: not decided yet
     int d16_layout_req = -1;     // forced layout, -1 automatic
-    // bits per stored offset in the sliced layout: 8 when every offset
-    // slice spans at most 256 columns, else 16 (one width per matrix)
+    // bits per column code in the sliced layout's offset slices (one width
+    // per matrix): 16 = offsets from the slice's reference column, 8 = deltas
+    // from the row's previous column with an escape code (255) for a gap
+    // that does not fit, the escaped column stored in d16s_esc
     int d16_offw = 16;
     int d16_offw_req = 0;        // forced width, 0 automatic
     int64_t d16_span = 0;        // largest column span of an offset slice
+    int64_t d16_esc_units = 0, d16_nesc = 0;  // sum of per-slice max escapes; escapes
+    spmvsel::DevBuf d16s_eunits, d16s_esc;    // per slice: first escape unit; escapes
     int64_t d16_nsl = 0, d16_slots = 0;
     int64_t d16_nnz_off = 0, d16_ndiag = 0;  // nonzeros of offset slices; diagonal slices
     spmvsel::DevBuf d16s_width, d16s_units, d16s_base, d16s_off, d16s_val;
@@ -197,10 +201,17 @@ hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16
 hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
                                int32_t *kind, int32_t *diag, int32_t *snnz, int32_t *span,
                                hipStream_t s);
-// off holds uint8 offsets when off_bytes is 1, uint16 when it is 2
+// off may be null: the values and masks are written, no 16-bit offsets
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
-                                 const int32_t *kind, const int32_t *diag, void *off, int off_bytes,
+                                 const int32_t *kind, const int32_t *diag, uint16_t *off,
                                  void *vals, uint32_t *mask, hipStream_t s);
+// per offset slice: the most escapes of one of its rows (E) and their sum
+hipError_t launch_sliced_escapes(const spmv_plan &P, const int32_t *base, const int32_t *kind,
+                                 int32_t *E, int32_t *nesc, hipStream_t s);
+// 8-bit delta codes of the offset slices and their escaped columns
+hipError_t launch_sliced_codes(const spmv_plan &P, const int32_t *units, const int32_t *base,
+                               const int32_t *kind, const int32_t *eunits, uint8_t *codes,
+                               int32_t *esc, hipStream_t s);
 hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t panels,
                            unsigned long long *d_max, hipStream_t s);
 hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,

@@ -142,7 +142,7 @@ hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *half
 // among the slice's (in LDS) by a binary search, writes its value to that
 // position and sets the diagonal's bit in the row's mask (LDS atomics; the
 // masks are stored once at the end, zero for rows of offset slices).
-template <class V, class O>
+template <class V>
 __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
                                                            const V *__restrict__ val,
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
                                                            const int32_t *__restrict__ base,
                                                            const int32_t *__restrict__ kind,
                                                            const int32_t *__restrict__ diag,
-                                                           O *__restrict__ off,
+                                                           uint16_t *__restrict__ off,
                                                            V *__restrict__ vals,
                                                            uint32_t *__restrict__ mask) {
     constexpr int kWaves = kBlock / kSellRows;
@@ -191,9 +191,9 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
             }
             k = a;
             atomicOr(&s_mask[lo], 1u << k);
-        } else {
+        } else if (off) {
             off[2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1)] =
-                (O)(ci[j] - base[sl]);
+                (uint16_t)(ci[j] - base[sl]);
         }
         vals[2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1)] = val[j];
     }
@@ -202,26 +202,124 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
 }
 
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
-                                 const int32_t *kind, const int32_t *diag, void *off, int off_bytes,
+                                 const int32_t *kind, const int32_t *diag, uint16_t *off,
                                  void *vals, uint32_t *mask, hipStream_t s) {
     if (P.n == 0) return hipSuccess;  // (with no nonzeros it still writes the zero masks)
-    if (off_bytes != 1 && off_bytes != 2) return hipErrorInvalidValue;
     const dim3 g((unsigned)((P.n + kBlock - 1) / kBlock));
-    auto go = [&](auto vtag, auto otag) {
-        using V = std::remove_pointer_t<decltype(vtag)>;
-        using O = std::remove_pointer_t<decltype(otag)>;
-        hipLaunchKernelGGL((k_sliced_scatter<V, O>), g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
-                           (const V *)P.val, units, base, kind, diag, (O *)off, (V *)vals, mask);
-    };
-    auto by_off = [&](auto vtag) {
-        if (off_bytes == 1) go(vtag, (uint8_t *)nullptr);
-        else go(vtag, (uint16_t *)nullptr);
-    };
     switch (P.dtype) {
-    case SPMV_F64: by_off((double *)nullptr); break;
-    case SPMV_F32: by_off((float *)nullptr); break;
-    default: by_off((uint16_t *)nullptr);
+    case SPMV_F64:
+        hipLaunchKernelGGL(k_sliced_scatter<double>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
+                           (const double *)P.val, units, base, kind, diag, off, (double *)vals, mask);
+        break;
+    case SPMV_F32:
+        hipLaunchKernelGGL(k_sliced_scatter<float>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
+                           (const float *)P.val, units, base, kind, diag, off, (float *)vals, mask);
+        break;
+    default:
+        hipLaunchKernelGGL(k_sliced_scatter<uint16_t>, g, dim3(kBlock), 0, s, P.n, P.rowptr,
+                           P.colind, (const uint16_t *)P.val, units, base, kind, diag, off,
+                           (uint16_t *)vals, mask);
     }
+    return hipGetLastError();
+}
+
+// 8-bit delta coding of the offset slices (Section 3.3).  A wavefront per
+// slice, a lane per row: the lane walks its row in column order; the code of
+// a nonzero is its column minus the previous one (the slice's reference
+// column before the first), or the escape code 255 when that gap is 255 or
+// more, in which case the column itself is stored.  k_sliced_escapes counts
+// the escapes, k_sliced_codes writes codes and escaped columns; the e-th
+// escape of lane l of slice s is esc[64 (eunits[s] + e) + l].  Codes go in
+// groups of four positions per lane (a 4-byte load per lane per step): code
+// k of lane l is byte 128 (units[s] + s) + 256 (k / 4) + 4 l + k % 4, one
+// spare unit per slice covering a width that is not a multiple of 4.
+// Neither kernel has a barrier, so whole wavefronts leave early.
+constexpr int kEscape = 255;
+
+__global__ __launch_bounds__(kBlock) void k_sliced_escapes(int64_t n, int64_t nsl,
+                                                           const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const int32_t *__restrict__ base,
+                                                           const int32_t *__restrict__ kind,
+                                                           int32_t *__restrict__ E,
+                                                           int32_t *__restrict__ nesc) {
+    const int64_t sl = blockIdx.x * (int64_t)(kBlock / kSellRows) + threadIdx.x / kSellRows;
+    if (sl >= nsl) return;
+    const int lane = threadIdx.x & (kSellRows - 1);
+    const int64_t r = sl * kSellRows + lane;
+    int cnt = 0;
+    if (kind[sl] == 0 && r < n) {
+        int32_t prev = base[sl];  // the slice's smallest column: no gap is negative
+        for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+            const int32_t c = ci[j];
+            cnt += (c - prev >= kEscape) ? 1 : 0;
+            prev = c;
+        }
+    }
+    int mx = cnt, sum = cnt;
+#pragma unroll
+    for (int d = kSellRows / 2; d > 0; d >>= 1) {
+        const int om = __shfl_xor(mx, d, kSellRows);
+        sum += __shfl_xor(sum, d, kSellRows);
+        mx = om > mx ? om : mx;
+    }
+    if (lane == 0) {
+        E[sl] = mx;
+        nesc[sl] = sum;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sliced_codes(int64_t n, int64_t nsl,
+                                                         const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         const int32_t *__restrict__ units,
+                                                         const int32_t *__restrict__ base,
+                                                         const int32_t *__restrict__ kind,
+                                                         const int32_t *__restrict__ eunits,
+                                                         uint8_t *__restrict__ codes,
+                                                         int32_t *__restrict__ esc) {
+    const int64_t sl = blockIdx.x * (int64_t)(kBlock / kSellRows) + threadIdx.x / kSellRows;
+    if (sl >= nsl || kind[sl] != 0) return;
+    const int lane = threadIdx.x & (kSellRows - 1);
+    const int64_t r = sl * kSellRows + lane;
+    if (r >= n) return;
+    const int64_t o = 2 * kSellRows * ((int64_t)units[sl] + sl) + 4 * lane;
+    int64_t q = (int64_t)kSellRows * eunits[sl] + lane;  // this lane's next escape entry
+    int32_t prev = base[sl];
+    const int32_t a = rp[r], b = rp[r + 1];
+    for (int32_t j = a; j < b; ++j) {
+        const int k = j - a;
+        const int32_t c = ci[j];
+        const int64_t slot = o + 4 * kSellRows * (int64_t)(k / 4) + (k & 3);
+        if (c - prev >= kEscape) {
+            codes[slot] = (uint8_t)kEscape;
+            esc[q] = c;
+            q += kSellRows;
+        } else {
+            codes[slot] = (uint8_t)(c - prev);
+        }
+        prev = c;
+    }
+}
+
+hipError_t launch_sliced_escapes(const spmv_plan &P, const int32_t *base, const int32_t *kind,
+                                 int32_t *E, int32_t *nesc, hipStream_t s) {
+    const int64_t nsl = (P.n + kSellRows - 1) / kSellRows;
+    if (nsl == 0) return hipSuccess;
+    const int64_t per = kBlock / kSellRows;
+    hipLaunchKernelGGL(k_sliced_escapes, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0,
+                       s, P.n, nsl, P.rowptr, P.colind, base, kind, E, nesc);
+    return hipGetLastError();
+}
+
+hipError_t launch_sliced_codes(const spmv_plan &P, const int32_t *units, const int32_t *base,
+                               const int32_t *kind, const int32_t *eunits, uint8_t *codes,
+                               int32_t *esc, hipStream_t s) {
+    const int64_t nsl = (P.n + kSellRows - 1) / kSellRows;
+    if (nsl == 0) return hipSuccess;
+    const int64_t per = kBlock / kSellRows;
+    hipLaunchKernelGGL(k_sliced_codes, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0, s,
+                       P.n, nsl, P.rowptr, P.colind, units, base, kind, eunits, codes, esc);
     return hipGetLastError();
 }
 

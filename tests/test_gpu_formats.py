@@ -6,9 +6,9 @@ import pytest
 
 import synth
 import paper_1511_02494_amd as S
-from oracle.encode import (delta16_layout_ref, delta16_offset_bits_ref, delta16_ref,
-                           delta16_sliced_ref, merge_search_ref, merge_walk_ref, partition_ref,
-                           xblock_split_ref, to_bf16_bits_ref, to_f32_ref)
+from oracle.encode import (delta8_codes_ref, delta16_layout_ref, delta16_offset_bits_ref,
+                           delta16_ref, delta16_sliced_ref, merge_search_ref, merge_walk_ref,
+                           partition_ref, xblock_split_ref, to_bf16_bits_ref, to_f32_ref)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -45,12 +45,9 @@ def test_formats_match_oracle(name, build, m):
         assert np.array_equal(S.spmv_plan_copy_format(h, 0, len(base)), base)
         assert np.array_equal(S.spmv_plan_copy_format(h, 1, nnz), off)
         S.spmv_set_delta16_layout(h, 1)
-        check_sliced(h, L, np.float64)
-        # compulsory bytes: no offsets in diagonal slices, their diagonals once
-        bits = delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"])
-        want = (4 * (n + 1) + 8 * nnz + bits // 8 * L["nnz_offset"] + 8 * m + 8 * n
-                + 16 * len(L["width"]) + 128 * int(np.count_nonzero(L["kind"])))
-        assert S.spmv_bytes(h, S.V_DELTA16) == want
+        bits = check_sliced(h, rp, ci, L, np.float64)
+        assert S.spmv_bytes(h, S.V_DELTA16) == sliced_bytes(L, delta8_codes_ref(rp, ci, L), bits,
+                                                            n, m, nnz)
     else:
         assert S.spmv_plan_query(h, 14) == -1
     T = S.spmv_plan_query(h, 3)
@@ -78,13 +75,37 @@ def test_formats_match_oracle(name, build, m):
     plan.close()
 
 
-def check_sliced(h, L, vdtype, bits=None):
+def sliced_bytes(L, C, bits, n, m, nnz):
+    """Compulsory bytes: no codes in diagonal slices, their diagonals once;
+    8-bit codes add their escaped columns and a first escape unit per slice."""
     ns = len(L["width"])
+    codes = L["nnz_offset"] * (1 if bits == 8 else 2) + (4 * C["escapes"] + 4 * ns if bits == 8 else 0)
+    return (4 * (n + 1) + 8 * nnz + codes + 8 * m + 8 * n + 16 * ns
+            + 128 * int(np.count_nonzero(L["kind"])))
+
+
+def check_sliced(h, rp, ci, L, vdtype, bits=None):
+    """The plan's sliced arrays against the oracle; returns the code width."""
+    ns = len(L["width"])
+    C = delta8_codes_ref(rp, ci, L)
     if bits is None:
-        bits = delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"])
+        bits = delta16_offset_bits_ref(L["nnz_offset"], int(C["E"].sum()))
     assert S.spmv_plan_query(h, 17) == bits
     spans = L["span"][L["kind"] == 0]
     assert S.spmv_plan_query(h, 18) == (int(spans.max()) if len(spans) else 0)
+    if bits == 8:
+        assert S.spmv_plan_query(h, 19) == int(C["E"].sum())
+        assert S.spmv_plan_query(h, 20) == C["escapes"]
+        got = S.spmv_plan_copy_format(h, 11, len(C["codes"]))
+        assert got.dtype == np.uint8 and np.array_equal(got, C["codes"])
+        assert np.array_equal(S.spmv_plan_copy_format(h, 16, len(C["esc"])), C["esc"])
+        assert np.array_equal(S.spmv_plan_copy_format(h, 17, ns), C["eunits"])
+    else:
+        assert S.spmv_plan_query(h, 19) == 0 and S.spmv_plan_query(h, 20) == 0
+        assert np.all(L["off"] < 65536)
+        got = S.spmv_plan_copy_format(h, 11, L["slots"])
+        assert got.dtype == np.uint16 and np.array_equal(got, L["off"].astype(np.uint16))
+        assert len(S.spmv_plan_copy_format(h, 17, 0)) == 0
     kinds = S.spmv_plan_copy_format(h, 13, ns)
     assert np.array_equal(kinds, np.where(L["kind"] > 0, 1 + L["ndiag"], 0))
     assert np.array_equal(S.spmv_plan_copy_format(h, 14, 32 * ns), L["diag"])
@@ -92,12 +113,9 @@ def check_sliced(h, L, vdtype, bits=None):
     assert np.array_equal(S.spmv_plan_copy_format(h, 8, ns), L["width"])
     assert np.array_equal(S.spmv_plan_copy_format(h, 9, ns), L["units"])
     assert np.array_equal(S.spmv_plan_copy_format(h, 10, ns), L["base"])
-    assert np.all(L["off"] < (1 << bits))
-    odt = np.uint8 if bits == 8 else np.uint16
-    got = S.spmv_plan_copy_format(h, 11, L["slots"])
-    assert got.dtype == odt and np.array_equal(got, L["off"].astype(odt))
     got = S.spmv_plan_copy_format(h, 12, L["slots"], vdtype)
     assert np.array_equal(got, L["vals"].astype(vdtype))
+    return bits
 
 
 @pytest.mark.parametrize("dtype", [S.SPMV_F32, S.SPMV_BF16])
@@ -109,50 +127,68 @@ def test_delta16_sliced_low_precision_values(dtype):
     if dtype == S.SPMV_F32:
         q = to_f32_ref(v).astype(np.float64)
         L = delta16_sliced_ref(rp, ci, q)
-        check_sliced(plan.handle, L, np.float32)
+        check_sliced(plan.handle, rp, ci, L, np.float32)
     else:
         bits = to_bf16_bits_ref(v)
         L = delta16_sliced_ref(rp, ci, bits.astype(np.float64))  # bit patterns as numbers
         L["vals"] = L["vals"].astype(np.uint16)
-        check_sliced(plan.handle, L, np.uint16)
+        check_sliced(plan.handle, rp, ci, L, np.uint16)
     plan.close()
 
 
-def test_delta16_offset_bits_forced():
-    """8 bits where every offset slice fits them, 16 when forced (the same
-    offsets, wider), and 8 refused where a slice spans more."""
-    rp, ci, v = synth.banded(6000, 960, 32, seed=5)
+def ragged_gaps(n=1024):
+    """Rows of 40 columns 7 apart; in every slice row 5 jumps 300 columns once
+    (one escape) and row 130 of every 256 twice."""
+    rows = []
+    for i in range(n):
+        c = i + 7 * np.arange(40)
+        if i % 64 == 5:
+            c[20:] += 300
+        if i % 256 == 130:
+            c[10:] += 300
+            c[30:] += 300
+        rows.append(c)
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    return rp, np.concatenate(rows).astype(np.int32)
+
+
+@pytest.mark.parametrize("name", ["narrowband", "wideband", "random", "ragged_gaps"])
+def test_delta16_code_widths(name):
+    """Automatic width, then 16 and 8 forced: codes, escapes and bytes as the
+    oracle's.  The narrow and the wide band (half width 200, slices spanning
+    about 460 columns) need no escape; on the random matrix every gap escapes
+    and the rule keeps 16 bits; the last case mixes rows of small gaps with
+    rows whose gaps escape."""
+    if name == "narrowband":
+        rp, ci, v = synth.banded(6000, 960, 32, seed=5)
+        m = 6000
+    elif name == "wideband":
+        rp, ci, v = synth.banded(6000, 300, 200, seed=4)
+        m = 6000
+    elif name == "random":
+        rp, ci, v = synth.uniform_random(3000, 5000, 8, seed=4)
+        m = 5000
+    else:
+        rp, ci = ragged_gaps()
+        v = synth.random_values(len(ci), 6)
+        m = 2000
+    n, nnz = len(rp) - 1, len(ci)
     L = delta16_sliced_ref(rp, ci, v)
-    assert delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"]) == 8
-    plan = make_plan(rp, ci, v, 6000)
+    C = delta8_codes_ref(rp, ci, L)
+    auto = delta16_offset_bits_ref(L["nnz_offset"], int(C["E"].sum()))
+    print(f"case={name} escapes={C['escapes']} E={int(C['E'].sum())} automatic bits={auto}", flush=True)
+    assert auto == (16 if name == "random" else 8)
+    assert (C["escapes"] > 0) == (name in ("random", "ragged_gaps"))
+    plan = make_plan(rp, ci, v, m)
     h = plan.handle
-    assert S.spmv_plan_query(h, 14) == 1
-    b8 = S.spmv_bytes(h, S.V_DELTA16)
-    check_sliced(h, L, np.float64)
-    S.spmv_set_delta16_offset_bits(h, 16)
-    check_sliced(h, L, np.float64, bits=16)
-    assert S.spmv_bytes(h, S.V_DELTA16) == b8 + L["nnz_offset"]
-    S.spmv_set_delta16_offset_bits(h, 8)
-    check_sliced(h, L, np.float64, bits=8)
+    S.spmv_set_delta16_layout(h, 1)
+    for req in (0, 16, 8, 0):
+        S.spmv_set_delta16_offset_bits(h, req)
+        bits = check_sliced(h, rp, ci, L, np.float64, bits=req or auto)
+        assert S.spmv_bytes(h, S.V_DELTA16) == sliced_bytes(L, C, bits, n, m, nnz)
     with pytest.raises(S.SpmvError) as e:
         S.spmv_set_delta16_offset_bits(h, 4)
     assert e.value.status == S.SPMV_ERR_ARG
-    plan.close()
-    rp, ci, v = synth.banded(6000, 300, 200, seed=4)  # offset slices span about 460 columns
-    L = delta16_sliced_ref(rp, ci, v)
-    plan = make_plan(rp, ci, v, 6000)
-    h = plan.handle
-    S.spmv_set_delta16_layout(h, 1)
-    assert S.spmv_plan_query(h, 17) == 16
-    S.spmv_set_delta16_offset_bits(h, 8)
-    with pytest.raises(S.SpmvError) as e:
-        S.spmv_plan_query(h, 17)
-    assert e.value.status == S.SPMV_ERR_INFEASIBLE
-    with pytest.raises(S.SpmvError) as e:
-        S.spmv_set_variant(h, S.V_DELTA16)
-    assert e.value.status == S.SPMV_ERR_INFEASIBLE
-    S.spmv_set_delta16_offset_bits(h, 0)
-    check_sliced(h, L, np.float64)
     plan.close()
 
 

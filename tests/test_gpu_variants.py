@@ -4,7 +4,7 @@ import pytest
 
 import synth
 import paper_1511_02494_amd as S
-from oracle.encode import delta16_offset_bits_ref, delta16_sliced_ref
+from oracle.encode import delta8_codes_ref, delta16_offset_bits_ref, delta16_sliced_ref
 from oracle.spmv import spmv_exact, spmv_seq, within_tolerance
 
 pytestmark = pytest.mark.gpu
@@ -122,10 +122,12 @@ def test_delta16_both_layouts(case, dtype):
 
 
 @pytest.mark.parametrize("dtype", [S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16])
-@pytest.mark.parametrize("case", ["narrowband_3000", "empty_rows", "banded_4000", "random_3000x8"])
-def test_delta16_offset_widths_agree(case, dtype):
-    """8- and 16-bit offsets store the same offsets, so the kernels gather the
-    same x entries and sum in the same order: identical results."""
+@pytest.mark.parametrize("case", ["narrowband_3000", "empty_rows", "banded_4000", "ragged",
+                                  "random_3000x8", "powerlaw_20000"])
+def test_delta16_code_widths_agree(case, dtype):
+    """8-bit delta codes (escapes included) and 16-bit offsets decode to the
+    same columns, so the kernels gather the same x entries and sum in the
+    same order: identical results, FP64 equal to the sequential sum."""
     build, m = CASES[case]
     rp, ci, v = build("random")
     x = synth.vector(m, 19)
@@ -134,16 +136,17 @@ def test_delta16_offset_widths_agree(case, dtype):
     S.spmv_set_delta16_layout(plan.handle, 1)
     y_auto = run(plan, S.V_DELTA16, x, dtype)
     bits = S.spmv_plan_query(plan.handle, 17)
-    print(f"case={case} dtype={dtype} automatic offset bits={bits}", flush=True)
     L = delta16_sliced_ref(rp, ci, v)
-    assert bits == delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"])
-    assert bits == (16 if case == "random_3000x8" else 8)
+    C = delta8_codes_ref(rp, ci, L)
+    print(f"case={case} dtype={dtype} automatic bits={bits} escapes={C['escapes']}", flush=True)
+    assert bits == delta16_offset_bits_ref(L["nnz_offset"], int(C["E"].sum()))
     assert within_tolerance(y_auto, y_ref, scale, TOL[dtype])[0]
-    S.spmv_set_delta16_offset_bits(plan.handle, 16)
-    assert np.array_equal(run(plan, S.V_DELTA16, x, dtype), y_auto)
-    if bits == 8:
-        S.spmv_set_delta16_offset_bits(plan.handle, 8)
-        assert np.array_equal(run(plan, S.V_DELTA16, x, dtype), y_auto)
+    if dtype == S.SPMV_F64:
+        assert np.array_equal(y_auto, spmv_seq(rp, ci, v, x))
+    for req in (16, 8):
+        S.spmv_set_delta16_offset_bits(plan.handle, req)
+        assert S.spmv_plan_query(plan.handle, 17) == req
+        assert np.array_equal(run(plan, S.V_DELTA16, x, dtype), y_auto), req
     plan.close()
 
 

@@ -6,8 +6,9 @@ import numpy as np
 import pytest
 
 import synth
-from oracle.encode import (bf16_bits_to_f64, delta16_layout_ref, delta16_offset_bits_ref,
-                           delta16_ref, delta16_sliced_ref, merge_search_ref, merge_walk_ref,
+from oracle.encode import (bf16_bits_to_f64, code_slot_ref, delta8_codes_ref, delta8_decode_ref,
+                           delta16_layout_ref, delta16_offset_bits_ref, delta16_ref,
+                           delta16_sliced_ref, merge_search_ref, merge_walk_ref,
                            partition_ref, slice_csr_ref, to_bf16_bits_ref, to_f32_ref)
 from oracle.spmv import spmv_seq
 
@@ -122,13 +123,13 @@ def dense_band(n, w):
     return rp, np.concatenate(cols)
 
 
-@pytest.mark.parametrize("w, bits", [(96, 8), (97, 16), (20, 8)])
-def test_delta16_offset_bits_dense_band(w, bits):
+@pytest.mark.parametrize("w", [20, 96, 200, 1000])
+def test_delta8_dense_band(w):
     """A dense band of half-width w has 2w + 1 > 32 diagonals, so every slice
-    stores offsets.  Slice s spans from max(0, 64 s - w) to
-    min(n - 1, 64 s + 63 + w); inside the matrix that is 2 w + 63 columns
-    apart, which fits 8-bit offsets up to w = 96.  There the offset of the
-    k-th nonzero of lane l is l + k (column 64 s + l - w + k)."""
+    stores codes.  Row r holds columns max(0, r - w) .. min(n - 1, r + w):
+    consecutive columns differ by 1, and the first lies max(0, r - w) -
+    max(0, 64 s - w) <= 63 past the slice's reference column, so no code
+    escapes, whatever the band's width, and the matrix takes 8 bits."""
     n = 640
     rp, ci = dense_band(n, w)
     L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
@@ -136,28 +137,71 @@ def test_delta16_offset_bits_dense_band(w, bits):
     assert L["kind"].tolist() == [0] * ns
     span = [min(n - 1, 64 * s + 63 + w) - max(0, 64 * s - w) for s in range(ns)]
     assert L["span"].tolist() == span
-    assert delta16_offset_bits_ref(L["kind"], L["span"], L["nnz_offset"]) == bits
-    for s in range(ns):
-        if 64 * s - w < 0 or 64 * s + 63 + w > n - 1:
-            continue  # clipped at the matrix edge
-        for lane in range(64):
-            for k in range(2 * w + 1):
-                slot = 128 * L["units"][s] + 128 * (k // 2) + 2 * lane + k % 2
-                assert L["off"][slot] == lane + k
+    C = delta8_codes_ref(rp, ci, L)
+    assert C["E"].tolist() == [0] * ns and C["escapes"] == 0 and len(C["esc"]) == 0
+    assert delta16_offset_bits_ref(L["nnz_offset"], int(C["E"].sum())) == 8
+    for r in range(n):
+        s, lane = divmod(r, 64)
+        length = rp[r + 1] - rp[r]
+        for k in range(length):
+            slot = 128 * (L["units"][s] + s) + 256 * (k // 4) + 4 * lane + k % 4
+            want = max(0, r - w) - max(0, 64 * s - w) if k == 0 else 1
+            assert C["codes"][slot] == want, (r, k)
+    # every byte is a code or padding: the nonzero codes are exactly the
+    # nonzeros' (each at least 1 after a row's first)
+    assert len(C["codes"]) == L["slots"] + 128 * ns
+
+
+def test_delta8_escape_closed_form():
+    """Row l of a 64-row matrix holds columns 3 l and 3 l + 254 + (l mod 2):
+    128 diagonals, one offset slice with reference column 0.  Codes: 3 l, then
+    254 (even l) or the escape (odd l, a gap of 255), whose column goes to
+    esc[l]; E = 1, 32 escapes.  8 bits would need 256 escape bytes for 128
+    codes, so the matrix keeps 16 bits."""
+    rp = np.arange(0, 129, 2)
+    ci = np.array([c for l in range(64) for c in (3 * l, 3 * l + 254 + l % 2)])
+    L = delta16_sliced_ref(rp, ci, np.ones(128))
+    assert L["kind"].tolist() == [0] and L["width"].tolist() == [2] and L["base"].tolist() == [0]
+    C = delta8_codes_ref(rp, ci, L)
+    assert len(C["codes"]) == 256  # width 2 plus the spare unit: one group of four
+    assert C["codes"][0:256:4].tolist() == [3 * l for l in range(64)]
+    assert C["codes"][1:256:4].tolist() == [254 + l % 2 for l in range(64)]
+    assert not C["codes"][2:256:4].any() and not C["codes"][3:256:4].any()
+    assert code_slot_ref(0, 0, 5, 1) == 21 and code_slot_ref(3, 2, 0, 6) == 128 * 5 + 256 + 2
+    assert C["E"].tolist() == [1] and C["eunits"].tolist() == [0] and C["escapes"] == 32
+    assert C["esc"].tolist() == [3 * l + 255 if l % 2 else 0 for l in range(64)]
+    assert delta16_offset_bits_ref(L["nnz_offset"], 1) == 16
+
+
+def test_delta8_decode_round_trip():
+    """Decoding the codes gives back every offset-slice row's columns."""
+    mats = [c for c in cases(seed=13)]
+    mats += [synth.banded(700, 48, 300, seed=3), synth.uniform_random(200, 70000, 9, seed=4),
+             synth.powerlaw(900, 109, 400, seed=5)]
+    for rp, ci, v in mats:
+        rp, ci = np.asarray(rp), np.asarray(ci)
+        L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
+        C = delta8_codes_ref(rp, ci, L)
+        L = dict(L, eunits=C["eunits"])
+        rows = delta8_decode_ref(C["codes"], C["esc"], L, np.diff(rp))
+        for i in range(len(rp) - 1):
+            if not L["kind"][i // 64]:
+                assert rows[i] == ci[rp[i]:rp[i + 1]].tolist(), i
+        n_esc = sum(1 for i in range(len(rp) - 1) if not L["kind"][i // 64]
+                    for j in range(rp[i], rp[i + 1])
+                    if ci[j] - (ci[j - 1] if j > rp[i] else L["base"][i // 64]) >= 255)
+        assert C["escapes"] == n_esc
 
 
 def test_delta16_offset_bits_rule():
-    # no offset slices at all (a tridiagonal matrix: 3 diagonals): 16 bits
+    assert delta16_offset_bits_ref(0, 0) == 16          # nothing to store
+    assert delta16_offset_bits_ref(100, 0) == 8
+    assert delta16_offset_bits_ref(512, 1) == 8          # 256 escape bytes = half the saving
+    assert delta16_offset_bits_ref(511, 1) == 16
+    # a tridiagonal matrix has only diagonal slices: 16 bits
     rp, ci = dense_band(200, 1)
     L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
-    assert L["nnz_offset"] == 0 and delta16_offset_bits_ref(L["kind"], L["span"], 0) == 16
-    # diagonal slices do not count: a slice may span far more than 256 columns
-    # if it stores diagonals
-    kind = np.array([1, 0, 3])
-    assert delta16_offset_bits_ref(kind, np.array([100000, 255, 70000]), 5) == 8
-    assert delta16_offset_bits_ref(kind, np.array([0, 256, 0]), 5) == 16
-    # an empty offset slice spans 0
-    assert delta16_offset_bits_ref(np.array([0, 0]), np.array([0, 17]), 3) == 8
+    assert L["nnz_offset"] == 0 and delta16_offset_bits_ref(0, 0) == 16
 
 
 def test_delta16_sliced_places_every_nonzero_once():
