@@ -423,16 +423,17 @@ def sweep_spec(seed: int, n_min: float = 1e4, n_max: float = 4e6,
     """One matrix of the mixed selector sweep (host-side parameters).
 
     N = floor(10**U[log10 n_min, log10 n_max]), d = 10**U[0, log10 d_max];
-    the pattern is chosen by ``seed % 4``: stencil (2D-5, 2D-9, 3D-7, 3D-27),
-    banded with half width d * {1, 4, 16, 64}, random, or power-law (Pareto
-    1.5 scaled to mean d, longest row N/5).  Only these host-side parameters
-    use transcendental functions; per-row draws are exact.
+    the pattern is chosen by ``seed % 5``: stencil (2D-5, 2D-9, 3D-7, 3D-27),
+    banded with half width d * {1, 4, 16, 64}, random, power-law (Pareto
+    1.5 scaled to mean d, longest row N/5), or short rows (the diagonal plus
+    (i, i+1) for about half the rows; d unused).  Only these host-side
+    parameters use transcendental functions; per-row draws are exact.
     """
     u = [u01_int(h_int(seed, ST_SWEEP, i)) for i in range(4)]
     n = int(math.floor(10 ** (math.log10(n_min)
                               + u[0] * (math.log10(n_max) - math.log10(n_min)))))
     d = 10 ** (u[1] * math.log10(d_max))
-    kind = seed % 4
+    kind = seed % 5
     sub = min(3, int(u[2] * 4))
     d16 = max(16, int(round(d * 16)))
     if kind == 0:
@@ -448,6 +449,8 @@ def sweep_spec(seed: int, n_min: float = 1e4, n_max: float = 4e6,
     if kind == 2:
         return MatrixSpec("random_rows", {"n": n, "d16": d16}, seed, seed,
                           f"sweep{seed}_random_{n}")
+    if kind == 4:
+        return MatrixSpec("short_rows", {"n": n}, seed, seed, f"sweep{seed}_shortrows_{n}")
     p16 = max(1, int(round(16 * d / 3)))
     return MatrixSpec("powerlaw", {"n": n, "p16": p16, "cap": max(1, n // 5),
                                    "force_long": False},
