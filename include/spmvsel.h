@@ -243,7 +243,8 @@ spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
  * one, 16 bytes per 64-row slice (width, unit offset, reference column,
  * kind) and 128 per diagonal slice (its diagonals), with 1 or 2 index bytes
  * (the code width) only for the nonzeros of offset slices, plus with 8-bit
- * codes 4 bytes per escaped column and 4 per slice (its eunits entry) (a
+ * codes 4 bytes per escaped column and 4 per offset slice (its eunits
+ * entry) (a
  * row's mask in a diagonal slice takes
  * the place of its row pointer).  The layout is decided here if needed; the
  * streamed form is counted where DELTA16 is infeasible.  Traffic a variant adds on top (the XBLOCK_LDS slice row

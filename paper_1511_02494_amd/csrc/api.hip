@@ -1093,11 +1093,11 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
             // offsets only in offset slices; width, units, base and kind per
             // slice, 32 diagonals per diagonal slice; a row's mask replaces
             // its row pointer in diagonal slices
-            // 8-bit codes: 4 bytes per escaped column and 4 per slice (its
-            // first escape unit)
+            // 8-bit codes: 4 bytes per escaped column and 4 per offset slice
+            // (its first escape unit, read only there)
             const bool d8 = P->d16_offw == 8;
             *bytes = 4 * (P->n + 1) + vb * P->nnz + (d8 ? 1 : 2) * P->d16_nnz_off +
-                     (d8 ? 4 * P->d16_nesc + 4 * P->d16_nsl : 0) + xb * P->m + xb * P->n +
+                     (d8 ? 4 * P->d16_nesc + 4 * (P->d16_nsl - P->d16_ndiag) : 0) + xb * P->m + xb * P->n +
                      16 * P->d16_nsl + 4 * kSellMaxDiag * P->d16_ndiag;
             return SPMV_OK;
         }

@@ -131,11 +131,41 @@ def counters_main(argv):
     print(f"wrote {a.out}")
 
 
+def stats_main(argv):
+    """Kernel-time table of one --kernel-trace --stats run, limited to the
+    kernels whose names start with one of --kernels (all if none given)."""
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dir", required=True)
+    ap.add_argument("--cmd", required=True)
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--kernels", nargs="*", default=[])
+    ap.add_argument("--notes", default="")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    rows = [r for r in read_stats(a.dir)
+            if not a.kernels or any(r["name"].startswith(k) for k in a.kernels)]
+    with open(a.out, "w") as f:
+        f.write(f"# {a.title}\n\nWorkload: {a.workload}\n\nCommand (repository root, one "
+                f"MI355X):\n\n    {a.cmd}\n\n")
+        if a.notes:
+            f.write(a.notes + "\n\n")
+        f.write("| kernel | calls | total ms | average us | min us | max us | % of all |\n"
+                "|---|---:|---:|---:|---:|---:|---:|\n")
+        for r in rows:
+            f.write(f"| `{_short(r['name'])}` | {r['calls']} | {r['total_ms']:.2f} | "
+                    f"{r['avg_us']:.1f} | {r['min_us']:.1f} | {r['max_us']:.1f} | "
+                    f"{r['pct']:.2f} |\n")
+    print(f"wrote {a.out}")
+
+
 def main(argv=None):
     import sys
     argv = sys.argv[1:] if argv is None else argv
     if argv and argv[0] == "counters":
         return counters_main(argv[1:])
+    if argv and argv[0] == "stats":
+        return stats_main(argv[1:])
     ap = argparse.ArgumentParser()
     for k in ("stats", "fetch", "write", "cmd-stats", "cmd-fetch", "cmd-write", "workload",
               "stats-md", "traffic-md", "traffic-json"):

@@ -107,3 +107,49 @@ def test_fullsize_selected_matches_oracle(spec):
     ys = y.cpu().numpy()[rows]
     assert np.all(np.abs(ys - y_ref) <= 1e-12 * scale), S.VARIANTS[info["variant"]]
     plan.close()
+
+
+def test_fullsize_delta_codes():
+    """The code-width report's wider band at its size (2M rows, 30..90
+    nonzeros per row, half width 200; the sliced layout forced as the report
+    does): 8-bit delta codes, taken automatically, and 16-bit offsets on
+    sampled rows against the correctly rounded reference, equal to the
+    sequential sum in FP64, and the two widths giving the same y in every
+    dtype."""
+    rp, ci, v = synth.banded(2_000_000, 960, 200, seed=9)
+    n = len(rp) - 1
+    x = synth.vector(n, 10)
+    rows = sample_rows(rp, np.random.default_rng(2))
+    y_ref, scale = spmv_exact(rp, ci, v, x, rows)
+    y_seq = spmv_seq_rows(rp, ci, v, x, rows)
+    r_t, c_t = dev(rp), dev(ci)
+    print(f"\nband_2000000_d60_w200: nnz={len(ci)} sampled rows={len(rows)}", flush=True)
+    for dtype in (S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16):
+        v_t = upload_values(v, dtype)
+        x_t = dev(x) if dtype == S.SPMV_F64 else dev(x.astype(np.float32))
+        tdt = torch.float64 if dtype == S.SPMV_F64 else torch.float32
+        plan = S.Plan(r_t, c_t, v_t, n, dtype, nnz=len(ci))
+        S.spmv_set_delta16_layout(plan.handle, 1)
+        ys = {}
+        for req in (0, 16):
+            S.spmv_set_delta16_offset_bits(plan.handle, req)
+            plan.set_variant(S.V_DELTA16)
+            bits = plan.query(17)
+            y = torch.full((n,), float("nan"), dtype=tdt, device=DEV)
+            plan.execute(x_t, y)
+            torch.cuda.synchronize()
+            assert not torch.isnan(y).any().item(), bits
+            got = y.cpu().numpy()[rows].astype(np.float64)
+            err = np.abs(got - y_ref)
+            rel = float(np.max(np.where(scale > 0, err / np.where(scale > 0, scale, 1), 0)))
+            print(f"  dtype={['f64', 'f32', 'bf16'][dtype]:>4s} {bits}-bit codes "
+                  f"(escapes {plan.query(20)}) max |y - y_ref| / sum|a||x| = {rel:.3e}", flush=True)
+            assert np.all(err <= TOL[dtype] * scale), (bits, dtype, rel)
+            if dtype == S.SPMV_F64:
+                assert np.array_equal(got, y_seq), bits
+            ys[bits] = y
+        assert sorted(ys) == [8, 16]
+        assert torch.equal(ys[8], ys[16])
+        plan.close()
+        del v_t, x_t, ys
+        torch.cuda.empty_cache()
