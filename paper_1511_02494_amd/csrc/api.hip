@@ -382,7 +382,7 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     std::vector<int32_t> eunits;
     int offw = 16;
     if (layout == 1 && P->d16_offw_req != 16 && (nnz_off > 0 || P->d16_offw_req == 8)) {
-        eunits.assign((size_t)nsl, 0);
+        eunits.assign(nb / 4 + 1, 0);  // S + 1 entries (nb covers at least one slice)
         if (max_span >= 255) {
             DevBuf dE, dN;
             SPMV_TRY(dE.alloc(nb));
@@ -398,13 +398,15 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
                 esc_units += hE[(size_t)k];
                 nesc += hN[(size_t)k];
             }
+            eunits[(size_t)nsl] = (int32_t)esc_units;
         }
         const bool want8 = P->d16_offw_req == 8 || 512 * esc_units <= nnz_off;
         if (want8) offw = 8;
     }
     if (offw == 8) {
-        SPMV_TRY(P->d16s_eunits.alloc(nb));
-        SPMV_HIP(hipMemcpyAsync(P->d16s_eunits.p, eunits.data(), nb, hipMemcpyHostToDevice, S(P)));
+        SPMV_TRY(P->d16s_eunits.alloc(nb + 4));
+        SPMV_HIP(hipMemcpyAsync(P->d16s_eunits.p, eunits.data(), nb + 4, hipMemcpyHostToDevice,
+                                S(P)));
         SPMV_TRY(sync(P));  // the host vector goes out of scope
     } else {
         P->d16s_eunits.release();
@@ -627,15 +629,18 @@ spmv_status_t build_format(spmv_plan *P, int v) {
             SPMV_HIP(hipMemsetAsync(P->d16s_val.p, 0, slots * vbytes(P->dtype) + 16, S(P)));
             SPMV_HIP(launch_sliced_scatter(*P, P->d16s_units.as<int32_t>(), P->d16s_base.as<int32_t>(),
                                            P->d16s_kind.as<int32_t>(), P->d16s_diag.as<int32_t>(),
-                                           d8 ? nullptr : P->d16s_off.as<uint16_t>(), P->d16s_val.p,
+                                           d8 ? nullptr : P->d16s_off.as<uint16_t>(),
+                                           d8 ? P->d16s_off.as<uint8_t>() : nullptr, P->d16s_val.p,
                                            P->d16s_mask.as<uint32_t>(), S(P)));
             if (d8) {
                 const size_t eb = (size_t)P->d16_esc_units * kSellRows * 4 + 16;
                 SPMV_TRY(P->d16s_esc.alloc(eb));
                 SPMV_HIP(hipMemsetAsync(P->d16s_esc.p, 0, eb, S(P)));
-                SPMV_HIP(launch_sliced_codes(*P, P->d16s_units.as<int32_t>(), P->d16s_base.as<int32_t>(),
-                                             P->d16s_kind.as<int32_t>(), P->d16s_eunits.as<int32_t>(),
-                                             P->d16s_off.as<uint8_t>(), P->d16s_esc.as<int32_t>(), S(P)));
+                if (P->d16_esc_units > 0)
+                    SPMV_HIP(launch_sliced_escape_cols(*P, P->d16s_base.as<int32_t>(),
+                                                       P->d16s_kind.as<int32_t>(),
+                                                       P->d16s_eunits.as<int32_t>(),
+                                                       P->d16s_esc.as<int32_t>(), S(P)));
             } else {
                 P->d16s_esc.release();
             }

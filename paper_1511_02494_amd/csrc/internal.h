@@ -201,17 +201,17 @@ hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16
 hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
                                int32_t *kind, int32_t *diag, int32_t *snnz, int32_t *span,
                                hipStream_t s);
-// off may be null: the values and masks are written, no 16-bit offsets
+// values, masks, and the 16-bit offsets or the 8-bit codes (off or codes
+// null: not written)
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
                                  const int32_t *kind, const int32_t *diag, uint16_t *off,
-                                 void *vals, uint32_t *mask, hipStream_t s);
+                                 uint8_t *codes, void *vals, uint32_t *mask, hipStream_t s);
 // per offset slice: the most escapes of one of its rows (E) and their sum
 hipError_t launch_sliced_escapes(const spmv_plan &P, const int32_t *base, const int32_t *kind,
                                  int32_t *E, int32_t *nesc, hipStream_t s);
-// 8-bit delta codes of the offset slices and their escaped columns
-hipError_t launch_sliced_codes(const spmv_plan &P, const int32_t *units, const int32_t *base,
-                               const int32_t *kind, const int32_t *eunits, uint8_t *codes,
-                               int32_t *esc, hipStream_t s);
+// the escaped columns of the 8-bit codes (eunits: S + 1 prefix sums of E)
+hipError_t launch_sliced_escape_cols(const spmv_plan &P, const int32_t *base, const int32_t *kind,
+                                    const int32_t *eunits, int32_t *esc, hipStream_t s);
 hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t panels,
                            unsigned long long *d_max, hipStream_t s);
 hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,

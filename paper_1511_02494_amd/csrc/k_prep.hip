@@ -151,6 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
                                                            const int32_t *__restrict__ kind,
                                                            const int32_t *__restrict__ diag,
                                                            uint16_t *__restrict__ off,
+                                                           uint8_t *__restrict__ codes,
                                                            V *__restrict__ vals,
                                                            uint32_t *__restrict__ mask) {
     constexpr int kWaves = kBlock / kSellRows;
@@ -191,9 +192,16 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
             }
             k = a;
             atomicOr(&s_mask[lo], 1u << k);
-        } else if (off) {
-            off[2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1)] =
-                (uint16_t)(ci[j] - base[sl]);
+        } else {
+            const int32_t c = ci[j];
+            if (off)
+                off[2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1)] =
+                    (uint16_t)(c - base[sl]);
+            if (codes) {  // 8-bit delta code (k_sliced_escape_cols stores escaped columns)
+                const int32_t d = c - (k > 0 ? ci[j - 1] : base[sl]);
+                codes[2 * kSellRows * ((int64_t)units[sl] + sl) + 4 * kSellRows * (int64_t)(k / 4) +
+                      4 * lane + (k & 3)] = (uint8_t)(d >= 255 ? 255 : d);
+            }
         }
         vals[2 * kSellRows * ((int64_t)units[sl] + k / 2) + 2 * lane + (k & 1)] = val[j];
     }
@@ -203,37 +211,41 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
 
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,
                                  const int32_t *kind, const int32_t *diag, uint16_t *off,
-                                 void *vals, uint32_t *mask, hipStream_t s) {
+                                 uint8_t *codes, void *vals, uint32_t *mask, hipStream_t s) {
     if (P.n == 0) return hipSuccess;  // (with no nonzeros it still writes the zero masks)
     const dim3 g((unsigned)((P.n + kBlock - 1) / kBlock));
     switch (P.dtype) {
     case SPMV_F64:
         hipLaunchKernelGGL(k_sliced_scatter<double>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
-                           (const double *)P.val, units, base, kind, diag, off, (double *)vals, mask);
+                           (const double *)P.val, units, base, kind, diag, off, codes, (double *)vals,
+                           mask);
         break;
     case SPMV_F32:
         hipLaunchKernelGGL(k_sliced_scatter<float>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
-                           (const float *)P.val, units, base, kind, diag, off, (float *)vals, mask);
+                           (const float *)P.val, units, base, kind, diag, off, codes, (float *)vals,
+                           mask);
         break;
     default:
         hipLaunchKernelGGL(k_sliced_scatter<uint16_t>, g, dim3(kBlock), 0, s, P.n, P.rowptr,
                            P.colind, (const uint16_t *)P.val, units, base, kind, diag, off,
-                           (uint16_t *)vals, mask);
+                           codes, (uint16_t *)vals, mask);
     }
     return hipGetLastError();
 }
 
-// 8-bit delta coding of the offset slices (Section 3.3).  A wavefront per
-// slice, a lane per row: the lane walks its row in column order; the code of
-// a nonzero is its column minus the previous one (the slice's reference
-// column before the first), or the escape code 255 when that gap is 255 or
-// more, in which case the column itself is stored.  k_sliced_escapes counts
-// the escapes, k_sliced_codes writes codes and escaped columns; the e-th
-// escape of lane l of slice s is esc[64 (eunits[s] + e) + l].  Codes go in
-// groups of four positions per lane (a 4-byte load per lane per step): code
-// k of lane l is byte 128 (units[s] + s) + 256 (k / 4) + 4 l + k % 4, one
-// spare unit per slice covering a width that is not a multiple of 4.
-// Neither kernel has a barrier, so whole wavefronts leave early.
+// 8-bit delta coding of the offset slices (Section 3.3).  The code of a
+// nonzero is its column minus the previous one of its row (the slice's
+// reference column before the first), or the escape code 255 when that gap
+// is 255 or more, in which case the column itself is stored: the e-th escape
+// of lane l of slice s is esc[64 (eunits[s] + e) + l].  Codes go in groups
+// of four positions per lane (a 4-byte load per lane per step): code k of
+// lane l is byte 128 (units[s] + s) + 256 (k / 4) + 4 l + k % 4, one spare
+// unit per slice covering a width that is not a multiple of 4.  The scatter
+// kernel writes the codes, nonzero by nonzero.  Here a wavefront per slice,
+// a lane per row, walks the rows in column order: k_sliced_escapes counts
+// the escapes (the per-slice maximum E and the sum), k_sliced_escape_cols
+// stores the escaped columns of the slices that have any.  Neither kernel
+// has a barrier, so whole wavefronts leave early.
 constexpr int kEscape = 255;
 
 __global__ __launch_bounds__(kBlock) void k_sliced_escapes(int64_t n, int64_t nsl,
@@ -250,7 +262,15 @@ __global__ __launch_bounds__(kBlock) void k_sliced_escapes(int64_t n, int64_t ns
     int cnt = 0;
     if (kind[sl] == 0 && r < n) {
         int32_t prev = base[sl];  // the slice's smallest column: no gap is negative
-        for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+        int32_t j = rp[r];
+        const int32_t b = rp[r + 1];
+        for (; j + 4 <= b; j += 4) {  // four loads in flight per lane
+            const int32_t c0 = ci[j], c1 = ci[j + 1], c2 = ci[j + 2], c3 = ci[j + 3];
+            cnt += (c0 - prev >= kEscape) + (c1 - c0 >= kEscape) + (c2 - c1 >= kEscape) +
+                   (c3 - c2 >= kEscape);
+            prev = c3;
+        }
+        for (; j < b; ++j) {
             const int32_t c = ci[j];
             cnt += (c - prev >= kEscape) ? 1 : 0;
             prev = c;
@@ -269,34 +289,27 @@ __global__ __launch_bounds__(kBlock) void k_sliced_escapes(int64_t n, int64_t ns
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sliced_codes(int64_t n, int64_t nsl,
-                                                         const int32_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ ci,
-                                                         const int32_t *__restrict__ units,
-                                                         const int32_t *__restrict__ base,
-                                                         const int32_t *__restrict__ kind,
-                                                         const int32_t *__restrict__ eunits,
-                                                         uint8_t *__restrict__ codes,
-                                                         int32_t *__restrict__ esc) {
+// eunits has S + 1 entries (the last is the total), so E_s = eunits[s + 1] -
+// eunits[s]; slices without escapes are skipped
+__global__ __launch_bounds__(kBlock) void k_sliced_escape_cols(int64_t n, int64_t nsl,
+                                                               const int32_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ ci,
+                                                               const int32_t *__restrict__ base,
+                                                               const int32_t *__restrict__ kind,
+                                                               const int32_t *__restrict__ eunits,
+                                                               int32_t *__restrict__ esc) {
     const int64_t sl = blockIdx.x * (int64_t)(kBlock / kSellRows) + threadIdx.x / kSellRows;
-    if (sl >= nsl || kind[sl] != 0) return;
+    if (sl >= nsl || kind[sl] != 0 || eunits[sl + 1] == eunits[sl]) return;
     const int lane = threadIdx.x & (kSellRows - 1);
     const int64_t r = sl * kSellRows + lane;
     if (r >= n) return;
-    const int64_t o = 2 * kSellRows * ((int64_t)units[sl] + sl) + 4 * lane;
     int64_t q = (int64_t)kSellRows * eunits[sl] + lane;  // this lane's next escape entry
     int32_t prev = base[sl];
-    const int32_t a = rp[r], b = rp[r + 1];
-    for (int32_t j = a; j < b; ++j) {
-        const int k = j - a;
+    for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
         const int32_t c = ci[j];
-        const int64_t slot = o + 4 * kSellRows * (int64_t)(k / 4) + (k & 3);
         if (c - prev >= kEscape) {
-            codes[slot] = (uint8_t)kEscape;
             esc[q] = c;
             q += kSellRows;
-        } else {
-            codes[slot] = (uint8_t)(c - prev);
         }
         prev = c;
     }
@@ -312,14 +325,13 @@ hipError_t launch_sliced_escapes(const spmv_plan &P, const int32_t *base, const 
     return hipGetLastError();
 }
 
-hipError_t launch_sliced_codes(const spmv_plan &P, const int32_t *units, const int32_t *base,
-                               const int32_t *kind, const int32_t *eunits, uint8_t *codes,
-                               int32_t *esc, hipStream_t s) {
+hipError_t launch_sliced_escape_cols(const spmv_plan &P, const int32_t *base, const int32_t *kind,
+                                    const int32_t *eunits, int32_t *esc, hipStream_t s) {
     const int64_t nsl = (P.n + kSellRows - 1) / kSellRows;
     if (nsl == 0) return hipSuccess;
     const int64_t per = kBlock / kSellRows;
-    hipLaunchKernelGGL(k_sliced_codes, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0, s,
-                       P.n, nsl, P.rowptr, P.colind, units, base, kind, eunits, codes, esc);
+    hipLaunchKernelGGL(k_sliced_escape_cols, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0,
+                       s, P.n, nsl, P.rowptr, P.colind, base, kind, eunits, esc);
     return hipGetLastError();
 }
 
