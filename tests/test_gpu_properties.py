@@ -1,6 +1,7 @@
-"""Property test through the C ABI: generated tiny integer-valued CSR
+"""Property tests through the C ABI: generated tiny integer-valued CSR
 matrices (Hypothesis) give the dense product exactly in every feasible
-variant, both delta16 layouts and every x-block slice count (GPU)."""
+variant, both delta16 layouts, both delta16 code widths (columns spread so
+that codes escape) and every x-block slice count (GPU)."""
 import numpy as np
 import pytest
 
@@ -11,7 +12,7 @@ torch = pytest.importorskip("torch")
 hypothesis = pytest.importorskip("hypothesis")
 from hypothesis import given, settings, strategies as st  # noqa: E402
 from gpu_util import make_plan, run  # noqa: E402
-from test_oracle_properties import csr  # noqa: E402
+from test_oracle_properties import csr, spread_csr  # noqa: E402
 
 
 @settings(max_examples=25, deadline=None, derandomize=True)
@@ -31,4 +32,18 @@ def test_every_variant_gives_the_dense_product(A):
     for slices in (2, 8):
         S.spmv_set_xblock_slices(plan.handle, slices)
         assert np.array_equal(run(plan, S.V_XBLOCK_LDS, x), want), slices
+    plan.close()
+
+
+@settings(max_examples=25, deadline=None, derandomize=True)
+@given(spread_csr())
+def test_delta16_code_widths_give_the_dense_product(A):
+    rowptr, colind, val, m, dense, x, xs = A
+    want = dense @ x  # integers: exact
+    plan = make_plan(rowptr, colind, val, m)
+    if (S.spmv_variant_mask(plan.handle) >> S.V_DELTA16) & 1:
+        S.spmv_set_delta16_layout(plan.handle, 1)
+        for bits in (8, 16, 0):
+            S.spmv_set_delta16_offset_bits(plan.handle, bits)
+            assert np.array_equal(run(plan, S.V_DELTA16, xs), want), bits
     plan.close()

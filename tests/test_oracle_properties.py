@@ -10,8 +10,8 @@ import pytest
 hypothesis = pytest.importorskip("hypothesis")
 from hypothesis import given, settings, strategies as st  # noqa: E402
 
-from oracle.encode import (delta16_ref, delta16_sliced_ref, merge_search_ref, merge_walk_ref,
-                           slice_csr_ref)
+from oracle.encode import (delta8_codes_ref, delta16_ref, delta16_sliced_ref, merge_search_ref,
+                           merge_walk_ref, slice_csr_ref)
 from oracle.spmv import spmv_seq
 
 SETTINGS = settings(max_examples=60, deadline=None, derandomize=True)
@@ -32,6 +32,18 @@ def csr(draw, max_rows=70, max_cols=50):
     val = dense[mask]
     x = rng.integers(-8, 9, m).astype(np.float64)
     return rowptr, colind, val, m, dense, x
+
+
+@st.composite
+def spread_csr(draw):
+    """A csr() matrix with its columns spread k apart (k = 1, 97 or 301), so
+    that consecutive columns of a row are often 255 or more apart; xs is x
+    placed at the spread columns (zeros between), so A_spread xs = dense x."""
+    rowptr, colind, val, m, dense, x = draw(csr(max_rows=150, max_cols=60))
+    k = draw(st.sampled_from([1, 97, 301]))
+    xs = np.zeros(m * k)
+    xs[::k] = x
+    return rowptr, colind * k, val, m * k, dense, x, xs
 
 
 @SETTINGS
@@ -98,3 +110,30 @@ def test_column_slices_put_back_the_matrix(A, S):
                 back[i, c] = True
         start += rp[n]
     assert start == len(colind) and np.array_equal(back, dense != 0)
+
+
+@SETTINGS
+@given(spread_csr())
+def test_delta8_codes_read_back_as_the_columns(A):
+    """Walking a row's 8-bit codes from the slice's reference column, adding
+    each code or taking the lane's next escape entry on code 255, at the
+    documented places (code k of lane l of slice s at 128 (u_s + s) +
+    256 (k // 4) + 4 l + k % 4, escape e at 64 (eunits_s + e) + l), gives
+    the row's columns; a row uses at most E_s escapes."""
+    rowptr, colind, val, m, dense, x, xs = A
+    L = delta16_sliced_ref(rowptr, colind, val)
+    C = delta8_codes_ref(rowptr, colind, L)
+    for i in range(len(rowptr) - 1):
+        s, lane = divmod(i, 64)
+        if L["kind"][s]:
+            continue
+        c, e = int(L["base"][s]), 0
+        for k in range(rowptr[i + 1] - rowptr[i]):
+            code = int(C["codes"][128 * (int(L["units"][s]) + s) + 256 * (k // 4) + 4 * lane + k % 4])
+            if code == 255:
+                c = int(C["esc"][64 * (int(C["eunits"][s]) + e) + lane])
+                e += 1
+            else:
+                c += code
+            assert c == colind[rowptr[i] + k], (i, k)
+        assert e <= C["E"][s]
