@@ -1,36 +1,39 @@
 """Full-size parity: the four FP64 class matrices at the sizes bench.py times.
 
-Inputs come from the seeded CPU generator (never from the library); every
+Inputs come from the seeded CPU generator (never from the library).  Every
 feasible variant runs in the bench's launch configuration (the plan's own
-parameters) and sampled rows are compared with the correctly rounded FP64
-reference computed row by row, plus whole-vector properties (no NaN, exact
-zeros on empty rows, determinism).  The precision path (FP32 / BF16 values,
-FP32 x and accumulation) is checked the same way against the FP64 reference
-of the original data, and the error table is printed.
+parameters), and EVERY row of y is compared with the oracle:
+
+* against the accuracy reference y_ref (Ogita-Rump-Oishi Dot2 of the
+  original FP64 data, as accurate as a twice-precision sum rounded once):
+  |y_i - y_ref,i| <= tol * sum_j |a_ij| |x_j| with tol 1e-12 (FP64 values),
+  1e-5 (FP32 values), 1e-2 (BF16 values), and y_i = 0 where that scale is 0;
+* variants that sum every row in column order from +0 (plan query 21) equal
+  Algorithm 1's sequential sum bit for bit in FP64.
+
+The twelve features and their exact accumulators are compared bit for bit
+with the oracle's on the same matrices, for FP64 and FP32 plans (the miss
+feature and the working-set test depend on the x and value sizes), and on
+the 2M-row band of the code-width report.
 """
 import numpy as np
 import pytest
 
 import synth
 import paper_1511_02494_amd as S
+from oracle import cref
 from oracle.encode import to_bf16_bits_ref, to_f32_ref
-from oracle.spmv import spmv_exact, spmv_seq_rows
+from oracle.features import features_ref, row_quantities
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 from gpu_util import DEV, dev  # noqa: E402
 
 TOL = {S.SPMV_F64: 1e-12, S.SPMV_F32: 1e-5, S.SPMV_BF16: 1e-2}
-SEQ_ORDER = {S.V_CSR_SCALAR, S.V_SHORT_ROW, S.V_DELTA16}  # sum in column order
+DNAME = {S.SPMV_F64: "f64", S.SPMV_F32: "f32", S.SPMV_BF16: "bf16"}
 SPECS = synth.class_matrices(scale=1)
-
-
-def sample_rows(rp, rng, k=1500):
-    n = len(rp) - 1
-    L = np.diff(rp)
-    rows = set(rng.choice(n, size=min(k, n), replace=False).tolist())
-    rows |= {0, n - 1, int(np.argmax(L))}
-    return np.array(sorted(rows))
+ACC_KEYS = ["nnz_min", "nnz_max", None, "S_L2", "S_bw", "S_bw2", None, "S_q", "S_q2", None,
+            "S_miss", "NNZ"]
 
 
 def upload_values(v, dtype):
@@ -41,22 +44,53 @@ def upload_values(v, dtype):
     return dev(to_bf16_bits_ref(v).view(np.int16))
 
 
+def check_whole_vector(y, y_ref, scale, tol, what):
+    """Every row within tol * scale of the reference; exact zeros where the
+    scale is zero.  Returns the largest |y - y_ref| / scale."""
+    y = np.asarray(y, np.float64)
+    err = np.abs(y - y_ref)
+    bad = np.flatnonzero(err > tol * scale)
+    assert len(bad) == 0, (what, f"{len(bad)} rows out of tolerance, first {bad[:5].tolist()}",
+                           y[bad[:3]].tolist(), y_ref[bad[:3]].tolist())
+    zero = scale == 0
+    assert np.all(y[zero] == 0), (what, "nonzero result on a row whose scale is 0")
+    return float(np.max(np.where(scale > 0, err / np.where(scale > 0, scale, 1), 0.0))) if len(y) else 0.0
+
+
+def check_features(plan, rp, ci, n_cols, dtype, what):
+    vb = {S.SPMV_F64: 8, S.SPMV_F32: 4, S.SPMV_BF16: 2}[dtype]
+    xb = 8 if dtype == S.SPMV_F64 else 4
+    f_ref, acc_ref = features_ref(rp, ci, n_cols, val_bytes=vb, x_bytes=xb, y_bytes=xb)
+    feats, acc = plan.features()
+    assert feats == f_ref, (what, feats, f_ref)
+    mask64 = (1 << 64) - 1
+    for k, name in enumerate(ACC_KEYS):
+        if name is None:
+            continue
+        want = acc_ref[name]
+        if name in ("S_bw2", "S_q2"):  # u128 as (lo, hi) words
+            assert acc[k] == want & mask64 and acc[k + 1] == want >> 64, (what, name)
+        else:
+            assert acc[k] == want, (what, name, acc[k], want)
+    _, bw, _, _ = row_quantities(rp, ci, xb)
+    assert acc[2] == (int(bw.max()) if len(bw) else 0), (what, "bw_max")
+
+
 @pytest.mark.parametrize("spec", SPECS, ids=[s.name for s in SPECS])
 def test_fullsize_variants(spec):
     rp, ci, v = spec.build()
     n = len(rp) - 1
     x = spec.x(n)
-    rng = np.random.default_rng(0)
-    rows = sample_rows(rp, rng)
-    y_ref, scale = spmv_exact(rp, ci, v, x, rows)
-    y_seq = spmv_seq_rows(rp, ci, v, x, rows)
+    y_ref, scale = cref.dot2(rp, ci, v, x)
+    y_seq = cref.seq(rp, ci, v, x)
     r_t, c_t = dev(rp), dev(ci)
-    print(f"\n{spec.name}: n={n} nnz={len(ci)} sampled rows={len(rows)}", flush=True)
+    print(f"\n{spec.name}: n={n} nnz={len(ci)} (every row compared)", flush=True)
     for dtype in (S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16):
         v_t = upload_values(v, dtype)
         x_t = dev(x) if dtype == S.SPMV_F64 else dev(x.astype(np.float32))
         tdt = torch.float64 if dtype == S.SPMV_F64 else torch.float32
         plan = S.Plan(r_t, c_t, v_t, n, dtype, nnz=len(ci))
+        check_features(plan, rp, ci, n, dtype, f"{spec.name}/{DNAME[dtype]}")
         mask = plan.mask()
         runs = [(var, None) for var in range(6) if (mask >> var) & 1]
         if (mask >> S.V_DELTA16) & 1:  # the layout the rule did not pick, forced
@@ -67,21 +101,20 @@ def test_fullsize_variants(spec):
             plan.set_variant(var)
             y = torch.full((n,), float("nan"), dtype=tdt, device=DEV)
             plan.execute(x_t, y)
-            y2 = torch.empty_like(y)
+            y2 = torch.full((n,), float("nan"), dtype=tdt, device=DEV)
             plan.execute(x_t, y2)
             torch.cuda.synchronize()
-            assert not torch.isnan(y).any().item(), S.VARIANTS[var]
-            assert torch.equal(y, y2), f"{S.VARIANTS[var]} not deterministic"
-            ys = y.cpu().numpy()[rows].astype(np.float64)
-            err = np.abs(ys - y_ref)
-            rel = float(np.max(np.where(scale > 0, err / np.where(scale > 0, scale, 1), 0)))
             name = S.VARIANTS[var] + ("" if layout is None else f"/layout{layout}")
-            print(f"  dtype={['f64', 'f32', 'bf16'][dtype]:>4s} {name:>18s} "
-                  f"max |y - y_ref| / sum|a||x| = {rel:.3e}", flush=True)
-            assert np.all(err <= TOL[dtype] * scale), (name, dtype, rel)
-            assert np.all(ys[scale == 0] == 0)
-            if dtype == S.SPMV_F64 and var in SEQ_ORDER:
-                assert np.array_equal(ys, y_seq), name
+            assert torch.equal(y, y2), f"{name} not deterministic"
+            ys = y.cpu().numpy().astype(np.float64)
+            rel = check_whole_vector(ys, y_ref, scale, TOL[dtype], (name, DNAME[dtype]))
+            seq = dtype == S.SPMV_F64 and plan.query(21) == 1
+            if seq:
+                diff = np.flatnonzero(ys != y_seq)
+                assert len(diff) == 0, (name, "differs from the sequential sum on rows",
+                                        diff[:5].tolist())
+            print(f"  {DNAME[dtype]:>4s} {name:>18s} max |y - y_ref| / sum|a||x| = {rel:.3e}"
+                  f"{'  (= sequential sum)' if seq else ''}", flush=True)
             del y, y2
         plan.close()
         del v_t, x_t
@@ -91,7 +124,8 @@ def test_fullsize_variants(spec):
 @pytest.mark.parametrize("spec", SPECS, ids=[s.name for s in SPECS])
 def test_fullsize_selected_matches_oracle(spec):
     """The variant chosen by the learned selector, as bench.py runs it."""
-    if S.DEFAULT_MODEL and not __import__("os").path.exists(S.DEFAULT_MODEL):
+    import os
+    if not os.path.exists(S.DEFAULT_MODEL):
         pytest.skip("no trained model")
     S.spmv_model_load(S.DEFAULT_MODEL)
     rp, ci, v = spec.build()
@@ -102,33 +136,32 @@ def test_fullsize_selected_matches_oracle(spec):
     y = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
     plan.execute(dev(x), y)
     torch.cuda.synchronize()
-    rows = sample_rows(rp, np.random.default_rng(1), 800)
-    y_ref, scale = spmv_exact(rp, ci, v, x, rows)
-    ys = y.cpu().numpy()[rows]
-    assert np.all(np.abs(ys - y_ref) <= 1e-12 * scale), S.VARIANTS[info["variant"]]
+    y_ref, scale = cref.dot2(rp, ci, v, x)
+    check_whole_vector(y.cpu().numpy(), y_ref, scale, 1e-12, S.VARIANTS[info["variant"]])
     plan.close()
 
 
 def test_fullsize_delta_codes():
     """The code-width report's wider band at its size (2M rows, 30..90
     nonzeros per row, half width 200; the sliced layout forced as the report
-    does): 8-bit delta codes, taken automatically, and 16-bit offsets on
-    sampled rows against the correctly rounded reference, equal to the
-    sequential sum in FP64, and the two widths giving the same y in every
-    dtype."""
+    does): features bit-exact for FP64 and FP32 plans; 8-bit delta codes,
+    taken automatically, and 16-bit offsets on every row against the
+    accuracy reference, equal to the sequential sum in FP64, and the two
+    widths giving the same y in every dtype."""
     rp, ci, v = synth.banded(2_000_000, 960, 200, seed=9)
     n = len(rp) - 1
     x = synth.vector(n, 10)
-    rows = sample_rows(rp, np.random.default_rng(2))
-    y_ref, scale = spmv_exact(rp, ci, v, x, rows)
-    y_seq = spmv_seq_rows(rp, ci, v, x, rows)
+    y_ref, scale = cref.dot2(rp, ci, v, x)
+    y_seq = cref.seq(rp, ci, v, x)
     r_t, c_t = dev(rp), dev(ci)
-    print(f"\nband_2000000_d60_w200: nnz={len(ci)} sampled rows={len(rows)}", flush=True)
+    print(f"\nband_2000000_d60_w200: nnz={len(ci)} (every row compared)", flush=True)
     for dtype in (S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16):
         v_t = upload_values(v, dtype)
         x_t = dev(x) if dtype == S.SPMV_F64 else dev(x.astype(np.float32))
         tdt = torch.float64 if dtype == S.SPMV_F64 else torch.float32
         plan = S.Plan(r_t, c_t, v_t, n, dtype, nnz=len(ci))
+        if dtype != S.SPMV_BF16:
+            check_features(plan, rp, ci, n, dtype, f"band/{DNAME[dtype]}")
         S.spmv_set_delta16_layout(plan.handle, 1)
         ys = {}
         for req in (0, 16):
@@ -138,13 +171,10 @@ def test_fullsize_delta_codes():
             y = torch.full((n,), float("nan"), dtype=tdt, device=DEV)
             plan.execute(x_t, y)
             torch.cuda.synchronize()
-            assert not torch.isnan(y).any().item(), bits
-            got = y.cpu().numpy()[rows].astype(np.float64)
-            err = np.abs(got - y_ref)
-            rel = float(np.max(np.where(scale > 0, err / np.where(scale > 0, scale, 1), 0)))
-            print(f"  dtype={['f64', 'f32', 'bf16'][dtype]:>4s} {bits}-bit codes "
-                  f"(escapes {plan.query(20)}) max |y - y_ref| / sum|a||x| = {rel:.3e}", flush=True)
-            assert np.all(err <= TOL[dtype] * scale), (bits, dtype, rel)
+            got = y.cpu().numpy().astype(np.float64)
+            rel = check_whole_vector(got, y_ref, scale, TOL[dtype], (bits, DNAME[dtype]))
+            print(f"  {DNAME[dtype]:>4s} {bits}-bit codes (escapes {plan.query(20)}) "
+                  f"max |y - y_ref| / sum|a||x| = {rel:.3e}", flush=True)
             if dtype == S.SPMV_F64:
                 assert np.array_equal(got, y_seq), bits
             ys[bits] = y

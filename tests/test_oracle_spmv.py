@@ -154,3 +154,85 @@ def test_stencil27_closed_form():
     y = spmv_seq(rp, ci, v, np.ones(10 ** 6))
     counts = {val: int((y == val).sum()) for val in (0.0, 9.0, 15.0, 19.0)}
     assert counts == {0.0: 98 ** 3, 9.0: 6 * 98 ** 2, 15.0: 12 * 98, 19.0: 8}
+
+
+# ---------------------------------------------------------------- Dot2
+# The full-size accuracy reference (numpy and C) is Ogita-Rump-Oishi Dot2.
+# Pins: the exact rational row sum within its published bound, exactness
+# on integer data, and ill-conditioned rows where the plain sum loses every
+# digit.
+from oracle.spmv import spmv_dot2  # noqa: E402
+
+U = 2.0 ** -53
+
+
+def exact_rows(rp, ci, v, x):
+    out = []
+    for i in range(len(rp) - 1):
+        out.append(sum((Fraction(float(v[k])) * Fraction(float(x[ci[k]]))
+                        for k in range(rp[i], rp[i + 1])), Fraction(0)))
+    return out
+
+
+def dot2_bound_holds(y, scale, exact, rp):
+    for i, tot in enumerate(exact):
+        L = int(rp[i + 1] - rp[i])
+        g = L * U / (1 - L * U)
+        err = abs(Fraction(float(y[i])) - tot)
+        assert err <= Fraction(U) * abs(tot) + Fraction(g * g) * Fraction(float(scale[i])) * 2, i
+
+
+@pytest.mark.parametrize("impl", ["numpy", "c"])
+def test_dot2_within_published_bound(impl):
+    """|Dot2 - exact| <= u |exact| + gamma_L^2 sum|a||x| against Fractions,
+    on wide-range values where plain summation is visibly worse."""
+    f = spmv_dot2 if impl == "numpy" else cref.dot2
+    for (rp, ci, v), m, rng in random_cases(40, seed=23):
+        x = rng.uniform(-1, 1, size=m) * 10.0 ** rng.integers(-12, 12, size=m)
+        y, sc = f(rp, ci, v, x)
+        dot2_bound_holds(y, sc, exact_rows(rp, ci, v, x), rp)
+
+
+@pytest.mark.parametrize("impl", ["numpy", "c"])
+def test_dot2_ill_conditioned_rows(impl):
+    """Rows whose terms cancel to far below their size: the plain sum is off
+    by about the largest term, Dot2 recovers the exact (representable) sum."""
+    f = spmv_dot2 if impl == "numpy" else cref.dot2
+    rows = [[1e16, 1.0, -1e16], [2.0 ** 60, 3.0, -(2.0 ** 60), 5.0],
+            [1.0, 1e100, 1.0, -1e100], [0.1, 0.2, -0.3]]
+    rp = np.cumsum([0] + [len(r) for r in rows]).astype(np.int32)
+    v = np.concatenate([np.asarray(r) for r in rows])
+    ci = np.concatenate([np.arange(len(r)) for r in rows]).astype(np.int32)
+    x = np.ones(4)
+    y, sc = f(rp, ci, v, x)
+    exact = exact_rows(rp, ci, v, x)
+    assert y[0] == 1.0 and y[1] == 8.0 and y[2] == 2.0
+    assert y[3] == float(exact[3])          # 0.1 + 0.2 - 0.3 in exact rationals
+    assert spmv_seq(rp, ci, v, x)[0] == 0.0  # the plain sum loses the 1
+    assert sc[0] == 2e16 + 1.0
+
+
+def test_dot2_integer_rows_exact_and_agree():
+    """Integer data: Dot2 is exact; numpy and C give the same bits on a
+    power-law matrix with long rows (same operations in the same order)."""
+    for (rp, ci, v), m, rng in random_cases(30, seed=29):
+        if not np.all(v == np.round(v)):
+            continue
+        x = rng.integers(-1024, 1025, size=m).astype(np.float64)
+        y, _ = spmv_dot2(rp, ci, v, x)
+        assert np.array_equal(y, dense(rp, ci, v, m) @ x)
+    rp, ci, v = synth.powerlaw(3000, 109, 1500, seed=6)
+    x = synth.vector(3000, 6)
+    yn, sn = spmv_dot2(rp, ci, v, x)
+    yc, sc = cref.dot2(rp, ci, v, x)
+    assert np.array_equal(yn, yc)
+    rows = np.arange(0, 3000, 11)
+    ye, se = spmv_exact(rp, ci, v, x, rows)
+    assert np.array_equal(yn[rows], ye) or np.all(np.abs(yn[rows] - ye) <= U * np.abs(ye))
+    np.testing.assert_allclose(sn[rows], se, rtol=1e-12)
+
+
+def test_seq_parallel_c_matches_sequential():
+    rp, ci, v = synth.powerlaw(3000, 109, 1500, seed=8)
+    x = synth.vector(3000, 8)
+    assert np.array_equal(cref.seq(rp, ci, v, x), spmv_seq(rp, ci, v, x))
