@@ -199,6 +199,14 @@ spmv_status_t spmv_execute(spmv_plan_t plan, const void *d_x, void *d_y,
 spmv_status_t spmv_set_variant(spmv_plan_t plan, int32_t variant);
 spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
 
+/* FP32/BF16 plans: rows of at least `len` nonzeros accumulate with Kahan's
+ * compensated sum (default 257, i.e. rows longer than 256; the merge-path
+ * variant compensates every FP32 sum that crosses its threads or tiles);
+ * INT32_MAX turns compensation off everywhere, to measure what it buys on
+ * the same kernels (Section 3's precision path; tests).  FP64 plans ignore
+ * it.  SPMV_ERR_ARG for len < 1. */
+spmv_status_t spmv_set_kahan_min_len(spmv_plan_t plan, int32_t len);
+
 /* Column slices of the XBLOCK_LDS format: 0 (default) picks the smallest of
  * 1, 2, 4, 8 that cuts x into slices of at most 256 Ki entries (2 MiB in
  * FP64) while keeping at least 2 nonzeros per slice row on average (the
@@ -276,7 +284,11 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
  * 17 delta16 code bits (8 or 16; -1 infeasible), 18 delta16 largest
  * offset of an offset slice (its columns minus its reference column; 0 with
  * no offset slices; -1 infeasible), 19 delta16 escape units (sum E; 0 with
- * 16-bit codes), 20 delta16 escaped nonzeros (0 with 16-bit codes). */
+ * 16-bit codes), 20 delta16 escaped nonzeros (0 with 16-bit codes),
+ * 21 1 if the current variant (its format built by this call if needed)
+ * sums every row from +0 in increasing column order, one product at a time
+ * (Algorithm 1's order: FP64 results equal the sequential sum bit for bit),
+ * else 0. */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:
@@ -489,6 +501,16 @@ spmv_status_t spmv_cache_flush(void *stream);
 /* Attainable HBM bandwidth over a `bytes` buffer: streaming read and copy,
  * median of 5 runs, in GB/s (1e9 B/s). */
 spmv_status_t spmv_hbm_probe(int64_t bytes, double *read_gbs, double *copy_gbs);
+
+/* Ceiling of an x-gather-bound SpMV: median time (s, hipEvents on the
+ * default stream, 5 runs after 2 warm-ups) of `gathers` random reads of
+ * elem_bytes (4 or 8) from `windows` (1, 2, 4 or 8) windows of window_elems
+ * elements, workgroup b reading window (b mod 8) mod windows as the x-block
+ * kernels map XCDs to column slices; eight reads per thread, four in
+ * flight, indices from a per-thread linear congruential sequence (no index
+ * loads).  The windows live in the cache-flush buffer (512 MiB). */
+spmv_status_t spmv_gather_probe(int64_t window_elems, int32_t elem_bytes, int32_t windows,
+                                int64_t gathers, double *t_median_s);
 
 /* Message of the calling thread's last error ("" if none). */
 const char *spmv_last_error(void);

@@ -66,6 +66,7 @@ _PROTOS = {
     "spmv_execute": (_I32, [_P, _P, _P, _P]),
     "spmv_set_variant": (_I32, [_P, _I32]),
     "spmv_get_variant": (_I32, [_P, _PI32]),
+    "spmv_set_kahan_min_len": (_I32, [_P, _I32]),
     "spmv_variant_mask": (_I32, [_P, _PU32]),
     "spmv_set_xblock_slices": (_I32, [_P, _I32]),
     "spmv_set_delta16_layout": (_I32, [_P, _I32]),
@@ -96,6 +97,7 @@ _PROTOS = {
     "spmv_release_cached_blocks": (_I32, []),
     "spmv_cache_flush": (_I32, [_P]),
     "spmv_hbm_probe": (_I32, [_I64, _PF64, _PF64]),
+    "spmv_gather_probe": (_I32, [_I64, _I32, _I32, _I64, _PF64]),
     "spmv_last_error": (ctypes.c_char_p, []),
 }
 
@@ -191,6 +193,10 @@ def spmv_select(plan, selector=SEL_MLP) -> dict:
 
 def spmv_execute(plan, x, y, stream=None):
     _check("spmv_execute", lib.spmv_execute(plan, _addr(x), _addr(y), _stream(stream)))
+
+
+def spmv_set_kahan_min_len(plan, length: int):
+    _check("spmv_set_kahan_min_len", lib.spmv_set_kahan_min_len(plan, length))
 
 
 def spmv_set_variant(plan, variant: int):
@@ -445,6 +451,14 @@ def spmv_hbm_probe(nbytes: int = 4 << 30):
     return r.value, c.value
 
 
+def spmv_gather_probe(window_elems: int, elem_bytes: int, windows: int, gathers: int) -> float:
+    """Median time (s) of `gathers` random reads from per-XCD windows (see the header)."""
+    t = _F64()
+    _check("spmv_gather_probe", lib.spmv_gather_probe(window_elems, elem_bytes, windows, gathers,
+                                                      ctypes.byref(t)))
+    return t.value
+
+
 def load_selector_config(path: str = SELECTOR_CONFIG) -> bool:
     """Set the profiling thresholds calibrated for this GPU, if the file exists."""
     if not os.path.exists(path):
@@ -513,7 +527,25 @@ class Plan:
     def mask(self):
         return spmv_variant_mask(self.handle)
 
+    def _check_vector(self, t, length, what):
+        """Reject a torch vector the plan would read or write out of bounds or
+        misread: wrong dtype for the plan's value type, too short, not
+        contiguous or not on a GPU.  Raw addresses (ints) are passed as given."""
+        if isinstance(t, int) or t is None:
+            return
+        want = "torch.float64" if self.dtype == SPMV_F64 else "torch.float32"
+        if str(t.dtype) != want:
+            raise ValueError(f"{what} must be {want} for this plan, got {t.dtype}")
+        if t.numel() < length:
+            raise ValueError(f"{what} has {t.numel()} elements, the plan needs {length}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if t.device.type != "cuda":
+            raise ValueError(f"{what} must be a device tensor, got {t.device}")
+
     def execute(self, x, y, stream=None):
+        self._check_vector(x, self.m if self.nnz > 0 else 0, "x")
+        self._check_vector(y, self.n, "y")
         spmv_execute(self.handle, x, y, stream)
 
     def bytes(self, v=None):

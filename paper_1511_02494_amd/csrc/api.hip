@@ -676,6 +676,19 @@ spmv_status_t build_format(spmv_plan *P, int v) {
     }
 }
 
+// 1 if variant v (format built) sums every row from +0 in increasing column
+// order, one product at a time: Algorithm 1's order, so FP64 results equal
+// the sequential sum bit for bit.
+int column_order(const spmv_plan *P, int v) {
+    switch (v) {
+    case V_CSR_SCALAR:
+    case V_SHORT_ROW:
+    case V_DELTA16: return 1;
+    case V_XBLOCK_LDS: return P->xs_pj > 0 ? 1 : 0;
+    default: return 0;
+    }
+}
+
 spmv_status_t feasible_mask(spmv_plan *P, uint32_t *bits) {
     SPMV_TRY(check_d16(P));
     uint32_t b = (1u << V_CSR_SCALAR) | (1u << V_CSR_VECTOR) | (1u << V_MERGE_PATH) |
@@ -1073,6 +1086,14 @@ spmv_status_t spmv_set_variant(spmv_plan_t P, int32_t v) {
     return SPMV_OK;
 }
 
+spmv_status_t spmv_set_kahan_min_len(spmv_plan_t P, int32_t len) {
+    clear_error();
+    if (!P) return fail(SPMV_ERR_ARG, "plan is NULL");
+    if (len < 1) return fail(SPMV_ERR_ARG, "length must be at least 1 (INT32_MAX: no compensation)");
+    P->kahan_min = len;
+    return SPMV_OK;
+}
+
 spmv_status_t spmv_get_variant(spmv_plan_t P, int32_t *v) {
     if (!P || !v) return fail(SPMV_ERR_ARG, "NULL argument");
     *v = P->variant;
@@ -1164,6 +1185,7 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
                  : key == 19 ? P->d16_esc_units : P->d16_nesc;
         break;
     case 10: *value = 1; break;
+    case 21: SPMV_TRY(build_format(P, P->variant)); *value = column_order(P, P->variant); break;
     default: return fail(SPMV_ERR_ARG, "unknown key %d", key);
     }
     return SPMV_OK;
@@ -1531,6 +1553,57 @@ spmv_status_t spmv_hbm_probe(int64_t bytes, double *read_gbs, double *copy_gbs) 
     (void)hipEventDestroy(e1);
     if (read_gbs) *read_gbs = (double)bytes / median(tr) * 1e-9;
     if (copy_gbs) *copy_gbs = 2.0 * (double)bytes / median(tc) * 1e-9;
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_gather_probe(int64_t window_elems, int32_t elem_bytes, int32_t windows,
+                                int64_t gathers, double *t_median_s) {
+    clear_error();
+    if (!t_median_s) return fail(SPMV_ERR_ARG, "NULL argument");
+    if (elem_bytes != 4 && elem_bytes != 8) return fail(SPMV_ERR_ARG, "elem_bytes must be 4 or 8");
+    if (windows != 1 && windows != 2 && windows != 4 && windows != 8)
+        return fail(SPMV_ERR_ARG, "windows must be 1, 2, 4 or 8");
+    if (window_elems < 1 || window_elems > UINT32_MAX ||
+        window_elems * elem_bytes * windows > (int64_t)kFlushBytes)
+        return fail(SPMV_ERR_ARG, "the windows must fit the %lld-byte probe buffer",
+                    (long long)kFlushBytes);
+    if (gathers < 8 || gathers > ((int64_t)1 << 34)) return fail(SPMV_ERR_ARG, "gathers out of range");
+    int dev = 0;
+    SPMV_HIP(hipGetDevice(&dev));
+    DevBuf *b;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_flush.find(dev);
+        if (it == g_flush.end()) it = g_flush.emplace(dev, new DevBuf()).first;
+        b = it->second;
+        if (!b->p) {
+            SPMV_TRY(b->alloc(kFlushBytes));
+            SPMV_HIP(hipMemset(b->p, 0, kFlushBytes));
+        }
+    }
+    DevBuf sink;
+    SPMV_TRY(sink.alloc((size_t)((gathers + 2047) / 2048 + 1) * 8));
+    hipEvent_t e0, e1;
+    SPMV_HIP(hipEventCreate(&e0));
+    SPMV_HIP(hipEventCreate(&e1));
+    std::vector<double> t;
+    spmv_status_t st = SPMV_OK;
+    for (int r = 0; r < 7 && st == SPMV_OK; ++r) {
+        float ms = 0.f;
+        hipError_t e = hipEventRecord(e0, nullptr);
+        if (e == hipSuccess)
+            e = launch_gather_probe(b->p, window_elems, elem_bytes, windows, gathers,
+                                    sink.as<unsigned long long>(), nullptr);
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) st = fail_hip(e, "gather probe", __FILE__, __LINE__);
+        else if (r >= 2) t.push_back(ms * 1e-3);  // two warm-ups
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    SPMV_TRY(st);
+    *t_median_s = median(t);
     return SPMV_OK;
 }
 

@@ -90,6 +90,9 @@ struct spmv_plan {
     int device = 0;
     int num_cus = 256;
     int variant = V_CSR_SCALAR;
+    // FP32/BF16 plans: rows of at least this many nonzeros use Kahan sums
+    // (INT32_MAX: no compensation anywhere, for measuring what it buys)
+    int kahan_min = spmvsel::kKahanMinLen;
 
     spmvsel::DevBuf own_rowptr, own_colind, own_val;  // SPMV_COPY_INPUTS
     spmvsel::DevBuf scratch;     // small: flags, feature partials, records
@@ -185,6 +188,13 @@ hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y
 hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 hipError_t phased_geometry(const spmv_plan &P, int *blocks_per_group, int64_t *groups);
 hipError_t launch_merge_path(const spmv_plan &P, const void *x, void *y, hipStream_t s);
+// merge path on explicit buffers: splits srow/snnz [tiles + 1], carries
+// crow [tiles] and cval [tiles] of the accumulation type (tiles =
+// ceil((n + nnz) / kMergeTile)); every carry is written before it is read
+hipError_t launch_merge_path_raw(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                                 const void *val, int dtype, const void *x, void *y,
+                                 const int32_t *srow, const int32_t *snnz, int32_t *crow,
+                                 void *cval, int kmin, hipStream_t s);
 hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 
 // format preparation (k_prep.hip)
@@ -269,5 +279,9 @@ hipError_t launch_exclusive_scan_i32(const int32_t *lens, int32_t *rowptr, int64
 hipError_t launch_flush(void *buf, size_t bytes, hipStream_t s);
 hipError_t launch_read_probe(const void *buf, size_t bytes, double *sink, hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
+// random gathers from ns windows of w elements (elem_bytes 4 or 8); sink
+// needs ceil(gathers / 2048) words
+hipError_t launch_gather_probe(const void *buf, int64_t w, int elem_bytes, int ns,
+                               int64_t gathers, unsigned long long *sink, hipStream_t s);
 
 }  // namespace spmvsel

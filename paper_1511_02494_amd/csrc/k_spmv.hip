@@ -17,12 +17,12 @@ __global__ __launch_bounds__(kBlock) void k_csr_scalar(int64_t n, const int32_t 
                                                        const int32_t *__restrict__ ci,
                                                        const V *__restrict__ val,
                                                        const typename VT<V>::A *__restrict__ x,
-                                                       typename VT<V>::A *__restrict__ y) {
+                                                       typename VT<V>::A *__restrict__ y, int kmin) {
     using A = typename VT<V>::A;
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= n) return;
     const int32_t a = rp[i], b = rp[i + 1];
-    const bool comp = is_f32<A>() && (b - a) >= kKahanMinLen;
+    const bool comp = is_f32<A>() && (b - a) >= kmin;
     Sum<A> s;
     for (int32_t k = a; k < b; ++k) s.add(VT<V>::cvt(val[k]) * x[ci[k]], comp);
     y[i] = s.s;
@@ -37,14 +37,14 @@ __global__ __launch_bounds__(kBlock) void k_csr_vector(int64_t n, const int32_t 
                                                        const int32_t *__restrict__ ci,
                                                        const V *__restrict__ val,
                                                        const typename VT<V>::A *__restrict__ x,
-                                                       typename VT<V>::A *__restrict__ y) {
+                                                       typename VT<V>::A *__restrict__ y, int kmin) {
     using A = typename VT<V>::A;
     const int lane = threadIdx.x & (W - 1);
     const int64_t nsub = (int64_t)gridDim.x * (kBlock / W);
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     for (int64_t i = blk * (kBlock / W) + threadIdx.x / W; i < n; i += nsub) {
         const int32_t a = rp[i], b = rp[i + 1];
-        const bool comp = is_f32<A>() && (b - a) >= kKahanMinLen;
+        const bool comp = is_f32<A>() && (b - a) >= kmin;
         Sum<A> s;
         int32_t k = a + lane;
         // two independent loads in flight per lane
@@ -86,7 +86,7 @@ __device__ __forceinline__ void rowstream_block(
     int64_t blk, int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const uint16_t *__restrict__ off, const int32_t *__restrict__ rbase,
     const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
-    typename VT<V>::A *__restrict__ y) {
+    typename VT<V>::A *__restrict__ y, int kmin) {
     using A = typename VT<V>::A;
     using VP = typename Pair<V>::type;
     using IP = typename Pair<int32_t>::type;
@@ -111,7 +111,7 @@ __device__ __forceinline__ void rowstream_block(
     int myr = threadIdx.x * R;
     const int myr_end = (myr + R) < nrows ? (myr + R) : nrows;
     int32_t k = myr < nrows ? s_rp[myr] : e;
-    bool comp = is_f32<A>() && myr < nrows && (s_rp[myr + 1] - s_rp[myr]) >= kKahanMinLen;
+    bool comp = is_f32<A>() && myr < nrows && (s_rp[myr + 1] - s_rp[myr]) >= kmin;
     Sum<A> acc;
 
     const int32_t a0 = s & ~1;
@@ -164,7 +164,7 @@ __device__ __forceinline__ void rowstream_block(
             if (SY) s_y[myr] = acc.s; else y[r0 + myr] = acc.s;
             acc.reset();
             ++myr;
-            comp = is_f32<A>() && myr < myr_end && (s_rp[myr + 1] - s_rp[myr]) >= kKahanMinLen;
+            comp = is_f32<A>() && myr < myr_end && (s_rp[myr + 1] - s_rp[myr]) >= kmin;
         }
         __syncthreads();
     }
@@ -183,8 +183,9 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
     int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const uint16_t *__restrict__ off, const int32_t *__restrict__ rbase,
     const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
-    typename VT<V>::A *__restrict__ y) {
-    rowstream_block<V, D16, R, false>(xcd_remap(blockIdx.x, gridDim.x), n, rp, ci, off, rbase, val, x, y);
+    typename VT<V>::A *__restrict__ y, int kmin) {
+    rowstream_block<V, D16, R, false>(xcd_remap(blockIdx.x, gridDim.x), n, rp, ci, off, rbase, val, x, y,
+                                      kmin);
 }
 
 // ============================================================ delta16, sliced
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     const int32_t *__restrict__ diag, const uint32_t *__restrict__ mask,
     const O *__restrict__ off, const int32_t *__restrict__ eunits,
     const int32_t *__restrict__ esc, const V *__restrict__ val,
-    const typename VT<V>::A *__restrict__ x, typename VT<V>::A *__restrict__ y) {
+    const typename VT<V>::A *__restrict__ x, typename VT<V>::A *__restrict__ y, int kmin) {
     using A = typename VT<V>::A;
     using VP = typename Pair<V>::type;
     using OP = typename Pair<O>::type;
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     }
     const int32_t b = base[sl];
     const int len = r < n ? rp[r + 1] - rp[r] : 0;
-    const bool comp = is_f32<A>() && len >= kKahanMinLen;
+    const bool comp = is_f32<A>() && len >= kmin;
     Sum<A> acc;
     int32_t cprev = b;  // 8-bit codes: the previous column
     const int32_t *ep = nullptr;  // 8-bit codes: this lane's next escape entry
@@ -366,9 +367,8 @@ __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64
                                            const int32_t *__restrict__ srow,
                                            const int32_t *__restrict__ snnz,
                                            int32_t *__restrict__ carry_row,
-                                           typename VT<V>::A *__restrict__ carry_val) {
+                                           typename VT<V>::A *__restrict__ carry_val, bool comp) {
     using A = typename VT<V>::A;
-    constexpr bool F32 = is_f32<A>();
     const int32_t i0 = srow[tile], j0 = snnz[tile];
     const int32_t i1 = srow[tile + 1], j1 = snnz[tile + 1];
     const int nr = i1 - i0, nz = j1 - j0;
@@ -413,7 +413,7 @@ __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64
     const int dend = (d + kMergeIpt) < total ? (d + kMergeIpt) : total;
     for (int it = d; it < dend; ++it) {
         if (yj < nz && j0 + yj < sm.end[xi]) {
-            run.add(sm.prod[yj], F32);
+            run.add(sm.prod[yj], comp);
             ++yj;
         } else {
             if (head_row < 0) {
@@ -434,8 +434,8 @@ __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64
         int t0 = threadIdx.x;
         while (t0 > 0 && sm.crow[t0 - 1] == head_row) --t0;
         Sum<A> c;
-        for (int t = t0; t < (int)threadIdx.x; ++t) c.add(sm.cval[t], F32);
-        c.add(head_val, F32);
+        for (int t = t0; t < (int)threadIdx.x; ++t) c.add(sm.cval[t], comp);
+        c.add(head_val, comp);
         y[i0 + head_row] = c.s;
     }
     if (threadIdx.x == kBlock - 1) {
@@ -444,7 +444,7 @@ __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64
         while (t0 > 0 && sm.crow[t0 - 1] == nr) --t0;
         Sum<A> c;
         if (sm.crow[kBlock - 1] == nr)
-            for (int t = t0; t < kBlock; ++t) c.add(sm.cval[t], F32);
+            for (int t = t0; t < kBlock; ++t) c.add(sm.cval[t], comp);
         carry_row[tile] = i1;
         carry_val[tile] = c.s;
     }
@@ -456,10 +456,11 @@ __global__ __launch_bounds__(kBlock) void k_merge_path(
     const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
     typename VT<V>::A *__restrict__ y, const int32_t *__restrict__ srow,
     const int32_t *__restrict__ snnz, int32_t *__restrict__ carry_row,
-    typename VT<V>::A *__restrict__ carry_val) {
+    typename VT<V>::A *__restrict__ carry_val, int kmin) {
     __shared__ MergeSmem<V> sm;
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    merge_tile<V>(sm, tile, n, rp, ci, val, x, y, srow, snnz, carry_row, carry_val);
+    merge_tile<V>(sm, tile, n, rp, ci, val, x, y, srow, snnz, carry_row, carry_val,
+                  is_f32<typename VT<V>::A>() && kmin < INT32_MAX);
 }
 
 // Adds the carries of consecutive tiles that end inside the same row, in
@@ -469,13 +470,13 @@ template <class A>
 __device__ __forceinline__ void merge_fixup_one(int64_t t, int64_t n, int64_t tiles,
                                                 const int32_t *__restrict__ carry_row,
                                                 const A *__restrict__ carry_val,
-                                                A *__restrict__ y) {
+                                                A *__restrict__ y, bool comp) {
     if (t >= tiles) return;
     const int32_t row = carry_row[t];
     if (row >= n) return;
     if (t > 0 && carry_row[t - 1] == row) return;
     Sum<A> c;
-    for (int64_t u = t; u < tiles && carry_row[u] == row; ++u) c.add(carry_val[u], is_f32<A>());
+    for (int64_t u = t; u < tiles && carry_row[u] == row; ++u) c.add(carry_val[u], comp);
     y[row] = y[row] + c.s;
 }
 
@@ -483,8 +484,9 @@ template <class A>
 __global__ __launch_bounds__(kBlock) void k_merge_fixup(int64_t n, int64_t tiles,
                                                         const int32_t *__restrict__ carry_row,
                                                         const A *__restrict__ carry_val,
-                                                        A *__restrict__ y) {
-    merge_fixup_one<A>(blockIdx.x * (int64_t)kBlock + threadIdx.x, n, tiles, carry_row, carry_val, y);
+                                                        A *__restrict__ y, int kmin) {
+    merge_fixup_one<A>(blockIdx.x * (int64_t)kBlock + threadIdx.x, n, tiles, carry_row, carry_val, y,
+                       is_f32<A>() && kmin < INT32_MAX);
 }
 
 // ============================================================ x blocking
@@ -521,13 +523,13 @@ template <class V>
 __global__ __launch_bounds__(kBlock) void k_merge_slices(int64_t n, const int32_t *__restrict__ ci,
                                                          const V *__restrict__ val,
                                                          const typename VT<V>::A *__restrict__ x,
-                                                         SliceTable<typename VT<V>::A> T) {
+                                                         SliceTable<typename VT<V>::A> T, int kmin) {
     __shared__ MergeSmem<V> sm;
     int s;
     const int64_t tile = slice_unit(T.ns, &s);
     if (tile >= T.tiles[s]) return;
     merge_tile<V>(sm, tile, n, T.rp[s], ci + T.off[s], val + T.off[s], x, T.y[s], T.srow[s],
-                  T.snnz[s], T.crow[s], T.cval[s]);
+                  T.snnz[s], T.crow[s], T.cval[s], is_f32<typename VT<V>::A>() && kmin < INT32_MAX);
 }
 
 // Long rows of the split, summed from the original CSR: one block per chunk
@@ -585,7 +587,7 @@ __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t 
                                                              const V *__restrict__ val,
                                                              const typename VT<V>::A *__restrict__ x,
                                                              SliceTable<typename VT<V>::A> T,
-                                                             int64_t sgrid, LongChunks LC) {
+                                                             int64_t sgrid, LongChunks LC, int kmin) {
     using A = typename VT<V>::A;
     if ((int64_t)blockIdx.x >= sgrid) {
         __shared__ A sh[kBlock];
@@ -597,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t 
     const int64_t b = slice_unit(T.ns, &s);
     if (b >= nblocks) return;
     rowstream_block<V, false, R, true>(b, n, T.rp[s], ci + T.off[s], nullptr, nullptr, val + T.off[s], x,
-                                 T.y[s]);
+                                 T.y[s], kmin);
 }
 
 // Phased row streaming on the slices, without partial y vectors.  Workgroup
@@ -615,7 +617,7 @@ template <class V, int J>
 __global__ __launch_bounds__(kBlock) void k_phased_slices(
     int64_t n, int64_t nblk, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
-    SliceTable<typename VT<V>::A> T, typename VT<V>::A *__restrict__ y) {
+    SliceTable<typename VT<V>::A> T, typename VT<V>::A *__restrict__ y, int kmin) {
     using A = typename VT<V>::A;
     using VP = typename Pair<V>::type;
     using IP = typename Pair<int32_t>::type;
@@ -629,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int64_t r = (w + j * G) * kBlock + t;
-        comp[j] = is_f32<A>() && r < n && (rp[r + 1] - rp[r]) >= kKahanMinLen;
+        comp[j] = is_f32<A>() && r < n && (rp[r + 1] - rp[r]) >= kmin;
     }
     for (int sl = 0; sl < T.ns; ++sl) {
         const int32_t *__restrict__ srp = T.rp[sl];
@@ -693,11 +695,12 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
 
 template <class A>
 __global__ __launch_bounds__(kBlock) void k_merge_fixup_slices(int64_t n, int64_t maxt,
-                                                               SliceTable<A> T) {
+                                                               SliceTable<A> T, int kmin) {
     const int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     const int s = (int)(g / (maxt > 0 ? maxt : 1));
     if (s >= T.ns) return;
-    merge_fixup_one<A>(g % maxt, n, T.tiles[s], T.crow[s], T.cval[s], T.y[s]);
+    merge_fixup_one<A>(g % maxt, n, T.tiles[s], T.crow[s], T.cval[s], T.y[s],
+                       is_f32<A>() && kmin < INT32_MAX);
 }
 
 // Slice sums and long rows in one launch: blocks below gsum add the partial
@@ -711,7 +714,7 @@ __global__ __launch_bounds__(kBlock) void k_slice_finish(int64_t n, SliceTable<A
                                                          const uint32_t *__restrict__ longmask,
                                                          int64_t L, const int32_t *__restrict__ rows,
                                                          const int32_t *__restrict__ first,
-                                                         const A *__restrict__ lsum) {
+                                                         const A *__restrict__ lsum, int kmin) {
     if ((int64_t)blockIdx.x < gsum) {
         for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += gsum * kBlock) {
             if ((longmask[i >> 5] >> (i & 31)) & 1u) continue;
@@ -725,7 +728,8 @@ __global__ __launch_bounds__(kBlock) void k_slice_finish(int64_t n, SliceTable<A
     const int lane = threadIdx.x & 63;
     if (t >= L) return;  // whole wavefronts leave together
     Sum<A> acc;
-    for (int32_t c = first[t] + lane; c < first[t + 1]; c += 64) acc.add(lsum[c], is_f32<A>());
+    for (int32_t c = first[t] + lane; c < first[t + 1]; c += 64)
+        acc.add(lsum[c], is_f32<A>() && kmin < INT32_MAX);
     const A v = group_sum<64>(acc.s);
     if (lane == 0) y[rows[t]] = v;
 }
@@ -769,7 +773,7 @@ hipError_t launch_csr_scalar(const spmv_plan &P, const void *x, void *y, hipStre
         using A = typename VT<V>::A;
         const unsigned g = grid_for(P.n, kBlock, INT32_MAX);
         hipLaunchKernelGGL(k_csr_scalar<V>, dim3(g), dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
-                           (const V *)P.val, (const A *)x, (A *)y);
+                           (const V *)P.val, (const A *)x, (A *)y, P.kahan_min);
         return hipGetLastError();
     });
 }
@@ -784,7 +788,7 @@ hipError_t launch_csr_vector(const spmv_plan &P, const void *x, void *y, hipStre
 #define SPMV_VEC(WW)                                                                       \
     case WW:                                                                               \
         hipLaunchKernelGGL((k_csr_vector<V, WW>), dim3(g), dim3(kBlock), 0, s, P.n, P.rowptr, \
-                           P.colind, (const V *)P.val, (const A *)x, (A *)y);             \
+                           P.colind, (const V *)P.val, (const A *)x, (A *)y, P.kahan_min); \
         break;
         switch (W) {
             SPMV_VEC(2) SPMV_VEC(4) SPMV_VEC(8) SPMV_VEC(16) SPMV_VEC(32) SPMV_VEC(64)
@@ -809,11 +813,12 @@ hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y
         if (d16)                                                                                  \
             hipLaunchKernelGGL((k_rowstream<V, true, RR>), dim3(g), dim3(kBlock), 0, s, P.n,     \
                                P.rowptr, P.colind, off, base, (const V *)P.val, (const A *)x,    \
-                               (A *)y);                                                           \
+                               (A *)y, P.kahan_min);                                              \
         else                                                                                      \
             hipLaunchKernelGGL((k_rowstream<V, false, RR>), dim3(g), dim3(kBlock), 0, s, P.n,    \
                                P.rowptr, P.colind, (const uint16_t *)nullptr,                     \
-                               (const int32_t *)nullptr, (const V *)P.val, (const A *)x, (A *)y); \
+                               (const int32_t *)nullptr, (const V *)P.val, (const A *)x, (A *)y,  \
+                               P.kahan_min);                                                      \
         break;
         switch (R) {
             SPMV_RS(1) SPMV_RS(2) SPMV_RS(4) SPMV_RS(8)
@@ -868,35 +873,44 @@ hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStre
                                P.d16s_kind.as<int32_t>(), P.d16s_diag.as<int32_t>(),
                                P.d16s_mask.as<uint32_t>(), P.d16s_off.as<uint8_t>(),
                                P.d16s_eunits.as<int32_t>(), P.d16s_esc.as<int32_t>(),
-                               P.d16s_val.as<V>(), (const A *)x, (A *)y);
+                               P.d16s_val.as<V>(), (const A *)x, (A *)y, P.kahan_min);
         else
             hipLaunchKernelGGL((k_sliced_d16<V, uint16_t>), dim3(g), dim3(kBlock), 0, s, P.n, P.m,
                                P.d16_nsl, P.rowptr, P.d16s_width.as<int32_t>(),
                                P.d16s_units.as<int32_t>(), P.d16s_base.as<int32_t>(),
                                P.d16s_kind.as<int32_t>(), P.d16s_diag.as<int32_t>(),
                                P.d16s_mask.as<uint32_t>(), P.d16s_off.as<uint16_t>(),
-                               nullptr, nullptr, P.d16s_val.as<V>(), (const A *)x, (A *)y);
+                               nullptr, nullptr, P.d16s_val.as<V>(), (const A *)x, (A *)y,
+                               P.kahan_min);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_merge_path_raw(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                                 const void *val, int dtype, const void *x, void *y,
+                                 const int32_t *srow, const int32_t *snnz, int32_t *crow,
+                                 void *cval, int kmin, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    return by_dtype(dtype, [&](auto tag) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
+        using A = typename VT<V>::A;
+        const int64_t tiles = (n + nnz + kMergeTile - 1) / kMergeTile;
+        if (tiles <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k_merge_path<V>, dim3((unsigned)tiles), dim3(kBlock), 0, s, n, rp, ci,
+                           (const V *)val, (const A *)x, (A *)y, srow, snnz, crow, (A *)cval, kmin);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const unsigned g = grid_for(tiles, kBlock, INT32_MAX);
+        hipLaunchKernelGGL(k_merge_fixup<A>, dim3(g), dim3(kBlock), 0, s, n, tiles, crow,
+                           (const A *)cval, (A *)y, kmin);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_merge_path(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
-    if (P.n == 0) return hipSuccess;
-    return by_dtype(P.dtype, [&](auto tag) {
-        using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
-        using A = typename VT<V>::A;
-        if (P.mp_tiles <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k_merge_path<V>, dim3((unsigned)P.mp_tiles), dim3(kBlock), 0, s, P.n,
-                           P.rowptr, P.colind, (const V *)P.val, (const A *)x, (A *)y,
-                           P.mp_split_row.as<int32_t>(), P.mp_split_nnz.as<int32_t>(),
-                           P.mp_carry_row.as<int32_t>(), P.mp_carry_val.as<A>());
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        const unsigned g = grid_for(P.mp_tiles, kBlock, INT32_MAX);
-        hipLaunchKernelGGL(k_merge_fixup<A>, dim3(g), dim3(kBlock), 0, s, P.n, P.mp_tiles,
-                           P.mp_carry_row.as<int32_t>(), P.mp_carry_val.as<A>(), (A *)y);
-        return hipGetLastError();
-    });
+    return launch_merge_path_raw(P.n, P.nnz, P.rowptr, P.colind, P.val, P.dtype, x, y,
+                                 P.mp_split_row.as<int32_t>(), P.mp_split_nnz.as<int32_t>(),
+                                 P.mp_carry_row.as<int32_t>(), P.mp_carry_val.p, P.kahan_min, s);
 }
 
 hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
@@ -930,7 +944,7 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
 #define SPMV_PH(JJ)                                                                                    \
     case JJ:                                                                                           \
         hipLaunchKernelGGL((k_phased_slices<V, JJ>), dim3(g), dim3(kBlock), 0, s, P.n, nblk,          \
-                           P.rowptr, xci, xv, (const A *)x, T, (A *)y);                             \
+                           P.rowptr, xci, xv, (const A *)x, T, (A *)y, P.kahan_min);                \
         break;
             if (P.xs_nlong > 0) return hipErrorInvalidValue;  // phased only without long rows
             switch (P.xs_pj) {
@@ -948,10 +962,10 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             const int32_t *xci = P.xs_colind.as<int32_t>();
             const V *xv = (const V *)P.xs_val.p;
             switch (R) {
-            case 1: hipLaunchKernelGGL((k_rowstream_slices<V, 1>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;
-            case 2: hipLaunchKernelGGL((k_rowstream_slices<V, 2>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;
-            case 4: hipLaunchKernelGGL((k_rowstream_slices<V, 4>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;
-            case 8: hipLaunchKernelGGL((k_rowstream_slices<V, 8>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC); break;
+            case 1: hipLaunchKernelGGL((k_rowstream_slices<V, 1>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC, P.kahan_min); break;
+            case 2: hipLaunchKernelGGL((k_rowstream_slices<V, 2>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC, P.kahan_min); break;
+            case 4: hipLaunchKernelGGL((k_rowstream_slices<V, 4>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC, P.kahan_min); break;
+            case 8: hipLaunchKernelGGL((k_rowstream_slices<V, 8>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC, P.kahan_min); break;
             default: return hipErrorInvalidValue;
             }
             hipError_t e = hipGetLastError();
@@ -959,11 +973,12 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
         } else if (maxt > 0) {
             hipLaunchKernelGGL(k_merge_slices<V>, dim3((unsigned)((maxt + G - 1) / G * 8)), dim3(kBlock), 0,
                                s, P.n, P.xs_colind.as<int32_t>(), (const V *)P.xs_val.p,
-                               (const A *)x, T);
+                               (const A *)x, T, P.kahan_min);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             const unsigned g = grid_for(maxt * T.ns, kBlock, INT32_MAX);
-            hipLaunchKernelGGL(k_merge_fixup_slices<A>, dim3(g), dim3(kBlock), 0, s, P.n, maxt, T);
+            hipLaunchKernelGGL(k_merge_fixup_slices<A>, dim3(g), dim3(kBlock), 0, s, P.n, maxt, T,
+                               P.kahan_min);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         if (P.xs_nlong > 0) {  // rows taken out of the slices (chunks summed above)
@@ -972,7 +987,7 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             hipLaunchKernelGGL(k_slice_finish<A>, dim3((unsigned)(gsum + glong)), dim3(kBlock), 0, s,
                                P.n, T, (A *)y, gsum, P.xs_lmask.as<uint32_t>(), P.xs_nlong,
                                P.xs_lrows.as<int32_t>(), P.xs_lfirst.as<int32_t>(),
-                               P.xs_lsum.as<A>());
+                               P.xs_lsum.as<A>(), P.kahan_min);
             return hipGetLastError();
         }
         const unsigned g = grid_for(P.n, kBlock, (int64_t)P.num_cus * 16);
