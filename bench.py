@@ -365,6 +365,23 @@ def main():
                 log(f"  {M['name']:>22s} {S.VARIANTS[v]:>10s} warm {warm * 1e6:8.1f} us "
                     f"({b / warm * 1e-9:6.0f} GB/s)  cold {cold * 1e6:8.1f} us "
                     f"({b / cold * 1e-9:6.0f} GB/s)")
+            # the same variants reading 16-bit column codes, where they fit
+            S.spmv_set_index_coding(plan.handle, S.SPMV_IDX_CODED)
+            cmask = plan.mask()
+            M["coded"] = {}
+            for v in (S.V_MERGE_PATH, S.V_XBLOCK_LDS, S.V_SHORT_ROW):
+                if not (cmask >> v) & 1:
+                    M["coded"][S.VARIANTS[v]] = None
+                    continue
+                warm, _ = plan.time(v, reps=20, cold=False)
+                cold, _ = plan.time(v, reps=5, cold=True)
+                b = plan.bytes(v)
+                M["coded"][S.VARIANTS[v]] = dict(
+                    warm_us=warm * 1e6, cold_us=cold * 1e6, bytes=b,
+                    warm_gbs=b / warm * 1e-9, cold_gbs=b / cold * 1e-9)
+                log(f"  {M['name']:>22s} {S.VARIANTS[v] + '+codes':>16s} warm {warm * 1e6:8.1f} us "
+                    f"cold {cold * 1e6:8.1f} us ({b / 1e6:.1f} MB)")
+            S.spmv_set_index_coding(plan.handle, S.SPMV_IDX_AUTO)
         plan.close()
 
     # ---- timed steps
@@ -436,6 +453,7 @@ def main():
             prepare_s=float(np.median([r["info"]["t_prepare_s"] for r in recs])),
             step_matrix_s=float(np.median([r["t_select"] + r["t_loop"] for r in recs])),
         )
+        rec["coded_forms"] = M.get("coded", {})
         if best:
             rec["best_variant"] = best
             rec["best_warm_gbs"] = var_tab[best]["warm_gbs"]

@@ -199,6 +199,36 @@ spmv_status_t spmv_execute(spmv_plan_t plan, const void *d_x, void *d_y,
 spmv_status_t spmv_set_variant(spmv_plan_t plan, int32_t variant);
 spmv_status_t spmv_get_variant(spmv_plan_t plan, int32_t *variant);
 
+/* Index coding of the column indices the variant kernels read (Section 3.3:
+ * column-index compression as an optimisation of its own, Table 2 class MB,
+ * applied on top of the other variants - the multi-level combinations of
+ * the Conclusions).  coding:
+ *   -1 (default) each variant's own: DELTA16 reads 16-bit codes, the others
+ *      the caller's int32 columns;
+ *    0 int32 columns everywhere (DELTA16 is then infeasible);
+ *    1 16-bit column codes everywhere they exist:
+ *      SHORT_ROW  the rows-streamed DELTA16 layout (offsets from one reference
+ *                 column per block of rows);
+ *      MERGE_PATH offsets from each merge-path tile's smallest column,
+ *                 feasible when every tile spans < 65536 columns;
+ *      XBLOCK_LDS offsets from the smallest column of each row block of each
+ *                 column slice (the slice kernel's block: 256 rows in the
+ *                 phased walk), feasible when every such segment spans
+ *                 < 65536 columns and the slices are row-streamed;
+ *      DELTA16    unchanged;
+ *      CSR_SCALAR, CSR_VECTOR have no coded form (infeasible).
+ * The request applies to spmv_set_variant, spmv_variant_mask, spmv_bytes,
+ * spmv_time_variant and spmv_select from then on (the selectors choose among
+ * the variants feasible under it); the current variant is rebuilt under it
+ * when it has a form there, else spmv_execute reports SPMV_ERR_ARG (no
+ * prepared format) until a variant is set.  A variant that cannot run under
+ * the request gives SPMV_ERR_INFEASIBLE from spmv_set_variant.  Results
+ * equal those of the int32 form of the same variant bit for bit (the codes
+ * decode to the same columns; the order of operations is unchanged).
+ * SPMV_ERR_ARG for any other value. */
+typedef enum { SPMV_IDX_AUTO = -1, SPMV_IDX_I32 = 0, SPMV_IDX_CODED = 1 } spmv_index_t;
+spmv_status_t spmv_set_index_coding(spmv_plan_t plan, int32_t coding);
+
 /* FP32/BF16 plans: rows of at least `len` nonzeros accumulate with Kahan's
  * compensated sum (default 257, i.e. rows longer than 256; the merge-path
  * variant compensates every FP32 sum that crosses its threads or tiles);
@@ -288,7 +318,10 @@ spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
  * 21 1 if the current variant (its format built by this call if needed)
  * sums every row from +0 in increasing column order, one product at a time
  * (Algorithm 1's order: FP64 results equal the sequential sum bit for bit),
- * else 0. */
+ * else 0, 22 1 if the current variant reads 16-bit column codes under the
+ * index-coding request, 23 1 if the merge-path tiles' codes fit 16 bits,
+ * 24 1 if the x-block slices' codes fit 16 bits, 25 rows per x-block code
+ * block. */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:
@@ -318,6 +351,12 @@ spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
  * k counts the row's nonzeros in an offset slice and is the diagonal's index
  * in a diagonal slice; offsets are 0 in diagonal slices and every other slot
  * holds zero.
+ * Coded forms (spmv_set_index_coding): 18 merge-path tile reference columns
+ * int32[tiles] (key 4), 19 merge-path codes uint16[NNZ] (column minus the
+ * reference of the nonzero's tile), 20 x-block reference columns
+ * int32[S x ceil(N / H)] (slice-major, H = key 25), 21 x-block codes
+ * uint16[NNZ minus the long rows' nonzeros] at the positions of array 5.
+ * These are built (and their feasibility required) by the copy itself.
  * `bytes` must equal the array size. */
 spmv_status_t spmv_plan_copy_format(spmv_plan_t plan, int32_t which,
                                     void *host_dst, int64_t bytes);

@@ -23,6 +23,13 @@
   taken before row end i exactly when ``j < rowptr[i+1]``.
 * ``slice_csr_ref``  the column-sliced CSR of x blocking (one slice per XCD);
   ``xblock_split_ref`` takes rows with a long slice segment out of it.
+* ``range_codes_ref``  16-bit column codes inside the other variants' work
+  units (Section 3.3's column-index compression combined with another
+  optimisation, the multi-level pool of the Conclusions): each unit - a
+  merge-path tile (``merge_codes_ref``) or a row block of an x-block column
+  slice (``xblock_codes_ref``) - takes its smallest column as reference and
+  stores every column as its offset from it; feasible iff no unit spans
+  more than 65535 columns.
 * ``partition_ref``  the paper's default static partition: contiguous row
   ranges with (as nearly as possible) equal nonzeros (Section 3.2.1).
 * ``to_bf16_bits_ref`` / ``to_f32_ref``  value rounding for the precision
@@ -394,6 +401,60 @@ def xblock_split_ref(rowptr, colind, n_cols: int, slices: int, max_seg: int = 12
                          [np.zeros(0, np.int64)])
     rps, cols = slice_csr_ref(rp2, ci2, n_cols, slices)
     return long_rows.astype(np.int32), rps, cols
+
+
+def range_codes_ref(colind, bounds):
+    """(feasible, base int32[R], off uint16[len(colind)], max span) for the
+    ranges [bounds[k], bounds[k+1]) of a column array: base[k] is the range's
+    smallest column (0 for an empty range) and off[j] = colind[j] - base[k]
+    for j in range k.  Feasible iff every range spans at most 65535 columns
+    (offsets are only filled in when feasible)."""
+    colind = np.asarray(colind, dtype=np.int64)
+    bounds = np.asarray(bounds, dtype=np.int64)
+    R = len(bounds) - 1
+    base = np.zeros(R, dtype=np.int64)
+    span = 0
+    for k in range(R):
+        seg = colind[bounds[k]:bounds[k + 1]]
+        if len(seg):
+            base[k] = seg.min()
+            span = max(span, int(seg.max() - seg.min()))
+    feasible = span <= 65535
+    off = np.zeros(len(colind), dtype=np.uint16)
+    if feasible:
+        for k in range(R):
+            a, b = bounds[k], bounds[k + 1]
+            off[a:b] = (colind[a:b] - base[k]).astype(np.uint16)
+    return feasible, base.astype(np.int32), off, span
+
+
+def merge_codes_ref(rowptr, colind, items_per_tile: int = 2048):
+    """16-bit codes inside merge-path tiles: the ranges are the tiles' nonzero
+    ranges [split_nnz[t], split_nnz[t+1]) of the sequential merge walk."""
+    _, sj = merge_walk_ref(rowptr, items_per_tile)
+    return range_codes_ref(colind, sj)
+
+
+def xblock_codes_ref(rowptr, colind, n_cols: int, slices: int, block_rows: int,
+                     max_seg: int = 128, max_share: float = 0.25):
+    """16-bit codes inside the x-block slices: for every slice (of the split
+    of ``xblock_split_ref``) and block b of ``block_rows`` rows, the range of
+    the slice-major columns of rows [b H, min((b+1) H, N)).  Returns
+    (feasible, base int32[slices * nblocks] (slice-major), off uint16 at the
+    positions of the slice-major columns, max span)."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    n = len(rowptr) - 1
+    _, rps, cols = xblock_split_ref(rowptr, colind, n_cols, slices, max_seg, max_share)
+    nb = (n + block_rows - 1) // block_rows
+    bounds, start = [0], 0
+    for s in range(slices):
+        srp = rps[s].astype(np.int64)
+        for b in range(nb):
+            bounds.append(start + int(srp[min((b + 1) * block_rows, n)]))
+        start += int(srp[n])
+    # ranges are consecutive: slice s block b ends where block b+1 (or the
+    # next slice's first block) starts
+    return range_codes_ref(cols, bounds)
 
 
 def partition_ref(rowptr, parts: int):

@@ -23,6 +23,7 @@ DEFAULT_MODEL = os.path.join(_HERE, "mlp_selector.bin")
 SPMV_OK, SPMV_ERR_ARG, SPMV_ERR_CSR_ROWPTR, SPMV_ERR_CSR_COL_RANGE, SPMV_ERR_CSR_UNSORTED, \
     SPMV_ERR_OOM, SPMV_ERR_HIP, SPMV_ERR_INFEASIBLE, SPMV_ERR_NO_MODEL = range(9)
 SPMV_F64, SPMV_F32, SPMV_BF16 = range(3)
+SPMV_IDX_AUTO, SPMV_IDX_I32, SPMV_IDX_CODED = -1, 0, 1
 V_CSR_SCALAR, V_CSR_VECTOR, V_MERGE_PATH, V_DELTA16, V_XBLOCK_LDS, V_SHORT_ROW = range(6)
 VARIANTS = ["csr_scalar", "csr_vector", "merge_path", "delta16", "xblock_lds", "short_row"]
 CLASSES = ["CML", "MB", "IMB", "CMP"]
@@ -67,6 +68,7 @@ _PROTOS = {
     "spmv_set_variant": (_I32, [_P, _I32]),
     "spmv_get_variant": (_I32, [_P, _PI32]),
     "spmv_set_kahan_min_len": (_I32, [_P, _I32]),
+    "spmv_set_index_coding": (_I32, [_P, _I32]),
     "spmv_variant_mask": (_I32, [_P, _PU32]),
     "spmv_set_xblock_slices": (_I32, [_P, _I32]),
     "spmv_set_delta16_layout": (_I32, [_P, _I32]),
@@ -195,6 +197,10 @@ def spmv_execute(plan, x, y, stream=None):
     _check("spmv_execute", lib.spmv_execute(plan, _addr(x), _addr(y), _stream(stream)))
 
 
+def spmv_set_index_coding(plan, coding: int):
+    _check("spmv_set_index_coding", lib.spmv_set_index_coding(plan, coding))
+
+
 def spmv_set_kahan_min_len(plan, length: int):
     _check("spmv_set_kahan_min_len", lib.spmv_set_kahan_min_len(plan, length))
 
@@ -249,7 +255,7 @@ def spmv_plan_query(plan, key: int) -> int:
 _FORMAT_DTYPES = {0: np.int32, 1: np.uint16, 2: np.int32, 3: np.int32, 4: np.int32,
                   5: np.int32, 6: np.int32, 7: np.int32, 8: np.int32, 9: np.int32, 10: np.int32,
                   11: np.uint16, 13: np.int32, 14: np.int32, 15: np.uint32, 16: np.int32,
-                  17: np.int32}
+                  17: np.int32, 18: np.int32, 19: np.uint16, 20: np.int32, 21: np.uint16}
 
 
 def spmv_plan_copy_format(plan, which: int, count: int, dtype=None) -> np.ndarray:

@@ -515,6 +515,7 @@ spmv_status_t split_long_rows(spmv_plan *P, int ns, int32_t *lens) {
 
 spmv_status_t build_xslices(spmv_plan *P) {
     if (P->xs_built) return SPMV_OK;
+    P->xsc_checked = P->xsc_feasible = P->xsc_built = false;
     const int64_t n = P->n, nnz = P->nnz;
     const int ns = xs_slice_count(P);
     const int64_t cw = xs_slice_width(P, ns);
@@ -607,12 +608,96 @@ spmv_status_t build_xslices(spmv_plan *P) {
     return SPMV_OK;
 }
 
+// 16-bit codes of the merge-path tiles (splits built): reference = the
+// tile's smallest column; feasible when every tile spans < 65536 columns.
+spmv_status_t check_merge_codes(spmv_plan *P) {
+    if (P->mpc_checked) return SPMV_OK;
+    const int64_t tiles = P->mp_tiles;
+    SPMV_TRY(P->mpc_base.alloc((size_t)(tiles > 0 ? tiles : 1) * 4));
+    DevBuf span;
+    SPMV_TRY(span.alloc((size_t)(tiles > 0 ? tiles : 1) * 4));
+    int32_t mx = 0;
+    if (tiles > 0 && P->nnz > 0) {
+        SPMV_HIP(launch_range_ref(tiles, tiles, 1, P->mp_split_nnz.as<int32_t>(), P->colind,
+                                  P->mpc_base.as<int32_t>(), span.as<int32_t>(), S(P)));
+        auto *d = scr<unsigned long long>(P, kOffSum);
+        SPMV_HIP(launch_max_i32(span.as<int32_t>(), tiles, scr<int32_t>(P, kOffPart), d, S(P)));
+        SPMV_HIP(hipMemcpyAsync(P->h_pinned, d, 8, hipMemcpyDeviceToHost, S(P)));
+        SPMV_TRY(sync(P));
+        unsigned long long m = 0;
+        memcpy(&m, P->h_pinned, 8);
+        mx = (int32_t)m;
+    }
+    P->mpc_span = mx;
+    P->mpc_feasible = mx <= 65535;
+    P->mpc_checked = true;
+    return SPMV_OK;
+}
+
+// 16-bit codes of the x-block slices (slices built, row-streamed): per slice
+// and row block of xsc_h rows (256 for the phased walk, else the per-slice
+// kernel's block height) the smallest column; feasible when every block's
+// segment of every slice spans < 65536 columns.
+spmv_status_t check_xblock_codes(spmv_plan *P) {
+    if (P->xsc_checked) return SPMV_OK;
+    P->xsc_checked = true;
+    P->xsc_feasible = false;
+    P->xsc_span = 0;
+    if (P->xs_rows == 0) return SPMV_OK;  // merge-path slices: no coded form
+    const int64_t n = P->n, H = P->xs_pj > 0 ? kBlock : P->xs_rows;
+    const int64_t nb = (n + H - 1) / H;
+    const int ns = P->xs_slices;
+    P->xsc_h = H;
+    for (int k = 0; k <= ns; ++k) P->xsc_boff[k] = (int64_t)k * nb;
+    SPMV_TRY(P->xsc_base.alloc((size_t)(ns * nb > 0 ? ns * nb : 1) * 4));
+    DevBuf span;
+    SPMV_TRY(span.alloc((size_t)(ns * nb > 0 ? ns * nb : 1) * 4));
+    int32_t mx = 0;
+    if (nb > 0) {
+        for (int k = 0; k < ns; ++k)
+            SPMV_HIP(launch_range_ref(nb, n, H, P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1),
+                                      P->xs_colind.as<int32_t>() + P->xs_nnz_off[k],
+                                      P->xsc_base.as<int32_t>() + P->xsc_boff[k],
+                                      span.as<int32_t>() + P->xsc_boff[k], S(P)));
+        auto *d = scr<unsigned long long>(P, kOffSum);
+        SPMV_HIP(launch_max_i32(span.as<int32_t>(), ns * nb, scr<int32_t>(P, kOffPart), d, S(P)));
+        SPMV_HIP(hipMemcpyAsync(P->h_pinned, d, 8, hipMemcpyDeviceToHost, S(P)));
+        SPMV_TRY(sync(P));
+        unsigned long long m = 0;
+        memcpy(&m, P->h_pinned, 8);
+        mx = (int32_t)m;
+    }
+    P->xsc_span = mx;
+    P->xsc_feasible = mx <= 65535;
+    return SPMV_OK;
+}
+
 spmv_status_t build_format(spmv_plan *P, int v) {
+    const int coded = P->code_of(v);
+    if (coded && (v == V_CSR_SCALAR || v == V_CSR_VECTOR))
+        return fail(SPMV_ERR_INFEASIBLE, "%s has no coded-index form",
+                    v == V_CSR_SCALAR ? "CSR_SCALAR" : "CSR_VECTOR");
+    if (v == V_DELTA16 && P->idx_req == 0)
+        return fail(SPMV_ERR_INFEASIBLE, "DELTA16 is the coded form: int32 indices requested");
     switch (v) {
     case V_CSR_SCALAR:
     case V_CSR_VECTOR:
-    case V_SHORT_ROW:
         return SPMV_OK;
+    case V_SHORT_ROW: {
+        if (!coded || P->srow_coded_built) return SPMV_OK;
+        // with codes: the rows-streamed delta16 arrays (block references
+        // from the feasibility check, 16-bit offsets from them)
+        SPMV_TRY(check_d16(P));
+        if (!d16_feasible(P))
+            return fail(SPMV_ERR_INFEASIBLE, "SHORT_ROW codes: a block of rows spans more than 65536 columns");
+        if (!(P->d16_built && P->d16_layout == 0)) {
+            SPMV_TRY(P->d16_off.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 2 + 16));
+            SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(), P->d16_off.as<uint16_t>(), S(P)));
+            SPMV_TRY(sync(P));
+        }
+        P->srow_coded_built = true;
+        return SPMV_OK;
+    }
     case V_DELTA16: {
         if (P->d16_built) return SPMV_OK;
         SPMV_TRY(d16_decide_layout(P));
@@ -656,7 +741,20 @@ spmv_status_t build_format(spmv_plan *P, int v) {
         return SPMV_OK;
     }
     case V_MERGE_PATH: {
-        if (P->mp_built) return SPMV_OK;
+        if (P->mp_built && (!coded || P->mpc_built)) return SPMV_OK;
+        if (P->mp_built) {  // splits there, codes wanted
+            SPMV_TRY(check_merge_codes(P));
+            if (!P->mpc_feasible)
+                return fail(SPMV_ERR_INFEASIBLE, "MERGE_PATH codes: a tile spans %d columns (> 65535)",
+                            (int)P->mpc_span);
+            SPMV_TRY(P->mpc_off.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 2 + 16));
+            SPMV_HIP(launch_range_encode(P->mp_tiles, P->mp_tiles, 1, P->mp_split_nnz.as<int32_t>(),
+                                         P->colind, P->mpc_base.as<int32_t>(), P->mpc_off.as<uint16_t>(),
+                                         S(P)));
+            SPMV_TRY(sync(P));
+            P->mpc_built = true;
+            return SPMV_OK;
+        }
         const int64_t tiles = (P->n + P->nnz + kMergeTile - 1) / kMergeTile;
         P->mp_tiles = tiles;
         SPMV_TRY(P->mp_split_row.alloc((size_t)(tiles + 1) * 4));
@@ -667,10 +765,30 @@ spmv_status_t build_format(spmv_plan *P, int v) {
                                      P->mp_split_nnz.as<int32_t>(), tiles, S(P)));
         SPMV_TRY(sync(P));
         P->mp_built = true;
+        return coded ? build_format(P, v) : SPMV_OK;
+    }
+    case V_XBLOCK_LDS: {
+        SPMV_TRY(build_xslices(P));
+        if (!coded || P->xsc_built) return SPMV_OK;
+        SPMV_TRY(check_xblock_codes(P));
+        if (!P->xsc_feasible)
+            return fail(SPMV_ERR_INFEASIBLE, P->xs_rows == 0
+                        ? "XBLOCK_LDS codes: the slices use merge-path tiles (no coded form)"
+                        : "XBLOCK_LDS codes: a row block of a slice spans %d columns (> 65535)",
+                        (int)P->xsc_span);
+        const size_t len = (size_t)(P->nnz + 8 * P->xs_slices);
+        SPMV_TRY(P->xsc_off.alloc(len * 2 + 16));
+        SPMV_HIP(hipMemsetAsync(P->xsc_off.p, 0, len * 2 + 16, S(P)));
+        const int64_t n = P->n, H = P->xsc_h, nb = (n + H - 1) / H;
+        for (int k = 0; k < P->xs_slices && nb > 0; ++k)
+            SPMV_HIP(launch_range_encode(nb, n, H, P->xs_rowptr.as<int32_t>() + (size_t)k * (n + 1),
+                                         P->xs_colind.as<int32_t>() + P->xs_nnz_off[k],
+                                         P->xsc_base.as<int32_t>() + P->xsc_boff[k],
+                                         P->xsc_off.as<uint16_t>() + P->xs_nnz_off[k], S(P)));
+        SPMV_TRY(sync(P));
+        P->xsc_built = true;
         return SPMV_OK;
     }
-    case V_XBLOCK_LDS:
-        return build_xslices(P);
     default:
         return fail(SPMV_ERR_ARG, "unknown variant %d", v);
     }
@@ -689,11 +807,31 @@ int column_order(const spmv_plan *P, int v) {
     }
 }
 
+// Variants that can run this matrix under the plan's index-coding request
+// (coded forms: their 16-bit codes must fit; building their base format to
+// find out).
 spmv_status_t feasible_mask(spmv_plan *P, uint32_t *bits) {
     SPMV_TRY(check_d16(P));
-    uint32_t b = (1u << V_CSR_SCALAR) | (1u << V_CSR_VECTOR) | (1u << V_MERGE_PATH) |
-                 (1u << V_SHORT_ROW) | (1u << V_XBLOCK_LDS);
-    if (d16_feasible(P)) b |= 1u << V_DELTA16;
+    uint32_t b = 0;
+    if (P->idx_req != 1) {
+        b = (1u << V_CSR_SCALAR) | (1u << V_CSR_VECTOR) | (1u << V_MERGE_PATH) |
+            (1u << V_SHORT_ROW) | (1u << V_XBLOCK_LDS);
+        if (d16_feasible(P) && P->idx_req != 0) b |= 1u << V_DELTA16;
+    } else {
+        if (d16_feasible(P)) b |= (1u << V_DELTA16) | (1u << V_SHORT_ROW);
+        if (!P->mp_built) {
+            const int req = P->idx_req;
+            P->idx_req = 0;  // the splits alone
+            const spmv_status_t st = build_format(P, V_MERGE_PATH);
+            P->idx_req = req;
+            SPMV_TRY(st);
+        }
+        SPMV_TRY(check_merge_codes(P));
+        if (P->mpc_feasible) b |= 1u << V_MERGE_PATH;
+        SPMV_TRY(build_xslices(P));
+        SPMV_TRY(check_xblock_codes(P));
+        if (P->xsc_feasible) b |= 1u << V_XBLOCK_LDS;
+    }
     *bits = b;
     return SPMV_OK;
 }
@@ -838,9 +976,13 @@ int class_variant(int k, const double feats[12], const double th[4], uint32_t fe
 
 // One SpMV with variant v (its format must be built).
 spmv_status_t run_variant(const spmv_plan *P, int v, const void *x, void *y, hipStream_t s) {
+    const int coded = P->code_of(v);
     if ((v == V_DELTA16 && !P->d16_built) || (v == V_MERGE_PATH && !P->mp_built) ||
-        (v == V_XBLOCK_LDS && !P->xs_built))
+        (v == V_XBLOCK_LDS && !P->xs_built) || (coded && v == V_MERGE_PATH && !P->mpc_built) ||
+        (coded && v == V_XBLOCK_LDS && !P->xsc_built) || (coded && v == V_SHORT_ROW && !P->srow_coded_built))
         return fail(SPMV_ERR_ARG, "variant %d has no prepared format", v);
+    if (coded && (v == V_CSR_SCALAR || v == V_CSR_VECTOR))
+        return fail(SPMV_ERR_INFEASIBLE, "variant %d has no coded-index form", v);
     switch (v) {
     case V_CSR_SCALAR: SPMV_HIP(launch_csr_scalar(*P, x, y, s)); break;
     case V_CSR_VECTOR: SPMV_HIP(launch_csr_vector(*P, x, y, s)); break;
@@ -850,7 +992,7 @@ spmv_status_t run_variant(const spmv_plan *P, int v, const void *x, void *y, hip
         else SPMV_HIP(launch_rowstream(*P, true, x, y, s));
         break;
     case V_XBLOCK_LDS: SPMV_HIP(launch_xblock(*P, x, y, s)); break;
-    case V_SHORT_ROW: SPMV_HIP(launch_rowstream(*P, false, x, y, s)); break;
+    case V_SHORT_ROW: SPMV_HIP(launch_rowstream(*P, coded == 1, x, y, s)); break;
     default: return fail(SPMV_ERR_ARG, "unknown variant %d", v);
     }
     return SPMV_OK;
@@ -1086,6 +1228,22 @@ spmv_status_t spmv_set_variant(spmv_plan_t P, int32_t v) {
     return SPMV_OK;
 }
 
+spmv_status_t spmv_set_index_coding(spmv_plan_t P, int32_t coding) {
+    clear_error();
+    if (!P) return fail(SPMV_ERR_ARG, "plan is NULL");
+    if (coding < -1 || coding > 1)
+        return fail(SPMV_ERR_ARG, "index coding must be -1 (each variant's own), 0 (int32) or 1 (16-bit codes)");
+    if (coding == P->idx_req) return SPMV_OK;
+    P->idx_req = coding;
+    // the current variant's format under the new coding, when it has one
+    const spmv_status_t st = build_format(P, P->variant);
+    if (st == SPMV_ERR_INFEASIBLE) {
+        clear_error();
+        return SPMV_OK;
+    }
+    return st;
+}
+
 spmv_status_t spmv_set_kahan_min_len(spmv_plan_t P, int32_t len) {
     clear_error();
     if (!P) return fail(SPMV_ERR_ARG, "plan is NULL");
@@ -1110,8 +1268,19 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
     if (!P || !bytes) return fail(SPMV_ERR_ARG, "NULL argument");
     if (v < 0 || v >= SPMV_N_VARIANTS) return fail(SPMV_ERR_ARG, "unknown variant %d", v);
     const int64_t vb = vbytes(P->dtype), xb = xbytes(P->dtype);
-    const int64_t ib = v == V_DELTA16 ? 2 : 4;
+    const int coded = P->code_of(v);
+    const int64_t ib = coded ? 2 : 4;
     int64_t extra = 0;
+    if (coded && v == V_MERGE_PATH) extra = 4 * ((P->n + P->nnz + kMergeTile - 1) / kMergeTile);
+    if (coded && v == V_XBLOCK_LDS) {  // a reference column per slice and row block
+        SPMV_TRY(build_xslices(P));
+        const int64_t H = P->xs_pj > 0 ? kBlock : (P->xs_rows > 0 ? P->xs_rows : kBlock);
+        extra = 4 * (int64_t)P->xs_slices * ((P->n + H - 1) / H);
+    }
+    if (coded && v == V_SHORT_ROW) {  // the rows-streamed delta16 layout
+        SPMV_TRY(check_d16(P));
+        extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
+    }
     if (v == V_DELTA16) {  // also defined where the variant is infeasible
         SPMV_TRY(check_d16(P));
         if (d16_feasible(P)) SPMV_TRY(d16_decide_layout(P));
@@ -1186,6 +1355,25 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
         break;
     case 10: *value = 1; break;
     case 21: SPMV_TRY(build_format(P, P->variant)); *value = column_order(P, P->variant); break;
+    case 22: *value = P->code_of(P->variant); break;
+    case 23: {  // merge-path codes feasible (tiles of the splits)
+        if (!P->mp_built) {
+            const int req = P->idx_req;
+            P->idx_req = 0;
+            const spmv_status_t st = build_format(P, V_MERGE_PATH);
+            P->idx_req = req;
+            SPMV_TRY(st);
+        }
+        SPMV_TRY(check_merge_codes(P));
+        *value = P->mpc_feasible;
+        break;
+    }
+    case 24:
+        SPMV_TRY(build_xslices(P));
+        SPMV_TRY(check_xblock_codes(P));
+        *value = P->xsc_feasible;
+        break;
+    case 25: SPMV_TRY(build_xslices(P)); SPMV_TRY(check_xblock_codes(P)); *value = P->xsc_h; break;
     default: return fail(SPMV_ERR_ARG, "unknown key %d", key);
     }
     return SPMV_OK;
@@ -1262,6 +1450,42 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
         src = P->xs_lrows.p;
         want = 4 * P->xs_nlong;
         break;
+    case 18: case 19: {  // coded merge path
+        const int req = P->idx_req;
+        P->idx_req = 1;
+        const spmv_status_t st = build_format(P, V_MERGE_PATH);
+        P->idx_req = req;
+        SPMV_TRY(st);
+        src = which == 18 ? P->mpc_base.p : P->mpc_off.p;
+        want = which == 18 ? 4 * P->mp_tiles : 2 * P->nnz;
+        break;
+    }
+    case 20: case 21: {  // coded x blocking
+        const int req = P->idx_req;
+        P->idx_req = 1;
+        const spmv_status_t st = build_format(P, V_XBLOCK_LDS);
+        P->idx_req = req;
+        SPMV_TRY(st);
+        if (which == 21) {  // the codes of the slices without their alignment padding
+            const int64_t want21 = 2 * (P->nnz - P->xs_long_nnz);
+            if (bytes != want21) return fail(SPMV_ERR_ARG, "array 21 has %lld bytes", (long long)want21);
+            int64_t done = 0;
+            for (int k = 0; k < P->xs_slices; ++k) {
+                int32_t last = 0;
+                SPMV_HIP(hipMemcpy(&last, P->xs_rowptr.as<int32_t>() + (size_t)k * (P->n + 1) + P->n, 4,
+                                   hipMemcpyDeviceToHost));
+                if (last > 0)
+                    SPMV_HIP(hipMemcpy(static_cast<uint16_t *>(dst) + done,
+                                       P->xsc_off.as<uint16_t>() + P->xs_nnz_off[k], (size_t)last * 2,
+                                       hipMemcpyDeviceToHost));
+                done += last;
+            }
+            return SPMV_OK;
+        }
+        src = P->xsc_base.p;
+        want = 4 * P->xsc_boff[P->xs_slices];
+        break;
+    }
     default: return fail(SPMV_ERR_ARG, "unknown array %d", which);
     }
     if (bytes != want) return fail(SPMV_ERR_ARG, "array %d has %lld bytes, not %lld", which,
@@ -1475,6 +1699,7 @@ spmv_status_t spmv_set_delta16_layout(spmv_plan_t P, int32_t layout) {
     P->d16_layout_req = layout;
     P->d16_layout = -1;
     P->d16_built = false;
+    P->srow_coded_built = false;
     P->d16_off.release();
     P->d16s_width.release();
     P->d16s_units.release();

@@ -154,6 +154,26 @@ struct spmv_plan {
     bool part_built = false;
     spmvsel::DevBuf part_bounds;
 
+    // index coding (spmv_set_index_coding): -1 each variant's own (DELTA16
+    // coded, the rest int32), 0 int32 column indices, 1 16-bit column codes
+    int idx_req = -1;
+    // 1 if variant v reads 16-bit column codes under the current request
+    int code_of(int v) const { return v == V_DELTA16 ? 1 : (idx_req == 1 ? 1 : 0); }
+    // coded merge path: per tile its smallest column (mpc_base) and 16-bit
+    // offsets from it (mpc_off), feasible when every tile spans < 65536
+    bool mpc_checked = false, mpc_feasible = false, mpc_built = false;
+    int32_t mpc_span = 0;
+    spmvsel::DevBuf mpc_base, mpc_off;
+    // coded x blocking: per slice and row block of xsc_h rows (the slice
+    // kernel's block) its smallest column (xsc_base from xsc_boff[s]) and
+    // 16-bit offsets at the positions of the slice-major columns (xsc_off)
+    bool xsc_checked = false, xsc_feasible = false, xsc_built = false;
+    int32_t xsc_span = 0;
+    int64_t xsc_h = 0, xsc_boff[spmvsel::kSlices + 1] = {0};
+    spmvsel::DevBuf xsc_base, xsc_off;
+    // SHORT_ROW with codes runs the rows-streamed delta16 kernel on these
+    bool srow_coded_built = false;
+
     // timing helpers (lazy)
     spmvsel::DevBuf tx, ty;      // x and y used by spmv_time_variant / profiling
 };
@@ -194,7 +214,8 @@ hipError_t launch_merge_path(const spmv_plan &P, const void *x, void *y, hipStre
 hipError_t launch_merge_path_raw(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
                                  const void *val, int dtype, const void *x, void *y,
                                  const int32_t *srow, const int32_t *snnz, int32_t *crow,
-                                 void *cval, int kmin, hipStream_t s);
+                                 void *cval, int kmin, hipStream_t s,
+                                 const uint16_t *off = nullptr, const int32_t *tbase = nullptr);
 hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t s);
 
 // format preparation (k_prep.hip)
@@ -222,6 +243,13 @@ hipError_t launch_sliced_escapes(const spmv_plan &P, const int32_t *base, const 
 // the escaped columns of the 8-bit codes (eunits: S + 1 prefix sums of E)
 hipError_t launch_sliced_escape_cols(const spmv_plan &P, const int32_t *base, const int32_t *kind,
                                     const int32_t *eunits, int32_t *esc, hipStream_t s);
+// 16-bit codes over ranges of a column array: range k covers positions
+// [bnd[min(k H, nb)], bnd[min((k + 1) H, nb)]); base[k] = its smallest
+// column (0 if empty), span[k] = largest - smallest; then off = ci - base
+hipError_t launch_range_ref(int64_t nranges, int64_t nb, int64_t H, const int32_t *bnd,
+                            const int32_t *ci, int32_t *base, int32_t *span, hipStream_t s);
+hipError_t launch_range_encode(int64_t nranges, int64_t nb, int64_t H, const int32_t *bnd,
+                               const int32_t *ci, const int32_t *base, uint16_t *off, hipStream_t s);
 hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t panels,
                            unsigned long long *d_max, hipStream_t s);
 hipError_t launch_merge_splits(const int32_t *rowptr, int64_t n, int64_t nnz, int32_t *srow,

@@ -380,6 +380,76 @@ hipError_t launch_max_span(const int32_t *cmin, const int32_t *cmax, int64_t pan
     return hipGetLastError();
 }
 
+// ---- 16-bit column codes over ranges of a column array: range k covers
+// positions [bnd[min(k H, nb)], bnd[min((k + 1) H, nb)]) (merge-path tiles:
+// bnd = the tiles' nonzero coordinates, H = 1; x-block row blocks of one
+// slice: bnd = the slice's row pointers, H = the block height).  Each range
+// takes its smallest column as reference; its span is its largest column
+// minus that (0 for an empty range, whose reference is 0).
+__global__ __launch_bounds__(kBlock) void k_range_ref(int64_t nb, int64_t H,
+                                                      const int32_t *__restrict__ bnd,
+                                                      const int32_t *__restrict__ ci,
+                                                      int32_t *__restrict__ base,
+                                                      int32_t *__restrict__ span) {
+    __shared__ int32_t s_lo[kBlock / 64], s_hi[kBlock / 64];
+    const int64_t k = blockIdx.x;
+    const int64_t i0 = k * H < nb ? k * H : nb, i1 = (k + 1) * H < nb ? (k + 1) * H : nb;
+    const int32_t a = bnd[i0], e = bnd[i1];
+    int32_t lo = INT32_MAX, hi = -1;
+    for (int32_t j = a + (int32_t)threadIdx.x; j < e; j += kBlock) {
+        const int32_t c = ci[j];
+        lo = c < lo ? c : lo;
+        hi = c > hi ? c : hi;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+        lo = lo2 < lo ? lo2 : lo;
+        hi = hi2 > hi ? hi2 : hi;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[threadIdx.x >> 6] = lo;
+        s_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            lo = s_lo[w] < lo ? s_lo[w] : lo;
+            hi = s_hi[w] > hi ? s_hi[w] : hi;
+        }
+        base[k] = hi < 0 ? 0 : lo;
+        span[k] = hi < 0 ? 0 : hi - lo;
+    }
+}
+
+// off[j] = ci[j] - base[k] for every position j of range k (ranges as above;
+// only called once every span is known to fit 16 bits).
+__global__ __launch_bounds__(kBlock) void k_range_encode(int64_t nb, int64_t H,
+                                                         const int32_t *__restrict__ bnd,
+                                                         const int32_t *__restrict__ ci,
+                                                         const int32_t *__restrict__ base,
+                                                         uint16_t *__restrict__ off) {
+    const int64_t k = blockIdx.x;
+    const int64_t i0 = k * H < nb ? k * H : nb, i1 = (k + 1) * H < nb ? (k + 1) * H : nb;
+    const int32_t a = bnd[i0], e = bnd[i1], b0 = base[k];
+    for (int32_t j = a + (int32_t)threadIdx.x; j < e; j += kBlock) off[j] = (uint16_t)(ci[j] - b0);
+}
+
+hipError_t launch_range_ref(int64_t nranges, int64_t nb, int64_t H, const int32_t *bnd,
+                            const int32_t *ci, int32_t *base, int32_t *span, hipStream_t s) {
+    if (nranges <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_range_ref, dim3((unsigned)nranges), dim3(kBlock), 0, s, nb, H, bnd, ci, base,
+                       span);
+    return hipGetLastError();
+}
+
+hipError_t launch_range_encode(int64_t nranges, int64_t nb, int64_t H, const int32_t *bnd,
+                               const int32_t *ci, const int32_t *base, uint16_t *off, hipStream_t s) {
+    if (nranges <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_range_encode, dim3((unsigned)nranges), dim3(kBlock), 0, s, nb, H, bnd, ci,
+                       base, off);
+    return hipGetLastError();
+}
+
 // ---- merge path: start coordinate of every tile (t = 0..tiles).  On
 // diagonal d the row coordinate is the smallest i in [max(0, d-NNZ),
 // min(d, N)] with rowptr[i+1] > d - i - 1; the nonzero coordinate is d - i.

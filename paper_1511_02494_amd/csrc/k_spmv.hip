@@ -357,7 +357,9 @@ struct MergeSmem {
     A cval[kBlock];
 };
 
-template <class V>
+// D16: the columns are tbase[tile] + off[j], 16-bit codes from the tile's
+// smallest column (delta16 inside merge-path tiles).
+template <class V, bool D16 = false>
 __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64_t n,
                                            const int32_t *__restrict__ rp,
                                            const int32_t *__restrict__ ci,
@@ -367,7 +369,9 @@ __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64
                                            const int32_t *__restrict__ srow,
                                            const int32_t *__restrict__ snnz,
                                            int32_t *__restrict__ carry_row,
-                                           typename VT<V>::A *__restrict__ carry_val, bool comp) {
+                                           typename VT<V>::A *__restrict__ carry_val, bool comp,
+                                           const uint16_t *__restrict__ off = nullptr,
+                                           const int32_t *__restrict__ tbase = nullptr) {
     using A = typename VT<V>::A;
     const int32_t i0 = srow[tile], j0 = snnz[tile];
     const int32_t i1 = srow[tile + 1], j1 = snnz[tile + 1];
@@ -383,10 +387,12 @@ __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64
         constexpr int PPT = kMergeTile / kBlock;
         int32_t c[PPT];
         V v[PPT];
+        const int32_t tb = D16 ? tbase[tile] : 0;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const int q = threadIdx.x + j * kBlock;
-            c[j] = q < nz ? ld_nt(ci + j0 + q) : 0;
+            if (D16) c[j] = q < nz ? tb + (int32_t)ld_nt(off + j0 + q) : 0;
+            else c[j] = q < nz ? ld_nt(ci + j0 + q) : 0;
             v[j] = q < nz ? ld_nt(val + j0 + q) : V(0);
         }
 #pragma unroll
@@ -450,17 +456,18 @@ __device__ __forceinline__ void merge_tile(MergeSmem<V> &sm, int64_t tile, int64
     }
 }
 
-template <class V>
+template <class V, bool D16>
 __global__ __launch_bounds__(kBlock) void k_merge_path(
     int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
     typename VT<V>::A *__restrict__ y, const int32_t *__restrict__ srow,
     const int32_t *__restrict__ snnz, int32_t *__restrict__ carry_row,
-    typename VT<V>::A *__restrict__ carry_val, int kmin) {
+    typename VT<V>::A *__restrict__ carry_val, int kmin, const uint16_t *__restrict__ off,
+    const int32_t *__restrict__ tbase) {
     __shared__ MergeSmem<V> sm;
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    merge_tile<V>(sm, tile, n, rp, ci, val, x, y, srow, snnz, carry_row, carry_val,
-                  is_f32<typename VT<V>::A>() && kmin < INT32_MAX);
+    merge_tile<V, D16>(sm, tile, n, rp, ci, val, x, y, srow, snnz, carry_row, carry_val,
+                       is_f32<typename VT<V>::A>() && kmin < INT32_MAX, off, tbase);
 }
 
 // Adds the carries of consecutive tiles that end inside the same row, in
@@ -517,6 +524,10 @@ struct SliceTable {
     A *y[kSlices];
     int64_t off[kSlices];
     int64_t tiles[kSlices];
+    // 16-bit column codes of the slice-major arrays (same positions as the
+    // int32 columns) and, per slice, the reference column of each row block
+    const uint16_t *code;
+    const int32_t *cb[kSlices];
 };
 
 template <class V>
@@ -581,7 +592,7 @@ struct LongChunks {
     void *lsum;
 };
 
-template <class V, int R>
+template <class V, int R, bool D16>
 __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t nblocks,
                                                              const int32_t *__restrict__ ci,
                                                              const V *__restrict__ val,
@@ -598,8 +609,8 @@ __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t 
     int s;
     const int64_t b = slice_unit(T.ns, &s);
     if (b >= nblocks) return;
-    rowstream_block<V, false, R, true>(b, n, T.rp[s], ci + T.off[s], nullptr, nullptr, val + T.off[s], x,
-                                 T.y[s], kmin);
+    rowstream_block<V, D16, R, true>(b, n, T.rp[s], ci + T.off[s], D16 ? T.code + T.off[s] : nullptr,
+                                     D16 ? T.cb[s] : nullptr, val + T.off[s], x, T.y[s], kmin);
 }
 
 // Phased row streaming on the slices, without partial y vectors.  Workgroup
@@ -613,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t 
 // row leaves the slices: the long rows' chunk sums, run as extra workgroups
 // of this grid, as a kernel of their own or after the slices, all cost more
 // than the per-slice kernel with partial y vectors below saves.
-template <class V, int J>
+template <class V, int J, bool D16>
 __global__ __launch_bounds__(kBlock) void k_phased_slices(
     int64_t n, int64_t nblk, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const V *__restrict__ val, const typename VT<V>::A *__restrict__ x,
@@ -621,6 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
     using A = typename VT<V>::A;
     using VP = typename Pair<V>::type;
     using IP = typename Pair<int32_t>::type;
+    using OP = typename Pair<uint16_t>::type;
     constexpr int NP = kRunLen / 2;  // pairs per thread per chunk
     __shared__ int32_t s_rp[kBlock + 1];
     __shared__ A s_prod[kChunk];
@@ -636,6 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
     for (int sl = 0; sl < T.ns; ++sl) {
         const int32_t *__restrict__ srp = T.rp[sl];
         const int32_t *__restrict__ sci = ci + T.off[sl];
+        const uint16_t *__restrict__ soff = D16 ? T.code + T.off[sl] : nullptr;
         const V *__restrict__ sv = val + T.off[sl];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -649,6 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
             const int32_t a = s_rp[0], e = s_rp[nrows];
             int32_t k = t < nrows ? s_rp[t] : e;
             const int32_t kend = t < nrows ? s_rp[t + 1] : e;
+            const int32_t bb = D16 ? T.cb[sl][blk] : 0;
             for (int32_t cs = a & ~1; cs < e; cs += kChunk) {
                 A p[kRunLen];
                 // each pair's gathers follow its own loads: with more
@@ -661,14 +675,20 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
                     int32_t c0 = 0, c1 = 0;
                     if (kk + 1 < e) {
                         const VP vv = __builtin_nontemporal_load(reinterpret_cast<const VP *>(sv + kk));
-                        const IP cc = __builtin_nontemporal_load(reinterpret_cast<const IP *>(sci + kk));
                         v0 = vv.x;
                         v1 = vv.y;
-                        c0 = cc.x;
-                        c1 = cc.y;
+                        if (D16) {
+                            const OP oo = __builtin_nontemporal_load(reinterpret_cast<const OP *>(soff + kk));
+                            c0 = bb + (int32_t)oo.x;
+                            c1 = bb + (int32_t)oo.y;
+                        } else {
+                            const IP cc = __builtin_nontemporal_load(reinterpret_cast<const IP *>(sci + kk));
+                            c0 = cc.x;
+                            c1 = cc.y;
+                        }
                     } else if (kk < e) {
                         v0 = sv[kk];
-                        c0 = sci[kk];
+                        c0 = D16 ? bb + (int32_t)soff[kk] : sci[kk];
                     }
                     const bool ok0 = kk >= a && kk < e, ok1 = kk + 1 >= a && kk + 1 < e;
                     p[2 * q] = ok0 ? VT<V>::cvt(v0) * x[c0] : A(0);
@@ -837,10 +857,10 @@ hipError_t phased_geometry(const spmv_plan &P, int *J, int64_t *G) {
     const int64_t nblk = (P.n + kBlock - 1) / kBlock;
     return by_dtype(P.dtype, [&](auto tag) -> hipError_t {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
-        const void *fns[4] = {reinterpret_cast<const void *>(&k_phased_slices<V, 1>),
-                              reinterpret_cast<const void *>(&k_phased_slices<V, 2>),
-                              reinterpret_cast<const void *>(&k_phased_slices<V, 4>),
-                              reinterpret_cast<const void *>(&k_phased_slices<V, 8>)};
+        const void *fns[4] = {reinterpret_cast<const void *>(&k_phased_slices<V, 1, false>),
+                              reinterpret_cast<const void *>(&k_phased_slices<V, 2, false>),
+                              reinterpret_cast<const void *>(&k_phased_slices<V, 4, false>),
+                              reinterpret_cast<const void *>(&k_phased_slices<V, 8, false>)};
         for (int i = 0; i < 4; ++i) {
             const int j = 1 << i;
             int per_cu = 0;
@@ -889,15 +909,22 @@ hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStre
 hipError_t launch_merge_path_raw(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
                                  const void *val, int dtype, const void *x, void *y,
                                  const int32_t *srow, const int32_t *snnz, int32_t *crow,
-                                 void *cval, int kmin, hipStream_t s) {
+                                 void *cval, int kmin, hipStream_t s, const uint16_t *off,
+                                 const int32_t *tbase) {
     if (n == 0) return hipSuccess;
     return by_dtype(dtype, [&](auto tag) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(tag)>>;
         using A = typename VT<V>::A;
         const int64_t tiles = (n + nnz + kMergeTile - 1) / kMergeTile;
         if (tiles <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k_merge_path<V>, dim3((unsigned)tiles), dim3(kBlock), 0, s, n, rp, ci,
-                           (const V *)val, (const A *)x, (A *)y, srow, snnz, crow, (A *)cval, kmin);
+        if (off)
+            hipLaunchKernelGGL((k_merge_path<V, true>), dim3((unsigned)tiles), dim3(kBlock), 0, s, n, rp,
+                               ci, (const V *)val, (const A *)x, (A *)y, srow, snnz, crow, (A *)cval,
+                               kmin, off, tbase);
+        else
+            hipLaunchKernelGGL((k_merge_path<V, false>), dim3((unsigned)tiles), dim3(kBlock), 0, s, n, rp,
+                               ci, (const V *)val, (const A *)x, (A *)y, srow, snnz, crow, (A *)cval,
+                               kmin, (const uint16_t *)nullptr, (const int32_t *)nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const unsigned g = grid_for(tiles, kBlock, INT32_MAX);
@@ -908,9 +935,12 @@ hipError_t launch_merge_path_raw(int64_t n, int64_t nnz, const int32_t *rp, cons
 }
 
 hipError_t launch_merge_path(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
+    const bool coded = P.code_of(V_MERGE_PATH) == 1;
     return launch_merge_path_raw(P.n, P.nnz, P.rowptr, P.colind, P.val, P.dtype, x, y,
                                  P.mp_split_row.as<int32_t>(), P.mp_split_nnz.as<int32_t>(),
-                                 P.mp_carry_row.as<int32_t>(), P.mp_carry_val.p, P.kahan_min, s);
+                                 P.mp_carry_row.as<int32_t>(), P.mp_carry_val.p, P.kahan_min, s,
+                                 coded ? P.mpc_off.as<uint16_t>() : nullptr,
+                                 coded ? P.mpc_base.as<int32_t>() : nullptr);
 }
 
 hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t s) {
@@ -920,6 +950,9 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
         using A = typename VT<V>::A;
         SliceTable<A> T;
         T.ns = P.xs_slices;
+        const bool coded = P.code_of(V_XBLOCK_LDS) == 1;
+        if (coded && !P.xsc_built) return hipErrorInvalidValue;
+        T.code = coded ? P.xsc_off.as<uint16_t>() : nullptr;
         const int G = 8 / T.ns;  // XCDs per slice
         int64_t maxt = 0;
         for (int k = 0; k < T.ns; ++k) {
@@ -931,6 +964,7 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             T.y[k] = P.xs_y.p ? P.xs_y.as<A>() + (size_t)k * P.n : nullptr;  // none when phased
             T.off[k] = P.xs_nnz_off[k];
             T.tiles[k] = P.xs_tiles[k];
+            T.cb[k] = coded ? P.xsc_base.as<int32_t>() + P.xsc_boff[k] : nullptr;
             if (T.tiles[k] > maxt) maxt = T.tiles[k];
         }
         if (P.xs_nlong > 0 && P.xs_rows == 0) return hipErrorInvalidValue;  // split implies streaming
@@ -943,8 +977,12 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             const V *xv = (const V *)P.xs_val.p;
 #define SPMV_PH(JJ)                                                                                    \
     case JJ:                                                                                           \
-        hipLaunchKernelGGL((k_phased_slices<V, JJ>), dim3(g), dim3(kBlock), 0, s, P.n, nblk,          \
-                           P.rowptr, xci, xv, (const A *)x, T, (A *)y, P.kahan_min);                \
+        if (coded)                                                                                     \
+            hipLaunchKernelGGL((k_phased_slices<V, JJ, true>), dim3(g), dim3(kBlock), 0, s, P.n, nblk, \
+                               P.rowptr, xci, xv, (const A *)x, T, (A *)y, P.kahan_min);            \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_phased_slices<V, JJ, false>), dim3(g), dim3(kBlock), 0, s, P.n,     \
+                               nblk, P.rowptr, xci, xv, (const A *)x, T, (A *)y, P.kahan_min);      \
         break;
             if (P.xs_nlong > 0) return hipErrorInvalidValue;  // phased only without long rows
             switch (P.xs_pj) {
@@ -961,16 +999,24 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             const unsigned g = (unsigned)(sg + P.xs_nchunks);
             const int32_t *xci = P.xs_colind.as<int32_t>();
             const V *xv = (const V *)P.xs_val.p;
+#define SPMV_RSS(RR)                                                                                   \
+    case RR:                                                                                           \
+        if (coded)                                                                                     \
+            hipLaunchKernelGGL((k_rowstream_slices<V, RR, true>), dim3(g), dim3(kBlock), 0, s, P.n, nb, \
+                               xci, xv, (const A *)x, T, sg, LC, P.kahan_min);                      \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_rowstream_slices<V, RR, false>), dim3(g), dim3(kBlock), 0, s, P.n,   \
+                               nb, xci, xv, (const A *)x, T, sg, LC, P.kahan_min);                  \
+        break;
             switch (R) {
-            case 1: hipLaunchKernelGGL((k_rowstream_slices<V, 1>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC, P.kahan_min); break;
-            case 2: hipLaunchKernelGGL((k_rowstream_slices<V, 2>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC, P.kahan_min); break;
-            case 4: hipLaunchKernelGGL((k_rowstream_slices<V, 4>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC, P.kahan_min); break;
-            case 8: hipLaunchKernelGGL((k_rowstream_slices<V, 8>), dim3(g), dim3(kBlock), 0, s, P.n, nb, xci, xv, (const A *)x, T, sg, LC, P.kahan_min); break;
+                SPMV_RSS(1) SPMV_RSS(2) SPMV_RSS(4) SPMV_RSS(8)
             default: return hipErrorInvalidValue;
             }
+#undef SPMV_RSS
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         } else if (maxt > 0) {
+            if (coded) return hipErrorInvalidValue;  // codes only for row-streamed slices
             hipLaunchKernelGGL(k_merge_slices<V>, dim3((unsigned)((maxt + G - 1) / G * 8)), dim3(kBlock), 0,
                                s, P.n, P.xs_colind.as<int32_t>(), (const V *)P.xs_val.p,
                                (const A *)x, T, P.kahan_min);

@@ -84,3 +84,14 @@ def test_null_plan_arguments():
         with pytest.raises(S.SpmvError) as e:
             fn(*args)
         assert e.value.status == S.SPMV_ERR_ARG
+
+
+def test_index_coding_rejects_unknown_values():
+    """Checked before the plan is touched (no device call)."""
+    for bad in (-2, 2, 16):
+        with pytest.raises(S.SpmvError) as e:
+            S.spmv_set_index_coding(16, bad)
+        assert e.value.status == S.SPMV_ERR_ARG
+    with pytest.raises(S.SpmvError) as e:
+        S.spmv_set_index_coding(None, 1)
+    assert e.value.status == S.SPMV_ERR_ARG

@@ -183,3 +183,35 @@ def test_fullsize_delta_codes():
         plan.close()
         del v_t, x_t, ys
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("spec", SPECS, ids=[s.name for s in SPECS])
+def test_fullsize_coded_forms(spec):
+    """16-bit column codes inside merge-path tiles, x-block slice blocks and
+    the rows-streamed layout, where they fit, at full size in FP64: every
+    row equal to the same variant on int32 columns and within 1e-12 of the
+    accuracy reference."""
+    rp, ci, v = spec.build()
+    n = len(rp) - 1
+    x = spec.x(n)
+    y_ref, scale = cref.dot2(rp, ci, v, x)
+    plan = S.Plan(dev(rp), dev(ci), dev(v), n, nnz=len(ci))
+    x_t = dev(x)
+    S.spmv_set_index_coding(plan.handle, S.SPMV_IDX_CODED)
+    mask = plan.mask()
+    print(f"\n{spec.name}: coded mask {bin(mask)}", flush=True)
+    for var in (S.V_MERGE_PATH, S.V_XBLOCK_LDS, S.V_SHORT_ROW):
+        if not (mask >> var) & 1:
+            continue
+        ys = []
+        for coding in (S.SPMV_IDX_CODED, S.SPMV_IDX_I32):
+            S.spmv_set_index_coding(plan.handle, coding)
+            plan.set_variant(var)
+            y = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+            plan.execute(x_t, y)
+            torch.cuda.synchronize()
+            ys.append(y.cpu().numpy())
+        assert np.array_equal(ys[0], ys[1]), S.VARIANTS[var]
+        rel = check_whole_vector(ys[0], y_ref, scale, 1e-12, S.VARIANTS[var] + "/coded")
+        print(f"  {S.VARIANTS[var]:>10s} coded = int32, max |y - y_ref| / sum|a||x| = {rel:.3e}", flush=True)
+    plan.close()

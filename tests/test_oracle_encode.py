@@ -417,3 +417,89 @@ def test_xblock_split_takes_long_rows_out():
     # long rows above a quarter of the nonzeros: nothing is split
     lr2, rps2, _ = xblock_split_ref(rp, ci, m, 4, max_share=0.1)
     assert len(lr2) == 0 and np.array_equal(rps2, full)
+
+
+# ---------------------------------------------------------------- 16-bit codes
+# inside merge-path tiles and x-block slice blocks (the index-coding axis)
+from oracle.encode import (merge_codes_ref, merge_walk_ref, range_codes_ref,  # noqa: E402
+                           slice_csr_ref, xblock_codes_ref, xblock_split_ref)
+
+
+def test_range_codes_definition_by_hand():
+    """Hand-counted case: three ranges, one empty."""
+    ci = np.array([7, 9, 12, 3, 100, 40], np.int32)
+    ok, base, off, span = range_codes_ref(ci, [0, 3, 3, 6])
+    assert ok and span == 97
+    assert base.tolist() == [7, 0, 3]
+    assert off.tolist() == [0, 2, 5, 0, 97, 37]
+    ok, _, _, span = range_codes_ref(np.array([0, 65536], np.int32), [0, 2])
+    assert not ok and span == 65536
+    ok, _, _, span = range_codes_ref(np.array([5, 65540], np.int32), [0, 2])
+    assert ok and span == 65535            # the widest span that fits 16 bits
+
+
+def test_merge_codes_tridiagonal_closed_form():
+    """Tridiagonal N = 3000 (row 0 has 2 nonzeros, row i >= 1 starts at
+    nonzero 3 i - 1): 2048 items = 512 row ends + 1536 nonzeros, so tile t
+    (t < 5) starts on row 512 t at nonzero 1536 t, that row's second nonzero,
+    column 512 t, which is the tile's smallest column; its last nonzero is
+    the first of row 512 (t + 1), column 512 (t + 1) - 1.  Every span is
+    below 513 and the codes decode back to the columns."""
+    n = 3000
+    rows = [[j for j in (i - 1, i, i + 1) if 0 <= j < n] for i in range(n)]
+    rp = np.cumsum([0] + [len(r) for r in rows]).astype(np.int32)
+    ci = np.concatenate([np.array(r) for r in rows]).astype(np.int32)
+    ok, base, off, span = merge_codes_ref(rp, ci)
+    si, sj = merge_walk_ref(rp, 2048)
+    assert ok and len(base) == len(si) - 1
+    assert si[:5].tolist() == [0, 512, 1024, 1536, 2048]
+    assert sj[:5].tolist() == [0, 1536, 3072, 4608, 6144]
+    assert base[:5].tolist() == [0, 512, 1024, 1536, 2048]
+    assert span <= 512
+    for t in range(len(base)):
+        seg = ci[sj[t]:sj[t + 1]]
+        assert np.array_equal(base[t] + off[sj[t]:sj[t + 1]].astype(np.int64), seg)
+        if len(seg):
+            assert off[sj[t]:sj[t + 1]].min() == 0     # the reference is attained
+
+
+def test_merge_codes_wide_rows_infeasible():
+    """A tile holding columns 0 and M - 1 with M > 65536 cannot be coded."""
+    rp, ci, _ = synth.uniform_random(3000, 200000, 6, seed=4)
+    ok, _, _, span = merge_codes_ref(rp, ci)
+    assert not ok and span > 65535
+
+
+@pytest.mark.parametrize("S,H", [(1, 256), (2, 256), (4, 512), (8, 256)])
+def test_xblock_codes_round_trip(S, H):
+    """Every slice-major column decodes from its block's reference; blocks
+    are the rows [b H, (b+1) H) of each slice, in slice-major order."""
+    rp, ci, _ = synth.banded(4000, 200, 400, seed=6)
+    n = len(rp) - 1
+    ok, base, off, span = xblock_codes_ref(rp, ci, n, S, H)
+    long_rows, rps, cols = xblock_split_ref(rp, ci, n, S)
+    assert ok
+    nb = (n + H - 1) // H
+    assert len(base) == S * nb
+    start = 0
+    for s in range(S):
+        for b in range(nb):
+            a = start + int(rps[s][b * H]) if b * H <= n else start
+            e = start + int(rps[s][min((b + 1) * H, n)])
+            seg = cols[a:e]
+            got = base[s * nb + b] + off[a:e].astype(np.int64)
+            assert np.array_equal(got, seg)
+            if len(seg):
+                assert seg.min() == base[s * nb + b]
+        start += int(rps[s][n])
+    assert start == len(cols)
+
+
+def test_xblock_codes_span_bound():
+    """Columns of a slice lie in a slice of ceil(M / S) columns, so a slice
+    narrower than 65536 columns always codes, whatever the rows."""
+    rp, ci, _ = synth.uniform_random(2000, 120000, 8, seed=7)
+    ok2, _, _, span2 = xblock_codes_ref(rp, ci, 120000, 2, 256)   # slices of 60000 columns
+    assert ok2 and span2 < 60000
+    ok1, _, _, span1 = xblock_codes_ref(rp, ci, 120000, 1, 256)   # one slice of 120000
+    assert not ok1 and span1 > 65535
