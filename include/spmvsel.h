@@ -505,6 +505,29 @@ spmv_status_t spmv_cg(spmv_plan_t plan, const double *d_b, double *d_x, int32_t 
                       double rtol, void *stream, int32_t *iters, double *rel_resid);
 
 /* ----------------------------------------------------------------------- */
+/* Allocation-free SpMV                                                     */
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  y = A x
+ * with the MERGE_PATH variant's kernels (merge-path splits, then tiles and
+ * their carry fix-up), without a plan: the splits and carries live in a
+ * static device array of 8 MiB that each GPU holds from the first call on it
+ * until the process ends.  Nothing is allocated (no hipMalloc, hipFree or
+ * allocating library call) and nothing needs clearing (every split and carry
+ * is written before it is read).  Arguments as for spmv_plan_create and
+ * spmv_execute; the CSR is not validated (the caller guarantees the
+ * invariants listed at the top of this file).  N + NNZ above 8 MiB / 20 B
+ * times 2048 items (about 858 million) returns SPMV_ERR_ARG before any
+ * device work.  Asynchronous on `stream`.  Calls that overlap in time on
+ * one GPU share its array and race: serialise them (one stream, or events).
+ * The result equals spmv_execute's with MERGE_PATH on the same data, bit for
+ * bit. */
+spmv_status_t spmv_merge_path_noalloc(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                      const int32_t *d_rowptr, const int32_t *d_colind,
+                                      const void *d_val, int32_t val_dtype, const void *d_x,
+                                      void *d_y, void *stream);
+
+/* ----------------------------------------------------------------------- */
 /* Utilities                                                                */
 
 /* FP64 -> FP32 (to_dtype SPMV_F32) or bfloat16 bits (SPMV_BF16), one

@@ -100,6 +100,7 @@ _PROTOS = {
     "spmv_cache_flush": (_I32, [_P]),
     "spmv_hbm_probe": (_I32, [_I64, _PF64, _PF64]),
     "spmv_gather_probe": (_I32, [_I64, _I32, _I32, _I64, _PF64]),
+    "spmv_merge_path_noalloc": (_I32, [_I64, _I64, _I64, _P, _P, _P, _I32, _P, _P, _P]),
     "spmv_last_error": (ctypes.c_char_p, []),
 }
 
@@ -441,6 +442,13 @@ def load_classifiers(dtree: str = DTREE_MODEL, gnb: str = GNB_MODEL) -> list:
             loader({k: np.asarray(v) for k, v in m.items()}, kind)
             got.append(name)
     return got
+
+
+def spmv_merge_path_noalloc(n_rows: int, n_cols: int, nnz: int, rowptr, colind, val, val_dtype: int,
+                            x, y, stream=None):
+    _check("spmv_merge_path_noalloc",
+           lib.spmv_merge_path_noalloc(n_rows, n_cols, nnz, _addr(rowptr), _addr(colind), _addr(val),
+                                       val_dtype, _addr(x), _addr(y), _stream(stream)))
 
 
 def spmv_release_cached_blocks():

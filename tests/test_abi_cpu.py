@@ -86,6 +86,17 @@ def test_null_plan_arguments():
         assert e.value.status == S.SPMV_ERR_ARG
 
 
+def test_noalloc_rejects_before_device_work():
+    """Sizes beyond the static scratch array, bad sizes and dtypes are
+    rejected on the host (no device call is made, so this runs without a GPU)."""
+    limit = (((8 << 20) - 1024) // 20) * 2048
+    for n, m, nnz, dt in [(-1, 4, 0, S.SPMV_F64), (4, 4, -1, S.SPMV_F64), (4, 4, 4, 9),
+                          (limit, 4, 1, S.SPMV_F64), (2 ** 31, 4, 0, S.SPMV_F64)]:
+        with pytest.raises(S.SpmvError) as e:
+            S.spmv_merge_path_noalloc(n, m, nnz, 16, 16, 16, dt, 16, 16, 0)
+        assert e.value.status == S.SPMV_ERR_ARG
+
+
 def test_index_coding_rejects_unknown_values():
     """Checked before the plan is touched (no device call)."""
     for bad in (-2, 2, 16):
