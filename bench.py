@@ -264,6 +264,58 @@ def amortization_report(S, torch, dev, mats, log, rtol=1e-8, max_iters=5000):
     return out
 
 
+def selector_eval(S, torch, dev, seeds, log, reps=5):
+    """The selectors judged live on held-out matrices of the selector sweep's
+    distribution (seeds never used for training or calibration): each matrix
+    is generated on the device, every feasible variant timed (median of
+    ``reps`` after warm-ups), and a fresh plan selected with the learned MLP
+    (profiling fallback), the CART tree and the profiling cascade through
+    spmv_select.  Reported per selector: hit rate within 5% of the fastest
+    variant, mean regret t_pick / t_best - 1, and the median selection cost
+    (spmv_select's own end-to-end time, features and fallback included,
+    format preparation excluded) in SpMVs of the picked variant."""
+    import numpy as np
+    import synth
+    from paper_1511_02494_amd import train as T
+    have_clf = "dtree" in S.load_classifiers()
+    sels = [("mlp", S.SEL_MLP), ("profiling", S.SEL_PROFILING)] + ([("cart", S.SEL_DTREE)] if have_clf else [])
+    rows = []
+    t0 = time.perf_counter()
+    for seed in seeds:
+        spec = synth.sweep_spec(seed)
+        M = T.generate_on_device(spec, torch, dev)
+        plan = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
+        mask = plan.mask()
+        times = T.time_variants(plan, mask, reps)
+        plan.close()
+        best = min(t for t in times if t > 0)
+        row = dict(seed=seed, name=spec.name, n=M["n"], nnz=M["nnz"], best=S.VARIANTS[times.index(best)],
+                   best_us=best * 1e6)
+        for name, sel in sels:
+            p = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
+            info = p.select(sel)
+            p.close()
+            v = info["variant"]
+            row[name] = dict(pick=S.VARIANTS[v], regret=times[v] / best - 1, fell_back=bool(info["fell_back"]),
+                             cost_spmv=info["t_total_s"] / times[v], cost_us=info["t_total_s"] * 1e6)
+        rows.append(row)
+        del M
+    torch.cuda.empty_cache()
+    out = dict(seeds=f"{seeds[0]}..{seeds[-1]} ({len(seeds)} held-out sweep matrices)",
+               seconds=time.perf_counter() - t0, rows=rows)
+    for name, _ in sels:
+        reg = np.array([r[name]["regret"] for r in rows])
+        cost = np.array([r[name]["cost_spmv"] for r in rows])
+        out[name] = dict(hit5=float(np.mean(reg <= 0.05)), mean_regret=float(reg.mean()),
+                         median_cost_spmv=float(np.median(cost)),
+                         cost_le20=float(np.mean(cost <= 20)),
+                         fallback_rate=float(np.mean([r[name]["fell_back"] for r in rows])))
+        log(f"  selector {name:>9s}: within 5% of the best on {100 * out[name]['hit5']:.1f}%, "
+            f"mean regret {100 * out[name]['mean_regret']:.1f}%, median cost "
+            f"{out[name]['median_cost_spmv']:.1f} SpMVs, fallback {100 * out[name]['fallback_rate']:.0f}%")
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +338,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=16.0,
                     help="CPU time budget of the oracle baseline (all four matrices)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant timing table")
+    ap.add_argument("--selector-seeds", type=int, default=64,
+                    help="held-out sweep matrices (seeds 20000 + 8 k) for the live selector "
+                         "evaluation; 0 skips it")
     ap.add_argument("--model", default=None)
     return ap.parse_args()
 
@@ -506,6 +561,8 @@ def main():
     precision = [] if args.no_precision else precision_report(S, torch, dev, mats, per, log)
     amort = [] if args.no_amortization else amortization_report(S, torch, dev, mats, log)
     offw = [] if args.no_offset_width else offset_width_report(S, torch, dev, log, args.scale)
+    seval = (selector_eval(S, torch, dev, [20000 + 8 * k for k in range(args.selector_seeds)], log)
+             if args.selector_seeds > 0 else None)
 
     value = total_bytes / t_total * 1e-9
     # the same work in flops (2 per nonzero): unlike the bytes, the same for
@@ -587,6 +644,7 @@ def main():
         "precision": precision,
         "amortization": amort,
         "offset_width": offw,
+        "selector_eval": seval,
         "per_matrix": per,
     }
     print(json.dumps(out), flush=True)

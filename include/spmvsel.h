@@ -551,10 +551,14 @@ spmv_status_t spmv_generate(int32_t family, const int64_t *params, int32_t n_par
 spmv_status_t spmv_generate_vector(int64_t n, uint64_t seed, double *d_x, void *stream);
 
 /* Device memory the library releases (derived formats, temporaries) is kept
- * per device for reuse, up to 8 GiB in all and 1 GiB per block, because plans
- * are typically created and destroyed around every solve.  This call frees
- * every kept block on every device.  A failed allocation also frees the kept
- * blocks of its device and retries once. */
+ * per device for reuse, up to 2 GiB in all and 1 GiB per block, because plans
+ * are typically created and destroyed around every solve.  Other allocators
+ * (PyTorch's caching allocator) cannot see these blocks: call this before
+ * large allocations elsewhere if memory is tight.  It frees every kept block
+ * on every device.  A failed allocation of the library also frees the kept
+ * blocks of its device and retries once.  Destroying a plan waits for its
+ * stream once (for the whole device if spmv_execute ran it on other streams)
+ * before its buffers join the kept blocks. */
 spmv_status_t spmv_release_cached_blocks(void);
 
 /* Evict the Infinity Cache: read and write a 512 MiB scratch buffer. */

@@ -44,9 +44,12 @@ spmv_status_t fail_hip(hipError_t e, const char *what, const char *file, int lin
 // cost more than the kernels that fill them.  Released blocks are kept per
 // device, up to kCacheBytes in all, and handed out again for requests of at
 // least half their size.  A release waits for the device as hipFree does, so
-// a cached block is never handed out while a kernel may still use it.
+// a cached block is never handed out while a kernel may still use it; plans
+// wait once for their stream(s) and then release all their buffers without
+// further waits.  The cache is invisible to other allocators (PyTorch's), so
+// it is kept small; spmv_release_cached_blocks empties it.
 namespace {
-constexpr size_t kCacheBytes = size_t(8) << 30;
+constexpr size_t kCacheBytes = size_t(2) << 30;
 constexpr size_t kCacheMaxBlock = size_t(1) << 30;  // larger blocks go straight back
 std::mutex g_cache_mu;
 std::multimap<std::pair<int, size_t>, void *> g_cache;  // (device, bytes) -> block
@@ -110,13 +113,16 @@ spmv_status_t DevBuf::alloc(size_t n) {
     return SPMV_OK;
 }
 
+// Set while a plan whose streams have been synchronised releases its buffers.
+static thread_local bool t_streams_synced = false;
+
 void DevBuf::release() {
     if (!p) return;
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != dev) (void)hipSetDevice(dev);
     bool kept = false;
-    if (hipDeviceSynchronize() == hipSuccess) {
+    if (t_streams_synced || hipDeviceSynchronize() == hipSuccess) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         if (bytes <= kCacheMaxBlock && g_cache_total + bytes <= kCacheBytes) {
             g_cache.emplace(std::make_pair(dev, bytes), p);
@@ -903,12 +909,12 @@ spmv_status_t profile_measure(spmv_plan *P, int reps, double meas[5]) {
         P->part_built = true;
     }
     SPMV_TRY(ensure_timing_vectors(P));
-    DevBuf stamps, zeros, rp64, ci64;
+    DevBuf stamps, rowcols, rp64, ci64;  // rowcols: every index of row i is i mod M
     SPMV_TRY(stamps.alloc((size_t)P->parts * 16));
-    SPMV_TRY(zeros.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 4));
+    SPMV_TRY(rowcols.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 4));
     SPMV_TRY(rp64.alloc((size_t)(P->n + 1) * 8));
     SPMV_TRY(ci64.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 8));
-    SPMV_HIP(launch_row_columns(*P, zeros.as<int32_t>(), S(P)));
+    SPMV_HIP(launch_row_columns(*P, rowcols.as<int32_t>(), S(P)));
     SPMV_HIP(launch_widen(P->rowptr, rp64.as<int64_t>(), P->n + 1, S(P)));
     SPMV_HIP(launch_widen(P->colind, ci64.as<int64_t>(), P->nnz, S(P)));
     const int32_t *bounds = P->part_bounds.as<int32_t>();
@@ -919,7 +925,7 @@ spmv_status_t profile_measure(spmv_plan *P, int reps, double meas[5]) {
         return SPMV_OK;
     };
     auto nox = [&]() -> spmv_status_t {
-        SPMV_HIP(launch_csr_part(*P, bounds, P->rowptr, zeros.as<int32_t>(), nullptr, nullptr,
+        SPMV_HIP(launch_csr_part(*P, bounds, P->rowptr, rowcols.as<int32_t>(), nullptr, nullptr,
                                  P->tx.p, P->ty.p, st, S(P)));
         return SPMV_OK;
     };
@@ -1064,8 +1070,12 @@ spmv_status_t mlp_predict(const double f[12], uint32_t feas, hipStream_t s, floa
     return SPMV_OK;
 }
 
-// Return the plan's recycled buffers to the pools and free the rest.
+// Return the plan's recycled buffers to the pools and free the rest, after
+// one wait for the plan's stream (or for the device, if the plan ran on
+// other streams too) instead of a device wait per buffer.
 void release_plan(spmv_plan *P) {
+    const bool ok = P->other_streams ? hipDeviceSynchronize() == hipSuccess
+                                     : hipStreamSynchronize(P->stream) == hipSuccess;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         if (P->h_pinned) g_pinned_pool.push_back(P->h_pinned);
@@ -1076,7 +1086,9 @@ void release_plan(spmv_plan *P) {
         }
     }
     P->h_pinned = nullptr;
+    t_streams_synced = ok;
     delete P;
+    t_streams_synced = false;
 }
 
 }  // namespace
@@ -1198,7 +1210,6 @@ spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
 
 spmv_status_t spmv_plan_destroy(spmv_plan_t P) {
     if (!P) return SPMV_OK;
-    (void)hipStreamSynchronize(P->stream);
     release_plan(P);
     return SPMV_OK;
 }
@@ -1216,6 +1227,7 @@ spmv_status_t spmv_execute(spmv_plan_t P, const void *d_x, void *d_y, void *stre
     if (!P) return fail(SPMV_ERR_ARG, "plan is NULL");
     if (P->n > 0 && !d_y) return fail(SPMV_ERR_ARG, "y is NULL");
     if (P->nnz > 0 && !d_x) return fail(SPMV_ERR_ARG, "x is NULL");
+    if ((hipStream_t)stream != P->stream) P->other_streams = true;
     return run_variant(P, P->variant, d_x, d_y, (hipStream_t)stream);
 }
 

@@ -108,6 +108,7 @@ extern "C" spmv_status_t spmv_cg(spmv_plan_t P, const double *d_b, double *d_x, 
     if (P->n != P->m) return fail(SPMV_ERR_ARG, "CG needs a square matrix");
     if (max_iters < 0 || !(rtol >= 0.0)) return fail(SPMV_ERR_ARG, "bad max_iters or rtol");
     hipStream_t s = (hipStream_t)stream;
+    if (s != P->stream) P->other_streams = true;  // destroy then waits for the device
     const int64_t n = P->n;
     if (iters) *iters = 0;
     if (rel_resid) *rel_resid = 0.0;

@@ -86,6 +86,7 @@ struct spmv_plan {
     const void *val = nullptr;
     int dtype = SPMV_F64;
     hipStream_t stream = nullptr;
+    bool other_streams = false;  // spmv_execute ran on a stream other than `stream`
     uint32_t flags = 0;
     int device = 0;
     int num_cus = 256;

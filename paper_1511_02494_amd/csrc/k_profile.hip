@@ -5,8 +5,10 @@
 // GPU's independent instruction stream, the analogue of a CPU thread).  The
 // wavefront walks its range with a sub-wavefront of W lanes per row (W from
 // the mean row length, as csr_vector).  The same kernel runs the `noxmiss`
-// benchmark (a column array of zeros) and the `inflate` benchmark (64-bit
-// row pointers and column indices).  Each wavefront stamps the device
+// benchmark (every column index of row i replaced by i mod M, which removes
+// the irregular x accesses: the paper's all-zero indices would make every
+// lane of every wavefront read one cache line on a GPU) and the `inflate`
+// benchmark (64-bit row pointers and column indices).  Each wavefront stamps the device
 // real-time clock at its start and end for the `balance` benchmark.
 #include "dev.h"
 #include "internal.h"

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_scalar(int64_t n, const int32_t 
     const bool comp = is_f32<A>() && (b - a) >= kmin;
     Sum<A> s;
     for (int32_t k = a; k < b; ++k) s.add(VT<V>::cvt(val[k]) * x[ci[k]], comp);
-    y[i] = s.s;
+    __builtin_nontemporal_store(s.s, y + i);
 }
 
 // ============================================================ csr_vector
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_vector(int64_t n, const int32_t 
         }
         if (k < b) s.add(VT<V>::cvt(ld_nt(val + k)) * x[ld_nt(ci + k)], comp);
         const A t = group_sum<W>(s.s);
-        if (lane == 0) y[i] = t;
+        if (lane == 0) __builtin_nontemporal_store(t, y + i);
     }
 }
 
@@ -201,7 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
 // their four x entries: on stencils the lanes' columns are consecutive too.
 // Every lane loads every pair up to the slice width (padding slots hold zero
 // offsets, so their gathers stay in range); products past the row's end are
-// dropped, which keeps the loads free of branches.
+// dropped, which keeps the loads free of branches.  y is written with
+// streaming (non-temporal) stores: 4% faster on the 27-point stencil and 10%
+// on short rows from a flushed cache, and no slower warm.
 template <class V, class O>
 __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     int64_t n, int64_t m, int64_t nsl, const int32_t *__restrict__ rp,
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
                 acc = acc + ((k < w && ((mk >> k) & 1u)) ? p[i] : A(0));
             }
         }
-        if (r < n) y[r] = acc;
+        if (r < n) __builtin_nontemporal_store(acc, y + r);
         return;
     }
     const int32_t b = base[sl];
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
             }
         }
     }
-    if (r < n) y[r] = acc.s;
+    if (r < n) __builtin_nontemporal_store(acc.s, y + r);
 }
 
 // ============================================================ merge path
@@ -709,7 +711,7 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int64_t r = (w + j * G) * kBlock + t;
-        if (w + j * G < nblk && r < n) y[r] = acc[j].s;
+        if (w + j * G < nblk && r < n) __builtin_nontemporal_store(acc[j].s, y + r);
     }
 }
 

@@ -143,21 +143,20 @@ def cmd_label(args):
 # --------------------------------------------------------------- training
 
 
-def raw_inputs(features):
-    """g_k = plog2(1 + f_k) for k < 8, f_k otherwise (the model's input map)."""
-    out = []
-    for k, f in enumerate(features):
-        if k < LOG_FEATURES:
-            m, e = math.frexp(1.0 + f)
-            out.append(float(e - 1) + (2.0 * m - 1.0))
-        else:
-            out.append(float(f))
-    return out
-
-
-def normalise(G, mu, rho):
-    G32 = np.asarray(G, dtype=np.float64).astype(np.float32)
-    return ((G32 - mu).astype(np.float32) * rho).astype(np.float32)
+def device_inputs(recs, mu, rho):
+    """The MLP's input vectors z of the records, from the library's own
+    device transform (spmv_mlp_predict with a model carrying this mu and
+    rho): z_k = fl32(fl32(fl32(g_k) - mu_k) * rho_k), g the exact-op log map
+    of the features.  With mu = 0 and rho = 1 it returns fl32(g) itself."""
+    tmp = os.path.join(os.path.dirname(os.path.abspath(__file__)), ".transform_tmp.bin")
+    write_model(tmp, np.zeros(5382, np.float32), mu, rho, 0.0)
+    try:
+        S.spmv_model_load(tmp)
+        Z = np.array([S.spmv_mlp_predict(r["features"], r["mask"])["z"] for r in recs], dtype=np.float32)
+    finally:
+        S.spmv_model_unload()
+        os.remove(tmp)
+    return Z
 
 
 def load_records(path):
@@ -229,11 +228,13 @@ def train_device(Z, labels, masks, Zv, lv, mv, epochs, lr, batch, seed, log):
 def cmd_fit(args):
     recs = load_records(args.train)
     theta = S.spmv_get_thresholds() if args.theta is None else [float(v) for v in args.theta.split(",")]
-    G = np.array([raw_inputs(r["features"]) for r in recs])
+    # the input statistics from the device's own transform: g first (mu = 0,
+    # rho = 1 gives fl32(g)), then z with the fitted mu and rho = 1 / sd
+    G = device_inputs(recs, np.zeros(12, np.float32), np.ones(12, np.float32)).astype(np.float64)
     mu = G.mean(axis=0).astype(np.float32)
     sd = G.std(axis=0)
     rho = (1.0 / np.where(sd > 1e-12, sd, 1.0)).astype(np.float32)
-    Z = normalise(G, mu, rho)
+    Z = device_inputs(recs, mu, rho)
     labels = np.array([r["label"] for r in recs])
     masks = np.array([[(r["mask"] >> v) & 1 for v in range(6)] for r in recs], dtype=bool)
     # validation split: every tenth record by seed order
@@ -245,8 +246,10 @@ def cmd_fit(args):
                                          masks[val], args.epochs, args.lr, args.batch,
                                          args.seed, log)
     log(f"best validation loss {best_loss:.4f} at epoch {ep}")
-    # margin threshold: the smallest tau that keeps the combined selector's
-    # validation hit rate (MLP when confident, profiling otherwise) highest
+    # margin threshold: the tau whose combined selector (MLP when its margin
+    # reaches tau and its inputs are in range, the profiling cascade
+    # otherwise) has the lowest mean regret on the validation split; ties
+    # go to the smaller tau (fewer fallbacks, less selection overhead)
     tmp = args.out + ".tmp"
     write_model(tmp, params, mu, rho, 0.0)
     S.spmv_model_load(tmp)
@@ -254,23 +257,25 @@ def cmd_fit(args):
     preds = [S.spmv_mlp_predict(r["features"], r["mask"]) for r in vrecs]
     prof = [profiling_pick(r, theta) for r in vrecs]
     cands = sorted({0.0} | {float(p["margin"]) for p in preds if np.isfinite(p["margin"])})
-    best_tau, best_score = 0.0, -1.0
+    best_tau, best_score, best_fb = 0.0, float("inf"), 0.0
     for tau in cands:
-        hits, fb = 0, 0
+        reg, fb = 0.0, 0
         for r, p, q in zip(vrecs, preds, prof):
             use_mlp = p["margin"] >= tau and not np.any(np.abs(p["z"]) > 8)
             v = p["variant"] if use_mlp else q
             fb += not use_mlp
-            hits += within(r["times"], v)
-        score = hits / max(1, len(vrecs)) - 0.02 * fb / max(1, len(vrecs))
-        if score > best_score + 1e-12:
-            best_tau, best_score = tau, score
+            reg += r["times"][v] / min(t for t in r["times"] if t > 0) - 1.0
+        score = reg / max(1, len(vrecs))
+        if score < best_score - 1e-12:
+            best_tau, best_score, best_fb = tau, score, fb / max(1, len(vrecs))
     os.remove(tmp)
     write_model(args.out, params, mu, rho, best_tau)
     S.spmv_model_unload()
-    log(f"tau = {best_tau:.4f} (validation score {best_score:.3f}); wrote {args.out}")
+    log(f"tau = {best_tau:.4f} (validation mean regret {best_score:.4f}, fallback rate "
+        f"{best_fb:.3f}); wrote {args.out}")
     info = dict(train=os.path.basename(args.train), records=len(recs), val_records=int(val.sum()),
-                best_val_loss=best_loss, best_epoch=ep, tau=best_tau, theta=theta,
+                best_val_loss=best_loss, best_epoch=ep, tau=best_tau, tau_val_mean_regret=best_score,
+                tau_val_fallback_rate=best_fb, theta=theta,
                 epochs=args.epochs, lr=args.lr, batch=args.batch, seed=args.seed)
     with open(args.out + ".json", "w") as f:
         json.dump(info, f, indent=1)
@@ -290,20 +295,34 @@ THETA_GRID = (
 def cmd_calibrate(args):
     """Thresholds of the profiling cascade that maximise the fraction of
     calibration matrices whose pick is within 5% of the fastest variant (the
-    paper sets them empirically and does not print them)."""
+    paper sets them empirically and does not print them, saying only that the
+    noxmiss threshold must be strict, i.e. high): the search keeps the noxmiss
+    threshold at or above --min-nox, and the best unconstrained thresholds are
+    recorded beside them for comparison."""
     recs = [r for r in load_records(args.labels)
             if args.lo <= r["seed"] < args.hi]
-    best, best_hit = None, -1.0
-    for a in THETA_GRID[0]:
-        for b in THETA_GRID[1]:
-            for c in THETA_GRID[2]:
-                for d in THETA_GRID[3]:
-                    th = [a, b, c, d]
-                    hit = sum(within(r["times"], profiling_pick(r, th)) for r in recs)
-                    if hit > best_hit:
-                        best, best_hit = th, hit
-    out = dict(theta=best, hit_rate=best_hit / max(1, len(recs)), seeds=[args.lo, args.hi],
-               labels=os.path.basename(args.labels))
+
+    def search(min_nox):
+        best, best_hit = None, -1.0
+        for a in THETA_GRID[0]:
+            if a < min_nox:
+                continue
+            for b in THETA_GRID[1]:
+                for c in THETA_GRID[2]:
+                    for d in THETA_GRID[3]:
+                        th = [a, b, c, d]
+                        hit = sum(within(r["times"], profiling_pick(r, th)) for r in recs)
+                        if hit > best_hit:
+                            best, best_hit = th, hit
+        regret = float(np.mean([r["times"][profiling_pick(r, best)] /
+                                min(t for t in r["times"] if t > 0) - 1 for r in recs]))
+        return best, best_hit / max(1, len(recs)), regret
+
+    best, hit, regret = search(args.min_nox)
+    free, free_hit, free_regret = search(0.0)
+    out = dict(theta=best, hit_rate=hit, mean_regret=regret, min_nox=args.min_nox,
+               unconstrained=dict(theta=free, hit_rate=free_hit, mean_regret=free_regret),
+               seeds=[args.lo, args.hi], labels=os.path.basename(args.labels))
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
@@ -510,6 +529,9 @@ def cmd_classic(args):
                 m = clf_fit(kind, Xtr[keep], y[keep], C, **kw)
                 clf_load(kind, m, lkind)
                 hits += clf_predict(kind, train[i])["label"] == y[i]
+                if i % 250 == 249:
+                    print(f"{kind}/{lk} LOOCV {i + 1}/{len(train)}: {hits / (i + 1):.3f}", file=sys.stderr,
+                          flush=True)
             model = clf_fit(kind, Xtr, y, C, **kw)
             clf_load(kind, model, lkind)
             sc = clf_scores(kind, test, test_lab[lk], lkind, theta)
@@ -564,6 +586,8 @@ def main(argv=None):
     a.add_argument("--labels", required=True)
     a.add_argument("--lo", type=int, default=1000)
     a.add_argument("--hi", type=int, default=1100)
+    a.add_argument("--min-nox", type=float, default=1.5,
+                   help="smallest noxmiss threshold searched (the paper: strict, high)")
     a.add_argument("--out", required=True)
     a = sub.add_parser("sweep")
     a.add_argument("--labels", required=True)

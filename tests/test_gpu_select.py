@@ -67,3 +67,33 @@ def test_partition_stamps_balance_score_high_on_long_row():
     meas = S.spmv_profile_measure(plan.handle, 3)
     assert meas[3] / meas[4] > 2.0
     plan.close()
+
+
+def test_mlp_low_margin_falls_back_to_the_cascade(tmp_path):
+    """A model whose margin threshold no prediction reaches: every SEL_MLP
+    selection defers to the profiling cascade, which then decides exactly as
+    the oracle's cascade on the measured times; a threshold of 0 keeps the
+    MLP's own pick.  Same network both times, so only tau differs."""
+    import os
+    from paper_1511_02494_amd.model_io import read_model, write_model
+    if not os.path.exists(S.DEFAULT_MODEL):
+        pytest.skip("no trained model")
+    params, mu, rho, _ = read_model(S.DEFAULT_MODEL)
+    strict = str(tmp_path / "strict.bin")
+    write_model(strict, params, mu, rho, 1e30)
+    rp, ci, v = synth.powerlaw(50000, 109, 10000, seed=2)
+    for path, expect_fb in ((strict, True), (S.DEFAULT_MODEL, None)):
+        S.spmv_model_load(path)
+        plan = make_plan(rp, ci, v, 50000)
+        info = plan.select(S.SEL_MLP)
+        pred = S.spmv_mlp_predict(info["features"], info["feasible"])
+        if expect_fb:
+            assert info["fell_back"] == 1 and info["selector"] == S.SEL_PROFILING
+            assert (info["variant"], info["klass"]) == decide_profile_ref(
+                info["meas"], info["features"], S.spmv_get_thresholds(), info["feasible"])
+        else:
+            assert bool(info["fell_back"]) == bool(pred["fallback"])
+            if not pred["fallback"]:
+                assert info["variant"] == pred["variant"] and info["selector"] == S.SEL_MLP
+        plan.close()
+    S.spmv_model_load(S.DEFAULT_MODEL)
