@@ -316,6 +316,57 @@ def selector_eval(S, torch, dev, seeds, log, reps=5):
     return out
 
 
+def bandwidth_bound_report(S, torch, dev, mats, read_gbs, log, scale=1):
+    """The matrices of the workload that the bandwidth-bound test admits
+    (working set above twice the 256 MiB Infinity Cache, fewer than 0.05
+    line misses per nonzero, at least 8 nonzeros per row; decided from the
+    features before timing): the 27-point stencil of the class set and three
+    bands (2M rows of 30-90 nonzeros in half widths 32 and 200, 4M rows of
+    8-24 nonzeros in half width 16).  For each: the learned selection, its
+    warm and cold time, GB/s on its own algorithmic bytes, % of the 8 TB/s
+    peak and % of the attainable streaming read measured by the probe."""
+    fam = S.FAMILY["banded"]
+    cands = [dict(name=M["name"], M=M, own=False) for M in mats if M["name"].startswith("stencil27")]
+    for n, d16, w, seed in ((2_000_000 // scale, 960, 32, 9), (2_000_000 // scale, 960, 200, 9),
+                            (4_000_000 // scale, 256, 16, 11)):
+        rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        nnz = S.spmv_generate(fam, [n, d16, w], seed, rp)
+        ci = torch.empty(nnz + 8, dtype=torch.int32, device=dev)
+        val = torch.empty(nnz + 8, dtype=torch.float64, device=dev)
+        S.spmv_generate(fam, [n, d16, w], seed, rp, ci, val)
+        x = torch.empty(n, dtype=torch.float64, device=dev)
+        S.spmv_generate_vector(n, seed + 1, x)
+        cands.append(dict(name=f"band_{n}_d{d16 // 16}_w{w}", own=True,
+                          M=dict(rp=rp, ci=ci, val=val, x=x, n=n, m=n, nnz=nnz)))
+    out = []
+    for c in cands:
+        M = c["M"]
+        plan = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
+        f, _ = plan.features()
+        ws = 4 * (M["n"] + 1) + 12 * M["nnz"] + 16 * M["n"]
+        admitted = ws > 2 * 256 * 2 ** 20 and f[10] < 0.05 and f[2] >= 8
+        info = plan.select(S.SEL_MLP)
+        v = info["variant"]
+        tw, _ = plan.time(v, reps=20)
+        tc, _ = plan.time(v, reps=10, cold=True)
+        b = plan.bytes(v)
+        r = dict(matrix=c["name"], n=M["n"], nnz=M["nnz"], working_set=ws, miss_per_nnz=f[10],
+                 nnz_avg=f[2], admitted=admitted, selected=S.VARIANTS[v], bytes_alg=b,
+                 warm_us=tw * 1e6, cold_us=tc * 1e6, warm_gbs=b / tw * 1e-9, cold_gbs=b / tc * 1e-9,
+                 pct_peak_cold=100 * b / tc * 1e-9 / HBM_PEAK_GBS,
+                 pct_peak_warm=100 * b / tw * 1e-9 / HBM_PEAK_GBS,
+                 pct_attainable_read_cold=100 * b / tc * 1e-9 / read_gbs)
+        out.append(r)
+        log(f"  bandwidth-bound {'yes' if admitted else 'no '} {c['name']:>22s} {r['selected']:>10s} "
+            f"cold {tc * 1e6:7.1f} us {r['cold_gbs']:5.0f} GB/s = {r['pct_peak_cold']:.1f}% of peak, "
+            f"{r['pct_attainable_read_cold']:.1f}% of the probe's read; warm {r['pct_peak_warm']:.1f}%")
+        plan.close()
+        if c["own"]:
+            del c["M"]
+    torch.cuda.empty_cache()
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,6 +389,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=16.0,
                     help="CPU time budget of the oracle baseline (all four matrices)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant timing table")
+    ap.add_argument("--no-bandwidth-bound", action="store_true",
+                    help="skip the report on the workload's bandwidth-bound matrices")
     ap.add_argument("--selector-seeds", type=int, default=64,
                     help="held-out sweep matrices (seeds 20000 + 8 k) for the live selector "
                          "evaluation; 0 skips it")
@@ -542,17 +595,25 @@ def main():
         rec["cold_launch_us"] = t_cold * 1e6
         rec["cold_gbs"] = rec["bytes_alg"] / t_cold * 1e-9
         rec["pct_hbm_peak_cold_live"] = 100 * rec["cold_gbs"] / HBM_PEAK_GBS
+        rec["pct_attainable_read_cold"] = 100 * rec["cold_gbs"] / read_gbs
         if v in (S.V_XBLOCK_LDS, S.V_CSR_VECTOR, S.V_MERGE_PATH):
             ns = plan.query(7) if v == S.V_XBLOCK_LDS else 1
             w = -(-M["m"] // ns)
             t_g = S.spmv_gather_probe(w, 8, ns, M["nnz"])
             t_g1 = S.spmv_gather_probe(M["m"], 8, 1, M["nnz"])
+            t_i = S.spmv_gather_probe2(w, 8, ns, M["nnz"], True)
+            t_i1 = S.spmv_gather_probe2(M["m"], 8, 1, M["nnz"], True)
             rec["gather_ceiling"] = dict(
                 gathers=M["nnz"], windows=ns, window_bytes=8 * w, probe_us=t_g * 1e6,
                 probe_whole_x_us=t_g1 * 1e6, frac_warm=t_g / (rec["spmv_us"] * 1e-6),
-                frac_cold=t_g / t_cold)
+                frac_cold=t_g / t_cold,
+                indexed_probe_us=t_i * 1e6, indexed_probe_whole_x_us=t_i1 * 1e6,
+                indexed_frac_warm=t_i / (rec["spmv_us"] * 1e-6), indexed_frac_cold=t_i / t_cold,
+                note="probe: random 8-byte reads alone; indexed: also streaming a 4-byte column "
+                     "and an 8-byte value per read, coalesced (no row sums, no y)")
             log(f"  gather ceiling {M['name']}: {M['nnz']} random 8-byte reads from {ns} x "
-                f"{8 * w / 2**20:.1f} MiB windows {t_g * 1e6:.1f} us (whole x: {t_g1 * 1e6:.1f} us); "
+                f"{8 * w / 2**20:.1f} MiB windows {t_g * 1e6:.1f} us (whole x: {t_g1 * 1e6:.1f} us), "
+                f"indexed {t_i * 1e6:.1f} us (whole x: {t_i1 * 1e6:.1f} us); "
                 f"kernel warm {rec['spmv_us']:.1f} us, cold {t_cold * 1e6:.1f} us")
         plan.close()
         log(f"  cold {M['name']:>22s} {rec['selected']:>10s} {t_cold * 1e6:8.1f} us "
@@ -563,6 +624,8 @@ def main():
     offw = [] if args.no_offset_width else offset_width_report(S, torch, dev, log, args.scale)
     seval = (selector_eval(S, torch, dev, [20000 + 8 * k for k in range(args.selector_seeds)], log)
              if args.selector_seeds > 0 else None)
+    bwb = [] if args.no_bandwidth_bound else bandwidth_bound_report(S, torch, dev, mats, read_gbs, log,
+                                                                    args.scale)
 
     value = total_bytes / t_total * 1e-9
     # the same work in flops (2 per nonzero): unlike the bytes, the same for
@@ -645,6 +708,7 @@ def main():
         "amortization": amort,
         "offset_width": offw,
         "selector_eval": seval,
+        "bandwidth_bound": bwb,
         "per_matrix": per,
     }
     print(json.dumps(out), flush=True)

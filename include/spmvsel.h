@@ -297,6 +297,14 @@ spmv_status_t spmv_bytes(spmv_plan_t plan, int32_t variant, int64_t *bytes);
 spmv_status_t spmv_time_variant(spmv_plan_t plan, int32_t variant, int32_t reps,
                                 int32_t cold, double *t_median_s, double *t_min_s);
 
+/* Back-to-back form of the above (the solver-loop rate): each of `reps`
+ * timed runs is `launches` executions between one event pair, and the times
+ * are per execution (median and minimum over the runs), which spreads the
+ * event overhead and launch jitter of microsecond-scale kernels over the
+ * batch.  Warm only.  launches in [1, 100000]. */
+spmv_status_t spmv_time_variant_batch(spmv_plan_t plan, int32_t variant, int32_t launches,
+                                      int32_t reps, double *t_median_s, double *t_min_s);
+
 /* Plan parameters and derived arrays, for tests and tools.
  * Keys: 0 variant, 1 csr_vector width, 2 short_row/delta16 rows per block,
  * 3 merge-path items per tile, 4 merge-path tiles, 5 x-block columns per
@@ -420,6 +428,18 @@ spmv_status_t spmv_mlp_forward_backward(const float *d_params, const float *d_Z,
                                         const int32_t *d_labels, const uint8_t *d_mask,
                                         int32_t B, float *d_grads, float *d_loss,
                                         void *stream);
+
+/* The same minibatch step with set-valued targets: d_accept[B*6] marks, per
+ * sample, every variant that counts as a correct pick (labelling: those
+ * within 5% of the fastest timed variant).  The loss is the mean of
+ * -log(sum over the feasible marked variants of softmax p_j), whose gradient
+ * with respect to logit j is p_j - p_j [j marked] / sum_marked p; a single
+ * mark per sample is exactly the cross-entropy above.  Every sample needs at
+ * least one feasible mark.  B <= 1024. */
+spmv_status_t spmv_mlp_forward_backward_sets(const float *d_params, const float *d_Z,
+                                             const uint8_t *d_accept, const uint8_t *d_mask,
+                                             int32_t B, float *d_grads, float *d_loss,
+                                             void *stream);
 
 /* Adam (Kingma and Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * p -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */
@@ -577,6 +597,15 @@ spmv_status_t spmv_hbm_probe(int64_t bytes, double *read_gbs, double *copy_gbs);
  * loads).  The windows live in the cache-flush buffer (512 MiB). */
 spmv_status_t spmv_gather_probe(int64_t window_elems, int32_t elem_bytes, int32_t windows,
                                 int64_t gathers, double *t_median_s);
+
+/* The same ceiling with the indices streamed (indexed != 0): every thread
+ * also reads, coalesced, a 4-byte column and an elem_bytes value per gather
+ * from arrays of `gathers` elements (uniform random columns in the window),
+ * which is all a CSR kernel must do per nonzero besides summing rows and
+ * writing y.  indexed = 0 is spmv_gather_probe.  Allocates the two arrays
+ * (12 or 8 bytes per gather) for the call. */
+spmv_status_t spmv_gather_probe2(int64_t window_elems, int32_t elem_bytes, int32_t windows,
+                                 int64_t gathers, int32_t indexed, double *t_median_s);
 
 /* Message of the calling thread's last error ("" if none). */
 const char *spmv_last_error(void);

@@ -114,12 +114,17 @@ def decide(logits, z, feasible_bits: int, tau: float):
 # ---------------------------------------------------------------- training
 
 
-def forward_backward64(params, Z, labels, mask=None):
+def forward_backward64(params, Z, labels, mask=None, accept=None):
     """Mean softmax cross-entropy and its gradient, in FP64.
 
     ``Z`` [B,12], ``labels`` [B] ints, ``mask`` [B,6] booleans of feasible
     variants (None = all feasible).  Infeasible logits are removed from the
-    softmax.  Returns (loss, grad flat float64[5382]).
+    softmax.  With ``accept`` [B,6] booleans (labels then unused), the
+    target of sample b is the set A_b of its accepted feasible variants and
+    its loss is -log(sum_{j in A_b} p_j): the probability that the network's
+    distribution picks an acceptable variant; differentiating,
+    dL/dlogit_j = p_j - [j in A_b] p_j / sum_{A_b} p.  Returns (loss, grad
+    flat float64[5382]).
     """
     P = {k: v.astype(np.float64) for k, v in unpack(np.asarray(params, np.float64)).items()}
     Z = np.asarray(Z, dtype=np.float64)
@@ -134,10 +139,19 @@ def forward_backward64(params, Z, labels, mask=None):
     mx = lg.max(axis=1, keepdims=True)
     ex = np.exp(lg - mx)
     sm = ex / ex.sum(axis=1, keepdims=True)
-    lab = np.asarray(labels, dtype=np.int64)
-    loss = float(np.mean(-np.log(sm[np.arange(B), lab])))
-    d_lg = sm.copy()
-    d_lg[np.arange(B), lab] -= 1.0
+    if accept is None:
+        lab = np.asarray(labels, dtype=np.int64)
+        loss = float(np.mean(-np.log(sm[np.arange(B), lab])))
+        d_lg = sm.copy()
+        d_lg[np.arange(B), lab] -= 1.0
+    else:
+        A = np.asarray(accept, dtype=bool)
+        if mask is not None:
+            A = A & np.asarray(mask, dtype=bool)
+        pa = np.where(A, sm, 0.0)
+        sa = pa.sum(axis=1, keepdims=True)
+        loss = float(np.mean(-np.log(sa[:, 0])))
+        d_lg = sm - pa / sa
     d_lg /= B
     g = {}
     g["W3"] = d_lg.T @ h2
@@ -156,8 +170,8 @@ def forward_backward64(params, Z, labels, mask=None):
     return loss, flat
 
 
-def loss64(params, Z, labels, mask=None) -> float:
-    return forward_backward64(params, Z, labels, mask)[0]
+def loss64(params, Z, labels, mask=None, accept=None) -> float:
+    return forward_backward64(params, Z, labels, mask, accept)[0]
 
 
 def adam_step_ref(p, g, m, v, step: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -75,6 +75,7 @@ _PROTOS = {
     "spmv_set_delta16_offset_bits": (_I32, [_P, _I32]),
     "spmv_bytes": (_I32, [_P, _I32, _PI64]),
     "spmv_time_variant": (_I32, [_P, _I32, _I32, _I32, _PF64, _PF64]),
+    "spmv_time_variant_batch": (_I32, [_P, _I32, _I32, _I32, _PF64, _PF64]),
     "spmv_plan_query": (_I32, [_P, _I32, _PI64]),
     "spmv_plan_copy_format": (_I32, [_P, _I32, _P, _I64]),
     "spmv_profile_measure": (_I32, [_P, _I32, _PF64]),
@@ -85,6 +86,7 @@ _PROTOS = {
     "spmv_model_unload": (_I32, []),
     "spmv_mlp_predict": (_I32, [_PF64, _U32, _PI32, _PF32, _PI32, _PF32, _PF32]),
     "spmv_mlp_forward_backward": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P]),
+    "spmv_mlp_forward_backward_sets": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P]),
     "spmv_mlp_adam_step": (_I32, [_P, _P, _P, _P, _I32, _I32, _F32, _F32, _F32, _F32, _P]),
     "spmv_quantize": (_I32, [_P, _P, _I64, _I32, _P]),
     "spmv_generate": (_I32, [_I32, _PI64, _I32, _U64, _P, _P, _P, _PI64, _P]),
@@ -100,6 +102,7 @@ _PROTOS = {
     "spmv_cache_flush": (_I32, [_P]),
     "spmv_hbm_probe": (_I32, [_I64, _PF64, _PF64]),
     "spmv_gather_probe": (_I32, [_I64, _I32, _I32, _I64, _PF64]),
+    "spmv_gather_probe2": (_I32, [_I64, _I32, _I32, _I64, _I32, _PF64]),
     "spmv_merge_path_noalloc": (_I32, [_I64, _I64, _I64, _P, _P, _P, _I32, _P, _P, _P]),
     "spmv_last_error": (ctypes.c_char_p, []),
 }
@@ -247,6 +250,14 @@ def spmv_time_variant(plan, variant: int, reps: int = 10, cold: bool = False):
     return med.value, mn.value
 
 
+def spmv_time_variant_batch(plan, variant: int, launches: int, reps: int = 5):
+    """(median, min) seconds per SpMV over ``reps`` runs of ``launches`` back-to-back executions."""
+    a, b = _F64(), _F64()
+    _check("spmv_time_variant_batch",
+           lib.spmv_time_variant_batch(plan, variant, launches, reps, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
 def spmv_plan_query(plan, key: int) -> int:
     v = _I64()
     _check("spmv_plan_query", lib.spmv_plan_query(plan, key, ctypes.byref(v)))
@@ -322,6 +333,12 @@ def spmv_mlp_forward_backward(params, Z, labels, mask, B, grads, loss, stream=No
     _check("spmv_mlp_forward_backward",
            lib.spmv_mlp_forward_backward(_addr(params), _addr(Z), _addr(labels), _addr(mask),
                                          B, _addr(grads), _addr(loss), _stream(stream)))
+
+
+def spmv_mlp_forward_backward_sets(params, Z, accept, mask, B, grads, loss, stream=None):
+    _check("spmv_mlp_forward_backward_sets",
+           lib.spmv_mlp_forward_backward_sets(_addr(params), _addr(Z), _addr(accept), _addr(mask), B,
+                                              _addr(grads), _addr(loss), _stream(stream)))
 
 
 def spmv_mlp_adam_step(params, grads, m, v, n, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8,
@@ -470,6 +487,15 @@ def spmv_gather_probe(window_elems: int, elem_bytes: int, windows: int, gathers:
     t = _F64()
     _check("spmv_gather_probe", lib.spmv_gather_probe(window_elems, elem_bytes, windows, gathers,
                                                       ctypes.byref(t)))
+    return t.value
+
+
+def spmv_gather_probe2(window_elems: int, elem_bytes: int, windows: int, gathers: int,
+                       indexed: bool) -> float:
+    """Median time (s) of the gather ceiling, with the indices streamed when ``indexed``."""
+    t = _F64()
+    _check("spmv_gather_probe2", lib.spmv_gather_probe2(window_elems, elem_bytes, windows, gathers,
+                                                        int(indexed), ctypes.byref(t)))
     return t.value
 
 

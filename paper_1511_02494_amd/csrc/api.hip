@@ -1330,6 +1330,27 @@ spmv_status_t spmv_time_variant(spmv_plan_t P, int32_t v, int32_t reps, int32_t 
     return SPMV_OK;
 }
 
+spmv_status_t spmv_time_variant_batch(spmv_plan_t P, int32_t v, int32_t launches, int32_t reps,
+                                      double *t_med, double *t_min) {
+    clear_error();
+    if (!P || reps < 1 || launches < 1 || launches > 100000) return fail(SPMV_ERR_ARG, "bad argument");
+    SPMV_TRY(build_format(P, v));
+    SPMV_TRY(ensure_timing_vectors(P));
+    auto one = [&]() { return run_variant(P, v, P->tx.p, P->ty.p, S(P)); };
+    auto batch = [&]() -> spmv_status_t {
+        for (int i = 0; i < launches; ++i) SPMV_TRY(one());
+        return SPMV_OK;
+    };
+    SPMV_TRY(one());
+    SPMV_TRY(one());
+    std::vector<double> t;
+    SPMV_TRY(time_runs(P, reps, false, batch, &t));
+    for (double &u : t) u /= launches;
+    if (t_med) *t_med = median(t);
+    if (t_min) *t_min = *std::min_element(t.begin(), t.end());
+    return SPMV_OK;
+}
+
 spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
     clear_error();
     if (!P || !value) return fail(SPMV_ERR_ARG, "NULL argument");
@@ -1665,7 +1686,19 @@ spmv_status_t spmv_mlp_forward_backward(const float *params, const float *Z, con
     clear_error();
     if (!params || !Z || !labels || !mask || !grads || !loss || B < 1 || B > 1024)
         return fail(SPMV_ERR_ARG, "bad argument");
-    SPMV_HIP(launch_mlp_fwd_bwd(params, Z, labels, mask, B, grads, loss, (hipStream_t)stream));
+    SPMV_HIP(launch_mlp_fwd_bwd(params, Z, labels, nullptr, mask, B, grads, loss,
+                                (hipStream_t)stream));
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_mlp_forward_backward_sets(const float *params, const float *Z,
+                                             const uint8_t *accept, const uint8_t *mask, int32_t B,
+                                             float *grads, float *loss, void *stream) {
+    clear_error();
+    if (!params || !Z || !accept || !mask || !grads || !loss || B < 1 || B > 1024)
+        return fail(SPMV_ERR_ARG, "bad argument");
+    SPMV_HIP(launch_mlp_fwd_bwd(params, Z, nullptr, accept, mask, B, grads, loss,
+                                (hipStream_t)stream));
     return SPMV_OK;
 }
 
@@ -1795,6 +1828,11 @@ spmv_status_t spmv_hbm_probe(int64_t bytes, double *read_gbs, double *copy_gbs) 
 
 spmv_status_t spmv_gather_probe(int64_t window_elems, int32_t elem_bytes, int32_t windows,
                                 int64_t gathers, double *t_median_s) {
+    return spmv_gather_probe2(window_elems, elem_bytes, windows, gathers, 0, t_median_s);
+}
+
+spmv_status_t spmv_gather_probe2(int64_t window_elems, int32_t elem_bytes, int32_t windows,
+                                 int64_t gathers, int32_t indexed, double *t_median_s) {
     clear_error();
     if (!t_median_s) return fail(SPMV_ERR_ARG, "NULL argument");
     if (elem_bytes != 4 && elem_bytes != 8) return fail(SPMV_ERR_ARG, "elem_bytes must be 4 or 8");
@@ -1818,8 +1856,14 @@ spmv_status_t spmv_gather_probe(int64_t window_elems, int32_t elem_bytes, int32_
             SPMV_HIP(hipMemset(b->p, 0, kFlushBytes));
         }
     }
-    DevBuf sink;
+    DevBuf sink, col, val;
     SPMV_TRY(sink.alloc((size_t)((gathers + 2047) / 2048 + 1) * 8));
+    if (indexed) {  // the streamed columns and values of the indexed form
+        SPMV_TRY(col.alloc((size_t)gathers * 4));
+        SPMV_TRY(val.alloc((size_t)gathers * elem_bytes));
+        SPMV_HIP(launch_fill_cols(col.as<int32_t>(), gathers, window_elems, nullptr));
+        SPMV_HIP(hipMemsetAsync(val.p, 0, (size_t)gathers * elem_bytes, nullptr));
+    }
     hipEvent_t e0, e1;
     SPMV_HIP(hipEventCreate(&e0));
     SPMV_HIP(hipEventCreate(&e1));
@@ -1829,8 +1873,10 @@ spmv_status_t spmv_gather_probe(int64_t window_elems, int32_t elem_bytes, int32_
         float ms = 0.f;
         hipError_t e = hipEventRecord(e0, nullptr);
         if (e == hipSuccess)
-            e = launch_gather_probe(b->p, window_elems, elem_bytes, windows, gathers,
-                                    sink.as<unsigned long long>(), nullptr);
+            e = indexed ? launch_indexed_probe(col.as<int32_t>(), val.p, b->p, window_elems, elem_bytes,
+                                               windows, gathers, sink.as<unsigned long long>(), nullptr)
+                        : launch_gather_probe(b->p, window_elems, elem_bytes, windows, gathers,
+                                              sink.as<unsigned long long>(), nullptr);
         if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);

@@ -291,8 +291,8 @@ hipError_t launch_csr_part(const spmv_plan &P, const int32_t *bounds, const int3
 hipError_t launch_mlp_infer(const float *d_params, const float *d_norm, const double *feats,
                             uint32_t feasible, float tau, float *d_out, hipStream_t s);
 hipError_t launch_mlp_fwd_bwd(const float *params, const float *Z, const int32_t *labels,
-                              const uint8_t *mask, int B, float *grads, float *loss,
-                              hipStream_t s);
+                              const uint8_t *accept, const uint8_t *mask, int B, float *grads,
+                              float *loss, hipStream_t s);
 hipError_t launch_mlp_adam(float *p, const float *g, float *m, float *v, int n, int step,
                            float lr, float b1, float b2, float eps, hipStream_t s);
 
@@ -312,5 +312,10 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
 // needs ceil(gathers / 2048) words
 hipError_t launch_gather_probe(const void *buf, int64_t w, int elem_bytes, int ns,
                                int64_t gathers, unsigned long long *sink, hipStream_t s);
+// the indexed form: stream col[nnz] and val[nnz], gather from the windows
+hipError_t launch_fill_cols(int32_t *col, int64_t nnz, int64_t w, hipStream_t s);
+hipError_t launch_indexed_probe(const int32_t *col, const void *val, const void *buf, int64_t w,
+                                int elem_bytes, int ns, int64_t nnz, unsigned long long *sink,
+                                hipStream_t s);
 
 }  // namespace spmvsel

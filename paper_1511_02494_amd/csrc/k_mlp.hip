@@ -107,10 +107,14 @@ hipError_t launch_mlp_infer(const float *d_params, const float *d_norm, const do
 constexpr int kTrainThreads = 1024;
 
 // workspace (floats): a1[B*64], a2[B*64], dl[B*6], da2[B*64], da1[B*64], lb[B]
+// Loss per sample: -log of the softmax mass of its target set A (feasible
+// logits only): A = {lab[b]} (cross-entropy) when accept is null, else the
+// feasible variants with accept[b*6+j] != 0 (every variant close enough to
+// the fastest).  d loss / d logit_j = p_j - p_j [j in A] / sum_A p.
 __global__ __launch_bounds__(kTrainThreads) void k_mlp_fwd_bwd(
     const float *__restrict__ P, const float *__restrict__ Z, const int32_t *__restrict__ lab,
-    const uint8_t *__restrict__ mask, int B, float *__restrict__ G, float *__restrict__ loss,
-    float *__restrict__ ws) {
+    const uint8_t *__restrict__ accept, const uint8_t *__restrict__ mask, int B,
+    float *__restrict__ G, float *__restrict__ loss, float *__restrict__ ws) {
     float *a1 = ws, *a2 = a1 + B * D1, *dl = a2 + B * D2, *da2 = dl + B * D3, *da1 = da2 + B * D2,
           *lb = da1 + B * D1;
     const int t = threadIdx.x;
@@ -138,13 +142,19 @@ __global__ __launch_bounds__(kTrainThreads) void k_mlp_fwd_bwd(
             lg[j] = acc;
             if (mask[b * D3 + j] && acc > mx) mx = acc;
         }
-        float se = 0.f;
-        for (int j = 0; j < D3; ++j) se += mask[b * D3 + j] ? expf(lg[j] - mx) : 0.f;
-        const int y = lab[b];
-        lb[b] = -(lg[y] - mx - logf(se));
+        float se = 0.f, sa = 0.f;
+        bool in[D3];
         for (int j = 0; j < D3; ++j) {
-            const float sm = mask[b * D3 + j] ? expf(lg[j] - mx) / se : 0.f;
-            dl[b * D3 + j] = (sm - (j == y ? 1.f : 0.f)) / (float)B;
+            const float e = mask[b * D3 + j] ? expf(lg[j] - mx) : 0.f;
+            in[j] = accept ? accept[b * D3 + j] != 0 && mask[b * D3 + j] : j == lab[b];
+            se += e;
+            sa += in[j] ? e : 0.f;
+        }
+        lb[b] = -(logf(sa) - logf(se));
+        for (int j = 0; j < D3; ++j) {
+            const float e = mask[b * D3 + j] ? expf(lg[j] - mx) : 0.f;
+            const float sm = e / se;
+            dl[b * D3 + j] = (sm - (in[j] ? e / sa : 0.f)) / (float)B;
         }
     }
     __syncthreads();
@@ -195,8 +205,8 @@ __global__ __launch_bounds__(kTrainThreads) void k_mlp_fwd_bwd(
 }
 
 hipError_t launch_mlp_fwd_bwd(const float *params, const float *Z, const int32_t *labels,
-                              const uint8_t *mask, int B, float *grads, float *loss,
-                              hipStream_t s) {
+                              const uint8_t *accept, const uint8_t *mask, int B, float *grads,
+                              float *loss, hipStream_t s) {
     static float *ws[64] = {nullptr};  // per-device workspace for B <= 1024
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -206,8 +216,8 @@ hipError_t launch_mlp_fwd_bwd(const float *params, const float *Z, const int32_t
         e = hipMalloc(&ws[dev], (size_t)1024 * (4 * 64 + 6 + 1) * sizeof(float));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3(1), dim3(kTrainThreads), 0, s, params, Z, labels, mask,
-                       B, grads, loss, ws[dev]);
+    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3(1), dim3(kTrainThreads), 0, s, params, Z, labels, accept,
+                       mask, B, grads, loss, ws[dev]);
     return hipGetLastError();
 }
 

@@ -161,6 +161,9 @@ __device__ __forceinline__ void rowstream_block(
             const int32_t lim = rend < ce ? rend : ce;
             for (; k < lim; ++k) acc.add(s_prod[k - cs], comp);
             if (k != rend) break;
+            // plain stores: with R rows per thread the lanes' stores are R rows
+            // apart, and streaming stores of such scattered words ran the
+            // 8M short-rows matrix at half speed (the L2 no longer merges them)
             if (SY) s_y[myr] = acc.s; else y[r0 + myr] = acc.s;
             acc.reset();
             ++myr;

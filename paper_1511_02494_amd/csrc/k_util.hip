@@ -103,4 +103,66 @@ hipError_t launch_gather_probe(const void *buf, int64_t w, int elem_bytes, int n
     return hipGetLastError();
 }
 
+// The indexed form of the gather ceiling: what any CSR kernel must at least
+// do per nonzero - stream its column index (4 bytes) and value (8 or 4),
+// gather x at that column - with no row structure, no sums across threads
+// and no y.  Thread t of the grid takes nonzeros t + j T (j < 8, T threads
+// in all), so every stream is coalesced; workgroup b gathers from window
+// (b mod 8) mod ns as the x-block kernels' XCDs do; the columns are uniform
+// random in [0, w) (k_fill_cols).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_indexed_probe(const int32_t *__restrict__ col,
+                                                          const T *__restrict__ val,
+                                                          const T *__restrict__ buf, uint32_t w,
+                                                          int ns, int64_t nnz,
+                                                          unsigned long long *__restrict__ sink) {
+    constexpr int PER = 8;
+    const T *__restrict__ win = buf + (size_t)((blockIdx.x % 8) % ns) * w;
+    const int64_t TT = (int64_t)gridDim.x * kBlock;
+    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    int32_t c[PER];
+    T v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int64_t k = t + j * TT;
+        c[j] = k < nnz ? __builtin_nontemporal_load(col + k) : 0;
+        v[j] = k < nnz ? __builtin_nontemporal_load(val + k) : T(0);
+    }
+    T a = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) a ^= v[j] ^ win[c[j]];
+    if ((unsigned long long)a == 0x9E3779B97F4A7C15ull) sink[blockIdx.x] = (unsigned long long)a;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_cols(int32_t *__restrict__ col, int64_t nnz,
+                                                      uint32_t w) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * kBlock) {
+        uint64_t h = ((uint64_t)k + 1) * 0x9E3779B97F4A7C15ull;
+        h ^= h >> 31;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 29;
+        col[k] = (int32_t)(((h >> 32) * (uint64_t)w) >> 32);
+    }
+}
+
+hipError_t launch_fill_cols(int32_t *col, int64_t nnz, int64_t w, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_cols, dim3(4096), dim3(kBlock), 0, s, col, nnz, (uint32_t)w);
+    return hipGetLastError();
+}
+
+hipError_t launch_indexed_probe(const int32_t *col, const void *val, const void *buf, int64_t w,
+                                int elem_bytes, int ns, int64_t nnz, unsigned long long *sink,
+                                hipStream_t s) {
+    const int64_t threads = (nnz + 7) / 8;
+    const unsigned g = (unsigned)((threads + kBlock - 1) / kBlock);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_indexed_probe<uint64_t>, dim3(g), dim3(kBlock), 0, s, col,
+                           (const uint64_t *)val, (const uint64_t *)buf, (uint32_t)w, ns, nnz, sink);
+    else
+        hipLaunchKernelGGL(k_indexed_probe<uint32_t>, dim3(g), dim3(kBlock), 0, s, col,
+                           (const uint32_t *)val, (const uint32_t *)buf, (uint32_t)w, ns, nnz, sink);
+    return hipGetLastError();
+}
+
 }  // namespace spmvsel

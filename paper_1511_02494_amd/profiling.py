@@ -38,10 +38,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(path: str, kernel_prefixes) -> float | None:
+def stored_traffic(path: str, kernel_prefixes, cold: bool = True) -> float | None:
     """HBM bytes per launch (fetch + write, summed over the given kernels)
     from a traffic record, or None when it is missing, was taken on other
-    kernel sources, or lacks one of the kernels."""
+    kernel sources, or lacks one of the kernels.  ``cold``: the dispatches
+    that ran right after a cache flush (the bench's cold launches), when the
+    record has them."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -53,7 +55,11 @@ def stored_traffic(path: str, kernel_prefixes) -> float | None:
         hits = [v for k, v in rec["kernels"].items() if k.startswith(name)]
         if not hits:
             return None
-        total += hits[0]["fetch_bytes"] + hits[0]["write_bytes"]
+        h = hits[0]
+        if cold and h.get("cold_dispatches"):
+            total += h["cold_fetch_bytes"] + h["cold_write_bytes"]
+        else:
+            total += h["fetch_bytes"] + h["write_bytes"]
     return total
 
 
@@ -83,6 +89,82 @@ def read_counter(d: str, counter: str):
             if r["Counter_Name"] == counter:
                 out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
     return out
+
+
+FLUSH = "spmvsel::k_flush"
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise SystemExit(f"none of {names} in the CSV columns {sorted(row)}")
+
+
+def cold_flags(names):
+    """For a dispatch sequence (in issue order), True for the dispatches of
+    the execute that follows each cache flush: the bench's cold leg flushes,
+    runs one execute (one to three kernels, none twice) and waits, so the
+    group is the dispatches after a flush up to three of them, ending early
+    at another flush or at a kernel already in the group (the next execute)."""
+    out = [False] * len(names)
+    i = 0
+    while i < len(names):
+        if names[i].startswith(FLUSH):
+            seen = set()
+            j = i + 1
+            while j < len(names) and j <= i + 3 and not names[j].startswith(FLUSH) \
+                    and names[j] not in seen:
+                seen.add(names[j])
+                out[j] = True
+                j += 1
+            i = j
+        else:
+            i += 1
+    return out
+
+
+def read_trace(d: str):
+    """Kernel dispatches of a --kernel-trace run in issue order: (name, ns)."""
+    rows = []
+    with open(_one(d, "kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(_col(r, "Dispatch_Id", "Correlation_Id")), r["Kernel_Name"],
+                         int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))))
+    rows.sort()
+    return [(n, t) for _, n, t in rows]
+
+
+def read_counter_dispatches(d: str, counter: str):
+    """Per dispatch of a --pmc run, in issue order: (name, value KiB); the
+    flush dispatches included (value None if the counter row is missing)."""
+    by = {}
+    with open(_one(d, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            k = int(_col(r, "Dispatch_Id", "Correlation_Id"))
+            if k not in by:
+                by[k] = [r["Kernel_Name"], None]
+            if r["Counter_Name"] == counter:
+                by[k][1] = (by[k][1] or 0.0) + float(r["Counter_Value"])
+    return [tuple(by[k]) for k in sorted(by)]
+
+
+def cold_warm_means(seq):
+    """name -> dict(cold_mean, cold_n, warm_mean, warm_n) over (name, value) pairs."""
+    flags = cold_flags([n for n, _ in seq])
+    acc = defaultdict(lambda: [0.0, 0, 0.0, 0])
+    for (n, v), c in zip(seq, flags):
+        if v is None:
+            continue
+        a = acc[n]
+        if c:
+            a[0] += v
+            a[1] += 1
+        else:
+            a[2] += v
+            a[3] += 1
+    return {n: dict(cold_mean=a[0] / a[1] if a[1] else None, cold_n=a[1],
+                    warm_mean=a[2] / a[3] if a[3] else None, warm_n=a[3]) for n, a in acc.items()}
 
 
 def _short(name: str, n: int = 100) -> str:
@@ -173,10 +255,23 @@ def main(argv=None):
     a = ap.parse_args(argv)
 
     stats = read_stats(a.stats)
+    cw = cold_warm_means(read_trace(a.stats))
     with open(a.stats_md, "w") as f:
         f.write("# Kernel time summary: selected-SpMV bench\n\n")
         f.write(f"Workload: {a.workload}\n\nCommand (repository root, one MI355X):\n\n"
                 f"    {a.cmd_stats}\n\n")
+        f.write("## SpMV kernels, cold and warm dispatches\n\nCold: the dispatches of an execute "
+                "that follows a cache flush (the bench's roofline leg); warm: all others (the "
+                "timed solver loops).  Means of the kernel trace's durations.\n\n"
+                "| kernel | cold dispatches | cold mean us | warm dispatches | warm mean us |\n"
+                "|---|---:|---:|---:|---:|\n")
+        for n in sorted(cw, key=lambda k: -(cw[k]["cold_mean"] or 0)):
+            c = cw[n]
+            if not c["cold_n"] or not n.startswith("void spmvsel::k_"):
+                continue
+            f.write(f"| `{_short(n)}` | {c['cold_n']} | {c['cold_mean'] / 1e3:.1f} | {c['warm_n']} | "
+                    f"{(c['warm_mean'] or 0) / 1e3:.1f} |\n")
+        f.write("\n## All kernels (rocprofv3 --stats)\n\n")
         f.write("| kernel | calls | total ms | average us | min us | max us | % |\n"
                 "|---|---:|---:|---:|---:|---:|---:|\n")
         for r in stats:
@@ -191,6 +286,8 @@ def main(argv=None):
     kib = PROBE_BYTES / 1024
     fscale = kib / (sum(rd) / len(rd))
     wscale = kib / (sum(cp) / len(cp))
+    fcw = cold_warm_means(read_counter_dispatches(a.fetch, "FETCH_SIZE"))
+    wcw = cold_warm_means(read_counter_dispatches(a.write, "WRITE_SIZE"))
     kernels = {}
     for name in sorted(set(fetch) | set(write)):
         fv, wv = fetch.get(name, []), write.get(name, [])
@@ -198,6 +295,11 @@ def main(argv=None):
         wk = sum(wv) / len(wv) if wv else 0.0
         kernels[name] = dict(dispatches=max(len(fv), len(wv)), fetch_kib=fk, write_kib=wk,
                              fetch_bytes=fk * 1024 * fscale, write_bytes=wk * 1024 * wscale)
+        fc, wc = fcw.get(name, {}), wcw.get(name, {})
+        if fc.get("cold_n") and wc.get("cold_n"):
+            kernels[name].update(cold_dispatches=fc["cold_n"],
+                                 cold_fetch_bytes=fc["cold_mean"] * 1024 * fscale,
+                                 cold_write_bytes=wc["cold_mean"] * 1024 * wscale)
     rec = dict(source_sha256=kernel_source_hash(), fetch_scale=fscale, write_scale=wscale,
                probe_bytes=PROBE_BYTES, commands=[a.cmd_fetch, a.cmd_write], kernels=kernels)
     with open(a.traffic_json, "w") as f:
@@ -209,12 +311,16 @@ def main(argv=None):
         f.write(f"Calibration in the same runs (bandwidth probe, {PROBE_BYTES >> 30} GiB buffer): "
                 f"`k_read` FETCH_SIZE scale {fscale:.3f}, `k_copy` WRITE_SIZE scale "
                 f"{wscale:.3f} (true bytes per counter byte). Mean per dispatch.\n\n")
-        f.write("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled fetch MB | "
-                "scaled write MB |\n|---|---:|---:|---:|---:|---:|\n")
+        f.write("Cold: dispatches of an execute right after a cache flush (the bench's roofline "
+                "leg).\n\n| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled fetch MB | "
+                "scaled write MB | cold dispatches | cold fetch MB | cold write MB |\n"
+                "|---|---:|---:|---:|---:|---:|---:|---:|---:|\n")
         for name, v in kernels.items():
+            cold = (f"{v['cold_dispatches']} | {v['cold_fetch_bytes'] / 1e6:.1f} | "
+                    f"{v['cold_write_bytes'] / 1e6:.1f}") if v.get("cold_dispatches") else "0 | | "
             f.write(f"| `{_short(name)}` | {v['dispatches']} | {v['fetch_kib']:.0f} | "
                     f"{v['write_kib']:.0f} | {v['fetch_bytes'] / 1e6:.1f} | "
-                    f"{v['write_bytes'] / 1e6:.1f} |\n")
+                    f"{v['write_bytes'] / 1e6:.1f} | {cold} |\n")
     print(f"wrote {a.stats_md}, {a.traffic_md}, {a.traffic_json}")
 
 

@@ -84,6 +84,32 @@ def test_gradients_against_fp64_oracle(B):
     assert abs(loss.item() - loss64) <= 1e-5 * max(1.0, abs(loss64))
 
 
+@pytest.mark.parametrize("B", [1, 9, 256])
+def test_set_gradients_against_fp64_oracle(B):
+    """Set-valued targets (every acceptable variant marked): device FP32
+    gradients within 1e-4 (Frobenius, per tensor) of the FP64 oracle."""
+    rng = np.random.default_rng(100 + B)
+    p = synth.he_uniform_params(11)
+    p += rng.normal(scale=0.02, size=p.shape).astype(np.float32)
+    Z = rng.normal(size=(B, 12)).astype(np.float32)
+    mask = rng.random((B, 6)) < 0.8
+    acc = (rng.random((B, 6)) < 0.4) & mask
+    first = np.argmax(mask | (np.arange(6) == 0)[None, :], axis=1)
+    mask[np.arange(B), first] = True
+    acc[np.arange(B), first] = True
+    loss64, g64 = mlp.forward_backward64(p.astype(np.float64), Z.astype(np.float64), None, mask, acc)
+    g = torch.empty(5382, dtype=torch.float32, device="cuda:0")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda:0")
+    S.spmv_mlp_forward_backward_sets(dev(p), dev(Z), dev(acc.astype(np.uint8)), dev(mask.astype(np.uint8)),
+                                     B, g, loss)
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy().astype(np.float64)
+    for name, shape, off in mlp.LAYOUT:
+        k = int(np.prod(shape))
+        assert rel_frob(gg[off:off + k], g64[off:off + k]) <= 1e-4, name
+    assert abs(loss.item() - loss64) <= 1e-5 * max(1.0, abs(loss64))
+
+
 def test_adam_step_against_oracle():
     rng = np.random.default_rng(3)
     n = 5382

@@ -109,3 +109,58 @@ def test_transform_order_of_operations():
         g = mlp.plog2(1.0 + f[k]) if k < 8 else f[k]
         assert z[k] == np.float32(np.float32(np.float32(g) - mu[k]) * rho[k])
     assert mlp.plog2(1.0 + 4096.0) == 12 + (2 * (4097 / 8192) - 1)
+
+
+# ---------------------------------------------------------------- set targets
+def accept_sets(seed, mask):
+    rng = np.random.default_rng(seed)
+    A = (rng.random(mask.shape) < 0.4) & mask
+    first = np.argmax(mask, axis=1)
+    A[np.arange(len(A)), first] = True           # at least one feasible mark
+    return A
+
+
+def test_set_loss_gradient_central_differences():
+    p = synth.he_uniform_params(5).astype(np.float64)
+    p += np.random.default_rng(6).normal(scale=0.05, size=p.shape)
+    Z, lab, mask = batch(7)
+    A = accept_sets(8, mask)
+    _, g = mlp.forward_backward64(p, Z, lab, mask, A)
+    idx = np.random.default_rng(9).choice(mlp.N_PARAMS, 300, replace=False)
+    eps = 1e-6
+    for i in idx:
+        d = np.zeros_like(p)
+        d[i] = eps
+        num = (mlp.loss64(p + d, Z, lab, mask, A) - mlp.loss64(p - d, Z, lab, mask, A)) / (2 * eps)
+        assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(num)) + 1e-9, (i, num, g[i])
+
+
+def test_set_loss_special_cases():
+    """Singleton sets are the cross-entropy bit for bit; a set holding every
+    feasible variant costs nothing (its probability is 1: loss 0, gradient 0)."""
+    p = synth.he_uniform_params(10).astype(np.float64)
+    Z, lab, mask = batch(11)
+    one = np.zeros_like(mask)
+    one[np.arange(len(lab)), lab] = True
+    l1, g1 = mlp.forward_backward64(p, Z, lab, mask)
+    l2, g2 = mlp.forward_backward64(p, Z, None, mask, one)
+    assert abs(l1 - l2) <= 1e-15 * max(1.0, abs(l1)) and np.allclose(g1, g2, rtol=0, atol=1e-17)
+    l3, g3 = mlp.forward_backward64(p, Z, None, mask, mask.copy())
+    assert abs(l3) < 1e-15 and np.max(np.abs(g3)) < 1e-15
+
+
+def test_set_loss_bias_only_closed_form():
+    """W = 0: logits = b3, so the loss is -log(sum_A softmax(b3)) for each
+    sample and the b3 gradient is mean(p - p [A] / sum_A p)."""
+    p = np.zeros(mlp.N_PARAMS)
+    b3 = np.array([0.3, -0.1, 0.0, 0.7, -0.4, 0.2])
+    off = dict((n, o) for n, _, o in mlp.LAYOUT)
+    p[off["b3"]:off["b3"] + 6] = b3
+    Z, lab, _ = batch(12)
+    A = accept_sets(13, np.ones((len(lab), 6), bool))
+    loss, g = mlp.forward_backward64(p, Z, None, None, A)
+    sm = np.exp(b3) / np.exp(b3).sum()
+    sa = (A * sm).sum(axis=1)
+    assert abs(loss - np.mean(-np.log(sa))) < 1e-14
+    want = (sm[None, :] - A * sm[None, :] / sa[:, None]).mean(axis=0)
+    np.testing.assert_allclose(g[off["b3"]:off["b3"] + 6], want, atol=1e-15)
