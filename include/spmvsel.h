@@ -130,8 +130,14 @@ typedef struct {
                                d_max, d_mean (per-partition device-clock ticks) */
     double scores[3];       /* s_nox, s_inf, s_bal */
     double features[12];    /* spmv_features output */
-    double t_features_s;    /* host wall-clock of the feature extraction */
-    double t_decide_s;      /* MLP inference (or cascade) */
+    double t_features_s;    /* host wall-clock of the feature extraction and
+                               feasibility test; for SPMV_SEL_MLP on a plan
+                               with no features yet (automatic index coding)
+                               these, the device finalisation of the features
+                               and the network run as one pass on the plan's
+                               stream with one wait, all counted here */
+    double t_decide_s;      /* MLP inference (0 when it ran in that one
+                               pass), or the cascade */
     double t_profile_s;     /* micro-benchmarks (0 unless they ran) */
     double t_total_s;       /* whole selection, excluding format preparation */
     double t_prepare_s;     /* format preparation of the chosen variant */
@@ -169,8 +175,9 @@ spmv_status_t spmv_plan_destroy(spmv_plan_t plan);
  * x between consecutive nonzeros of a row; size is 1 if the CSR working set
  * fits a 256 MiB last-level cache.  Standard deviations are population ones.
  * Computed from exact integer sums (one pass over rowptr and colind on the
- * device) and one fixed FP64 finalisation on the host, so the result is
- * bit-reproducible.  out_acc (nullable) receives the exact sums:
+ * device) and one fixed FP64 finalisation (on the host, or on the device
+ * by the same IEEE operations in the one-pass MLP selection of spmv_select),
+ * so the result is bit-reproducible.  out_acc (nullable) receives the exact sums:
  * nnz_min, nnz_max, bw_max, S_L2, S_bw, S_bw2 (lo, hi), S_q, S_q2 (lo, hi),
  * S_miss, NNZ.  Synchronous on the plan stream. */
 spmv_status_t spmv_features(spmv_plan_t plan, double out_features[12],
@@ -178,7 +185,10 @@ spmv_status_t spmv_features(spmv_plan_t plan, double out_features[12],
 
 /* Choose a variant with `selector` (spmv_selector_t), set it on the plan and
  * build its format.  info (nullable) receives the decision record.
- * Synchronous. */
+ * Synchronous.  SPMV_SEL_MLP on a plan with no features yet, under automatic
+ * index coding, takes one pass (feature kernels, delta16 span test, device
+ * finalisation, network; one wait); the result is the same as that of the
+ * step-by-step path taken otherwise. */
 spmv_status_t spmv_select(spmv_plan_t plan, int32_t selector,
                           spmv_select_info_t *info);
 

@@ -221,7 +221,7 @@ constexpr size_t kOffRec = 256;                       // 16 u64
 constexpr size_t kOffSum = 512;                       // 9 u64: a maximum, slice totals
 constexpr size_t kOffLong = 640;                      // 1 i64: long-row count
 constexpr size_t kOffClf = 768;                       // 80 bytes: classifier output
-constexpr size_t kOffMlp = 1024;                      // 64 floats
+constexpr size_t kOffMlp = 1024;                      // kSelectRecordBytes
 constexpr size_t kOffPart = 4096;                     // kFeatBlocks * 16 u64
 constexpr size_t kScratchBytes = kOffPart + kFeatBlocks * 16 * 8;
 
@@ -306,6 +306,16 @@ spmv_status_t check_d16(spmv_plan *P) {
 }
 
 bool d16_feasible(const spmv_plan *P) { return P->d16_feasible; }
+
+// The block reference columns the delta16 encoder reads: one int32 per block
+// of d16_rows rows, present after the feasibility test.
+spmv_status_t check_d16_base(const spmv_plan *P) {
+    const int64_t blocks = (P->n + P->d16_rows - 1) / P->d16_rows;
+    if (blocks > 0 && (!P->d16_base.p || P->d16_base.bytes < (size_t)blocks * 4))
+        return fail(SPMV_ERR_HIP, "delta16: block references missing (%lld blocks of %d rows)",
+                    (long long)blocks, P->d16_rows);
+    return SPMV_OK;
+}
 
 // delta16 layout: the shape of the sliced layout (widths, reference columns,
 // slot offsets) decides it; sliced when its slots, padding included, are at
@@ -698,7 +708,8 @@ spmv_status_t build_format(spmv_plan *P, int v) {
             return fail(SPMV_ERR_INFEASIBLE, "SHORT_ROW codes: a block of rows spans more than 65536 columns");
         if (!(P->d16_built && P->d16_layout == 0)) {
             SPMV_TRY(P->d16_off.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 2 + 16));
-            SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(), P->d16_off.as<uint16_t>(), S(P)));
+            SPMV_TRY(check_d16_base(P));
+        SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(), P->d16_off.as<uint16_t>(), S(P)));
             SPMV_TRY(sync(P));
         }
         P->srow_coded_built = true;
@@ -740,6 +751,7 @@ spmv_status_t build_format(spmv_plan *P, int v) {
             return SPMV_OK;
         }
         SPMV_TRY(P->d16_off.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 2 + 16));
+        SPMV_TRY(check_d16_base(P));
         SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(), P->d16_off.as<uint16_t>(),
                                        S(P)));
         SPMV_TRY(sync(P));
@@ -1067,6 +1079,74 @@ spmv_status_t mlp_predict(const double f[12], uint32_t feas, hipStream_t s, floa
     if (fallback) *fallback = h_out[2] != 0.f;
     if (logits) memcpy(logits, h_out + 3, 6 * 4);
     if (z) memcpy(z, h_out + 9, 12 * 4);
+    return SPMV_OK;
+}
+
+// The MLP selector's one-pass path for a plan with neither features nor the
+// delta16 test yet, under automatic index coding: one kernel takes the
+// feature sums and the delta16 block windows at both block heights in one
+// pass over the rows, a second reduces them, finalises the features on the
+// device and runs the network, writing the record straight into pinned host
+// memory; one wait.  Returns SPMV_ERR_NO_MODEL (error cleared) without
+// launching anything when no model is loaded.
+spmv_status_t select_mlp_onepass(spmv_plan *P, uint32_t *feas, int32_t *variant, float *margin,
+                                 int32_t *fallback, float *logits) {
+    const float *dp, *dn;
+    {
+        const spmv_status_t st = model_device(&dp, &dn);
+        if (st == SPMV_ERR_NO_MODEL) { clear_error(); return st; }
+        SPMV_TRY(st);
+    }
+    float tau;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        tau = g_model.tau;
+    }
+    const hipStream_t s = S(P);
+    // heights as check_d16 tries them: H0 = the short_row block, then H1 = kBlock;
+    // H1's bases go to d16_cmax, which becomes d16_base when H1 is taken
+    const int R = P->rs_rows, H0 = R * kBlock, H1 = kBlock;
+    const int64_t b0 = (P->n + H0 - 1) / H0, b1 = (P->n + H1 - 1) / H1;
+    SPMV_TRY(P->d16_base.alloc((size_t)b0 * 4));
+    if (R > 1) SPMV_TRY(P->d16_cmax.alloc((size_t)b1 * 4));
+    hipError_t e = hipSuccess;
+    const int parts = launch_select_pass(*P, R, scr<uint64_t>(P, kOffPart), P->d16_base.as<int32_t>(),
+                                         R > 1 ? P->d16_cmax.as<int32_t>() : nullptr,
+                                         xbytes(P->dtype), s, &e);
+    SPMV_HIP(e);  // hipErrorInvalidValue for a row count per thread other than 1, 2, 4, 8
+    char *h = static_cast<char *>(P->h_pinned) + 2048;
+    void *hd = nullptr;
+    SPMV_HIP(hipHostGetDevicePointer(&hd, h, 0));
+    const uint32_t base_bits = (1u << V_CSR_SCALAR) | (1u << V_CSR_VECTOR) |
+                               (1u << V_MERGE_PATH) | (1u << V_SHORT_ROW) | (1u << V_XBLOCK_LDS);
+    SPMV_HIP(launch_mlp_select(dp, dn, scr<uint64_t>(P, kOffPart), parts, P->n, P->m, P->nnz,
+                               vbytes(P->dtype), xbytes(P->dtype), R > 1 ? 1 : 0, base_bits, tau,
+                               static_cast<float *>(hd), s));
+    SPMV_TRY(sync(P));
+    float hf[33];
+    double f[12];
+    uint64_t w[16];
+    memcpy(hf, h, sizeof hf);
+    memcpy(f, h + 192, sizeof f);
+    memcpy(w, h + 288, sizeof w);
+    // delta16: the first height whose blocks fit 16-bit offsets
+    const bool ok0 = w[12] <= 65535, ok1 = R > 1 && w[13] <= 65535;
+    P->d16_feasible = ok0 || ok1;
+    P->d16_rows = ok0 || R == 1 ? H0 : H1;
+    if (R > 1 && P->d16_rows == H1) P->d16_base.swap(P->d16_cmax);  // H0 == H1 when R == 1
+    P->d16_cmax.release();
+    P->d16_checked = true;
+    memcpy(P->feats, f, sizeof f);
+    const int64_t smiss = (int64_t)(w[10] - w[11]);
+    const uint64_t a[12] = {w[0], w[1], w[2], w[3], w[4], w[5],
+                            w[6], w[7], w[8], w[9], (uint64_t)smiss, (uint64_t)P->nnz};
+    memcpy(P->acc, a, sizeof a);
+    P->have_features = true;
+    memcpy(feas, &hf[32], 4);
+    memcpy(variant, &hf[0], 4);
+    *margin = hf[1];
+    *fallback = hf[2] != 0.f;
+    memcpy(logits, hf + 3, 6 * 4);
     return SPMV_OK;
 }
 
@@ -1567,16 +1647,32 @@ spmv_status_t spmv_select(spmv_plan_t P, int32_t selector, spmv_select_info_t *i
     double th[4];
     spmv_get_thresholds(th);
     const double t0 = now_s();
-    SPMV_TRY(ensure_features(P));
     uint32_t feas = 0;
-    SPMV_TRY(feasible_mask(P, &feas));
+    int32_t v = V_CSR_VECTOR;
+    int used = selector;
+    bool onepass = false;
+    if (selector == SEL_MLP && !P->have_features && !P->d16_checked && P->idx_req < 0 && P->n > 0) {
+        int32_t fb = 1;
+        const spmv_status_t st = select_mlp_onepass(P, &feas, &v, &I.margin, &fb, I.logits);
+        if (st == SPMV_OK) {
+            onepass = true;
+            if (fb || v < 0) {
+                I.fell_back = 1;
+                used = SEL_PROFILING;
+            }
+        } else if (st != SPMV_ERR_NO_MODEL) {
+            return st;
+        }
+    }
+    if (!onepass) {
+        SPMV_TRY(ensure_features(P));
+        SPMV_TRY(feasible_mask(P, &feas));
+    }
     const double t1 = now_s();
     I.t_features_s = t1 - t0;
     I.feasible = feas;
     memcpy(I.features, P->feats, sizeof I.features);
-    int32_t v = V_CSR_VECTOR;
-    int used = selector;
-    if (selector == SEL_MLP) {
+    if (selector == SEL_MLP && !onepass) {
         int32_t fb = 1;
         spmv_status_t st = mlp_predict(P->feats, feas, S(P), scr<float>(P, kOffMlp),
                                        static_cast<float *>(P->h_pinned) + 512, &v, &I.margin,

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <type_traits>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,11 @@ struct DevBuf {
     ~DevBuf() { release(); }
     spmv_status_t alloc(size_t n);        // no-op if already >= n bytes
     void release();
+    void swap(DevBuf &o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(dev, o.dev);
+    }
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
@@ -290,6 +296,21 @@ hipError_t launch_csr_part(const spmv_plan &P, const int32_t *bounds, const int3
 // MLP (k_mlp.hip)
 hipError_t launch_mlp_infer(const float *d_params, const float *d_norm, const double *feats,
                             uint32_t feasible, float tau, float *d_out, hipStream_t s);
+// One-pass MLP selection: k_select_pass<R> (feature sums and the delta16
+// block windows at heights 256 R and 256, bases written to base0/base1,
+// partial records to d_partials; returns the partial count, 0 on a bad R),
+// then k_mlp_select (reduction, device finalisation of the features,
+// feasibility, network and decision in one workgroup).  out:
+// kSelectRecordBytes (the inference record in floats 0..31, feasibility bits
+// at float 32, features as doubles 24..35, the reduced record as words
+// 36..51, with the spans in words 48 and 49).
+constexpr size_t kSelectRecordBytes = 416;
+int launch_select_pass(const spmv_plan &P, int R, uint64_t *d_partials, int32_t *base0,
+                       int32_t *base1, int xb, hipStream_t s, hipError_t *err);
+hipError_t launch_mlp_select(const float *d_params, const float *d_norm, const uint64_t *d_partials,
+                             int nparts, int64_t n, int64_t m, int64_t nnz, int vb, int xb,
+                             int two_heights, uint32_t feas_base, float tau, float *out,
+                             hipStream_t s);
 hipError_t launch_mlp_fwd_bwd(const float *params, const float *Z, const int32_t *labels,
                               const uint8_t *accept, const uint8_t *mask, int B, float *grads,
                               float *loss, hipStream_t s);

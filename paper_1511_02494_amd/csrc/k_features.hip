@@ -13,56 +13,12 @@
 // (lo/hi), 7 S_q, 8/9 S_q2 (lo/hi), 10 long gaps (all pairs), 11 long gaps at
 // row starts.
 #include "dev.h"
+#include "feat_acc.h"
 #include "internal.h"
 
 namespace spmvsel {
+using namespace feat;
 
-namespace {
-typedef unsigned __int128 u128;
-
-struct Acc {
-    uint64_t lmin, lmax, bwmax, sl2, sbw, sq, gaps, corr;
-    u128 sbw2, sq2;
-    __device__ void init() {
-        lmin = ~0ull; lmax = 0; bwmax = 0; sl2 = 0; sbw = 0; sq = 0; gaps = 0; corr = 0;
-        sbw2 = 0; sq2 = 0;
-    }
-    __device__ void merge(const Acc &o) {
-        lmin = o.lmin < lmin ? o.lmin : lmin;
-        lmax = o.lmax > lmax ? o.lmax : lmax;
-        bwmax = o.bwmax > bwmax ? o.bwmax : bwmax;
-        sl2 += o.sl2; sbw += o.sbw; sq += o.sq; gaps += o.gaps; corr += o.corr;
-        sbw2 += o.sbw2; sq2 += o.sq2;
-    }
-    __device__ void store(uint64_t *w) const {
-        w[0] = lmin; w[1] = lmax; w[2] = bwmax; w[3] = sl2; w[4] = sbw;
-        w[5] = (uint64_t)sbw2; w[6] = (uint64_t)(sbw2 >> 64); w[7] = sq;
-        w[8] = (uint64_t)sq2; w[9] = (uint64_t)(sq2 >> 64); w[10] = gaps; w[11] = corr;
-        w[12] = w[13] = w[14] = w[15] = 0;
-    }
-    __device__ void load(const uint64_t *w) {
-        lmin = w[0]; lmax = w[1]; bwmax = w[2]; sl2 = w[3]; sbw = w[4];
-        sbw2 = ((u128)w[6] << 64) | w[5]; sq = w[7]; sq2 = ((u128)w[9] << 64) | w[8];
-        gaps = w[10]; corr = w[11];
-    }
-};
-
-__device__ void block_reduce(Acc &a, uint64_t *out) {
-    __shared__ uint64_t sw[kBlock][16];
-    a.store(sw[threadIdx.x]);
-    __syncthreads();
-    for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
-        if ((int)threadIdx.x < stride) {
-            Acc o;
-            o.load(sw[threadIdx.x + stride]);
-            a.merge(o);
-            a.store(sw[threadIdx.x]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) a.store(out);
-}
-}  // namespace
 
 __global__ __launch_bounds__(kBlock) void k_features(int64_t n, int64_t nnz, int xb,
                                                      const int32_t *__restrict__ rp,
@@ -71,24 +27,8 @@ __global__ __launch_bounds__(kBlock) void k_features(int64_t n, int64_t nnz, int
     Acc a;
     a.init();
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += stride) {
-        const int32_t s = rp[i], e = rp[i + 1];
-        const uint64_t L = (uint64_t)(e - s);
-        a.lmin = L < a.lmin ? L : a.lmin;
-        a.lmax = L > a.lmax ? L : a.lmax;
-        a.sl2 += L * L;
-        if (L > 0) {
-            const int32_t c0 = ci[s], cl = ci[e - 1];
-            const uint64_t bw = (uint64_t)(cl - c0);
-            const uint64_t q = (L << 31) / (bw + 1);
-            a.bwmax = bw > a.bwmax ? bw : a.bwmax;
-            a.sbw += bw;
-            a.sbw2 += (u128)bw * bw;
-            a.sq += q;
-            a.sq2 += (u128)q * q;
-            if (s >= 1 && (int64_t)(c0 - ci[s - 1]) * xb > kLineBytes) ++a.corr;
-        }
-    }
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += stride)
+        a.row(ci, rp[i], rp[i + 1], xb);
     for (int64_t k = 1 + blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nnz; k += stride)
         if ((int64_t)(ci[k] - ci[k - 1]) * xb > kLineBytes) ++a.gaps;
     block_reduce(a, partials + 16 * blockIdx.x);
@@ -107,10 +47,12 @@ __global__ __launch_bounds__(kBlock) void k_features_final(int nparts,
     block_reduce(a, rec);
 }
 
+// one row (and one nonzero) per thread up to kFeatBlocks workgroups: a small
+// matrix is then one round of dependent loads, not several
 hipError_t launch_features(const spmv_plan &P, uint64_t *d_partials, uint64_t *d_rec, int xb,
                            hipStream_t s) {
     int64_t items = P.n > P.nnz ? P.n : P.nnz;
-    int64_t g = (items + kBlock * 8 - 1) / (kBlock * 8);
+    int64_t g = (items + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
     if (g > kFeatBlocks) g = kFeatBlocks;
     hipLaunchKernelGGL(k_features, dim3((unsigned)g), dim3(kBlock), 0, s, P.n, P.nnz, xb,
@@ -119,6 +61,104 @@ hipError_t launch_features(const spmv_plan &P, uint64_t *d_partials, uint64_t *d
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_features_final, dim3(1), dim3(kBlock), 0, s, (int)g, d_partials, d_rec);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- one-pass selection
+// The feature sums of k_features and the delta16 block windows in one pass
+// over the rows.  Blocks of H0 = R * 256 rows are walked by workgroups in
+// turn; thread t takes rows t, t + 256, ..., t + (R - 1) 256 of a block, so
+// its k-th row lies in 256-row sub-block k.  Each sub-block's window [min
+// first column, max last column] gives base1 (H1 = 256) and the block's
+// union gives base0 (H0), both as k_panel_windows writes them; the largest
+// spans go to words 12 (H0) and 13 (H1) of the partial records.  The rows'
+// feature sums and the nonzero gap count are the same integers as
+// k_features's, in another grouping.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_select_pass(int64_t n, int64_t nnz, int xb,
+                                                        const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        uint64_t *__restrict__ partials,
+                                                        int32_t *__restrict__ base0,
+                                                        int32_t *__restrict__ base1) {
+    __shared__ int32_t wlo[R][kBlock / 64], whi[R][kBlock / 64];
+    Acc a;
+    a.init();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t blocks0 = (n + R * kBlock - 1) / (R * kBlock);
+    for (int64_t p = blockIdx.x; p < blocks0; p += gridDim.x) {
+        int32_t lo[R], hi[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            lo[k] = INT32_MAX;
+            hi[k] = -1;
+            const int64_t i = p * (R * kBlock) + k * kBlock + threadIdx.x;
+            if (i < n) {
+                const int32_t s = rp[i], e = rp[i + 1];
+                a.row(ci, s, e, xb);
+                if (s < e) {
+                    lo[k] = ci[s];
+                    hi[k] = ci[e - 1];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            for (int o = 32; o > 0; o >>= 1) {
+                const int32_t lo2 = __shfl_xor(lo[k], o, 64), hi2 = __shfl_xor(hi[k], o, 64);
+                lo[k] = lo2 < lo[k] ? lo2 : lo[k];
+                hi[k] = hi2 > hi[k] ? hi2 : hi[k];
+            }
+            if (lane == 0) {
+                wlo[k][wv] = lo[k];
+                whi[k][wv] = hi[k];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t l0 = INT32_MAX, h0 = -1;
+            for (int k = 0; k < R; ++k) {
+                int32_t l1 = INT32_MAX, h1 = -1;
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    l1 = wlo[k][w] < l1 ? wlo[k][w] : l1;
+                    h1 = whi[k][w] > h1 ? whi[k][w] : h1;
+                }
+                const int64_t q = p * R + k;
+                if (R > 1 && q * kBlock < n) {
+                    base1[q] = h1 < 0 ? 0 : l1;
+                    const uint64_t d = h1 < 0 ? 0 : (uint64_t)(h1 - l1);
+                    a.span1 = d > a.span1 ? d : a.span1;
+                }
+                l0 = l1 < l0 ? l1 : l0;
+                h0 = h1 > h0 ? h1 : h0;
+            }
+            base0[p] = h0 < 0 ? 0 : l0;
+            const uint64_t d = h0 < 0 ? 0 : (uint64_t)(h0 - l0);
+            a.span0 = d > a.span0 ? d : a.span0;
+        }
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = 1 + blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nnz; k += stride)
+        if ((int64_t)(ci[k] - ci[k - 1]) * xb > kLineBytes) ++a.gaps;
+    block_reduce(a, partials + 16 * blockIdx.x);
+}
+
+int launch_select_pass(const spmv_plan &P, int R, uint64_t *d_partials, int32_t *base0,
+                       int32_t *base1, int xb, hipStream_t s, hipError_t *err) {
+    const int64_t blocks0 = (P.n + (int64_t)R * kBlock - 1) / ((int64_t)R * kBlock);
+    const int64_t by_nnz = (P.nnz + kBlock - 1) / kBlock;
+    int64_t g = blocks0 > by_nnz ? blocks0 : by_nnz;
+    g = g < 1 ? 1 : g > kFeatBlocks ? kFeatBlocks : g;
+    const dim3 grid((unsigned)g), blk(kBlock);
+    switch (R) {
+    case 1: hipLaunchKernelGGL(k_select_pass<1>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials, base0, base1); break;
+    case 2: hipLaunchKernelGGL(k_select_pass<2>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials, base0, base1); break;
+    case 4: hipLaunchKernelGGL(k_select_pass<4>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials, base0, base1); break;
+    case 8: hipLaunchKernelGGL(k_select_pass<8>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials, base0, base1); break;
+    default: *err = hipErrorInvalidValue; return 0;
+    }
+    *err = hipGetLastError();
+    return (int)g;
 }
 
 }  // namespace spmvsel

@@ -4,6 +4,8 @@ import pytest
 
 import synth
 import paper_1511_02494_amd as S
+from oracle.encode import delta16_ref
+from oracle.features import features_ref
 from oracle.select import decide_profile_ref, profile_scores
 from oracle.spmv import spmv_exact, within_tolerance
 
@@ -97,3 +99,63 @@ def test_mlp_low_margin_falls_back_to_the_cascade(tmp_path):
                 assert info["variant"] == pred["variant"] and info["selector"] == S.SEL_MLP
         plan.close()
     S.spmv_model_load(S.DEFAULT_MODEL)
+
+
+def strided_rows(n, stride, seed):
+    """Two nonzeros per row at columns stride * i and stride * i + 50: a
+    block of 256 rows spans 255 stride + 50 columns, a block of 1024 rows
+    four times as many."""
+    rng = np.random.default_rng(seed)
+    rp = np.arange(0, 2 * n + 1, 2, dtype=np.int32)
+    ci = np.empty(2 * n, np.int32)
+    ci[0::2] = stride * np.arange(n)
+    ci[1::2] = stride * np.arange(n) + 50
+    return rp, ci, rng.uniform(-1, 1, 2 * n), stride * n
+
+
+ONEPASS = MATS + [
+    ("laplace256", lambda: synth.laplace2d(256), 65536),
+    ("strided", lambda: strided_rows(20000, 200, 7)[:3], 4_000_000),
+]
+
+
+@pytest.mark.parametrize("name,build,m", ONEPASS)
+def test_mlp_one_pass_matches_two_step(name, build, m):
+    """SEL_MLP on a fresh plan runs features, the delta16 span test, the
+    device finalisation of the features and the network in one pass; on a
+    plan whose features were already taken it runs them step by step.  Both
+    give the same features (bit for bit the oracle's), feasibility, delta16
+    block height and base columns, logits, margin and (unless the margin sent
+    it to the timed cascade) variant."""
+    import os
+    if not os.path.exists(S.DEFAULT_MODEL):
+        pytest.skip("no trained model")
+    S.spmv_model_load(S.DEFAULT_MODEL)
+    rp, ci, v = build()
+    a = make_plan(rp, ci, v, m)
+    b = make_plan(rp, ci, v, m)
+    b.features()
+    ia, ib = a.select(S.SEL_MLP), b.select(S.SEL_MLP)
+    f_ref, _ = features_ref(rp, ci, m)
+    assert list(ia["features"]) == f_ref == list(ib["features"])
+    assert a.features() == b.features()
+    assert ia["feasible"] == ib["feasible"] == a.mask()
+    assert list(ia["logits"]) == list(ib["logits"]) and ia["margin"] == ib["margin"]
+    assert ia["fell_back"] == ib["fell_back"]
+    if not ia["fell_back"]:
+        assert ia["variant"] == ib["variant"]
+    H, ok = a.query(11), a.query(9)
+    assert (H, ok) == (b.query(11), b.query(9))
+    ok_ref, base, _ = delta16_ref(rp, ci, H)
+    assert ok == int(ok_ref)
+    if name == "strided":  # the 1024-row blocks are too wide: the 256-row base is kept
+        assert (H, ok) == (256, 1) and not delta16_ref(rp, ci, 1024)[0]
+    if ok:
+        S.spmv_set_delta16_layout(a.handle, 0)
+        assert np.array_equal(S.spmv_plan_copy_format(a.handle, 0, len(base)), base)
+        x = synth.vector(m, 3)
+        y = run(a, S.V_DELTA16, x)
+        yr, sc = spmv_exact(rp, ci, v, x)
+        assert within_tolerance(y, yr, sc, 1e-12)[0]
+    a.close()
+    b.close()
