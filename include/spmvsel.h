@@ -184,7 +184,10 @@ spmv_status_t spmv_features(spmv_plan_t plan, double out_features[12],
                             uint64_t out_acc[12]);
 
 /* Choose a variant with `selector` (spmv_selector_t), set it on the plan and
- * build its format.  info (nullable) receives the decision record.
+ * build its format: the online step of the method (Section 3.2): the
+ * profiling selector's micro-benchmarks and bottleneck cascade (Section
+ * 3.2.1, Table 2's class-to-optimisation map), or a classifier on the
+ * structural features of Table 1 (Section 3.2.2).  info (nullable) receives the decision record.
  * Synchronous.  SPMV_SEL_MLP on a plan with no features yet, under automatic
  * index coding, takes one pass (feature kernels, delta16 span test, device
  * finalisation, network; one wait); the result is the same as that of the
@@ -192,8 +195,9 @@ spmv_status_t spmv_features(spmv_plan_t plan, double out_features[12],
 spmv_status_t spmv_select(spmv_plan_t plan, int32_t selector,
                           spmv_select_info_t *info);
 
-/* y = A x with the plan's current variant (CSR_SCALAR before any select or
- * set_variant), on `stream`, asynchronously.  y is fully overwritten.
+/* y = A x (Algorithm 1, the CSR product) with the plan's current variant
+ * (CSR_SCALAR before any select or set_variant), on `stream`,
+ * asynchronously.  y is fully overwritten.
  * d_x has M elements and d_y N elements, of type double for F64 plans and
  * float otherwise.  Calls on one plan must not overlap in time (the merge
  * path variant keeps per-tile carries in plan scratch). */

@@ -302,15 +302,28 @@ spmv_status_t check_d16(spmv_plan *P) {
     }
     P->d16_cmax.release();
     P->d16_checked = true;
+    P->d16_base_ready = true;
     return SPMV_OK;
 }
 
 bool d16_feasible(const spmv_plan *P) { return P->d16_feasible; }
 
 // The block reference columns the delta16 encoder reads: one int32 per block
-// of d16_rows rows, present after the feasibility test.
-spmv_status_t check_d16_base(const spmv_plan *P) {
+// of d16_rows rows (the smallest column of the block), computed here when the
+// feasibility test took only the spans.
+spmv_status_t ensure_d16_base(spmv_plan *P) {
     const int64_t blocks = (P->n + P->d16_rows - 1) / P->d16_rows;
+    if (!P->d16_base_ready) {
+        SPMV_TRY(P->d16_base.alloc((size_t)(blocks > 0 ? blocks : 1) * 4));
+        if (blocks > 0) {
+            SPMV_TRY(P->d16_cmax.alloc((size_t)blocks * 4));
+            SPMV_HIP(launch_panel_windows(*P, P->d16_rows, P->d16_base.as<int32_t>(),
+                                          P->d16_cmax.as<int32_t>(), blocks, S(P)));
+            SPMV_TRY(sync(P));
+            P->d16_cmax.release();
+        }
+        P->d16_base_ready = true;
+    }
     if (blocks > 0 && (!P->d16_base.p || P->d16_base.bytes < (size_t)blocks * 4))
         return fail(SPMV_ERR_HIP, "delta16: block references missing (%lld blocks of %d rows)",
                     (long long)blocks, P->d16_rows);
@@ -708,8 +721,9 @@ spmv_status_t build_format(spmv_plan *P, int v) {
             return fail(SPMV_ERR_INFEASIBLE, "SHORT_ROW codes: a block of rows spans more than 65536 columns");
         if (!(P->d16_built && P->d16_layout == 0)) {
             SPMV_TRY(P->d16_off.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 2 + 16));
-            SPMV_TRY(check_d16_base(P));
-        SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(), P->d16_off.as<uint16_t>(), S(P)));
+            SPMV_TRY(ensure_d16_base(P));
+            SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(),
+                                           P->d16_off.as<uint16_t>(), S(P)));
             SPMV_TRY(sync(P));
         }
         P->srow_coded_built = true;
@@ -751,7 +765,7 @@ spmv_status_t build_format(spmv_plan *P, int v) {
             return SPMV_OK;
         }
         SPMV_TRY(P->d16_off.alloc((size_t)(P->nnz > 0 ? P->nnz : 1) * 2 + 16));
-        SPMV_TRY(check_d16_base(P));
+        SPMV_TRY(ensure_d16_base(P));
         SPMV_HIP(launch_delta16_encode(*P, P->d16_base.as<int32_t>(), P->d16_off.as<uint16_t>(),
                                        S(P)));
         SPMV_TRY(sync(P));
@@ -1084,10 +1098,10 @@ spmv_status_t mlp_predict(const double f[12], uint32_t feas, hipStream_t s, floa
 
 // The MLP selector's one-pass path for a plan with neither features nor the
 // delta16 test yet, under automatic index coding: one kernel takes the
-// feature sums and the delta16 block windows at both block heights in one
-// pass over the rows, a second reduces them, finalises the features on the
-// device and runs the network, writing the record straight into pinned host
-// memory; one wait.  Returns SPMV_ERR_NO_MODEL (error cleared) without
+// feature sums and the delta16 block spans at both block heights in one pass
+// over the rows, a second reduces them, finalises the features on the device
+// and runs the network, writing the record straight into pinned host memory;
+// one wait, no allocation.  Returns SPMV_ERR_NO_MODEL (error cleared) without
 // launching anything when no model is loaded.
 spmv_status_t select_mlp_onepass(spmv_plan *P, uint32_t *feas, int32_t *variant, float *margin,
                                  int32_t *fallback, float *logits) {
@@ -1103,25 +1117,18 @@ spmv_status_t select_mlp_onepass(spmv_plan *P, uint32_t *feas, int32_t *variant,
         tau = g_model.tau;
     }
     const hipStream_t s = S(P);
-    // heights as check_d16 tries them: H0 = the short_row block, then H1 = kBlock;
-    // H1's bases go to d16_cmax, which becomes d16_base when H1 is taken
+    // spans at the heights check_d16 tries: H0 = the short_row block, then H1 = kBlock
     const int R = P->rs_rows, H0 = R * kBlock, H1 = kBlock;
-    const int64_t b0 = (P->n + H0 - 1) / H0, b1 = (P->n + H1 - 1) / H1;
-    SPMV_TRY(P->d16_base.alloc((size_t)b0 * 4));
-    if (R > 1) SPMV_TRY(P->d16_cmax.alloc((size_t)b1 * 4));
     hipError_t e = hipSuccess;
-    const int parts = launch_select_pass(*P, R, scr<uint64_t>(P, kOffPart), P->d16_base.as<int32_t>(),
-                                         R > 1 ? P->d16_cmax.as<int32_t>() : nullptr,
-                                         xbytes(P->dtype), s, &e);
+    const int parts = launch_select_pass(*P, R, scr<uint64_t>(P, kOffPart), xbytes(P->dtype), s, &e);
     SPMV_HIP(e);  // hipErrorInvalidValue for a row count per thread other than 1, 2, 4, 8
     char *h = static_cast<char *>(P->h_pinned) + 2048;
-    void *hd = nullptr;
-    SPMV_HIP(hipHostGetDevicePointer(&hd, h, 0));
     const uint32_t base_bits = (1u << V_CSR_SCALAR) | (1u << V_CSR_VECTOR) |
                                (1u << V_MERGE_PATH) | (1u << V_SHORT_ROW) | (1u << V_XBLOCK_LDS);
     SPMV_HIP(launch_mlp_select(dp, dn, scr<uint64_t>(P, kOffPart), parts, P->n, P->m, P->nnz,
                                vbytes(P->dtype), xbytes(P->dtype), R > 1 ? 1 : 0, base_bits, tau,
-                               static_cast<float *>(hd), s));
+                               reinterpret_cast<float *>(static_cast<char *>(P->h_pinned_dev) + 2048),
+                               s));
     SPMV_TRY(sync(P));
     float hf[33];
     double f[12];
@@ -1133,9 +1140,8 @@ spmv_status_t select_mlp_onepass(spmv_plan *P, uint32_t *feas, int32_t *variant,
     const bool ok0 = w[12] <= 65535, ok1 = R > 1 && w[13] <= 65535;
     P->d16_feasible = ok0 || ok1;
     P->d16_rows = ok0 || R == 1 ? H0 : H1;
-    if (R > 1 && P->d16_rows == H1) P->d16_base.swap(P->d16_cmax);  // H0 == H1 when R == 1
-    P->d16_cmax.release();
     P->d16_checked = true;
+    P->d16_base_ready = false;
     memcpy(P->feats, f, sizeof f);
     const int64_t smiss = (int64_t)(w[10] - w[11]);
     const uint64_t a[12] = {w[0], w[1], w[2], w[3], w[4], w[5],
@@ -1243,6 +1249,7 @@ spmv_status_t spmv_plan_create(spmv_plan_t *out, int64_t n_rows, int64_t n_cols,
         }
     }
     if (!P->h_pinned) BAIL_HIP(hipHostMalloc(&P->h_pinned, 4096, hipHostMallocDefault));
+    BAIL_HIP(hipHostGetDevicePointer(&P->h_pinned_dev, P->h_pinned, 0));
     BAIL(P->scratch.alloc(kScratchBytes));
     if (flags & SPMV_COPY_INPUTS) {
         const size_t vb = vbytes(val_dtype);
@@ -1520,6 +1527,7 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
     case 0: case 1:
         SPMV_TRY(build_format(P, V_DELTA16));
         if (P->d16_layout != 0) return fail(SPMV_ERR_ARG, "delta16 is not in the streamed layout");
+        if (which == 0) SPMV_TRY(ensure_d16_base(P));
         src = which == 0 ? P->d16_base.p : P->d16_off.p;
         want = which == 0 ? 4 * ((P->n + P->d16_rows - 1) / P->d16_rows) : 2 * P->nnz;
         break;

@@ -117,6 +117,10 @@ struct spmv_plan {
 
     // derived formats (lazy)
     bool d16_checked = false, d16_feasible = false, d16_built = false;
+    // d16_base holds the block references at d16_rows (the one-pass
+    // selection takes only the spans; the references follow at preparation)
+    bool d16_base_ready = false;
+    void *h_pinned_dev = nullptr;  // h_pinned's device address
     int d16_rows = 256;          // rows per block sharing one reference column
     spmvsel::DevBuf d16_base, d16_off, d16_cmax;
     // delta16 layout: 0 rows streamed (d16_base/d16_off), 1 sliced (64-row
@@ -296,17 +300,17 @@ hipError_t launch_csr_part(const spmv_plan &P, const int32_t *bounds, const int3
 // MLP (k_mlp.hip)
 hipError_t launch_mlp_infer(const float *d_params, const float *d_norm, const double *feats,
                             uint32_t feasible, float tau, float *d_out, hipStream_t s);
-// One-pass MLP selection: k_select_pass<R> (feature sums and the delta16
-// block windows at heights 256 R and 256, bases written to base0/base1,
-// partial records to d_partials; returns the partial count, 0 on a bad R),
+// One-pass MLP selection: k_select_pass<R> (feature sums and the largest
+// delta16 block spans at heights 256 R and 256 into the partial records at
+// d_partials; returns the partial count, 0 on a bad R),
 // then k_mlp_select (reduction, device finalisation of the features,
 // feasibility, network and decision in one workgroup).  out:
 // kSelectRecordBytes (the inference record in floats 0..31, feasibility bits
 // at float 32, features as doubles 24..35, the reduced record as words
 // 36..51, with the spans in words 48 and 49).
 constexpr size_t kSelectRecordBytes = 416;
-int launch_select_pass(const spmv_plan &P, int R, uint64_t *d_partials, int32_t *base0,
-                       int32_t *base1, int xb, hipStream_t s, hipError_t *err);
+int launch_select_pass(const spmv_plan &P, int R, uint64_t *d_partials, int xb, hipStream_t s,
+                       hipError_t *err);
 hipError_t launch_mlp_select(const float *d_params, const float *d_norm, const uint64_t *d_partials,
                              int nparts, int64_t n, int64_t m, int64_t nnz, int vb, int xb,
                              int two_heights, uint32_t feas_base, float tau, float *out,

@@ -64,22 +64,20 @@ hipError_t launch_features(const spmv_plan &P, uint64_t *d_partials, uint64_t *d
 }
 
 // ---------------------------------------------------------------- one-pass selection
-// The feature sums of k_features and the delta16 block windows in one pass
+// The feature sums of k_features and the delta16 block spans in one pass
 // over the rows.  Blocks of H0 = R * 256 rows are walked by workgroups in
 // turn; thread t takes rows t, t + 256, ..., t + (R - 1) 256 of a block, so
 // its k-th row lies in 256-row sub-block k.  Each sub-block's window [min
-// first column, max last column] gives base1 (H1 = 256) and the block's
-// union gives base0 (H0), both as k_panel_windows writes them; the largest
-// spans go to words 12 (H0) and 13 (H1) of the partial records.  The rows'
-// feature sums and the nonzero gap count are the same integers as
-// k_features's, in another grouping.
+// first column, max last column] gives its span at H1 = 256, their union the
+// block's span at H0 (the windows k_panel_windows computes); the largest go
+// to words 12 (H0) and 13 (H1) of the partial records.  The rows' feature
+// sums and the nonzero gap count are the same integers as k_features's, in
+// another grouping.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_select_pass(int64_t n, int64_t nnz, int xb,
                                                         const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ ci,
-                                                        uint64_t *__restrict__ partials,
-                                                        int32_t *__restrict__ base0,
-                                                        int32_t *__restrict__ base1) {
+                                                        uint64_t *__restrict__ partials) {
     __shared__ int32_t wlo[R][kBlock / 64], whi[R][kBlock / 64];
     Acc a;
     a.init();
@@ -122,16 +120,11 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int64_t n, int64_t nnz, 
                     l1 = wlo[k][w] < l1 ? wlo[k][w] : l1;
                     h1 = whi[k][w] > h1 ? whi[k][w] : h1;
                 }
-                const int64_t q = p * R + k;
-                if (R > 1 && q * kBlock < n) {
-                    base1[q] = h1 < 0 ? 0 : l1;
-                    const uint64_t d = h1 < 0 ? 0 : (uint64_t)(h1 - l1);
-                    a.span1 = d > a.span1 ? d : a.span1;
-                }
+                const uint64_t d = h1 < 0 ? 0 : (uint64_t)(h1 - l1);
+                a.span1 = d > a.span1 ? d : a.span1;
                 l0 = l1 < l0 ? l1 : l0;
                 h0 = h1 > h0 ? h1 : h0;
             }
-            base0[p] = h0 < 0 ? 0 : l0;
             const uint64_t d = h0 < 0 ? 0 : (uint64_t)(h0 - l0);
             a.span0 = d > a.span0 ? d : a.span0;
         }
@@ -143,18 +136,18 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int64_t n, int64_t nnz, 
     block_reduce(a, partials + 16 * blockIdx.x);
 }
 
-int launch_select_pass(const spmv_plan &P, int R, uint64_t *d_partials, int32_t *base0,
-                       int32_t *base1, int xb, hipStream_t s, hipError_t *err) {
+int launch_select_pass(const spmv_plan &P, int R, uint64_t *d_partials, int xb, hipStream_t s,
+                       hipError_t *err) {
     const int64_t blocks0 = (P.n + (int64_t)R * kBlock - 1) / ((int64_t)R * kBlock);
     const int64_t by_nnz = (P.nnz + kBlock - 1) / kBlock;
     int64_t g = blocks0 > by_nnz ? blocks0 : by_nnz;
     g = g < 1 ? 1 : g > kFeatBlocks ? kFeatBlocks : g;
     const dim3 grid((unsigned)g), blk(kBlock);
     switch (R) {
-    case 1: hipLaunchKernelGGL(k_select_pass<1>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials, base0, base1); break;
-    case 2: hipLaunchKernelGGL(k_select_pass<2>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials, base0, base1); break;
-    case 4: hipLaunchKernelGGL(k_select_pass<4>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials, base0, base1); break;
-    case 8: hipLaunchKernelGGL(k_select_pass<8>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials, base0, base1); break;
+    case 1: hipLaunchKernelGGL(k_select_pass<1>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials); break;
+    case 2: hipLaunchKernelGGL(k_select_pass<2>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials); break;
+    case 4: hipLaunchKernelGGL(k_select_pass<4>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials); break;
+    case 8: hipLaunchKernelGGL(k_select_pass<8>, grid, blk, 0, s, P.n, P.nnz, xb, P.rowptr, P.colind, d_partials); break;
     default: *err = hipErrorInvalidValue; return 0;
     }
     *err = hipGetLastError();

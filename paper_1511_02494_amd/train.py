@@ -97,7 +97,7 @@ def time_variants(plan, mask, reps=10):
     return t
 
 
-def label_one(seed, torch, dev, reps=10):
+def label_one(seed, torch, dev, reps=10, with_model=False):
     spec = synth.sweep_spec(seed)
     M = generate_on_device(spec, torch, dev)
     plan = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
@@ -114,6 +114,12 @@ def label_one(seed, torch, dev, reps=10):
                features=feats, mask=mask, times=times, label=label, meas=meas,
                bytes=[plan.bytes(v) for v in range(6)], t_features=t_feat, t_profile=t_prof)
     plan.close()
+    if with_model:
+        # the MLP selector's own cost on a fresh plan: features, delta16 test
+        # and network in one pass (the same for any weights)
+        fresh = S.Plan(M["rp"], M["ci"], M["val"], M["m"], nnz=M["nnz"])
+        rec["t_select"] = fresh.select(S.SEL_MLP)["t_features_s"]
+        fresh.close()
     return rec
 
 
@@ -126,6 +132,9 @@ def cmd_label(args):
         with open(args.out) as f:
             for line in f:
                 done.add(json.loads(line)["seed"])
+    with_model = os.path.exists(S.DEFAULT_MODEL)
+    if with_model:
+        S.spmv_model_load(S.DEFAULT_MODEL)
     t_start = time.time()
     with open(args.out, "a") as f:
         for seed in range(lo, hi):
@@ -134,7 +143,7 @@ def cmd_label(args):
             if args.budget_s and time.time() - t_start > args.budget_s:
                 print(f"budget reached at seed {seed}", flush=True)
                 break
-            rec = label_one(seed, torch, dev, args.reps)
+            rec = label_one(seed, torch, dev, args.reps, with_model)
             f.write(json.dumps(rec) + "\n")
             f.flush()
             print(f"seed {seed} {rec['name']:>40s} nnz={rec['nnz']:>10d} "
@@ -388,6 +397,14 @@ def cmd_calibrate(args):
 # --------------------------------------------------------------- evaluation
 
 
+def mlp_cost(r, t_infer_s, fell_back):
+    """The MLP selector's cost on record r: its measured one-pass selection
+    where the record has one, else the feature pass plus one inference; plus
+    the micro-benchmarks when it defers to the cascade."""
+    base = r["t_select"] if "t_select" in r else r["t_features"] + t_infer_s
+    return base + (r["t_profile"] if fell_back else 0.0)
+
+
 def evaluate(recs, model, theta, t_infer_s):
     """Accuracy, regret and gain of the selectors over the records."""
     S.spmv_model_load(model)
@@ -402,7 +419,7 @@ def evaluate(recs, model, theta, t_infer_s):
         rows.append(dict(seed=r["seed"], label=r["label"], mlp=p["variant"], fallback=fb,
                          pick=pick, prof=q, best=best, t_pick=t[pick], t_mlp=t[p["variant"]],
                          t_prof=t[q], t_vec=t[S.V_CSR_VECTOR], t_scalar=t[S.V_CSR_SCALAR],
-                         ov_mlp=r["t_features"] + t_infer_s + (r["t_profile"] if fb else 0.0),
+                         ov_mlp=mlp_cost(r, t_infer_s, fb),
                          ov_prof=r["t_features"] + r["t_profile"]))
     S.spmv_model_unload()
 
@@ -465,8 +482,7 @@ def cmd_sweep(args):
             p = S.spmv_mlp_predict(r["features"], r["mask"])
             v = q if p["fallback"] else p["variant"]
             row.update(mlp=S.VARIANTS[v], mlp_regret=t[v] / t[best_v] - 1, fell_back=bool(p["fallback"]),
-                       mlp_overhead_spmv=(r["t_features"] + t_inf
-                                          + (r["t_profile"] if p["fallback"] else 0)) / t[v])
+                       mlp_overhead_spmv=mlp_cost(r, t_inf, bool(p["fallback"])) / t[v])
         f = r["features"]
         ws = 4 * (r["n"] + 1) + 12 * r["nnz"] + 16 * r["n"]
         row["bandwidth_bound"] = bool(ws > 2 * 256 * 2 ** 20 and f[10] < 0.05 and f[2] >= 8)

@@ -56,7 +56,8 @@ def test_mlp_gain_over_profiling_cascade():
         S.spmv_model_unload()
     hit_p, reg_p = score(recs, lambda r: profiling(r, theta))
     hit_v, _ = score(recs, lambda r: S.V_CSR_VECTOR)
-    over = [(r["t_features"] + t_inf) / min(x for x in r["times"] if x > 0) for r in recs]
+    over = [(r["t_select"] if "t_select" in r else r["t_features"] + t_inf)
+            / min(x for x in r["times"] if x > 0) for r in recs]
     print(f"\nheld-out: MLP {hit_m:.3f} within 5% (regret {reg_m:.3f}); profiling {hit_p:.3f} "
           f"({reg_p:.3f}); always csr_vector {hit_v:.3f}; median selection cost "
           f"{np.median(over):.1f} SpMVs of the fastest variant", flush=True)
