@@ -76,7 +76,9 @@ typedef enum { SPMV_F64 = 0, SPMV_F32 = 1, SPMV_BF16 = 2 } spmv_dtype_t;
  *              16-bit offsets from the slice's reference column or 8-bit
  *              deltas from the row's previous column, code 255 escaping to
  *              the full column: one width per matrix, never both
- *              (Section 3.3; spmv_set_delta16_offset_bits).
+ *              (Section 3.3; spmv_set_delta16_offset_bits).  An offset
+ *              slice whose columns span fewer than 512 reads x from a copy
+ *              of that window in LDS.
  *  XBLOCK_LDS  x blocking (class CML; replaces software prefetching of x):
  *              the columns are cut into S <= 8 slices (spmv_set_xblock_slices),
  *              each stored as its own CSR and run on the XCDs that take that
@@ -293,15 +295,16 @@ spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
  * ib NNZ + vb NNZ + xb M + yb N, plus for DELTA16 (ib = 2 there, else 4)
  * 4 bytes per block reference column in the streamed layout; in the sliced
  * one, 16 bytes per 64-row slice (width, unit offset, reference column,
- * kind) and 128 per diagonal slice (its diagonals), with 1 or 2 index bytes
- * (the code width) only for the nonzeros of offset slices, plus with 8-bit
- * codes 4 bytes per escaped column and 4 per offset slice (its eunits
- * entry) (a
- * row's mask in a diagonal slice takes
- * the place of its row pointer).  The layout is decided here if needed; the
- * streamed form is counted where DELTA16 is infeasible.  Traffic a variant adds on top (the XBLOCK_LDS slice row
- * pointers and partial y vectors, the sliced layout's padding slots) is
- * overhead and is not counted. */
+ * kind), 4 per offset slice (its column span) and 128 per diagonal slice
+ * (its diagonals), with 1 or 2 index bytes (the code width) only for the
+ * nonzeros of offset slices, plus with 8-bit codes 4 bytes per escaped
+ * column and 4 per offset slice (its eunits entry) (a row's mask in a
+ * diagonal slice takes the place of its row pointer).  The layout is
+ * decided here if needed; the streamed form is counted where DELTA16 is
+ * infeasible.  Traffic a variant adds on top (the XBLOCK_LDS slice row
+ * pointers and partial y vectors, the sliced layout's padding slots, the
+ * x windows a sliced offset slice stages in LDS) is overhead and is not
+ * counted. */
 spmv_status_t spmv_bytes(spmv_plan_t plan, int32_t variant, int64_t *bytes);
 
 /* Median and minimum time of `reps` executions of `variant` (hipEvents on

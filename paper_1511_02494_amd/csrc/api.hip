@@ -356,7 +356,8 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     SPMV_TRY(P->d16s_kind.alloc(nb));
     SPMV_TRY(P->d16s_diag.alloc(nb * kSellMaxDiag));
     SPMV_TRY(P->d16s_nnz.alloc(nb));
-    DevBuf halfw, tmp, span;
+    DevBuf halfw, tmp;
+    DevBuf &span = P->d16s_span;
     SPMV_TRY(halfw.alloc(nb));
     SPMV_TRY(span.alloc(nb));
     int64_t units = 0, nnz_off = 0, ndiag = 0, max_span = 0;
@@ -452,6 +453,7 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
         P->d16s_base.release();
         P->d16s_kind.release();
         P->d16s_diag.release();
+        P->d16s_span.release();
     }
     return SPMV_OK;
 }
@@ -1385,14 +1387,16 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
         if (d16_feasible(P)) SPMV_TRY(d16_decide_layout(P));
         if (d16_feasible(P) && P->d16_layout == 1) {
             // offsets only in offset slices; width, units, base and kind per
-            // slice, 32 diagonals per diagonal slice; a row's mask replaces
-            // its row pointer in diagonal slices
+            // slice, the column span per offset slice, 32 diagonals per
+            // diagonal slice; a row's mask replaces its row pointer in
+            // diagonal slices
             // 8-bit codes: 4 bytes per escaped column and 4 per offset slice
             // (its first escape unit, read only there)
             const bool d8 = P->d16_offw == 8;
+            const int64_t n_off = P->d16_nsl - P->d16_ndiag;
             *bytes = 4 * (P->n + 1) + vb * P->nnz + (d8 ? 1 : 2) * P->d16_nnz_off +
-                     (d8 ? 4 * P->d16_nesc + 4 * (P->d16_nsl - P->d16_ndiag) : 0) + xb * P->m + xb * P->n +
-                     16 * P->d16_nsl + 4 * kSellMaxDiag * P->d16_ndiag;
+                     (d8 ? 4 * P->d16_nesc + 4 * n_off : 0) + xb * P->m + xb * P->n +
+                     16 * P->d16_nsl + 4 * n_off + 4 * kSellMaxDiag * P->d16_ndiag;
             return SPMV_OK;
         }
         extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
@@ -1857,6 +1861,7 @@ spmv_status_t spmv_set_delta16_layout(spmv_plan_t P, int32_t layout) {
     P->d16s_val.release();
     P->d16s_kind.release();
     P->d16s_diag.release();
+    P->d16s_span.release();
     P->d16s_mask.release();
     P->d16s_esc.release();
     P->d16s_eunits.release();

@@ -142,6 +142,7 @@ struct spmv_plan {
     // per slice: 0 for an offset slice, 1 + D for a diagonal slice of D
     // diagonals (listed in d16s_diag[32 s .. 32 s + D)); one mask per row
     spmvsel::DevBuf d16s_kind, d16s_diag, d16s_mask, d16s_nnz;
+    spmvsel::DevBuf d16s_span;  // per slice: largest offset from its reference column
     bool mp_built = false;
     int64_t mp_tiles = 0;
     spmvsel::DevBuf mp_split_row, mp_split_nnz, mp_carry_row, mp_carry_val;

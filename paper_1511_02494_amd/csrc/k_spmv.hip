@@ -191,6 +191,18 @@ __global__ __launch_bounds__(kBlock) void k_rowstream(
                                       kmin);
 }
 
+// Lane l receives lane l + 1's value (DPP wave shift; the last lane keeps
+// its own, to be replaced by the caller).
+__device__ __forceinline__ float wave_shl1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130,
+                                                      0xF, 0xF, false));
+}
+__device__ __forceinline__ double wave_shl1(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false));
+}
+
 // ============================================================ delta16, sliced
 // The sliced layout (slices of 64 rows, one row per lane, nonzeros stored
 // column-major in pairs; see k_sliced_scatter).  The column codes of offset
@@ -213,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     const int32_t *__restrict__ width, const int32_t *__restrict__ units,
     const int32_t *__restrict__ base, const int32_t *__restrict__ kind,
     const int32_t *__restrict__ diag, const uint32_t *__restrict__ mask,
-    const O *__restrict__ off, const int32_t *__restrict__ eunits,
+    const int32_t *__restrict__ span, const O *__restrict__ off, const int32_t *__restrict__ eunits,
     const int32_t *__restrict__ esc, const V *__restrict__ val,
     const typename VT<V>::A *__restrict__ x, typename VT<V>::A *__restrict__ y, int kmin) {
     using A = typename VT<V>::A;
@@ -233,20 +245,44 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
         // Rows here hold at most 32 nonzeros, so FP32 needs no Kahan sum.
         const int32_t *dg = diag + sl * kSellMaxDiag;
         const uint32_t mk = r < n ? mask[r] : 0u;
+        const int64_t r0 = sl * kSellRows;
         A acc = A(0);
+        // consecutive diagonals d, d + 1 (stencils): lane l's x[r + d + 1] is
+        // lane l + 1's x[r + d], shifted down the wavefront (DPP), and only
+        // the last lane loads (a uniform address, through the scalar cache):
+        // a third of the x loads of a 27-point stencil go through the
+        // vector memory path.  Slices narrower than 8 positions load every
+        // x (there the shift's dependence on the previous load costs more
+        // than the load it saves: 17% on short rows)
+        const bool reuse = w >= 8;
+        A xp = A(0);
+        int32_t dp = INT32_MIN;
         for (int k0 = 0; k0 < w; k0 += 4) {
             const int k1 = (k0 + 2) < w ? k0 + 2 : w - 2;
             const VP v0 = __builtin_nontemporal_load(
                 reinterpret_cast<const VP *>(val + o + (int64_t)(k0 / 2) * (2 * kSellRows)));
             const VP v1 = __builtin_nontemporal_load(
                 reinterpret_cast<const VP *>(val + o + (int64_t)(k1 / 2) * (2 * kSellRows)));
-            const int32_t d[4] = {dg[k0], dg[k0 + 1], dg[k1], dg[k1 + 1]};
             A xv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {  // a position the row lacks may point outside x
-                int64_t c = r + d[i];
-                c = c < 0 ? 0 : (c >= m ? m - 1 : c);
-                xv[i] = x[c];
+            for (int i = 0; i < 4; ++i) {
+                const int kk = i < 2 ? k0 + i : k1 + (i - 2);
+                const int32_t dk = dg[kk];
+                A xk;
+                if (reuse && dp != INT32_MIN && dk == dp + 1) {
+                    int64_t c = r0 + (kSellRows - 1) + dk;
+                    c = c < 0 ? 0 : (c >= m ? m - 1 : c);
+                    const A e = x[c];
+                    const A sh = wave_shl1(xp);
+                    xk = lane == kSellRows - 1 ? e : sh;
+                } else {  // a position the row lacks may point outside x
+                    int64_t c = r + dk;
+                    c = c < 0 ? 0 : (c >= m ? m - 1 : c);
+                    xk = x[c];
+                }
+                xv[i] = xk;
+                xp = xk;
+                dp = dk;
             }
             const A p[4] = {VT<V>::cvt(v0.x) * xv[0], VT<V>::cvt(v0.y) * xv[1],
                             VT<V>::cvt(v1.x) * xv[2], VT<V>::cvt(v1.y) * xv[3]};
@@ -271,75 +307,103 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
         ep = esc + (int64_t)kSellRows * eunits[sl] + lane;
         oq = 2 * kSellRows * ((int64_t)units[sl] + sl) + 4 * lane;
     }
-    for (int k0 = 0; k0 < w; k0 += 4) {
-        const int k1 = (k0 + 2) < w ? k0 + 2 : w - 2;  // past the width: reload the last pair
-        const int64_t q0 = o + (int64_t)(k0 / 2) * (2 * kSellRows);
-        const int64_t q1 = o + (int64_t)(k1 / 2) * (2 * kSellRows);
-        VP v0, v1;
-        A x0, x1, x2, x3;
-        if constexpr (sizeof(O) == 1) {
-            // this lane's four codes of the step in one 4-byte load
-            // (positions past the width hold code 0, as padding positions
-            // do, and keep the column).  Two 2-byte loads per step, codes
-            // stored in pairs like the values, ran a 2M-row band in 305 us
-            // cold against 256 us for this (FP64; 16-bit offsets: 277 us)
-            const uint32_t cq = __builtin_nontemporal_load(
-                reinterpret_cast<const uint32_t *>(off + oq + (int64_t)k0 * kSellRows));
-            v0 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q0));
-            v1 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q1));
-            const int32_t d[4] = {(int32_t)(cq & 0xff), (int32_t)((cq >> 8) & 0xff),
-                                  (int32_t)((cq >> 16) & 0xff), (int32_t)(cq >> 24)};
-            const bool esc4 = d[0] == 255 || d[1] == 255 || d[2] == 255 || d[3] == 255;
-            int32_t col[4];
-            if (__any(esc4)) {  // wavefront-uniform: most steps load no escape
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (d[i] == 255) {
-                        cprev = *ep;
-                        ep += kSellRows;
-                    } else {
-                        cprev += d[i];
+    // x staging: a slice whose columns lie within kXs of its reference
+    // column (and whose gathers number at least twice the window) reads x
+    // from a copy of the window in LDS, loaded coalesced.  Band matrices
+    // keep the vector memory path's address unit 90% busy with their x
+    // gathers otherwise; from LDS they run 8-20% faster (half widths 16 to
+    // 200).  16 KiB per workgroup leaves the occupancy at 8 waves per SIMD.
+    constexpr int kXs = 512;
+    __shared__ A xs[kBlock / kSellRows][kXs];
+    const int wv = threadIdx.x / kSellRows;
+    const int sp = span[sl];
+    const bool staged = sp < kXs && 2 * (sp + 1) <= kSellRows * w;
+    auto run = [&](auto st) {
+        constexpr bool ST = decltype(st)::value;
+        A *xw = &xs[wv][0];
+        if constexpr (ST) {
+            for (int i = lane; i <= sp; i += kSellRows) xw[i] = x[b + i];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // x of column c: from the window in LDS, or from memory
+#define GX(c) (ST ? xw[(c) - b] : x[(c)])
+        for (int k0 = 0; k0 < w; k0 += 4) {
+            const int k1 = (k0 + 2) < w ? k0 + 2 : w - 2;  // past the width: reload the last pair
+            const int64_t q0 = o + (int64_t)(k0 / 2) * (2 * kSellRows);
+            const int64_t q1 = o + (int64_t)(k1 / 2) * (2 * kSellRows);
+            VP v0, v1;
+            A x0, x1, x2, x3;
+            if constexpr (sizeof(O) == 1) {
+                // this lane's four codes of the step in one 4-byte load
+                // (positions past the width hold code 0, as padding positions
+                // do, and keep the column).  Two 2-byte loads per step, codes
+                // stored in pairs like the values, ran a 2M-row band in 305 us
+                // cold against 256 us for this (FP64; 16-bit offsets: 277 us)
+                const uint32_t cq = __builtin_nontemporal_load(
+                    reinterpret_cast<const uint32_t *>(off + oq + (int64_t)k0 * kSellRows));
+                v0 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q0));
+                v1 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q1));
+                const int32_t d[4] = {(int32_t)(cq & 0xff), (int32_t)((cq >> 8) & 0xff),
+                                      (int32_t)((cq >> 16) & 0xff), (int32_t)(cq >> 24)};
+                const bool esc4 = d[0] == 255 || d[1] == 255 || d[2] == 255 || d[3] == 255;
+                int32_t col[4];
+                if (__any(esc4)) {  // wavefront-uniform: most steps load no escape
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (d[i] == 255) {
+                            cprev = *ep;
+                            ep += kSellRows;
+                        } else {
+                            cprev += d[i];
+                        }
+                        col[i] = cprev;
                     }
-                    col[i] = cprev;
+                    // settle the escape loads on this rare path: left pending,
+                    // the paths join with a wait for every load in flight, and
+                    // the common path's gathers would also wait for this step's
+                    // value loads
+                    __builtin_amdgcn_s_waitcnt(0);
+                } else {
+                    col[0] = cprev + d[0];
+                    col[1] = col[0] + d[1];
+                    col[2] = col[1] + d[2];
+                    col[3] = col[2] + d[3];
+                    cprev = col[3];
                 }
-                // settle the escape loads on this rare path: left pending,
-                // the paths join with a wait for every load in flight, and
-                // the common path's gathers would also wait for this step's
-                // value loads
-                __builtin_amdgcn_s_waitcnt(0);
+                x0 = GX(col[0]);
+                x1 = GX(col[1]);
+                x2 = GX(col[2]);
+                x3 = GX(col[3]);
             } else {
-                col[0] = cprev + d[0];
-                col[1] = col[0] + d[1];
-                col[2] = col[1] + d[2];
-                col[3] = col[2] + d[3];
-                cprev = col[3];
+                v0 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q0));
+                const OP c0 = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + q0));
+                v1 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q1));
+                const OP c1 = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + q1));
+                x0 = GX(b + (int32_t)c0.x);
+                x1 = GX(b + (int32_t)c0.y);
+                x2 = GX(b + (int32_t)c1.x);
+                x3 = GX(b + (int32_t)c1.y);
             }
-            x0 = x[col[0]];
-            x1 = x[col[1]];
-            x2 = x[col[2]];
-            x3 = x[col[3]];
-        } else {
-            v0 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q0));
-            const OP c0 = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + q0));
-            v1 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q1));
-            const OP c1 = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + q1));
-            x0 = x[b + (int32_t)c0.x];
-            x1 = x[b + (int32_t)c0.y];
-            x2 = x[b + (int32_t)c1.x];
-            x3 = x[b + (int32_t)c1.y];
-        }
-        const A p[4] = {VT<V>::cvt(v0.x) * x0, VT<V>::cvt(v0.y) * x1, VT<V>::cvt(v1.x) * x2,
-                        VT<V>::cvt(v1.y) * x3};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (comp) {
-                if (k0 + i < len) acc.add_comp(p[i]);
-            } else {
-                // a +0 addend leaves a sum that started at +0 unchanged
-                acc.add(k0 + i < len ? p[i] : A(0));
+            const A p[4] = {VT<V>::cvt(v0.x) * x0, VT<V>::cvt(v0.y) * x1, VT<V>::cvt(v1.x) * x2,
+                            VT<V>::cvt(v1.y) * x3};
+    #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (comp) {
+                    if (k0 + i < len) acc.add_comp(p[i]);
+                } else {
+                    // a +0 addend leaves a sum that started at +0 unchanged
+                    acc.add(k0 + i < len ? p[i] : A(0));
+                }
             }
         }
-    }
+#undef GX
+    };
+    if (staged)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
     if (r < n) __builtin_nontemporal_store(acc.s, y + r);
 }
 
@@ -896,7 +960,7 @@ hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStre
                                P.d16_nsl, P.rowptr, P.d16s_width.as<int32_t>(),
                                P.d16s_units.as<int32_t>(), P.d16s_base.as<int32_t>(),
                                P.d16s_kind.as<int32_t>(), P.d16s_diag.as<int32_t>(),
-                               P.d16s_mask.as<uint32_t>(), P.d16s_off.as<uint8_t>(),
+                               P.d16s_mask.as<uint32_t>(), P.d16s_span.as<int32_t>(), P.d16s_off.as<uint8_t>(),
                                P.d16s_eunits.as<int32_t>(), P.d16s_esc.as<int32_t>(),
                                P.d16s_val.as<V>(), (const A *)x, (A *)y, P.kahan_min);
         else
@@ -904,7 +968,7 @@ hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStre
                                P.d16_nsl, P.rowptr, P.d16s_width.as<int32_t>(),
                                P.d16s_units.as<int32_t>(), P.d16s_base.as<int32_t>(),
                                P.d16s_kind.as<int32_t>(), P.d16s_diag.as<int32_t>(),
-                               P.d16s_mask.as<uint32_t>(), P.d16s_off.as<uint16_t>(),
+                               P.d16s_mask.as<uint32_t>(), P.d16s_span.as<int32_t>(), P.d16s_off.as<uint16_t>(),
                                nullptr, nullptr, P.d16s_val.as<V>(), (const A *)x, (A *)y,
                                P.kahan_min);
         return hipGetLastError();

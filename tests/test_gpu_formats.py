@@ -77,12 +77,12 @@ def test_formats_match_oracle(name, build, m):
 
 def sliced_bytes(L, C, bits, n, m, nnz):
     """Compulsory bytes: no codes in diagonal slices, their diagonals once;
-    8-bit codes add their escaped columns and a first escape unit per offset
-    slice."""
+    a column span per offset slice; 8-bit codes add their escaped columns
+    and a first escape unit per offset slice."""
     ns = len(L["width"])
     n_off = ns - int(np.count_nonzero(L["kind"]))
     codes = L["nnz_offset"] * (1 if bits == 8 else 2) + (4 * C["escapes"] + 4 * n_off if bits == 8 else 0)
-    return (4 * (n + 1) + 8 * nnz + codes + 8 * m + 8 * n + 16 * ns
+    return (4 * (n + 1) + 8 * nnz + codes + 8 * m + 8 * n + 16 * ns + 4 * n_off
             + 128 * int(np.count_nonzero(L["kind"])))
 
 

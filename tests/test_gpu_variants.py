@@ -284,3 +284,54 @@ def test_xblock_slice_count_change_rebuilds():
         S.spmv_set_xblock_slices(plan.handle, 3)
     assert e.value.status == S.SPMV_ERR_ARG
     plan.close()
+
+
+NONFINITE = {
+    "stencil27_12": CASES["stencil27_12"],        # diagonal slices, x shared across lanes
+    "narrowband_3000": CASES["narrowband_3000"],  # offset slices, x window in LDS
+    "shortrows_5000": CASES["shortrows_5000"],
+}
+
+
+@pytest.mark.parametrize("case", list(NONFINITE))
+def test_nonfinite_x_reaches_only_the_rows_that_use_it(case):
+    """x holds +inf, -inf and NaN at a few columns.  In every variant (both
+    delta16 layouts) a row with no nonzero in those columns stays finite and
+    within tolerance; the others are NaN or an infinity of the sign the
+    column-order sum gives, whatever the order (kernels that read neighbour
+    lanes' x, or a window of x around the row's columns, must drop what the
+    row does not hold)."""
+    build, m = NONFINITE[case]
+    rp, ci, v = build("random")
+    x = synth.vector(m, 11)
+    rng = np.random.default_rng(12)
+    bad = rng.choice(m, size=6, replace=False)
+    x[bad[:2]] = np.inf
+    x[bad[2:4]] = -np.inf
+    x[bad[4:]] = np.nan
+    with np.errstate(invalid="ignore"):
+        want = spmv_seq(rp, ci, v, x)
+    finite_x = x.copy()
+    finite_x[bad] = 0.0
+    touched = np.zeros(len(rp) - 1, bool)
+    for i in range(len(rp) - 1):
+        touched[i] = np.isin(ci[rp[i]:rp[i + 1]], bad).any()
+    yr, s = spmv_exact(rp, ci, v, finite_x)
+    plan = make_plan(rp, ci, v, m)
+    mask = expected_mask(plan)
+    runs = [(var, None) for var in range(6) if (mask >> var) & 1]
+    if (mask >> S.V_DELTA16) & 1:
+        runs += [(S.V_DELTA16, 0), (S.V_DELTA16, 1)]
+    for var, layout in runs:
+        if layout is not None:
+            S.spmv_set_delta16_layout(plan.handle, layout)
+        y = run(plan, var, x)
+        name = (S.VARIANTS[var], layout)
+        assert np.array_equal(np.isnan(y), np.isnan(want)), name
+        assert np.array_equal(np.isinf(y), np.isinf(want)), name
+        inf = np.isinf(want)
+        assert np.array_equal(np.sign(y[inf]), np.sign(want[inf])), name
+        assert np.all(np.isfinite(y[~touched])), name
+        ok, _ = within_tolerance(y[~touched], yr[~touched], s[~touched], 1e-12)
+        assert ok, name
+    plan.close()
