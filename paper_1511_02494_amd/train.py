@@ -301,21 +301,23 @@ def cmd_fit(args):
     vrecs = [r for r, v in zip(recs, val) if v]
     score = lambda p: val_score(p, mu, rho, vrecs)  # noqa: E731
     runs = []
-    for k in range(args.restarts):  # independent starts, kept by validation loss
+    for k in range(args.restarts):  # independent starts, kept by validation regret
         res = train_device(Z[tr], labels[tr], masks[tr], Z[val], labels[val], masks[val],
                            args.epochs, args.lr, args.batch, args.seed + k, log, score)
         log(f"start {k} (seed {args.seed + k}): epoch {res[2]}, validation loss {res[0]:.4f}, "
             f"regret {res[3][0]:.4f}, hit {res[3][1]:.3f}")
         runs.append((res[3][0], res[0], k, res))
-    runs.sort(key=lambda t: (t[1], t[0], t[2]))
+    runs.sort(key=lambda t: (t[0], t[1], t[2]))  # the regret the selector is judged by, then loss
     best_loss, params, ep, (vreg, vhit) = runs[0][3]
     start = runs[0][2]
     log(f"kept start {start}: validation regret {vreg:.4f}, hit {vhit:.3f}, loss {best_loss:.4f} "
         f"at epoch {ep}")
     # margin threshold: the tau whose combined selector (MLP when its margin
     # reaches tau and its inputs are in range, the profiling cascade
-    # otherwise) has the lowest mean regret on the validation split; ties
-    # go to the smaller tau (fewer fallbacks, less selection overhead)
+    # otherwise) has the lowest mean regret on the validation split, for a
+    # job of --amortise SpMVs per selection: a fallback also pays the
+    # cascade's micro-benchmarks (t_profile / (K t_best)); ties go to the
+    # smaller tau (fewer fallbacks, less selection overhead)
     tmp = args.out + ".tmp"
     write_model(tmp, params, mu, rho, 0.0)
     S.spmv_model_load(tmp)
@@ -329,7 +331,10 @@ def cmd_fit(args):
             use_mlp = p["margin"] >= tau and not np.any(np.abs(p["z"]) > 8)
             v = p["variant"] if use_mlp else q
             fb += not use_mlp
-            reg += r["times"][v] / min(t for t in r["times"] if t > 0) - 1.0
+            t_best = min(t for t in r["times"] if t > 0)
+            reg += r["times"][v] / t_best - 1.0
+            if not use_mlp:
+                reg += r["t_profile"] / (args.amortise * t_best)
         score = reg / max(1, len(vrecs))
         if score < best_score - 1e-12:
             best_tau, best_score, best_fb = tau, score, fb / max(1, len(vrecs))
@@ -341,6 +346,7 @@ def cmd_fit(args):
     info = dict(train=os.path.basename(args.train), records=len(recs), val_records=int(val.sum()),
                 best_val_loss=best_loss, best_epoch=ep, val_regret=vreg, val_hit5=vhit,
                 restarts=args.restarts, kept_start=start, tau=best_tau, tau_val_mean_regret=best_score,
+                amortise=args.amortise,
                 tau_val_fallback_rate=best_fb, theta=theta,
                 epochs=args.epochs, lr=args.lr, batch=args.batch, seed=args.seed)
     with open(args.out + ".json", "w") as f:
@@ -654,7 +660,9 @@ def main(argv=None):
     a.add_argument("--lr", type=float, default=1e-3)
     a.add_argument("--batch", type=int, default=128)
     a.add_argument("--seed", type=int, default=7)
-    a.add_argument("--restarts", type=int, default=4)
+    a.add_argument("--restarts", type=int, default=8)
+    a.add_argument("--amortise", type=float, default=100.0,
+                   help="SpMVs per selection when weighing the fallback's profiling cost")
     a.add_argument("--theta", default=None)
     a = sub.add_parser("calibrate")
     a.add_argument("--labels", required=True)
