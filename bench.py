@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_bench_config1_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "selected_spmv_fp64_class_matrices_traffic.json")
 
 
 def stored_traffic(kernel_names):

@@ -178,38 +178,99 @@ def _find(d, prefix):
     raise SystemExit(f"calibration kernel {prefix} not in the counter run")
 
 
+# Derived shares of the busy time, from counters rocprofv3 sums over the
+# device: GRBM_GUI_ACTIVE over the 8 XCDs, the TA/TCP counters over the 256
+# CUs.  (name, numerator, denominator kind)
+XCDS, CUS = 8, 256
+DERIVED = [
+    ("address unit busy", "TA_TA_BUSY_sum", "cu"),
+    ("address unit stalled by L1", "TA_ADDR_STALLED_BY_TC_CYCLES_sum", "cu"),
+    ("L1 waiting on L2", "TCP_PENDING_STALL_CYCLES_sum", "cu"),
+    ("L1 tag conflicts", "TCP_READ_TAGCONFLICT_STALL_CYCLES_sum", "cu"),
+]
+
+
+def derived_columns(m):
+    """Derived metrics of one kernel's counter means m (missing -> None)."""
+    out = {}
+    cyc = m.get("GRBM_GUI_ACTIVE")
+    if cyc:
+        cyc /= XCDS
+        out["busy us (2.4 GHz)"] = cyc / 2.4e3
+        for name, num, _ in DERIVED:
+            if num in m:
+                out[name] = m[num] / (CUS * cyc)
+    if "TCC_HIT_sum" in m and "TCC_MISS_sum" in m and m["TCC_HIT_sum"] + m["TCC_MISS_sum"] > 0:
+        out["L2 hit rate"] = m["TCC_HIT_sum"] / (m["TCC_HIT_sum"] + m["TCC_MISS_sum"])
+    if m.get("TCP_TCC_READ_REQ_sum"):
+        if "TCP_TCC_READ_REQ_LATENCY_sum" in m:
+            out["L2 read latency (cycles)"] = m["TCP_TCC_READ_REQ_LATENCY_sum"] / m["TCP_TCC_READ_REQ_sum"]
+        if "TCP_TOTAL_CACHE_ACCESSES_sum" in m:
+            out["L1 accesses per L2 read"] = m["TCP_TOTAL_CACHE_ACCESSES_sum"] / m["TCP_TCC_READ_REQ_sum"]
+    return out
+
+
 def counters_main(argv):
-    """Per-kernel means of arbitrary counters from several --pmc runs."""
+    """Per-kernel means of arbitrary counters from several --pmc runs of the
+    same command; --by-grid keeps launches of different grid sizes (different
+    matrices) apart, and the derived shares follow where their counters are
+    present."""
     ap = argparse.ArgumentParser(prog="profiling counters")
     ap.add_argument("--dirs", nargs="+", required=True)
     ap.add_argument("--cmds", nargs="+", required=True)
     ap.add_argument("--kernels", nargs="+", required=True, help="kernel name prefixes to report")
     ap.add_argument("--title", required=True)
     ap.add_argument("--notes", default="")
+    ap.add_argument("--by-grid", action="store_true")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     vals = defaultdict(lambda: defaultdict(list))
     order = []
     for d in a.dirs:
         with open(_one(d, "counter_collection.csv")) as f:
+            per = defaultdict(dict)  # one dispatch: counter -> summed value
             for r in csv.DictReader(f):
+                if not any(r["Kernel_Name"].startswith(k) for k in a.kernels):
+                    continue
                 c = r["Counter_Name"]
                 if c not in order:
                     order.append(c)
-                vals[r["Kernel_Name"]][c].append(float(r["Counter_Value"]))
+                key = (r["Kernel_Name"], r.get("Grid_Size", "") if a.by_grid else "")
+                disp = per[(key, r["Dispatch_Id"])]
+                disp[c] = disp.get(c, 0.0) + float(r["Counter_Value"])
+            for (key, _), cs in per.items():
+                for c, v in cs.items():
+                    vals[key][c].append(v)
+    rows = []
+    for key in sorted(vals):
+        m = {c: sum(v) / len(v) for c, v in vals[key].items() if v}
+        rows.append((key, m, derived_columns(m)))
+    dnames = []
+    for _, _, dv in rows:
+        for k in dv:
+            if k not in dnames:
+                dnames.append(k)
     with open(a.out, "w") as f:
         f.write(f"# {a.title}\n\nCommands (repository root, one MI355X), one counter group per "
                 "run:\n\n" + "".join(f"    {c}\n" for c in a.cmds) + "\n")
         if a.notes:
             f.write(a.notes + "\n\n")
+        label = "kernel | grid" if a.by_grid else "kernel"
+        if dnames:
+            f.write("Derived (busy time = GRBM_GUI_ACTIVE / 8 XCDs; shares of it per CU):\n\n")
+            f.write(f"| {label} | " + " | ".join(dnames) + " |\n|---|" + ("---|" if a.by_grid else "")
+                    + "---:|" * len(dnames) + "\n")
+            for (name, grid), m, dv in rows:
+                cells = " | ".join(f"{dv[k]:.3g}" if k in dv else "" for k in dnames)
+                g = f" | {grid}" if a.by_grid else ""
+                f.write(f"| `{_short(name, 60)}`{g} | {cells} |\n")
+            f.write("\n")
         f.write("Mean per dispatch (rocprofv3 sums each counter over the device).\n\n")
-        f.write("| kernel | " + " | ".join(order) + " |\n|---|" + "---:|" * len(order) + "\n")
-        for name in sorted(vals):
-            if not any(name.startswith(k) for k in a.kernels):
-                continue
-            row = [sum(vals[name][c]) / len(vals[name][c]) if vals[name][c] else float("nan")
-                   for c in order]
-            f.write(f"| `{_short(name, 60)}` | " + " | ".join(f"{v:.4g}" for v in row) + " |\n")
+        f.write(f"| {label} | " + " | ".join(order) + " |\n|---|" + ("---|" if a.by_grid else "")
+                + "---:|" * len(order) + "\n")
+        for (name, grid), m, _ in rows:
+            g = f" | {grid}" if a.by_grid else ""
+            f.write(f"| `{_short(name, 60)}`{g} | " + " | ".join(f"{m.get(c, float('nan')):.4g}" for c in order) + " |\n")
     print(f"wrote {a.out}")
 
 
