@@ -49,19 +49,20 @@ def log(*a):
 def kernel_names(v, plan):
     """Demangled-name prefixes of the kernels one FP64 execute of variant v launches."""
     import paper_1511_02494_amd as S
+    coded = "true" if plan.query(22) == S.SPMV_IDX_CODED else "false"  # 16-bit column codes
     if v == S.V_CSR_SCALAR:
         return ["void spmvsel::k_csr_scalar<double>"]
     if v == S.V_CSR_VECTOR:
         return [f"void spmvsel::k_csr_vector<double, {plan.query(1)}>"]
     if v == S.V_MERGE_PATH:
-        return ["void spmvsel::k_merge_path<double>", "void spmvsel::k_merge_fixup<double>"]
+        return [f"void spmvsel::k_merge_path<double, {coded}>", "void spmvsel::k_merge_fixup<double>"]
     if v == S.V_XBLOCK_LDS:
         rows = plan.query(12)  # rows per block of the per-slice row-streaming kernel, 0 = merge path
         if plan.query(16) > 0:  # phased slices: no partial y, no slice sum
-            return [f"void spmvsel::k_phased_slices<double, {plan.query(16)}>"]
+            return [f"void spmvsel::k_phased_slices<double, {plan.query(16)}, {coded}>"]
         if rows > 0:  # per-slice partials; with long rows their sums join the slice sum
             finish = "k_slice_finish" if plan.query(13) > 0 else "k_slice_sum"
-            return [f"void spmvsel::k_rowstream_slices<double, {rows // 256}>",
+            return [f"void spmvsel::k_rowstream_slices<double, {rows // 256}, {coded}>",
                     f"void spmvsel::{finish}<double>"]
         return ["void spmvsel::k_merge_slices<double>", "void spmvsel::k_merge_fixup_slices<double>",
                 "void spmvsel::k_slice_sum<double>"]
