@@ -133,13 +133,14 @@ typedef struct {
     double scores[3];       /* s_nox, s_inf, s_bal */
     double features[12];    /* spmv_features output */
     double t_features_s;    /* host wall-clock of the feature extraction and
-                               feasibility test; for SPMV_SEL_MLP on a plan
-                               with no features yet (automatic index coding)
-                               these, the device finalisation of the features
-                               and the network run as one pass on the plan's
-                               stream with one wait, all counted here */
-    double t_decide_s;      /* MLP inference (0 when it ran in that one
-                               pass), or the cascade */
+                               feasibility test; for a learned selector on a
+                               plan with no features yet (automatic index
+                               coding) these, the device finalisation of the
+                               features and the selector run as one pass on
+                               the plan's stream with one wait, all counted
+                               here */
+    double t_decide_s;      /* the learned selector's inference (0 when it
+                               ran in that one pass), or the cascade */
     double t_profile_s;     /* micro-benchmarks (0 unless they ran) */
     double t_total_s;       /* whole selection, excluding format preparation */
     double t_prepare_s;     /* format preparation of the chosen variant */
@@ -190,10 +191,11 @@ spmv_status_t spmv_features(spmv_plan_t plan, double out_features[12],
  * profiling selector's micro-benchmarks and bottleneck cascade (Section
  * 3.2.1, Table 2's class-to-optimisation map), or a classifier on the
  * structural features of Table 1 (Section 3.2.2).  info (nullable) receives the decision record.
- * Synchronous.  SPMV_SEL_MLP on a plan with no features yet, under automatic
- * index coding, takes one pass (feature kernels, delta16 span test, device
- * finalisation, network; one wait); the result is the same as that of the
- * step-by-step path taken otherwise. */
+ * Synchronous.  The learned selectors (SPMV_SEL_MLP, SPMV_SEL_DTREE,
+ * SPMV_SEL_GNB) on a plan with no features yet, under automatic index
+ * coding, take one pass (feature sums and delta16 spans, device
+ * finalisation, the selector; one wait); the result is the same as that of
+ * the step-by-step path taken otherwise. */
 spmv_status_t spmv_select(spmv_plan_t plan, int32_t selector,
                           spmv_select_info_t *info);
 

@@ -1098,25 +1098,28 @@ spmv_status_t mlp_predict(const double f[12], uint32_t feas, hipStream_t s, floa
     return SPMV_OK;
 }
 
-// The MLP selector's one-pass path for a plan with neither features nor the
-// delta16 test yet, under automatic index coding: one kernel takes the
-// feature sums and the delta16 block spans at both block heights in one pass
-// over the rows, a second reduces them, finalises the features on the device
-// and runs the network, writing the record straight into pinned host memory;
-// one wait, no allocation.  Returns SPMV_ERR_NO_MODEL (error cleared) without
-// launching anything when no model is loaded.
-spmv_status_t select_mlp_onepass(spmv_plan *P, uint32_t *feas, int32_t *variant, float *margin,
-                                 int32_t *fallback, float *logits) {
-    const float *dp, *dn;
-    {
+// The one-pass path of the learned selectors (MLP, CART, naive Bayes) for a
+// plan with neither features nor the delta16 test yet, under automatic
+// index coding: one kernel takes the feature sums and the delta16 block
+// spans at both block heights in one pass over the rows, a second reduces
+// them, finalises the features on the device and runs the selector, writing
+// the record straight into pinned host memory; one wait, no allocation.
+// Returns SPMV_ERR_NO_MODEL (error cleared) without launching anything when
+// the selector has no model.  variant: the pick (for class labels mapped
+// through Table 2 with thresholds th); margin and logits: the MLP's.
+spmv_status_t select_onepass(spmv_plan *P, int32_t selector, const double th[4], uint32_t *feas,
+                             int32_t *variant, float *margin, int32_t *fallback, float *logits) {
+    const float *dp = nullptr, *dn = nullptr;
+    float tau = 0.f;
+    const int which = selector == SEL_DTREE ? 0 : 1;
+    if (selector == SEL_MLP) {
         const spmv_status_t st = model_device(&dp, &dn);
         if (st == SPMV_ERR_NO_MODEL) { clear_error(); return st; }
         SPMV_TRY(st);
-    }
-    float tau;
-    {
         std::lock_guard<std::mutex> lk(g_mu);
         tau = g_model.tau;
+    } else if (!classic_loaded(which)) {
+        return SPMV_ERR_NO_MODEL;
     }
     const hipStream_t s = S(P);
     // spans at the heights check_d16 tries: H0 = the short_row block, then H1 = kBlock
@@ -1125,17 +1128,29 @@ spmv_status_t select_mlp_onepass(spmv_plan *P, uint32_t *feas, int32_t *variant,
     const int parts = launch_select_pass(*P, R, scr<uint64_t>(P, kOffPart), xbytes(P->dtype), s, &e);
     SPMV_HIP(e);  // hipErrorInvalidValue for a row count per thread other than 1, 2, 4, 8
     char *h = static_cast<char *>(P->h_pinned) + 2048;
+    void *hd = static_cast<char *>(P->h_pinned_dev) + 2048;
     const uint32_t base_bits = (1u << V_CSR_SCALAR) | (1u << V_CSR_VECTOR) |
                                (1u << V_MERGE_PATH) | (1u << V_SHORT_ROW) | (1u << V_XBLOCK_LDS);
-    SPMV_HIP(launch_mlp_select(dp, dn, scr<uint64_t>(P, kOffPart), parts, P->n, P->m, P->nnz,
-                               vbytes(P->dtype), xbytes(P->dtype), R > 1 ? 1 : 0, base_bits, tau,
-                               reinterpret_cast<float *>(static_cast<char *>(P->h_pinned_dev) + 2048),
-                               s));
+    int label_kind = 0;
+    if (selector == SEL_MLP) {
+        SPMV_HIP(launch_mlp_select(dp, dn, scr<uint64_t>(P, kOffPart), parts, P->n, P->m, P->nnz,
+                                   vbytes(P->dtype), xbytes(P->dtype), R > 1 ? 1 : 0, base_bits,
+                                   tau, static_cast<float *>(hd), s));
+    } else {
+        const spmv_status_t st =
+            classic_select_launch(which, scr<uint64_t>(P, kOffPart), parts, P->n, P->m, P->nnz,
+                                  vbytes(P->dtype), xbytes(P->dtype), R > 1 ? 1 : 0, base_bits, hd,
+                                  s, &label_kind);
+        if (st == SPMV_ERR_NO_MODEL) {  // unloaded meanwhile: the pass only wrote scratch
+            clear_error();
+            return st;
+        }
+        SPMV_TRY(st);
+    }
     SPMV_TRY(sync(P));
-    float hf[33];
     double f[12];
     uint64_t w[16];
-    memcpy(hf, h, sizeof hf);
+    memcpy(feas, h + 128, 4);
     memcpy(f, h + 192, sizeof f);
     memcpy(w, h + 288, sizeof w);
     // delta16: the first height whose blocks fit 16-bit offsets
@@ -1150,11 +1165,19 @@ spmv_status_t select_mlp_onepass(spmv_plan *P, uint32_t *feas, int32_t *variant,
                             w[6], w[7], w[8], w[9], (uint64_t)smiss, (uint64_t)P->nnz};
     memcpy(P->acc, a, sizeof a);
     P->have_features = true;
-    memcpy(feas, &hf[32], 4);
-    memcpy(variant, &hf[0], 4);
-    *margin = hf[1];
-    *fallback = hf[2] != 0.f;
-    memcpy(logits, hf + 3, 6 * 4);
+    if (selector == SEL_MLP) {
+        float hf[9];
+        memcpy(hf, h, sizeof hf);
+        memcpy(variant, &hf[0], 4);
+        *margin = hf[1];
+        *fallback = hf[2] != 0.f;
+        memcpy(logits, hf + 3, 6 * 4);
+    } else {
+        int32_t hi[3];
+        memcpy(hi, h, sizeof hi);
+        *fallback = hi[2];
+        *variant = label_kind == 0 ? hi[0] : class_variant(hi[0], f, th, *feas);
+    }
     return SPMV_OK;
 }
 
@@ -1663,12 +1686,13 @@ spmv_status_t spmv_select(spmv_plan_t P, int32_t selector, spmv_select_info_t *i
     int32_t v = V_CSR_VECTOR;
     int used = selector;
     bool onepass = false;
-    if (selector == SEL_MLP && !P->have_features && !P->d16_checked && P->idx_req < 0 && P->n > 0) {
+    const bool learned = selector == SEL_MLP || selector == SEL_DTREE || selector == SEL_GNB;
+    if (learned && !P->have_features && !P->d16_checked && P->idx_req < 0 && P->n > 0) {
         int32_t fb = 1;
-        const spmv_status_t st = select_mlp_onepass(P, &feas, &v, &I.margin, &fb, I.logits);
+        const spmv_status_t st = select_onepass(P, selector, th, &feas, &v, &I.margin, &fb, I.logits);
         if (st == SPMV_OK) {
             onepass = true;
-            if (fb || v < 0) {
+            if (fb || v < 0 || !((feas >> v) & 1)) {
                 I.fell_back = 1;
                 used = SEL_PROFILING;
             }
@@ -1696,7 +1720,7 @@ spmv_status_t spmv_select(spmv_plan_t P, int32_t selector, spmv_select_info_t *i
             I.fell_back = 1;
             used = SEL_PROFILING;
         }
-    } else if (selector == SEL_DTREE || selector == SEL_GNB) {
+    } else if ((selector == SEL_DTREE || selector == SEL_GNB) && !onepass) {
         int32_t fb = 1, lab = -1;
         spmv_status_t st = classic_predict(selector == SEL_DTREE ? 0 : 1, P->feats, feas, th, S(P),
                                            scr<char>(P, kOffClf), &v, &lab, &fb);

@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "dev.h"
+#include "feat_acc.h"
 #include "internal.h"
 
 namespace spmvsel {
@@ -205,10 +206,11 @@ spmv_status_t device_model(int which, const int32_t **di, const double **dd, Cla
 
 // ---------------------------------------------------------------- kernels
 // out: int32 [label, leaf, fallback, pad], then double scores[kMaxClasses]
-__global__ __launch_bounds__(64) void k_tree_infer(const int32_t *__restrict__ ints, int n_nodes,
-                                                   int C, const double *__restrict__ thr, F12 x,
-                                                   uint32_t feasible, int32_t *__restrict__ out) {
-    if (threadIdx.x != 0) return;
+
+// The tree walk and decision for features x (one thread).
+__device__ void tree_decide(const int32_t *__restrict__ ints, int n_nodes, int C,
+                            const double *__restrict__ thr, const double *x, uint32_t feasible,
+                            int32_t *__restrict__ out) {
     const int32_t *feat = ints, *lft = ints + n_nodes, *rgt = ints + 2 * n_nodes,
                   *cnt = ints + 3 * n_nodes;
     int node = 0;
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(64) void k_tree_infer(const int32_t *__restrict__ i
         const int j = feat[node];
 #pragma unroll
         for (int q = 0; q < kNF; ++q)
-            if (q == j) v = x.f[q];
+            if (q == j) v = x[q];
         node = v <= thr[node] ? lft[node] : rgt[node];
     }
     int best = -1, bc = 0;
@@ -233,17 +235,17 @@ __global__ __launch_bounds__(64) void k_tree_infer(const int32_t *__restrict__ i
     out[2] = best < 0;
 }
 
-__global__ __launch_bounds__(64) void k_gnb_infer(const int32_t *__restrict__ count,
-                                                  const double *__restrict__ mu,
-                                                  const double *__restrict__ w,
-                                                  const double *__restrict__ c, int C, F12 g,
-                                                  uint32_t feasible, int32_t *__restrict__ out) {
+// The class scores and decision for inputs g (all threads of the
+// workgroup, C <= its size; ends with the decision written by thread 0).
+__device__ void gnb_decide(const int32_t *__restrict__ count, const double *__restrict__ mu,
+                           const double *__restrict__ w, const double *__restrict__ c, int C,
+                           const double *g, uint32_t feasible, int32_t *__restrict__ out) {
     __shared__ double s[kMaxClasses];
     const int k = threadIdx.x;
     if (k < C) {
         double acc = 0.0;
         for (int j = 0; j < kNF; ++j) {
-            const double d = g.f[j] - mu[k * kNF + j];
+            const double d = g[j] - mu[k * kNF + j];
             acc = acc + w[k * kNF + j] * (d * d);
         }
         s[k] = count[k] > 0 ? c[k] - acc : -INFINITY;
@@ -259,6 +261,49 @@ __global__ __launch_bounds__(64) void k_gnb_infer(const int32_t *__restrict__ co
         out[0] = best < 0 ? 0 : best;
         out[1] = -1;
         out[2] = best < 0;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_tree_infer(const int32_t *__restrict__ ints, int n_nodes,
+                                                   int C, const double *__restrict__ thr, F12 x,
+                                                   uint32_t feasible, int32_t *__restrict__ out) {
+    if (threadIdx.x != 0) return;
+    tree_decide(ints, n_nodes, C, thr, x.f, feasible, out);
+}
+
+__global__ __launch_bounds__(64) void k_gnb_infer(const int32_t *__restrict__ count,
+                                                  const double *__restrict__ mu,
+                                                  const double *__restrict__ w,
+                                                  const double *__restrict__ c, int C, F12 g,
+                                                  uint32_t feasible, int32_t *__restrict__ out) {
+    gnb_decide(count, mu, w, c, C, g.f, feasible, out);
+}
+
+// One-pass selection with classifier `which` (0 tree, 1 NB): the features,
+// feasibility and record from the selection kernel's partials (as for the
+// MLP), then the classifier on the device.  Class labels (label_variants 0)
+// take every class as feasible; the host maps the class to a variant.
+// out: the classifier record above in bytes 0..79, then the common part.
+__global__ __launch_bounds__(64) void k_classic_select(int which, const int32_t *__restrict__ ints,
+                                                       int n_nodes, const double *__restrict__ dd,
+                                                       int C, int label_variants,
+                                                       const uint64_t *__restrict__ partials,
+                                                       int nparts, int64_t n, int64_t m,
+                                                       int64_t nnz, int vb, int xb, int two_heights,
+                                                       uint32_t feas_base, char *__restrict__ out) {
+    __shared__ uint64_t w[16];
+    __shared__ double f[kNF], g[kNF];
+    __shared__ uint32_t feas;
+    feat::select_prologue(nparts, partials, n, m, nnz, vb, xb, two_heights, feas_base, w, f, &feas);
+    if (threadIdx.x == 0) feat::select_store_common(out, f, feas, w);
+    const uint32_t lab_feas = label_variants ? feas : 0xFu;
+    int32_t *o = reinterpret_cast<int32_t *>(out);
+    if (which == 0) {
+        if (threadIdx.x == 0) tree_decide(ints, n_nodes, C, dd, f, lab_feas, o);
+    } else {
+        if (threadIdx.x < kNF) g[threadIdx.x] = threadIdx.x < 8 ? feat::plog2(1.0 + f[threadIdx.x]) : f[threadIdx.x];
+        __syncthreads();
+        gnb_decide(ints, dd, dd + C * kNF, dd + 2 * C * kNF, C, g, lab_feas, o);
     }
 }
 
@@ -302,6 +347,27 @@ spmv_status_t classic_run(int which, const double f[12], uint32_t feas, const do
 }
 
 }  // namespace
+
+bool classic_loaded(int which) {
+    std::lock_guard<std::mutex> lk(g_cmu);
+    return g_clf[which].loaded;
+}
+
+spmv_status_t classic_select_launch(int which, const uint64_t *d_partials, int nparts, int64_t n,
+                                    int64_t m, int64_t nnz, int vb, int xb, int two_heights,
+                                    uint32_t feas_base, void *out, hipStream_t s,
+                                    int *label_kind) {
+    const int32_t *di;
+    const double *dd;
+    Classic snap;
+    SPMV_TRY(device_model(which, &di, &dd, &snap));
+    *label_kind = snap.label_kind;
+    hipLaunchKernelGGL(k_classic_select, dim3(1), dim3(64), 0, s, which, di, snap.n_nodes,
+                       dd, snap.n_classes, snap.label_kind == 0 ? 1 : 0, d_partials, nparts, n, m,
+                       nnz, vb, xb, two_heights, feas_base, static_cast<char *>(out));
+    SPMV_HIP(hipGetLastError());
+    return SPMV_OK;
+}
 
 spmv_status_t classic_predict(int which, const double f[12], uint32_t feas, const double th[4],
                               hipStream_t s, void *d_out, int32_t *variant, int32_t *label,

@@ -203,6 +203,16 @@ spmv_status_t run_variant(const spmv_plan *P, int v, const void *x, void *y, hip
 int class_variant(int k, const double feats[12], const double th[4], uint32_t feas);
 // Device inference of the CART (which 0) or naive Bayes (1) selector; d_out
 // needs 80 bytes of device memory.  SPMV_ERR_NO_MODEL if none is loaded.
+// One-pass selection with a classifier (0 tree, 1 naive Bayes): whether a
+// model is loaded; launching its selection kernel on the partials of the
+// selection pass (the record of kSelectRecordBytes at out: int32 label,
+// leaf, fallback, then the common part at the MLP's offsets); label_kind
+// tells how to read the label (0 variant, 1 bottleneck class).
+bool classic_loaded(int which);
+spmv_status_t classic_select_launch(int which, const uint64_t *d_partials, int nparts, int64_t n,
+                                    int64_t m, int64_t nnz, int vb, int xb, int two_heights,
+                                    uint32_t feas_base, void *out, hipStream_t s,
+                                    int *label_kind);
 spmv_status_t classic_predict(int which, const double f[12], uint32_t feas, const double th[4],
                               hipStream_t s, void *d_out, int32_t *variant, int32_t *label,
                               int32_t *fallback);
@@ -307,8 +317,8 @@ hipError_t launch_mlp_infer(const float *d_params, const float *d_norm, const do
 // then k_mlp_select (reduction, device finalisation of the features,
 // feasibility, network and decision in one workgroup).  out:
 // kSelectRecordBytes (the inference record in floats 0..31, feasibility bits
-// at float 32, features as doubles 24..35, the reduced record as words
-// 36..51, with the spans in words 48 and 49).
+// at byte 128, features as doubles from byte 192, the reduced record as 16
+// words from byte 288, with the spans in its words 12 and 13).
 constexpr size_t kSelectRecordBytes = 416;
 int launch_select_pass(const spmv_plan &P, int R, uint64_t *d_partials, int xb, hipStream_t s,
                        hipError_t *err);

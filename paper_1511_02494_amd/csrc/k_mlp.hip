@@ -31,12 +31,9 @@ struct Feat12 {
     double f[12];
 };
 
-__device__ __forceinline__ double plog2(double v) {
-    int e;
-    const double m = frexp(v, &e);
-    return (double)(e - 1) + (2.0 * m - 1.0);
-}
 }  // namespace
+
+using feat::plog2;
 
 // The network and decision for features f (LDS or registers), 64 threads.
 __device__ __forceinline__ void mlp_infer_body(const float *__restrict__ P,
@@ -103,52 +100,12 @@ __global__ __launch_bounds__(64) void k_mlp_infer(const float *__restrict__ P,
 }
 
 // ---------------------------------------------------------------- selection in one pass
-// The twelve features from the feature kernels' exact integer record, on the
-// device, by the same sequence of IEEE double operations as the host
-// finalisation (u128 numerators rounded to double once, with a sticky bit;
-// correctly rounded division and square root): the selection then needs no
-// host round trip between the features and the network.
-typedef unsigned __int128 u128d;
-
-__device__ __forceinline__ double u128_to_double_dev(u128d v) {
-    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
-    if (hi == 0) return (double)lo;
-    const int sh = 64 - __builtin_clzll(hi);
-    const uint64_t top = (uint64_t)(v >> sh);
-    const uint64_t sticky = (v & (((u128d)1 << sh) - 1)) != 0 ? 1 : 0;
-    return ldexp((double)(top | sticky), sh);
-}
-
-__device__ void finalize_features_dev(const uint64_t *w, int64_t n, int64_t m, int64_t nnz, int vb,
-                                      int xb, double *f) {
-    for (int i = 0; i < 12; ++i) f[i] = 0.0;
-    if (n == 0) return;
-    const double f0 = (double)n, f1 = (double)nnz, nn = f0 * f0;
-    const u128d sl2 = w[3], sbw = w[4], sbw2 = ((u128d)w[6] << 64) | w[5];
-    const u128d sq = w[7], sq2 = ((u128d)w[9] << 64) | w[8];
-    const int64_t smiss = (int64_t)(w[10] - w[11]);
-    f[0] = f0;
-    f[1] = f1;
-    f[2] = f1 / f0;
-    f[3] = sqrt(u128_to_double_dev((u128d)n * sl2 - (u128d)nnz * (u128d)nnz) / nn);
-    f[4] = (double)w[1];
-    f[5] = (double)w[0];
-    f[6] = (double)(uint64_t)sbw / f0;
-    f[7] = sqrt(u128_to_double_dev((u128d)n * sbw2 - sbw * sbw) / nn);
-    f[8] = ((double)(uint64_t)sq / 2147483648.0) / f0;
-    f[9] = sqrt(u128_to_double_dev((u128d)n * sq2 - sq * sq) / 4611686018427387904.0 / nn);
-    f[10] = nnz > 0 ? (double)smiss / f1 : 0.0;
-    const int64_t ws = 4 * (n + 1) + (4 + vb) * nnz + (int64_t)xb * m + (int64_t)xb * n;
-    f[11] = ws <= kLlcBytes ? 1.0 : 0.0;
-}
-
 // partials: the nparts partial records of the one-pass selection kernel
 // (feature sums, and the delta16 block spans in words 12 (height H0) and 13
 // (H1; meaningful when two_heights)); feas_base: the variants feasible
-// whatever the spans.  out (kSelectRecordBytes, pinned host memory or
-// device): the inference record of k_mlp_infer in floats 0..31, the
-// feasibility bits at float 32, the twelve features as doubles 24..35 and
-// the reduced record as words 36..51.
+// whatever the spans.  out (kRecBytes, pinned host memory or device): the
+// inference record of k_mlp_infer in floats 0..31, then the common part
+// (feasibility bits, features, reduced record; see select_store_common).
 __global__ __launch_bounds__(64) void k_mlp_select(const float *__restrict__ P,
                                                    const float *__restrict__ norm,
                                                    const uint64_t *__restrict__ partials,
@@ -159,20 +116,8 @@ __global__ __launch_bounds__(64) void k_mlp_select(const float *__restrict__ P,
     __shared__ uint64_t w[16];
     __shared__ double f[12];
     __shared__ uint32_t feas;
-    feat::reduce_partials_64(nparts, partials, w);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (n == 0) w[0] = 0;
-        finalize_features_dev(w, n, m, nnz, vb, xb, f);
-        const bool d16 = w[12] <= 65535ull || (two_heights && w[13] <= 65535ull);
-        feas = feas_base | (d16 ? (1u << V_DELTA16) : 0u);
-        double *fo = reinterpret_cast<double *>(out) + 24;
-        for (int i = 0; i < 12; ++i) fo[i] = f[i];
-        reinterpret_cast<uint32_t *>(out)[32] = feas;
-        uint64_t *wo = reinterpret_cast<uint64_t *>(out) + 36;
-        for (int i = 0; i < 16; ++i) wo[i] = w[i];
-    }
-    __syncthreads();
+    feat::select_prologue(nparts, partials, n, m, nnz, vb, xb, two_heights, feas_base, w, f, &feas);
+    if (threadIdx.x == 0) feat::select_store_common(reinterpret_cast<char *>(out), f, feas, w);
     mlp_infer_body(P, norm, f, feas, tau, out);
 }
 

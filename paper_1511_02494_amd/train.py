@@ -569,7 +569,9 @@ def clf_scores(kind, recs, labels, label_kind, theta):
         hit.append(t[v] <= 1.05 * best)
         reg.append(t[v] / best - 1)
         fb.append(p["fallback"])
-        ov.append(r["t_features"] + (r["t_profile"] if p["fallback"] else 0.0))
+        # the one-pass selection time where the record has it (the classifiers
+        # run in the same pass as the MLP), else features plus one inference
+        ov.append((r.get("t_select"), r["t_features"], r["t_profile"] if p["fallback"] else 0.0))
     return dict(accuracy=float(np.mean(acc)), hit5=float(np.mean(hit)), mean_regret=float(np.mean(reg)),
                 fallback_rate=float(np.mean(fb)), overhead_s=ov)
 
@@ -620,7 +622,8 @@ def cmd_classic(args):
                 clf_predict(kind, test[0])
                 ts.append(time.perf_counter() - t0)
             t_inf = float(np.median(ts))
-            ov = [o + t_inf for o in sc.pop("overhead_s")]
+            ov = [(one if one is not None else feat + t_inf) + prof
+                  for one, feat, prof in sc.pop("overhead_s")]
             picks_t = []
             for r in test:
                 p = clf_predict(kind, r)

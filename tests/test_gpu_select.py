@@ -119,6 +119,55 @@ ONEPASS = MATS + [
 ]
 
 
+def _class_label_models():
+    """A tree and naive Bayes on the training records' cascade classes (the
+    paper's labelling), installed with class labels."""
+    import json
+    import os
+    from oracle.select import classify, profile_scores
+    path = os.path.join(os.path.dirname(S.__file__), "data", "labels_train.jsonl")
+    with open(path) as f:
+        recs = [json.loads(line) for line in f]
+    X = np.array([r["features"] for r in recs])
+    theta = S.spmv_get_thresholds()
+    yc = np.array([classify(profile_scores(r["meas"]), theta) for r in recs])
+    S.spmv_dtree_load(S.spmv_dtree_fit(X, yc, 4, 6, 5), S.SPMV_LABEL_CLASS)
+    S.spmv_gnb_load(S.spmv_gnb_fit(X, yc, 4), S.SPMV_LABEL_CLASS)
+
+
+@pytest.mark.parametrize("labels", ["variant", "class"])
+@pytest.mark.parametrize("sel", [S.SEL_DTREE, S.SEL_GNB])
+@pytest.mark.parametrize("name,build,m", ONEPASS[:2] + ONEPASS[4:])
+def test_classifier_one_pass_matches_two_step(name, build, m, sel, labels):
+    """SEL_DTREE / SEL_GNB on a fresh plan (one pass: the classifier runs on
+    the device features) and on a plan whose features were already taken
+    (step by step) pick the same variant from the same features and
+    feasibility, with variant labels and with the cascade's class labels
+    (mapped to a variant through Table 2 on the host)."""
+    if labels == "variant":
+        if "dtree" not in S.load_classifiers() or "gnb" not in S.load_classifiers():
+            pytest.skip("no stored classifiers")
+    else:
+        _class_label_models()
+    rp, ci, v = build()
+    a = make_plan(rp, ci, v, m)
+    b = make_plan(rp, ci, v, m)
+    b.features()
+    ia, ib = a.select(sel), b.select(sel)
+    f_ref, _ = features_ref(rp, ci, m)
+    assert list(ia["features"]) == f_ref == list(ib["features"])
+    assert ia["feasible"] == ib["feasible"] == a.mask()
+    assert ia["fell_back"] == ib["fell_back"]
+    if not ia["fell_back"]:
+        assert ia["variant"] == ib["variant"]
+        assert (ia["feasible"] >> ia["variant"]) & 1
+    assert (a.query(11), a.query(9)) == (b.query(11), b.query(9))
+    a.close()
+    b.close()
+    if labels == "class":
+        S.load_classifiers()  # the stored variant-label models back
+
+
 @pytest.mark.parametrize("name,build,m", ONEPASS)
 def test_mlp_one_pass_matches_two_step(name, build, m):
     """SEL_MLP on a fresh plan runs features, the delta16 span test, the
