@@ -63,9 +63,9 @@ def kernel_names(v, plan):
         if rows > 0:  # per-slice partials; with long rows their sums join the slice sum
             finish = "k_slice_finish" if plan.query(13) > 0 else "k_slice_sum"
             return [f"void spmvsel::k_rowstream_slices<double, {rows // 256}, {coded}>",
-                    f"void spmvsel::{finish}<double>"]
+                    f"void spmvsel::{finish}<double, {plan.query(7)}>"]
         return ["void spmvsel::k_merge_slices<double>", "void spmvsel::k_merge_fixup_slices<double>",
-                "void spmvsel::k_slice_sum<double>"]
+                f"void spmvsel::k_slice_sum<double, {plan.query(7)}>"]
     if v == S.V_DELTA16:
         if plan.query(14) == 1:  # sliced layout, offsets of 8 or 16 bits
             o = "unsigned char" if plan.query(17) == 8 else "unsigned short"

@@ -792,12 +792,25 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup_slices(int64_t n, int64_
                        is_f32<A>() && kmin < INT32_MAX);
 }
 
+// The sum of row i's partials in slice order; the NS loads are issued
+// together (streamed once: non-temporal), then added in order.
+template <class A, int NS>
+__device__ __forceinline__ A slice_total(const SliceTable<A> &T, int64_t i) {
+    A v[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) v[k] = __builtin_nontemporal_load(T.y[k] + i);
+    A s = v[0];
+#pragma unroll
+    for (int k = 1; k < NS; ++k) s = s + v[k];
+    return s;
+}
+
 // Slice sums and long rows in one launch: blocks below gsum add the partial
 // y vectors in slice order for every row whose bit in `longmask` is clear;
 // the blocks after them give each long row a wavefront that adds its chunk
 // sums (per lane in order, Kahan for FP32, then a fixed butterfly) and
 // stores the row.  The two sets of rows are disjoint.
-template <class A>
+template <class A, int NS>
 __global__ __launch_bounds__(kBlock) void k_slice_finish(int64_t n, SliceTable<A> T,
                                                          A *__restrict__ y, int64_t gsum,
                                                          const uint32_t *__restrict__ longmask,
@@ -807,9 +820,7 @@ __global__ __launch_bounds__(kBlock) void k_slice_finish(int64_t n, SliceTable<A
     if ((int64_t)blockIdx.x < gsum) {
         for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += gsum * kBlock) {
             if ((longmask[i >> 5] >> (i & 31)) & 1u) continue;
-            A s = T.y[0][i];
-            for (int k = 1; k < T.ns; ++k) s = s + T.y[k][i];
-            y[i] = s;
+            __builtin_nontemporal_store(slice_total<A, NS>(T, i), y + i);
         }
         return;
     }
@@ -823,15 +834,12 @@ __global__ __launch_bounds__(kBlock) void k_slice_finish(int64_t n, SliceTable<A
     if (lane == 0) y[rows[t]] = v;
 }
 
-template <class A>
+template <class A, int NS>
 __global__ __launch_bounds__(kBlock) void k_slice_sum(int64_t n, SliceTable<A> T,
                                                       A *__restrict__ y) {
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        A s = T.y[0][i];
-        for (int k = 1; k < T.ns; ++k) s = s + T.y[k][i];
-        y[i] = s;
-    }
+         i += (int64_t)gridDim.x * kBlock)
+        __builtin_nontemporal_store(slice_total<A, NS>(T, i), y + i);
 }
 
 // ============================================================ launchers
@@ -1099,14 +1107,30 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
         if (P.xs_nlong > 0) {  // rows taken out of the slices (chunks summed above)
             const int64_t gsum = grid_for(P.n, kBlock, (int64_t)P.num_cus * 16);
             const int64_t glong = (P.xs_nlong * 64 + kBlock - 1) / kBlock;
-            hipLaunchKernelGGL(k_slice_finish<A>, dim3((unsigned)(gsum + glong)), dim3(kBlock), 0, s,
-                               P.n, T, (A *)y, gsum, P.xs_lmask.as<uint32_t>(), P.xs_nlong,
-                               P.xs_lrows.as<int32_t>(), P.xs_lfirst.as<int32_t>(),
-                               P.xs_lsum.as<A>(), P.kahan_min);
+#define SPMV_FIN(NS)                                                                              \
+    case NS:                                                                                      \
+        hipLaunchKernelGGL((k_slice_finish<A, NS>), dim3((unsigned)(gsum + glong)), dim3(kBlock), 0, \
+                           s, P.n, T, (A *)y, gsum, P.xs_lmask.as<uint32_t>(), P.xs_nlong,        \
+                           P.xs_lrows.as<int32_t>(), P.xs_lfirst.as<int32_t>(),                    \
+                           P.xs_lsum.as<A>(), P.kahan_min);                                        \
+        break;
+            switch (T.ns) {
+                SPMV_FIN(1) SPMV_FIN(2) SPMV_FIN(4) SPMV_FIN(8)
+            default: return hipErrorInvalidValue;
+            }
+#undef SPMV_FIN
             return hipGetLastError();
         }
         const unsigned g = grid_for(P.n, kBlock, (int64_t)P.num_cus * 16);
-        hipLaunchKernelGGL(k_slice_sum<A>, dim3(g), dim3(kBlock), 0, s, P.n, T, (A *)y);
+#define SPMV_SUM(NS)                                                                              \
+    case NS:                                                                                      \
+        hipLaunchKernelGGL((k_slice_sum<A, NS>), dim3(g), dim3(kBlock), 0, s, P.n, T, (A *)y);      \
+        break;
+        switch (T.ns) {
+            SPMV_SUM(1) SPMV_SUM(2) SPMV_SUM(4) SPMV_SUM(8)
+        default: return hipErrorInvalidValue;
+        }
+#undef SPMV_SUM
         return hipGetLastError();
     });
 }
