@@ -216,7 +216,11 @@ __device__ __forceinline__ double wave_shl1(double v) {
 // their four x entries: on stencils the lanes' columns are consecutive too.
 // Every lane loads every pair up to the slice width (padding slots hold zero
 // offsets, so their gathers stay in range); products past the row's end are
-// dropped, which keeps the loads free of branches.  y is written with
+// dropped, which keeps the loads free of per-lane branches.  A step whose
+// second pair lies past the width skips it (a wavefront-uniform branch) with
+// 16-bit offsets and in diagonal slices, 2-4% on short rows, whose slices
+// are one pair wide; with 8-bit codes it reloads the last pair instead (the
+// branch cost 3-5% on bands there).  y is written with
 // streaming (non-temporal) stores: 4% faster on the 27-point stencil and 10%
 // on short rows from a flushed cache, and no slower warm.
 template <class V, class O>
@@ -261,11 +265,15 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
             const int k1 = (k0 + 2) < w ? k0 + 2 : w - 2;
             const VP v0 = __builtin_nontemporal_load(
                 reinterpret_cast<const VP *>(val + o + (int64_t)(k0 / 2) * (2 * kSellRows)));
-            const VP v1 = __builtin_nontemporal_load(
-                reinterpret_cast<const VP *>(val + o + (int64_t)(k1 / 2) * (2 * kSellRows)));
-            A xv[4];
+            const bool two = k0 + 2 < w;  // wavefront-uniform: the step has a second pair
+            VP v1 = {};
+            if (two)
+                v1 = __builtin_nontemporal_load(
+                    reinterpret_cast<const VP *>(val + o + (int64_t)(k1 / 2) * (2 * kSellRows)));
+            A xv[4] = {A(0), A(0), A(0), A(0)};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
+                if (i >= 2 && !two) break;
                 const int kk = i < 2 ? k0 + i : k1 + (i - 2);
                 const int32_t dk = dg[kk];
                 A xk;
@@ -379,12 +387,17 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
             } else {
                 v0 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q0));
                 const OP c0 = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + q0));
-                v1 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q1));
-                const OP c1 = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + q1));
                 x0 = GX(b + (int32_t)c0.x);
                 x1 = GX(b + (int32_t)c0.y);
-                x2 = GX(b + (int32_t)c1.x);
-                x3 = GX(b + (int32_t)c1.y);
+                if (k0 + 2 < w) {  // wavefront-uniform: the step has a second pair
+                    v1 = __builtin_nontemporal_load(reinterpret_cast<const VP *>(val + q1));
+                    const OP c1 = __builtin_nontemporal_load(reinterpret_cast<const OP *>(off + q1));
+                    x2 = GX(b + (int32_t)c1.x);
+                    x3 = GX(b + (int32_t)c1.y);
+                } else {
+                    v1 = VP{};
+                    x2 = x3 = A(0);
+                }
             }
             const A p[4] = {VT<V>::cvt(v0.x) * x0, VT<V>::cvt(v0.y) * x1, VT<V>::cvt(v1.x) * x2,
                             VT<V>::cvt(v1.y) * x3};
