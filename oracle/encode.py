@@ -73,11 +73,32 @@ SLICE_MAX_PAD_LONG = 1.5  # or this many when the rows average at least
 SLICE_LONG_MEAN = 16      # this many nonzeros
 
 
-def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
+SELL_WINDOW = 256  # rows per window of the length-sorted sliced layout
+
+
+def sell_perm_ref(rowptr, window: int = SELL_WINDOW):
+    """Row order of the length-sorted sliced layout (sorting rows by length
+    inside windows, as in Kreutzer et al.'s SELL-C-sigma, to cut a slice's
+    padding): the rows of each window of ``window`` consecutive rows, longest
+    first, ties in row order.  Position p of the layout holds row perm[p]."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    n = len(rowptr) - 1
+    lens = rowptr[1:] - rowptr[:-1]
+    perm = np.empty(n, dtype=np.int64)
+    for w0 in range(0, n, window):
+        rows = sorted(range(w0, min(n, w0 + window)), key=lambda i: (-int(lens[i]), i))
+        perm[w0:w0 + len(rows)] = rows
+    return perm
+
+
+def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS, sort_rows: bool = False):
     """The sliced delta16 layout of a CSR matrix.
 
     Slice s holds rows [64 s, 64 s + 64) (lanes past the last row are empty
-    rows).  Each slice is of one of two kinds:
+    rows).  With ``sort_rows`` it holds rows perm[64 s .. 64 s + 63] of
+    ``sell_perm_ref`` instead (positions past the last row empty) and every
+    slice is an offset slice; everything below then reads "the row at
+    position p" for "row p".  Each slice is of one of two kinds:
 
     * diagonal (kind 1): U_s, the sorted distinct values of c - r over the
       slice's nonzeros, has at most 32 entries and, rounded up to an even
@@ -102,13 +123,15 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
     the slice minus base_s, 0 if it has no nonzeros), diag
     (int32[32 S]: U_s zero-padded, zeros for offset slices), mask (uint32[N]:
     0 in offset slices), slots (64 sum w_s), off (int64[slots]; the caller
-    checks they fit 16 bits), vals (float64[slots]) and nnz_offset (the
-    nonzeros of the offset slices).
+    checks they fit 16 bits), vals (float64[slots]), nnz_offset (the
+    nonzeros of the offset slices) and perm (the row at each position: the
+    identity unless sorted).
     """
     rowptr = np.asarray(rowptr, dtype=np.int64)
     colind = np.asarray(colind, dtype=np.int64)
     val = np.asarray(val, dtype=np.float64)
     n = len(rowptr) - 1
+    perm = sell_perm_ref(rowptr) if sort_rows else np.arange(n, dtype=np.int64)
     ns = (n + slice_rows - 1) // slice_rows
     kind = np.zeros(ns, dtype=np.int64)
     ndiag = np.zeros(ns, dtype=np.int64)
@@ -118,17 +141,17 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
     diag = np.zeros(32 * ns, dtype=np.int64)
     diag_sets = []
     for s in range(ns):
-        r0, r1 = s * slice_rows, min(n, (s + 1) * slice_rows)
-        lens = rowptr[r0 + 1:r1 + 1] - rowptr[r0:r1]
+        rows = perm[s * slice_rows:min(n, (s + 1) * slice_rows)]
+        lens = rowptr[rows + 1] - rowptr[rows]
         longest = int(lens.max()) if len(lens) else 0
         w_off = longest + (longest % 2)
-        a, e = rowptr[r0], rowptr[r1]
-        base[s] = colind[a:e].min() if a < e else 0
-        span[s] = colind[a:e].max() - base[s] if a < e else 0
-        rel = sorted({int(colind[j]) - i for i in range(r0, r1)
+        cols = np.concatenate([colind[rowptr[i]:rowptr[i + 1]] for i in rows]) if len(rows) else colind[:0]
+        base[s] = cols.min() if len(cols) else 0
+        span[s] = cols.max() - base[s] if len(cols) else 0
+        rel = sorted({int(colind[j]) - int(i) for i in rows
                       for j in range(rowptr[i], rowptr[i + 1])})
         d_even = len(rel) + (len(rel) % 2)
-        if len(rel) <= 32 and d_even <= w_off:
+        if not sort_rows and len(rel) <= 32 and d_even <= w_off:
             kind[s], ndiag[s], width[s] = 1, len(rel), d_even
             diag[32 * s:32 * s + len(rel)] = rel
         else:
@@ -143,8 +166,9 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
     mask = np.zeros(n, dtype=np.int64)
     nnz_offset = 0
     pair_stride = 2 * slice_rows
-    for i in range(n):
-        s, lane = divmod(i, slice_rows)
+    for p in range(n):
+        i = int(perm[p])
+        s, lane = divmod(p, slice_rows)
         for k_row in range(rowptr[i + 1] - rowptr[i]):
             j = rowptr[i] + k_row
             if kind[s]:
@@ -162,7 +186,7 @@ def delta16_sliced_ref(rowptr, colind, val, slice_rows: int = SLICE_ROWS):
                 base=base.astype(np.int32), units=units.astype(np.int32),
                 span=span.astype(np.int32),
                 diag=diag.astype(np.int32), mask=mask.astype(np.uint32), slots=slots,
-                off=off, vals=vals, nnz_offset=nnz_offset)
+                off=off, vals=vals, nnz_offset=nnz_offset, perm=perm.astype(np.int32))
 
 
 ESCAPE = 255  # 8-bit code of a column stored in full
@@ -194,9 +218,11 @@ def delta8_codes_ref(rowptr, colind, L, slice_rows: int = SLICE_ROWS):
     n = len(rowptr) - 1
     ns = len(L["width"])
     E = np.zeros(ns, dtype=np.int64)
+    perm = L.get("perm", np.arange(n))
     row_escapes = []
-    for i in range(n):
-        s, lane = divmod(i, slice_rows)
+    for p in range(n):
+        i = int(perm[p])
+        s, lane = divmod(p, slice_rows)
         if L["kind"][s]:
             row_escapes.append([])
             continue
@@ -213,8 +239,9 @@ def delta8_codes_ref(rowptr, colind, L, slice_rows: int = SLICE_ROWS):
     codes = np.zeros(L["slots"] + 2 * slice_rows * ns, dtype=np.uint8)
     esc = np.zeros(slice_rows * int(E.sum()), dtype=np.int64)
     escapes = 0
-    for i in range(n):
-        s, lane = divmod(i, slice_rows)
+    for p in range(n):
+        i = int(perm[p])
+        s, lane = divmod(p, slice_rows)
         if L["kind"][s]:
             continue
         prev, e = int(L["base"][s]), 0
@@ -242,9 +269,12 @@ def delta8_decode_ref(codes, esc, L, row_lengths, slice_rows: int = SLICE_ROWS):
     """The columns of every offset-slice row back from its codes (the
     inverse of ``delta8_codes_ref``), as a list of lists (empty for rows of
     diagonal slices)."""
+    n = len(row_lengths)
+    pos = np.empty(n, dtype=np.int64)
+    pos[np.asarray(L.get("perm", np.arange(n)), dtype=np.int64)] = np.arange(n)
     out = []
     for i, length in enumerate(row_lengths):
-        s, lane = divmod(i, slice_rows)
+        s, lane = divmod(int(pos[i]), slice_rows)
         cols = []
         if not L["kind"][s]:
             c, e = int(L["base"][s]), 0
@@ -271,6 +301,20 @@ def delta16_offset_bits_ref(nnz_offset: int, escape_units: int) -> int:
     byte the codes save per nonzero: 256 sum E <= nnz_offset / 2.
     """
     return 8 if nnz_offset > 0 and 512 * escape_units <= nnz_offset else 16
+
+
+def delta16_sort_ref(slots: int, slots_sorted: int, ndiag: int, nslices: int, nnz: int, n: int) -> bool:
+    """Whether the sliced layout sorts its rows (``sell_perm_ref``).
+
+    Sorting gives up diagonal slices and costs a 4-byte row index per row
+    (the kernel reads the row it owns and stores y there), so it is taken
+    when the plain layout has at most 1% diagonal slices and over 5% of
+    padding, and sorting saves at least 5% of its slots and at least two
+    slots per row (9 or more bytes of values and codes against 4)."""
+    if ndiag * 100 > nslices or slots * 100 <= 105 * nnz:
+        return False
+    saved = slots - slots_sorted
+    return saved * 20 >= slots and saved >= 2 * n
 
 
 def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int, n: int) -> int:

@@ -7,6 +7,7 @@ import pytest
 
 import synth
 from oracle.encode import (bf16_bits_to_f64, code_slot_ref, delta8_codes_ref, delta8_decode_ref,
+                           delta16_sort_ref, sell_perm_ref,
                            delta16_layout_ref, delta16_offset_bits_ref, delta16_ref,
                            delta16_sliced_ref, merge_search_ref, merge_walk_ref,
                            partition_ref, slice_csr_ref, to_bf16_bits_ref, to_f32_ref)
@@ -503,3 +504,86 @@ def test_xblock_codes_span_bound():
     assert ok2 and span2 < 60000
     ok1, _, _, span1 = xblock_codes_ref(rp, ci, 120000, 1, 256)   # one slice of 120000
     assert not ok1 and span1 > 65535
+
+
+# ------------------------------------------------ the length-sorted sliced layout
+def test_sell_perm_by_hand():
+    """Longest first inside each window, ties in row order."""
+    rp = np.array([0, 1, 4, 6, 9])                      # lengths 1, 3, 2, 3
+    assert sell_perm_ref(rp, 4).tolist() == [1, 3, 2, 0]
+    assert sell_perm_ref(rp, 2).tolist() == [1, 0, 3, 2]
+    lens = np.arange(600) % 7                            # windows of 256 rows, then a partial one
+    rp = np.concatenate([[0], np.cumsum(lens)])
+    perm = sell_perm_ref(rp)
+    for w0 in (0, 256, 512):
+        rows = perm[w0:w0 + 256]
+        assert sorted(rows.tolist()) == list(range(w0, min(600, w0 + 256)))
+        key = [(-lens[i], i) for i in rows]
+        assert key == sorted(key)
+
+
+def _slots_for(rp, perm):
+    lens = np.diff(np.asarray(rp))[perm]
+    w = [int(lens[k:k + 64].max()) for k in range(0, len(lens), 64)]
+    return 64 * sum(x + x % 2 for x in w)
+
+
+def test_sorted_rows_minimise_padding():
+    """Sorting each window's rows by length gives the fewest slots of any
+    order of the rows inside their windows (the sum of the 64-row maxima of
+    a sorted sequence is minimal), and the layout's slot count is that sum."""
+    rng = np.random.default_rng(21)
+    for n in (64, 300, 700):
+        lens = rng.integers(0, 50, n)
+        rp = np.concatenate([[0], np.cumsum(lens)])
+        ci = np.concatenate([np.sort(rng.choice(400, l, replace=False)) for l in lens]).astype(np.int64)
+        L = delta16_sliced_ref(rp, ci, np.ones(len(ci)), sort_rows=True)
+        assert L["slots"] == _slots_for(rp, L["perm"])
+        assert not np.any(L["kind"])
+        for _ in range(30):
+            other = np.concatenate([rng.permutation(np.arange(w0, min(n, w0 + 256)))
+                                    for w0 in range(0, n, 256)])
+            assert L["slots"] <= _slots_for(rp, other)
+
+
+def test_sorted_layout_places_every_nonzero_once_and_sums_in_order():
+    """Every nonzero of the row at each position sits once at its slot with
+    its offset; summing a lane's positions in order is Algorithm 1's sum of
+    the row it holds; 8-bit codes decode back to every row."""
+    rng = np.random.default_rng(22)
+    mats = [synth.banded(700, 960, 32, seed=3), synth.short_rows(900, seed=4),
+            synth.powerlaw(800, 109, 300, seed=5), synth.uniform_random(300, 70000, 9, seed=6)]
+    for rp, ci, v in mats:
+        rp, ci, v = np.asarray(rp), np.asarray(ci), np.asarray(v)
+        n = len(rp) - 1
+        L = delta16_sliced_ref(rp, ci, v, sort_rows=True)
+        perm = L["perm"]
+        assert sorted(perm.tolist()) == list(range(n))
+        seen = np.zeros(L["slots"], dtype=bool)
+        x = rng.uniform(-1, 1, int(ci.max()) + 1)
+        y = np.zeros(n)
+        for p in range(n):
+            i, (s_, lane) = int(perm[p]), divmod(p, 64)
+            acc = 0.0
+            for k in range(rp[i + 1] - rp[i]):
+                slot = 128 * L["units"][s_] + 128 * (k // 2) + 2 * lane + k % 2
+                assert not seen[slot]
+                seen[slot] = True
+                assert L["vals"][slot] == v[rp[i] + k]
+                assert L["base"][s_] + L["off"][slot] == ci[rp[i] + k]
+                acc = acc + L["vals"][slot] * x[L["base"][s_] + L["off"][slot]]
+            y[i] = acc
+        assert not np.any(L["vals"][~seen]) and not np.any(L["off"][~seen])
+        assert np.array_equal(y, spmv_seq(rp, ci, v, x))
+        C = delta8_codes_ref(rp, ci, L)
+        rows = delta8_decode_ref(C["codes"], C["esc"], dict(L, eunits=C["eunits"]), np.diff(rp))
+        assert all(rows[i] == ci[rp[i]:rp[i + 1]].tolist() for i in range(n))
+
+
+def test_delta16_sort_rule():
+    n, nnz, ns = 1000, 20000, 16
+    assert not delta16_sort_ref(21000, 20000, 0, ns, nnz, n)      # padding 5%: not worth it
+    assert delta16_sort_ref(30000, 22000, 0, ns, nnz, n)          # saves 27% and 8 slots per row
+    assert not delta16_sort_ref(30000, 28600, 0, ns, nnz, n)      # saves under 5%
+    assert not delta16_sort_ref(30000, 22000, 1, ns, nnz, n)      # a diagonal slice in 16
+    assert not delta16_sort_ref(3000, 1900, 0, ns, 1500, n)       # 1.1 slots per row saved (short rows)
