@@ -273,6 +273,24 @@ spmv_status_t spmv_set_xblock_slices(spmv_plan_t plan, int32_t slices);
  * value; building reports SPMV_ERR_INFEASIBLE as for the variant. */
 spmv_status_t spmv_set_delta16_layout(spmv_plan_t plan, int32_t layout);
 
+/* Row order of the sliced DELTA16 layout.  Sorted (as in SELL-C-sigma): the
+ * rows of each window of 256 are placed by length, longest first (ties in
+ * row order), so that a 64-row slice holds rows of similar lengths and pads
+ * less; the kernel then reads the row index of each slice position (4 bytes
+ * per row) and writes y through it.  Only offset slices are formed (no
+ * diagonal slices), and a window lies inside one block of the streamed
+ * layout, so the 16-bit feasibility is unchanged.  A sorted slice spans
+ * its window's columns, so fewer slices stage x in LDS (an offset slice
+ * does when its span is under 512 columns and at most 32 w - 1 for width
+ * w).  -1 (default) sorts when at most 1% of the plain layout's slices are
+ * diagonal, its slots exceed 1.05 per nonzero, its staging slices hold under
+ * half of its offset-slice nonzeros, and sorting saves at least 5% of its
+ * slots and at least 2 slots per row; 0 never sorts, 1 always does (with
+ * the sliced layout).
+ * A built format is dropped and, if DELTA16 is the plan's variant, rebuilt
+ * (synchronous).  SPMV_ERR_ARG for any other value. */
+spmv_status_t spmv_set_delta16_sort(spmv_plan_t plan, int32_t mode);
+
 /* Column-code width of the sliced DELTA16 layout's offset slices, the same
  * for the whole matrix (Section 3.3 uses 8- or 16-bit deltas, never both).
  * 16: offsets c - ref from the slice's reference column (its smallest).
@@ -300,8 +318,9 @@ spmv_status_t spmv_variant_mask(spmv_plan_t plan, uint32_t *feasible_bits);
  * kind), 4 per offset slice (its column span) and 128 per diagonal slice
  * (its diagonals), with 1 or 2 index bytes (the code width) only for the
  * nonzeros of offset slices, plus with 8-bit codes 4 bytes per escaped
- * column and 4 per offset slice (its eunits entry) (a row's mask in a
- * diagonal slice takes the place of its row pointer).  The layout is
+ * column and 4 per offset slice (its eunits entry), and with sorted rows
+ * 4 per row (its index) (a row's mask in a diagonal slice takes the place
+ * of its row pointer).  The layout is
  * decided here if needed; the streamed form is counted where DELTA16 is
  * infeasible.  Traffic a variant adds on top (the XBLOCK_LDS slice row
  * pointers and partial y vectors, the sliced layout's padding slots, the
@@ -348,7 +367,8 @@ spmv_status_t spmv_time_variant_batch(spmv_plan_t plan, int32_t variant, int32_t
  * else 0, 22 1 if the current variant reads 16-bit column codes under the
  * index-coding request, 23 1 if the merge-path tiles' codes fit 16 bits,
  * 24 1 if the x-block slices' codes fit 16 bits, 25 rows per x-block code
- * block. */
+ * block, 26 1 if the sliced delta16 layout sorts rows by length (0 when it
+ * does not or the layout is streamed; -1 infeasible). */
 spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
 
 /* Copy a derived array to host memory (builds it if needed).  which:
@@ -373,11 +393,13 @@ spmv_status_t spmv_plan_query(spmv_plan_t plan, int32_t key, int64_t *value);
  * offset slice, 1 + D for a diagonal slice of D diagonals), 14 diagonals
  * int32[32 S] (slice s's sorted diagonals c - r from 32 s, zero-padded;
  * zeros for offset slices), 15 masks uint32[N] (bit k: the row has a
- * nonzero on diagonal k of its slice; 0 in offset slices).  Position k of
- * row 64 s + l is at slot 128 units[s] + 128 (k / 2) + 2 l + (k % 2), where
- * k counts the row's nonzeros in an offset slice and is the diagonal's index
- * in a diagonal slice; offsets are 0 in diagonal slices and every other slot
- * holds zero.
+ * nonzero on diagonal k of its slice; 0 in offset slices), 22 with sorted
+ * rows (key 26) the row at each slice position int32[N], else empty.
+ * Position k of the row at slice position 64 s + l (that row itself, or
+ * array 22's entry with sorted rows) is at slot 128 units[s] + 128 (k / 2) +
+ * 2 l + (k % 2), where k counts the row's nonzeros in an offset slice and
+ * is the diagonal's index in a diagonal slice; offsets are 0 in diagonal
+ * slices and every other slot holds zero.
  * Coded forms (spmv_set_index_coding): 18 merge-path tile reference columns
  * int32[tiles] (key 4), 19 merge-path codes uint16[NNZ] (column minus the
  * reference of the nonzero's tile), 20 x-block reference columns

@@ -303,18 +303,61 @@ def delta16_offset_bits_ref(nnz_offset: int, escape_units: int) -> int:
     return 8 if nnz_offset > 0 and 512 * escape_units <= nnz_offset else 16
 
 
-def delta16_sort_ref(slots: int, slots_sorted: int, ndiag: int, nslices: int, nnz: int, n: int) -> bool:
+SELL_X_WINDOW = 512  # x entries an offset slice can stage in LDS
+
+
+def sliced_stages_x_ref(span: int, width: int, slice_rows: int = SLICE_ROWS) -> bool:
+    """Whether an offset slice reads x from a staged copy of its column
+    window: its columns lie within SELL_X_WINDOW of its reference column and
+    its gathers (64 per pair of positions) number at least twice the window
+    it would load."""
+    return span < SELL_X_WINDOW and 2 * (span + 1) <= slice_rows * width
+
+
+def staged_nnz_ref(rowptr, L, slice_rows: int = SLICE_ROWS) -> int:
+    """Nonzeros of the offset slices of layout L that stage x."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    lens = np.diff(rowptr)[np.asarray(L["perm"], dtype=np.int64)]
+    total = 0
+    for s in range(len(L["width"])):
+        if L["kind"][s] == 0 and sliced_stages_x_ref(int(L["span"][s]), int(L["width"][s]), slice_rows):
+            total += int(lens[s * slice_rows:(s + 1) * slice_rows].sum())
+    return total
+
+
+def delta16_sort_ref(slots: int, slots_sorted: int, ndiag: int, nslices: int, nnz: int, n: int,
+                     staged_nnz: int = 0, nnz_offset: int = 1) -> bool:
     """Whether the sliced layout sorts its rows (``sell_perm_ref``).
 
-    Sorting gives up diagonal slices and costs a 4-byte row index per row
-    (the kernel reads the row it owns and stores y there), so it is taken
-    when the plain layout has at most 1% diagonal slices and over 5% of
-    padding, and sorting saves at least 5% of its slots and at least two
-    slots per row (9 or more bytes of values and codes against 4)."""
-    if ndiag * 100 > nslices or slots * 100 <= 105 * nnz:
+    Sorting gives up diagonal slices, widens each slice's column span to its
+    window's (so that a slice of a band may no longer stage x), and costs a
+    4-byte row index per row (the kernel reads the row it owns and stores y
+    there).  It is taken when the plain layout has at most 1% diagonal
+    slices, over 5% of padding, and stages x for fewer than half of its
+    offset nonzeros (``staged_nnz`` of ``nnz_offset``), and sorting saves at
+    least 5% of its slots and at least two slots per row (9 or more bytes of
+    values and codes against 4)."""
+    if ndiag * 100 > nslices or slots * 100 <= 105 * nnz or 2 * staged_nnz >= nnz_offset:
         return False
     saved = slots - slots_sorted
     return saved * 20 >= slots and saved >= 2 * n
+
+
+def delta16_sliced_auto_ref(rowptr, colind, val):
+    """The sliced layout under the automatic row order: the plain layout, or
+    the length-sorted one when ``delta16_sort_ref`` takes it.  Returns the
+    layout and whether it is sorted."""
+    L = delta16_sliced_ref(rowptr, colind, val)
+    n, nnz, ns = len(rowptr) - 1, len(colind), len(L["width"])
+    ndiag = int(np.count_nonzero(L["kind"]))
+    staged = staged_nnz_ref(rowptr, L)
+    if (n == 0 or ndiag * 100 > ns or L["slots"] * 100 <= 105 * nnz
+            or 2 * staged >= L["nnz_offset"]):
+        return L, False  # the rule declines before the sorted layout is needed
+    Ls = delta16_sliced_ref(rowptr, colind, val, sort_rows=True)
+    if delta16_sort_ref(L["slots"], Ls["slots"], ndiag, ns, nnz, n, staged, L["nnz_offset"]):
+        return Ls, True
+    return L, False
 
 
 def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int, n: int) -> int:

@@ -72,6 +72,7 @@ _PROTOS = {
     "spmv_variant_mask": (_I32, [_P, _PU32]),
     "spmv_set_xblock_slices": (_I32, [_P, _I32]),
     "spmv_set_delta16_layout": (_I32, [_P, _I32]),
+    "spmv_set_delta16_sort": (_I32, [_P, _I32]),
     "spmv_set_delta16_offset_bits": (_I32, [_P, _I32]),
     "spmv_bytes": (_I32, [_P, _I32, _PI64]),
     "spmv_time_variant": (_I32, [_P, _I32, _I32, _I32, _PF64, _PF64]),
@@ -227,6 +228,10 @@ def spmv_set_delta16_layout(plan, layout: int):
     _check("spmv_set_delta16_layout", lib.spmv_set_delta16_layout(plan, layout))
 
 
+def spmv_set_delta16_sort(plan, mode: int):
+    _check("spmv_set_delta16_sort", lib.spmv_set_delta16_sort(plan, mode))
+
+
 def spmv_set_delta16_offset_bits(plan, bits: int):
     _check("spmv_set_delta16_offset_bits", lib.spmv_set_delta16_offset_bits(plan, bits))
 
@@ -267,7 +272,8 @@ def spmv_plan_query(plan, key: int) -> int:
 _FORMAT_DTYPES = {0: np.int32, 1: np.uint16, 2: np.int32, 3: np.int32, 4: np.int32,
                   5: np.int32, 6: np.int32, 7: np.int32, 8: np.int32, 9: np.int32, 10: np.int32,
                   11: np.uint16, 13: np.int32, 14: np.int32, 15: np.uint32, 16: np.int32,
-                  17: np.int32, 18: np.int32, 19: np.uint16, 20: np.int32, 21: np.uint16}
+                  17: np.int32, 18: np.int32, 19: np.uint16, 20: np.int32, 21: np.uint16,
+                  22: np.int32}
 
 
 def spmv_plan_copy_format(plan, which: int, count: int, dtype=None) -> np.ndarray:
@@ -556,6 +562,9 @@ class Plan:
 
     def set_delta16_layout(self, layout):
         spmv_set_delta16_layout(self.handle, layout)
+
+    def set_delta16_sort(self, mode):
+        spmv_set_delta16_sort(self.handle, mode)
 
     def set_delta16_offset_bits(self, bits):
         spmv_set_delta16_offset_bits(self.handle, bits)

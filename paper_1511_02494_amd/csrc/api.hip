@@ -360,9 +360,13 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     DevBuf &span = P->d16s_span;
     SPMV_TRY(halfw.alloc(nb));
     SPMV_TRY(span.alloc(nb));
-    int64_t units = 0, nnz_off = 0, ndiag = 0, max_span = 0;
-    if (nsl > 0) {
-        SPMV_HIP(launch_sliced_shape(*P, P->d16s_width.as<int32_t>(), halfw.as<int32_t>(),
+    int64_t units = 0, nnz_off = 0, ndiag = 0, max_span = 0, staged_nnz = 0;
+    // the slices' shape (widths, references, kinds, spans) and unit offsets,
+    // of the plain layout or, with perm, of the length-sorted one
+    auto shape = [&](const int32_t *perm) -> spmv_status_t {
+        units = nnz_off = ndiag = max_span = staged_nnz = 0;
+        if (nsl == 0) return SPMV_OK;
+        SPMV_HIP(launch_sliced_shape(*P, perm, P->d16s_width.as<int32_t>(), halfw.as<int32_t>(),
                                      P->d16s_base.as<int32_t>(), P->d16s_kind.as<int32_t>(),
                                      P->d16s_diag.as<int32_t>(), P->d16s_nnz.as<int32_t>(),
                                      span.as<int32_t>(), S(P)));
@@ -374,8 +378,10 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
         SPMV_HIP(launch_exclusive_scan_i32(halfw.as<int32_t>(), P->d16s_units.as<int32_t>(), nsl, 1,
                                            dtot, tmp.p, tmp.bytes, S(P), nullptr));
         SPMV_HIP(hipMemcpyAsync(P->h_pinned, dtot, 8, hipMemcpyDeviceToHost, S(P)));
-        std::vector<int32_t> kinds((size_t)nsl), counts((size_t)nsl), spans((size_t)nsl);
+        std::vector<int32_t> kinds((size_t)nsl), counts((size_t)nsl), spans((size_t)nsl),
+            widths((size_t)nsl);
         SPMV_HIP(hipMemcpyAsync(kinds.data(), P->d16s_kind.p, nb, hipMemcpyDeviceToHost, S(P)));
+        SPMV_HIP(hipMemcpyAsync(widths.data(), P->d16s_width.p, nb, hipMemcpyDeviceToHost, S(P)));
         SPMV_HIP(hipMemcpyAsync(counts.data(), P->d16s_nnz.p, nb, hipMemcpyDeviceToHost, S(P)));
         SPMV_HIP(hipMemcpyAsync(spans.data(), span.p, nb, hipMemcpyDeviceToHost, S(P)));
         SPMV_TRY(sync(P));
@@ -386,7 +392,42 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
             } else {
                 nnz_off += counts[k];
                 if (spans[k] > max_span) max_span = spans[k];
+                if (sell_stages_x(spans[k], widths[k])) staged_nnz += counts[k];
             }
+        }
+        return SPMV_OK;
+    };
+    SPMV_TRY(shape(nullptr));
+    // Length-sorted rows (rows sorted by length inside each 256-row window,
+    // as in SELL-C-sigma): taken when requested, or automatically when the
+    // plain layout has at most 1% diagonal slices, over 5% of padding and
+    // stages x in LDS for under half of its offset nonzeros (a sorted slice
+    // spans its window's columns, up to 192 more than a plain one, and loses
+    // the staging that plain bands keep), and sorting saves at least 5% of
+    // its slots and two slots per row (the sorted kernel reads a 4-byte row
+    // index per row).  A window lies inside one block of the streamed
+    // layout, so its slices stay within 16 bits.
+    P->d16_sort = 0;
+    P->d16s_perm.release();
+    P->d16s_pinv.release();
+    const int64_t plain_slots = units * 2 * kSellRows;
+    const bool consider =
+        P->d16_layout_req != 0 &&
+        (P->d16_sort_req == 1 ||
+         (P->d16_sort_req < 0 && ndiag * 100 <= nsl && plain_slots * 100 > 105 * P->nnz &&
+          staged_nnz * 2 < nnz_off));
+    if (consider && P->n > 0) {
+        SPMV_TRY(P->d16s_perm.alloc((size_t)P->n * 4));
+        SPMV_TRY(P->d16s_pinv.alloc((size_t)P->n * 4));
+        SPMV_HIP(launch_sell_perm(*P, P->d16s_perm.as<int32_t>(), P->d16s_pinv.as<int32_t>(), S(P)));
+        SPMV_TRY(shape(P->d16s_perm.as<int32_t>()));
+        const int64_t saved = plain_slots - units * 2 * kSellRows;
+        if (P->d16_sort_req == 1 || (saved * 20 >= plain_slots && saved >= 2 * P->n)) {
+            P->d16_sort = 1;
+        } else {
+            P->d16s_perm.release();
+            P->d16s_pinv.release();
+            SPMV_TRY(shape(nullptr));
         }
     }
     P->d16_nnz_off = nnz_off;
@@ -454,6 +495,9 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
         P->d16s_kind.release();
         P->d16s_diag.release();
         P->d16s_span.release();
+        P->d16s_perm.release();
+        P->d16s_pinv.release();
+        P->d16_sort = 0;
     }
     return SPMV_OK;
 }
@@ -763,6 +807,7 @@ spmv_status_t build_format(spmv_plan *P, int v) {
                 P->d16s_esc.release();
             }
             SPMV_TRY(sync(P));
+            P->d16s_pinv.release();  // the scatter's; the layout is decided again before any rebuild
             P->d16_built = true;
             return SPMV_OK;
         }
@@ -1419,7 +1464,8 @@ spmv_status_t spmv_bytes(spmv_plan_t P, int32_t v, int64_t *bytes) {
             const int64_t n_off = P->d16_nsl - P->d16_ndiag;
             *bytes = 4 * (P->n + 1) + vb * P->nnz + (d8 ? 1 : 2) * P->d16_nnz_off +
                      (d8 ? 4 * P->d16_nesc + 4 * n_off : 0) + xb * P->m + xb * P->n +
-                     16 * P->d16_nsl + 4 * n_off + 4 * kSellMaxDiag * P->d16_ndiag;
+                     16 * P->d16_nsl + 4 * n_off + 4 * kSellMaxDiag * P->d16_ndiag +
+                     (P->d16_sort ? 4 * P->n : 0);  // the sorted layout's row index per row
             return SPMV_OK;
         }
         extra = 4 * ((P->n + P->d16_rows - 1) / P->d16_rows);
@@ -1521,6 +1567,12 @@ spmv_status_t spmv_plan_query(spmv_plan_t P, int32_t key, int64_t *value) {
         *value = P->xsc_feasible;
         break;
     case 25: SPMV_TRY(build_xslices(P)); SPMV_TRY(check_xblock_codes(P)); *value = P->xsc_h; break;
+    case 26:
+        SPMV_TRY(check_d16(P));
+        if (!d16_feasible(P)) { *value = -1; break; }
+        SPMV_TRY(d16_decide_layout(P));
+        *value = P->d16_layout == 1 ? P->d16_sort : 0;
+        break;
     default: return fail(SPMV_ERR_ARG, "unknown key %d", key);
     }
     return SPMV_OK;
@@ -1532,7 +1584,7 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
     const void *src = nullptr;
     int64_t want = 0;
     switch (which) {
-    case 8: case 9: case 10: case 11: case 12: case 13: case 14: case 15: case 16: case 17:
+    case 8: case 9: case 10: case 11: case 12: case 13: case 14: case 15: case 16: case 17: case 22:
         SPMV_TRY(build_format(P, V_DELTA16));
         if (P->d16_layout != 1) return fail(SPMV_ERR_ARG, "delta16 is not in the sliced layout");
         switch (which) {
@@ -1548,6 +1600,7 @@ spmv_status_t spmv_plan_copy_format(spmv_plan_t P, int32_t which, void *dst, int
         case 12: src = P->d16s_val.p; want = vbytes(P->dtype) * P->d16_slots; break;
         case 13: src = P->d16s_kind.p; want = 4 * P->d16_nsl; break;
         case 14: src = P->d16s_diag.p; want = 4 * kSellMaxDiag * P->d16_nsl; break;
+        case 22: src = P->d16s_perm.p; want = P->d16_sort ? 4 * P->n : 0; break;
         default: src = P->d16s_mask.p; want = 4 * P->n; break;
         }
         break;
@@ -1866,14 +1919,8 @@ spmv_status_t spmv_set_xblock_slices(spmv_plan_t P, int32_t slices) {
     return SPMV_OK;
 }
 
-spmv_status_t spmv_set_delta16_layout(spmv_plan_t P, int32_t layout) {
-    clear_error();
-    if (!P) return fail(SPMV_ERR_ARG, "NULL plan");
-    if (layout < -1 || layout > 1)
-        return fail(SPMV_ERR_ARG, "delta16 layout must be -1 (automatic), 0 or 1, not %d", layout);
-    if (layout == P->d16_layout_req) return SPMV_OK;
-    SPMV_TRY(sync(P));
-    P->d16_layout_req = layout;
+// Drops every delta16 array so that the next use builds the format again.
+static void release_d16(spmv_plan *P) {
     P->d16_layout = -1;
     P->d16_built = false;
     P->srow_coded_built = false;
@@ -1889,7 +1936,34 @@ spmv_status_t spmv_set_delta16_layout(spmv_plan_t P, int32_t layout) {
     P->d16s_mask.release();
     P->d16s_esc.release();
     P->d16s_eunits.release();
+    P->d16s_perm.release();
+    P->d16s_pinv.release();
+    P->d16_sort = 0;
+}
+
+spmv_status_t spmv_set_delta16_layout(spmv_plan_t P, int32_t layout) {
+    clear_error();
+    if (!P) return fail(SPMV_ERR_ARG, "NULL plan");
+    if (layout < -1 || layout > 1)
+        return fail(SPMV_ERR_ARG, "delta16 layout must be -1 (automatic), 0 or 1, not %d", layout);
+    if (layout == P->d16_layout_req) return SPMV_OK;
+    SPMV_TRY(sync(P));
+    P->d16_layout_req = layout;
+    release_d16(P);
     if (P->variant == V_DELTA16) SPMV_TRY(build_format(P, V_DELTA16));  // else on next use
+    return SPMV_OK;
+}
+
+spmv_status_t spmv_set_delta16_sort(spmv_plan_t P, int32_t mode) {
+    clear_error();
+    if (!P) return fail(SPMV_ERR_ARG, "NULL plan");
+    if (mode < -1 || mode > 1)
+        return fail(SPMV_ERR_ARG, "delta16 row sorting must be -1 (automatic), 0 or 1, not %d", mode);
+    if (mode == P->d16_sort_req) return SPMV_OK;
+    SPMV_TRY(sync(P));
+    P->d16_sort_req = mode;
+    release_d16(P);
+    if (P->variant == V_DELTA16) SPMV_TRY(build_format(P, V_DELTA16));
     return SPMV_OK;
 }
 

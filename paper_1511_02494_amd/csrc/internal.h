@@ -34,6 +34,13 @@ constexpr double kSellMaxPad = 1.35;  // ... taken when its slots are at most th
 constexpr double kSellMaxPadLong = 1.5;  // or this many when the mean row has
 constexpr int kSellLongMean = 16;        // at least this many nonzeros
 constexpr int kSellMaxDiag = 32;         // diagonals a diagonal slice can hold (mask bits)
+constexpr int kSellXWindow = 512;        // x entries an offset slice can stage in LDS
+// An offset slice of width w whose columns lie within kSellXWindow of its
+// reference column and whose gathers number at least twice its column span
+// reads x from a copy of that window in LDS.
+__host__ __device__ inline bool sell_stages_x(int span, int w) {
+    return span < kSellXWindow && 2 * (span + 1) <= kSellRows * w;
+}
 constexpr int kLineBytes = 128;       // cache line assumed by the miss feature
 constexpr int64_t kLlcBytes = 256ll << 20;
 constexpr int kFeatBlocks = 1024;     // feature kernel partial records
@@ -143,6 +150,11 @@ struct spmv_plan {
     // diagonals (listed in d16s_diag[32 s .. 32 s + D)); one mask per row
     spmvsel::DevBuf d16s_kind, d16s_diag, d16s_mask, d16s_nnz;
     spmvsel::DevBuf d16s_span;  // per slice: largest offset from its reference column
+    // length-sorted sliced layout: the row at each position (perm) and the
+    // position of each row (pinv, until the layout is built); requested
+    // -1 automatic, 0 plain, 1 sorted
+    spmvsel::DevBuf d16s_perm, d16s_pinv;
+    int d16_sort_req = -1, d16_sort = 0;
     bool mp_built = false;
     int64_t mp_tiles = 0;
     spmvsel::DevBuf mp_split_row, mp_split_nnz, mp_carry_row, mp_carry_val;
@@ -251,9 +263,11 @@ hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16
 // kSellMaxDiag and, rounded up to even, its offset width, lists them in
 // diag[32 s ..] (kind = 1 + D) and sets bit k of a row's mask for each
 // diagonal k the row has; its positions follow the diagonals, not the row.
-hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
-                               int32_t *kind, int32_t *diag, int32_t *snnz, int32_t *span,
-                               hipStream_t s);
+hipError_t launch_sliced_shape(const spmv_plan &P, const int32_t *perm, int32_t *width,
+                               int32_t *halfw, int32_t *base, int32_t *kind, int32_t *diag,
+                               int32_t *snnz, int32_t *span, hipStream_t s);
+// the row order of the length-sorted sliced layout (windows of kBlock rows)
+hipError_t launch_sell_perm(const spmv_plan &P, int32_t *perm, int32_t *pinv, hipStream_t s);
 // values, masks, and the 16-bit offsets or the 8-bit codes (off or codes
 // null: not written)
 hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const int32_t *base,

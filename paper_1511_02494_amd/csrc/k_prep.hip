@@ -48,6 +48,7 @@ hipError_t launch_delta16_encode(const spmv_plan &P, const int32_t *base, uint16
 __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
                                                          const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci,
+                                                         const int32_t *__restrict__ perm,
                                                          int32_t *__restrict__ width,
                                                          int32_t *__restrict__ halfw,
                                                          int32_t *__restrict__ base,
@@ -61,9 +62,11 @@ __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
     const int64_t sl = blockIdx.x * (int64_t)kWaves + wv;
     const bool live = sl < nsl;  // (no early exit: every thread reaches the barrier)
     const int lane = threadIdx.x & (kSellRows - 1);
-    const int64_t r = sl * kSellRows + lane;
+    const int64_t pos = sl * kSellRows + lane;
+    // the row at this position (sorted layout: perm; else the position)
+    const int64_t r = perm && live && pos < n ? perm[pos] : pos;
     int32_t a = 0, e = 0;
-    if (live && r < n) {
+    if (live && pos < n) {
         a = rp[r];
         e = rp[r + 1];
     }
@@ -81,8 +84,9 @@ __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
     }
     const int w_off = len + (len & 1);
     // A slice with a row longer than 32 has more than 32 diagonals.  Else its
-    // nonzeros (at most 64 x 32) are staged in LDS with coalesced loads.
-    const bool maybe = live && len <= kSellMaxDiag;
+    // nonzeros (at most 64 x 32) are staged in LDS with coalesced loads.  The
+    // sorted layout has offset slices only.
+    const bool maybe = live && len <= kSellMaxDiag && !perm;
     const int32_t A = live ? rp[sl * kSellRows] : 0;
     const int32_t E = live ? rp[(sl + 1) * kSellRows < n ? (sl + 1) * kSellRows : n] : 0;
     if (maybe)
@@ -124,14 +128,46 @@ __global__ __launch_bounds__(kBlock) void k_sliced_shape(int64_t n, int64_t nsl,
     }
 }
 
-hipError_t launch_sliced_shape(const spmv_plan &P, int32_t *width, int32_t *halfw, int32_t *base,
-                               int32_t *kind, int32_t *diag, int32_t *snnz, int32_t *span,
-                               hipStream_t s) {
+hipError_t launch_sliced_shape(const spmv_plan &P, const int32_t *perm, int32_t *width,
+                               int32_t *halfw, int32_t *base, int32_t *kind, int32_t *diag,
+                               int32_t *snnz, int32_t *span, hipStream_t s) {
     const int64_t nsl = (P.n + kSellRows - 1) / kSellRows;
     if (nsl == 0) return hipSuccess;
     const int64_t per = kBlock / kSellRows;
     hipLaunchKernelGGL(k_sliced_shape, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0, s,
-                       P.n, nsl, P.rowptr, P.colind, width, halfw, base, kind, diag, snnz, span);
+                       P.n, nsl, P.rowptr, P.colind, perm, width, halfw, base, kind, diag, snnz,
+                       span);
+    return hipGetLastError();
+}
+
+// Row order of the length-sorted sliced layout: inside each window of
+// kBlock rows, the rows by decreasing length, ties in row order (a row's
+// position is the number of rows of its window that come before it).
+// perm[p] = the row at position p, pinv[r] = the position of row r.
+__global__ __launch_bounds__(kBlock) void k_sell_perm(int64_t n, const int32_t *__restrict__ rp,
+                                                      int32_t *__restrict__ perm,
+                                                      int32_t *__restrict__ pinv) {
+    __shared__ int32_t s_len[kBlock];
+    const int64_t r0 = (int64_t)blockIdx.x * kBlock;
+    const int t = threadIdx.x;
+    const int64_t r = r0 + t;
+    const int32_t mine = r < n ? rp[r + 1] - rp[r] : -1;  // past the end: after every row
+    s_len[t] = mine;
+    __syncthreads();
+    if (r >= n) return;
+    int rank = 0;
+    for (int u = 0; u < kBlock; ++u) {
+        const int32_t l = s_len[u];
+        rank += (l > mine || (l == mine && u < t)) ? 1 : 0;
+    }
+    perm[r0 + rank] = (int32_t)r;
+    pinv[r] = (int32_t)(r0 + rank);
+}
+
+hipError_t launch_sell_perm(const spmv_plan &P, int32_t *perm, int32_t *pinv, hipStream_t s) {
+    if (P.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sell_perm, dim3((unsigned)((P.n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, P.n, P.rowptr, perm, pinv);
     return hipGetLastError();
 }
 
@@ -153,7 +189,8 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
                                                            uint16_t *__restrict__ off,
                                                            uint8_t *__restrict__ codes,
                                                            V *__restrict__ vals,
-                                                           uint32_t *__restrict__ mask) {
+                                                           uint32_t *__restrict__ mask,
+                                                           const int32_t *__restrict__ pinv) {
     constexpr int kWaves = kBlock / kSellRows;
     __shared__ int32_t s_rp[kBlock + 1];
     __shared__ int32_t s_dg[kWaves][kSellMaxDiag];
@@ -178,8 +215,11 @@ __global__ __launch_bounds__(kBlock) void k_sliced_scatter(int64_t n, const int3
             const int mid = (lo + hi + 1) >> 1;
             if (s_rp[mid] <= j) lo = mid; else hi = mid - 1;
         }
-        const int ls = lo / kSellRows;  // the slice within the block
-        const int lane = lo % kSellRows;
+        // the row's position within the block (the sorted layout permutes the
+        // rows of each block), then its slice within the block and lane
+        const int q = pinv ? (int)(pinv[r0 + lo] - r0) : lo;
+        const int ls = q / kSellRows;
+        const int lane = q % kSellRows;
         const int64_t sl = sl0 + ls;
         const int kd = s_kind[ls];
         int k = j - s_rp[lo];
@@ -214,21 +254,22 @@ hipError_t launch_sliced_scatter(const spmv_plan &P, const int32_t *units, const
                                  uint8_t *codes, void *vals, uint32_t *mask, hipStream_t s) {
     if (P.n == 0) return hipSuccess;  // (with no nonzeros it still writes the zero masks)
     const dim3 g((unsigned)((P.n + kBlock - 1) / kBlock));
+    const int32_t *pinv = P.d16_sort ? P.d16s_pinv.as<int32_t>() : nullptr;
     switch (P.dtype) {
     case SPMV_F64:
         hipLaunchKernelGGL(k_sliced_scatter<double>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
                            (const double *)P.val, units, base, kind, diag, off, codes, (double *)vals,
-                           mask);
+                           mask, pinv);
         break;
     case SPMV_F32:
         hipLaunchKernelGGL(k_sliced_scatter<float>, g, dim3(kBlock), 0, s, P.n, P.rowptr, P.colind,
                            (const float *)P.val, units, base, kind, diag, off, codes, (float *)vals,
-                           mask);
+                           mask, pinv);
         break;
     default:
         hipLaunchKernelGGL(k_sliced_scatter<uint16_t>, g, dim3(kBlock), 0, s, P.n, P.rowptr,
                            P.colind, (const uint16_t *)P.val, units, base, kind, diag, off,
-                           codes, (uint16_t *)vals, mask);
+                           codes, (uint16_t *)vals, mask, pinv);
     }
     return hipGetLastError();
 }
@@ -253,14 +294,16 @@ __global__ __launch_bounds__(kBlock) void k_sliced_escapes(int64_t n, int64_t ns
                                                            const int32_t *__restrict__ ci,
                                                            const int32_t *__restrict__ base,
                                                            const int32_t *__restrict__ kind,
+                                                           const int32_t *__restrict__ perm,
                                                            int32_t *__restrict__ E,
                                                            int32_t *__restrict__ nesc) {
     const int64_t sl = blockIdx.x * (int64_t)(kBlock / kSellRows) + threadIdx.x / kSellRows;
     if (sl >= nsl) return;
     const int lane = threadIdx.x & (kSellRows - 1);
-    const int64_t r = sl * kSellRows + lane;
+    const int64_t pos = sl * kSellRows + lane;
+    const int64_t r = perm && pos < n ? perm[pos] : pos;  // the row at this position
     int cnt = 0;
-    if (kind[sl] == 0 && r < n) {
+    if (kind[sl] == 0 && pos < n) {
         int32_t prev = base[sl];  // the slice's smallest column: no gap is negative
         int32_t j = rp[r];
         const int32_t b = rp[r + 1];
@@ -297,12 +340,14 @@ __global__ __launch_bounds__(kBlock) void k_sliced_escape_cols(int64_t n, int64_
                                                                const int32_t *__restrict__ base,
                                                                const int32_t *__restrict__ kind,
                                                                const int32_t *__restrict__ eunits,
+                                                               const int32_t *__restrict__ perm,
                                                                int32_t *__restrict__ esc) {
     const int64_t sl = blockIdx.x * (int64_t)(kBlock / kSellRows) + threadIdx.x / kSellRows;
     if (sl >= nsl || kind[sl] != 0 || eunits[sl + 1] == eunits[sl]) return;
     const int lane = threadIdx.x & (kSellRows - 1);
-    const int64_t r = sl * kSellRows + lane;
-    if (r >= n) return;
+    const int64_t pos = sl * kSellRows + lane;
+    if (pos >= n) return;
+    const int64_t r = perm ? perm[pos] : pos;  // the row at this position
     int64_t q = (int64_t)kSellRows * eunits[sl] + lane;  // this lane's next escape entry
     int32_t prev = base[sl];
     for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
@@ -321,7 +366,8 @@ hipError_t launch_sliced_escapes(const spmv_plan &P, const int32_t *base, const 
     if (nsl == 0) return hipSuccess;
     const int64_t per = kBlock / kSellRows;
     hipLaunchKernelGGL(k_sliced_escapes, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0,
-                       s, P.n, nsl, P.rowptr, P.colind, base, kind, E, nesc);
+                       s, P.n, nsl, P.rowptr, P.colind, base, kind,
+                       P.d16_sort ? P.d16s_perm.as<int32_t>() : nullptr, E, nesc);
     return hipGetLastError();
 }
 
@@ -331,7 +377,8 @@ hipError_t launch_sliced_escape_cols(const spmv_plan &P, const int32_t *base, co
     if (nsl == 0) return hipSuccess;
     const int64_t per = kBlock / kSellRows;
     hipLaunchKernelGGL(k_sliced_escape_cols, dim3((unsigned)((nsl + per - 1) / per)), dim3(kBlock), 0,
-                       s, P.n, nsl, P.rowptr, P.colind, base, kind, eunits, esc);
+                       s, P.n, nsl, P.rowptr, P.colind, base, kind, eunits,
+                       P.d16_sort ? P.d16s_perm.as<int32_t>() : nullptr, esc);
     return hipGetLastError();
 }
 

@@ -229,7 +229,8 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     const int32_t *__restrict__ width, const int32_t *__restrict__ units,
     const int32_t *__restrict__ base, const int32_t *__restrict__ kind,
     const int32_t *__restrict__ diag, const uint32_t *__restrict__ mask,
-    const int32_t *__restrict__ span, const O *__restrict__ off, const int32_t *__restrict__ eunits,
+    const int32_t *__restrict__ span, const int32_t *__restrict__ perm,
+    const O *__restrict__ off, const int32_t *__restrict__ eunits,
     const int32_t *__restrict__ esc, const V *__restrict__ val,
     const typename VT<V>::A *__restrict__ x, typename VT<V>::A *__restrict__ y, int kmin) {
     using A = typename VT<V>::A;
@@ -239,7 +240,10 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
                        __builtin_amdgcn_readfirstlane(threadIdx.x / kSellRows);
     if (sl >= nsl) return;  // whole wavefronts leave together
     const int lane = threadIdx.x & (kSellRows - 1);
-    const int64_t r = sl * kSellRows + lane;
+    // the row this lane owns: the position's, or the one the length-sorted
+    // layout put there (that layout has offset slices only)
+    const int64_t pos = sl * kSellRows + lane;
+    const int64_t r = perm && pos < n ? perm[pos] : pos;
     const int w = width[sl];
     const int64_t o = 2 * kSellRows * (int64_t)units[sl] + 2 * lane;
     if (kind[sl] > 0) {
@@ -315,17 +319,16 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
         ep = esc + (int64_t)kSellRows * eunits[sl] + lane;
         oq = 2 * kSellRows * ((int64_t)units[sl] + sl) + 4 * lane;
     }
-    // x staging: a slice whose columns lie within kXs of its reference
-    // column (and whose gathers number at least twice the window) reads x
-    // from a copy of the window in LDS, loaded coalesced.  Band matrices
-    // keep the vector memory path's address unit 90% busy with their x
-    // gathers otherwise; from LDS they run 8-20% faster (half widths 16 to
-    // 200).  16 KiB per workgroup leaves the occupancy at 8 waves per SIMD.
-    constexpr int kXs = 512;
+    // x staging (sell_stages_x): the slice reads x from a copy of its
+    // column window in LDS, loaded coalesced.  Band matrices keep the vector
+    // memory path's address unit 90% busy with their x gathers otherwise;
+    // from LDS they run 8-20% faster (half widths 16 to 200).  16 KiB per
+    // workgroup leaves the occupancy at 8 waves per SIMD.
+    constexpr int kXs = kSellXWindow;
     __shared__ A xs[kBlock / kSellRows][kXs];
     const int wv = threadIdx.x / kSellRows;
     const int sp = span[sl];
-    const bool staged = sp < kXs && 2 * (sp + 1) <= kSellRows * w;
+    const bool staged = sell_stages_x(sp, w);
     auto run = [&](auto st) {
         constexpr bool ST = decltype(st)::value;
         A *xw = &xs[wv][0];
@@ -976,12 +979,13 @@ hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStre
         using A = typename VT<V>::A;
         const int64_t per = kBlock / kSellRows;
         const unsigned g = (unsigned)((P.d16_nsl + per - 1) / per);
+        const int32_t *perm = P.d16_sort ? P.d16s_perm.as<int32_t>() : nullptr;
         if (P.d16_offw == 8)
             hipLaunchKernelGGL((k_sliced_d16<V, uint8_t>), dim3(g), dim3(kBlock), 0, s, P.n, P.m,
                                P.d16_nsl, P.rowptr, P.d16s_width.as<int32_t>(),
                                P.d16s_units.as<int32_t>(), P.d16s_base.as<int32_t>(),
                                P.d16s_kind.as<int32_t>(), P.d16s_diag.as<int32_t>(),
-                               P.d16s_mask.as<uint32_t>(), P.d16s_span.as<int32_t>(), P.d16s_off.as<uint8_t>(),
+                               P.d16s_mask.as<uint32_t>(), P.d16s_span.as<int32_t>(), perm, P.d16s_off.as<uint8_t>(),
                                P.d16s_eunits.as<int32_t>(), P.d16s_esc.as<int32_t>(),
                                P.d16s_val.as<V>(), (const A *)x, (A *)y, P.kahan_min);
         else
@@ -989,7 +993,7 @@ hipError_t launch_sliced_d16(const spmv_plan &P, const void *x, void *y, hipStre
                                P.d16_nsl, P.rowptr, P.d16s_width.as<int32_t>(),
                                P.d16s_units.as<int32_t>(), P.d16s_base.as<int32_t>(),
                                P.d16s_kind.as<int32_t>(), P.d16s_diag.as<int32_t>(),
-                               P.d16s_mask.as<uint32_t>(), P.d16s_span.as<int32_t>(), P.d16s_off.as<uint16_t>(),
+                               P.d16s_mask.as<uint32_t>(), P.d16s_span.as<int32_t>(), perm, P.d16s_off.as<uint16_t>(),
                                nullptr, nullptr, P.d16s_val.as<V>(), (const A *)x, (A *)y,
                                P.kahan_min);
         return hipGetLastError();

@@ -7,8 +7,9 @@ import pytest
 import synth
 import paper_1511_02494_amd as S
 from oracle.encode import (delta8_codes_ref, delta16_layout_ref, delta16_offset_bits_ref,
-                           delta16_ref, delta16_sliced_ref, merge_search_ref, merge_walk_ref,
-                           partition_ref, xblock_split_ref, to_bf16_bits_ref, to_f32_ref)
+                           delta16_ref, delta16_sliced_auto_ref, delta16_sliced_ref,
+                           merge_search_ref, merge_walk_ref, partition_ref, xblock_split_ref,
+                           to_bf16_bits_ref, to_f32_ref)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -37,17 +38,27 @@ def test_formats_match_oracle(name, build, m):
         pytest.fail("delta16 should have retried with 256-row blocks")
     assert S.spmv_plan_query(h, 9) == int(ok)
     if ok:
-        L = delta16_sliced_ref(rp, ci, v)
+        L, srt = delta16_sliced_auto_ref(rp, ci, v)  # the row order the rule takes
+        print(f"case={name} sorted={srt} slots={L['slots']}", flush=True)
         assert S.spmv_plan_query(h, 14) == delta16_layout_ref(True, L["slots"], nnz, n)
         assert S.spmv_plan_query(h, 15) == L["slots"]
         S.spmv_set_delta16_layout(h, 0)
         assert S.spmv_plan_query(h, 14) == 0
+        assert S.spmv_plan_query(h, 26) == 0
         assert np.array_equal(S.spmv_plan_copy_format(h, 0, len(base)), base)
         assert np.array_equal(S.spmv_plan_copy_format(h, 1, nnz), off)
         S.spmv_set_delta16_layout(h, 1)
-        bits = check_sliced(h, rp, ci, L, np.float64)
+        bits = check_sliced(h, rp, ci, L, np.float64, srt=srt)
         assert S.spmv_bytes(h, S.V_DELTA16) == sliced_bytes(L, delta8_codes_ref(rp, ci, L), bits,
-                                                            n, m, nnz)
+                                                            n, m, nnz, srt)
+        for mode in (1 - int(srt), int(srt)):  # the other order forced, then this one
+            S.spmv_set_delta16_sort(h, mode)
+            Lm = delta16_sliced_ref(rp, ci, v, sort_rows=bool(mode))
+            bits = check_sliced(h, rp, ci, Lm, np.float64, srt=bool(mode))
+            assert S.spmv_bytes(h, S.V_DELTA16) == sliced_bytes(Lm, delta8_codes_ref(rp, ci, Lm),
+                                                                bits, n, m, nnz, bool(mode))
+        S.spmv_set_delta16_sort(h, -1)
+        assert S.spmv_plan_query(h, 26) == int(srt)
     else:
         assert S.spmv_plan_query(h, 14) == -1
     T = S.spmv_plan_query(h, 3)
@@ -75,20 +86,25 @@ def test_formats_match_oracle(name, build, m):
     plan.close()
 
 
-def sliced_bytes(L, C, bits, n, m, nnz):
+def sliced_bytes(L, C, bits, n, m, nnz, srt=False):
     """Compulsory bytes: no codes in diagonal slices, their diagonals once;
     a column span per offset slice; 8-bit codes add their escaped columns
-    and a first escape unit per offset slice."""
+    and a first escape unit per offset slice; sorted rows a row index each."""
     ns = len(L["width"])
     n_off = ns - int(np.count_nonzero(L["kind"]))
     codes = L["nnz_offset"] * (1 if bits == 8 else 2) + (4 * C["escapes"] + 4 * n_off if bits == 8 else 0)
     return (4 * (n + 1) + 8 * nnz + codes + 8 * m + 8 * n + 16 * ns + 4 * n_off
-            + 128 * int(np.count_nonzero(L["kind"])))
+            + 128 * int(np.count_nonzero(L["kind"])) + (4 * n if srt else 0))
 
 
-def check_sliced(h, rp, ci, L, vdtype, bits=None):
+def check_sliced(h, rp, ci, L, vdtype, bits=None, srt=False):
     """The plan's sliced arrays against the oracle; returns the code width."""
     ns = len(L["width"])
+    assert S.spmv_plan_query(h, 26) == int(srt)
+    if srt:
+        assert np.array_equal(S.spmv_plan_copy_format(h, 22, len(L["perm"])), L["perm"])
+    else:
+        assert len(S.spmv_plan_copy_format(h, 22, 0)) == 0
     C = delta8_codes_ref(rp, ci, L)
     if bits is None:
         bits = delta16_offset_bits_ref(L["nnz_offset"], int(C["E"].sum()))
@@ -154,13 +170,14 @@ def ragged_gaps(n=1024):
     return rp, np.concatenate(rows).astype(np.int32)
 
 
+@pytest.mark.parametrize("srt", [False, True])
 @pytest.mark.parametrize("name", ["narrowband", "wideband", "random", "ragged_gaps"])
-def test_delta16_code_widths(name):
+def test_delta16_code_widths(name, srt):
     """Automatic width, then 16 and 8 forced: codes, escapes and bytes as the
     oracle's.  The narrow and the wide band (half width 200, slices spanning
     about 460 columns) need no escape; on the random matrix every gap escapes
     and the rule keeps 16 bits; the last case mixes rows of small gaps with
-    rows whose gaps escape."""
+    rows whose gaps escape.  Each with rows in order and sorted by length."""
     if name == "narrowband":
         rp, ci, v = synth.banded(6000, 960, 32, seed=5)
         m = 6000
@@ -175,38 +192,60 @@ def test_delta16_code_widths(name):
         v = synth.random_values(len(ci), 6)
         m = 2000
     n, nnz = len(rp) - 1, len(ci)
-    L = delta16_sliced_ref(rp, ci, v)
+    L = delta16_sliced_ref(rp, ci, v, sort_rows=srt)
     C = delta8_codes_ref(rp, ci, L)
     auto = delta16_offset_bits_ref(L["nnz_offset"], int(C["E"].sum()))
-    print(f"case={name} escapes={C['escapes']} E={int(C['E'].sum())} automatic bits={auto}", flush=True)
+    print(f"case={name} sorted={srt} escapes={C['escapes']} E={int(C['E'].sum())} "
+          f"automatic bits={auto}", flush=True)
     assert auto == (16 if name == "random" else 8)
-    assert (C["escapes"] > 0) == (name in ("random", "ragged_gaps"))
+    # sorted bands: a slice's rows come from a 256-row window, so a row can
+    # start more than 254 columns above the slice's smallest column
+    assert (C["escapes"] > 0) == (name in ("random", "ragged_gaps") or (srt and "band" in name))
     plan = make_plan(rp, ci, v, m)
     h = plan.handle
     S.spmv_set_delta16_layout(h, 1)
+    S.spmv_set_delta16_sort(h, int(srt))
     for req in (0, 16, 8, 0):
         S.spmv_set_delta16_offset_bits(h, req)
-        bits = check_sliced(h, rp, ci, L, np.float64, bits=req or auto)
-        assert S.spmv_bytes(h, S.V_DELTA16) == sliced_bytes(L, C, bits, n, m, nnz)
+        bits = check_sliced(h, rp, ci, L, np.float64, bits=req or auto, srt=srt)
+        assert S.spmv_bytes(h, S.V_DELTA16) == sliced_bytes(L, C, bits, n, m, nnz, srt)
     with pytest.raises(S.SpmvError) as e:
         S.spmv_set_delta16_offset_bits(h, 4)
+    assert e.value.status == S.SPMV_ERR_ARG
+    with pytest.raises(S.SpmvError) as e:
+        S.spmv_set_delta16_sort(h, 2)
     assert e.value.status == S.SPMV_ERR_ARG
     plan.close()
 
 
-def test_delta16_sliced_on_stencil_streamed_on_uneven_rows():
+def test_delta16_sliced_on_stencil_streamed_on_uneven_rows_unless_sorted():
     rp, ci, v = synth.stencil3d_27(16)
     plan = make_plan(rp, ci, v, 4096)
     assert S.spmv_plan_query(plan.handle, 14) == 1
+    assert S.spmv_plan_query(plan.handle, 26) == 0  # diagonal slices are kept
     plan.close()
     rp, ci, v = synth.banded(6000, 128, 30, seed=4)  # 8 per row on average, 0.5 d .. 1.5 d
     plan = make_plan(rp, ci, v, 6000)
-    assert S.spmv_plan_query(plan.handle, 14) == 0
+    assert S.spmv_plan_query(plan.handle, 14) == 0  # x staged in LDS: rows kept in order
+    assert S.spmv_plan_query(plan.handle, 26) == 0
+    assert not delta16_sliced_auto_ref(rp, ci, v)[1]
     with pytest.raises(S.SpmvError) as e:
         S.spmv_plan_copy_format(plan.handle, 8, 1)
     assert e.value.status == S.SPMV_ERR_ARG
     with pytest.raises(S.SpmvError):
         S.spmv_set_delta16_layout(plan.handle, 2)
+    plan.close()
+    rp, ci, v = synth.banded(6000, 128, 400, seed=4)  # the same rows, too wide to stage x
+    plan = make_plan(rp, ci, v, 6000)
+    S.spmv_set_delta16_sort(plan.handle, 0)  # rows in order: slices padded to their longest rows
+    assert S.spmv_plan_query(plan.handle, 14) == 0
+    assert S.spmv_plan_query(plan.handle, 26) == 0
+    S.spmv_set_delta16_sort(plan.handle, -1)  # sorted by length, the slices pad little
+    L, srt = delta16_sliced_auto_ref(rp, ci, v)
+    assert srt and delta16_layout_ref(True, L["slots"], len(ci), 6000) == 1
+    assert S.spmv_plan_query(plan.handle, 14) == 1
+    assert S.spmv_plan_query(plan.handle, 26) == 1
+    assert S.spmv_plan_query(plan.handle, 15) == L["slots"]
     plan.close()
 
 

@@ -95,9 +95,11 @@ def test_fullsize_variants(spec):
         runs = [(var, None) for var in range(6) if (mask >> var) & 1]
         if (mask >> S.V_DELTA16) & 1:  # the layout the rule did not pick, forced
             runs.append((S.V_DELTA16, 1 - plan.query(14)))
+            runs.append((S.V_DELTA16, 2))  # sliced with rows sorted by length
         for var, layout in runs:
             if layout is not None:
-                S.spmv_set_delta16_layout(plan.handle, layout)
+                S.spmv_set_delta16_layout(plan.handle, min(layout, 1))
+                S.spmv_set_delta16_sort(plan.handle, 1 if layout == 2 else -1)
             plan.set_variant(var)
             y = torch.full((n,), float("nan"), dtype=tdt, device=DEV)
             plan.execute(x_t, y)

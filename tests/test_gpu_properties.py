@@ -26,9 +26,10 @@ def test_every_variant_gives_the_dense_product(A):
         if (mask >> v) & 1:
             assert np.array_equal(run(plan, v, x), want), S.VARIANTS[v]
     if (mask >> S.V_DELTA16) & 1:
-        for layout in (0, 1):
+        for layout, srt in ((0, -1), (1, 0), (1, 1)):
             S.spmv_set_delta16_layout(plan.handle, layout)
-            assert np.array_equal(run(plan, S.V_DELTA16, x), want), layout
+            S.spmv_set_delta16_sort(plan.handle, srt)
+            assert np.array_equal(run(plan, S.V_DELTA16, x), want), (layout, srt)
     for slices in (2, 8):
         S.spmv_set_xblock_slices(plan.handle, slices)
         assert np.array_equal(run(plan, S.V_XBLOCK_LDS, x), want), slices
@@ -43,7 +44,9 @@ def test_delta16_code_widths_give_the_dense_product(A):
     plan = make_plan(rowptr, colind, val, m)
     if (S.spmv_variant_mask(plan.handle) >> S.V_DELTA16) & 1:
         S.spmv_set_delta16_layout(plan.handle, 1)
-        for bits in (8, 16, 0):
-            S.spmv_set_delta16_offset_bits(plan.handle, bits)
-            assert np.array_equal(run(plan, S.V_DELTA16, xs), want), bits
+        for srt in (0, 1):
+            S.spmv_set_delta16_sort(plan.handle, srt)
+            for bits in (8, 16, 0):
+                S.spmv_set_delta16_offset_bits(plan.handle, bits)
+                assert np.array_equal(run(plan, S.V_DELTA16, xs), want), (srt, bits)
     plan.close()

@@ -88,9 +88,10 @@ def test_variants_within_tolerance(case, dtype):
 @pytest.mark.parametrize("case", ["laplace64", "stencil27_12", "random_3000x8", "shortrows_5000",
                                   "banded_4000", "narrowband_3000", "ragged", "empty_rows"])
 def test_delta16_both_layouts(case, dtype):
-    """delta16 rows streamed and sliced: FP64 in Algorithm 1's order bit for
-    bit, FP32/BF16 (Kahan on the ragged case's rows above 256) within
-    tolerance, integer-valued inputs exact in every dtype."""
+    """delta16 rows streamed, sliced with rows in order and sliced with rows
+    sorted by length: FP64 in Algorithm 1's order bit for bit, FP32/BF16
+    (Kahan on the ragged case's rows above 256) within tolerance,
+    integer-valued inputs exact in every dtype."""
     build, m = CASES[case]
     rp, ci, v = build("random")
     x = synth.vector(m, 15)
@@ -99,25 +100,28 @@ def test_delta16_both_layouts(case, dtype):
     ri, cii, vi = build("int")
     xi = synth.int_vector(m, 16)
     yi_seq = spmv_seq(ri, cii, vi, xi)
-    for layout in (0, 1):
+    for layout, srt in ((0, -1), (1, 0), (1, 1)):
         plan = make_plan(rp, ci, v, m, dtype)
         if not (plan.mask() >> S.V_DELTA16) & 1:
             plan.close()
             pytest.skip("delta16 infeasible")
         S.spmv_set_delta16_layout(plan.handle, layout)
+        S.spmv_set_delta16_sort(plan.handle, srt)
         y = run(plan, S.V_DELTA16, x, dtype)
         assert S.spmv_plan_query(plan.handle, 14) == layout
+        assert S.spmv_plan_query(plan.handle, 26) == max(srt, 0)
         ok, worst = within_tolerance(y, y_ref, scale, TOL[dtype])
-        assert ok, (layout, worst)
+        assert ok, (layout, srt, worst)
         if dtype == S.SPMV_F64:
-            assert np.array_equal(y, y_seq), layout
+            assert np.array_equal(y, y_seq), (layout, srt)
         assert np.array_equal(y, run(plan, S.V_DELTA16, x, dtype))
         plan.close()
         if case == "empty_rows":  # its generator has no integer-valued form
             continue
         plan = make_plan(ri, cii, vi, m, dtype)
         S.spmv_set_delta16_layout(plan.handle, layout)
-        assert np.array_equal(run(plan, S.V_DELTA16, xi, dtype), yi_seq), layout
+        S.spmv_set_delta16_sort(plan.handle, srt)
+        assert np.array_equal(run(plan, S.V_DELTA16, xi, dtype), yi_seq), (layout, srt)
         plan.close()
 
 
@@ -129,26 +133,32 @@ def test_delta16_code_widths_agree(case, dtype):
     same columns, so the kernels gather the same x entries and sum in the
     same order: identical results, FP64 equal to the sequential sum.  The
     stencil and the Laplacian have diagonal slices only (no codes stored),
-    where forcing 8 bits must change nothing."""
+    where forcing 8 bits must change nothing.  The same with rows sorted by
+    length (offset slices only, every case then stores codes)."""
     build, m = CASES[case]
     rp, ci, v = build("random")
     x = synth.vector(m, 19)
     y_ref, scale = spmv_exact(rp, ci, v, x)
+    y_seq = spmv_seq(rp, ci, v, x)
     plan = make_plan(rp, ci, v, m, dtype)
     S.spmv_set_delta16_layout(plan.handle, 1)
-    y_auto = run(plan, S.V_DELTA16, x, dtype)
-    bits = S.spmv_plan_query(plan.handle, 17)
-    L = delta16_sliced_ref(rp, ci, v)
-    C = delta8_codes_ref(rp, ci, L)
-    print(f"case={case} dtype={dtype} automatic bits={bits} escapes={C['escapes']}", flush=True)
-    assert bits == delta16_offset_bits_ref(L["nnz_offset"], int(C["E"].sum()))
-    assert within_tolerance(y_auto, y_ref, scale, TOL[dtype])[0]
-    if dtype == S.SPMV_F64:
-        assert np.array_equal(y_auto, spmv_seq(rp, ci, v, x))
-    for req in (16, 8):
-        S.spmv_set_delta16_offset_bits(plan.handle, req)
-        assert S.spmv_plan_query(plan.handle, 17) == req
-        assert np.array_equal(run(plan, S.V_DELTA16, x, dtype), y_auto), req
+    for srt in (0, 1):
+        S.spmv_set_delta16_sort(plan.handle, srt)
+        S.spmv_set_delta16_offset_bits(plan.handle, 0)
+        y_auto = run(plan, S.V_DELTA16, x, dtype)
+        bits = S.spmv_plan_query(plan.handle, 17)
+        L = delta16_sliced_ref(rp, ci, v, sort_rows=bool(srt))
+        C = delta8_codes_ref(rp, ci, L)
+        print(f"case={case} dtype={dtype} sorted={srt} automatic bits={bits} "
+              f"escapes={C['escapes']}", flush=True)
+        assert bits == delta16_offset_bits_ref(L["nnz_offset"], int(C["E"].sum()))
+        assert within_tolerance(y_auto, y_ref, scale, TOL[dtype])[0]
+        if dtype == S.SPMV_F64:
+            assert np.array_equal(y_auto, y_seq), srt
+        for req in (16, 8):
+            S.spmv_set_delta16_offset_bits(plan.handle, req)
+            assert S.spmv_plan_query(plan.handle, 17) == req
+            assert np.array_equal(run(plan, S.V_DELTA16, x, dtype), y_auto), (srt, req)
     plan.close()
 
 
@@ -158,13 +168,15 @@ def test_delta16_layout_change_rebuilds():
     y_seq = spmv_seq(rp, ci, v, x)
     plan = make_plan(rp, ci, v, 1728)
     run(plan, S.V_DELTA16, x)
-    for layout in (0, 1, -1, 0):
+    for layout, srt in ((0, -1), (1, -1), (-1, -1), (0, -1), (1, 1), (1, 0), (-1, 1), (-1, -1)):
         S.spmv_set_delta16_layout(plan.handle, layout)  # active variant: rebuilt at once
+        S.spmv_set_delta16_sort(plan.handle, srt)
         xt = torch.from_numpy(np.asarray(x, np.float64)).to("cuda:0")
         y = torch.full((plan.n,), float("nan"), dtype=torch.float64, device="cuda:0")
         plan.execute(xt, y)
         torch.cuda.synchronize()
-        assert np.array_equal(y.cpu().numpy(), y_seq), layout
+        assert np.array_equal(y.cpu().numpy(), y_seq), (layout, srt)
+        assert S.spmv_plan_query(plan.handle, 26) == (1 if srt == 1 and layout != 0 else 0)
     plan.close()
 
 
@@ -321,10 +333,11 @@ def test_nonfinite_x_reaches_only_the_rows_that_use_it(case):
     mask = expected_mask(plan)
     runs = [(var, None) for var in range(6) if (mask >> var) & 1]
     if (mask >> S.V_DELTA16) & 1:
-        runs += [(S.V_DELTA16, 0), (S.V_DELTA16, 1)]
+        runs += [(S.V_DELTA16, 0), (S.V_DELTA16, 1), (S.V_DELTA16, 2)]  # 2: sliced, rows sorted
     for var, layout in runs:
         if layout is not None:
-            S.spmv_set_delta16_layout(plan.handle, layout)
+            S.spmv_set_delta16_layout(plan.handle, min(layout, 1))
+            S.spmv_set_delta16_sort(plan.handle, 1 if layout == 2 else 0)
         y = run(plan, var, x)
         name = (S.VARIANTS[var], layout)
         assert np.array_equal(np.isnan(y), np.isnan(want)), name

@@ -7,7 +7,8 @@ import pytest
 
 import synth
 from oracle.encode import (bf16_bits_to_f64, code_slot_ref, delta8_codes_ref, delta8_decode_ref,
-                           delta16_sort_ref, sell_perm_ref,
+                           delta16_sort_ref, delta16_sliced_auto_ref, sell_perm_ref,
+                           sliced_stages_x_ref, staged_nnz_ref,
                            delta16_layout_ref, delta16_offset_bits_ref, delta16_ref,
                            delta16_sliced_ref, merge_search_ref, merge_walk_ref,
                            partition_ref, slice_csr_ref, to_bf16_bits_ref, to_f32_ref)
@@ -587,3 +588,49 @@ def test_delta16_sort_rule():
     assert not delta16_sort_ref(30000, 28600, 0, ns, nnz, n)      # saves under 5%
     assert not delta16_sort_ref(30000, 22000, 1, ns, nnz, n)      # a diagonal slice in 16
     assert not delta16_sort_ref(3000, 1900, 0, ns, 1500, n)       # 1.1 slots per row saved (short rows)
+    assert delta16_sort_ref(30000, 22000, 0, ns, nnz, n, 9999, 20000)      # x staged for under half
+    assert not delta16_sort_ref(30000, 22000, 0, ns, nnz, n, 10000, 20000)  # staged for half
+
+
+def test_x_staging_rule_by_hand():
+    """A slice stages x when its span is under 512 columns and its 64 w
+    gathers are at least twice the span + 1 entries it loads."""
+    assert sliced_stages_x_ref(0, 2) and sliced_stages_x_ref(63, 2)
+    assert not sliced_stages_x_ref(64, 2)                  # 130 entries > 128 gathers
+    assert sliced_stages_x_ref(511, 16) and not sliced_stages_x_ref(512, 64)
+    # one offset slice of two 40-wide rows spanning 100 columns, one of two
+    # rows spanning 3000 (both with 64-row slices padded by empty rows)
+    lens = np.zeros(128, np.int64)
+    lens[[0, 1, 64, 65]] = 40
+    ci = np.concatenate([np.arange(0, 100, 100 / 40).astype(np.int64)[:40] for _ in range(2)] +
+                        [np.linspace(0, 3000, 40).astype(np.int64) for _ in range(2)])
+    rp = np.concatenate([[0], np.cumsum(lens)])
+    L = delta16_sliced_ref(rp, ci, np.ones(len(ci)))
+    assert list(L["kind"]) == [0, 0] and list(L["span"]) == [97, 3000]
+    assert staged_nnz_ref(rp, L) == 80
+
+
+def test_automatic_row_order():
+    """The automatic order keeps diagonal slices and evenly long rows plain
+    and sorts rows of mixed lengths when that saves enough slots."""
+    rp, ci, v = synth.stencil3d_27(8)
+    L, sorted_ = delta16_sliced_auto_ref(rp, ci, v)
+    assert not sorted_ and np.any(L["kind"]) and np.all(L["perm"] == np.arange(len(rp) - 1))
+    rng = np.random.default_rng(23)
+    lens = rng.choice([2, 40], 1024)                     # lengths mixed inside every slice
+    rp = np.concatenate([[0], np.cumsum(lens)])
+    ci = np.concatenate([np.sort(rng.choice(3000, l, replace=False)) for l in lens]).astype(np.int64)
+    v = np.ones(len(ci))
+    L, sorted_ = delta16_sliced_auto_ref(rp, ci, v)
+    plain = delta16_sliced_ref(rp, ci, v)
+    assert sorted_ and L["slots"] < 0.7 * plain["slots"]
+    rp, ci, v = synth.banded(6000, 128, 30, seed=4)      # uneven rows, x staged: kept in order
+    L, sorted_ = delta16_sliced_auto_ref(rp, ci, v)
+    assert not sorted_ and 2 * staged_nnz_ref(rp, L) >= L["nnz_offset"]
+    rp, ci, v = synth.banded(6000, 128, 400, seed=4)     # too wide to stage x: sorted
+    L, sorted_ = delta16_sliced_auto_ref(rp, ci, v)
+    assert sorted_ and staged_nnz_ref(rp, delta16_sliced_ref(rp, ci, v)) == 0
+    lens = np.full(1024, 12)                             # equal lengths: no padding to save
+    rp = np.concatenate([[0], np.cumsum(lens)])
+    ci = np.concatenate([np.sort(rng.choice(3000, 12, replace=False)) for _ in lens]).astype(np.int64)
+    assert not delta16_sliced_auto_ref(rp, ci, np.ones(len(ci)))[1]
