@@ -240,19 +240,34 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
                        __builtin_amdgcn_readfirstlane(threadIdx.x / kSellRows);
     if (sl >= nsl) return;  // whole wavefronts leave together
     const int lane = threadIdx.x & (kSellRows - 1);
+    // The slice's descriptors and first four diagonals, all loaded before
+    // any is used, so that they cost one scalar round trip; the loads that
+    // depend on the lane's row take clamped indices instead of a branch, so
+    // that none waits before the step loop issues its own.
+    const int w = width[sl];
+    const int32_t u = units[sl];
+    const int kd = kind[sl];
+    const int32_t b = base[sl];
+    const int sp = span[sl];
+    const int32_t eu = sizeof(O) == 1 ? eunits[sl] : 0;
+    const int4 *dg4 = reinterpret_cast<const int4 *>(diag + sl * kSellMaxDiag);
+    int4 dn = dg4[0];
     // the row this lane owns: the position's, or the one the length-sorted
     // layout put there (that layout has offset slices only)
     const int64_t pos = sl * kSellRows + lane;
-    const int64_t r = perm && pos < n ? perm[pos] : pos;
-    const int w = width[sl];
-    const int64_t o = 2 * kSellRows * (int64_t)units[sl] + 2 * lane;
-    if (kind[sl] > 0) {
+    const int64_t pc = pos < n ? pos : n - 1;  // (n >= 1: slice sl has a row)
+    const int64_t r = perm ? (pos < n ? (int64_t)perm[pc] : pos) : pos;
+    const int64_t rc = r < n ? r : n - 1;
+    const int64_t o = 2 * kSellRows * (int64_t)u + 2 * lane;
+    if (kd > 0) {
         // diagonal slice: the column of position k is r + dg[k] (the same
-        // diagonals for every lane, so those are scalar loads); only values
-        // are streamed, and the row's mask says which positions it has.
-        // Rows here hold at most 32 nonzeros, so FP32 needs no Kahan sum.
-        const int32_t *dg = diag + sl * kSellMaxDiag;
-        const uint32_t mk = r < n ? mask[r] : 0u;
+        // diagonals for every lane, so those are scalar loads, four per step
+        // and one step ahead); only values are streamed, and the row's mask
+        // says which positions it has.  Rows here hold at most 32 nonzeros,
+        // so FP32 needs no Kahan sum.
+        // (a lane past the last row reads row N-1's mask: its sum is not
+        // stored; no select here, which would wait for the load at once)
+        const uint32_t mk = mask[rc];
         const int64_t r0 = sl * kSellRows;
         A acc = A(0);
         // consecutive diagonals d, d + 1 (stencils): lane l's x[r + d + 1] is
@@ -266,20 +281,20 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
         A xp = A(0);
         int32_t dp = INT32_MIN;
         for (int k0 = 0; k0 < w; k0 += 4) {
-            const int k1 = (k0 + 2) < w ? k0 + 2 : w - 2;
+            const int32_t dd[4] = {dn.x, dn.y, dn.z, dn.w};  // diagonals k0 .. k0 + 3
+            if (k0 + 4 < w) dn = dg4[k0 / 4 + 1];            // the next step's (uniform)
             const VP v0 = __builtin_nontemporal_load(
                 reinterpret_cast<const VP *>(val + o + (int64_t)(k0 / 2) * (2 * kSellRows)));
             const bool two = k0 + 2 < w;  // wavefront-uniform: the step has a second pair
             VP v1 = {};
             if (two)
                 v1 = __builtin_nontemporal_load(
-                    reinterpret_cast<const VP *>(val + o + (int64_t)(k1 / 2) * (2 * kSellRows)));
+                    reinterpret_cast<const VP *>(val + o + (int64_t)(k0 / 2 + 1) * (2 * kSellRows)));
             A xv[4] = {A(0), A(0), A(0), A(0)};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (i >= 2 && !two) break;
-                const int kk = i < 2 ? k0 + i : k1 + (i - 2);
-                const int32_t dk = dg[kk];
+                const int32_t dk = dd[i];
                 A xk;
                 if (reuse && dp != INT32_MIN && dk == dp + 1) {
                     int64_t c = r0 + (kSellRows - 1) + dk;
@@ -308,15 +323,18 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
         if (r < n) __builtin_nontemporal_store(acc, y + r);
         return;
     }
-    const int32_t b = base[sl];
-    const int len = r < n ? rp[r + 1] - rp[r] : 0;
-    const bool comp = is_f32<A>() && len >= kmin;
+    // the row's nonzeros are [ra, re) (a lane past the last row takes row
+    // N-1's and does not store its sum); position k is in the row when
+    // ra + k < re, a test the step makes after its own loads, so that these
+    // two are not waited for before the step loop starts
+    const int32_t ra = rp[rc], re = rp[rc + 1];
+    const bool comp = is_f32<A>() && re - ra >= kmin;
     Sum<A> acc;
     int32_t cprev = b;  // 8-bit codes: the previous column
     const int32_t *ep = nullptr;  // 8-bit codes: this lane's next escape entry
     int64_t oq = 0;  // 8-bit codes: this lane's first group of four
     if constexpr (sizeof(O) == 1) {
-        ep = esc + (int64_t)kSellRows * eunits[sl] + lane;
+        ep = esc + (int64_t)kSellRows * eu + lane;
         oq = 2 * kSellRows * ((int64_t)units[sl] + sl) + 4 * lane;
     }
     // x staging (sell_stages_x): the slice reads x from a copy of its
@@ -327,7 +345,6 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     constexpr int kXs = kSellXWindow;
     __shared__ A xs[kBlock / kSellRows][kXs];
     const int wv = threadIdx.x / kSellRows;
-    const int sp = span[sl];
     const bool staged = sell_stages_x(sp, w);
     auto run = [&](auto st) {
         constexpr bool ST = decltype(st)::value;
@@ -407,10 +424,10 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (comp) {
-                    if (k0 + i < len) acc.add_comp(p[i]);
+                    if (ra + k0 + i < re) acc.add_comp(p[i]);
                 } else {
                     // a +0 addend leaves a sum that started at +0 unchanged
-                    acc.add(k0 + i < len ? p[i] : A(0));
+                    acc.add(ra + k0 + i < re ? p[i] : A(0));
                 }
             }
         }
