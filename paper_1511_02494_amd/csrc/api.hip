@@ -159,6 +159,7 @@ std::map<int, DevBuf *> g_flush;  // 512 MiB eviction buffer per device
 std::vector<void *> g_pinned_pool;
 std::map<int, std::vector<void *>> g_scratch_pool;
 constexpr size_t kFlushBytes = 512ull << 20;
+constexpr size_t kFlushSink = 256;  // the flush kernel's sink words, after its buffer
 constexpr int kNParams = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 6 + 6;
 
 typedef unsigned __int128 u128;
@@ -934,11 +935,11 @@ spmv_status_t flush_cache(hipStream_t s) {
         if (it == g_flush.end()) it = g_flush.emplace(dev, new DevBuf()).first;
         b = it->second;
         if (!b->p) {
-            SPMV_TRY(b->alloc(kFlushBytes));
-            SPMV_HIP(hipMemset(b->p, 0, kFlushBytes));
+            SPMV_TRY(b->alloc(kFlushBytes + kFlushSink));
+            SPMV_HIP(hipMemset(b->p, 0, kFlushBytes + kFlushSink));
         }
     }
-    SPMV_HIP(launch_flush(b->p, kFlushBytes, s));
+    SPMV_HIP(launch_flush(b->p, kFlushBytes, s));  // (its sink words follow the buffer)
     return SPMV_OK;
 }
 
@@ -2059,8 +2060,8 @@ spmv_status_t spmv_gather_probe2(int64_t window_elems, int32_t elem_bytes, int32
         if (it == g_flush.end()) it = g_flush.emplace(dev, new DevBuf()).first;
         b = it->second;
         if (!b->p) {
-            SPMV_TRY(b->alloc(kFlushBytes));
-            SPMV_HIP(hipMemset(b->p, 0, kFlushBytes));
+            SPMV_TRY(b->alloc(kFlushBytes + kFlushSink));
+            SPMV_HIP(hipMemset(b->p, 0, kFlushBytes + kFlushSink));
         }
     }
     DevBuf sink, col, val;

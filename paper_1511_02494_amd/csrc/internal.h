@@ -355,6 +355,7 @@ hipError_t launch_gen_vector(int64_t n, uint64_t seed, double *x, hipStream_t s)
 hipError_t launch_exclusive_scan_i32(const int32_t *lens, int32_t *rowptr, int64_t n, int segs,
                                      int64_t *totals, void *tmp, size_t tmp_bytes, hipStream_t s,
                                      size_t *tmp_needed);
+// reads buf[0, bytes) (evicting the caches); 256 sink bytes must follow it
 hipError_t launch_flush(void *buf, size_t bytes, hipStream_t s);
 hipError_t launch_read_probe(const void *buf, size_t bytes, double *sink, hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);

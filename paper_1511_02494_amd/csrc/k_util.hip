@@ -4,20 +4,28 @@
 
 namespace spmvsel {
 
-// Read and rewrite every 16-byte word: evicts the Infinity Cache when the
-// buffer is twice its size.
-__global__ __launch_bounds__(kBlock) void k_flush(u32x4 *__restrict__ p, int64_t n) {
+// Cache eviction: every 16-byte word of a buffer twice the Infinity Cache's
+// size is read with ordinary (allocating) loads, which replaces what the L2s
+// and the Infinity Cache hold.  Read only, so that the caches are left with
+// clean lines and the next kernel's misses cost no write-backs: a flush that
+// rewrites its buffer leaves up to 256 MiB of dirty lines, whose write-back
+// then lands inside the kernel that follows.  A thread stores its xor of the
+// words only if it equals an arbitrary constant, which keeps the loads.
+__global__ __launch_bounds__(kBlock) void k_flush(const u32x4 *__restrict__ p, int64_t n,
+                                                  uint32_t *__restrict__ sink) {
+    uint32_t acc = 0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
-        u32x4 v = p[i];
-        v.x += 1u;
-        p[i] = v;
+        const u32x4 v = p[i];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
+    if (acc == 0x5bd1e995u) sink[blockIdx.x & 63] = acc;
 }
 
 hipError_t launch_flush(void *buf, size_t bytes, hipStream_t s) {
     const int64_t n = (int64_t)(bytes / 16);
-    hipLaunchKernelGGL(k_flush, dim3(8192), dim3(kBlock), 0, s, (u32x4 *)buf, n);
+    hipLaunchKernelGGL(k_flush, dim3(8192), dim3(kBlock), 0, s, (const u32x4 *)buf, n,
+                       (uint32_t *)((char *)buf + bytes));
     return hipGetLastError();
 }
 
