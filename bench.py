@@ -205,6 +205,58 @@ def offset_width_report(S, torch, dev, log, scale=1):
     return out
 
 
+def row_order_report(S, torch, dev, log, scale=1):
+    """delta16 on three bands whose row lengths vary from d/2 to 3d/2
+    (generator family banded) and whose slices are too wide to stage x in
+    LDS: 4M rows with d = 8 in half width 400, 2M rows with d = 20 in half
+    width 300, 1M rows with d = 100 in half width 500.  FP64; the streamed
+    layout, the sliced one with rows in order and with rows sorted by length
+    inside 256-row windows; warm and cold time, algorithmic bytes and slots
+    of each, the automatic choice, and whether the three give the same y
+    (they sum every row in column order from +0)."""
+    out = []
+    for n, d16, w, seed in ((4_000_000 // scale, 128, 400, 4), (2_000_000 // scale, 320, 300, 5),
+                            (1_000_000 // scale, 1600, 500, 6)):
+        prm = [n, d16, w]
+        rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        nnz = S.spmv_generate(S.FAMILY["banded"], prm, seed, rp)
+        ci = torch.empty(nnz + 8, dtype=torch.int32, device=dev)
+        val = torch.empty(nnz + 8, dtype=torch.float64, device=dev)
+        S.spmv_generate(S.FAMILY["banded"], prm, seed, rp, ci, val)
+        x = torch.empty(n, dtype=torch.float64, device=dev)
+        S.spmv_generate_vector(n, seed + 1, x)
+        plan = S.Plan(rp, ci, val, n, nnz=nnz)
+        h = plan.handle
+        name = f"band_{n}_d{d16 / 16:g}_w{w}"
+        r = dict(matrix=name, n=n, nnz=nnz, automatic_layout=S.spmv_plan_query(h, 14),
+                 automatic_sorted=S.spmv_plan_query(h, 26))
+        ys = []
+        for key, layout, srt in (("streamed", 0, -1), ("sliced_in_order", 1, 0), ("sliced_sorted", 1, 1)):
+            S.spmv_set_delta16_layout(h, layout)
+            S.spmv_set_delta16_sort(h, srt)
+            t, _ = plan.time(S.V_DELTA16, reps=20)
+            tc, _ = plan.time(S.V_DELTA16, reps=10, cold=True)
+            by = plan.bytes(S.V_DELTA16)
+            plan.set_variant(S.V_DELTA16)
+            y = torch.empty(n, dtype=torch.float64, device=dev)
+            plan.execute(x, y)
+            ys.append(y)
+            r[key] = dict(us=t * 1e6, cold_us=tc * 1e6, bytes=by, gbs=by / t * 1e-9,
+                          slots=S.spmv_plan_query(h, 15) if layout == 1 else None)
+        torch.cuda.synchronize()
+        r["same_y"] = bool(torch.equal(ys[0], ys[1]) and torch.equal(ys[0], ys[2]))
+        out.append(r)
+        st, so, ss = r["streamed"], r["sliced_in_order"], r["sliced_sorted"]
+        log(f"  rows {name} (auto layout {r['automatic_layout']}, sorted {r['automatic_sorted']}): "
+            f"streamed {st['us']:6.1f} / {st['cold_us']:6.1f} us, in order {so['us']:6.1f} / "
+            f"{so['cold_us']:6.1f} us ({so['slots'] / nnz:.2f} slots/nnz), sorted {ss['us']:6.1f} / "
+            f"{ss['cold_us']:6.1f} us ({ss['slots'] / nnz:.2f} slots/nnz); same y {r['same_y']}")
+        plan.close()
+        del rp, ci, val, x, ys
+    torch.cuda.empty_cache()
+    return out
+
+
 def amortization_report(S, torch, dev, mats, log, rtol=1e-8, max_iters=5000):
     """Conjugate gradients on the SPD systems of the workload (the 5-point
     Laplacian on 64^2 and the 27-point stencil on 100^3, b ~ U[-1, 1) from a
@@ -387,6 +439,8 @@ def parse():
     ap.add_argument("--no-amortization", action="store_true", help="skip the CG report")
     ap.add_argument("--no-offset-width", action="store_true",
                     help="skip the 8- against 16-bit delta16 offset report")
+    ap.add_argument("--no-row-order", action="store_true",
+                    help="skip the delta16 row-order report (wide bands, rows sorted or not)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0,
                     help="CPU time budget of the oracle baseline (all four matrices)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-variant timing table")
@@ -623,6 +677,7 @@ def main():
     precision = [] if args.no_precision else precision_report(S, torch, dev, mats, per, log)
     amort = [] if args.no_amortization else amortization_report(S, torch, dev, mats, log)
     offw = [] if args.no_offset_width else offset_width_report(S, torch, dev, log, args.scale)
+    rows = [] if args.no_row_order else row_order_report(S, torch, dev, log, args.scale)
     seval = (selector_eval(S, torch, dev, [20000 + 8 * k for k in range(args.selector_seeds)], log)
              if args.selector_seeds > 0 else None)
     bwb = [] if args.no_bandwidth_bound else bandwidth_bound_report(S, torch, dev, mats, read_gbs, log,
@@ -708,6 +763,7 @@ def main():
         "precision": precision,
         "amortization": amort,
         "offset_width": offw,
+        "row_order": rows,
         "selector_eval": seval,
         "bandwidth_bound": bwb,
         "per_matrix": per,
