@@ -265,8 +265,10 @@ spmv_status_t spmv_set_kahan_min_len(spmv_plan_t plan, int32_t len);
 spmv_status_t spmv_set_xblock_slices(spmv_plan_t plan, int32_t slices);
 
 /* Layout of the DELTA16 format: -1 (default) picks the sliced layout when
- * its slots (each slice padded to its longest row, rounded up to even) are
- * at most 1.35 per nonzero, or 1.5 when NNZ >= 16 N, else rows streamed
+ * its slots (each slice padded to its longest row, rounded up to even; with
+ * the row order of spmv_set_delta16_sort) are at most 1.35 per nonzero, or
+ * 1.6 when 2 NNZ >= 15 N and no offset slice spans 8192 columns or more,
+ * else rows streamed
  * (sliced layouts also need NNZ < 2^30); 0 forces rows streamed, 1
  * forces sliced (tests, tuning).  A built format is dropped and, if DELTA16
  * is the plan's variant, rebuilt (synchronous).  SPMV_ERR_ARG for any other
@@ -283,10 +285,12 @@ spmv_status_t spmv_set_delta16_layout(spmv_plan_t plan, int32_t layout);
  * its window's columns, so fewer slices stage x in LDS (an offset slice
  * does when its span is under 512 columns and at most 32 w - 1 for width
  * w).  -1 (default) sorts when at most 1% of the plain layout's slices are
- * diagonal, its slots exceed 1.05 per nonzero, its staging slices hold under
- * half of its offset-slice nonzeros, and sorting saves at least 5% of its
- * slots and at least 2 slots per row; 0 never sorts, 1 always does (with
- * the sliced layout).
+ * diagonal and its slots exceed 1.05 per nonzero, sorting saves at least 5%
+ * of its slots, and either under half of the plain layout's offset-slice
+ * nonzeros are in staging slices and sorting saves at least 4 slots per
+ * row, or sorting keeps at least half of the nonzeros in staging slices and
+ * saves at least 8 slots per row; 0 never sorts, 1 always does (with the
+ * sliced layout).
  * A built format is dropped and, if DELTA16 is the plan's variant, rebuilt
  * (synchronous).  SPMV_ERR_ARG for any other value. */
 spmv_status_t spmv_set_delta16_sort(spmv_plan_t plan, int32_t mode);

@@ -69,8 +69,11 @@ def delta16_ref(rowptr, colind, block_rows: int = 256):
 
 SLICE_ROWS = 64          # rows per slice: one per lane of a wavefront
 SLICE_MAX_PAD = 1.35     # sliced layout only if its slots are at most this many per nonzero,
-SLICE_MAX_PAD_LONG = 1.5  # or this many when the rows average at least
-SLICE_LONG_MEAN = 16      # this many nonzeros
+SLICE_MAX_PAD_LONG = 1.6  # or this many when the rows average at least
+SLICE_LONG_MEAN = 7.5     # this many nonzeros
+SLICE_MAX_SPAN_LONG = 8192  # and the offset slices span fewer columns than this
+SORT_MIN_SAVED = 8        # slots per row that sorting rows by length must save,
+SORT_MIN_SAVED_FREE = 4   # or this many where the plain layout stages little x
 
 
 SELL_WINDOW = 256  # rows per window of the length-sorted sliced layout
@@ -326,21 +329,33 @@ def staged_nnz_ref(rowptr, L, slice_rows: int = SLICE_ROWS) -> int:
 
 
 def delta16_sort_ref(slots: int, slots_sorted: int, ndiag: int, nslices: int, nnz: int, n: int,
-                     staged_nnz: int = 0, nnz_offset: int = 1) -> bool:
+                     staged: int = 0, staged_sorted: int = 0, nnz_offset: int = 0) -> bool:
     """Whether the sliced layout sorts its rows (``sell_perm_ref``).
 
-    Sorting gives up diagonal slices, widens each slice's column span to its
-    window's (so that a slice of a band may no longer stage x), and costs a
-    4-byte row index per row (the kernel reads the row it owns and stores y
-    there).  It is taken when the plain layout has at most 1% diagonal
-    slices, over 5% of padding, and stages x for fewer than half of its
-    offset nonzeros (``staged_nnz`` of ``nnz_offset``), and sorting saves at
-    least 5% of its slots and at least two slots per row (9 or more bytes of
-    values and codes against 4)."""
-    if ndiag * 100 > nslices or slots * 100 <= 105 * nnz or 2 * staged_nnz >= nnz_offset:
+    Sorting gives up diagonal slices, costs a 4-byte row index per row and
+    scattered y stores (the kernel reads the row it owns and stores y
+    there), and widens each slice's column span to its window's, so that a
+    slice of a band may no longer stage x.  It is taken when the plain layout
+    has at most 1% diagonal slices and over 5% of padding, sorting saves at
+    least 5% of its slots, and either the plain layout stages x for under
+    half of its ``nnz_offset`` offset-slice nonzeros and sorting saves
+    SORT_MIN_SAVED_FREE slots per row, or sorting keeps at least half of the
+    staging (``staged_sorted`` against ``staged``, the nonzeros of staging
+    slices, ``staged_nnz_ref``) and saves SORT_MIN_SAVED slots per row."""
+    if ndiag * 100 > nslices or slots * 100 <= 105 * nnz:
         return False
     saved = slots - slots_sorted
-    return saved * 20 >= slots and saved >= 2 * n
+    if saved * 20 < slots:
+        return False
+    if 2 * staged < nnz_offset and saved >= SORT_MIN_SAVED_FREE * n:
+        return True
+    return 2 * staged_sorted >= staged and saved >= SORT_MIN_SAVED * n
+
+
+def sliced_max_span_ref(L) -> int:
+    """The largest column span of an offset slice of layout L (0 if none)."""
+    spans = np.asarray(L["span"])[np.asarray(L["kind"]) == 0]
+    return int(spans.max()) if len(spans) else 0
 
 
 def delta16_sliced_auto_ref(rowptr, colind, val):
@@ -350,30 +365,33 @@ def delta16_sliced_auto_ref(rowptr, colind, val):
     L = delta16_sliced_ref(rowptr, colind, val)
     n, nnz, ns = len(rowptr) - 1, len(colind), len(L["width"])
     ndiag = int(np.count_nonzero(L["kind"]))
-    staged = staged_nnz_ref(rowptr, L)
-    if (n == 0 or ndiag * 100 > ns or L["slots"] * 100 <= 105 * nnz
-            or 2 * staged >= L["nnz_offset"]):
+    if n == 0 or ndiag * 100 > ns or L["slots"] * 100 <= 105 * nnz:
         return L, False  # the rule declines before the sorted layout is needed
     Ls = delta16_sliced_ref(rowptr, colind, val, sort_rows=True)
-    if delta16_sort_ref(L["slots"], Ls["slots"], ndiag, ns, nnz, n, staged, L["nnz_offset"]):
+    if delta16_sort_ref(L["slots"], Ls["slots"], ndiag, ns, nnz, n,
+                        staged_nnz_ref(rowptr, L), staged_nnz_ref(rowptr, Ls), L["nnz_offset"]):
         return Ls, True
     return L, False
 
 
-def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int, n: int) -> int:
+def delta16_layout_ref(block_feasible: bool, slots: int, nnz: int, n: int, max_span: int = 0) -> int:
     """Layout of the delta16 variant: -1 infeasible, 0 rows streamed, 1 sliced.
 
     A 64-row slice lies inside one block of the streamed layout, so it spans
     no more columns than that block: the sliced layout is feasible whenever
-    the streamed one is.  It is taken when padding keeps its slot count at
-    most 1.35 times the nonzero count, or 1.5 times when the rows of the n-row
-    matrix average at least 16 nonzeros, and NNZ < 2^30.
+    the streamed one is.  It is taken when padding keeps its slots (in the
+    row order ``delta16_sort_ref`` takes) at most 1.35 times the nonzero
+    count, or 1.6 times when the rows of the n-row matrix average at least
+    7.5 nonzeros and its offset slices span fewer than 8192 columns
+    (``max_span``, the largest span of an offset slice), and NNZ < 2^30.
     """
     if not block_feasible:
         return -1
     if nnz >= 1 << 30:
         return 0
-    ok = slots <= SLICE_MAX_PAD * nnz or (nnz >= SLICE_LONG_MEAN * n and slots <= SLICE_MAX_PAD_LONG * nnz)
+    ok = slots <= SLICE_MAX_PAD * nnz or (2 * nnz >= 2 * SLICE_LONG_MEAN * n and
+                                          slots <= SLICE_MAX_PAD_LONG * nnz and
+                                          max_span < SLICE_MAX_SPAN_LONG)
     return 1 if ok else 0
 
 

@@ -334,7 +334,10 @@ spmv_status_t ensure_d16_base(spmv_plan *P) {
 // delta16 layout: the shape of the sliced layout (widths, reference columns,
 // slot offsets) decides it; sliced when its slots, padding included, are at
 // most kSellMaxPad per nonzero, or kSellMaxPadLong when rows average at least
-// kSellLongMean nonzeros (longer rows hide more padding), or when forced.  A
+// 7.5 nonzeros and its offset slices span fewer than kSellMaxSpanLong columns
+// (on bands padded to 1.5 slots per nonzero the sliced kernel ran about 10%
+// faster than the streamed one with 8 to 16 nonzeros per row, slower with 6,
+// and slower across 40000 columns), or when forced.  A
 // 64-row slice lies inside one block of the streamed layout, so it is
 // feasible whenever that is.
 spmv_status_t d16_decide_layout(spmv_plan *P) {
@@ -401,29 +404,37 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     SPMV_TRY(shape(nullptr));
     // Length-sorted rows (rows sorted by length inside each 256-row window,
     // as in SELL-C-sigma): taken when requested, or automatically when the
-    // plain layout has at most 1% diagonal slices, over 5% of padding and
-    // stages x in LDS for under half of its offset nonzeros (a sorted slice
-    // spans its window's columns, up to 192 more than a plain one, and loses
-    // the staging that plain bands keep), and sorting saves at least 5% of
-    // its slots and two slots per row (the sorted kernel reads a 4-byte row
-    // index per row).  A window lies inside one block of the streamed
-    // layout, so its slices stay within 16 bits.
+    // plain layout has at most 1% diagonal slices and over 5% of padding,
+    // sorting saves at least 5% of its slots, and either the plain layout
+    // stages x for under half of its offset nonzeros and sorting saves
+    // kSortMinSavedFree slots per row, or sorting keeps at least half of the
+    // staging and saves kSortMinSaved slots per row.  The sorted kernel
+    // reads a 4-byte row index per row and scatters its y stores over the
+    // window, and a sorted slice spans its window's columns, up to 192 more
+    // than a plain one, so that it may no longer stage x in LDS: with the
+    // staging kept, sorting paid from about 8 saved slots per row; where
+    // neither stages, from about 3.  A window lies inside one block of the
+    // streamed layout, so its slices stay within 16 bits.
     P->d16_sort = 0;
     P->d16s_perm.release();
     P->d16s_pinv.release();
     const int64_t plain_slots = units * 2 * kSellRows;
+    const int64_t staged_plain = staged_nnz, nnz_off_plain = nnz_off;
     const bool consider =
         P->d16_layout_req != 0 &&
         (P->d16_sort_req == 1 ||
-         (P->d16_sort_req < 0 && ndiag * 100 <= nsl && plain_slots * 100 > 105 * P->nnz &&
-          staged_nnz * 2 < nnz_off));
+         (P->d16_sort_req < 0 && ndiag * 100 <= nsl && plain_slots * 100 > 105 * P->nnz));
     if (consider && P->n > 0) {
         SPMV_TRY(P->d16s_perm.alloc((size_t)P->n * 4));
         SPMV_TRY(P->d16s_pinv.alloc((size_t)P->n * 4));
         SPMV_HIP(launch_sell_perm(*P, P->d16s_perm.as<int32_t>(), P->d16s_pinv.as<int32_t>(), S(P)));
         SPMV_TRY(shape(P->d16s_perm.as<int32_t>()));
         const int64_t saved = plain_slots - units * 2 * kSellRows;
-        if (P->d16_sort_req == 1 || (saved * 20 >= plain_slots && saved >= 2 * P->n)) {
+        const bool free_x = 2 * staged_plain < nnz_off_plain;
+        if (P->d16_sort_req == 1 ||
+            (saved * 20 >= plain_slots &&
+             ((free_x && saved >= (int64_t)kSortMinSavedFree * P->n) ||
+              (2 * staged_nnz >= staged_plain && saved >= (int64_t)kSortMinSaved * P->n)))) {
             P->d16_sort = 1;
         } else {
             P->d16s_perm.release();
@@ -440,7 +451,8 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
     const bool representable = units <= INT32_MAX;
     const double slots = (double)P->d16_slots, nnz = (double)P->nnz;
     const bool padded_ok = slots <= kSellMaxPad * nnz ||
-                           (P->nnz >= (int64_t)kSellLongMean * P->n && slots <= kSellMaxPadLong * nnz);
+                           (2 * P->nnz >= (int64_t)kSellLongMeanX2 * P->n &&
+                            slots <= kSellMaxPadLong * nnz && max_span < kSellMaxSpanLong);
     const int automatic = representable && padded_ok ? 1 : 0;
     if (P->d16_layout_req == 1 && !representable)
         return fail(SPMV_ERR_INFEASIBLE, "delta16: the sliced layout needs under 2^31 slot pairs");

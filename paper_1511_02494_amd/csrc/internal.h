@@ -31,8 +31,11 @@ constexpr double kLongMaxShare = 0.25;  // long rows leave the slices up to this
 constexpr int kKahanMinLen = 257;     // FP32 rows longer than 256 use Kahan sums
 constexpr int kSellRows = 64;         // rows per slice of the sliced delta16 layout (one per lane)
 constexpr double kSellMaxPad = 1.35;  // ... taken when its slots are at most this many per nonzero,
-constexpr double kSellMaxPadLong = 1.5;  // or this many when the mean row has
-constexpr int kSellLongMean = 16;        // at least this many nonzeros
+constexpr double kSellMaxPadLong = 1.6;  // or this many when rows average at least
+constexpr int kSellLongMeanX2 = 15;      // 7.5 nonzeros (twice the mean, in integers)
+constexpr int kSellMaxSpanLong = 8192;   // and its offset slices span fewer columns
+constexpr int kSortMinSaved = 8;         // slots per row that sorting rows by length must save,
+constexpr int kSortMinSavedFree = 4;     // or this many where the plain layout stages little x
 constexpr int kSellMaxDiag = 32;         // diagonals a diagonal slice can hold (mask bits)
 constexpr int kSellXWindow = 512;        // x entries an offset slice can stage in LDS
 // An offset slice of width w whose columns lie within kSellXWindow of its

@@ -8,8 +8,8 @@ import synth
 import paper_1511_02494_amd as S
 from oracle.encode import (delta8_codes_ref, delta16_layout_ref, delta16_offset_bits_ref,
                            delta16_ref, delta16_sliced_auto_ref, delta16_sliced_ref,
-                           merge_search_ref, merge_walk_ref, partition_ref, xblock_split_ref,
-                           to_bf16_bits_ref, to_f32_ref)
+                           merge_search_ref, merge_walk_ref, partition_ref, sliced_max_span_ref,
+                           xblock_split_ref, to_bf16_bits_ref, to_f32_ref)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -40,7 +40,8 @@ def test_formats_match_oracle(name, build, m):
     if ok:
         L, srt = delta16_sliced_auto_ref(rp, ci, v)  # the row order the rule takes
         print(f"case={name} sorted={srt} slots={L['slots']}", flush=True)
-        assert S.spmv_plan_query(h, 14) == delta16_layout_ref(True, L["slots"], nnz, n)
+        assert S.spmv_plan_query(h, 14) == delta16_layout_ref(True, L["slots"], nnz, n,
+                                                              sliced_max_span_ref(L))
         assert S.spmv_plan_query(h, 15) == L["slots"]
         S.spmv_set_delta16_layout(h, 0)
         assert S.spmv_plan_query(h, 14) == 0
@@ -218,34 +219,50 @@ def test_delta16_code_widths(name, srt):
     plan.close()
 
 
-def test_delta16_sliced_on_stencil_streamed_on_uneven_rows_unless_sorted():
+def test_delta16_layouts_and_row_orders_by_rule():
+    """The stencil: sliced, diagonal slices, rows in order.  Rows of 2 to 6
+    (mean 4): streamed.  Rows of 4 to 12 in half width 30 (1.5 slots per
+    nonzero, mean 8): sliced, in order.  Rows of 10 to 30 in half width 400:
+    sliced and sorted by length (the slices stage no x either way); forced
+    in order, sliced with 1.5 slots per nonzero."""
     rp, ci, v = synth.stencil3d_27(16)
     plan = make_plan(rp, ci, v, 4096)
     assert S.spmv_plan_query(plan.handle, 14) == 1
     assert S.spmv_plan_query(plan.handle, 26) == 0  # diagonal slices are kept
     plan.close()
-    rp, ci, v = synth.banded(6000, 128, 30, seed=4)  # 8 per row on average, 0.5 d .. 1.5 d
+    rp, ci, v = synth.banded(6000, 64, 30, seed=4)
     plan = make_plan(rp, ci, v, 6000)
-    assert S.spmv_plan_query(plan.handle, 14) == 0  # x staged in LDS: rows kept in order
+    L, srt = delta16_sliced_auto_ref(rp, ci, v)
+    assert not srt and delta16_layout_ref(True, L["slots"], len(ci), 6000, sliced_max_span_ref(L)) == 0
+    assert S.spmv_plan_query(plan.handle, 14) == 0
     assert S.spmv_plan_query(plan.handle, 26) == 0
-    assert not delta16_sliced_auto_ref(rp, ci, v)[1]
     with pytest.raises(S.SpmvError) as e:
         S.spmv_plan_copy_format(plan.handle, 8, 1)
     assert e.value.status == S.SPMV_ERR_ARG
     with pytest.raises(S.SpmvError):
         S.spmv_set_delta16_layout(plan.handle, 2)
     plan.close()
-    rp, ci, v = synth.banded(6000, 128, 400, seed=4)  # the same rows, too wide to stage x
+    rp, ci, v = synth.banded(6000, 128, 30, seed=4)
     plan = make_plan(rp, ci, v, 6000)
-    S.spmv_set_delta16_sort(plan.handle, 0)  # rows in order: slices padded to their longest rows
-    assert S.spmv_plan_query(plan.handle, 14) == 0
-    assert S.spmv_plan_query(plan.handle, 26) == 0
-    S.spmv_set_delta16_sort(plan.handle, -1)  # sorted by length, the slices pad little
     L, srt = delta16_sliced_auto_ref(rp, ci, v)
-    assert srt and delta16_layout_ref(True, L["slots"], len(ci), 6000) == 1
+    assert not srt and delta16_layout_ref(True, L["slots"], len(ci), 6000, sliced_max_span_ref(L)) == 1
+    assert S.spmv_plan_query(plan.handle, 14) == 1
+    assert S.spmv_plan_query(plan.handle, 26) == 0
+    assert S.spmv_plan_query(plan.handle, 15) == L["slots"]
+    plan.close()
+    rp, ci, v = synth.banded(6000, 320, 400, seed=4)
+    plan = make_plan(rp, ci, v, 6000)
+    L, srt = delta16_sliced_auto_ref(rp, ci, v)
+    assert srt and delta16_layout_ref(True, L["slots"], len(ci), 6000, sliced_max_span_ref(L)) == 1
     assert S.spmv_plan_query(plan.handle, 14) == 1
     assert S.spmv_plan_query(plan.handle, 26) == 1
     assert S.spmv_plan_query(plan.handle, 15) == L["slots"]
+    S.spmv_set_delta16_sort(plan.handle, 0)
+    plain = delta16_sliced_ref(rp, ci, v)
+    assert S.spmv_plan_query(plan.handle, 14) == delta16_layout_ref(True, plain["slots"], len(ci), 6000,
+                                                                       sliced_max_span_ref(plain))
+    assert S.spmv_plan_query(plan.handle, 26) == 0
+    assert S.spmv_plan_query(plan.handle, 15) == plain["slots"]
     plan.close()
 
 

@@ -97,14 +97,30 @@ def test_delta16_sliced_layout_rule():
     assert delta16_layout_ref(True, L["slots"], len(ci), 64) == 0
     assert delta16_layout_ref(False, 0, 0, 0) == -1
     # one row of 30 among rows of 20: 1920 slots per 1290 nonzeros (1.49),
-    # sliced because rows average 20 nonzeros; one row of 14 among rows of
-    # 10: 896 per 644 (1.39), streamed because they average 10
+    # and one row of 14 among rows of 10: 896 per 644 (1.39), sliced because
+    # rows average at least 8 nonzeros; one row of 7 among rows of 5: 512 per
+    # 322 (1.59), streamed because they average 5; one row of 14 among rows
+    # of 8: 896 per 518 (1.73), streamed
     rp, ci, L = csr([30] + [20] * 63)
     assert L["slots"] == 1920 and len(ci) == 1290
     assert delta16_layout_ref(True, L["slots"], len(ci), 64) == 1
     rp, ci, L = csr([14] + [10] * 63)
     assert L["slots"] == 896 and len(ci) == 644
+    assert delta16_layout_ref(True, L["slots"], len(ci), 64) == 1
+    rp, ci, L = csr([7] + [5] * 63)
+    assert L["slots"] == 512 and len(ci) == 322
     assert delta16_layout_ref(True, L["slots"], len(ci), 64) == 0
+    rp, ci, L = csr([14] + [8] * 63)
+    assert L["slots"] == 896 and len(ci) == 518
+    assert delta16_layout_ref(True, L["slots"], len(ci), 64) == 0
+    # the 1.6 bound: a mean of 7.5 or more, and offset slices spanning
+    # fewer than 8192 columns
+    assert delta16_layout_ref(True, 150, 100, 13) == 1                 # mean 7.69
+    assert delta16_layout_ref(True, 150, 100, 14) == 0                 # mean 7.14
+    assert delta16_layout_ref(True, 160, 100, 13) == 1 and delta16_layout_ref(True, 161, 100, 13) == 0
+    assert delta16_layout_ref(True, 150, 100, 13, 8191) == 1
+    assert delta16_layout_ref(True, 150, 100, 13, 8192) == 0
+    assert delta16_layout_ref(True, 135, 100, 50, 100000) == 1         # 1.35 holds at any span
     # equal odd rows of 27: 28 slots per 27 nonzeros -> sliced
     rp = np.arange(0, 27 * 128 + 1, 27)
     ci = np.concatenate([np.arange(27) + i for i in range(128)])
@@ -588,8 +604,12 @@ def test_delta16_sort_rule():
     assert not delta16_sort_ref(30000, 28600, 0, ns, nnz, n)      # saves under 5%
     assert not delta16_sort_ref(30000, 22000, 1, ns, nnz, n)      # a diagonal slice in 16
     assert not delta16_sort_ref(3000, 1900, 0, ns, 1500, n)       # 1.1 slots per row saved (short rows)
-    assert delta16_sort_ref(30000, 22000, 0, ns, nnz, n, 9999, 20000)      # x staged for under half
-    assert not delta16_sort_ref(30000, 22000, 0, ns, nnz, n, 10000, 20000)  # staged for half
+    assert not delta16_sort_ref(30000, 22100, 0, ns, nnz, n)      # 7.9 slots per row saved
+    assert delta16_sort_ref(30000, 22000, 0, ns, nnz, n, 20000, 10000, 20000)     # 8, half the staging kept
+    assert not delta16_sort_ref(30000, 22000, 0, ns, nnz, n, 20000, 9999, 20000)  # staging lost
+    assert delta16_sort_ref(30000, 26000, 0, ns, nnz, n, 9999, 0, 20000)      # 4 per row, little staged
+    assert not delta16_sort_ref(30000, 26100, 0, ns, nnz, n, 9999, 0, 20000)  # 3.9 per row
+    assert not delta16_sort_ref(30000, 26000, 0, ns, nnz, n, 10000, 0, 20000)  # half staged, lost
 
 
 def test_x_staging_rule_by_hand():
@@ -612,7 +632,8 @@ def test_x_staging_rule_by_hand():
 
 def test_automatic_row_order():
     """The automatic order keeps diagonal slices and evenly long rows plain
-    and sorts rows of mixed lengths when that saves enough slots."""
+    and sorts rows of mixed lengths when that saves enough slots per row and
+    keeps the x staging."""
     rp, ci, v = synth.stencil3d_27(8)
     L, sorted_ = delta16_sliced_auto_ref(rp, ci, v)
     assert not sorted_ and np.any(L["kind"]) and np.all(L["perm"] == np.arange(len(rp) - 1))
@@ -624,12 +645,20 @@ def test_automatic_row_order():
     L, sorted_ = delta16_sliced_auto_ref(rp, ci, v)
     plain = delta16_sliced_ref(rp, ci, v)
     assert sorted_ and L["slots"] < 0.7 * plain["slots"]
-    rp, ci, v = synth.banded(6000, 128, 30, seed=4)      # uneven rows, x staged: kept in order
+    rp, ci, v = synth.banded(6000, 128, 400, seed=4)     # 4 to 12 per row: too little saved
+    assert not delta16_sliced_auto_ref(rp, ci, v)[1]
+    rp, ci, v = synth.banded(6000, 480, 200, seed=4)     # 15 to 45 per row, staging lost
+    plain, srt = delta16_sliced_ref(rp, ci, v), delta16_sliced_ref(rp, ci, v, sort_rows=True)
+    assert plain["slots"] - srt["slots"] >= 6 * 6000
+    assert 2 * staged_nnz_ref(rp, srt) < staged_nnz_ref(rp, plain)
+    assert not delta16_sliced_auto_ref(rp, ci, v)[1]
+    rp, ci, v = synth.banded(6000, 480, 20, seed=4)      # the same rows, staged either way: sorted
     L, sorted_ = delta16_sliced_auto_ref(rp, ci, v)
-    assert not sorted_ and 2 * staged_nnz_ref(rp, L) >= L["nnz_offset"]
-    rp, ci, v = synth.banded(6000, 128, 400, seed=4)     # too wide to stage x: sorted
-    L, sorted_ = delta16_sliced_auto_ref(rp, ci, v)
-    assert sorted_ and staged_nnz_ref(rp, delta16_sliced_ref(rp, ci, v)) == 0
+    plain = delta16_sliced_ref(rp, ci, v)
+    assert sorted_ and 2 * staged_nnz_ref(rp, L) >= staged_nnz_ref(rp, plain) > 0
+    rp, ci, v = synth.banded(6000, 320, 400, seed=4)     # 10 to 30 per row, staged near the
+    L, sorted_ = delta16_sliced_auto_ref(rp, ci, v)      # first columns only: sorted
+    assert sorted_ and staged_nnz_ref(rp, delta16_sliced_ref(rp, ci, v)) < 0.05 * len(ci)
     lens = np.full(1024, 12)                             # equal lengths: no padding to save
     rp = np.concatenate([[0], np.cumsum(lens)])
     ci = np.concatenate([np.sort(rng.choice(3000, 12, replace=False)) for _ in lens]).astype(np.int64)
