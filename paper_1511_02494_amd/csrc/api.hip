@@ -543,7 +543,7 @@ int64_t xs_slice_width(const spmv_plan *P, int ns) {
 // merge-path tiles.
 spmv_status_t split_long_rows(spmv_plan *P, int ns, int32_t *lens) {
     const int64_t n = P->n;
-    P->xs_nlong = P->xs_nchunks = P->xs_long_nnz = 0;
+    P->xs_nlong = P->xs_nchunks = P->xs_long_nnz = P->xs_nslots = 0;
     DevBuf flags, pos, tmp, rows, beg, end;
     SPMV_TRY(flags.alloc((size_t)n * 4));
     SPMV_TRY(pos.alloc((size_t)(n + 1) * 4));
@@ -572,31 +572,62 @@ spmv_status_t split_long_rows(spmv_plan *P, int ns, int32_t *lens) {
     int64_t long_nnz = 0;
     for (int64_t t = 0; t < L; ++t) long_nnz += he[t] - hb[t];
     if ((double)long_nnz > kLongMaxShare * (double)P->nnz) return SPMV_OK;
+    // chunks of at most kLongChunk nonzeros, each inside one column slice,
+    // in row and column order (the order the finish adds their sums in)
+    DevBuf dbnd;
+    SPMV_TRY(dbnd.alloc((size_t)L * (ns + 1) * 4));
+    SPMV_HIP(launch_long_bounds(L, ns, P->xs_width, P->colind, beg.as<int32_t>(), end.as<int32_t>(),
+                                dbnd.as<int32_t>(), S(P)));
+    std::vector<int32_t> bnd((size_t)L * (ns + 1));
+    SPMV_HIP(hipMemcpyAsync(bnd.data(), dbnd.p, bnd.size() * 4, hipMemcpyDeviceToHost, S(P)));
+    SPMV_TRY(sync(P));
     std::vector<int32_t> first(L + 1), ck0, ck1;
+    std::vector<std::vector<int32_t>> queue((size_t)ns);
     for (int64_t t = 0; t < L; ++t) {
         first[t] = (int32_t)ck0.size();
-        for (int64_t k = hb[t]; k < he[t]; k += kLongChunk) {
-            ck0.push_back((int32_t)k);
-            ck1.push_back((int32_t)std::min<int64_t>(he[t], k + kLongChunk));
+        for (int sl = 0; sl < ns; ++sl) {
+            const int64_t b0 = bnd[(size_t)t * (ns + 1) + sl], b1 = bnd[(size_t)t * (ns + 1) + sl + 1];
+            for (int64_t k = b0; k < b1; k += kLongChunk) {
+                queue[(size_t)sl].push_back((int32_t)ck0.size());
+                ck0.push_back((int32_t)k);
+                ck1.push_back((int32_t)std::min<int64_t>(b1, k + kLongChunk));
+            }
         }
     }
     first[L] = (int32_t)ck0.size();
     const int64_t nc = (int64_t)ck0.size();
+    // chunk workgroup c of the slice kernel (its grid's slice part is a
+    // multiple of 8 workgroups) runs on XCD c mod 8, whose L2 holds slice
+    // (c mod 8) mod S: it takes the next chunk of that slice, or none
+    std::vector<int32_t> cmap;
+    std::vector<size_t> head((size_t)ns, 0);
+    for (int64_t c = 0, left = nc; left > 0; ++c) {
+        const size_t sl = (size_t)((c % 8) % ns);
+        if (head[sl] < queue[sl].size()) {
+            cmap.push_back(queue[sl][head[sl]++]);
+            --left;
+        } else {
+            cmap.push_back(-1);
+        }
+    }
     SPMV_TRY(P->xs_lrows.alloc((size_t)L * 4));
     SPMV_TRY(P->xs_lfirst.alloc((size_t)(L + 1) * 4));
     SPMV_TRY(P->xs_lck0.alloc((size_t)nc * 4));
     SPMV_TRY(P->xs_lck1.alloc((size_t)nc * 4));
     SPMV_TRY(P->xs_lsum.alloc((size_t)nc * 8));
+    SPMV_TRY(P->xs_lcmap.alloc(cmap.size() * 4));
     SPMV_TRY(P->xs_lmask.alloc((size_t)((n + 31) / 32) * 4));
     SPMV_HIP(launch_long_mask(n, flags.as<int32_t>(), P->xs_lmask.as<uint32_t>(), S(P)));
     SPMV_HIP(hipMemcpyAsync(P->xs_lrows.p, rows.p, (size_t)L * 4, hipMemcpyDeviceToDevice, S(P)));
     SPMV_HIP(hipMemcpyAsync(P->xs_lfirst.p, first.data(), (size_t)(L + 1) * 4, hipMemcpyHostToDevice, S(P)));
     SPMV_HIP(hipMemcpyAsync(P->xs_lck0.p, ck0.data(), (size_t)nc * 4, hipMemcpyHostToDevice, S(P)));
     SPMV_HIP(hipMemcpyAsync(P->xs_lck1.p, ck1.data(), (size_t)nc * 4, hipMemcpyHostToDevice, S(P)));
+    SPMV_HIP(hipMemcpyAsync(P->xs_lcmap.p, cmap.data(), cmap.size() * 4, hipMemcpyHostToDevice, S(P)));
     SPMV_HIP(launch_long_zero(L, ns, n, rows.as<int32_t>(), lens, S(P)));
     SPMV_TRY(sync(P));  // the host vectors above must outlive the copies
     P->xs_nlong = L;
     P->xs_nchunks = nc;
+    P->xs_nslots = (int64_t)cmap.size();
     P->xs_long_nnz = long_nnz;
     return SPMV_OK;
 }
@@ -609,7 +640,7 @@ spmv_status_t build_xslices(spmv_plan *P) {
     const int64_t cw = xs_slice_width(P, ns);
     P->xs_slices = ns;
     P->xs_width = cw;
-    P->xs_nlong = P->xs_nchunks = P->xs_long_nnz = 0;
+    P->xs_nlong = P->xs_nchunks = P->xs_long_nnz = P->xs_nslots = 0;
     P->xs_pj = 0;
     P->xs_pg = 0;
     for (int k = 0; k < kSlices; ++k) P->xs_nnz_off[k] = P->xs_tiles[k] = P->xs_tile_off[k] = 0;

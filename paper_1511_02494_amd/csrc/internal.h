@@ -171,8 +171,10 @@ struct spmv_plan {
     spmvsel::DevBuf xs_rowptr, xs_colind, xs_val, xs_srow, xs_snnz, xs_crow, xs_cval, xs_y;
     // rows with a slice segment longer than kSliceStreamMaxLen, taken out of
     // the slices and summed from the original CSR in chunks of kLongChunk
-    int64_t xs_nlong = 0, xs_nchunks = 0, xs_long_nnz = 0;
-    spmvsel::DevBuf xs_lrows, xs_lfirst, xs_lck0, xs_lck1, xs_lsum;
+    // inside one column slice each; xs_lcmap gives the chunk of each chunk
+    // workgroup of the slice kernel (-1: none), xs_nslots of them
+    int64_t xs_nlong = 0, xs_nchunks = 0, xs_long_nnz = 0, xs_nslots = 0;
+    spmvsel::DevBuf xs_lrows, xs_lfirst, xs_lck0, xs_lck1, xs_lsum, xs_lcmap;
     spmvsel::DevBuf xs_lmask;    // one bit per row: set for the long rows
     // phased row streaming (no partial y): row blocks per workgroup and
     // workgroups; 0 when the slices use the partial-y kernels
@@ -300,6 +302,8 @@ hipError_t launch_long_flags(int64_t n, int ns, const int32_t *lens, int32_t *fl
 hipError_t launch_long_compact(int64_t n, const int32_t *flags, const int32_t *pos,
                                const int32_t *rp, int32_t *rows, int32_t *beg, int32_t *end,
                                hipStream_t s);
+hipError_t launch_long_bounds(int64_t L, int ns, int64_t cw, const int32_t *ci, const int32_t *beg,
+                              const int32_t *end, int32_t *bounds, hipStream_t s);
 hipError_t launch_long_zero(int64_t L, int ns, int64_t n, const int32_t *rows, int32_t *lens,
                             hipStream_t s);
 // mask[w] bit b = flags[32 w + b] != 0

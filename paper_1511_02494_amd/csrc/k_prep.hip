@@ -655,6 +655,41 @@ __global__ __launch_bounds__(kBlock) void k_long_zero(int64_t L, int ns, int64_t
         for (int s = 0; s < ns; ++s) lens[(int64_t)s * n + rows[t]] = 0;
 }
 
+// Slice boundaries inside each long row: bounds[t (S + 1) + s] is the first
+// nonzero of long row t whose column is at least s cw (the row's columns
+// increase), from beg[t] (s = 0) to end[t] (s = S).
+__global__ __launch_bounds__(kBlock) void k_long_bounds(int64_t L, int ns, int64_t cw,
+                                                       const int32_t *__restrict__ ci,
+                                                       const int32_t *__restrict__ beg,
+                                                       const int32_t *__restrict__ end,
+                                                       int32_t *__restrict__ bounds) {
+    const int64_t total = L * (ns + 1);
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int64_t t = i / (ns + 1);
+        const int sl = (int)(i % (ns + 1));
+        int32_t lo = beg[t], hi = end[t];
+        if (sl > 0 && sl < ns) {
+            const int64_t c = (int64_t)sl * cw;
+            while (lo < hi) {
+                const int32_t mid = lo + (hi - lo) / 2;
+                if (ci[mid] < c) lo = mid + 1; else hi = mid;
+            }
+        }
+        bounds[i] = sl == ns ? hi : lo;
+    }
+}
+
+hipError_t launch_long_bounds(int64_t L, int ns, int64_t cw, const int32_t *ci, const int32_t *beg,
+                              const int32_t *end, int32_t *bounds, hipStream_t s) {
+    if (L == 0) return hipSuccess;
+    int64_t g = (L * (ns + 1) + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_long_bounds, dim3((unsigned)g), dim3(kBlock), 0, s, L, ns, cw, ci, beg, end,
+                       bounds);
+    return hipGetLastError();
+}
+
 hipError_t launch_long_flags(int64_t n, int ns, const int32_t *lens, int32_t *flags, hipStream_t s) {
     if (n == 0) return hipSuccess;
     int64_t g = (n + kBlock - 1) / kBlock;

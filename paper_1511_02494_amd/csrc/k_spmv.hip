@@ -646,10 +646,12 @@ __global__ __launch_bounds__(kBlock) void k_merge_slices(int64_t n, const int32_
 }
 
 // Long rows of the split, summed from the original CSR: one block per chunk
-// of at most kLongChunk nonzeros of one row (all loads first, then the
-// gathers; per-thread sums folded by a fixed tree; these blocks ride at the
-// end of the slice kernel's grid, filling CUs as slice blocks finish); then
-// k_slice_finish gives each long row a wavefront that adds its chunk sums.
+// of at most kLongChunk nonzeros of one row inside one column slice (all
+// loads first, then the gathers; per-thread sums folded by a fixed tree;
+// these blocks ride at the end of the slice kernel's grid, filling CUs as
+// slice blocks finish, each on an XCD that gathers from its chunk's slice);
+// then k_slice_finish gives each long row a wavefront that adds its chunk
+// sums in column order.
 // `sh` is kBlock elements of the calling kernel's LDS (its own arrays, so
 // the chunk blocks add nothing to the kernel's LDS size and occupancy).
 template <class V>
@@ -692,6 +694,7 @@ struct LongChunks {
     const int32_t *ck0, *ck1, *ci;
     const void *val;
     void *lsum;
+    const int32_t *cmap;  // the chunk of each chunk workgroup (-1: none)
 };
 
 template <class V, int R, bool D16>
@@ -704,8 +707,10 @@ __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t 
     using A = typename VT<V>::A;
     if ((int64_t)blockIdx.x >= sgrid) {
         __shared__ A sh[kBlock];
-        long_chunk_block<V>((int64_t)blockIdx.x - sgrid, LC.ck0, LC.ck1, LC.ci,
-                            static_cast<const V *>(LC.val), x, static_cast<A *>(LC.lsum), sh);
+        const int32_t c = LC.cmap[(int64_t)blockIdx.x - sgrid];
+        if (c < 0) return;  // the same for the whole workgroup
+        long_chunk_block<V>(c, LC.ck0, LC.ck1, LC.ci, static_cast<const V *>(LC.val), x,
+                            static_cast<A *>(LC.lsum), sh);
         return;
     }
     int s;
@@ -1080,7 +1085,7 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
         }
         if (P.xs_nlong > 0 && P.xs_rows == 0) return hipErrorInvalidValue;  // split implies streaming
         const LongChunks LC{P.xs_lck0.as<int32_t>(), P.xs_lck1.as<int32_t>(), P.colind, P.val,
-                            P.xs_lsum.p};
+                            P.xs_lsum.p, P.xs_lcmap.as<int32_t>()};
         if (P.xs_rows > 0 && P.xs_pj > 0) {  // phased row streaming: no partial y
             const int64_t nblk = (P.n + kBlock - 1) / kBlock;
             const unsigned g = (unsigned)P.xs_pg;
@@ -1107,7 +1112,7 @@ hipError_t launch_xblock(const spmv_plan &P, const void *x, void *y, hipStream_t
             const int R = P.xs_rows / kBlock;
             const int64_t nb = (P.n + P.xs_rows - 1) / P.xs_rows;
             const int64_t sg = (nb + G - 1) / G * 8;
-            const unsigned g = (unsigned)(sg + P.xs_nchunks);
+            const unsigned g = (unsigned)(sg + P.xs_nslots);
             const int32_t *xci = P.xs_colind.as<int32_t>();
             const V *xv = (const V *)P.xs_val.p;
 #define SPMV_RSS(RR)                                                                                   \
