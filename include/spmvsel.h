@@ -257,9 +257,10 @@ spmv_status_t spmv_set_kahan_min_len(spmv_plan_t plan, int32_t len);
 
 /* Column slices of the XBLOCK_LDS format: 0 (default) picks the smallest of
  * 1, 2, 4, 8 that cuts x into slices of at most 256 Ki entries (2 MiB in
- * FP64) while keeping at least 2 nonzeros per slice row on average (the
- * partial y vectors grow with the count), so that each XCD's 4 MB L2 mostly
- * holds the slice it gathers from; 1, 2, 4 or 8 force that count (tests,
+ * FP64), doubling only while a slice row keeps at least 0.9 nonzeros on
+ * average (10 NNZ >= 9 (2 S) N; the row pointers and partial y vectors grow
+ * with the count), so that each XCD's 4 MB L2 mostly holds the slice it
+ * gathers from; 1, 2, 4 or 8 force that count (tests,
  * tuning).  If the format is built with another count it is rebuilt
  * (synchronous).  SPMV_ERR_ARG for any other value. */
 spmv_status_t spmv_set_xblock_slices(spmv_plan_t plan, int32_t slices);

@@ -520,15 +520,20 @@ spmv_status_t d16_decide_layout(spmv_plan *P) {
 // and store each slice as its own CSR (rowptr per slice, slice-major
 // colind/val), with merge-path tiles per slice when a slice row is long, and
 // one partial y per slice.
-// Slice count: the requested one, else the smallest power of two that cuts
-// x into slices of at most kSliceXEntries (at most one slice per XCD), as long
-// as a slice row keeps kSliceMinAvg nonzeros on average (fewer, and the
-// partial y vectors cost more than the L2 hits gain).
+// Slice count: the requested one, else the smallest of 1, 2, 4, 8 (at most
+// one slice per XCD) that leaves at most kSliceXEntries columns per slice,
+// doubled only while a slice row keeps 0.9 nonzeros on average: with fewer,
+// the per-slice row pointers and partial y vectors cost more than the
+// smaller windows gain (a sweep of random-row and power-law matrices of 250k
+// to 4M rows and 2 to 32 nonzeros per row put the best count there; at 2
+// per slice row the count stopped one doubling short on 4M rows, 8-18%
+// slower).
 int xs_slice_count(const spmv_plan *P) {
     if (P->xs_req > 0) return P->xs_req;
-    const double avg = P->n > 0 ? (double)P->nnz / (double)P->n : 0.0;
     int ns = 1;
-    while (ns < kSlices && P->m > kSliceXEntries * ns && avg >= (double)kSliceMinAvg * 2 * ns) ns *= 2;
+    while (ns < kSlices && P->m > kSliceXEntries * ns &&
+           10 * P->nnz >= (int64_t)kSliceMinAvg10 * 2 * ns * P->n)
+        ns *= 2;
     return ns;
 }
 

@@ -24,7 +24,7 @@ constexpr int64_t kMaxNnz = (1ll << 31) - (1ll << 16);  // NNZ below this: int32
 constexpr int kMergeTile = kBlock * kMergeIpt;
 constexpr int kSlices = 8;            // x-block column slices at most (one per XCD)
 constexpr int64_t kSliceXEntries = 256ll << 10;  // x entries per slice the automatic count aims at
-constexpr int kSliceMinAvg = 2;       // ... keeping at least this many nonzeros per slice row
+constexpr int kSliceMinAvg10 = 9;     // ... keeping at least this many tenths of a nonzero per slice row
 constexpr int kSliceStreamMaxLen = 128;  // longest slice segment for row streaming
 constexpr int kLongChunk = 256;       // nonzeros per block of the long-row sums
 constexpr double kLongMaxShare = 0.25;  // long rows leave the slices up to this share of NNZ
