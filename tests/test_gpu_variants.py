@@ -257,6 +257,49 @@ def test_xblock_every_slice_count(case, slices):
         plan.close()
 
 
+def skewed_long_rows(seed=21):
+    """4000 x 40000: ten rows of 3000 nonzeros all in the first 5000 columns,
+    ten of 3000 spread over every column (23% of the nonzeros), the rest 40 to
+    60 nonzeros; integer values and x, so every summation order gives the
+    exact product."""
+    rng = np.random.default_rng(seed)
+    n, m = 4000, 40000
+    rows = []
+    for i in range(n):
+        if i % 400 == 7:
+            c = rng.choice(5000, 3000, replace=False)
+        elif i % 400 == 207:
+            c = rng.choice(m, 3000, replace=False)
+        else:
+            c = rng.choice(m, rng.integers(40, 61), replace=False)
+        rows.append(np.sort(c))
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    ci = np.concatenate(rows).astype(np.int32)
+    v = rng.integers(-8, 9, len(ci)).astype(np.float64)
+    return rp, ci, v, m
+
+
+def test_xblock_long_rows_in_one_slice_and_across_all():
+    """Long rows cut into chunks at the slice boundaries: chunks of one slice
+    only (most chunk workgroups of the other slices idle) and of every slice;
+    exact with integer data at each slice count, and deterministic."""
+    rp, ci, v, m = skewed_long_rows()
+    x = np.random.default_rng(22).integers(-8, 9, m).astype(np.float64)
+    dense = np.zeros(len(rp) - 1)
+    for i in range(len(rp) - 1):
+        dense[i] = float(np.dot(v[rp[i]:rp[i + 1]], x[ci[rp[i]:rp[i + 1]]]))
+    for slices in (2, 4, 8):
+        plan = make_plan(rp, ci, v, m)
+        S.spmv_set_xblock_slices(plan.handle, slices)
+        y = run(plan, S.V_XBLOCK_LDS, x)
+        nlong = S.spmv_plan_query(plan.handle, 13)
+        print(f"slices={slices} long rows={nlong}", flush=True)
+        assert nlong == 20
+        assert np.array_equal(y, dense), slices
+        assert np.array_equal(y, run(plan, S.V_XBLOCK_LDS, x))
+        plan.close()
+
+
 @pytest.mark.parametrize("case", ["laplace64", "stencil27_12", "random_3000x8", "shortrows_5000",
                                   "banded_4000", "empty_rows", "powerlaw_20000", "ragged"])
 def test_xblock_phased_walk_is_sequential(case):
