@@ -856,9 +856,14 @@ __global__ __launch_bounds__(kBlock) void k_slice_finish(int64_t n, SliceTable<A
                                                          const int32_t *__restrict__ first,
                                                          const A *__restrict__ lsum, int kmin) {
     if ((int64_t)blockIdx.x < gsum) {
+        // the partials are loaded with the row's mask word, not after it (a
+        // long row's partials are zeros, loaded and dropped); the empty asm
+        // uses the sum before the test, so that the loads are not sunk into it
         for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += gsum * kBlock) {
-            if ((longmask[i >> 5] >> (i & 31)) & 1u) continue;
-            __builtin_nontemporal_store(slice_total<A, NS>(T, i), y + i);
+            const uint32_t w = longmask[i >> 5];
+            const A v = slice_total<A, NS>(T, i);
+            __asm__ volatile("" : : "v"(v));
+            if (!((w >> (i & 31)) & 1u)) __builtin_nontemporal_store(v, y + i);
         }
         return;
     }
