@@ -785,10 +785,14 @@ __global__ __launch_bounds__(kBlock) void k_slice_scatter(int64_t n, int64_t nnz
                                                           V *__restrict__ xval) {
     __shared__ int32_t s_end[kMergeTile + 1];
     __shared__ int32_t s_ci[kMergeTile + 1];
+    __shared__ int64_t s_dst[kMergeTile];  // each of the tile's nonzeros: its position, or -1
     SliceTile T = slice_tile_begin(blockIdx.x, n, nnz, rp, ci, srow, snnz, s_end, s_ci);
     int cur_row = -1, cur_s = -1;
     int64_t shift = 0;
     int32_t run_end = 0;  // first position past the run's slot (writes stay inside it)
+    // the merge-path walk only finds positions; the copies below go
+    // nonzero by nonzero across the workgroup, so that the value loads are
+    // coalesced and the stores too within each run
     for (; T.it < T.dend; ++T.it) {
         if (T.yj < T.nz && T.j0 + T.yj < s_end[T.xi]) {
             const int32_t k = T.j0 + T.yj;
@@ -803,13 +807,18 @@ __global__ __launch_bounds__(kBlock) void k_slice_scatter(int64_t n, int64_t nnz
                 cur_row = T.xi;
                 cur_s = s;
             }
-            if (k < run_end) {
-                xci[k + shift] = c;
-                xval[k + shift] = val[k];
-            }
+            s_dst[T.yj] = k < run_end ? k + shift : -1;
             ++T.yj;
         } else {
             ++T.xi;
+        }
+    }
+    __syncthreads();
+    for (int q = (int)threadIdx.x; q < T.nz; q += kBlock) {
+        const int64_t d = s_dst[q];
+        if (d >= 0) {
+            xci[d] = s_ci[q];
+            xval[d] = val[T.j0 + q];
         }
     }
 }
