@@ -266,6 +266,27 @@ def test_delta16_layouts_and_row_orders_by_rule():
     plan.close()
 
 
+@pytest.mark.parametrize("d16,w", [(64, 30), (128, 30), (128, 400), (320, 400), (480, 20),
+                                   (480, 200), (640, 2000)])
+def test_delta16_rules_agree_with_oracle(d16, w):
+    """The automatic layout and row order, and the slots and spans they give,
+    equal the oracle's rules on bands of rows d/2 to 3d/2 long (d = d16/16)."""
+    rp, ci, v = synth.banded(6000, d16, w, seed=7)
+    plan = make_plan(rp, ci, v, 6000)
+    h = plan.handle
+    L, srt = delta16_sliced_auto_ref(rp, ci, v)
+    layout = delta16_layout_ref(True, L["slots"], len(ci), 6000, sliced_max_span_ref(L))
+    print(f"d16={d16} w={w} sorted={srt} layout={layout} slots/nnz={L['slots'] / len(ci):.3f}",
+          flush=True)
+    assert S.spmv_plan_query(h, 14) == layout
+    assert S.spmv_plan_query(h, 26) == (int(srt) if layout == 1 else 0)
+    S.spmv_set_delta16_layout(h, 1)  # the sliced arrays of the automatic row order
+    assert S.spmv_plan_query(h, 26) == int(srt)
+    assert S.spmv_plan_query(h, 15) == L["slots"]
+    assert S.spmv_plan_query(h, 18) == sliced_max_span_ref(L)
+    plan.close()
+
+
 def test_delta16_infeasible_on_wide_rows():
     rp, ci, v = synth.uniform_random(3000, 2_000_000, 8, seed=2)
     plan = make_plan(rp, ci, v, 2_000_000)
