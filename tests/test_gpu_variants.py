@@ -321,6 +321,27 @@ def test_xblock_phased_walk_is_sequential(case):
         plan.close()
 
 
+def slice_count_rule(n, m, nnz):
+    """The automatic x-block slice count restated: double from 1 while a
+    slice would hold more than 256 Ki columns and a slice row would keep at
+    least 0.9 nonzeros on average, up to 8."""
+    ns = 1
+    while ns < 8 and m > 262144 * ns and 10 * nnz >= 9 * 2 * ns * n:
+        ns *= 2
+    return ns
+
+
+@pytest.mark.parametrize("n,m,per,want", [(300_000, 1_200_000, 2, 2), (300_000, 1_200_000, 4, 4),
+                                          (300_000, 2_200_000, 8, 8), (300_000, 200_000, 8, 1)])
+def test_xblock_automatic_slice_count(n, m, per, want):
+    rp, ci, v = synth.uniform_random(n, m, per, seed=9)
+    assert slice_count_rule(n, m, len(ci)) == want
+    plan = make_plan(rp, ci, v, m)
+    S.spmv_set_variant(plan.handle, S.V_XBLOCK_LDS)
+    assert S.spmv_plan_query(plan.handle, 7) == want
+    plan.close()
+
+
 def test_xblock_slice_count_change_rebuilds():
     rp, ci, v = CASES["powerlaw_20000"][0]("int")
     x = synth.int_vector(20000, 14)
