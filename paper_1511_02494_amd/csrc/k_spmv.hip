@@ -326,8 +326,11 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     // the row's nonzeros are [ra, re) (a lane past the last row takes row
     // N-1's and does not store its sum); position k is in the row when
     // ra + k < re, a test the step makes after its own loads, so that these
-    // two are not waited for before the step loop starts
+    // two are not waited for before the step loop starts (in 32-bit unsigned
+    // arithmetic: ra + k stays below 2^32 where a signed sum could pass
+    // 2^31 - 1 in a wide slice near the end of the nonzeros)
     const int32_t ra = rp[rc], re = rp[rc + 1];
+    const uint32_t ua = (uint32_t)ra, ue = (uint32_t)re;
     const bool comp = is_f32<A>() && re - ra >= kmin;
     Sum<A> acc;
     int32_t cprev = b;  // 8-bit codes: the previous column
@@ -424,10 +427,10 @@ __global__ __launch_bounds__(kBlock) void k_sliced_d16(
     #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (comp) {
-                    if (ra + k0 + i < re) acc.add_comp(p[i]);
+                    if (ua + (uint32_t)(k0 + i) < ue) acc.add_comp(p[i]);
                 } else {
                     // a +0 addend leaves a sum that started at +0 unchanged
-                    acc.add(ra + k0 + i < re ? p[i] : A(0));
+                    acc.add(ua + (uint32_t)(k0 + i) < ue ? p[i] : A(0));
                 }
             }
         }
