@@ -69,7 +69,12 @@ def row_quantities(rowptr, colind, x_bytes: int = 8):
 
 def accumulators(rowptr, colind, x_bytes: int = 8) -> dict:
     """Exact integer sums over rows (Python ints)."""
-    L, bw, q, misses = row_quantities(rowptr, colind, x_bytes)
+    return row_sums(*row_quantities(rowptr, colind, x_bytes))
+
+
+def row_sums(L, bw, q, misses) -> dict:
+    """The exact sums over rows of the per-row quantities (int64 arrays, as
+    row_quantities gives them)."""
     n = len(L)
     Lo = L.astype(object)
     bwo = bw.astype(object)
