@@ -93,6 +93,26 @@ def row_sums(L, bw, q, misses) -> dict:
     }
 
 
+def row_sums_of_kinds(L, bw, q, misses, counts) -> dict:
+    """row_sums of a matrix whose rows come in a few kinds: entry j of the
+    per-row arrays stands for counts[j] identical rows (exact Python ints)."""
+    kinds = [(int(c), int(a), int(b), int(d), int(e))
+             for c, a, b, d, e in zip(counts, L, bw, q, misses) if c > 0]
+    n = sum(c for c, *_ in kinds)
+    return {
+        "N": n,
+        "NNZ": sum(c * a for c, a, _, _, _ in kinds),
+        "nnz_min": min(a for _, a, _, _, _ in kinds) if n else 0,
+        "nnz_max": max(a for _, a, _, _, _ in kinds) if n else 0,
+        "S_L2": sum(c * a * a for c, a, _, _, _ in kinds),
+        "S_bw": sum(c * b for c, _, b, _, _ in kinds),
+        "S_bw2": sum(c * b * b for c, _, b, _, _ in kinds),
+        "S_q": sum(c * d for c, _, _, d, _ in kinds),
+        "S_q2": sum(c * d * d for c, _, _, d, _ in kinds),
+        "S_miss": sum(c * e for c, _, _, _, e in kinds),
+    }
+
+
 def finalize(acc: dict, n_cols: int, val_bytes: int = 8, x_bytes: int = 8,
              y_bytes: int = 8) -> list[float]:
     """The twelve FP64 features from the exact accumulators."""

@@ -22,9 +22,9 @@ first and last 256, and 512 seeded random ones) equal the oracle's
 sequential sum of the same products.  The device arrays are generated with
 torch from the closed forms above and checked against the same closed forms
 in NumPy at the sampled rows.  The twelve features are compared bit for bit
-with the oracle's sums of the per-row quantities, which take three distinct
-values (rows of 1024, the row of 1023, empty rows) computed by the oracle on
-one row of each kind.
+with the oracle's sums of the per-row quantities over the kinds of rows
+(rows of 1024, the row of 1023, empty rows), each kind's quantities computed
+by the oracle on one row of it.  A last case takes the largest row count.
 """
 from collections import namedtuple
 
@@ -33,7 +33,7 @@ import pytest
 
 import paper_1511_02494_amd as S
 from oracle import cref
-from oracle.features import finalize, row_quantities, row_sums
+from oracle.features import finalize, row_quantities, row_sums_of_kinds
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -162,8 +162,7 @@ def expected_features(cs, dtype):
     rp = np.concatenate([[0], np.cumsum(L)])
     c = np.concatenate([cols_np(cs, r, np.arange(row_len(cs, r))) for r in kinds])
     per = row_quantities(rp, c, xb)
-    full = [np.repeat(q, counts) for q in per]
-    return finalize(row_sums(*full), M, vb, xb, xb)
+    return finalize(row_sums_of_kinds(*per, counts), M, vb, xb, xb)
 
 
 def run_into(plan, x, n):
@@ -253,4 +252,92 @@ def test_largest_matrices_every_variant(cs, xs):
             S.spmv_set_delta16_offset_bits(plan.handle, 0)
         plan.close()
         del ci, v, plan
+        torch.cuda.empty_cache()
+
+
+# ---- the largest row count: N = 2^31 - 2 rows, the odd ones holding one
+# nonzero on the diagonal (NNZ = 2^30 - 1, the last column N - 1 in use), the
+# even ones empty.  Every variant, both delta16 layouts (the sliced one
+# forced: 64-row slices of 32 rows with one diagonal), all dtypes.
+TALL_N = 2 ** 31 - 2
+TALL_NNZ = TALL_N // 2
+
+
+def tall_expected(rows):
+    L = rows % 2
+    rp = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
+    r = rows[L == 1]
+    y = cref.seq(rp.astype(np.int32), np.arange(len(r), dtype=np.int32), vals_np(r, 0),
+                 x_np(r))
+    return y
+
+
+def tall_dev(dtype):
+    rp = torch.empty(TALL_N + 1, dtype=torch.int32, device=DEV)
+    ci = torch.empty(TALL_NNZ, dtype=torch.int32, device=DEV)
+    v = torch.empty(TALL_NNZ, dtype=TDT[dtype], device=DEV)
+    ch = 1 << 28
+    for i0 in range(0, TALL_N + 1, ch):
+        i = torch.arange(i0, min(i0 + ch, TALL_N + 1), dtype=torch.int64, device=DEV)
+        rp[i0:i0 + i.numel()] = (i // 2).to(torch.int32)  # odd rows below i
+        del i
+    for k0 in range(0, TALL_NNZ, ch):
+        k = torch.arange(k0, min(k0 + ch, TALL_NNZ), dtype=torch.int64, device=DEV)
+        r = 2 * k + 1  # the k-th odd row
+        ci[k0:k0 + k.numel()] = r.to(torch.int32)
+        v[k0:k0 + k.numel()] = (r % 7 - 3).to(TDT[dtype])
+        del k, r
+    if dtype == S.SPMV_BF16:
+        v = v.view(torch.int16)
+    return rp, ci, v
+
+
+def test_largest_row_count_every_variant(xs):
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([np.arange(256), np.arange(TALL_N - 256, TALL_N),
+                                     rng.integers(256, TALL_N - 256, 512)]))
+    y_exp = tall_expected(rows)
+    rows_t = torch.from_numpy(rows).to(DEV)
+    y_first = None
+    print(f"\ntall: n={TALL_N} m={TALL_N} nnz={TALL_NNZ}", flush=True)
+    kinds = np.array([0, 1])  # an empty row, a row with its diagonal
+    for dtype in (S.SPMV_F64, S.SPMV_F32, S.SPMV_BF16):
+        rp, ci, v = tall_dev(dtype)
+        if dtype == S.SPMV_F64:
+            assert np.array_equal(rp[rows_t].cpu().numpy(), rows // 2), "device row pointers"
+            odd = torch.from_numpy(rows[rows % 2 == 1] // 2).to(DEV)
+            assert np.array_equal(ci[odd].cpu().numpy(), rows[rows % 2 == 1]), "device columns"
+            assert np.array_equal(v[odd].cpu().numpy(), vals_np(rows[rows % 2 == 1], 0))
+        x = xs[dtype]
+        plan = S.Plan(rp, ci, v, TALL_N, dtype, nnz=TALL_NNZ)
+        xb = 8 if dtype == S.SPMV_F64 else 4
+        vb = {S.SPMV_F64: 8, S.SPMV_F32: 4, S.SPMV_BF16: 2}[dtype]
+        per = row_quantities(np.array([0, 0, 1]), np.array([1]), xb)
+        want_f = finalize(row_sums_of_kinds(*per, [TALL_N // 2, TALL_N // 2]), TALL_N, vb, xb, xb)
+        assert plan.features()[0] == want_f, DNAME[dtype]
+        mask = plan.mask()
+        assert mask == 0b111111, bin(mask)
+        runs = [(var, -1) for var in range(6)] + [(S.V_DELTA16, 1)]
+        for var, layout in runs:
+            if layout >= 0:
+                S.spmv_set_delta16_layout(plan.handle, layout)
+            plan.set_variant(var)
+            name = f"{DNAME[dtype]}/{S.VARIANTS[var]}" + (f" layout {plan.query(14)}"
+                                                          if var == S.V_DELTA16 else "")
+            y = run_into(plan, x, TALL_N)
+            assert not torch.isnan(y).any(), name
+            got = y[rows_t].cpu().numpy()
+            bad = np.flatnonzero(got != y_exp)
+            assert len(bad) == 0, (name, rows[bad[:5]].tolist(), got[bad[:5]].tolist(),
+                                   y_exp[bad[:5]].tolist())
+            if y_first is None:
+                y_first = y
+            else:
+                assert torch.equal(y, y_first), (name, "differs from the first run")
+            del y
+            print(f"  {name}: {len(rows)} sampled rows equal the oracle, all rows equal the "
+                  f"first run", flush=True)
+        assert plan.query(14) == 1
+        plan.close()
+        del rp, ci, v, plan
         torch.cuda.empty_cache()

@@ -132,3 +132,26 @@ def test_column_shift_invariant():
     f0, _ = features_ref(rp, ci, 5000)
     f1, _ = features_ref(rp, ci + 1234, 5000)
     assert f0 == f1
+
+
+def test_sums_over_row_kinds_equal_sums_over_rows():
+    """row_sums_of_kinds (rows given as kinds with multiplicities) equals
+    row_sums over the rows written out, on random matrices grouped by their
+    per-row quantities, with a kind of count 0 added (it must not count),
+    and on an empty matrix."""
+    from oracle.features import row_quantities, row_sums, row_sums_of_kinds
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        n = int(rng.integers(1, 60))
+        lens = rng.integers(0, 6, n)
+        rp = np.concatenate([[0], np.cumsum(lens)])
+        ci = np.concatenate([np.sort(rng.choice(500, int(L), replace=False)) for L in lens]
+                            + [np.zeros(0, np.int64)]).astype(np.int64)
+        per = row_quantities(rp, ci, 8)
+        want = row_sums(*per)
+        assert want == accumulators(rp, ci, 8)
+        keys, counts = np.unique(np.stack(per, axis=1), axis=0, return_counts=True)
+        cols = [np.append(keys[:, j], 7 + j) for j in range(4)]  # plus a kind of count 0
+        assert row_sums_of_kinds(*cols, np.append(counts, 0)) == want, trial
+    empty = [np.zeros(0, np.int64)] * 4
+    assert row_sums_of_kinds(*empty, np.zeros(0, np.int64)) == row_sums(*empty)
