@@ -724,16 +724,31 @@ __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t 
 }
 
 // Phased row streaming on the slices, without partial y vectors.  Workgroup
-// w owns the 256-row blocks w, w + G, ..., w + (J - 1) G and walks the slices
-// in order, each owned row's sum kept in a register of the thread that owns
-// the row.  The slices are column ranges in increasing order, so every row
-// (long rows aside) is summed in column order: Algorithm 1's order, bit for
-// bit in FP64.  The grid holds at most as many of these workgroups as the
-// CUs run at once, so they walk the slices together and the part of x being
-// gathered at any time is about one slice, which the L2s hold.  Used when no
-// row leaves the slices: the long rows' chunk sums, run as extra workgroups
-// of this grid, as a kernel of their own or after the slices, all cost more
-// than the per-slice kernel with partial y vectors below saves.
+// w owns the consecutive 256-row blocks [w nblk / G, (w + 1) nblk / G) (at
+// most J of them) and walks the slices in order; in each slice it streams the
+// nonzeros of all its rows as one run, thread t summing rows t, t + 256, ...
+// of its range, each row's sum kept in a register across the slices.  The
+// slices are column ranges in increasing order, so every row is summed in
+// column order: Algorithm 1's order, bit for bit in FP64.  The grid holds at
+// most as many of these workgroups as the CUs run at once, so they walk the
+// slices together and the part of x being gathered at any time is about one
+// slice, which the L2s hold.  Used when no row leaves the slices: the long
+// rows' chunk sums, run as extra workgroups of this grid, as a kernel of
+// their own or after the slices, all cost more than the per-slice kernel
+// with partial y vectors below saves.
+// The reference column of the block holding position kk of a phased run:
+// that of the last of its blocks whose first position (s_rp at the block's
+// first row; nrows rows in all) is at most kk.
+template <int J>
+__device__ __forceinline__ int32_t block_base(const int32_t *s_rp, const int32_t *s_cb, int nrows,
+                                              int32_t kk) {
+    int32_t bb = s_cb[0];
+#pragma unroll
+    for (int j = 1; j < J; ++j)
+        if (j * kBlock < nrows && kk >= s_rp[j * kBlock]) bb = s_cb[j];
+    return bb;
+}
+
 template <class V, int J, bool D16>
 __global__ __launch_bounds__(kBlock) void k_phased_slices(
     int64_t n, int64_t nblk, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -744,82 +759,88 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
     using IP = typename Pair<int32_t>::type;
     using OP = typename Pair<uint16_t>::type;
     constexpr int NP = kRunLen / 2;  // pairs per thread per chunk
-    __shared__ int32_t s_rp[kBlock + 1];
+    __shared__ int32_t s_rp[J * kBlock + 1];
+    __shared__ int32_t s_cb[J];
     __shared__ A s_prod[kChunk];
     const int64_t G = gridDim.x, w = blockIdx.x;
     const int t = threadIdx.x;
+    // the block range (at least one block: G <= nblk; at most J: G >= nblk / J)
+    const int64_t b0 = w * nblk / G, b1 = (w + 1) * nblk / G;
+    const int64_t r0 = b0 * kBlock;
+    const int64_t rlim = b1 * kBlock < n ? b1 * kBlock : n;
+    const int nrows = (int)(rlim - r0);
     Sum<A> acc[J];
     bool comp[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        const int64_t r = (w + j * G) * kBlock + t;
-        comp[j] = is_f32<A>() && r < n && (rp[r + 1] - rp[r]) >= kmin;
+        const int lr = j * kBlock + t;
+        comp[j] = is_f32<A>() && lr < nrows && (rp[r0 + lr + 1] - rp[r0 + lr]) >= kmin;
     }
     for (int sl = 0; sl < T.ns; ++sl) {
         const int32_t *__restrict__ srp = T.rp[sl];
         const int32_t *__restrict__ sci = ci + T.off[sl];
         const uint16_t *__restrict__ soff = D16 ? T.code + T.off[sl] : nullptr;
         const V *__restrict__ sv = val + T.off[sl];
+        __syncthreads();  // the previous slice is done with s_rp and s_prod
+        for (int r = t; r <= nrows; r += kBlock) s_rp[r] = srp[r0 + r];
+        if (D16 && t < J) s_cb[t] = b0 + t < b1 ? T.cb[sl][b0 + t] : 0;
+        __syncthreads();
+        const int32_t a = s_rp[0], e = s_rp[nrows];
+        int32_t k[J], kend[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            const int64_t blk = w + j * G;
-            if (blk >= nblk) break;  // the same for the whole workgroup
-            const int64_t r0 = blk * kBlock;
-            const int nrows = (int)((n - r0) < kBlock ? (n - r0) : kBlock);
-            __syncthreads();  // the previous pass is done with s_rp and s_prod
-            for (int r = t; r <= nrows; r += kBlock) s_rp[r] = srp[r0 + r];
-            __syncthreads();
-            const int32_t a = s_rp[0], e = s_rp[nrows];
-            int32_t k = t < nrows ? s_rp[t] : e;
-            const int32_t kend = t < nrows ? s_rp[t + 1] : e;
-            const int32_t bb = D16 ? T.cb[sl][blk] : 0;
-            for (int32_t cs = a & ~1; cs < e; cs += kChunk) {
-                A p[kRunLen];
-                // each pair's gathers follow its own loads: with more
-                // gathers in flight per thread (all loads first) the kernel
-                // ran slower, its L1 miss slots being the limit
+            const int lr = j * kBlock + t;
+            k[j] = lr < nrows ? s_rp[lr] : e;
+            kend[j] = lr < nrows ? s_rp[lr + 1] : e;
+        }
+        for (int32_t cs = a & ~1; cs < e; cs += kChunk) {
+            A p[kRunLen];
+            // each pair's gathers follow its own loads: with more gathers in
+            // flight per thread (all loads first) the kernel ran slower, its
+            // L1 miss slots being the limit
 #pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    const int32_t kk = cs + 2 * t + 2 * kBlock * q;
-                    V v0 = V(0), v1 = V(0);
-                    int32_t c0 = 0, c1 = 0;
-                    if (kk + 1 < e) {
-                        const VP vv = __builtin_nontemporal_load(reinterpret_cast<const VP *>(sv + kk));
-                        v0 = vv.x;
-                        v1 = vv.y;
-                        if (D16) {
-                            const OP oo = __builtin_nontemporal_load(reinterpret_cast<const OP *>(soff + kk));
-                            c0 = bb + (int32_t)oo.x;
-                            c1 = bb + (int32_t)oo.y;
-                        } else {
-                            const IP cc = __builtin_nontemporal_load(reinterpret_cast<const IP *>(sci + kk));
-                            c0 = cc.x;
-                            c1 = cc.y;
-                        }
-                    } else if (kk < e) {
-                        v0 = sv[kk];
-                        c0 = D16 ? bb + (int32_t)soff[kk] : sci[kk];
+            for (int q = 0; q < NP; ++q) {
+                const int32_t kk = cs + 2 * t + 2 * kBlock * q;
+                V v0 = V(0), v1 = V(0);
+                int32_t c0 = 0, c1 = 0;
+                if (kk + 1 < e) {
+                    const VP vv = __builtin_nontemporal_load(reinterpret_cast<const VP *>(sv + kk));
+                    v0 = vv.x;
+                    v1 = vv.y;
+                    if (D16) {
+                        const OP oo = __builtin_nontemporal_load(reinterpret_cast<const OP *>(soff + kk));
+                        c0 = block_base<J>(s_rp, s_cb, nrows, kk) + (int32_t)oo.x;
+                        c1 = block_base<J>(s_rp, s_cb, nrows, kk + 1) + (int32_t)oo.y;
+                    } else {
+                        const IP cc = __builtin_nontemporal_load(reinterpret_cast<const IP *>(sci + kk));
+                        c0 = cc.x;
+                        c1 = cc.y;
                     }
-                    const bool ok0 = kk >= a && kk < e, ok1 = kk + 1 >= a && kk + 1 < e;
-                    p[2 * q] = ok0 ? VT<V>::cvt(v0) * x[c0] : A(0);
-                    p[2 * q + 1] = ok1 ? VT<V>::cvt(v1) * x[c1] : A(0);
+                } else if (kk < e) {
+                    v0 = sv[kk];
+                    c0 = D16 ? block_base<J>(s_rp, s_cb, nrows, kk) + (int32_t)soff[kk] : sci[kk];
                 }
-#pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    s_prod[2 * t + 2 * kBlock * q] = p[2 * q];
-                    s_prod[2 * t + 2 * kBlock * q + 1] = p[2 * q + 1];
-                }
-                __syncthreads();
-                const int32_t ce = (cs + kChunk) < e ? (cs + kChunk) : e;
-                for (; k < kend && k < ce; ++k) acc[j].add(s_prod[k - cs], comp[j]);
-                __syncthreads();
+                const bool ok0 = kk >= a && kk < e, ok1 = kk + 1 >= a && kk + 1 < e;
+                p[2 * q] = ok0 ? VT<V>::cvt(v0) * x[c0] : A(0);
+                p[2 * q + 1] = ok1 ? VT<V>::cvt(v1) * x[c1] : A(0);
             }
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                s_prod[2 * t + 2 * kBlock * q] = p[2 * q];
+                s_prod[2 * t + 2 * kBlock * q + 1] = p[2 * q + 1];
+            }
+            __syncthreads();
+            const int32_t ce = (cs + kChunk) < e ? (cs + kChunk) : e;
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                for (; k[j] < kend[j] && k[j] < ce; ++k[j]) acc[j].add(s_prod[k[j] - cs], comp[j]);
+            __syncthreads();
         }
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        const int64_t r = (w + j * G) * kBlock + t;
-        if (w + j * G < nblk && r < n) __builtin_nontemporal_store(acc[j].s, y + r);
+        const int lr = j * kBlock + t;
+        if (lr < nrows) __builtin_nontemporal_store(acc[j].s, y + r0 + lr);
     }
 }
 
