@@ -736,17 +736,16 @@ __global__ __launch_bounds__(kBlock) void k_rowstream_slices(int64_t n, int64_t 
 // rows' chunk sums, run as extra workgroups of this grid, as a kernel of
 // their own or after the slices, all cost more than the per-slice kernel
 // with partial y vectors below saves.
-// The reference column of the block holding position kk of a phased run:
-// that of the last of its blocks whose first position (s_rp at the block's
-// first row; nrows rows in all) is at most kk.
-template <int J>
-__device__ __forceinline__ int32_t block_base(const int32_t *s_rp, const int32_t *s_cb, int nrows,
-                                              int32_t kk) {
-    int32_t bb = s_cb[0];
-#pragma unroll
-    for (int j = 1; j < J; ++j)
-        if (j * kBlock < nrows && kk >= s_rp[j * kBlock]) bb = s_cb[j];
-    return bb;
+// The block of a phased run (nb blocks, the first positions s_rp[j kBlock])
+// holding position kk: the last whose first position is at most kk, so
+// empty blocks are passed over.
+__device__ __forceinline__ int run_block_of(const int32_t *s_rp, int nb, int32_t kk) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rp[mid * kBlock] <= kk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 template <class V, int J, bool D16>
@@ -769,6 +768,7 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
     const int64_t r0 = b0 * kBlock;
     const int64_t rlim = b1 * kBlock < n ? b1 * kBlock : n;
     const int nrows = (int)(rlim - r0);
+    const int nb = (nrows + kBlock - 1) / kBlock;  // blocks in the run (1 .. J)
     Sum<A> acc[J];
     bool comp[J];
 #pragma unroll
@@ -809,8 +809,11 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
                     v1 = vv.y;
                     if (D16) {
                         const OP oo = __builtin_nontemporal_load(reinterpret_cast<const OP *>(soff + kk));
-                        c0 = block_base<J>(s_rp, s_cb, nrows, kk) + (int32_t)oo.x;
-                        c1 = block_base<J>(s_rp, s_cb, nrows, kk + 1) + (int32_t)oo.y;
+                        const int j0 = run_block_of(s_rp, nb, kk);
+                        int j1 = j0;
+                        while (j1 + 1 < nb && kk + 1 >= s_rp[(j1 + 1) * kBlock]) ++j1;
+                        c0 = s_cb[j0] + (int32_t)oo.x;
+                        c1 = s_cb[j1] + (int32_t)oo.y;
                     } else {
                         const IP cc = __builtin_nontemporal_load(reinterpret_cast<const IP *>(sci + kk));
                         c0 = cc.x;
@@ -818,7 +821,7 @@ __global__ __launch_bounds__(kBlock) void k_phased_slices(
                     }
                 } else if (kk < e) {
                     v0 = sv[kk];
-                    c0 = D16 ? block_base<J>(s_rp, s_cb, nrows, kk) + (int32_t)soff[kk] : sci[kk];
+                    c0 = D16 ? s_cb[run_block_of(s_rp, nb, kk)] + (int32_t)soff[kk] : sci[kk];
                 }
                 const bool ok0 = kk >= a && kk < e, ok1 = kk + 1 >= a && kk + 1 < e;
                 p[2 * q] = ok0 ? VT<V>::cvt(v0) * x[c0] : A(0);
