@@ -361,7 +361,7 @@ spmv_status_t spmv_time_variant_batch(spmv_plan_t plan, int32_t variant, int32_t
  * the slices use merge-path tiles), 14 delta16 layout (-1 infeasible,
  * 0 rows streamed, 1 sliced), 15 delta16 sliced slots (64 x the sum of the
  * slice widths, padding included), 16 x-block row blocks per workgroup of
- * the phased slice kernel (0 when the slices use merge-path tiles),
+ * the phased slice kernel, at most (0 when the slices use merge-path tiles),
  * 17 delta16 code bits (8 or 16; -1 infeasible), 18 delta16 largest
  * offset of an offset slice (its columns minus its reference column; 0 with
  * no offset slices; -1 infeasible), 19 delta16 escape units (sum E; 0 with

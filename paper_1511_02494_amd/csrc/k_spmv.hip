@@ -997,9 +997,11 @@ hipError_t launch_rowstream(const spmv_plan &P, bool d16, const void *x, void *y
 }
 
 // Geometry of the phased x-block kernel: the fewest row blocks per workgroup
-// J (1, 2, 4 or 8) for which the G = ceil(blocks / J) workgroups fit on the
-// CUs at once (by the occupancy the runtime reports for that instance), else
-// J = 8 with more workgroups than fit.
+// J (1, 2, 4 or 8) for which ceil(blocks / J) workgroups fit on the CUs at
+// once (by the occupancy the runtime reports for that instance); G is then
+// as many workgroups as fit, at most one per block, each taking a range of
+// at most J consecutive blocks.  Else J = 8 and G = ceil(blocks / 8), more
+// workgroups than fit.
 hipError_t phased_geometry(const spmv_plan &P, int *J, int64_t *G) {
     const int64_t nblk = (P.n + kBlock - 1) / kBlock;
     return by_dtype(P.dtype, [&](auto tag) -> hipError_t {
