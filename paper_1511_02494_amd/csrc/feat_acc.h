@@ -84,12 +84,25 @@ template <int NT> __device__ inline void block_reduce_n(Acc &a, uint64_t *out) {
 
 __device__ inline void block_reduce(Acc &a, uint64_t *out) { block_reduce_n<kBlock>(a, out); }
 
-// The 64-thread reduction of nparts partial records into out.
+// The 64-thread reduction of nparts partial records into out.  Each thread
+// loads four records before merging them, so that four round trips to the
+// records (written by workgroups on every XCD) are in flight at once instead
+// of one; the merge is exact integer arithmetic, so its order does not
+// change the result.
 __device__ inline void reduce_partials_64(int nparts, const uint64_t *__restrict__ partials,
                                           uint64_t *out) {
+    constexpr int U = 4;
     Acc a;
     a.init();
-    for (int b = threadIdx.x; b < nparts; b += 64) {
+    int b = threadIdx.x;
+    for (; b + 64 * (U - 1) < nparts; b += 64 * U) {
+        Acc o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) o[u].load(partials + 16 * (b + 64 * u));
+#pragma unroll
+        for (int u = 0; u < U; ++u) a.merge(o[u]);
+    }
+    for (; b < nparts; b += 64) {
         Acc o;
         o.load(partials + 16 * b);
         a.merge(o);
