@@ -13,6 +13,7 @@ import pytest
 import synth
 import paper_1511_02494_amd as S
 from oracle.encode import delta16_ref, merge_codes_ref, xblock_codes_ref
+from oracle import cref
 from oracle.spmv import spmv_exact, spmv_seq, within_tolerance
 
 pytestmark = pytest.mark.gpu
@@ -137,4 +138,46 @@ def test_coded_bytes():
     ok, base, _ = delta16_ref(rp, ci, plan.query(11))
     assert ok
     assert plan.bytes(S.V_SHORT_ROW) == plain[S.V_SHORT_ROW] - 2 * nnz + 4 * len(base)
+    plan.close()
+
+
+def with_empty_row_blocks():
+    """A band of 1.2M rows whose 256-row blocks 1, 2 (mod 4) are empty, and
+    the last block too: with more blocks than the workgroups that fit, the
+    runs of a phased workgroup hold empty blocks between nonempty ones and
+    at their end."""
+    rp, ci, v = synth.banded(1_200_000, 80, 300, seed=23)
+    L = np.diff(rp)
+    n = len(L)
+    blk = np.arange(n) // 256
+    empty = (blk % 4 == 1) | (blk % 4 == 2) | (blk == (n - 1) // 256)
+    keep = np.repeat(~empty, L)
+    L = np.where(empty, 0, L)
+    rp2 = np.zeros(len(rp), np.int32)
+    rp2[1:] = np.cumsum(L)
+    return rp2, ci[keep], v[keep]
+
+
+@pytest.mark.parametrize("slices", [2, 4, 8])
+def test_phased_coded_runs_over_empty_row_blocks(slices):
+    """The phased x-block kernel streams a workgroup's row blocks as one run
+    per slice; with 16-bit codes each position takes the reference column of
+    the block that holds it, passing over empty blocks.  Coded equals int32
+    bit for bit and both equal Algorithm 1's sequential sum (FP64), in every
+    forced slice count."""
+    rp, ci, v = with_empty_row_blocks()
+    n = len(rp) - 1
+    x = synth.vector(n, 6)
+    seq = cref.seq(rp, ci, v, x)
+    plan = make_plan(rp, ci, v, n)
+    S.spmv_set_xblock_slices(plan.handle, slices)
+    S.spmv_set_index_coding(plan.handle, S.SPMV_IDX_CODED)
+    assert (plan.mask() >> S.V_XBLOCK_LDS) & 1
+    yc = run(plan, S.V_XBLOCK_LDS, x)
+    assert plan.query(22) == 1 and plan.query(16) > 1  # coded, phased, runs of blocks
+    S.spmv_set_index_coding(plan.handle, S.SPMV_IDX_I32)
+    yi = run(plan, S.V_XBLOCK_LDS, x)
+    assert plan.query(22) == 0 and plan.query(16) > 0
+    assert np.array_equal(yc, yi), slices
+    assert np.array_equal(yc, seq), slices
     plan.close()
